@@ -1,0 +1,127 @@
+"""Expansion orders and crossover point (Sec. 3).
+
+TEST INFRASTRUCTURE ONLY (see :mod:`oracle`).
+
+For order nu and tolerance eps the method uses
+* M   asymptotic terms, from the heuristic eq. num-asy-terms (Sec. 3.3);
+* z   the crossover: the root of xi(z) = B^asy(z) - eps found by Newton's method,
+      B^asy being the first-neglected-terms bound of eq. asy-error (Sec. 3.2);
+* L   the smallest integer with B^loc(z) < eps, B^loc being the Wimp truncation
+      bound of Lemma 3.1 (Sec. 3.1); the local sum keeps l = 0 .. L.
+
+Readings of the paper taken here (each listed in the design doc):
+* a_l(nu) is the product prod_{s=1}^{l} (4 nu^2 - (2s-1)^2) / (l! 8^l): the printed
+  second factor "(4nu^2 - 3)" is read as "(4nu^2 - 9)", the pattern its last
+  factor fixes.
+* Lemma 3.1 sums l = 0 .. L, so an "L-term" local expansion keeps L + 1 terms.
+* Odd nu: the paper only says a similar expansion and bound exist.  The bound
+  used here follows the even-order proof step by step for the odd-order Wimp
+  expansion sum_l 2 J_{(nu+1)/2+l}(x/2) J_{(nu-1)/2-l}(x/2) T_{2l+1}(y).
+* Outside the Lemma's hypotheses (a Siegel argument >= 1, or a non-convergent
+  geometric tail) the bound is taken as +inf, so that L grows until they hold.
+* Negative orders use |nu| (J_{-nu} = (-1)^nu J_nu).
+"""
+import math
+
+SQRT_2_OVER_PI = math.sqrt(2.0 / math.pi)
+
+
+def num_asy_terms(nu: int, eps: float) -> int:
+    """M = min(floor(1 + nu/5 - log10(eps)/4), 20)  (eq. num-asy-terms)."""
+    return min(math.floor(1.0 + abs(nu) / 5.0 - math.log10(eps) / 4.0), 20)
+
+
+def hankel_coef(nu: float, l: int) -> float:
+    """a_l(nu) = prod_{s=1}^{l} (4 nu^2 - (2s-1)^2) / (l! 8^l)  (Sec. 3.2)."""
+    a = 1.0
+    for s in range(1, l + 1):
+        a *= (4.0 * nu * nu - (2 * s - 1) ** 2) / (8.0 * s)
+    return a
+
+
+def asy_bound(nu: int, M: int, z: float) -> float:
+    """B^asy(z): the first two neglected terms of the M-term expansion at
+    argument z, times sqrt(2/pi)  (eq. asy-error)."""
+    a0 = abs(hankel_coef(nu, 2 * M))
+    a1 = abs(hankel_coef(nu, 2 * M + 1))
+    return SQRT_2_OVER_PI * (a0 / z ** (2 * M + 0.5) + a1 / z ** (2 * M + 1.5))
+
+
+def crossover(nu: int, eps: float, M: int) -> float:
+    """z: root of xi(z) = B^asy(z) - eps by Newton's method (Sec. 3.3).
+
+    xi is convex and decreasing on z > 0, so Newton's iteration started left of
+    the root increases monotonically to it.  The start is the root of the first
+    term alone, which lies left of the root of the full bound.
+    """
+    a0 = SQRT_2_OVER_PI * abs(hankel_coef(nu, 2 * M))
+    a1 = SQRT_2_OVER_PI * abs(hankel_coef(nu, 2 * M + 1))
+    p0 = 2 * M + 0.5
+    p1 = 2 * M + 1.5
+    z = (a0 / eps) ** (1.0 / p0)
+    for _ in range(200):
+        xi = a0 * z ** -p0 + a1 * z ** -p1 - eps
+        dxi = -p0 * a0 * z ** (-p0 - 1.0) - p1 * a1 * z ** (-p1 - 1.0)
+        step = xi / dxi
+        z_new = z - step
+        if abs(z_new - z) <= 1e-15 * z:
+            return z_new
+        z = z_new
+    return z
+
+
+def psi(p: float) -> float:
+    """psi(p) = log p + sqrt(1-p^2) - log(1 + sqrt(1-p^2)), 0 < p <= 1 (Lemma 3.1)."""
+    s = math.sqrt(1.0 - p * p)
+    return math.log(p) + s - math.log(1.0 + s)
+
+
+def local_bound(nu: int, L: int, z: float) -> float:
+    """B^loc(z) for the local expansion with terms l = 0 .. L (Lemma 3.1)."""
+    nu = abs(nu)
+    if z <= 0.0:
+        return 0.0
+    if nu % 2 == 0:
+        d_beta = 2 * L + 2 + nu
+        d_gamma = 2 * L + 2 - nu
+        gamma_applies = (L + 1) >= nu / 2.0
+        lead_b, lead_g = nu / 2.0, nu / 2.0
+    else:
+        d_beta = 2 * L + 3 + nu
+        d_gamma = 2 * L + 3 - nu
+        gamma_applies = d_gamma > 0
+        lead_b, lead_g = (nu + 1) / 2.0, (nu - 1) / 2.0
+    pb = z / d_beta
+    if pb >= 1.0:
+        return math.inf
+    beta = psi(pb)
+    if gamma_applies:
+        if d_gamma <= 0:
+            return math.inf
+        pg = z / d_gamma
+        if pg >= 1.0:
+            return math.inf
+        gamma = psi(pg)
+    else:
+        gamma = 0.0
+    if beta + gamma >= 0.0:
+        return math.inf
+    return (2.0 * math.exp(lead_b * beta - lead_g * gamma + (L + 1) * (beta + gamma))
+            / (1.0 - math.exp(beta + gamma)))
+
+
+def local_rank(nu: int, eps: float, z: float, L_max: int = 100000) -> int:
+    """L: the smallest integer with B^loc(z) < eps (Sec. 3.3)."""
+    for L in range(0, L_max):
+        if local_bound(nu, L, z) < eps:
+            return L
+    raise ValueError("no local rank below L_max")
+
+
+def parameters(nu: int, eps: float, M: int = None):
+    """(M, z, L) for order nu and tolerance eps (Alg. 2, first three lines)."""
+    if M is None:
+        M = num_asy_terms(nu, eps)
+    z = crossover(nu, eps, M)
+    L = local_rank(nu, eps, z)
+    return M, z, L

@@ -1,0 +1,83 @@
+"""Seeded synthetic inputs for the nonuniform discrete Hankel transform.
+
+This module only draws inputs; it holds none of the transform's arithmetic.
+The tests, the benchmark and the smoke check use it on both sides of every
+comparison (GPU library and CPU oracle).
+
+All arrays are float64.  Draw order within one workload: r, then w, then c,
+then y (the cotangent of the gradient workload).  The workloads follow the
+shapes and distributions of the paper's experiments (Sec. 5) and of the
+benchmark configurations:
+
+* ``uniform``       r ~ U[0, rmax), w ~ U[0, wmax), c ~ N(0, 1)
+* ``radial_2d``     the radial 2-D Fourier transform of a smooth profile:
+                    Chebyshev-clustered r on [0, 1], trapezoid weights w_k,
+                    c_k = r_k w_k exp(-40 r_k^2) cos(30 r_k), log-spaced w on
+                    [1e-2, 1e5] (stands in for the radial-FT study of Sec. 5.2)
+* ``sparse_c``      c with a fixed number of N(0, 1) nonzeros at random indices
+                    (the accuracy study of Sec. 5.1.3)
+* ``batch``         many independent transforms with uneven n, m and order
+"""
+import numpy as np
+
+
+def uniform(n: int, m: int, rmax: float, wmax: float, seed: int):
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(0.0, rmax, n)
+    w = rng.uniform(0.0, wmax, m)
+    c = rng.standard_normal(n)
+    return r, w, c
+
+
+def small_dense(seed: int = 1):
+    """n = m = 2000, r ~ U[0,1), w ~ U[0,500), c ~ N(0,1)."""
+    return uniform(2000, 2000, 1.0, 500.0, seed)
+
+
+def large_uniform(seed: int = 2, n: int = 1_000_000, m: int = 1_000_000):
+    """n = m = 1e6, r ~ U[0,1) unsorted, w ~ U[0,1e5), c ~ N(0,1)."""
+    return uniform(n, m, 1.0, 1e5, seed)
+
+
+def radial_2d(n: int = 1_000_000, m: int = 1_000_000):
+    """Deterministic radial 2-D Fourier-transform workload (no randomness)."""
+    i = np.arange(n, dtype=np.float64)
+    r = 0.5 * (1.0 - np.cos(np.pi * i / (n - 1)))
+    wt = np.empty(n)
+    wt[0] = 0.5 * (r[1] - r[0])
+    wt[-1] = 0.5 * (r[-1] - r[-2])
+    wt[1:-1] = 0.5 * (r[2:] - r[:-2])
+    c = r * wt * np.exp(-40.0 * r * r) * np.cos(30.0 * r)
+    k = np.arange(m, dtype=np.float64)
+    w = 10.0 ** (-2.0 + 7.0 * k / (m - 1))
+    return r, w, c
+
+
+def sparse_c(n: int, nnz: int, seed: int):
+    """A length-n vector with nnz N(0,1) entries at distinct random indices."""
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(n, size=nnz, replace=False)
+    c = np.zeros(n)
+    c[idx] = rng.standard_normal(nnz)
+    return c
+
+
+def cotangent(m: int, seed: int):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(m)
+
+
+def batch(count: int = 256, seed: int = 5, lo: float = 3.0, hi: float = 6.0, nu_max: int = 63):
+    """count independent transforms: nu ~ U{0..nu_max}, n and m log-uniform in
+    [10^lo, 10^hi], r ~ U[0,1), w ~ U[0, n_i), c ~ N(0,1)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        nu = int(rng.integers(0, nu_max + 1))
+        n = int(round(10.0 ** rng.uniform(lo, hi)))
+        m = int(round(10.0 ** rng.uniform(lo, hi)))
+        r = rng.uniform(0.0, 1.0, n)
+        w = rng.uniform(0.0, float(n), m)
+        c = rng.standard_normal(n)
+        out.append(dict(nu=nu, r=r, w=w, c=c))
+    return out
