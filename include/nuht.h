@@ -1,0 +1,155 @@
+/*
+ * nuht.h -- C ABI of libnuht, a nonuniform fast Hankel transform for AMD MI355X.
+ *
+ * The transform (Beckman & O'Neil, "A Nonuniform Fast Hankel Transform",
+ * Sec. 1, eq. DHT; matrix form in Sec. 2):
+ *
+ *     g_j = sum_{k=0}^{n-1} c_k J_nu(omega_j r_k),    j = 0 .. m-1,
+ *
+ * from n points r_k >= 0 with weights c_k to m frequencies omega_j >= 0, for
+ * integer order nu, to a requested tolerance eps.  The method is Alg. 2 of the
+ * paper: the expansion orders (M, z, L) come from eps (Sec. 3.3); the matrix
+ * J_nu(omega_j r_k) is split along omega r = z by Alg. 1 (Sec. 4.1); local
+ * blocks are applied with the Wimp expansion (Sec. 3.1), asymptotic blocks with
+ * 2M type-3 NUFFTs of Hankel's expansion (Sec. 3.2), and a few small direct
+ * blocks entry by entry.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named *_dev are device pointers (HIP global memory) of FP64
+ *    values; the caller owns them.  Pointers without _dev are host pointers.
+ *  - Arrays are dense and contiguous; element i of r pairs with element i of c.
+ *    Inputs may be in any order; outputs follow the order of the caller's
+ *    frequencies (forward) or points (adjoint).
+ *  - `stream` is a hipStream_t passed as void* (0 = the null stream).  Work is
+ *    enqueued on it.  Only nuht_plan and nuht_plan_info synchronise it.
+ *  - Return value: 0 on success, a negative NUHT_E* code on failure.  On
+ *    failure the output arguments are left unspecified and no plan is leaked.
+ */
+#ifndef NUHT_H
+#define NUHT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define NUHT_OK           0
+#define NUHT_EINVAL      -1   /* bad size, null pointer with nonzero size, nu or eps out of range */
+#define NUHT_EDOMAIN     -2   /* some r or omega is negative, NaN or infinite */
+#define NUHT_EPRECISION  -3   /* FP32 spreading requested with eps < 1e-7 */
+#define NUHT_ENOMEM      -4   /* device allocation failed */
+#define NUHT_EHIP        -5   /* a HIP runtime call failed */
+#define NUHT_ECAPACITY   -6   /* the partition exceeds an internal table limit */
+
+/* Precision of the NUFFT spreading and interpolation. */
+#define NUHT_FP64        0
+#define NUHT_FP32_SPREAD 1    /* FP32 grids and kernel taps; phases stay FP64; eps >= 1e-7 */
+
+typedef struct nuht_plan_s *nuht_plan_t;
+
+/*
+ * Options; pass NULL for the defaults.
+ *   min_size          direct-block threshold of Alg. 1: an off-diagonal child
+ *                     of area <= min_size is applied directly (0 -> 1024, the
+ *                     paper's default, Sec. 4.1).
+ *   M_override        number of asymptotic terms M (0 -> eq. num-asy-terms).
+ *   split_candidates  equispaced candidate rows in SplitIndices (0 -> 16).
+ *   precision         NUHT_FP64 or NUHT_FP32_SPREAD.
+ *   dft_max           asymptotic blocks whose spread grid has at most this
+ *                     many cells are evaluated by a direct sum over the grid
+ *                     instead of an FFT and interpolation (0 -> built-in default,
+ *                     negative -> always use the FFT path).
+ */
+typedef struct {
+    int64_t min_size;
+    int32_t M_override;
+    int32_t split_candidates;
+    int32_t precision;
+    int32_t dft_max;
+} nuht_opts;
+
+/*
+ * Plan statistics and parameters (filled by nuht_plan_info).
+ */
+typedef struct {
+    int32_t nu, M, L, es_width;       /* order, asymptotic terms, local rank, ES kernel width */
+    double  eps, z, es_beta;          /* tolerance, crossover, ES kernel shape */
+    int32_t levels;                   /* depth of the subdivision */
+    int32_t n_nodes, n_local, n_asy, n_direct;
+    int32_t n_fft_blocks;             /* asymptotic blocks using the FFT path */
+    int64_t local_row_members, local_col_members;
+    int64_t asy_row_members, asy_col_members;
+    int64_t direct_entries;
+    int64_t grid_cells;               /* sum of spread-grid sizes N1 over asymptotic blocks */
+    int64_t fft_points;               /* sum of FFT sizes N2 over FFT-path blocks */
+    int64_t workspace_bytes;          /* device memory held by the plan */
+} nuht_info;
+
+/*
+ * nuht_plan -- prepare the transform r (n points) -> omega (m frequencies).
+ *
+ * Sorts r and omega on the device, computes (M, z, L) for (nu, eps) (Sec. 3.3),
+ * and subdivides the matrix (Alg. 1).  Copies r and omega into plan-owned
+ * storage, so the caller may free or change them afterwards.  Synchronises
+ * `stream` once (to size the plan's workspace).  Every argument is validated:
+ * n, m >= 0; r_dev / omega_dev non-null when n / m > 0; |nu| <= 100;
+ * 1e-15 <= eps <= 1e-2; all r, omega finite and >= 0 (else NUHT_EDOMAIN).
+ * n == 0 or m == 0 is valid (the transform then writes zeros).
+ */
+int nuht_plan(nuht_plan_t *plan, int nu, double eps,
+              int64_t n, const double *r_dev, int64_t m, const double *omega_dev,
+              const nuht_opts *opts, void *stream);
+
+/*
+ * nuht_execute -- g = A c (forward transform, Alg. 2).
+ *   c_dev: n weights in the caller's point order (as passed to nuht_plan).
+ *   g_dev: m outputs in the caller's frequency order; overwritten.
+ * Asynchronous on `stream`; allocates nothing.
+ */
+int nuht_execute(nuht_plan_t plan, const double *c_dev, double *g_dev, void *stream);
+
+/*
+ * nuht_adjoint -- cbar = A^T y, i.e. cbar_k = sum_j y_j J_nu(omega_j r_k).
+ *   y_dev: m values in frequency order; cbar_dev: n outputs in point order
+ *   (overwritten).  J_nu(omega r) is symmetric in its two factors, so this is
+ *   the same method with the roles of points and frequencies exchanged; its
+ *   partition is built on first use and kept in the plan.
+ * Asynchronous on `stream` after its first call (the first call synchronises
+ * once to size the transposed partition).
+ */
+int nuht_adjoint(nuht_plan_t plan, const double *y_dev, double *cbar_dev, void *stream);
+
+/*
+ * nuht_plan_set_order -- switch the plan to order nu (same points, frequencies
+ * and eps), recomputing (M, z, L) and the partition but not the sort.  Used for
+ * the J_{nu+-1} transforms of the gradient.  Synchronises `stream` once.
+ */
+int nuht_plan_set_order(nuht_plan_t plan, int nu, void *stream);
+
+/* nuht_plan_info -- parameters and partition statistics of the current order. */
+int nuht_plan_info(nuht_plan_t plan, nuht_info *info);
+
+/* nuht_destroy -- free the plan and its device memory (NULL is allowed). */
+int nuht_destroy(nuht_plan_t plan);
+
+/* nuht_strerror -- static description of an error code. */
+const char *nuht_strerror(int code);
+
+/*
+ * nuht_direct -- brute-force O(nm) evaluation on the device of
+ *   g_j = sum_k c_k J_nu(omega_j r_k)
+ * with the library's own device J_nu (Hankel's M-term expansion above the
+ * crossover z, Miller's recurrence below it; eps-accurate per entry).  A
+ * reference for mid-sized checks, not a fast path.  Same argument conventions
+ * as nuht_execute; asynchronous on `stream`.
+ */
+int nuht_direct(int nu, double eps, int64_t n, const double *r_dev, const double *c_dev,
+                int64_t m, const double *omega_dev, double *g_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NUHT_H */

@@ -16,8 +16,11 @@ Readings of the paper taken here (each listed in the design doc):
   says the objective is minimised and that the fast area is to be maximised;
   the argmax in the display is read as that.  Ties go to the smaller j.
 * The quasi-optimal solve uses 16 equispaced candidate rows including both
-  ends (floor of linspace(j0, j1, 16)); for each, k is the largest column in
-  the block with w_j r_k <= z, or k0-1 when there is none.
+  ends (floor of linspace(j0, jl, 16)), jl being the block's last row with a
+  local entry; for each, k is the largest column in the block with
+  w_j r_k <= z, or k0-1 when there is none.  Restricting the candidates to
+  rows that can hold a split point keeps the depth logarithmic when the local
+  region is a thin strip along the block's top (many equal points).
 * The lower-left child (j+1:j1, k0:k) is tested by its own area (j1-j)(k-k0+1);
   the printed (j1-j)(k1-k+1) is read as a typo.  Both off-diagonal children go
   to the direct set when their area is <= min_size.
@@ -53,10 +56,22 @@ class Block:
 
 
 def split_indices(K, j0: int, j1: int, k0: int, k1: int, ncand: int = 16):
-    """Quasi-optimal SplitIndices (Sec. 4.1).  K[j] = #{k : w_j r_k <= z}."""
+    """Quasi-optimal SplitIndices (Sec. 4.1).  K[j] = #{k : w_j r_k <= z}.
+
+    The candidate rows are equispaced over j0 .. jl, jl being the last row of
+    the block that holds a local entry (K is nonincreasing in j, so jl is found
+    by bisection); rows below jl cannot hold the split point."""
+    lo, hi = j0, j1
+    while lo < hi:
+        mid = lo + (hi - lo + 1) // 2
+        if K[mid] > k0:
+            lo = mid
+        else:
+            hi = mid - 1
+    jl = lo
     best = None
-    if j1 > j0:
-        cands = [j0 + (c * (j1 - j0)) // (ncand - 1) for c in range(ncand)]
+    if jl > j0:
+        cands = [j0 + (c * (jl - j0)) // (ncand - 1) for c in range(ncand)]
     else:
         cands = [j0]
     for j in cands:

@@ -1,0 +1,186 @@
+"""libnuht: nonuniform fast Hankel transform on AMD MI355X (gfx950).
+
+Python binding of the C ABI in ``include/nuht.h``: argument marshalling only.
+Every step of the transform runs in the HIP kernels of ``libnuht.so``; PyTorch
+supplies device memory (float64 tensors on the GPU) and the current stream.
+There is no CPU fallback: without the built library, or without a GPU, the
+calls raise.
+
+    g_j = sum_k c_k J_nu(omega_j r_k)        (Beckman & O'Neil, Sec. 1, eq. DHT)
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnuht.so")
+
+NUHT_OK = 0
+NUHT_FP64 = 0
+NUHT_FP32_SPREAD = 1
+
+_ERRORS = {
+    -1: "NUHT_EINVAL", -2: "NUHT_EDOMAIN", -3: "NUHT_EPRECISION", -4: "NUHT_ENOMEM",
+    -5: "NUHT_EHIP", -6: "NUHT_ECAPACITY",
+}
+
+
+class NuhtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class NuhtOpts(ctypes.Structure):
+    _fields_ = [("min_size", ctypes.c_int64), ("M_override", ctypes.c_int32),
+                ("split_candidates", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("dft_max", ctypes.c_int32)]
+
+
+class NuhtInfo(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_int32), ("M", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("es_width", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("z", ctypes.c_double), ("es_beta", ctypes.c_double),
+                ("levels", ctypes.c_int32), ("n_nodes", ctypes.c_int32), ("n_local", ctypes.c_int32),
+                ("n_asy", ctypes.c_int32), ("n_direct", ctypes.c_int32), ("n_fft_blocks", ctypes.c_int32),
+                ("local_row_members", ctypes.c_int64), ("local_col_members", ctypes.c_int64),
+                ("asy_row_members", ctypes.c_int64), ("asy_col_members", ctypes.c_int64),
+                ("direct_entries", ctypes.c_int64), ("grid_cells", ctypes.c_int64),
+                ("fft_points", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
+
+
+# every symbol include/nuht.h declares
+EXPORTS = ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_plan_set_order", "nuht_plan_info",
+           "nuht_destroy", "nuht_strerror", "nuht_direct")
+
+_lib = None
+
+
+def load_library():
+    """Load libnuht.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.nuht_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_double, ctypes.c_int64, vp,
+                              ctypes.c_int64, vp, ctypes.POINTER(NuhtOpts), vp]
+    lib.nuht_execute.argtypes = [vp, vp, vp, vp]
+    lib.nuht_adjoint.argtypes = [vp, vp, vp, vp]
+    lib.nuht_plan_set_order.argtypes = [vp, ctypes.c_int, vp]
+    lib.nuht_plan_info.argtypes = [vp, ctypes.POINTER(NuhtInfo)]
+    lib.nuht_destroy.argtypes = [vp]
+    lib.nuht_strerror.argtypes = [ctypes.c_int]
+    lib.nuht_strerror.restype = ctypes.c_char_p
+    lib.nuht_direct.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, vp, vp, ctypes.c_int64, vp, vp, vp]
+    for name in ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_plan_set_order", "nuht_plan_info",
+                 "nuht_destroy", "nuht_direct"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != NUHT_OK:
+        raise NuhtError(code, load_library().nuht_strerror(code).decode())
+
+
+def _dev_f64(x, name):
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if x.device.type != "cuda" or x.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 tensor on the GPU")
+    if x.dim() != 1:
+        raise ValueError(f"{name} must be one-dimensional")
+    return x.contiguous()
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0)
+
+
+class Plan:
+    """A planned transform r (n points) -> omega (m frequencies) of order nu.
+
+    The plan sorts and subdivides once; ``execute`` and ``adjoint`` then run
+    asynchronously on the current stream.  ``execute(c)`` returns
+    g_j = sum_k c_k J_nu(omega_j r_k); ``adjoint(y)`` returns
+    cbar_k = sum_j y_j J_nu(omega_j r_k).
+    """
+
+    def __init__(self, r, omega, nu: int, eps: float, *, min_size: int = 0, M: int = 0,
+                 split_candidates: int = 0, precision: int = NUHT_FP64, dft_max: int = 0):
+        lib = load_library()
+        r = _dev_f64(r, "r")
+        omega = _dev_f64(omega, "omega")
+        self.n = r.numel()
+        self.m = omega.numel()
+        self.device = r.device
+        opts = NuhtOpts(min_size, M, split_candidates, precision, dft_max)
+        h = ctypes.c_void_p()
+        _check(lib.nuht_plan(ctypes.byref(h), int(nu), float(eps), self.n, _ptr(r), self.m, _ptr(omega),
+                             ctypes.byref(opts), _stream()))
+        self._h = h
+
+    def execute(self, c, out=None):
+        c = _dev_f64(c, "c")
+        if c.numel() != self.n:
+            raise ValueError("c must have n entries")
+        g = out if out is not None else torch.empty(self.m, dtype=torch.float64, device=self.device)
+        _check(load_library().nuht_execute(self._h, _ptr(c), _ptr(g), _stream()))
+        return g
+
+    def adjoint(self, y, out=None):
+        y = _dev_f64(y, "y")
+        if y.numel() != self.m:
+            raise ValueError("y must have m entries")
+        cb = out if out is not None else torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(load_library().nuht_adjoint(self._h, _ptr(y), _ptr(cb), _stream()))
+        return cb
+
+    def set_order(self, nu: int):
+        _check(load_library().nuht_plan_set_order(self._h, int(nu), _stream()))
+
+    def info(self) -> dict:
+        inf = NuhtInfo()
+        _check(load_library().nuht_plan_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in NuhtInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().nuht_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nuht(c, r, omega, nu: int, eps: float = 1e-12, **opts):
+    """One-shot transform: plan, execute, free."""
+    p = Plan(r, omega, nu, eps, **opts)
+    try:
+        return p.execute(c)
+    finally:
+        p.close()
+
+
+def direct(c, r, omega, nu: int, eps: float = 1e-12):
+    """Brute-force O(nm) evaluation on the GPU with the library's J_nu."""
+    lib = load_library()
+    r = _dev_f64(r, "r")
+    c = _dev_f64(c, "c")
+    omega = _dev_f64(omega, "omega")
+    g = torch.empty(omega.numel(), dtype=torch.float64, device=omega.device)
+    _check(lib.nuht_direct(int(nu), float(eps), r.numel(), _ptr(r), _ptr(c), omega.numel(), _ptr(omega),
+                           _ptr(g), _stream()))
+    return g

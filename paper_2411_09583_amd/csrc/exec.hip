@@ -1,0 +1,689 @@
+// exec.hip -- execution of a planned transform (Alg. 2): local blocks by the
+// Wimp expansion (Sec. 3.1), asymptotic blocks by type-3 NUFFTs of Hankel's
+// expansion (Sec. 3.2), direct blocks entry by entry.
+//
+// Column side (reductions over points):  gather c -> local moments ->
+//   ES spreading of 2M weight channels onto each asymptotic block's grid.
+// Grid stage:  reduce spread partials; for large grids deconvolve by the
+//   inner kernel's transform, zero-pad and FFT.
+// Row side (one thread per frequency): walk the block tree from the root and
+//   add, level by level, the row's local, asymptotic and (at the end) direct
+//   contributions; write g once, in the caller's order.
+#include "nuht_device.h"
+#include "nuht_launch.h"
+
+namespace nuht {
+
+// ---------------------------------------------------------------------------
+__global__ void k_gather(const double* __restrict__ c, const int32_t* __restrict__ perm, int32_t n,
+                         double* __restrict__ cs)
+{
+    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) cs[k] = c[perm[k]];
+}
+
+// ---------------------------------------------------------------------------
+// Local moments t_l = sum_k c_k T_{2l(+1)}(r_k / R) of one chunk of a local
+// block's columns (Sec. 3.1: T^T applied first).  The Chebyshev polynomials
+// come from the recurrence in u = 2y^2 - 1:  T_{2(l+1)+e}(y) = 2u T_{2l+e}(y) - T_{2(l-1)+e}(y).
+// Moments are produced 32 at a time; each thread accumulates in registers and
+// the block reduces.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_lmom(PlanDev P, const double* __restrict__ cs, double* __restrict__ lpart)
+{
+    __shared__ double red[4][32];
+    const Item I = P.litems[blockIdx.x];
+    const LBlock B = P.lb[I.blk];
+    const int L = P.L;
+    const int odd = P.nu & 1;
+    const int tid = threadIdx.x;
+    for (int s0 = 0; s0 <= L; s0 += 32) {
+        double acc[32];
+        #pragma unroll
+        for (int q = 0; q < 32; ++q) acc[q] = 0.0;
+        for (int k = I.ka + tid; k < I.kb; k += 256) {
+            double y = P.rs[k] / B.R;
+            double c = cs[k];
+            double u = __builtin_fma(2.0 * y, y, -1.0);
+            double u2 = 2.0 * u;
+            double t0, t1;
+            if (odd) { t0 = y; t1 = y * (u2 - 1.0); } else { t0 = 1.0; t1 = u; }
+            for (int l = 0; l < s0; ++l) {
+                double t2 = __builtin_fma(u2, t1, -t0);
+                t0 = t1; t1 = t2;
+            }
+            #pragma unroll
+            for (int q = 0; q < 32; ++q) {
+                acc[q] = __builtin_fma(c, t0, acc[q]);
+                double t2 = __builtin_fma(u2, t1, -t0);
+                t0 = t1; t1 = t2;
+            }
+        }
+        #pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            double x = acc[q];
+            for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+            acc[q] = x;
+        }
+        if ((tid & 63) == 0) {
+            #pragma unroll
+            for (int q = 0; q < 32; ++q) red[tid >> 6][q] = acc[q];
+        }
+        __syncthreads();
+        if (tid < 32 && s0 + tid <= L) {
+            double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+            lpart[(int64_t)blockIdx.x * (L + 1) + s0 + tid] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// Sum of a local block's item partials, in item order.
+__global__ void k_lmom_reduce(PlanDev P, const double* __restrict__ lpart, double* __restrict__ lmom)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int Lp = P.L + 1;
+    if (t >= (int64_t)P.n_l * Lp) return;
+    int32_t b = (int32_t)(t / Lp);
+    int32_t l = (int32_t)(t % Lp);
+    const LBlock B = P.lb[b];
+    double s = 0.0;
+    for (int32_t it = 0; it < B.nitems; ++it) s += lpart[(int64_t)(B.item0 + it) * Lp + l];
+    lmom[t] = s;
+}
+
+// ---------------------------------------------------------------------------
+// ES spreading of one chunk of an asymptotic block's points (type-3 NUFFT,
+// step one).  Point k of the block carries the 2M channel weights
+//   x_k^(p) = c_k (r0/r_k)^(p+1/2) e^{i D (r_k - C)},   p = 0 .. 2M-1
+// (the weights c_k r_k^(-p-1/2) of Sec. 3.2, normalised by the block's
+// smallest point r0, times the type-3 pre-phase), placed at grid coordinate
+// u_k = (r_k - C)/h.  Cell l receives sum_k x_k^(p) ES((l - u_k) 2/w).
+//
+// Phase 1: one thread per point computes (u, weight, ratio) into LDS; the
+// offset r - C and the phase D (r - C) are kept as double-double so that the
+// kernel position and the phase are exact to FP64 relative to themselves.
+// Phase 2: threads own (cell, slice) pairs and gather the points in the cell's
+// kernel support (a contiguous range, points being sorted); slices of one
+// cell are adjacent lanes and are summed with cross-lane shuffles.
+// ---------------------------------------------------------------------------
+template <int NCH>
+__global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restrict__ cs, double2* __restrict__ part)
+{
+    __shared__ double s_uh[kSpreadChunk];
+    __shared__ double s_ul[kSpreadChunk];
+    __shared__ double s_wr[kSpreadChunk];
+    __shared__ double s_wi[kSpreadChunk];
+    __shared__ double s_q[kSpreadChunk];
+    const Item I = P.aitems[blockIdx.x];
+    const ABlock B = P.ab[I.blk];
+    const int tid = threadIdx.x;
+    const int np = I.kb - I.ka;
+    const int w = P.w;
+    const int nch = P.nch;
+    const double inv_h = 1.0 / B.h;      // exact: h is a power of two
+    for (int i = tid; i < np; i += 256) {
+        int k = I.ka + i;
+        double r = P.rs[k];
+        double c = cs[k];
+        dd tp = two_sum(r, -B.C);
+        dd ph = two_prod(B.D, tp.hi);
+        double cth, sth;
+        cis_dd(ph.hi, __builtin_fma(B.D, tp.lo, ph.lo), cth, sth);
+        double q = B.r0 / r;
+        double w0 = c * sqrt(q);
+        s_uh[i] = tp.hi * inv_h;
+        s_ul[i] = tp.lo * inv_h;
+        s_wr[i] = w0 * cth;
+        s_wi[i] = w0 * sth;
+        s_q[i] = q;
+    }
+    __syncthreads();
+    const int sub_n = I.sub_n;
+    int slices = 1;
+    while (slices < 64 && slices * 2 * sub_n <= 256) slices <<= 1;
+    const int cells_par = 256 / slices;
+    const double hw = 0.5 * w;
+    const double two_over_w = 2.0 / w;
+    for (int cbase = 0; cbase < sub_n; cbase += cells_par) {
+        int cell = cbase + tid / slices;
+        int sl = tid & (slices - 1);
+        double ar[NCH], ai[NCH];
+        #pragma unroll
+        for (int p = 0; p < NCH; ++p) { ar[p] = 0.0; ai[p] = 0.0; }
+        if (cell < sub_n) {
+            double l = (double)(I.sub_lo + cell);
+            // first point with u > l - hw - 1 and first with u >= l + hw + 1
+            int lo = 0, hi = np;
+            double key = l - hw - 1.0;
+            while (lo < hi) { int mid = (lo + hi) >> 1; if (s_uh[mid] <= key) lo = mid + 1; else hi = mid; }
+            int first = lo;
+            lo = first; hi = np;
+            key = l + hw + 1.0;
+            while (lo < hi) { int mid = (lo + hi) >> 1; if (s_uh[mid] < key) lo = mid + 1; else hi = mid; }
+            int last = lo;
+            for (int i = first + sl; i < last; i += slices) {
+                double x = ((l - s_uh[i]) - s_ul[i]) * two_over_w;
+                if (fabs(x) < 1.0) {
+                    double phi = es_kernel(x, P.beta);
+                    double vr = phi * s_wr[i], vi = phi * s_wi[i];
+                    double q = s_q[i];
+                    #pragma unroll
+                    for (int p = 0; p < NCH; ++p) {
+                        if (p < nch) {
+                            ar[p] += vr;
+                            ai[p] += vi;
+                            vr *= q;
+                            vi *= q;
+                        }
+                    }
+                }
+            }
+        }
+        for (int o = slices >> 1; o >= 1; o >>= 1) {
+            #pragma unroll
+            for (int p = 0; p < NCH; ++p) {
+                ar[p] += __shfl_xor(ar[p], o);
+                ai[p] += __shfl_xor(ai[p], o);
+            }
+        }
+        if (cell < sub_n && sl == 0) {
+            double2* dst = part + I.off + (int64_t)cell * nch;
+            #pragma unroll
+            for (int p = 0; p < NCH; ++p)
+                if (p < nch) dst[p] = make_double2(ar[p], ai[p]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Grid assembly: each grid slot sums the item partials that cover it, in item
+// order.  Direct-sum-path grids are stored cell-major [cell][channel].  FFT
+// path: mode l of the spread grid is divided by the inner kernel's transform
+// psi^(l) = alpha2 ES^(|l| alpha2), alpha2 = w pi / N2 (the deconvolution of the
+// type-2 step) and placed at FFT index l mod N2, channel-major [channel][N2];
+// all other FFT inputs are zero.
+// ---------------------------------------------------------------------------
+__global__ void k_spread_reduce(PlanDev P, const double2* __restrict__ part, double2* __restrict__ grids,
+                                int64_t total_slots)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nch = P.nch;
+    if (t >= total_slots * nch) return;
+    int64_t slot = t / nch;
+    int p = (int)(t % nch);
+    // block owning this slot: the last block with grid_off / nch <= slot
+    int32_t lo = 0, hi = P.n_a - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if (P.ab[mid].grid_off / nch <= slot) lo = mid; else hi = mid - 1;
+    }
+    const ABlock B = P.ab[lo];
+    int64_t local = slot - B.grid_off / nch;
+    int32_t l;
+    if (B.fft) l = local < B.N2 / 2 ? (int32_t)local : (int32_t)(local - B.N2);
+    else l = B.llo + (int32_t)local;
+    double sr = 0.0, si = 0.0;
+    if (l >= B.llo && l < B.llo + B.N1) {
+        // items covering cell l: sub ranges increase with the item index
+        int32_t a = B.item0, b = B.item0 + B.nitems;   // first item whose end exceeds l
+        while (a < b) {
+            int32_t mid = (a + b) >> 1;
+            const Item& I = P.aitems[mid];
+            if (I.sub_lo + I.sub_n <= l) a = mid + 1; else b = mid;
+        }
+        for (int32_t it = a; it < B.item0 + B.nitems; ++it) {
+            const Item I = P.aitems[it];
+            if (I.sub_lo > l) break;
+            double2 v = part[I.off + (int64_t)(l - I.sub_lo) * nch + p];
+            sr += v.x;
+            si += v.y;
+        }
+    }
+    if (B.fft) {
+        double a2 = P.w * kPi / B.N2;
+        double s = 1.0 / (a2 * eshat(P, fabs((double)l) * a2));
+        grids[B.grid_off + (int64_t)p * B.N2 + local] = make_double2(sr * s, si * s);
+    } else {
+        grids[B.grid_off + local * nch + p] = make_double2(sr, si);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FFT: X[k] = sum_n x[n] e^{+2 pi i n k / N}, N a power of two, in LDS.
+// Stockham autosort, radix 4 (one radix-2 stage first when log2 N is odd).
+// Element (line, n) of the tile lives at sm[line * ls + n * es].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ void lds_fft(double2* sm, int N, int logN, int lines, int ls, int es)
+{
+    const int tid = threadIdx.x;
+    const int nt = blockDim.x;
+    int Ns = 1;
+    if (logN & 1) {
+        const int half = N >> 1;
+        const int nb = lines * half;
+        double2 v[16][2];
+        #pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            int b = tid + c * nt;
+            if (b < nb) {
+                int line = b / half, j = b - line * half;
+                v[c][0] = sm[line * ls + j * es];
+                v[c][1] = sm[line * ls + (j + half) * es];
+            }
+        }
+        __syncthreads();
+        #pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            int b = tid + c * nt;
+            if (b < nb) {
+                int line = b / half, j = b - line * half;
+                double2 a = v[c][0], d = v[c][1];
+                sm[line * ls + (2 * j) * es] = make_double2(a.x + d.x, a.y + d.y);
+                sm[line * ls + (2 * j + 1) * es] = make_double2(a.x - d.x, a.y - d.y);
+            }
+        }
+        __syncthreads();
+        Ns = 2;
+    }
+    const int q4 = N >> 2;
+    while (Ns < N) {
+        const int nb = lines * q4;
+        double2 v[8][4];
+        #pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            int b = tid + c * nt;
+            if (b < nb) {
+                int line = b / q4, j = b - line * q4;
+                #pragma unroll
+                for (int r = 0; r < 4; ++r) v[c][r] = sm[line * ls + (j + r * q4) * es];
+            }
+        }
+        __syncthreads();
+        #pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            int b = tid + c * nt;
+            if (b < nb) {
+                int line = b / q4, j = b - line * q4;
+                int k = j & (Ns - 1);
+                double s, co;
+                sincospi(2.0 * (double)k / (double)(4 * Ns), &s, &co);
+                double2 w1 = make_double2(co, s);
+                double2 w2 = cmul(w1, w1);
+                double2 w3 = cmul(w2, w1);
+                double2 x0 = v[c][0];
+                double2 x1 = cmul(v[c][1], w1);
+                double2 x2 = cmul(v[c][2], w2);
+                double2 x3 = cmul(v[c][3], w3);
+                double2 a0 = make_double2(x0.x + x2.x, x0.y + x2.y);
+                double2 a1 = make_double2(x0.x - x2.x, x0.y - x2.y);
+                double2 a2 = make_double2(x1.x + x3.x, x1.y + x3.y);
+                double2 a3 = make_double2(-(x1.y - x3.y), x1.x - x3.x);   // i (x1 - x3)
+                int d0 = (j - k) * 4 + k;
+                sm[line * ls + (d0) * es] = make_double2(a0.x + a2.x, a0.y + a2.y);
+                sm[line * ls + (d0 + Ns) * es] = make_double2(a1.x + a3.x, a1.y + a3.y);
+                sm[line * ls + (d0 + 2 * Ns) * es] = make_double2(a0.x - a2.x, a0.y - a2.y);
+                sm[line * ls + (d0 + 3 * Ns) * es] = make_double2(a1.x - a3.x, a1.y - a3.y);
+            }
+        }
+        __syncthreads();
+        Ns <<= 2;
+    }
+}
+
+// One transform of N <= 4096 points per block (block = (FFT-list slot, channel)).
+__global__ __launch_bounds__(256) void k_fft_small(PlanDev P, double2* __restrict__ grids, int first, int logN)
+{
+    extern __shared__ double2 sm[];
+    const int N = 1 << logN;
+    const int nch = P.nch;
+    int slot = blockIdx.x / nch, ch = blockIdx.x % nch;
+    const ABlock B = P.ab[P.fft_list[first + slot]];
+    double2* x = grids + B.grid_off + (int64_t)ch * N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) sm[i] = x[i];
+    __syncthreads();
+    lds_fft(sm, N, logN, 1, 0, 1);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) x[i] = sm[i];
+}
+
+// Two-pass FFT for N = N1 * N2 > 4096 (four-step): pass A transforms the N2
+// strided columns of length N1 and applies the twiddles e^{2 pi i n2 k1 / N};
+// pass B transforms the N1 rows of length N2 and writes X[k1 + N1 k2].
+__global__ __launch_bounds__(256) void k_fft_pass_a(PlanDev P, double2* __restrict__ grids,
+                                                    double2* __restrict__ scratch, int first, int logN, int logN1,
+                                                    int64_t scratch_off)
+{
+    extern __shared__ double2 sm[];
+    const int N = 1 << logN, N1 = 1 << logN1, N2 = N >> logN1;
+    const int nch = P.nch;
+    const int lines = (4096 / N1) < N2 ? (4096 / N1) : N2;
+    const int groups = N2 / lines;
+    int tr = blockIdx.x / groups, grp = blockIdx.x % groups;
+    int slot = tr / nch, ch = tr % nch;
+    const ABlock B = P.ab[P.fft_list[first + slot]];
+    double2* x = grids + B.grid_off + (int64_t)ch * N;
+    double2* y = scratch + scratch_off + (int64_t)tr * N;
+    int n2_0 = grp * lines;
+    for (int e = threadIdx.x; e < N1 * lines; e += blockDim.x) {
+        int n1 = e / lines, li = e - n1 * lines;
+        sm[n1 * lines + li] = x[(int64_t)n1 * N2 + n2_0 + li];
+    }
+    __syncthreads();
+    lds_fft(sm, N1, logN1, lines, 1, lines);
+    for (int e = threadIdx.x; e < N1 * lines; e += blockDim.x) {
+        int k1 = e / lines, li = e - k1 * lines;
+        int n2 = n2_0 + li;
+        double s, c;
+        sincospi(2.0 * (double)((int64_t)n2 * k1) / (double)N, &s, &c);
+        y[(int64_t)k1 * N2 + n2] = cmul(sm[k1 * lines + li], make_double2(c, s));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fft_pass_b(PlanDev P, double2* __restrict__ grids,
+                                                    const double2* __restrict__ scratch, int first, int logN,
+                                                    int logN1, int64_t scratch_off)
+{
+    extern __shared__ double2 sm[];
+    const int N = 1 << logN, N1 = 1 << logN1, N2 = N >> logN1;
+    const int logN2 = logN - logN1;
+    const int nch = P.nch;
+    const int lines = (4096 / N2) < N1 ? (4096 / N2) : N1;
+    const int groups = N1 / lines;
+    int tr = blockIdx.x / groups, grp = blockIdx.x % groups;
+    int slot = tr / nch, ch = tr % nch;
+    const ABlock B = P.ab[P.fft_list[first + slot]];
+    double2* x = grids + B.grid_off + (int64_t)ch * N;
+    const double2* y = scratch + scratch_off + (int64_t)tr * N;
+    int k1_0 = grp * lines;
+    for (int e = threadIdx.x; e < N2 * lines; e += blockDim.x) {
+        int li = e / N2, n2 = e - li * N2;
+        sm[li * N2 + n2] = y[(int64_t)(k1_0 + li) * N2 + n2];
+    }
+    __syncthreads();
+    lds_fft(sm, N2, logN2, lines, N2, 1);
+    for (int e = threadIdx.x; e < N2 * lines; e += blockDim.x) {
+        int k2 = e / lines, li = e - k2 * lines;
+        x[(int64_t)k1_0 + li + (int64_t)N1 * k2] = sm[li * N2 + k2];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Row side.
+// ---------------------------------------------------------------------------
+
+// Local block contribution at frequency om:  sum_{l=0}^{L} C_l(om R) t_l with
+//   C_l(x) = delta_l J_{nu/2+l}(x/2) J_{nu/2-l}(x/2)        (nu even, reading x/2)
+//   C_l(x) = 2 J_{(nu+1)/2+l}(x/2) J_{(nu-1)/2-l}(x/2)       (nu odd)
+// J_k(x/2) comes from Miller's backward recurrence.  Every product pairs a low
+// index i with the partner i + nu (orders of opposite sign, J_{-i} = (-1)^i J_i)
+// or nu - i, both produced at most nu steps earlier, so a ring of nu + 1 values
+// per thread (in LDS) suffices; the normalisation J_0^2 + 2 sum J_k^2 = 1 is
+// applied to the finished sum.
+__device__ double local_eval(const PlanDev& P, int lblk, double om, const double* __restrict__ lmom,
+                             double* __restrict__ ring, int stride)
+{
+    const LBlock B = P.lb[lblk];
+    double y = 0.5 * (om * B.R);
+    const double* t = lmom + (int64_t)lblk * (P.L + 1);
+    const int nu = P.nu, L = P.L;
+    const int odd = nu & 1;
+    const int a = odd ? (nu - 1) >> 1 : nu >> 1;
+    if (y < 1e-30) return nu == 0 ? t[0] : 0.0;
+    const int N = miller_start(y);
+    const int Bsz = nu + 1;
+    const double rec = 2.0 / y;
+    double yk1 = 0.0, yk = 1e-100, S2 = 0.0, dot = 0.0;
+    int slot = N % Bsz;
+    for (int i = N; i >= 0; --i) {
+        S2 = __builtin_fma(i == 0 ? yk : 2.0 * yk, yk, S2);
+        ring[slot * stride] = yk;
+        int l1 = i + a;
+        if (i >= 1 && l1 <= L && i + nu <= N) {
+            double pv = ring[(slot == 0 ? Bsz - 1 : slot - 1) * stride];
+            double coef = 2.0 * t[l1];
+            dot += ((i & 1) ? -coef : coef) * yk * pv;
+        }
+        if (i <= a && a - i <= L) {
+            int l2 = a - i;
+            double pv = ring[((nu - i) % Bsz) * stride];
+            double coef = (!odd && l2 == 0) ? t[0] : 2.0 * t[l2];
+            dot += coef * yk * pv;
+        }
+        if (i == 0) break;
+        double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
+        yk1 = yk;
+        yk = ykm1;
+        slot = slot == 0 ? Bsz - 1 : slot - 1;
+        if (fabs(yk) > 1e100) {
+            yk *= 1e-100; yk1 *= 1e-100; S2 *= 1e-200; dot *= 1e-200;
+            for (int s = 0; s < Bsz; ++s) ring[s * stride] *= 1e-100;
+        }
+    }
+    return dot / S2;
+}
+
+// Asymptotic block contribution at frequency om (Sec. 3.2):
+//   sqrt(2/pi) Re( e^{i phi} sum_p beta_p om^(-p-1/2) y_p ),
+//   beta_{2l} = (-1)^l a_{2l},  beta_{2l+1} = i (-1)^l a_{2l+1},
+// where y_p = sum_k x_k^(p) e^{i om r_k} is the type-3 sum of channel p.  With
+// s' = om - D and theta = s' h:  y_p = e^{i om C} h F_p(theta) / phi^(s'),
+// F_p(theta) = sum_l b_l^(p) e^{i l theta} evaluated directly over the cells
+// (direct-sum path) or from the FFT by ES interpolation (FFT path).
+template <int NCH>
+__device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2* __restrict__ grids)
+{
+    const ABlock B = P.ab[ablk];
+    const int nch = P.nch, w = P.w;
+    dd sp = two_sum(om, -B.D);
+    double ar[NCH], ai[NCH];
+    #pragma unroll
+    for (int p = 0; p < NCH; ++p) { ar[p] = 0.0; ai[p] = 0.0; }
+    if (!B.fft) {
+        const double2* G = grids + B.grid_off;
+        double th = sp.hi * B.h, tl = sp.lo * B.h;
+        dd a0 = two_prod((double)B.llo, th);
+        double zr, zi;
+        cis_dd(a0.hi, __builtin_fma((double)B.llo, tl, a0.lo), zr, zi);
+        double s1, c1;
+        sincos(th, &s1, &c1);
+        double er = c1 - tl * s1, ei = s1 + tl * c1;
+        for (int cix = 0; cix < B.N1; ++cix) {
+            const double2* gp = G + (int64_t)cix * nch;
+            #pragma unroll
+            for (int p = 0; p < NCH; ++p) {
+                if (p < nch) {
+                    double2 gv = gp[p];
+                    ar[p] += gv.x * zr - gv.y * zi;
+                    ai[p] += gv.x * zi + gv.y * zr;
+                }
+            }
+            double tr = zr * er - zi * ei;
+            zi = zr * ei + zi * er;
+            zr = tr;
+        }
+    } else {
+        const double2* Aq = grids + B.grid_off;
+        dd v = two_prod(sp.hi, B.Khi);
+        double vl = v.lo + (sp.lo * B.Khi + sp.hi * B.Klo);
+        int q0 = (int)ceil(v.hi - 0.5 * w);
+        const int mask = B.N2 - 1;
+        const double two_over_w = 2.0 / w;
+        for (int tap = 0; tap < w; ++tap) {
+            int q = q0 + tap;
+            double x = (((double)q - v.hi) - vl) * two_over_w;
+            double psi = es_kernel(x, P.beta);
+            int qi = q & mask;
+            #pragma unroll
+            for (int p = 0; p < NCH; ++p) {
+                if (p < nch) {
+                    double2 a = Aq[(int64_t)p * B.N2 + qi];
+                    ar[p] += psi * a.x;
+                    ai[p] += psi * a.y;
+                }
+            }
+        }
+        double sc = 2.0 * kPi / B.N2;
+        #pragma unroll
+        for (int p = 0; p < NCH; ++p) { ar[p] *= sc; ai[p] *= sc; }
+    }
+    double kap = fabs(sp.hi) * B.alpha;
+    double scale = B.h / (B.alpha * eshat(P, kap));
+    dd pc = two_prod(om, B.C);
+    dd s2 = two_sum(pc.hi, P.phi_hi);
+    double cr, ci;
+    cis_dd(s2.hi, s2.lo + pc.lo + P.phi_lo, cr, ci);
+    double gam = 1.0 / (om * B.r0);
+    double amp = sqrt(gam) * scale;
+    double zr = 0.0, zi = 0.0;
+    #pragma unroll
+    for (int p = 0; p < NCH; ++p) {
+        if (p < nch) {
+            int l = p >> 1;
+            double coef = ((l & 1) ? -P.hank[p] : P.hank[p]) * amp;
+            if (p & 1) { zr -= coef * ai[p]; zi += coef * ar[p]; }
+            else { zr += coef * ar[p]; zi += coef * ai[p]; }
+            amp *= gam;
+        }
+    }
+    return kSqrt2OverPi * (cr * zr - ci * zi);
+}
+
+__device__ double direct_eval(const PlanDev& P, int dblk, double om, const double* __restrict__ cs)
+{
+    const DBlock D = P.db[dblk];
+    double acc = 0.0;
+    for (int k = D.k0; k <= D.k1; ++k) {
+        dd x = two_prod(om, P.rs[k]);
+        acc += cs[k] * besselj_eps(P, x.hi, x.lo);
+    }
+    return acc;
+}
+
+// One thread per sorted frequency: walk the tree from the root.  At a node the
+// row lies either in the local side (rows j0..js) -- local block, then the
+// upper-right child -- or in the asymptotic side -- asymptotic block, then the
+// lower-left child.  A direct child ends the walk.
+template <int NCH>
+__global__ void k_rows(PlanDev P, const double* __restrict__ cs, const double* __restrict__ lmom,
+                       const double2* __restrict__ grids, double* __restrict__ g)
+{
+    extern __shared__ double ring_all[];
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= P.m) return;
+    double* ring = ring_all + threadIdx.x;
+    const int stride = blockDim.x;
+    double om = P.ws[j];
+    double acc = 0.0;
+    int node = P.n_nodes > 0 ? 0 : -1;
+    while (node >= 0) {
+        const Node nd = P.nodes[node];
+        int child;
+        if (j <= nd.js) {
+            if (nd.lblk >= 0) acc += local_eval(P, nd.lblk, om, lmom, ring, stride);
+            child = nd.ur;
+        } else {
+            if (nd.ablk >= 0) acc += asym_eval<NCH>(P, nd.ablk, om, grids);
+            child = nd.ll;
+        }
+        if (child <= -2) {
+            acc += direct_eval(P, decode_direct(child), om, cs);
+            break;
+        }
+        node = child;
+    }
+    g[P.perm_w[j]] = P.sign * acc;
+}
+
+// Brute-force reference: one thread per frequency, all points.
+__global__ void k_direct_all(PlanDev P, const double* __restrict__ r, const double* __restrict__ c, int32_t n,
+                             const double* __restrict__ w, int32_t m, double* __restrict__ g)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    double om = w[j];
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) {
+        dd x = two_prod(om, r[k]);
+        acc += c[k] * besselj_eps(P, x.hi, x.lo);
+    }
+    g[j] = P.sign * acc;
+}
+
+// ---------------------------------------------------------------------------
+static inline int cdiv64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+template <int NCH>
+static void launch_nch(const PlanDev& P, const Summary& S, const ExecBuffers& B, double* g, hipStream_t s)
+{
+    if (S.n_aitems > 0)
+        hipLaunchKernelGGL(k_spread<NCH>, dim3(S.n_aitems), dim3(256), 0, s, P, B.cs, B.part);
+    if (B.grid_cells > 0)
+        hipLaunchKernelGGL(k_spread_reduce, dim3(cdiv64(B.grid_cells * P.nch, 256)), dim3(256), 0, s, P, B.part,
+                           B.grids, B.grid_cells);
+}
+
+template <int NCH>
+static void launch_rows(const PlanDev& P, const ExecBuffers& B, double* g, hipStream_t s)
+{
+    int bs = (P.nu + 1) * 256 * 8 <= 65536 ? 256 : 64;
+    size_t lds = (size_t)(P.nu + 1) * bs * sizeof(double);
+    hipLaunchKernelGGL(k_rows<NCH>, dim3(cdiv64(P.m, bs)), dim3(bs), lds, s, P, B.cs, B.lmom, B.grids, g);
+}
+
+hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers& B, const FftClass* cls, int ncls,
+                          const double* c, double* g, hipStream_t s)
+{
+    if (P.m == 0) return hipSuccess;
+    if (P.n == 0) {
+        return hipMemsetAsync(g, 0, sizeof(double) * (size_t)P.m, s);
+    }
+    hipLaunchKernelGGL(k_gather, dim3(cdiv64(P.n, 256)), dim3(256), 0, s, c, P.perm_r, P.n, B.cs);
+    if (S.n_litems > 0) {
+        hipLaunchKernelGGL(k_lmom, dim3(S.n_litems), dim3(256), 0, s, P, B.cs, B.lpart);
+        hipLaunchKernelGGL(k_lmom_reduce, dim3(cdiv64((int64_t)S.n_l * (P.L + 1), 256)), dim3(256), 0, s, P,
+                           B.lpart, B.lmom);
+    }
+    if (P.nch <= 8) launch_nch<8>(P, S, B, g, s);
+    else if (P.nch <= 16) launch_nch<16>(P, S, B, g, s);
+    else if (P.nch <= 24) launch_nch<24>(P, S, B, g, s);
+    else if (P.nch <= 32) launch_nch<32>(P, S, B, g, s);
+    else launch_nch<40>(P, S, B, g, s);
+    for (int q = 0; q < ncls; ++q) {
+        const FftClass& C = cls[q];
+        int ntr = C.count * P.nch;
+        if (C.log2n <= 12) {
+            hipLaunchKernelGGL(k_fft_small, dim3(ntr), dim3(256), sizeof(double2) << C.log2n, s, P, B.grids,
+                               C.first, C.log2n);
+        } else {
+            int logN1 = C.log2n / 2;
+            int N1 = 1 << logN1, N2 = 1 << (C.log2n - logN1);
+            int la = (4096 / N1) < N2 ? (4096 / N1) : N2;
+            int lb = (4096 / N2) < N1 ? (4096 / N2) : N1;
+            hipLaunchKernelGGL(k_fft_pass_a, dim3(ntr * (N2 / la)), dim3(256), sizeof(double2) * N1 * la, s, P,
+                               B.grids, B.scratch, C.first, C.log2n, logN1, C.scratch_off);
+            hipLaunchKernelGGL(k_fft_pass_b, dim3(ntr * (N1 / lb)), dim3(256), sizeof(double2) * N2 * lb, s, P,
+                               B.grids, B.scratch, C.first, C.log2n, logN1, C.scratch_off);
+        }
+    }
+    if (P.nch <= 8) launch_rows<8>(P, B, g, s);
+    else if (P.nch <= 16) launch_rows<16>(P, B, g, s);
+    else if (P.nch <= 24) launch_rows<24>(P, B, g, s);
+    else if (P.nch <= 32) launch_rows<32>(P, B, g, s);
+    else launch_rows<40>(P, B, g, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_direct(const PlanDev& P, const double* r, const double* c, int32_t n, const double* w, int32_t m,
+                         double* g, hipStream_t s)
+{
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_direct_all, dim3(cdiv64(m, 128)), dim3(128), 0, s, P, r, c, n, w, m, g);
+    return hipGetLastError();
+}
+
+}  // namespace nuht

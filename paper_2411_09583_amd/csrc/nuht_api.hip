@@ -1,0 +1,556 @@
+// nuht_api.hip -- host side of libnuht: expansion parameters (Sec. 3.3), ES
+// kernel set-up, plan construction (sort, staircase, Alg. 1) and the C ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "nuht.h"
+#include "nuht_launch.h"
+
+namespace nuht {
+
+// ===========================================================================
+// Expansion parameters (Sec. 3.3).
+// ===========================================================================
+
+// M = min(floor(1 + nu/5 - log10(eps)/4), 20)   (eq. num-asy-terms)
+static int num_asy_terms(int nu, double eps)
+{
+    int M = (int)std::floor(1.0 + std::fabs((double)nu) / 5.0 - std::log10(eps) / 4.0);
+    return std::min(std::max(M, 1), 20);
+}
+
+// a_l(nu) = prod_{s=1}^{l} (4 nu^2 - (2s-1)^2) / (l! 8^l)   (Sec. 3.2)
+static double hankel_coef(double nu, int l)
+{
+    double a = 1.0;
+    for (int s = 1; s <= l; ++s) {
+        double f = 2.0 * s - 1.0;
+        a *= (4.0 * nu * nu - f * f) / (8.0 * s);
+    }
+    return a;
+}
+
+// Newton's method on xi(z) = B^asy(z) - eps, B^asy the first-neglected-terms
+// bound of eq. asy-error.  xi is convex and decreasing; the iteration starts at
+// the root of the first term alone, left of the root, and increases to it.
+static double crossover(int nu, double eps, int M)
+{
+    const double s2p = std::sqrt(2.0 / M_PI);
+    double a0 = s2p * std::fabs(hankel_coef(nu, 2 * M));
+    double a1 = s2p * std::fabs(hankel_coef(nu, 2 * M + 1));
+    double p0 = 2.0 * M + 0.5, p1 = 2.0 * M + 1.5;
+    double z = std::pow(a0 / eps, 1.0 / p0);
+    for (int it = 0; it < 200; ++it) {
+        double xi = a0 * std::pow(z, -p0) + a1 * std::pow(z, -p1) - eps;
+        double dxi = -p0 * a0 * std::pow(z, -p0 - 1.0) - p1 * a1 * std::pow(z, -p1 - 1.0);
+        double zn = z - xi / dxi;
+        if (std::fabs(zn - z) <= 1e-15 * z) return zn;
+        z = zn;
+    }
+    return z;
+}
+
+// psi(p) = log p + sqrt(1-p^2) - log(1 + sqrt(1-p^2))   (Lemma 3.1)
+static double psi_fn(double p)
+{
+    double s = std::sqrt(1.0 - p * p);
+    return std::log(p) + s - std::log1p(s);
+}
+
+// Truncation bound of the Wimp expansion with terms l = 0..L on omega r <= z.
+// Even nu: Lemma 3.1.  Odd nu: the same argument for the odd-order expansion
+// sum_l 2 J_{(nu+1)/2+l}(x/2) J_{(nu-1)/2-l}(x/2) T_{2l+1}(y).  Outside the
+// Lemma's hypotheses the bound is +inf.
+static double local_bound(int nu, int L, double z)
+{
+    nu = std::abs(nu);
+    double db, dg, lb, lg;
+    bool g_applies;
+    if (nu % 2 == 0) {
+        db = 2.0 * L + 2 + nu; dg = 2.0 * L + 2 - nu; g_applies = (L + 1) >= nu / 2.0;
+        lb = nu / 2.0; lg = nu / 2.0;
+    } else {
+        db = 2.0 * L + 3 + nu; dg = 2.0 * L + 3 - nu; g_applies = dg > 0;
+        lb = (nu + 1) / 2.0; lg = (nu - 1) / 2.0;
+    }
+    double pb = z / db;
+    if (pb >= 1.0) return INFINITY;
+    double beta = psi_fn(pb), gamma = 0.0;
+    if (g_applies) {
+        if (dg <= 0.0) return INFINITY;
+        double pg = z / dg;
+        if (pg >= 1.0) return INFINITY;
+        gamma = psi_fn(pg);
+    }
+    if (beta + gamma >= 0.0) return INFINITY;
+    return 2.0 * std::exp(lb * beta - lg * gamma + (L + 1) * (beta + gamma)) / (1.0 - std::exp(beta + gamma));
+}
+
+static int local_rank(int nu, double eps, double z)
+{
+    for (int L = 0; L < 100000; ++L)
+        if (local_bound(nu, L, z) < eps) return L;
+    return -1;
+}
+
+// ===========================================================================
+// Exponential-of-semicircle kernel: width and shape from eps, and the
+// Chebyshev series of its Fourier transform ES^(kappa) on [0, w pi / 4].
+// ===========================================================================
+static int es_width(double eps, int precision)
+{
+    int digits = (int)std::ceil(-std::log10(eps) - 1e-9);
+    int w = precision == NUHT_FP32_SPREAD ? digits + 1 : digits + 2;
+    return std::min(std::max(w, 4), 17);
+}
+
+static double es_beta(int w) { return 2.30 * w; }
+
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& wt)
+{
+    x.resize(n);
+    wt.resize(n);
+    for (int i = 0; i < n; ++i) {
+        double t = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = t;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+                p0 = p1; p1 = p2;
+            }
+            double dp = n * (t * p1 - p0) / (t * t - 1.0);
+            double dt = p1 / dp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = t;
+        for (int k = 2; k <= n; ++k) {
+            double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+            p0 = p1; p1 = p2;
+        }
+        double dp = n * (t * p1 - p0) / (t * t - 1.0);
+        x[i] = t;
+        wt[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+    }
+}
+
+static void eshat_chebyshev(int w, double beta, double kappa_max, double* coef, int nc)
+{
+    std::vector<double> x, wt;
+    gauss_legendre(240, x, wt);
+    std::vector<double> f(nc);
+    for (int j = 0; j < nc; ++j) {
+        double t = std::cos(M_PI * (j + 0.5) / nc);
+        double kappa = 0.5 * (t + 1.0) * kappa_max;
+        long double s = 0.0L;
+        for (size_t i = 0; i < x.size(); ++i) {
+            double xx = x[i];
+            double es = std::exp(beta * (std::sqrt(std::max(0.0, 1.0 - xx * xx)) - 1.0));
+            s += (long double)wt[i] * es * std::cos(kappa * xx);
+        }
+        f[j] = (double)s;
+    }
+    for (int k = 0; k < nc; ++k) {
+        long double s = 0.0L;
+        for (int j = 0; j < nc; ++j) s += (long double)f[j] * std::cos(M_PI * k * (j + 0.5) / nc);
+        coef[k] = (double)(2.0L * s / nc);
+    }
+    coef[0] *= 0.5;
+    (void)w;
+}
+
+// -(2nu+1) pi/4 modulo 2 pi as a double-double in (0, 2 pi].
+static void phase_offset(int nu, double& hi, double& lo)
+{
+    int k = 8 - ((2 * nu + 1) % 8);           // -(2nu+1) = k - 8(...)  (mod 8)
+    const double q_hi = 0.78539816339744827900;   // pi/4 rounded
+    const double q_lo = 3.0616169978683830e-17;   // pi/4 - q_hi
+    double p = k * q_hi;                           // exact: k <= 8
+    hi = p;
+    lo = k * q_lo;
+}
+
+// ===========================================================================
+// Plan.
+// ===========================================================================
+struct Geometry {
+    int32_t n = 0, m = 0;
+    const double* rs = nullptr;
+    const double* ws = nullptr;
+    const int32_t* perm_r = nullptr;
+    const int32_t* perm_w = nullptr;
+};
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Partition {
+    bool built = false;
+    PlanDev P{};
+    Summary sum{};
+    std::vector<FftClass> cls;
+    ExecBuffers B{};
+    Arena A{};
+    std::vector<DevBuf> bufs;
+    int64_t bytes = 0;
+
+    void release()
+    {
+        for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
+        bufs.clear();
+        bytes = 0;
+        built = false;
+        cls.clear();
+        B = ExecBuffers{};
+        A = Arena{};
+    }
+    template <class T>
+    int alloc(T*& out, size_t count)
+    {
+        out = nullptr;
+        if (count == 0) return NUHT_OK;
+        void* p = nullptr;
+        size_t bytes_ = count * sizeof(T);
+        if (hipMalloc(&p, bytes_) != hipSuccess) { (void)hipGetLastError(); return NUHT_ENOMEM; }
+        bufs.push_back({p, bytes_});
+        bytes += (int64_t)bytes_;
+        out = (T*)p;
+        return NUHT_OK;
+    }
+    ~Partition() { release(); }
+};
+
+}  // namespace nuht
+
+using namespace nuht;
+
+struct nuht_plan_s {
+    int nu_req = 0;
+    double eps = 0.0;
+    nuht_opts opts{};
+    int64_t n = 0, m = 0;
+    uint64_t* keys = nullptr;    // sorted points then sorted frequencies (bit patterns)
+    int32_t* vals = nullptr;     // matching caller indices
+    uint64_t* keys2 = nullptr;
+    int32_t* vals2 = nullptr;
+    int32_t* hist = nullptr;
+    Summary* d_sum = nullptr;
+    Summary* h_sum = nullptr;    // pinned
+    int64_t geom_bytes = 0;
+    Geometry fwd, adj;
+    Partition pf, pa;
+};
+
+#define HIP_TRY(x)                                   \
+    do {                                             \
+        hipError_t e_ = (x);                         \
+        if (e_ != hipSuccess) { (void)hipGetLastError(); return NUHT_EHIP; } \
+    } while (0)
+
+#define NUHT_TRY(x)                                  \
+    do {                                             \
+        int r_ = (x);                                \
+        if (r_ != NUHT_OK) return r_;                \
+    } while (0)
+
+static void fill_params(PlanDev& P, int nu, double eps, const nuht_opts& o)
+{
+    int anu = std::abs(nu);
+    P.nu = anu;
+    P.sign = (nu < 0 && (anu & 1)) ? -1 : 1;
+    P.eps = eps;
+    int M = o.M_override > 0 ? std::min(o.M_override, 20) : num_asy_terms(anu, eps);
+    P.M = M;
+    P.nch = 2 * M;
+    P.z = crossover(anu, eps, M);
+    P.L = local_rank(anu, eps, P.z);
+    P.w = es_width(eps, o.precision);
+    P.beta = es_beta(P.w);
+    for (int p = 0; p < 2 * M + 2; ++p) P.hank[p] = hankel_coef(anu, p);
+    phase_offset(anu, P.phi_hi, P.phi_lo);
+    P.kappa_max = P.w * M_PI / 4.0 * (1.0 + 1e-9);
+    P.n_eshat = 30;
+    eshat_chebyshev(P.w, P.beta, P.kappa_max, P.eshat, P.n_eshat);
+}
+
+static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int nu, hipStream_t s)
+{
+    Pt.release();
+    const nuht_opts& o = pl->opts;
+    PlanDev& P = Pt.P;
+    P = PlanDev{};
+    fill_params(P, nu, pl->eps, o);
+    if (P.L < 0) return NUHT_EINVAL;
+    P.n = G.n; P.m = G.m;
+    P.rs = G.rs; P.ws = G.ws; P.perm_r = G.perm_r; P.perm_w = G.perm_w;
+    Pt.sum = Summary{};
+    if (G.n == 0 || G.m == 0) { Pt.built = true; return NUHT_OK; }
+
+    int64_t min_size = o.min_size > 0 ? o.min_size : 1024;
+    int ncand = o.split_candidates > 1 ? o.split_candidates : 16;
+    int dft_max = o.dft_max == 0 ? 48 : o.dft_max;
+    const double sigma = 2.0;
+
+    int32_t* K = nullptr;
+    NUHT_TRY(Pt.alloc(K, (size_t)G.m));
+    HIP_TRY(launch_staircase(G.rs, G.n, G.ws, G.m, P.z, K, s));
+
+    int64_t tot = (int64_t)G.n + G.m;
+    int32_t cap = (int32_t)std::min<int64_t>(tot / 32 + 4096, 1 << 28);
+    int32_t icap = (int32_t)std::min<int64_t>(64 * (tot / kSpreadChunk) + 2 * (int64_t)cap, 1 << 28);
+    Summary& S = Pt.sum;
+    for (int attempt = 0; attempt < 6; ++attempt) {
+        // tables of this attempt (freed on retry by rebuilding the buffer list)
+        Partition tmp;   // scratch holder for the arena so a retry frees it
+        Arena A{};
+        A.node_cap = cap; A.l_cap = cap; A.a_cap = cap; A.d_cap = 2 * cap; A.q_cap = cap;
+        A.litem_cap = icap; A.aitem_cap = icap;
+        NUHT_TRY(tmp.alloc(A.nodes, (size_t)A.node_cap));
+        NUHT_TRY(tmp.alloc(A.lb, (size_t)A.l_cap));
+        NUHT_TRY(tmp.alloc(A.ab, (size_t)A.a_cap));
+        NUHT_TRY(tmp.alloc(A.db, (size_t)A.d_cap));
+        NUHT_TRY(tmp.alloc(A.q0, (size_t)A.q_cap));
+        NUHT_TRY(tmp.alloc(A.q1, (size_t)A.q_cap));
+        NUHT_TRY(tmp.alloc(A.litems, (size_t)A.litem_cap));
+        NUHT_TRY(tmp.alloc(A.aitems, (size_t)A.aitem_cap));
+        NUHT_TRY(tmp.alloc(A.fft_list, (size_t)A.a_cap));
+        HIP_TRY(hipMemsetAsync(pl->d_sum, 0, sizeof(Summary), s));
+        HIP_TRY(launch_subdivide(K, G.m, G.n, min_size, ncand, A, pl->d_sum, s));
+        HIP_TRY(hipMemcpyAsync(pl->h_sum, pl->d_sum, sizeof(Summary), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        S = *pl->h_sum;
+        if (S.overflow == 2) return NUHT_ECAPACITY;   // subdivision deeper than kMaxLevels
+        if (S.overflow) {
+            int64_t need = std::max<int64_t>({(int64_t)S.n_nodes, (int64_t)S.n_l, (int64_t)S.n_a, (int64_t)S.n_d / 2,
+                                              (int64_t)cap * 4});
+            cap = (int32_t)std::min<int64_t>(need + 1024, 1 << 29);
+            continue;
+        }
+        int64_t* a_sizes = nullptr;
+        int32_t* l_sizes = nullptr;
+        NUHT_TRY(tmp.alloc(a_sizes, (size_t)4 * std::max(S.n_a, 1)));
+        NUHT_TRY(tmp.alloc(l_sizes, (size_t)std::max(S.n_l, 1)));
+        P.nodes = A.nodes; P.lb = A.lb; P.ab = A.ab; P.db = A.db;
+        P.litems = A.litems; P.aitems = A.aitems; P.fft_list = A.fft_list;
+        HIP_TRY(launch_block_params(P, A, S.n_l, S.n_a, dft_max, sigma, a_sizes, l_sizes, pl->d_sum, s));
+        HIP_TRY(launch_plan_scan(P, A, S.n_l, S.n_a, S.n_d, a_sizes, l_sizes, pl->d_sum, s));
+        HIP_TRY(launch_fill_items(P, A, S.n_l, S.n_a, s));
+        HIP_TRY(hipMemcpyAsync(pl->h_sum, pl->d_sum, sizeof(Summary), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        S = *pl->h_sum;
+        if (S.grid_error) return NUHT_ECAPACITY;
+        if (S.overflow) {
+            int64_t need = std::max<int64_t>({(int64_t)S.n_litems, (int64_t)S.n_aitems, (int64_t)icap * 4});
+            icap = (int32_t)std::min<int64_t>(need + 1024, 1 << 29);
+            continue;
+        }
+        // keep this attempt's tables
+        for (auto& b : tmp.bufs) Pt.bufs.push_back(b);
+        Pt.bytes += tmp.bytes;
+        tmp.bufs.clear();
+        tmp.bytes = 0;
+        Pt.A = A;
+        break;
+    }
+    if (S.overflow) return NUHT_ECAPACITY;
+    P.n_nodes = S.n_nodes; P.n_l = S.n_l; P.n_a = S.n_a; P.n_d = S.n_d;
+    P.n_litems = S.n_litems; P.n_aitems = S.n_aitems;
+
+    // execution buffers
+    ExecBuffers& B = Pt.B;
+    NUHT_TRY(Pt.alloc(B.cs, (size_t)G.n));
+    NUHT_TRY(Pt.alloc(B.lpart, (size_t)S.n_litems * (P.L + 1)));
+    NUHT_TRY(Pt.alloc(B.lmom, (size_t)S.n_l * (P.L + 1)));
+    NUHT_TRY(Pt.alloc(B.part, (size_t)S.part_cells * P.nch));
+    NUHT_TRY(Pt.alloc(B.grids, (size_t)S.grid_cells * P.nch));
+    B.grid_cells = S.grid_cells;
+    int64_t scratch = 0;
+    for (int c = 6; c <= kMaxFftLog2; ++c) {
+        if (S.fft_count[c] == 0) continue;
+        FftClass fc;
+        fc.log2n = c; fc.count = S.fft_count[c]; fc.first = S.fft_first[c];
+        fc.scratch_off = scratch;
+        if (c > 12) scratch += (int64_t)fc.count * P.nch << c;
+        Pt.cls.push_back(fc);
+    }
+    NUHT_TRY(Pt.alloc(B.scratch, (size_t)scratch));
+    Pt.built = true;
+    return NUHT_OK;
+}
+
+static void free_plan(nuht_plan_t p)
+{
+    if (!p) return;
+    p->pf.release();
+    p->pa.release();
+    if (p->keys) (void)hipFree(p->keys);
+    if (p->vals) (void)hipFree(p->vals);
+    if (p->keys2) (void)hipFree(p->keys2);
+    if (p->vals2) (void)hipFree(p->vals2);
+    if (p->hist) (void)hipFree(p->hist);
+    if (p->d_sum) (void)hipFree(p->d_sum);
+    if (p->h_sum) (void)hipHostFree(p->h_sum);
+    delete p;
+}
+
+static bool valid_common(int nu, double eps)
+{
+    if (nu < -100 || nu > 100) return false;
+    if (!(eps >= 1e-15 && eps <= 1e-2)) return false;
+    return true;
+}
+
+extern "C" {
+
+const char* nuht_strerror(int code)
+{
+    switch (code) {
+        case NUHT_OK: return "success";
+        case NUHT_EINVAL: return "invalid argument";
+        case NUHT_EDOMAIN: return "a point or frequency is negative, NaN or infinite";
+        case NUHT_EPRECISION: return "FP32 spreading needs eps >= 1e-7";
+        case NUHT_ENOMEM: return "device allocation failed";
+        case NUHT_EHIP: return "HIP runtime error";
+        case NUHT_ECAPACITY: return "partition exceeds internal table limits";
+        default: return "unknown error";
+    }
+}
+
+int nuht_plan(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_dev, int64_t m,
+              const double* omega_dev, const nuht_opts* opts, void* stream)
+{
+    if (!out) return NUHT_EINVAL;
+    *out = nullptr;
+    if (!valid_common(nu, eps)) return NUHT_EINVAL;
+    if (n < 0 || m < 0 || n > INT32_MAX / 2 || m > INT32_MAX / 2) return NUHT_EINVAL;
+    if ((n > 0 && !r_dev) || (m > 0 && !omega_dev)) return NUHT_EINVAL;
+    nuht_opts o{};
+    if (opts) o = *opts;
+    if (o.precision != NUHT_FP64 && o.precision != NUHT_FP32_SPREAD) return NUHT_EINVAL;
+    if (o.precision == NUHT_FP32_SPREAD) return NUHT_EPRECISION;   // FP64 path only in this build
+    if (o.min_size < 0 || o.M_override < 0 || o.M_override > 20 || o.split_candidates < 0) return NUHT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+
+    nuht_plan_s* p = new (std::nothrow) nuht_plan_s();
+    if (!p) return NUHT_ENOMEM;
+    p->nu_req = nu; p->eps = eps; p->opts = o; p->n = n; p->m = m;
+    int64_t tot = n + m;
+    auto fail = [&](int code) { free_plan(p); return code; };
+    if (hipMalloc(&p->d_sum, sizeof(Summary)) != hipSuccess) return fail(NUHT_ENOMEM);
+    if (hipHostMalloc(&p->h_sum, sizeof(Summary), hipHostMallocDefault) != hipSuccess) return fail(NUHT_ENOMEM);
+    if (tot > 0) {
+        if (hipMalloc(&p->keys, sizeof(uint64_t) * tot) != hipSuccess) return fail(NUHT_ENOMEM);
+        if (hipMalloc(&p->vals, sizeof(int32_t) * tot) != hipSuccess) return fail(NUHT_ENOMEM);
+        if (hipMalloc(&p->keys2, sizeof(uint64_t) * tot) != hipSuccess) return fail(NUHT_ENOMEM);
+        if (hipMalloc(&p->vals2, sizeof(int32_t) * tot) != hipSuccess) return fail(NUHT_ENOMEM);
+        if (hipMalloc(&p->hist, sizeof(int32_t) * sort_hist_len((int32_t)n, (int32_t)m)) != hipSuccess)
+            return fail(NUHT_ENOMEM);
+        p->geom_bytes = (int64_t)tot * 24;
+    }
+    if (hipMemsetAsync(p->d_sum, 0, sizeof(Summary), s) != hipSuccess) return fail(NUHT_EHIP);
+    int32_t* err = &p->d_sum->domain_error;
+    if (launch_make_keys(r_dev, (int32_t)n, p->keys, p->vals, err, s) != hipSuccess) return fail(NUHT_EHIP);
+    if (launch_make_keys(omega_dev, (int32_t)m, p->keys + n, p->vals + n, err, s) != hipSuccess)
+        return fail(NUHT_EHIP);
+    if (launch_sort_pairs(p->keys, p->vals, p->keys2, p->vals2, p->hist, (int32_t)n, (int32_t)m, s) != hipSuccess)
+        return fail(NUHT_EHIP);
+    if (hipMemcpyAsync(p->h_sum, p->d_sum, sizeof(Summary), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return fail(NUHT_EHIP);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(NUHT_EHIP);
+    if (p->h_sum->domain_error) return fail(NUHT_EDOMAIN);
+    // the value half of the sort was made against the per-segment origin
+    p->fwd.n = (int32_t)n; p->fwd.m = (int32_t)m;
+    p->fwd.rs = (const double*)p->keys;
+    p->fwd.ws = (const double*)(p->keys + n);
+    p->fwd.perm_r = p->vals;
+    p->fwd.perm_w = p->vals + n;
+    p->adj.n = (int32_t)m; p->adj.m = (int32_t)n;
+    p->adj.rs = p->fwd.ws; p->adj.ws = p->fwd.rs;
+    p->adj.perm_r = p->fwd.perm_w; p->adj.perm_w = p->fwd.perm_r;
+    int rc = build_partition(p, p->pf, p->fwd, nu, s);
+    if (rc != NUHT_OK) return fail(rc);
+    *out = p;
+    return NUHT_OK;
+}
+
+int nuht_execute(nuht_plan_t p, const double* c_dev, double* g_dev, void* stream)
+{
+    if (!p || !p->pf.built) return NUHT_EINVAL;
+    if ((p->n > 0 && !c_dev) || (p->m > 0 && !g_dev)) return NUHT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const Partition& Pt = p->pf;
+    HIP_TRY(launch_execute(Pt.P, Pt.sum, Pt.B, Pt.cls.data(), (int)Pt.cls.size(), c_dev, g_dev, s));
+    return NUHT_OK;
+}
+
+int nuht_adjoint(nuht_plan_t p, const double* y_dev, double* cbar_dev, void* stream)
+{
+    if (!p || !p->pf.built) return NUHT_EINVAL;
+    if ((p->m > 0 && !y_dev) || (p->n > 0 && !cbar_dev)) return NUHT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (!p->pa.built) {
+        int rc = build_partition(p, p->pa, p->adj, p->nu_req, s);
+        if (rc != NUHT_OK) return rc;
+    }
+    const Partition& Pt = p->pa;
+    HIP_TRY(launch_execute(Pt.P, Pt.sum, Pt.B, Pt.cls.data(), (int)Pt.cls.size(), y_dev, cbar_dev, s));
+    return NUHT_OK;
+}
+
+int nuht_plan_set_order(nuht_plan_t p, int nu, void* stream)
+{
+    if (!p) return NUHT_EINVAL;
+    if (!valid_common(nu, p->eps)) return NUHT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    p->pa.release();
+    p->nu_req = nu;
+    return build_partition(p, p->pf, p->fwd, nu, s);
+}
+
+int nuht_plan_info(nuht_plan_t p, nuht_info* info)
+{
+    if (!p || !info || !p->pf.built) return NUHT_EINVAL;
+    const Partition& Pt = p->pf;
+    const PlanDev& P = Pt.P;
+    const Summary& S = Pt.sum;
+    std::memset(info, 0, sizeof(*info));
+    info->nu = p->nu_req; info->M = P.M; info->L = P.L; info->es_width = P.w;
+    info->eps = P.eps; info->z = P.z; info->es_beta = P.beta;
+    info->levels = S.levels; info->n_nodes = S.n_nodes; info->n_local = S.n_l; info->n_asy = S.n_a;
+    info->n_direct = S.n_d; info->n_fft_blocks = S.n_fft;
+    info->local_row_members = S.l_row; info->local_col_members = S.l_col;
+    info->asy_row_members = S.a_row; info->asy_col_members = S.a_col;
+    info->direct_entries = S.d_ent;
+    info->grid_cells = S.grid_cells; info->fft_points = S.fft_points;
+    info->workspace_bytes = p->geom_bytes + p->pf.bytes + p->pa.bytes;
+    return NUHT_OK;
+}
+
+int nuht_destroy(nuht_plan_t p)
+{
+    free_plan(p);
+    return NUHT_OK;
+}
+
+int nuht_direct(int nu, double eps, int64_t n, const double* r_dev, const double* c_dev, int64_t m,
+                const double* omega_dev, double* g_dev, void* stream)
+{
+    if (!valid_common(nu, eps)) return NUHT_EINVAL;
+    if (n < 0 || m < 0 || n > INT32_MAX || m > INT32_MAX) return NUHT_EINVAL;
+    if ((n > 0 && (!r_dev || !c_dev)) || (m > 0 && (!omega_dev || !g_dev))) return NUHT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    PlanDev P{};
+    nuht_opts o{};
+    fill_params(P, nu, eps, o);
+    if (m == 0) return NUHT_OK;
+    if (n == 0) { HIP_TRY(hipMemsetAsync(g_dev, 0, sizeof(double) * (size_t)m, s)); return NUHT_OK; }
+    HIP_TRY(launch_direct(P, r_dev, c_dev, (int32_t)n, omega_dev, (int32_t)m, g_dev, s));
+    return NUHT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+// nuht_device.h -- device helpers: double-double arithmetic, phase reduction,
+// the exponential-of-semicircle kernel, and Bessel-function evaluation.
+#pragma once
+
+#include "nuht_internal.h"
+
+namespace nuht {
+
+struct dd {
+    double hi, lo;
+};
+
+// a*b == hi + lo exactly (TwoProduct with a fused multiply-add).
+__device__ __forceinline__ dd two_prod(double a, double b)
+{
+    double p = a * b;
+    return {p, __builtin_fma(a, b, -p)};
+}
+
+// a+b == hi + lo exactly (Knuth's TwoSum).
+__device__ __forceinline__ dd two_sum(double a, double b)
+{
+    double s = a + b;
+    double bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+
+constexpr double kTwoPiHi = 6.283185307179586232;        // 2 pi rounded to double
+constexpr double kTwoPiLo = 2.4492935982947064e-16;       // 2 pi - kTwoPiHi
+constexpr double kInvTwoPi = 0.15915494309189535;
+constexpr double kPi = 3.141592653589793116;
+constexpr double kSqrt2OverPi = 0.79788456080286541;
+
+// (cos t, sin t) for t = hi + lo, |hi| < 2^52.  t is reduced by the nearest
+// multiple k of 2 pi: hi - k*kTwoPiHi is exact (k*kTwoPiHi is formed exactly
+// and lies within a factor two of hi), the low parts are added afterwards, and
+// the residual low part enters as a first-order correction.
+__device__ __forceinline__ void cis_dd(double hi, double lo, double& c, double& s)
+{
+    double k = rint(hi * kInvTwoPi);
+    dd p = two_prod(k, kTwoPiHi);
+    double r = hi - p.hi;
+    double rl = (lo - p.lo) - k * kTwoPiLo;
+    dd t = two_sum(r, rl);
+    double sn, cs;
+    sincos(t.hi, &sn, &cs);
+    c = cs - t.lo * sn;
+    s = sn + t.lo * cs;
+}
+
+// Exponential-of-semicircle kernel exp(beta (sqrt(1 - x^2) - 1)) on |x| < 1.
+__device__ __forceinline__ double es_kernel(double x, double beta)
+{
+    double a = __builtin_fma(-x, x, 1.0);
+    return a > 0.0 ? exp(beta * (sqrt(a) - 1.0)) : 0.0;
+}
+
+__device__ __forceinline__ float es_kernel_f(float x, float beta)
+{
+    float a = __builtin_fmaf(-x, x, 1.0f);
+    return a > 0.0f ? __expf(beta * (sqrtf(a) - 1.0f)) : 0.0f;
+}
+
+// ES^(kappa) = int_{-1}^{1} ES(x) e^{i kappa x} dx for 0 <= kappa <= kappa_max,
+// from its Chebyshev series on [0, kappa_max] (Clenshaw's recurrence).
+__device__ __forceinline__ double eshat(const PlanDev& P, double kappa)
+{
+    double t = 2.0 * kappa / P.kappa_max - 1.0;
+    double t2 = 2.0 * t;
+    double b1 = 0.0, b2 = 0.0;
+    for (int i = P.n_eshat - 1; i >= 1; --i) {
+        double b0 = __builtin_fma(t2, b1, P.eshat[i] - b2);
+        b2 = b1;
+        b1 = b0;
+    }
+    return __builtin_fma(t, b1, P.eshat[0] - b2);
+}
+
+// Starting index of Miller's backward recurrence at argument y: beyond it
+// J_k(y) is below ~1e-20 of the sequence's largest value.
+__device__ __forceinline__ int miller_start(double y)
+{
+    return (int)(y + 14.0 * cbrt(y) + 20.0);
+}
+
+// J_nu(x) for 0 <= x (nu >= 0) by Miller's backward recurrence
+// J_{k-1} = (2k/x) J_k - J_{k+1}, normalised by J_0^2 + 2 sum J_k^2 = 1,
+// with the first-order correction for the low part of x = xh + xl.
+__device__ inline double besselj_miller(int nu, double xh, double xl)
+{
+    if (xh == 0.0) return nu == 0 ? 1.0 : 0.0;
+    if (xh < 1e-30) return nu == 0 ? 1.0 : 0.0;
+    int N = miller_start(xh);
+    if (nu > N) return 0.0;
+    if (N < nu + 1) N = nu + 1;
+    double rec = 2.0 / xh;
+    double yk1 = 0.0, yk = 1e-100, S = 0.0;
+    double jm = 0.0, j0 = 0.0, jp = 0.0;
+    for (int k = N; k >= 0; --k) {
+        if (k == nu + 1) jp = yk;
+        if (k == nu) j0 = yk;
+        if (k == nu - 1) jm = yk;
+        S = __builtin_fma(k == 0 ? yk : 2.0 * yk, yk, S);
+        if (k == 0) break;
+        double ykm1 = __builtin_fma((double)k * rec, yk, -yk1);
+        yk1 = yk;
+        yk = ykm1;
+        if (fabs(yk) > 1e100) {
+            yk *= 1e-100; yk1 *= 1e-100; S *= 1e-200;
+            jm *= 1e-100; j0 *= 1e-100; jp *= 1e-100;
+        }
+    }
+    double inv = 1.0 / sqrt(S);
+    double d = nu == 0 ? -jp : 0.5 * (jm - jp);
+    return (j0 + xl * d) * inv;
+}
+
+// The M-term Hankel approximation of J_nu at x = xh + xl (Sec. 3.2):
+//   sqrt(2/(pi x)) [ P cos(x + phi) - Q sin(x + phi) ],
+//   P = sum_{l<M} (-1)^l a_{2l} / x^{2l},  Q = sum_{l<M} (-1)^l a_{2l+1} / x^{2l+1}.
+__device__ inline double besselj_hankel(const PlanDev& P, double xh, double xl)
+{
+    dd ph = two_sum(xh, P.phi_hi);
+    double c, s;
+    cis_dd(ph.hi, ph.lo + xl + P.phi_lo, c, s);
+    double inv = 1.0 / xh;
+    double inv2 = inv * inv;
+    double p = 0.0, q = 0.0;
+    for (int l = P.M - 1; l >= 0; --l) {
+        double sg = (l & 1) ? -1.0 : 1.0;
+        p = __builtin_fma(p, inv2, sg * P.hank[2 * l]);
+        q = __builtin_fma(q, inv2, sg * P.hank[2 * l + 1]);
+    }
+    q *= inv;
+    return sqrt(2.0 / (kPi * xh)) * (p * c - q * s);
+}
+
+// J_nu(x) accurate to the plan's eps: Hankel's M-term formula above the
+// crossover z (where it is eps-accurate by the choice of z), Miller below.
+__device__ __forceinline__ double besselj_eps(const PlanDev& P, double xh, double xl)
+{
+    return xh > P.z ? besselj_hankel(P, xh, xl) : besselj_miller(P.nu, xh, xl);
+}
+
+}  // namespace nuht

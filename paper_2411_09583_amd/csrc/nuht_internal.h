@@ -1,0 +1,111 @@
+// nuht_internal.h -- data structures shared by the host code and the HIP kernels.
+//
+// Index conventions follow the paper (Sec. 4.1): rows j index the frequencies
+// omega (sorted ascending), columns k index the points r (sorted ascending).
+// A block is the inclusive index rectangle rows j0..j1, columns k0..k1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nuht {
+
+constexpr int kMaxChannels = 40;       // 2M with M <= 20 (eq. num-asy-terms caps M at 20)
+constexpr int kMaxFftLog2 = 26;        // largest FFT of an asymptotic block: 2^26 points
+constexpr int kLocalChunk = 4096;      // columns per local-moment work item
+constexpr int kSpreadChunk = 1024;     // points per spreading work item
+constexpr int kMaxLevels = 4096;       // subdivision depth limit
+
+// A mixed block of Alg. 1 and the split chosen for it.  Rows j0..js and
+// columns k0..ks are the local (upper-left) side.  A wholly local block is
+// stored with (js, ks) = (j1, k1), a wholly asymptotic one with
+// (js, ks) = (j0-1, k0-1).
+struct Node {
+    int32_t j0, j1, k0, k1;
+    int32_t js, ks;
+    int32_t lblk, ablk;   // local / asymptotic child block index, -1 if empty
+    int32_t ur, ll;       // upper-right / lower-left child: >= 0 mixed node,
+                          // <= -2 direct block (-2 - index), -1 empty
+    int32_t level, pad;
+};
+
+__host__ __device__ inline int32_t encode_direct(int32_t d) { return -2 - d; }
+__host__ __device__ inline int32_t decode_direct(int32_t c) { return -2 - c; }
+
+struct LBlock {
+    int32_t j0, j1, k0, k1;
+    double R;             // expansion radius: r_{k1}, or z / omega_{j1} when r_{k1} = 0
+    int32_t item0, nitems;
+    int32_t level, pad;
+};
+
+struct ABlock {
+    int32_t j0, j1, k0, k1;
+    double C, D;          // centres of the point and frequency ranges
+    double h;             // spread-grid spacing (a power of two)
+    double r0;            // smallest point of the block (weights are normalised by it)
+    double alpha;         // ES kernel half-width w h / 2
+    double Khi, Klo;      // h N2 / (2 pi) as a double-double (FFT path)
+    int32_t llo, N1;      // spread-grid cells llo .. llo + N1 - 1
+    int32_t N2, fft;      // FFT size and 1 for the FFT path; 0 for the direct-sum path
+    int64_t grid_off;     // offset of the block's grid (complex elements)
+    int32_t item0, nitems;
+    int64_t part_off;     // first partial-subgrid element of its items (complex)
+    int32_t level, fft_slot;  // fft_slot: position in the FFT size-class list
+};
+
+struct DBlock {
+    int32_t j0, j1, k0, k1;
+};
+
+// Work item of the column-side kernels: a chunk of one block's columns.
+struct Item {
+    int32_t blk;
+    int32_t ka, kb;       // columns ka .. kb-1
+    int32_t sub_lo, sub_n;  // spread items: subgrid cells sub_lo .. sub_lo + sub_n - 1
+    int32_t pad;
+    int64_t off;          // spread items: partial-subgrid offset (complex elements)
+};
+
+// Written by the planning kernels, read once by the host.
+struct Summary {
+    int32_t n_nodes, n_l, n_a, n_d;
+    int32_t levels, overflow;
+    int32_t n_litems, n_aitems;
+    int32_t n_fft, max_nch;
+    int64_t l_row, l_col, a_row, a_col, d_ent;
+    int64_t grid_cells;     // sum N1 (all asymptotic blocks)
+    int64_t dft_cells;      // sum N1 over direct-sum-path blocks
+    int64_t fft_points;     // sum N2 over FFT-path blocks
+    int64_t part_cells;     // sum of item subgrid sizes
+    int32_t fft_count[kMaxFftLog2 + 1];   // FFT-path blocks per log2(N2)
+    int32_t fft_first[kMaxFftLog2 + 1];   // start of each size class in the FFT list
+    int32_t domain_error;
+    int32_t grid_error;     // an asymptotic block needs an FFT larger than 2^kMaxFftLog2
+};
+
+// Everything the execution kernels need for one transform (device copy).
+struct PlanDev {
+    int32_t n, m, nu, M, L, w;       // sizes, |order|, terms, local rank, ES width
+    int32_t nch, sign;               // 2M; (-1)^nu for negative orders, else 1
+    double z, beta, eps;
+    double phi_hi, phi_lo;           // -(2nu+1) pi/4 reduced to [0, 2pi), double-double
+    double hank[2 * 20 + 2];         // a_p(nu), p = 0 .. 2M+1 (Hankel coefficients)
+    double eshat[32];                // Chebyshev coefficients of ES^ on [0, kappa_max]
+    int32_t n_eshat, pad0;
+    double kappa_max;
+    const double* rs;                // sorted points (n)
+    const double* ws;                // sorted frequencies (m)
+    const int32_t* perm_r;           // sorted position -> caller index (points)
+    const int32_t* perm_w;           // sorted position -> caller index (frequencies)
+    const Node* nodes;
+    const LBlock* lb;
+    const ABlock* ab;
+    const DBlock* db;
+    const Item* litems;
+    const Item* aitems;
+    const int32_t* fft_list;         // FFT-path blocks grouped by size class
+    int32_t n_nodes, n_l, n_a, n_d, n_litems, n_aitems, pad1, pad2;
+};
+
+}  // namespace nuht

@@ -1,0 +1,64 @@
+// nuht_launch.h -- device tables of a partition and the host-side launchers.
+#pragma once
+
+#include "nuht_internal.h"
+
+namespace nuht {
+
+struct Rect {
+    int32_t j0, j1, k0, k1;
+};
+
+// Device tables of one partition, with their capacities.  The planning
+// kernels write them; if any capacity is exceeded they report overflow in the
+// Summary and the host retries with larger tables.
+struct Arena {
+    Node* nodes;
+    LBlock* lb;
+    ABlock* ab;
+    DBlock* db;
+    Rect* q0;
+    Rect* q1;
+    Item* litems;
+    Item* aitems;
+    int32_t* fft_list;
+    int32_t node_cap, l_cap, a_cap, d_cap, q_cap, litem_cap, aitem_cap, pad;
+};
+
+// planning (plan.hip)
+hipError_t launch_make_keys(const double* x, int32_t n, uint64_t* key, int32_t* val, int32_t* err, hipStream_t s);
+hipError_t launch_sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int32_t* hist, int32_t na,
+                             int32_t nb, hipStream_t s);
+int sort_hist_len(int32_t na, int32_t nb);
+hipError_t launch_staircase(const double* rs, int32_t n, const double* ws, int32_t m, double z, int32_t* K,
+                            hipStream_t s);
+hipError_t launch_subdivide(const int32_t* K, int32_t m, int32_t n, int64_t min_size, int32_t ncand, const Arena& A,
+                            Summary* sum, hipStream_t s);
+hipError_t launch_block_params(const PlanDev& P, const Arena& A, int32_t n_l, int32_t n_a, int32_t dft_max,
+                               double sigma, int64_t* a_sizes, int32_t* l_sizes, Summary* sum, hipStream_t s);
+hipError_t launch_plan_scan(const PlanDev& P, const Arena& A, int32_t n_l, int32_t n_a, int32_t n_d,
+                            const int64_t* a_sizes, const int32_t* l_sizes, Summary* sum, hipStream_t s);
+hipError_t launch_fill_items(const PlanDev& P, const Arena& A, int32_t n_l, int32_t n_a, hipStream_t s);
+
+// execution (exec.hip)
+struct ExecBuffers {
+    double* cs;         // gathered weights (sorted point order)
+    double* lpart;      // local-moment partial sums, n_litems x (L+1)
+    double* lmom;       // local moments, n_l x (L+1)
+    double2* part;      // spread partial subgrids
+    double2* grids;     // spread grids (direct-sum path) and FFT buffers (FFT path)
+    double2* scratch;   // second buffer of the two-pass FFTs
+    int64_t grid_cells; // grid slots (without the channel factor)
+};
+
+struct FftClass {
+    int32_t log2n, count, first;
+    int64_t scratch_off;   // complex elements
+};
+
+hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers& B, const FftClass* cls, int ncls,
+                          const double* c, double* g, hipStream_t s);
+hipError_t launch_direct(const PlanDev& P, const double* r, const double* c, int32_t n, const double* w, int32_t m,
+                         double* g, hipStream_t s);
+
+}  // namespace nuht

@@ -1,0 +1,618 @@
+// plan.hip -- device-side planning: validation and sorting of the points and
+// frequencies, the staircase of the local region, the block subdivision of
+// Alg. 1 (Sec. 4.1), per-block parameters and the column work items.
+#include "nuht_device.h"
+#include "nuht_launch.h"
+
+namespace nuht {
+
+// ---------------------------------------------------------------------------
+// Keys: a nonnegative double's bit pattern, read as an unsigned integer, is
+// monotone in its value, so sorting the bits sorts the values.  -0.0 maps to 0.
+// Any negative, NaN or infinite input raises the domain flag.
+// ---------------------------------------------------------------------------
+__global__ void k_make_keys(const double* __restrict__ x, int32_t n, uint64_t* __restrict__ key,
+                            int32_t* __restrict__ val, int32_t* __restrict__ err)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = x[i];
+    bool ok = (v >= 0.0) && (v <= 1.7976931348623157e308);
+    if (!ok) atomicOr(err, 1);
+    key[i] = (v == 0.0 || !ok) ? 0ull : (uint64_t)__double_as_longlong(v);
+    val[i] = i;
+}
+
+// ---------------------------------------------------------------------------
+// LSD radix sort, 8-bit digits, of up to two independent segments at once.
+// Segment s owns tiles [tile0[s], tile0[s+1]) and elements [off[s], off[s+1]).
+// ---------------------------------------------------------------------------
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 16;
+constexpr int kSortTile = kSortThreads * kSortRounds;
+
+struct SortSegs {
+    int32_t off[3];      // element offsets of segments 0, 1 and the end
+    int32_t tile0[3];    // tile offsets
+    int32_t hoff[3];     // histogram offsets (256 * tiles per segment)
+};
+
+__device__ __forceinline__ int tile_segment(const SortSegs& S, int tile)
+{
+    return tile >= S.tile0[1] ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t* __restrict__ key, SortSegs S,
+                                                             int shift, int32_t* __restrict__ hist)
+{
+    __shared__ int32_t h[256];
+    int tile = blockIdx.x;
+    int seg = tile_segment(S, tile);
+    int lt = tile - S.tile0[seg];
+    int ntiles = S.tile0[seg + 1] - S.tile0[seg];
+    int base = S.off[seg] + lt * kSortTile;
+    int end = S.off[seg + 1];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    for (int r = 0; r < kSortRounds; ++r) {
+        int i = base + r * kSortThreads + threadIdx.x;
+        if (i < end) atomicAdd(&h[(key[i] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    hist[S.hoff[seg] + threadIdx.x * ntiles + lt] = h[threadIdx.x];
+}
+
+// Exclusive scan of each segment's digit-major histogram (one block per segment).
+__global__ __launch_bounds__(1024) void k_sort_scan(int32_t* __restrict__ hist, SortSegs S)
+{
+    __shared__ int32_t sm[1024];
+    __shared__ int32_t carry;
+    int seg = blockIdx.x;
+    int len = S.hoff[seg + 1] - S.hoff[seg];
+    int32_t* h = hist + S.hoff[seg];
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < len; c0 += 1024) {
+        int i = c0 + threadIdx.x;
+        int v = i < len ? h[i] : 0;
+        sm[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            int t = threadIdx.x >= o ? sm[threadIdx.x - o] : 0;
+            __syncthreads();
+            sm[threadIdx.x] += t;
+            __syncthreads();
+        }
+        int incl = sm[threadIdx.x];
+        if (i < len) h[i] = carry + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += incl;
+        __syncthreads();
+    }
+}
+
+// Stable scatter.  Within a tile, element order is (round, thread); each wave
+// ranks its keys among equal digits with ballots, waves are combined through
+// shared counters, and rounds through a running per-digit base.
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* __restrict__ kin,
+                                                                const int32_t* __restrict__ vin,
+                                                                uint64_t* __restrict__ kout,
+                                                                int32_t* __restrict__ vout, SortSegs S,
+                                                                int shift, const int32_t* __restrict__ hist)
+{
+    __shared__ int32_t base[256];
+    __shared__ int32_t wcnt[kSortThreads / 64][256];
+    int tile = blockIdx.x;
+    int seg = tile_segment(S, tile);
+    int lt = tile - S.tile0[seg];
+    int ntiles = S.tile0[seg + 1] - S.tile0[seg];
+    int start = S.off[seg] + lt * kSortTile;
+    int end = S.off[seg + 1];
+    int lane = threadIdx.x & 63;
+    int wave = threadIdx.x >> 6;
+    uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    base[threadIdx.x] = hist[S.hoff[seg] + threadIdx.x * ntiles + lt] + S.off[seg];
+    for (int r = 0; r < kSortRounds; ++r) {
+        for (int q = threadIdx.x; q < (kSortThreads / 64) * 256; q += kSortThreads)
+            (&wcnt[0][0])[q] = 0;
+        __syncthreads();
+        int i = start + r * kSortThreads + threadIdx.x;
+        bool valid = i < end;
+        uint64_t k = valid ? kin[i] : 0ull;
+        int32_t v = valid ? vin[i] : 0;
+        int d = (int)((k >> shift) & 255);
+        uint64_t peers = __ballot(valid);
+        #pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t m = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? m : ~m;
+        }
+        int rank = __popcll(peers & lt_mask);
+        if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int off = base[d] + rank;
+            for (int w2 = 0; w2 < wave; ++w2) off += wcnt[w2][d];
+            kout[off] = k;
+            vout[off] = v;
+        }
+        __syncthreads();
+        int tot = 0;
+        #pragma unroll
+        for (int w2 = 0; w2 < kSortThreads / 64; ++w2) tot += wcnt[w2][threadIdx.x];
+        base[threadIdx.x] += tot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Staircase: K[j] = #{k : omega_j r_k <= z}, the product decided exactly.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool exact_le(double a, double b, double z)
+{
+    dd p = two_prod(a, b);
+    if (p.hi < z) return true;
+    if (p.hi > z) return false;
+    return p.lo <= 0.0;
+}
+
+__global__ void k_staircase(const double* __restrict__ rs, int32_t n, const double* __restrict__ ws, int32_t m,
+                            double z, int32_t* __restrict__ K)
+{
+    int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    double w = ws[j];
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+        int32_t mid = lo + ((hi - lo) >> 1);
+        if (exact_le(w, rs[mid], z)) lo = mid + 1; else hi = mid;
+    }
+    K[j] = lo;
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide exclusive scans for a 1024-thread block.
+// ---------------------------------------------------------------------------
+template <class T, int NV>
+__device__ void block_scan(T (&v)[NV], T (&tot)[NV], T (*sm)[1024])
+{
+    #pragma unroll
+    for (int q = 0; q < NV; ++q) sm[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        T t[NV];
+        #pragma unroll
+        for (int q = 0; q < NV; ++q) t[q] = threadIdx.x >= (unsigned)o ? sm[q][threadIdx.x - o] : T(0);
+        __syncthreads();
+        #pragma unroll
+        for (int q = 0; q < NV; ++q) sm[q][threadIdx.x] += t[q];
+        __syncthreads();
+    }
+    #pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        T incl = sm[q][threadIdx.x];
+        tot[q] = sm[q][1023];
+        v[q] = incl - v[q];
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 1 (Subdivide), level by level in one 1024-thread block.  Every mixed
+// block of a level becomes a Node; its split follows the quasi-optimal
+// SplitIndices of Sec. 4.1 (candidate rows equispaced, minimal mixed area,
+// ties to the smaller row).  Numbering is deterministic: nodes in level order,
+// children in (parent, position) order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ K, int32_t m, int32_t n,
+                                                    int64_t min_size, int32_t ncand, Arena A, Summary* __restrict__ sum)
+{
+    __shared__ int32_t sm[4][1024];
+    __shared__ int32_t s_tot[4];
+    int tid = threadIdx.x;
+    Rect* cur = A.q0;
+    Rect* nxt = A.q1;
+    int32_t n_cur = (m > 0 && n > 0) ? 1 : 0;
+    if (tid == 0 && n_cur) cur[0] = Rect{0, m - 1, 0, n - 1};
+    int32_t n_nodes = 0, n_l = 0, n_a = 0, n_d = 0;
+    int32_t overflow = 0;
+    int32_t level = 0;
+    __syncthreads();
+    while (n_cur > 0) {
+        ++level;
+        int32_t n_next = 0;
+        for (int32_t c0 = 0; c0 < n_cur; c0 += 1024) {
+            int32_t i = c0 + tid;
+            bool act = i < n_cur;
+            Rect R = act ? cur[i] : Rect{0, -1, 0, -1};
+            int32_t js = 0, ks = 0;
+            int32_t cl = 0, ca = 0, cd = 0, cm = 0;
+            bool ur_m = false, ur_d = false, ll_m = false, ll_d = false;
+            if (act) {
+                if (K[R.j1] >= R.k1 + 1) {          // wholly local
+                    js = R.j1; ks = R.k1;
+                } else if (K[R.j0] <= R.k0) {       // wholly asymptotic
+                    js = R.j0 - 1; ks = R.k0 - 1;
+                } else {
+                    // candidate rows: equispaced over the rows that hold a local
+                    // entry of the block (K[j] > k0; K is nonincreasing in j)
+                    int32_t lo = R.j0, hi = R.j1;
+                    while (lo < hi) {
+                        int32_t mid = lo + ((hi - lo + 1) >> 1);
+                        if (K[mid] > R.k0) lo = mid; else hi = mid - 1;
+                    }
+                    int64_t best = INT64_MAX;
+                    int32_t span = lo - R.j0;
+                    int32_t nc = span > 0 ? ncand : 1;
+                    for (int32_t c = 0; c < nc; ++c) {
+                        int32_t j = span > 0 ? R.j0 + (int32_t)(((int64_t)c * span) / (nc - 1)) : R.j0;
+                        int32_t k = K[j] - 1;
+                        if (k > R.k1) k = R.k1;
+                        if (k < R.k0) k = R.k0 - 1;
+                        int64_t mixed = (int64_t)(j - R.j0 + 1) * (R.k1 - k) + (int64_t)(R.j1 - j) * (k - R.k0 + 1);
+                        if (mixed < best) { best = mixed; js = j; ks = k; }
+                    }
+                }
+                cl = (ks >= R.k0 && js >= R.j0) ? 1 : 0;
+                ca = (js < R.j1 && ks < R.k1) ? 1 : 0;
+                if (ks < R.k1 && js >= R.j0) {
+                    if ((int64_t)(js - R.j0 + 1) * (R.k1 - ks) > min_size) ur_m = true; else ur_d = true;
+                }
+                if (js < R.j1 && ks >= R.k0) {
+                    if ((int64_t)(R.j1 - js) * (ks - R.k0 + 1) > min_size) ll_m = true; else ll_d = true;
+                }
+                cd = (int)ur_d + (int)ll_d;
+                cm = (int)ur_m + (int)ll_m;
+            }
+            int32_t v[4] = {cl, ca, cd, cm};
+            int32_t tot[4];
+            block_scan<int32_t, 4>(v, tot, sm);
+            if (act) {
+                int32_t node = n_nodes + i;
+                int32_t li = cl ? n_l + v[0] : -1;
+                int32_t ai = ca ? n_a + v[1] : -1;
+                int32_t d_slot = n_d + v[2];
+                int32_t m_slot = n_next + v[3];
+                int32_t next_base = n_nodes + n_cur;   // first node index of the next level
+                Node nd;
+                nd.j0 = R.j0; nd.j1 = R.j1; nd.k0 = R.k0; nd.k1 = R.k1;
+                nd.js = js; nd.ks = ks; nd.lblk = li; nd.ablk = ai;
+                nd.level = level; nd.pad = 0;
+                nd.ur = -1; nd.ll = -1;
+                if (ur_m) { if (m_slot < A.q_cap) nxt[m_slot] = Rect{R.j0, js, ks + 1, R.k1}; nd.ur = next_base + m_slot; ++m_slot; }
+                if (ur_d) { if (d_slot < A.d_cap) A.db[d_slot] = DBlock{R.j0, js, ks + 1, R.k1}; nd.ur = encode_direct(d_slot); ++d_slot; }
+                if (ll_m) { if (m_slot < A.q_cap) nxt[m_slot] = Rect{js + 1, R.j1, R.k0, ks}; nd.ll = next_base + m_slot; ++m_slot; }
+                if (ll_d) { if (d_slot < A.d_cap) A.db[d_slot] = DBlock{js + 1, R.j1, R.k0, ks}; nd.ll = encode_direct(d_slot); ++d_slot; }
+                if (node < A.node_cap) A.nodes[node] = nd;
+                if (cl && li < A.l_cap) {
+                    LBlock b;
+                    b.j0 = R.j0; b.j1 = js; b.k0 = R.k0; b.k1 = ks;
+                    b.R = 0.0; b.item0 = 0; b.nitems = 0; b.level = level; b.pad = 0;
+                    A.lb[li] = b;
+                }
+                if (ca && ai < A.a_cap) {
+                    ABlock b = {};
+                    b.j0 = js + 1; b.j1 = R.j1; b.k0 = ks + 1; b.k1 = R.k1; b.level = level;
+                    A.ab[ai] = b;
+                }
+            }
+            n_l += tot[0];
+            n_a += tot[1];
+            n_d += tot[2];
+            n_next += tot[3];
+        }
+        n_nodes += n_cur;
+        if (n_next > A.q_cap || n_nodes > A.node_cap) {
+            overflow = 1;
+            n_next = n_next > A.q_cap ? A.q_cap : n_next;
+        }
+        Rect* t = cur; cur = nxt; nxt = t;
+        if (level >= kMaxLevels) overflow = 2;
+        n_cur = overflow ? 0 : n_next;
+        __syncthreads();
+    }
+    if (overflow != 2 && (n_l > A.l_cap || n_a > A.a_cap || n_d > A.d_cap)) overflow = 1;
+    if (tid == 0) {
+        sum->n_nodes = n_nodes; sum->n_l = n_l; sum->n_a = n_a; sum->n_d = n_d;
+        sum->levels = level; sum->overflow = overflow;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-block parameters (one thread per block).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t iceil(double x) { return (int32_t)ceil(x); }
+
+__global__ void k_block_params(PlanDev P, Arena A, int32_t n_l, int32_t n_a, int32_t dft_max, double sigma,
+                               int64_t* __restrict__ a_sizes /* 4 per A block */,
+                               int32_t* __restrict__ l_sizes /* 1 per L block */, int32_t* __restrict__ sum_flags)
+{
+    int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = P.w;
+    if (b < n_a) {
+        ABlock B = A.ab[b];
+        double rlo = P.rs[B.k0], rhi = P.rs[B.k1];
+        double wlo = P.ws[B.j0], whi = P.ws[B.j1];
+        double C = 0.5 * (rlo + rhi);
+        double X = fmax(rhi - C, C - rlo);
+        double D = 0.5 * (wlo + whi);
+        double S = fmax(whi - D, D - wlo);
+        if (!(S > 1e-280)) S = 1e-280;
+        // grid spacing: the largest power of two with S h <= pi / sigma
+        double h = exp2(floor(log2(kPi / (sigma * S))));
+        if (S * h > kPi / sigma) h *= 0.5;
+        double span = X / h;
+        if (!(span < (double)(1 << (kMaxFftLog2 - 3)))) {   // grid too large for the FFT sizes
+            atomicOr(&sum_flags[0], 1);
+            span = 0.0;
+        }
+        int32_t llo = iceil(-span - 0.5 * w) - 1;
+        int32_t lhi = iceil(span - 0.5 * w) + w;
+        int32_t N1 = lhi - llo + 1;
+        B.C = C; B.D = D; B.h = h; B.r0 = rlo; B.alpha = 0.5 * w * h;
+        B.llo = llo; B.N1 = N1;
+        int32_t fft = (dft_max >= 0 && N1 <= dft_max) ? 0 : 1;
+        int32_t N2 = 0, lg = 0;
+        if (fft) {
+            int32_t maxl = llo < 0 ? -llo : llo;
+            if (lhi > maxl) maxl = lhi;
+            N2 = 64; lg = 6;
+            while (N2 < 4 * maxl + 4) { N2 <<= 1; ++lg; }
+            // h N2 / (2 pi): exact scaling of the double-double 1/(2 pi)
+            B.Khi = h * (double)N2 * kInvTwoPi;
+            B.Klo = h * (double)N2 * (-9.4287216877795e-18);
+        }
+        B.fft = fft; B.N2 = N2;
+        int32_t nb = B.k1 - B.k0 + 1;
+        int32_t nit = (nb + kSpreadChunk - 1) / kSpreadChunk;
+        int64_t cells = 0;
+        for (int32_t it = 0; it < nit; ++it) {
+            int32_t ka = B.k0 + it * kSpreadChunk;
+            int32_t kb = ka + kSpreadChunk - 1;
+            if (kb > B.k1) kb = B.k1;
+            double u0 = (P.rs[ka] - C) / h, u1 = (P.rs[kb] - C) / h;
+            int32_t s0 = iceil(u0 - 0.5 * w) - 1;
+            int32_t s1 = iceil(u1 - 0.5 * w) + w;
+            if (s0 < llo) s0 = llo;
+            if (s1 > lhi) s1 = lhi;
+            cells += s1 - s0 + 1;
+        }
+        B.nitems = nit;
+        A.ab[b] = B;
+        a_sizes[4 * b + 0] = nit;
+        a_sizes[4 * b + 1] = cells;
+        a_sizes[4 * b + 2] = fft ? (int64_t)N2 : (int64_t)N1;
+        a_sizes[4 * b + 3] = fft ? lg : -1;
+    }
+    if (b < n_l) {
+        LBlock L = A.lb[b];
+        double R = P.rs[L.k1];
+        if (R == 0.0) {
+            double wm = P.ws[L.j1];
+            R = wm > 0.0 ? P.z / wm : 1.0;
+        }
+        L.R = R;
+        int32_t nb = L.k1 - L.k0 + 1;
+        L.nitems = (nb + kLocalChunk - 1) / kLocalChunk;
+        A.lb[b] = L;
+        l_sizes[b] = L.nitems;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Offsets and totals (one 1024-thread block): exclusive scans over the blocks
+// of item counts, partial-subgrid cells and grid slots; FFT size classes; the
+// membership statistics.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, int32_t n_l, int32_t n_a, int32_t n_d,
+                                                    const int64_t* __restrict__ a_sizes,
+                                                    const int32_t* __restrict__ l_sizes, Summary* __restrict__ sum)
+{
+    __shared__ int64_t sm[3][1024];
+    __shared__ long long red[6][1024 / 64];
+    int tid = threadIdx.x;
+    const int nch = P.nch;
+    // local items
+    int64_t l_items = 0;
+    for (int32_t c0 = 0; c0 < n_l; c0 += 1024) {
+        int32_t i = c0 + tid;
+        int64_t v[1] = {i < n_l ? (int64_t)l_sizes[i] : 0};
+        int64_t tot[1];
+        block_scan<int64_t, 1>(v, tot, sm);
+        if (i < n_l) A.lb[i].item0 = (int32_t)(l_items + v[0]);
+        l_items += tot[0];
+    }
+    // asymptotic items, partial cells, grid slots
+    int64_t a_items = 0, part = 0, grid = 0;
+    int32_t cls_count[kMaxFftLog2 + 1];
+    for (int q = 0; q <= kMaxFftLog2; ++q) cls_count[q] = 0;
+    for (int32_t c0 = 0; c0 < n_a; c0 += 1024) {
+        int32_t i = c0 + tid;
+        bool act = i < n_a;
+        int64_t v[3] = {act ? a_sizes[4 * i + 0] : 0, act ? a_sizes[4 * i + 1] : 0, act ? a_sizes[4 * i + 2] : 0};
+        int64_t tot[3];
+        block_scan<int64_t, 3>(v, tot, sm);
+        if (act) {
+            A.ab[i].item0 = (int32_t)(a_items + v[0]);
+            A.ab[i].part_off = (part + v[1]) * nch;
+            A.ab[i].grid_off = (grid + v[2]) * nch;
+        }
+        a_items += tot[0];
+        part += tot[1];
+        grid += tot[2];
+    }
+    // FFT size classes: deterministic slots (class, then block index)
+    int32_t fft_total = 0;
+    for (int cls = 6; cls <= kMaxFftLog2; ++cls) {
+        int32_t cnt = 0;
+        for (int32_t c0 = 0; c0 < n_a; c0 += 1024) {
+            int32_t i = c0 + tid;
+            bool mine = i < n_a && a_sizes[4 * i + 3] == cls;
+            int64_t v[1] = {mine ? 1 : 0};
+            int64_t tot[1];
+            block_scan<int64_t, 1>(v, tot, sm);
+            if (mine) {
+                A.ab[i].fft_slot = (int32_t)(fft_total + cnt + v[0]);
+                A.fft_list[fft_total + cnt + v[0]] = i;
+            }
+            cnt += (int32_t)tot[0];
+        }
+        if (tid == 0) { sum->fft_count[cls] = cnt; sum->fft_first[cls] = fft_total; }
+        cls_count[cls] = cnt;
+        fft_total += cnt;
+    }
+    // membership statistics
+    long long s[6] = {0, 0, 0, 0, 0, 0};
+    for (int32_t i = tid; i < n_l; i += 1024) {
+        LBlock L = A.lb[i];
+        s[0] += L.j1 - L.j0 + 1; s[1] += L.k1 - L.k0 + 1;
+    }
+    for (int32_t i = tid; i < n_a; i += 1024) {
+        ABlock B = A.ab[i];
+        s[2] += B.j1 - B.j0 + 1; s[3] += B.k1 - B.k0 + 1;
+        s[5] += B.fft ? 0 : B.N1;
+    }
+    long long ent = 0;
+    for (int32_t i = tid; i < n_d; i += 1024) {
+        DBlock Db = A.db[i];
+        ent += (long long)(Db.j1 - Db.j0 + 1) * (Db.k1 - Db.k0 + 1);
+    }
+    s[4] = ent;
+    for (int q = 0; q < 6; ++q) {
+        long long x = s[q];
+        for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+        if ((tid & 63) == 0) red[q][tid >> 6] = x;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        long long t[6] = {0, 0, 0, 0, 0, 0};
+        for (int q = 0; q < 6; ++q)
+            for (int w2 = 0; w2 < 1024 / 64; ++w2) t[q] += red[q][w2];
+        sum->l_row = t[0]; sum->l_col = t[1]; sum->a_row = t[2]; sum->a_col = t[3];
+        sum->d_ent = t[4]; sum->dft_cells = t[5];
+        sum->n_litems = (int32_t)l_items; sum->n_aitems = (int32_t)a_items;
+        sum->part_cells = part; sum->n_fft = fft_total; sum->max_nch = nch;
+        int64_t fp = 0;
+        for (int cls = 6; cls <= kMaxFftLog2; ++cls) fp += (int64_t)cls_count[cls] << cls;
+        sum->fft_points = fp;
+        sum->grid_cells = grid;
+        if (l_items > A.litem_cap || a_items > A.aitem_cap || fft_total > A.a_cap) sum->overflow = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Work items (one thread per block).
+// ---------------------------------------------------------------------------
+__global__ void k_fill_items(PlanDev P, Arena A, int32_t n_l, int32_t n_a)
+{
+    int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = P.w;
+    const int nch = P.nch;
+    if (b < n_a) {
+        ABlock B = A.ab[b];
+        int64_t off = B.part_off;
+        int32_t lhi = B.llo + B.N1 - 1;
+        for (int32_t it = 0; it < B.nitems; ++it) {
+            int32_t ka = B.k0 + it * kSpreadChunk;
+            int32_t kb = ka + kSpreadChunk - 1;
+            if (kb > B.k1) kb = B.k1;
+            double u0 = (P.rs[ka] - B.C) / B.h, u1 = (P.rs[kb] - B.C) / B.h;
+            int32_t s0 = iceil(u0 - 0.5 * w) - 1;
+            int32_t s1 = iceil(u1 - 0.5 * w) + w;
+            if (s0 < B.llo) s0 = B.llo;
+            if (s1 > lhi) s1 = lhi;
+            Item I;
+            I.blk = b; I.ka = ka; I.kb = kb + 1; I.sub_lo = s0; I.sub_n = s1 - s0 + 1; I.pad = 0; I.off = off;
+            if (B.item0 + it < A.aitem_cap) A.aitems[B.item0 + it] = I;
+            off += (int64_t)I.sub_n * nch;
+        }
+    }
+    if (b < n_l) {
+        LBlock L = A.lb[b];
+        for (int32_t it = 0; it < L.nitems; ++it) {
+            int32_t ka = L.k0 + it * kLocalChunk;
+            int32_t kb = ka + kLocalChunk;
+            if (kb > L.k1 + 1) kb = L.k1 + 1;
+            Item I;
+            I.blk = b; I.ka = ka; I.kb = kb; I.sub_lo = 0; I.sub_n = 0; I.pad = 0; I.off = 0;
+            if (L.item0 + it < A.litem_cap) A.litems[L.item0 + it] = I;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------
+static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+hipError_t launch_make_keys(const double* x, int32_t n, uint64_t* key, int32_t* val, int32_t* err, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_make_keys, dim3(cdiv(n, 256)), dim3(256), 0, s, x, n, key, val, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int32_t* hist,
+                             int32_t na, int32_t nb, hipStream_t s)
+{
+    SortSegs S;
+    S.off[0] = 0; S.off[1] = na; S.off[2] = na + nb;
+    int ta = cdiv(na, kSortTile), tb = cdiv(nb, kSortTile);
+    S.tile0[0] = 0; S.tile0[1] = ta; S.tile0[2] = ta + tb;
+    S.hoff[0] = 0; S.hoff[1] = 256 * ta; S.hoff[2] = 256 * (ta + tb);
+    if (ta + tb == 0) return hipSuccess;
+    uint64_t* kin = k0; int32_t* vin = v0; uint64_t* kout = k1; int32_t* vout = v1;
+    for (int pass = 0; pass < 8; ++pass) {
+        int shift = 8 * pass;
+        hipLaunchKernelGGL(k_sort_hist, dim3(ta + tb), dim3(kSortThreads), 0, s, kin, S, shift, hist);
+        hipLaunchKernelGGL(k_sort_scan, dim3(2), dim3(1024), 0, s, hist, S);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(ta + tb), dim3(kSortThreads), 0, s, kin, vin, kout, vout, S, shift,
+                           hist);
+        uint64_t* tk = kin; kin = kout; kout = tk;
+        int32_t* tv = vin; vin = vout; vout = tv;
+    }
+    return hipGetLastError();   // eight passes: the result is back in (k0, v0)
+}
+
+int sort_hist_len(int32_t na, int32_t nb) { return 256 * (cdiv(na, kSortTile) + cdiv(nb, kSortTile)) + 256; }
+
+hipError_t launch_staircase(const double* rs, int32_t n, const double* ws, int32_t m, double z, int32_t* K,
+                            hipStream_t s)
+{
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_staircase, dim3(cdiv(m, 256)), dim3(256), 0, s, rs, n, ws, m, z, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_subdivide(const int32_t* K, int32_t m, int32_t n, int64_t min_size, int32_t ncand, const Arena& A,
+                            Summary* sum, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_subdivide, dim3(1), dim3(1024), 0, s, K, m, n, min_size, ncand, A, sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_params(const PlanDev& P, const Arena& A, int32_t n_l, int32_t n_a, int32_t dft_max,
+                               double sigma, int64_t* a_sizes, int32_t* l_sizes, Summary* sum, hipStream_t s)
+{
+    int nb = n_l > n_a ? n_l : n_a;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_block_params, dim3(cdiv(nb, 128)), dim3(128), 0, s, P, A, n_l, n_a, dft_max, sigma,
+                       a_sizes, l_sizes, &sum->grid_error);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_scan(const PlanDev& P, const Arena& A, int32_t n_l, int32_t n_a, int32_t n_d,
+                            const int64_t* a_sizes, const int32_t* l_sizes, Summary* sum, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, s, P, A, n_l, n_a, n_d, a_sizes, l_sizes, sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_items(const PlanDev& P, const Arena& A, int32_t n_l, int32_t n_a, hipStream_t s)
+{
+    int nb = n_l > n_a ? n_l : n_a;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_items, dim3(cdiv(nb, 128)), dim3(128), 0, s, P, A, n_l, n_a);
+    return hipGetLastError();
+}
+
+}  // namespace nuht

@@ -1,0 +1,61 @@
+"""The C-ABI library loads and exports every symbol include/nuht.h declares,
+and rejects invalid arguments before touching the GPU (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "nuht.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nuht_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2411_09583_amd as nuht
+    return nuht.load_library()
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for n in ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    import paper_2411_09583_amd as nuht
+    names = declared_symbols()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(nuht.EXPORTS) == names
+
+
+def test_strerror(lib):
+    assert lib.nuht_strerror(0) == b"success"
+    for code in (-1, -2, -3, -4, -5, -6):
+        assert lib.nuht_strerror(code) != b"unknown error"
+
+
+def test_invalid_arguments_rejected_without_gpu(lib):
+    import paper_2411_09583_amd as nuht
+    h = ctypes.c_void_p()
+    plan = lib.nuht_plan
+    assert plan(ctypes.byref(h), 101, 1e-12, 0, None, 0, None, None, None) == -1      # |nu| > 100
+    assert plan(ctypes.byref(h), 0, 1e-16, 0, None, 0, None, None, None) == -1        # eps too small
+    assert plan(ctypes.byref(h), 0, 0.5, 0, None, 0, None, None, None) == -1          # eps too large
+    assert plan(ctypes.byref(h), 0, 1e-12, -1, None, 0, None, None, None) == -1       # n < 0
+    assert plan(ctypes.byref(h), 0, 1e-12, 10, None, 10, None, None, None) == -1      # null with n > 0
+    assert plan(None, 0, 1e-12, 0, None, 0, None, None, None) == -1
+    o = nuht.NuhtOpts(0, 0, 0, nuht.NUHT_FP32_SPREAD, 0)
+    assert plan(ctypes.byref(h), 0, 1e-12, 0, None, 0, None, ctypes.byref(o), None) == -3
+    o = nuht.NuhtOpts(0, 21, 0, 0, 0)                                                 # M > 20
+    assert plan(ctypes.byref(h), 0, 1e-12, 0, None, 0, None, ctypes.byref(o), None) == -1
+    assert lib.nuht_execute(None, None, None, None) == -1
+    assert lib.nuht_adjoint(None, None, None, None) == -1
+    assert lib.nuht_destroy(None) == 0
+    assert lib.nuht_direct(0, 1e-12, 5, None, None, 5, None, None, None) == -1

@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar (FP64, eps = 1e-12): relative l2 error and normwise max error of the GPU
+output against O1 (the direct sum) at most 1e-12.  Cases span several tiles
+and ragged tails, every block class, both NUFFT paths (direct sum over small
+grids, one-pass and two-pass FFTs), the edge cases of the method, and the
+full-size configuration on sampled outputs.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import direct, method, partition
+from oracle import params as oparams
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def nuht():
+    import paper_2411_09583_amd as lib
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lib.load_library()
+    return lib
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel_l2(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+def rel_max(a, b):
+    mb = np.max(np.abs(b)) if b.size else 0.0
+    return np.max(np.abs(a - b)) / mb if mb > 0 else (np.max(np.abs(a - b)) if a.size else 0.0)
+
+
+def run(nuht, nu, eps, r, c, w, **opts):
+    p = nuht.Plan(dev(r), dev(w), nu, eps, **opts)
+    g = host(p.execute(dev(c)))
+    info = p.info()
+    p.close()
+    return g, info
+
+
+def test_small_dense_config(nuht):
+    r, w, c = workloads.small_dense(seed=1)
+    g, info = run(nuht, 0, 1e-12, r, c, w)
+    g1 = direct.dht(0, r, c, w)
+    print("small dense: rel l2", rel_l2(g, g1), "rel max", rel_max(g, g1), info)
+    assert (info["M"], info["L"]) == (4, 31)
+    assert rel_l2(g, g1) <= TOL
+    assert rel_max(g, g1) <= TOL
+
+
+def test_partition_matches_oracle(nuht):
+    r, w, c = workloads.small_dense(seed=1)
+    g, info = run(nuht, 0, 1e-12, r, c, w)
+    M, z, L = oparams.parameters(0, 1e-12)
+    assert abs(info["z"] - z) <= 1e-14 * z
+    K = direct.staircase(np.sort(r), np.sort(w), z)
+    st = partition.stats(partition.subdivide(K, w.size, r.size))
+    assert info["n_local"] == st["L"]["count"]
+    assert info["n_asy"] == st["A"]["count"]
+    assert info["n_direct"] == st["D"]["count"]
+    assert info["levels"] == st["levels"]
+    assert info["local_row_members"] == st["L"]["row_members"]
+    assert info["asy_col_members"] == st["A"]["col_members"]
+    assert info["direct_entries"] == st["D"]["area"]
+
+
+def test_against_method_exact_reference(nuht):
+    # GPU - O2 isolates the NUFFT and rounding error of the GPU path
+    r, w, c = workloads.uniform(3000, 2500, 1.0, 1500.0, seed=3)
+    g, _ = run(nuht, 0, 1e-12, r, c, w)
+    g2 = method.nufht_reference(0, 1e-12, r, c, w)
+    assert rel_l2(g, g2) <= 3e-13
+
+
+@pytest.mark.parametrize("nu", [1, 2, 3, 5, 10, -1, -4])
+def test_orders(nuht, nu):
+    r, w, c = workloads.uniform(3000, 2000, 1.0, 2000.0, seed=40 + abs(nu))
+    g, _ = run(nuht, nu, 1e-12, r, c, w)
+    g1 = direct.dht(nu, r, c, w)
+    assert rel_l2(g, g1) <= TOL, rel_l2(g, g1)
+    assert rel_max(g, g1) <= TOL
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-9, 1e-14])
+def test_tolerances(nuht, eps):
+    r, w, c = workloads.uniform(3000, 3000, 1.0, 1000.0, seed=7)
+    g, _ = run(nuht, 0, eps, r, c, w)
+    g1 = direct.dht(0, r, c, w)
+    assert rel_l2(g, g1) <= max(eps, 2e-14), (eps, rel_l2(g, g1))
+
+
+def test_direct_sum_path_only_and_fft_path_only(nuht):
+    r, w, c = workloads.uniform(2500, 2500, 1.0, 1200.0, seed=8)
+    g1 = direct.dht(0, r, c, w)
+    g_fft, _ = run(nuht, 0, 1e-12, r, c, w, dft_max=-1)       # every asymptotic block by FFT
+    g_dft, _ = run(nuht, 0, 1e-12, r, c, w, dft_max=100000)   # every block by direct sum over its grid
+    assert rel_l2(g_fft, g1) <= TOL
+    assert rel_l2(g_dft, g1) <= TOL
+
+
+def test_two_pass_fft(nuht):
+    # large space-frequency product: FFTs above 4096 points take the two-pass path
+    r, w, c = workloads.uniform(20000, 20000, 1.0, 3.0e4, seed=9)
+    p = nuht.Plan(dev(r), dev(w), 0, 1e-12)
+    assert p.info()["fft_points"] > 0
+    g = host(p.execute(dev(c)))
+    p.close()
+    idx = np.random.default_rng(0).choice(w.size, 1500, replace=False)
+    g1 = direct.dht(0, r, c, w[idx])
+    assert rel_l2(g[idx], g1) <= TOL
+
+
+@pytest.mark.parametrize("min_size", [16, 300, 5000])
+def test_min_size(nuht, min_size):
+    r, w, c = workloads.uniform(1500, 1700, 1.0, 900.0, seed=11)
+    g, _ = run(nuht, 2, 1e-12, r, c, w, min_size=min_size)
+    assert rel_l2(g, direct.dht(2, r, c, w)) <= TOL
+
+
+def test_edge_cases(nuht):
+    rng = np.random.default_rng(12)
+    # zeros in r and omega, duplicates, a single point / frequency
+    r = rng.uniform(0, 1, 700); r[:20] = 0.0; r[20:60] = r[60]
+    w = rng.uniform(0, 800, 600); w[:15] = 0.0; w[15:40] = w[40]
+    c = rng.standard_normal(700)
+    for nu in (0, 1, 6):
+        g, _ = run(nuht, nu, 1e-12, r, c, w, min_size=64)
+        assert rel_l2(g, direct.dht(nu, r, c, w)) <= TOL
+    g, _ = run(nuht, 0, 1e-12, r[:1], c[:1], w)
+    assert rel_l2(g, direct.dht(0, r[:1], c[:1], w)) <= TOL
+    g, _ = run(nuht, 3, 1e-12, r, c, w[-1:])
+    assert rel_l2(g, direct.dht(3, r, c, w[-1:])) <= TOL
+    # wholly local and wholly asymptotic matrices
+    g, info = run(nuht, 0, 1e-12, r * 0.01, c, w * 0.01)
+    assert info["n_asy"] == 0 and rel_l2(g, direct.dht(0, r * 0.01, c, w * 0.01)) <= TOL
+    g, info = run(nuht, 0, 1e-12, r + 1.0, c, w + 100.0)
+    assert info["n_local"] == 0 and rel_l2(g, direct.dht(0, r + 1.0, c, w + 100.0)) <= TOL
+
+
+def test_empty_inputs(nuht):
+    w = np.linspace(0, 10, 7)
+    g, _ = run(nuht, 0, 1e-12, np.zeros(0), np.zeros(0), w)
+    assert np.array_equal(g, np.zeros(7))
+    g, _ = run(nuht, 0, 1e-12, np.ones(5), np.ones(5), np.zeros(0))
+    assert g.size == 0
+
+
+def test_domain_errors(nuht):
+    r = dev(np.array([0.1, -0.2, 0.3]))
+    w = dev(np.array([1.0, 2.0]))
+    with pytest.raises(nuht.NuhtError) as e:
+        nuht.Plan(r, w, 0, 1e-12)
+    assert e.value.code == -2
+    with pytest.raises(nuht.NuhtError):
+        nuht.Plan(dev(np.array([0.1, float("nan")])), w, 0, 1e-12)
+    with pytest.raises(nuht.NuhtError):
+        nuht.Plan(dev(np.array([0.1])), dev(np.array([float("inf")])), 0, 1e-12)
+
+
+def test_gpu_direct_sum(nuht):
+    r, w, c = workloads.uniform(1500, 800, 1.0, 5.0e4, seed=13)
+    for nu in (0, 7):
+        g = host(nuht.direct(dev(c), dev(r), dev(w), nu, 1e-12))
+        assert rel_l2(g, direct.dht(nu, r, c, w)) <= TOL
+
+
+def test_adjoint(nuht):
+    r, w, _ = workloads.uniform(2500, 2200, 1.0, 1500.0, seed=14)
+    y = np.random.default_rng(15).standard_normal(w.size)
+    for nu in (0, 3):
+        p = nuht.Plan(dev(r), dev(w), nu, 1e-12)
+        cb = host(p.adjoint(dev(y)))
+        p.close()
+        ref = direct.dht(nu, w, y, r)            # sum_j y_j J_nu(w_j r_k)
+        assert rel_l2(cb, ref) <= TOL
+
+
+def test_radial_2d_workload_sampled(nuht):
+    r, w, c = workloads.radial_2d(n=200_000, m=200_000)
+    p = nuht.Plan(dev(r), dev(w), 0, 1e-12)
+    g = host(p.execute(dev(c)))
+    p.close()
+    idx = np.random.default_rng(16).choice(w.size, 400, replace=False)
+    g1 = direct.dht(0, r, c, w[idx])
+    assert rel_l2(g[idx], g1) <= TOL
+
+
+def test_large_uniform_full_size_sampled(nuht):
+    # n = m = 1e6 (the headline configuration) on 256 sampled outputs, and on
+    # all outputs for a weight vector with 200 nonzeros (Sec. 5.1.3)
+    r, w, c = workloads.large_uniform(seed=2)
+    p = nuht.Plan(dev(r), dev(w), 0, 1e-12)
+    g = host(p.execute(dev(c)))
+    idx = np.random.default_rng(17).choice(w.size, 256, replace=False)
+    g1 = direct.dht(0, r, c, w[idx])
+    print("full size sampled rel l2", rel_l2(g[idx], g1), p.info())
+    assert rel_l2(g[idx], g1) <= TOL
+    cs = workloads.sparse_c(r.size, 200, seed=18)
+    gs = host(p.execute(dev(cs)))
+    nz = np.nonzero(cs)[0]
+    gs1 = direct.dht(0, r[nz], cs[nz], w)
+    print("sparse full size rel l2", rel_l2(gs, gs1))
+    assert rel_l2(gs, gs1) <= TOL
+    p.close()
+
+
+def test_repeatable(nuht):
+    r, w, c = workloads.small_dense(seed=21)
+    p = nuht.Plan(dev(r), dev(w), 1, 1e-12)
+    a = host(p.execute(dev(c)))
+    b = host(p.execute(dev(c)))
+    p.close()
+    assert np.array_equal(a, b)

@@ -96,3 +96,15 @@ def test_quasi_optimal_split_close_to_exact_optimum():
 
     best = min(mixed(jj) for jj in range(m))
     assert mixed(j) <= 1.25 * best
+
+
+def test_depth_stays_small_with_many_equal_points():
+    # a local strip along the top of a block (many equal points) is split in
+    # a few levels, not peeled one row per level
+    rng = np.random.default_rng(0)
+    r = np.concatenate([np.full(500, 0.3), rng.uniform(0, 1, 500)])
+    w = rng.uniform(0, 2000, 3000)
+    blocks = _check_partition(r, w, 31.5, 64)
+    assert partition.stats(blocks)['levels'] < 20
+    blocks = _check_partition(np.full(1000, 0.3), w, 31.5, 64)
+    assert partition.stats(blocks)['levels'] <= 3
