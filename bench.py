@@ -1,0 +1,219 @@
+#!/usr/bin/env python
+"""Throughput of the nonuniform fast Hankel transform on one MI355X.
+
+Workload (one step): the transform g_j = sum_k c_k J_nu(omega_j r_k) at
+n = m = 1e6, r ~ U[0,1) unsorted, omega ~ U[0,1e5), c ~ N(0,1), eps = 1e-12,
+FP64, for each order nu in {0, 1, 10} (inputs drawn with seeds 2, 3, 4).  Each
+transform is planned (device sort, staircase, Alg. 1) and executed; inputs are
+resident in GPU memory before the timed region.  value = (n+m) per second over
+the whole step (3 transforms).
+
+Also reported: execute-only throughput (plans reused), per-stage times from
+HIP events recorded on the transform's stream inside the timed region, the
+roofline of the dominant kernel, and the CPU oracle (direct O(nm) sum) timed
+on a bounded sample of the same workload.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+ORDERS = (0, 1, 10)
+SEEDS = {0: 2, 1: 3, 10: 4}
+EPS = 1e-12
+N = M_OUT = 1_000_000
+PEAK_FP64 = 78.6e12          # MI355X FP64 vector, flop/s
+PEAK_HBM = 8.0e12            # bytes/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-sample", type=int, default=512,
+                    help="outputs of the nu=0 transform computed by the CPU oracle")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2411_09583_amd as nuht
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    nuht.load_library()
+    inputs = {}
+    for nu in ORDERS:
+        r, w, c = workloads.large_uniform(seed=SEEDS[nu], n=N, m=M_OUT)
+        inputs[nu] = tuple(torch.as_tensor(a, device=dev) for a in (r, w, c))
+    torch.cuda.synchronize()
+    log("inputs resident")
+
+    def step(keep):
+        outs = {}
+        for nu in ORDERS:
+            r, w, c = inputs[nu]
+            p = nuht.Plan(r, w, nu, EPS)
+            if keep is not None:
+                p.profile(True)
+            outs[nu] = p.execute(c)
+            if keep is not None:
+                keep.append((nu, p))
+            else:
+                p.close()
+        return outs
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    kept = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        outs = step(kept)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    work = len(ORDERS) * (N + M_OUT)
+    value = work * args.steps / elapsed
+    log(f"timed: {ms_per_step:.3f} ms/step, {value:.4e} (n+m)/s")
+
+    # per-stage times (events recorded inside the timed region)
+    stage_tot = {s: 0.0 for s in nuht.STAGES}
+    calls = 0
+    infos = {}
+    for nu, p in kept:
+        st, nc = p.profile_read()
+        for k, v in st.items():
+            stage_tot[k] += v
+        calls += nc
+        infos[nu] = p.info()
+    for _, p in kept:
+        p.close()
+    kept.clear()
+    stage_ms = {k: v / args.steps for k, v in stage_tot.items()}   # per step (3 transforms)
+
+    # execute-only and plan-only times per order
+    per_order = {}
+    for nu in ORDERS:
+        r, w, c = inputs[nu]
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        p = nuht.Plan(r, w, nu, EPS)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        reps = max(3, args.steps)
+        for _ in range(reps):
+            g = p.execute(c)
+        torch.cuda.synchronize()
+        e = time.perf_counter()
+        inf = p.info()
+        p.close()
+        ex_ms = 1e3 * (e - b) / reps
+        per_order[str(nu)] = dict(plan_ms=1e3 * (b - a), execute_ms=ex_ms,
+                                  execute_rate=(N + M_OUT) / (ex_ms * 1e-3),
+                                  M=inf["M"], L=inf["L"], z=inf["z"], es_width=inf["es_width"],
+                                  levels=inf["levels"], blocks=[inf["n_local"], inf["n_asy"], inf["n_direct"]],
+                                  asy_members=[inf["asy_row_members"], inf["asy_col_members"]],
+                                  local_members=[inf["local_row_members"], inf["local_col_members"]],
+                                  direct_entries=inf["direct_entries"], fft_points=inf["fft_points"])
+    exec_total = sum(v["execute_ms"] for v in per_order.values())
+    log("per order:", json.dumps(per_order))
+    log("stage ms per step:", json.dumps(stage_ms))
+
+    # roofline of the dominant kernel: spreading (k_spread) or the row pass (k_rows).
+    # Algorithmic flops: every (point, cell) pair of the spreading adds a
+    # real-weighted sample to 2M complex channels, 2 FMA = 4 flops per channel;
+    # every (frequency, tap) pair of the interpolation does the same.
+    dom = max(("spread", "rows"), key=lambda s: stage_ms[s])
+    flops = 0.0
+    for nu in ORDERS:
+        inf = infos[nu]
+        two_m = 2 * inf["M"]
+        if dom == "spread":
+            flops += inf["asy_col_members"] * inf["es_width"] * two_m * 4.0
+        else:
+            flops += inf["asy_row_members"] * inf["es_width"] * two_m * 4.0
+    achieved = flops / (stage_ms[dom] * 1e-3)
+    roofline = dict(bound="alu", kernel="k_spread" if dom == "spread" else "k_rows",
+                    achieved=achieved / 1e12, peak=PEAK_FP64 / 1e12, unit="TFLOP/s",
+                    frac=achieved / PEAK_FP64, traffic=None)
+
+    # accuracy on sampled outputs (outside the timed region)
+    accuracy = None
+    if not args.no_check:
+        from oracle import direct as odirect
+        r, w, c = (t.cpu().numpy() for t in inputs[0])
+        g = outs[0].cpu().numpy()
+        idx = np.random.default_rng(99).choice(M_OUT, 64, replace=False)
+        ref = odirect.dht(0, r, c, w[idx])
+        accuracy = dict(nu=0, sampled_outputs=64,
+                        rel_l2=float(np.linalg.norm(g[idx] - ref) / np.linalg.norm(ref)))
+        log("accuracy", accuracy)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import direct as odirect
+        r, w, c = (t.cpu().numpy() for t in inputs[0])
+        k = args.cpu_sample
+        idx = np.random.default_rng(7).choice(M_OUT, k, replace=False)
+        threads = odirect.max_threads()
+        a = time.perf_counter()
+        odirect.dht(0, r, c, w[idx], nthreads=threads)
+        b = time.perf_counter()
+        full_s = (b - a) * M_OUT / k
+        cpu = dict(value=(N + M_OUT) / full_s, unit="(n+m)/s", cores=threads, kind="oracle",
+                   sample=f"direct sum for {k} of the 1e6 outputs (all 1e6 points, nu=0), "
+                          f"{b - a:.1f} s, extrapolated to the full transform")
+        log("cpu baseline", cpu)
+
+    out = {
+        "metric": "(n+m)/s at eps=1e-12 vs direct sum; batched and fwd+bwd speedup, HBM GB/s",
+        "value": value,
+        "unit": "(n+m)/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "large uniform: n=m=1e6, r~U[0,1) unsorted, omega~U[0,1e5), c~N(0,1), "
+                               "eps=1e-12, one transform each for nu=0,1,10 (plan+execute)",
+                   "n": N, "m": M_OUT, "orders": list(ORDERS), "eps": EPS},
+        "execute_only_value": len(ORDERS) * (N + M_OUT) / (exec_total * 1e-3),
+        "per_order": per_order,
+        "stage_ms_per_step": stage_ms,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "accuracy": accuracy,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

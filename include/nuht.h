@@ -131,6 +131,20 @@ int nuht_plan_set_order(nuht_plan_t plan, int nu, void *stream);
 /* nuht_plan_info -- parameters and partition statistics of the current order. */
 int nuht_plan_info(nuht_plan_t plan, nuht_info *info);
 
+/*
+ * Stage timing (diagnostics).  nuht_profile(plan, 1) clears and starts it:
+ * every later nuht_execute / nuht_adjoint on the plan records HIP events on its
+ * own stream between its NUHT_NSTAGES stages (0 gather of c, 1 local moments,
+ * 2 ES spreading, 3 grid assembly, 4 FFTs, 5 direct blocks, 6 row pass).
+ * nuht_profile(plan, 0)
+ * stops it.  nuht_profile_read synchronises on the last recorded event and
+ * writes the per-stage totals in milliseconds to stage_ms[NUHT_NSTAGES] and
+ * the number of profiled calls to *calls (may be NULL).
+ */
+#define NUHT_NSTAGES 7
+int nuht_profile(nuht_plan_t plan, int enable);
+int nuht_profile_read(nuht_plan_t plan, double *stage_ms, int64_t *calls);
+
 /* nuht_destroy -- free the plan and its device memory (NULL is allowed). */
 int nuht_destroy(nuht_plan_t plan);
 

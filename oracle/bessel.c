@@ -294,6 +294,7 @@ void orc_asy_block(int nu, int M, int64_t mb, const double *w, int64_t nb,
     for (int64_t i = 0; i < mb; ++i) {
         double sum = 0.0, comp = 0.0;
         for (int64_t k = 0; k < nb; ++k) {
+            if (c[k] == 0.0) continue;
             double xh, xl;
             two_prod(w[i], r[k], &xh, &xl);
             double cx = cos(xh), sx = sin(xh);

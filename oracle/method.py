@@ -113,3 +113,42 @@ def nufht_reference(nu: int, eps: float, r, c, w, min_size: int = 1024,
     if return_blocks:
         return g, dict(M=M, z=z, L=L, blocks=blocks)
     return g
+
+
+def nufht_reference_rows(nu: int, eps: float, r, c, w, rows, min_size: int = 1024,
+                         ncand: int = 16, M: int = None):
+    """O2 at selected outputs only: the same partition and expansions as
+    :func:`nufht_reference`, summed for the outputs w[rows] (caller order).
+    Cost O(len(rows) * n) plus the local moments of the blocks involved."""
+    r = np.asarray(r, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    rows = np.asarray(rows, dtype=np.int64)
+    sign = -1.0 if (nu < 0 and (-nu) % 2 == 1) else 1.0
+    anu = abs(nu)
+    M, z, L = prm.parameters(anu, eps, M)
+    pr = np.argsort(r, kind='stable')
+    pw = np.argsort(w, kind='stable')
+    rs, cs, ws = r[pr], c[pr], w[pw]
+    inv = np.empty_like(pw)
+    inv[pw] = np.arange(pw.size)
+    sel = np.sort(inv[rows])                  # sorted positions of the wanted outputs
+    K = direct.staircase(rs, ws, z)
+    blocks = partition.subdivide(K, ws.size, rs.size, min_size, ncand)
+    acc = {int(j): 0.0 for j in sel}
+    for b in blocks:
+        lo = np.searchsorted(sel, b.j0)
+        hi = np.searchsorted(sel, b.j1, side='right')
+        if lo == hi:
+            continue
+        js = sel[lo:hi]
+        cols = slice(b.k0, b.k1 + 1)
+        if b.kind == 'L':
+            v = local_block_apply(anu, L, z, ws[js], rs[cols], cs[cols])
+        elif b.kind == 'A':
+            v = direct.asy_block_apply(anu, M, ws[js], rs[cols], cs[cols])
+        else:
+            v = direct.dht(anu, rs[cols], cs[cols], ws[js])
+        for j, x in zip(js, v):
+            acc[int(j)] += x
+    return sign * np.array([acc[int(inv[q])] for q in rows])

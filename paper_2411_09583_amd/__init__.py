@@ -52,7 +52,9 @@ class NuhtInfo(ctypes.Structure):
 
 # every symbol include/nuht.h declares
 EXPORTS = ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_plan_set_order", "nuht_plan_info",
-           "nuht_destroy", "nuht_strerror", "nuht_direct")
+           "nuht_destroy", "nuht_strerror", "nuht_direct", "nuht_profile", "nuht_profile_read")
+
+STAGES = ("gather", "local_moments", "spread", "grid_assembly", "fft", "direct", "rows")
 
 _lib = None
 
@@ -76,8 +78,10 @@ def load_library():
     lib.nuht_strerror.argtypes = [ctypes.c_int]
     lib.nuht_strerror.restype = ctypes.c_char_p
     lib.nuht_direct.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, vp, vp, ctypes.c_int64, vp, vp, vp]
+    lib.nuht_profile.argtypes = [vp, ctypes.c_int]
+    lib.nuht_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for name in ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_plan_set_order", "nuht_plan_info",
-                 "nuht_destroy", "nuht_direct"):
+                 "nuht_destroy", "nuht_direct", "nuht_profile", "nuht_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -152,6 +156,17 @@ class Plan:
         inf = NuhtInfo()
         _check(load_library().nuht_plan_info(self._h, ctypes.byref(inf)))
         return {f: getattr(inf, f) for f, _ in NuhtInfo._fields_}
+
+    def profile(self, enable: bool = True):
+        """Start (clearing earlier records) or stop per-stage event timing."""
+        _check(load_library().nuht_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """Per-stage totals in ms over the profiled calls, and the call count."""
+        ms = (ctypes.c_double * len(STAGES))()
+        calls = ctypes.c_int64()
+        _check(load_library().nuht_profile_read(self._h, ms, ctypes.byref(calls)))
+        return dict(zip(STAGES, list(ms))), calls.value
 
     def close(self):
         if getattr(self, "_h", None):

@@ -23,6 +23,10 @@ COMMON = [
     f"--offload-arch={ARCH}",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit multiply-add fusion: it would break the error-free
+    # transformations (TwoProduct/TwoSum) the phase arithmetic relies on;
+    # fused operations are written explicitly where they are wanted
+    "-ffp-contract=off",
     "-I", INCLUDE, "-I", CSRC,
     "-Wno-unused-result",
 ]

@@ -252,11 +252,13 @@ __global__ void k_spread_reduce(PlanDev P, const double2* __restrict__ part, dou
 // ---------------------------------------------------------------------------
 // FFT: X[k] = sum_n x[n] e^{+2 pi i n k / N}, N a power of two, in LDS.
 // Stockham autosort, radix 4 (one radix-2 stage first when log2 N is odd).
-// Element (line, n) of the tile lives at sm[line * ls + n * es].
+// Element (line, n) of the tile lives at sm[line * ls + n * es].  The tile
+// holds at most 4096 points and the block 256 threads, so a thread carries at
+// most 8 radix-2 or 4 radix-4 butterflies per stage.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_double2(__builtin_fma(a.x, b.x, -a.y * b.y), __builtin_fma(a.x, b.y, a.y * b.x));
 }
 
 __device__ void lds_fft(double2* sm, int N, int logN, int lines, int ls, int es)
@@ -267,9 +269,9 @@ __device__ void lds_fft(double2* sm, int N, int logN, int lines, int ls, int es)
     if (logN & 1) {
         const int half = N >> 1;
         const int nb = lines * half;
-        double2 v[16][2];
+        double2 v[8][2];
         #pragma unroll
-        for (int c = 0; c < 16; ++c) {
+        for (int c = 0; c < 8; ++c) {
             int b = tid + c * nt;
             if (b < nb) {
                 int line = b / half, j = b - line * half;
@@ -279,7 +281,7 @@ __device__ void lds_fft(double2* sm, int N, int logN, int lines, int ls, int es)
         }
         __syncthreads();
         #pragma unroll
-        for (int c = 0; c < 16; ++c) {
+        for (int c = 0; c < 8; ++c) {
             int b = tid + c * nt;
             if (b < nb) {
                 int line = b / half, j = b - line * half;
@@ -294,9 +296,9 @@ __device__ void lds_fft(double2* sm, int N, int logN, int lines, int ls, int es)
     const int q4 = N >> 2;
     while (Ns < N) {
         const int nb = lines * q4;
-        double2 v[8][4];
+        double2 v[4][4];
         #pragma unroll
-        for (int c = 0; c < 8; ++c) {
+        for (int c = 0; c < 4; ++c) {
             int b = tid + c * nt;
             if (b < nb) {
                 int line = b / q4, j = b - line * q4;
@@ -306,7 +308,7 @@ __device__ void lds_fft(double2* sm, int N, int logN, int lines, int ls, int es)
         }
         __syncthreads();
         #pragma unroll
-        for (int c = 0; c < 8; ++c) {
+        for (int c = 0; c < 4; ++c) {
             int b = tid + c * nt;
             if (b < nb) {
                 int line = b / q4, j = b - line * q4;
@@ -446,13 +448,13 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
         if (i >= 1 && l1 <= L && i + nu <= N) {
             double pv = ring[(slot == 0 ? Bsz - 1 : slot - 1) * stride];
             double coef = 2.0 * t[l1];
-            dot += ((i & 1) ? -coef : coef) * yk * pv;
+            dot = __builtin_fma(((i & 1) ? -coef : coef) * yk, pv, dot);
         }
         if (i <= a && a - i <= L) {
             int l2 = a - i;
             double pv = ring[((nu - i) % Bsz) * stride];
             double coef = (!odd && l2 == 0) ? t[0] : 2.0 * t[l2];
-            dot += coef * yk * pv;
+            dot = __builtin_fma(coef * yk, pv, dot);
         }
         if (i == 0) break;
         double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
@@ -474,6 +476,10 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
 // s' = om - D and theta = s' h:  y_p = e^{i om C} h F_p(theta) / phi^(s'),
 // F_p(theta) = sum_l b_l^(p) e^{i l theta} evaluated directly over the cells
 // (direct-sum path) or from the FFT by ES interpolation (FFT path).
+// Called with a wave-uniform block index whenever every active lane of the
+// wave is in the same block (the usual case, frequencies being sorted); the
+// block's fields and its direct-sum grid are then read through the scalar
+// unit and broadcast to all lanes.
 template <int NCH>
 __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2* __restrict__ grids)
 {
@@ -498,12 +504,12 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
             for (int p = 0; p < NCH; ++p) {
                 if (p < nch) {
                     double2 gv = gp[p];
-                    ar[p] += gv.x * zr - gv.y * zi;
-                    ai[p] += gv.x * zi + gv.y * zr;
+                    ar[p] = __builtin_fma(gv.x, zr, __builtin_fma(-gv.y, zi, ar[p]));
+                    ai[p] = __builtin_fma(gv.x, zi, __builtin_fma(gv.y, zr, ai[p]));
                 }
             }
-            double tr = zr * er - zi * ei;
-            zi = zr * ei + zi * er;
+            double tr = __builtin_fma(zr, er, -zi * ei);
+            zi = __builtin_fma(zr, ei, zi * er);
             zr = tr;
         }
     } else {
@@ -522,8 +528,8 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
             for (int p = 0; p < NCH; ++p) {
                 if (p < nch) {
                     double2 a = Aq[(int64_t)p * B.N2 + qi];
-                    ar[p] += psi * a.x;
-                    ai[p] += psi * a.y;
+                    ar[p] = __builtin_fma(psi, a.x, ar[p]);
+                    ai[p] = __builtin_fma(psi, a.y, ai[p]);
                 }
             }
         }
@@ -545,31 +551,57 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
         if (p < nch) {
             int l = p >> 1;
             double coef = ((l & 1) ? -P.hank[p] : P.hank[p]) * amp;
-            if (p & 1) { zr -= coef * ai[p]; zi += coef * ar[p]; }
-            else { zr += coef * ar[p]; zi += coef * ai[p]; }
+            if (p & 1) { zr = __builtin_fma(-coef, ai[p], zr); zi = __builtin_fma(coef, ar[p], zi); }
+            else { zr = __builtin_fma(coef, ar[p], zr); zi = __builtin_fma(coef, ai[p], zi); }
             amp *= gam;
         }
     }
-    return kSqrt2OverPi * (cr * zr - ci * zi);
+    return kSqrt2OverPi * __builtin_fma(cr, zr, -ci * zi);
 }
 
-__device__ double direct_eval(const PlanDev& P, int dblk, double om, const double* __restrict__ cs)
+// Direct blocks (entry by entry, J_nu to full precision).  One 64-lane wave
+// per block: each row of the block is given G lanes (G a power of two, as many
+// as fit), the lanes of a row sum strided entries and combine by shuffles.  A
+// row lies in at most one direct block (the last block of its path down the
+// subdivision tree), so the per-row sums are stored, not accumulated.
+__global__ __launch_bounds__(64) void k_direct_blocks(PlanDev P, const double* __restrict__ cs,
+                                                      double* __restrict__ gd)
 {
-    const DBlock D = P.db[dblk];
-    double acc = 0.0;
-    for (int k = D.k0; k <= D.k1; ++k) {
-        dd x = two_prod(om, P.rs[k]);
-        acc += cs[k] * besselj_eps(P, x.hi, x.lo);
+    const DBlock D = P.db[blockIdx.x];
+    const int mb = D.j1 - D.j0 + 1, nb = D.k1 - D.k0 + 1;
+    int G = 1;
+    while (G < 64 && 2 * G * mb <= 64) G <<= 1;
+    const int rows_per_pass = 64 / G;
+    const int lane = threadIdx.x;
+    const int grp = lane / G, gl = lane & (G - 1);
+    for (int r0 = 0; r0 < mb; r0 += rows_per_pass) {
+        int i = r0 + grp;
+        double acc = 0.0;
+        if (i < mb) {
+            double om = P.ws[D.j0 + i];
+            for (int k = gl; k < nb; k += G) {
+                dd x = two_prod(om, P.rs[D.k0 + k]);
+                acc = __builtin_fma(cs[D.k0 + k], besselj_full(P, x.hi, x.lo), acc);
+            }
+        }
+        for (int o = G >> 1; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+        if (i < mb && gl == 0) gd[D.j0 + i] = acc;
     }
-    return acc;
+}
+
+__global__ void k_fill_zero(double* __restrict__ x, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0;
 }
 
 // One thread per sorted frequency: walk the tree from the root.  At a node the
 // row lies either in the local side (rows j0..js) -- local block, then the
 // upper-right child -- or in the asymptotic side -- asymptotic block, then the
-// lower-left child.  A direct child ends the walk.
+// lower-left child.  A direct child ends the walk with the row's direct sum,
+// computed beforehand by k_direct_blocks.
 template <int NCH>
-__global__ void k_rows(PlanDev P, const double* __restrict__ cs, const double* __restrict__ lmom,
+__global__ __launch_bounds__(256) void k_rows(PlanDev P, const double* __restrict__ gd, const double* __restrict__ lmom,
                        const double2* __restrict__ grids, double* __restrict__ g)
 {
     extern __shared__ double ring_all[];
@@ -584,14 +616,24 @@ __global__ void k_rows(PlanDev P, const double* __restrict__ cs, const double* _
         const Node nd = P.nodes[node];
         int child;
         if (j <= nd.js) {
-            if (nd.lblk >= 0) acc += local_eval(P, nd.lblk, om, lmom, ring, stride);
+            if (nd.lblk >= 0) {
+                int lb = nd.lblk;
+                int lbu = __builtin_amdgcn_readfirstlane(lb);
+                if (__all(lb == lbu)) acc += local_eval(P, lbu, om, lmom, ring, stride);
+                else acc += local_eval(P, lb, om, lmom, ring, stride);
+            }
             child = nd.ur;
         } else {
-            if (nd.ablk >= 0) acc += asym_eval<NCH>(P, nd.ablk, om, grids);
+            if (nd.ablk >= 0) {
+                int ab = nd.ablk;
+                int abu = __builtin_amdgcn_readfirstlane(ab);
+                if (__all(ab == abu)) acc += asym_eval<NCH>(P, abu, om, grids);
+                else acc += asym_eval<NCH>(P, ab, om, grids);
+            }
             child = nd.ll;
         }
         if (child <= -2) {
-            acc += direct_eval(P, decode_direct(child), om, cs);
+            acc += gd[j];
             break;
         }
         node = child;
@@ -609,7 +651,7 @@ __global__ void k_direct_all(PlanDev P, const double* __restrict__ r, const doub
     double acc = 0.0;
     for (int k = 0; k < n; ++k) {
         dd x = two_prod(om, r[k]);
-        acc += c[k] * besselj_eps(P, x.hi, x.lo);
+        acc = __builtin_fma(c[k], besselj_full(P, x.hi, x.lo), acc);
     }
     g[j] = P.sign * acc;
 }
@@ -618,13 +660,10 @@ __global__ void k_direct_all(PlanDev P, const double* __restrict__ r, const doub
 static inline int cdiv64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 template <int NCH>
-static void launch_nch(const PlanDev& P, const Summary& S, const ExecBuffers& B, double* g, hipStream_t s)
+static void launch_spread(const PlanDev& P, const Summary& S, const ExecBuffers& B, hipStream_t s)
 {
     if (S.n_aitems > 0)
         hipLaunchKernelGGL(k_spread<NCH>, dim3(S.n_aitems), dim3(256), 0, s, P, B.cs, B.part);
-    if (B.grid_cells > 0)
-        hipLaunchKernelGGL(k_spread_reduce, dim3(cdiv64(B.grid_cells * P.nch, 256)), dim3(256), 0, s, P, B.part,
-                           B.grids, B.grid_cells);
 }
 
 template <int NCH>
@@ -632,27 +671,40 @@ static void launch_rows(const PlanDev& P, const ExecBuffers& B, double* g, hipSt
 {
     int bs = (P.nu + 1) * 256 * 8 <= 65536 ? 256 : 64;
     size_t lds = (size_t)(P.nu + 1) * bs * sizeof(double);
-    hipLaunchKernelGGL(k_rows<NCH>, dim3(cdiv64(P.m, bs)), dim3(bs), lds, s, P, B.cs, B.lmom, B.grids, g);
+    hipLaunchKernelGGL(k_rows<NCH>, dim3(cdiv64(P.m, bs)), dim3(bs), lds, s, P, B.gd, B.lmom, B.grids, g);
+}
+
+static inline void mark(hipEvent_t* marks, int i, hipStream_t s)
+{
+    if (marks) (void)hipEventRecord(marks[i], s);
 }
 
 hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers& B, const FftClass* cls, int ncls,
-                          const double* c, double* g, hipStream_t s)
+                          const double* c, double* g, hipStream_t s, hipEvent_t* marks)
 {
     if (P.m == 0) return hipSuccess;
     if (P.n == 0) {
         return hipMemsetAsync(g, 0, sizeof(double) * (size_t)P.m, s);
     }
+    mark(marks, 0, s);
     hipLaunchKernelGGL(k_gather, dim3(cdiv64(P.n, 256)), dim3(256), 0, s, c, P.perm_r, P.n, B.cs);
+    mark(marks, 1, s);
     if (S.n_litems > 0) {
         hipLaunchKernelGGL(k_lmom, dim3(S.n_litems), dim3(256), 0, s, P, B.cs, B.lpart);
         hipLaunchKernelGGL(k_lmom_reduce, dim3(cdiv64((int64_t)S.n_l * (P.L + 1), 256)), dim3(256), 0, s, P,
                            B.lpart, B.lmom);
     }
-    if (P.nch <= 8) launch_nch<8>(P, S, B, g, s);
-    else if (P.nch <= 16) launch_nch<16>(P, S, B, g, s);
-    else if (P.nch <= 24) launch_nch<24>(P, S, B, g, s);
-    else if (P.nch <= 32) launch_nch<32>(P, S, B, g, s);
-    else launch_nch<40>(P, S, B, g, s);
+    mark(marks, 2, s);
+    if (P.nch <= 8) launch_spread<8>(P, S, B, s);
+    else if (P.nch <= 16) launch_spread<16>(P, S, B, s);
+    else if (P.nch <= 24) launch_spread<24>(P, S, B, s);
+    else if (P.nch <= 32) launch_spread<32>(P, S, B, s);
+    else launch_spread<40>(P, S, B, s);
+    mark(marks, 3, s);
+    if (B.grid_cells > 0)
+        hipLaunchKernelGGL(k_spread_reduce, dim3(cdiv64(B.grid_cells * P.nch, 256)), dim3(256), 0, s, P, B.part,
+                           B.grids, B.grid_cells);
+    mark(marks, 4, s);
     for (int q = 0; q < ncls; ++q) {
         const FftClass& C = cls[q];
         int ntr = C.count * P.nch;
@@ -670,11 +722,18 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
                                B.grids, B.scratch, C.first, C.log2n, logN1, C.scratch_off);
         }
     }
+    mark(marks, 5, s);
+    if (P.n_d > 0) {
+        hipLaunchKernelGGL(k_fill_zero, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, B.gd, (int64_t)P.m);
+        hipLaunchKernelGGL(k_direct_blocks, dim3(P.n_d), dim3(64), 0, s, P, B.cs, B.gd);
+    }
+    mark(marks, 6, s);
     if (P.nch <= 8) launch_rows<8>(P, B, g, s);
     else if (P.nch <= 16) launch_rows<16>(P, B, g, s);
     else if (P.nch <= 24) launch_rows<24>(P, B, g, s);
     else if (P.nch <= 32) launch_rows<32>(P, B, g, s);
     else launch_rows<40>(P, B, g, s);
+    mark(marks, 7, s);
     return hipGetLastError();
 }
 

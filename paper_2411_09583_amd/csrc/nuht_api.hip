@@ -100,11 +100,14 @@ static int local_rank(int nu, double eps, double z)
 // Exponential-of-semicircle kernel: width and shape from eps, and the
 // Chebyshev series of its Fourier transform ES^(kappa) on [0, w pi / 4].
 // ===========================================================================
+// The type-3 transforms are run about a decade tighter than eps: the method's
+// own truncation error already reaches ~0.8 eps in the max norm, so the NUFFT
+// error must stay near eps/10 for the total to stay within eps.
 static int es_width(double eps, int precision)
 {
     int digits = (int)std::ceil(-std::log10(eps) - 1e-9);
-    int w = precision == NUHT_FP32_SPREAD ? digits + 1 : digits + 2;
-    return std::min(std::max(w, 4), 17);
+    int w = precision == NUHT_FP32_SPREAD ? digits + 2 : digits + 3;
+    return std::min(std::max(w, 4), 18);
 }
 
 static double es_beta(int w) { return 2.30 * w; }
@@ -244,7 +247,32 @@ struct nuht_plan_s {
     int64_t geom_bytes = 0;
     Geometry fwd, adj;
     Partition pf, pa;
+    // stage timing (diagnostics): kStages + 1 events per profiled call
+    bool prof = false;
+    std::vector<hipEvent_t> prof_events;
+    int64_t prof_calls = 0;
 };
+
+static void prof_clear(nuht_plan_t p)
+{
+    for (hipEvent_t e : p->prof_events) (void)hipEventDestroy(e);
+    p->prof_events.clear();
+    p->prof_calls = 0;
+}
+
+// Events for one profiled execute call, or null when profiling is off.
+static hipEvent_t* prof_marks(nuht_plan_t p)
+{
+    if (!p->prof) return nullptr;
+    size_t base = p->prof_events.size();
+    for (int i = 0; i <= kStages; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+        p->prof_events.push_back(e);
+    }
+    p->prof_calls++;
+    return p->prof_events.data() + base;
+}
 
 #define HIP_TRY(x)                                   \
     do {                                             \
@@ -379,6 +407,7 @@ static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int
         Pt.cls.push_back(fc);
     }
     NUHT_TRY(Pt.alloc(B.scratch, (size_t)scratch));
+    NUHT_TRY(Pt.alloc(B.gd, (size_t)G.m));
     Pt.built = true;
     return NUHT_OK;
 }
@@ -386,6 +415,7 @@ static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int
 static void free_plan(nuht_plan_t p)
 {
     if (!p) return;
+    prof_clear(p);
     p->pf.release();
     p->pa.release();
     if (p->keys) (void)hipFree(p->keys);
@@ -484,7 +514,7 @@ int nuht_execute(nuht_plan_t p, const double* c_dev, double* g_dev, void* stream
     if ((p->n > 0 && !c_dev) || (p->m > 0 && !g_dev)) return NUHT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const Partition& Pt = p->pf;
-    HIP_TRY(launch_execute(Pt.P, Pt.sum, Pt.B, Pt.cls.data(), (int)Pt.cls.size(), c_dev, g_dev, s));
+    HIP_TRY(launch_execute(Pt.P, Pt.sum, Pt.B, Pt.cls.data(), (int)Pt.cls.size(), c_dev, g_dev, s, prof_marks(p)));
     return NUHT_OK;
 }
 
@@ -498,7 +528,8 @@ int nuht_adjoint(nuht_plan_t p, const double* y_dev, double* cbar_dev, void* str
         if (rc != NUHT_OK) return rc;
     }
     const Partition& Pt = p->pa;
-    HIP_TRY(launch_execute(Pt.P, Pt.sum, Pt.B, Pt.cls.data(), (int)Pt.cls.size(), y_dev, cbar_dev, s));
+    HIP_TRY(launch_execute(Pt.P, Pt.sum, Pt.B, Pt.cls.data(), (int)Pt.cls.size(), y_dev, cbar_dev, s,
+                           prof_marks(p)));
     return NUHT_OK;
 }
 
@@ -528,6 +559,32 @@ int nuht_plan_info(nuht_plan_t p, nuht_info* info)
     info->direct_entries = S.d_ent;
     info->grid_cells = S.grid_cells; info->fft_points = S.fft_points;
     info->workspace_bytes = p->geom_bytes + p->pf.bytes + p->pa.bytes;
+    return NUHT_OK;
+}
+
+int nuht_profile(nuht_plan_t p, int enable)
+{
+    if (!p) return NUHT_EINVAL;
+    prof_clear(p);
+    p->prof = enable != 0;
+    return NUHT_OK;
+}
+
+int nuht_profile_read(nuht_plan_t p, double* stage_ms, int64_t* calls)
+{
+    if (!p || !stage_ms) return NUHT_EINVAL;
+    for (int i = 0; i < kStages; ++i) stage_ms[i] = 0.0;
+    int64_t nc = (int64_t)p->prof_events.size() / (kStages + 1);
+    if (nc > 0) HIP_TRY(hipEventSynchronize(p->prof_events.back()));
+    for (int64_t c = 0; c < nc; ++c) {
+        hipEvent_t* e = p->prof_events.data() + c * (kStages + 1);
+        for (int i = 0; i < kStages; ++i) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, e[i], e[i + 1]));
+            stage_ms[i] += ms;
+        }
+    }
+    if (calls) *calls = nc;
     return NUHT_OK;
 }
 

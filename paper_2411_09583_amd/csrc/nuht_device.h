@@ -27,7 +27,8 @@ __device__ __forceinline__ dd two_sum(double a, double b)
 
 constexpr double kTwoPiHi = 6.283185307179586232;        // 2 pi rounded to double
 constexpr double kTwoPiLo = 2.4492935982947064e-16;       // 2 pi - kTwoPiHi
-constexpr double kInvTwoPi = 0.15915494309189535;
+constexpr double kInvTwoPi = 0.15915494309189535;        // 1/(2 pi) rounded to double
+constexpr double kInvTwoPiLo = -9.8393383375912433e-18;   // 1/(2 pi) - kInvTwoPi
 constexpr double kPi = 3.141592653589793116;
 constexpr double kSqrt2OverPi = 0.79788456080286541;
 
@@ -44,8 +45,8 @@ __device__ __forceinline__ void cis_dd(double hi, double lo, double& c, double& 
     dd t = two_sum(r, rl);
     double sn, cs;
     sincos(t.hi, &sn, &cs);
-    c = cs - t.lo * sn;
-    s = sn + t.lo * cs;
+    c = __builtin_fma(-t.lo, sn, cs);
+    s = __builtin_fma(t.lo, cs, sn);
 }
 
 // Exponential-of-semicircle kernel exp(beta (sqrt(1 - x^2) - 1)) on |x| < 1.
@@ -112,7 +113,7 @@ __device__ inline double besselj_miller(int nu, double xh, double xl)
     }
     double inv = 1.0 / sqrt(S);
     double d = nu == 0 ? -jp : 0.5 * (jm - jp);
-    return (j0 + xl * d) * inv;
+    return __builtin_fma(xl, d, j0) * inv;
 }
 
 // The M-term Hankel approximation of J_nu at x = xh + xl (Sec. 3.2):
@@ -132,7 +133,7 @@ __device__ inline double besselj_hankel(const PlanDev& P, double xh, double xl)
         q = __builtin_fma(q, inv2, sg * P.hank[2 * l + 1]);
     }
     q *= inv;
-    return sqrt(2.0 / (kPi * xh)) * (p * c - q * s);
+    return sqrt(2.0 / (kPi * xh)) * __builtin_fma(p, c, -q * s);
 }
 
 // J_nu(x) accurate to the plan's eps: Hankel's M-term formula above the
@@ -140,6 +141,57 @@ __device__ inline double besselj_hankel(const PlanDev& P, double xh, double xl)
 __device__ __forceinline__ double besselj_eps(const PlanDev& P, double xh, double xl)
 {
     return xh > P.z ? besselj_hankel(P, xh, xl) : besselj_miller(P.nu, xh, xl);
+}
+
+// J_nu(x) to full FP64 accuracy: Hankel's expansion summed until its terms
+// fall below 1e-17 where it converges that far (x >= 25, terms never above
+// 1e3), Miller's recurrence otherwise.  Used for the direct blocks.
+__device__ inline double besselj_full(const PlanDev& P, double xh, double xl)
+{
+    if (xh >= 25.0) {
+        const double mu = 4.0 * (double)P.nu * (double)P.nu;
+        double t = 1.0, p = 1.0, q = 0.0, prev = 1e300;
+        bool ok = false;
+        for (int k = 1; k < 120; ++k) {
+            double f = 2.0 * k - 1.0;
+            t *= (mu - f * f) / (8.0 * k * xh);
+            double at = fabs(t);
+            double sg = ((k >> 1) & 1) ? -1.0 : 1.0;
+            if (k & 1) q = __builtin_fma(sg, t, q); else p = __builtin_fma(sg, t, p);
+            if (at < 1e-17) { ok = true; break; }
+            if ((at > prev && k > 2) || at > 1e3) break;
+            prev = at;
+        }
+        if (ok) {
+            dd ph = two_sum(xh, P.phi_hi);
+            double c, s;
+            cis_dd(ph.hi, ph.lo + xl + P.phi_lo, c, s);
+            return sqrt(2.0 / (kPi * xh)) * __builtin_fma(p, c, -q * s);
+        }
+    }
+    if (xh < 1e-30) return P.nu == 0 ? 1.0 : 0.0;
+    double top = (double)(P.nu + 1) > xh ? (double)(P.nu + 1) : xh;
+    int N = (int)(top + 20.0 + 15.0 * cbrt(xh > 1.0 ? xh : 1.0));
+    double rec = 2.0 / xh;
+    double yk1 = 0.0, yk = 1e-100, S = 0.0;
+    double jm = 0.0, j0 = 0.0, jp = 0.0;
+    const int nu = P.nu;
+    for (int k = N; k >= 0; --k) {
+        if (k == nu + 1) jp = yk;
+        if (k == nu) j0 = yk;
+        if (k == nu - 1) jm = yk;
+        S = __builtin_fma(k == 0 ? yk : 2.0 * yk, yk, S);
+        if (k == 0) break;
+        double ykm1 = __builtin_fma((double)k * rec, yk, -yk1);
+        yk1 = yk;
+        yk = ykm1;
+        if (fabs(yk) > 1e100) {
+            yk *= 1e-100; yk1 *= 1e-100; S *= 1e-200;
+            jm *= 1e-100; j0 *= 1e-100; jp *= 1e-100;
+        }
+    }
+    double d = nu == 0 ? -jp : 0.5 * (jm - jp);
+    return __builtin_fma(xl, d, j0) / sqrt(S);
 }
 
 }  // namespace nuht

@@ -359,7 +359,7 @@ __global__ void k_block_params(PlanDev P, Arena A, int32_t n_l, int32_t n_a, int
             while (N2 < 4 * maxl + 4) { N2 <<= 1; ++lg; }
             // h N2 / (2 pi): exact scaling of the double-double 1/(2 pi)
             B.Khi = h * (double)N2 * kInvTwoPi;
-            B.Klo = h * (double)N2 * (-9.4287216877795e-18);
+            B.Klo = h * (double)N2 * kInvTwoPiLo;
         }
         B.fft = fft; B.N2 = N2;
         int32_t nb = B.k1 - B.k0 + 1;
