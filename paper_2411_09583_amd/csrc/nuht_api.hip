@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -187,10 +188,62 @@ struct Geometry {
     const int32_t* perm_w = nullptr;
 };
 
+// Device memory comes from a stream-ordered pool per device (plans are made
+// and dropped often, and the pool keeps the memory between them).  Each
+// buffer remembers the stream it was allocated on and is released there.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    hipStream_t stream = nullptr;
 };
+
+static hipMemPool_t device_pool()
+{
+    static std::mutex mu;
+    static hipMemPool_t pools[64] = {};
+    static bool tried[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) { (void)hipGetLastError(); return nullptr; }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!tried[dev]) {
+        tried[dev] = true;
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t pool = nullptr;
+        if (hipMemPoolCreate(&pool, &props) == hipSuccess) {
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+            pools[dev] = pool;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    return pools[dev];
+}
+
+static int dev_alloc(DevBuf& b, size_t bytes, hipStream_t s)
+{
+    b = DevBuf{};
+    if (bytes == 0) return NUHT_OK;
+    void* p = nullptr;
+    hipMemPool_t pool = device_pool();
+    hipError_t e = pool ? hipMallocFromPoolAsync(&p, bytes, pool, s) : hipMalloc(&p, bytes);
+    if (e != hipSuccess) { (void)hipGetLastError(); return NUHT_ENOMEM; }
+    b.p = p; b.bytes = bytes; b.stream = pool ? s : nullptr;
+    return NUHT_OK;
+}
+
+static void dev_free(DevBuf& b)
+{
+    if (b.p) {
+        if (b.stream || device_pool()) (void)hipFreeAsync(b.p, b.stream);
+        else (void)hipFree(b.p);
+    }
+    b = DevBuf{};
+}
 
 struct Partition {
     bool built = false;
@@ -201,10 +254,11 @@ struct Partition {
     Arena A{};
     std::vector<DevBuf> bufs;
     int64_t bytes = 0;
+    hipStream_t stream = nullptr;   // where this partition's memory lives
 
     void release()
     {
-        for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
+        for (auto& b : bufs) dev_free(b);
         bufs.clear();
         bytes = 0;
         built = false;
@@ -217,12 +271,12 @@ struct Partition {
     {
         out = nullptr;
         if (count == 0) return NUHT_OK;
-        void* p = nullptr;
-        size_t bytes_ = count * sizeof(T);
-        if (hipMalloc(&p, bytes_) != hipSuccess) { (void)hipGetLastError(); return NUHT_ENOMEM; }
-        bufs.push_back({p, bytes_});
-        bytes += (int64_t)bytes_;
-        out = (T*)p;
+        DevBuf b;
+        int rc = dev_alloc(b, count * sizeof(T), stream);
+        if (rc != NUHT_OK) return rc;
+        bufs.push_back(b);
+        bytes += (int64_t)b.bytes;
+        out = (T*)b.p;
         return NUHT_OK;
     }
     ~Partition() { release(); }
@@ -237,13 +291,16 @@ struct nuht_plan_s {
     double eps = 0.0;
     nuht_opts opts{};
     int64_t n = 0, m = 0;
+    DevBuf b_keys, b_vals, b_keys2, b_vals2, b_hist, b_sum, b_flag;
     uint64_t* keys = nullptr;    // sorted points then sorted frequencies (bit patterns)
     int32_t* vals = nullptr;     // matching caller indices
     uint64_t* keys2 = nullptr;
     int32_t* vals2 = nullptr;
     int32_t* hist = nullptr;
     Summary* d_sum = nullptr;
+    int32_t* d_flag = nullptr;   // domain error flag of the input check
     Summary* h_sum = nullptr;    // pinned
+    int32_t* h_flag = nullptr;   // pinned
     int64_t geom_bytes = 0;
     Geometry fwd, adj;
     Partition pf, pa;
@@ -303,12 +360,22 @@ static void fill_params(PlanDev& P, int nu, double eps, const nuht_opts& o)
     phase_offset(anu, P.phi_hi, P.phi_lo);
     P.kappa_max = P.w * M_PI / 4.0 * (1.0 + 1e-9);
     P.n_eshat = 30;
-    eshat_chebyshev(P.w, P.beta, P.kappa_max, P.eshat, P.n_eshat);
+    // the Chebyshev series depends only on the kernel width (beta follows w)
+    static std::mutex mu;
+    static double cache[32][32];
+    static bool have[32] = {};
+    std::lock_guard<std::mutex> lock(mu);
+    if (!have[P.w]) {
+        eshat_chebyshev(P.w, P.beta, P.kappa_max, cache[P.w], P.n_eshat);
+        have[P.w] = true;
+    }
+    for (int i = 0; i < P.n_eshat; ++i) P.eshat[i] = cache[P.w][i];
 }
 
 static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int nu, hipStream_t s)
 {
     Pt.release();
+    Pt.stream = s;
     const nuht_opts& o = pl->opts;
     PlanDev& P = Pt.P;
     P = PlanDev{};
@@ -317,27 +384,33 @@ static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int
     P.n = G.n; P.m = G.m;
     P.rs = G.rs; P.ws = G.ws; P.perm_r = G.perm_r; P.perm_w = G.perm_w;
     Pt.sum = Summary{};
-    if (G.n == 0 || G.m == 0) { Pt.built = true; return NUHT_OK; }
+    *pl->h_flag = 0;
+    if (G.n == 0 || G.m == 0) {
+        HIP_TRY(hipMemcpyAsync(pl->h_flag, pl->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        Pt.built = true;
+        return NUHT_OK;
+    }
 
     int64_t min_size = o.min_size > 0 ? o.min_size : 1024;
     int ncand = o.split_candidates > 1 ? o.split_candidates : 16;
     int dft_max = o.dft_max == 0 ? 48 : o.dft_max;
     const double sigma = 2.0;
 
-    int32_t* K = nullptr;
-    NUHT_TRY(Pt.alloc(K, (size_t)G.m));
-    HIP_TRY(launch_staircase(G.rs, G.n, G.ws, G.m, P.z, K, s));
-
     int64_t tot = (int64_t)G.n + G.m;
     int32_t cap = (int32_t)std::min<int64_t>(tot / 32 + 4096, 1 << 28);
     int32_t icap = (int32_t)std::min<int64_t>(64 * (tot / kSpreadChunk) + 2 * (int64_t)cap, 1 << 28);
     Summary& S = Pt.sum;
     for (int attempt = 0; attempt < 6; ++attempt) {
-        // tables of this attempt (freed on retry by rebuilding the buffer list)
-        Partition tmp;   // scratch holder for the arena so a retry frees it
+        Partition tmp;   // this attempt's tables; dropped on a retry
+        tmp.stream = s;
         Arena A{};
         A.node_cap = cap; A.l_cap = cap; A.a_cap = cap; A.d_cap = 2 * cap; A.q_cap = cap;
         A.litem_cap = icap; A.aitem_cap = icap;
+        int32_t *K = nullptr, *Jc = nullptr, *a_cells = nullptr;
+        NUHT_TRY(tmp.alloc(K, (size_t)G.m));
+        NUHT_TRY(tmp.alloc(Jc, (size_t)G.n));
+        NUHT_TRY(tmp.alloc(a_cells, (size_t)A.aitem_cap));
         NUHT_TRY(tmp.alloc(A.nodes, (size_t)A.node_cap));
         NUHT_TRY(tmp.alloc(A.lb, (size_t)A.l_cap));
         NUHT_TRY(tmp.alloc(A.ab, (size_t)A.a_cap));
@@ -347,34 +420,23 @@ static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int
         NUHT_TRY(tmp.alloc(A.litems, (size_t)A.litem_cap));
         NUHT_TRY(tmp.alloc(A.aitems, (size_t)A.aitem_cap));
         NUHT_TRY(tmp.alloc(A.fft_list, (size_t)A.a_cap));
-        HIP_TRY(hipMemsetAsync(pl->d_sum, 0, sizeof(Summary), s));
-        HIP_TRY(launch_subdivide(K, G.m, G.n, min_size, ncand, A, pl->d_sum, s));
-        HIP_TRY(hipMemcpyAsync(pl->h_sum, pl->d_sum, sizeof(Summary), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        S = *pl->h_sum;
-        if (S.overflow == 2) return NUHT_ECAPACITY;   // subdivision deeper than kMaxLevels
-        if (S.overflow) {
-            int64_t need = std::max<int64_t>({(int64_t)S.n_nodes, (int64_t)S.n_l, (int64_t)S.n_a, (int64_t)S.n_d / 2,
-                                              (int64_t)cap * 4});
-            cap = (int32_t)std::min<int64_t>(need + 1024, 1 << 29);
-            continue;
-        }
-        int64_t* a_sizes = nullptr;
-        int32_t* l_sizes = nullptr;
-        NUHT_TRY(tmp.alloc(a_sizes, (size_t)4 * std::max(S.n_a, 1)));
-        NUHT_TRY(tmp.alloc(l_sizes, (size_t)std::max(S.n_l, 1)));
         P.nodes = A.nodes; P.lb = A.lb; P.ab = A.ab; P.db = A.db;
         P.litems = A.litems; P.aitems = A.aitems; P.fft_list = A.fft_list;
-        HIP_TRY(launch_block_params(P, A, S.n_l, S.n_a, dft_max, sigma, a_sizes, l_sizes, pl->d_sum, s));
-        HIP_TRY(launch_plan_scan(P, A, S.n_l, S.n_a, S.n_d, a_sizes, l_sizes, pl->d_sum, s));
-        HIP_TRY(launch_fill_items(P, A, S.n_l, S.n_a, s));
+        HIP_TRY(hipMemsetAsync(pl->d_sum, 0, sizeof(Summary), s));
+        HIP_TRY(launch_planning(P, A, K, Jc, a_cells, min_size, ncand, dft_max, sigma, pl->d_sum, s));
         HIP_TRY(hipMemcpyAsync(pl->h_sum, pl->d_sum, sizeof(Summary), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(pl->h_flag, pl->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         S = *pl->h_sum;
+        if (*pl->h_flag) return NUHT_EDOMAIN;
+        if (S.overflow == 2) return NUHT_ECAPACITY;   // subdivision deeper than kMaxLevels
         if (S.grid_error) return NUHT_ECAPACITY;
         if (S.overflow) {
-            int64_t need = std::max<int64_t>({(int64_t)S.n_litems, (int64_t)S.n_aitems, (int64_t)icap * 4});
-            icap = (int32_t)std::min<int64_t>(need + 1024, 1 << 29);
+            int64_t need = std::max<int64_t>({(int64_t)S.n_nodes, (int64_t)S.n_l, (int64_t)S.n_a, (int64_t)S.n_d / 2});
+            if (need >= cap) cap = (int32_t)std::min<int64_t>(2 * need + 1024, 1 << 29);
+            int64_t ineed = std::max<int64_t>((int64_t)S.n_litems, (int64_t)S.n_aitems);
+            if (ineed >= icap) icap = (int32_t)std::min<int64_t>(2 * ineed + 1024, 1 << 29);
+            if (need < cap && ineed < icap) { cap *= 2; icap *= 2; }
             continue;
         }
         // keep this attempt's tables
@@ -418,13 +480,15 @@ static void free_plan(nuht_plan_t p)
     prof_clear(p);
     p->pf.release();
     p->pa.release();
-    if (p->keys) (void)hipFree(p->keys);
-    if (p->vals) (void)hipFree(p->vals);
-    if (p->keys2) (void)hipFree(p->keys2);
-    if (p->vals2) (void)hipFree(p->vals2);
-    if (p->hist) (void)hipFree(p->hist);
-    if (p->d_sum) (void)hipFree(p->d_sum);
+    dev_free(p->b_keys);
+    dev_free(p->b_vals);
+    dev_free(p->b_keys2);
+    dev_free(p->b_vals2);
+    dev_free(p->b_hist);
+    dev_free(p->b_sum);
+    dev_free(p->b_flag);
     if (p->h_sum) (void)hipHostFree(p->h_sum);
+    if (p->h_flag) (void)hipHostFree(p->h_flag);
     delete p;
 }
 
@@ -471,29 +535,30 @@ int nuht_plan(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_d
     p->nu_req = nu; p->eps = eps; p->opts = o; p->n = n; p->m = m;
     int64_t tot = n + m;
     auto fail = [&](int code) { free_plan(p); return code; };
-    if (hipMalloc(&p->d_sum, sizeof(Summary)) != hipSuccess) return fail(NUHT_ENOMEM);
+    if (dev_alloc(p->b_sum, sizeof(Summary), s) != NUHT_OK) return fail(NUHT_ENOMEM);
+    if (dev_alloc(p->b_flag, sizeof(int32_t), s) != NUHT_OK) return fail(NUHT_ENOMEM);
+    p->d_sum = (Summary*)p->b_sum.p;
+    p->d_flag = (int32_t*)p->b_flag.p;
     if (hipHostMalloc(&p->h_sum, sizeof(Summary), hipHostMallocDefault) != hipSuccess) return fail(NUHT_ENOMEM);
+    if (hipHostMalloc(&p->h_flag, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) return fail(NUHT_ENOMEM);
     if (tot > 0) {
-        if (hipMalloc(&p->keys, sizeof(uint64_t) * tot) != hipSuccess) return fail(NUHT_ENOMEM);
-        if (hipMalloc(&p->vals, sizeof(int32_t) * tot) != hipSuccess) return fail(NUHT_ENOMEM);
-        if (hipMalloc(&p->keys2, sizeof(uint64_t) * tot) != hipSuccess) return fail(NUHT_ENOMEM);
-        if (hipMalloc(&p->vals2, sizeof(int32_t) * tot) != hipSuccess) return fail(NUHT_ENOMEM);
-        if (hipMalloc(&p->hist, sizeof(int32_t) * sort_hist_len((int32_t)n, (int32_t)m)) != hipSuccess)
+        if (dev_alloc(p->b_keys, sizeof(uint64_t) * tot, s) != NUHT_OK) return fail(NUHT_ENOMEM);
+        if (dev_alloc(p->b_vals, sizeof(int32_t) * tot, s) != NUHT_OK) return fail(NUHT_ENOMEM);
+        if (dev_alloc(p->b_keys2, sizeof(uint64_t) * tot, s) != NUHT_OK) return fail(NUHT_ENOMEM);
+        if (dev_alloc(p->b_vals2, sizeof(int32_t) * tot, s) != NUHT_OK) return fail(NUHT_ENOMEM);
+        if (dev_alloc(p->b_hist, sizeof(int32_t) * sort_hist_len((int32_t)n, (int32_t)m), s) != NUHT_OK)
             return fail(NUHT_ENOMEM);
+        p->keys = (uint64_t*)p->b_keys.p; p->vals = (int32_t*)p->b_vals.p;
+        p->keys2 = (uint64_t*)p->b_keys2.p; p->vals2 = (int32_t*)p->b_vals2.p;
+        p->hist = (int32_t*)p->b_hist.p;
         p->geom_bytes = (int64_t)tot * 24;
     }
-    if (hipMemsetAsync(p->d_sum, 0, sizeof(Summary), s) != hipSuccess) return fail(NUHT_EHIP);
-    int32_t* err = &p->d_sum->domain_error;
-    if (launch_make_keys(r_dev, (int32_t)n, p->keys, p->vals, err, s) != hipSuccess) return fail(NUHT_EHIP);
-    if (launch_make_keys(omega_dev, (int32_t)m, p->keys + n, p->vals + n, err, s) != hipSuccess)
+    if (hipMemsetAsync(p->d_flag, 0, sizeof(int32_t), s) != hipSuccess) return fail(NUHT_EHIP);
+    if (launch_make_keys(r_dev, (int32_t)n, p->keys, p->vals, p->d_flag, s) != hipSuccess) return fail(NUHT_EHIP);
+    if (launch_make_keys(omega_dev, (int32_t)m, p->keys + n, p->vals + n, p->d_flag, s) != hipSuccess)
         return fail(NUHT_EHIP);
     if (launch_sort_pairs(p->keys, p->vals, p->keys2, p->vals2, p->hist, (int32_t)n, (int32_t)m, s) != hipSuccess)
         return fail(NUHT_EHIP);
-    if (hipMemcpyAsync(p->h_sum, p->d_sum, sizeof(Summary), hipMemcpyDeviceToHost, s) != hipSuccess)
-        return fail(NUHT_EHIP);
-    if (hipStreamSynchronize(s) != hipSuccess) return fail(NUHT_EHIP);
-    if (p->h_sum->domain_error) return fail(NUHT_EDOMAIN);
-    // the value half of the sort was made against the per-segment origin
     p->fwd.n = (int32_t)n; p->fwd.m = (int32_t)m;
     p->fwd.rs = (const double*)p->keys;
     p->fwd.ws = (const double*)(p->keys + n);
@@ -502,6 +567,8 @@ int nuht_plan(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_d
     p->adj.n = (int32_t)m; p->adj.m = (int32_t)n;
     p->adj.rs = p->fwd.ws; p->adj.ws = p->fwd.rs;
     p->adj.perm_r = p->fwd.perm_w; p->adj.perm_w = p->fwd.perm_r;
+    // the one synchronisation of the plan happens inside (it also reads the
+    // input check's flag)
     int rc = build_partition(p, p->pf, p->fwd, nu, s);
     if (rc != NUHT_OK) return fail(rc);
     *out = p;

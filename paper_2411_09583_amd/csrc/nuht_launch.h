@@ -30,15 +30,11 @@ hipError_t launch_make_keys(const double* x, int32_t n, uint64_t* key, int32_t* 
 hipError_t launch_sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int32_t* hist, int32_t na,
                              int32_t nb, hipStream_t s);
 int sort_hist_len(int32_t na, int32_t nb);
-hipError_t launch_staircase(const double* rs, int32_t n, const double* ws, int32_t m, double z, int32_t* K,
-                            hipStream_t s);
-hipError_t launch_subdivide(const int32_t* K, int32_t m, int32_t n, int64_t min_size, int32_t ncand, const Arena& A,
-                            Summary* sum, hipStream_t s);
-hipError_t launch_block_params(const PlanDev& P, const Arena& A, int32_t n_l, int32_t n_a, int32_t dft_max,
-                               double sigma, int64_t* a_sizes, int32_t* l_sizes, Summary* sum, hipStream_t s);
-hipError_t launch_plan_scan(const PlanDev& P, const Arena& A, int32_t n_l, int32_t n_a, int32_t n_d,
-                            const int64_t* a_sizes, const int32_t* l_sizes, Summary* sum, hipStream_t s);
-hipError_t launch_fill_items(const PlanDev& P, const Arena& A, int32_t n_l, int32_t n_a, hipStream_t s);
+// Staircases, subdivision (Alg. 1), block parameters, work items and their
+// offsets, all on the device; counts and totals are left in *sum.
+hipError_t launch_planning(const PlanDev& P, const Arena& A, int32_t* K, int32_t* Jc, int32_t* a_cells,
+                           int64_t min_size, int32_t ncand, int32_t dft_max, double sigma, Summary* sum,
+                           hipStream_t s);
 
 // execution (exec.hip)
 struct ExecBuffers {

@@ -62,33 +62,72 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t* __re
     hist[S.hoff[seg] + threadIdx.x * ntiles + lt] = h[threadIdx.x];
 }
 
-// Exclusive scan of each segment's digit-major histogram (one block per segment).
-__global__ __launch_bounds__(1024) void k_sort_scan(int32_t* __restrict__ hist, SortSegs S)
+// ---------------------------------------------------------------------------
+// Block-wide scans (1024 threads = 16 waves): inclusive scans inside each wave
+// with cross-lane shuffles, then a scan of the 16 wave totals.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T v)
 {
-    __shared__ int32_t sm[1024];
-    __shared__ int32_t carry;
-    int seg = blockIdx.x;
-    int len = S.hoff[seg + 1] - S.hoff[seg];
-    int32_t* h = hist + S.hoff[seg];
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int c0 = 0; c0 < len; c0 += 1024) {
-        int i = c0 + threadIdx.x;
-        int v = i < len ? h[i] : 0;
-        sm[threadIdx.x] = v;
-        __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {
-            int t = threadIdx.x >= o ? sm[threadIdx.x - o] : 0;
-            __syncthreads();
-            sm[threadIdx.x] += t;
-            __syncthreads();
-        }
-        int incl = sm[threadIdx.x];
-        if (i < len) h[i] = carry + incl - v;
-        __syncthreads();
-        if (threadIdx.x == 1023) carry += incl;
-        __syncthreads();
+    const int lane = threadIdx.x & 63;
+    #pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T t = __shfl_up(v, o);
+        if (lane >= o) v += t;
     }
+    return v;
+}
+
+// Exclusive scan of v[q] over the block; tot[q] receives the block total.
+template <class T, int NV>
+__device__ void block_scan(T (&v)[NV], T (&tot)[NV], T (*wsum)[16])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T incl[NV];
+    #pragma unroll
+    for (int q = 0; q < NV; ++q) incl[q] = wave_incl_scan(v[q]);
+    if (lane == 63) {
+        #pragma unroll
+        for (int q = 0; q < NV; ++q) wsum[q][wave] = incl[q];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        #pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            T x = lane < 16 ? wsum[q][lane] : T(0);
+            x = wave_incl_scan(x);
+            if (lane < 16) wsum[q][lane] = x;
+        }
+    }
+    __syncthreads();
+    #pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        T base = wave > 0 ? wsum[q][wave - 1] : T(0);
+        tot[q] = wsum[q][15];
+        v[q] = base + incl[q] - v[q];
+    }
+    __syncthreads();
+}
+
+// Per-digit scan of the tile counts: one block per (segment, digit) turns the
+// digit's row of tile counts into exclusive offsets within the digit and
+// stores the digit's total; the scatter adds the digits' own offsets.
+__global__ __launch_bounds__(1024) void k_sort_scan(int32_t* __restrict__ hist, int32_t* __restrict__ dtot,
+                                                    SortSegs S)
+{
+    __shared__ int32_t wsum[1][16];
+    int seg = blockIdx.x >> 8, d = blockIdx.x & 255;
+    int ntiles = S.tile0[seg + 1] - S.tile0[seg];
+    int32_t* h = hist + S.hoff[seg] + d * ntiles;
+    int32_t run = 0;
+    for (int c0 = 0; c0 < ntiles; c0 += 1024) {
+        int i = c0 + threadIdx.x;
+        int32_t v[1] = {i < ntiles ? h[i] : 0}, tot[1];
+        block_scan<int32_t, 1>(v, tot, wsum);
+        if (i < ntiles) h[i] = run + v[0];
+        run += tot[0];
+    }
+    if (threadIdx.x == 0) dtot[seg * 256 + d] = run;
 }
 
 // Stable scatter.  Within a tile, element order is (round, thread); each wave
@@ -98,7 +137,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
                                                                 const int32_t* __restrict__ vin,
                                                                 uint64_t* __restrict__ kout,
                                                                 int32_t* __restrict__ vout, SortSegs S,
-                                                                int shift, const int32_t* __restrict__ hist)
+                                                                int shift, const int32_t* __restrict__ hist,
+                                                                const int32_t* __restrict__ dtot)
 {
     __shared__ int32_t base[256];
     __shared__ int32_t wcnt[kSortThreads / 64][256];
@@ -111,7 +151,22 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
     int lane = threadIdx.x & 63;
     int wave = threadIdx.x >> 6;
     uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    base[threadIdx.x] = hist[S.hoff[seg] + threadIdx.x * ntiles + lt] + S.off[seg];
+    // digit offsets: exclusive scan of the segment's digit totals
+    {
+        int32_t t = dtot[seg * 256 + threadIdx.x];
+        int32_t incl = t;
+        #pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            int32_t u = __shfl_up(incl, o);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) wcnt[0][wave] = incl;
+        __syncthreads();
+        int32_t wb = 0;
+        for (int w2 = 0; w2 < wave; ++w2) wb += wcnt[0][w2];
+        __syncthreads();
+        base[threadIdx.x] = S.off[seg] + wb + incl - t + hist[S.hoff[seg] + threadIdx.x * ntiles + lt];
+    }
     for (int r = 0; r < kSortRounds; ++r) {
         for (int q = threadIdx.x; q < (kSortThreads / 64) * 256; q += kSortThreads)
             (&wcnt[0][0])[q] = 0;
@@ -145,7 +200,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
 }
 
 // ---------------------------------------------------------------------------
-// Staircase: K[j] = #{k : omega_j r_k <= z}, the product decided exactly.
+// Staircases of the local region (the product decided exactly):
+//   K[j]  = #{k : omega_j r_k <= z}   (rows; K is nonincreasing in j)
+//   Jc[k] = #{j : omega_j r_k <= z}   (columns; Jc is nonincreasing in k)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool exact_le(double a, double b, double z)
 {
@@ -155,59 +212,32 @@ __device__ __forceinline__ bool exact_le(double a, double b, double z)
     return p.lo <= 0.0;
 }
 
-__global__ void k_staircase(const double* __restrict__ rs, int32_t n, const double* __restrict__ ws, int32_t m,
-                            double z, int32_t* __restrict__ K)
+__global__ void k_staircase(const double* __restrict__ sorted, int32_t len, const double* __restrict__ q, int32_t nq,
+                            double z, int32_t* __restrict__ out)
 {
     int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
-    double w = ws[j];
-    int32_t lo = 0, hi = n;
+    if (j >= nq) return;
+    double w = q[j];
+    int32_t lo = 0, hi = len;
     while (lo < hi) {
         int32_t mid = lo + ((hi - lo) >> 1);
-        if (exact_le(w, rs[mid], z)) lo = mid + 1; else hi = mid;
+        if (exact_le(w, sorted[mid], z)) lo = mid + 1; else hi = mid;
     }
-    K[j] = lo;
-}
-
-// ---------------------------------------------------------------------------
-// Block-wide exclusive scans for a 1024-thread block.
-// ---------------------------------------------------------------------------
-template <class T, int NV>
-__device__ void block_scan(T (&v)[NV], T (&tot)[NV], T (*sm)[1024])
-{
-    #pragma unroll
-    for (int q = 0; q < NV; ++q) sm[q][threadIdx.x] = v[q];
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        T t[NV];
-        #pragma unroll
-        for (int q = 0; q < NV; ++q) t[q] = threadIdx.x >= (unsigned)o ? sm[q][threadIdx.x - o] : T(0);
-        __syncthreads();
-        #pragma unroll
-        for (int q = 0; q < NV; ++q) sm[q][threadIdx.x] += t[q];
-        __syncthreads();
-    }
-    #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        T incl = sm[q][threadIdx.x];
-        tot[q] = sm[q][1023];
-        v[q] = incl - v[q];
-    }
-    __syncthreads();
+    out[j] = lo;
 }
 
 // ---------------------------------------------------------------------------
 // Alg. 1 (Subdivide), level by level in one 1024-thread block.  Every mixed
 // block of a level becomes a Node; its split follows the quasi-optimal
-// SplitIndices of Sec. 4.1 (candidate rows equispaced, minimal mixed area,
-// ties to the smaller row).  Numbering is deterministic: nodes in level order,
-// children in (parent, position) order.
+// SplitIndices of Sec. 4.1 (candidate rows equispaced over the rows that hold
+// a local entry, minimal mixed area, ties to the smaller row).  Numbering is
+// deterministic: nodes in level order, children in (parent, position) order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ K, int32_t m, int32_t n,
-                                                    int64_t min_size, int32_t ncand, Arena A, Summary* __restrict__ sum)
+__global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ K, const int32_t* __restrict__ Jc,
+                                                    int32_t m, int32_t n, int64_t min_size, int32_t ncand, Arena A,
+                                                    Summary* __restrict__ sum)
 {
-    __shared__ int32_t sm[4][1024];
-    __shared__ int32_t s_tot[4];
+    __shared__ int32_t wsum[4][16];
     int tid = threadIdx.x;
     Rect* cur = A.q0;
     Rect* nxt = A.q1;
@@ -233,15 +263,11 @@ __global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ 
                 } else if (K[R.j0] <= R.k0) {       // wholly asymptotic
                     js = R.j0 - 1; ks = R.k0 - 1;
                 } else {
-                    // candidate rows: equispaced over the rows that hold a local
-                    // entry of the block (K[j] > k0; K is nonincreasing in j)
-                    int32_t lo = R.j0, hi = R.j1;
-                    while (lo < hi) {
-                        int32_t mid = lo + ((hi - lo + 1) >> 1);
-                        if (K[mid] > R.k0) lo = mid; else hi = mid - 1;
-                    }
+                    // the last row holding a local entry: K[j] > k0 <=> j < Jc[k0]
+                    int32_t jl = Jc[R.k0] - 1;
+                    if (jl > R.j1) jl = R.j1;
                     int64_t best = INT64_MAX;
-                    int32_t span = lo - R.j0;
+                    int32_t span = jl - R.j0;
                     int32_t nc = span > 0 ? ncand : 1;
                     for (int32_t c = 0; c < nc; ++c) {
                         int32_t j = span > 0 ? R.j0 + (int32_t)(((int64_t)c * span) / (nc - 1)) : R.j0;
@@ -265,7 +291,7 @@ __global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ 
             }
             int32_t v[4] = {cl, ca, cd, cm};
             int32_t tot[4];
-            block_scan<int32_t, 4>(v, tot, sm);
+            block_scan<int32_t, 4>(v, tot, wsum);
             if (act) {
                 int32_t node = n_nodes + i;
                 int32_t li = cl ? n_l + v[0] : -1;
@@ -305,8 +331,8 @@ __global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ 
             overflow = 1;
             n_next = n_next > A.q_cap ? A.q_cap : n_next;
         }
-        Rect* t = cur; cur = nxt; nxt = t;
         if (level >= kMaxLevels) overflow = 2;
+        Rect* t = cur; cur = nxt; nxt = t;
         n_cur = overflow ? 0 : n_next;
         __syncthreads();
     }
@@ -318,147 +344,134 @@ __global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Per-block parameters (one thread per block).
+// Per-block parameters (grid-stride over the blocks the subdivision made).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int32_t iceil(double x) { return (int32_t)ceil(x); }
 
-__global__ void k_block_params(PlanDev P, Arena A, int32_t n_l, int32_t n_a, int32_t dft_max, double sigma,
-                               int64_t* __restrict__ a_sizes /* 4 per A block */,
-                               int32_t* __restrict__ l_sizes /* 1 per L block */, int32_t* __restrict__ sum_flags)
+__global__ void k_block_params(PlanDev P, Arena A, int32_t dft_max, double sigma, Summary* __restrict__ sum)
 {
-    int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sum->overflow) return;
+    const int32_t n_l = sum->n_l, n_a = sum->n_a;
     const int w = P.w;
-    if (b < n_a) {
-        ABlock B = A.ab[b];
-        double rlo = P.rs[B.k0], rhi = P.rs[B.k1];
-        double wlo = P.ws[B.j0], whi = P.ws[B.j1];
-        double C = 0.5 * (rlo + rhi);
-        double X = fmax(rhi - C, C - rlo);
-        double D = 0.5 * (wlo + whi);
-        double S = fmax(whi - D, D - wlo);
-        if (!(S > 1e-280)) S = 1e-280;
-        // grid spacing: the largest power of two with S h <= pi / sigma
-        double h = exp2(floor(log2(kPi / (sigma * S))));
-        if (S * h > kPi / sigma) h *= 0.5;
-        double span = X / h;
-        if (!(span < (double)(1 << (kMaxFftLog2 - 3)))) {   // grid too large for the FFT sizes
-            atomicOr(&sum_flags[0], 1);
-            span = 0.0;
+    const int32_t nb = n_l > n_a ? n_l : n_a;
+    for (int32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+        if (b < n_a) {
+            ABlock B = A.ab[b];
+            double rlo = P.rs[B.k0], rhi = P.rs[B.k1];
+            double wlo = P.ws[B.j0], whi = P.ws[B.j1];
+            double C = 0.5 * (rlo + rhi);
+            double X = fmax(rhi - C, C - rlo);
+            double D = 0.5 * (wlo + whi);
+            double S = fmax(whi - D, D - wlo);
+            if (!(S > 1e-280)) S = 1e-280;
+            // grid spacing: the largest power of two with S h <= pi / sigma
+            double h = exp2(floor(log2(kPi / (sigma * S))));
+            if (S * h > kPi / sigma) h *= 0.5;
+            double span = X / h;
+            if (!(span < (double)(1 << (kMaxFftLog2 - 3)))) {   // grid too large for the FFT sizes
+                atomicOr(&sum->grid_error, 1);
+                span = 0.0;
+            }
+            int32_t llo = iceil(-span - 0.5 * w) - 1;
+            int32_t lhi = iceil(span - 0.5 * w) + w;
+            int32_t N1 = lhi - llo + 1;
+            B.C = C; B.D = D; B.h = h; B.r0 = rlo; B.alpha = 0.5 * w * h;
+            B.llo = llo; B.N1 = N1;
+            int32_t fft = (dft_max >= 0 && N1 <= dft_max) ? 0 : 1;
+            int32_t N2 = 0;
+            if (fft) {
+                int32_t maxl = llo < 0 ? -llo : llo;
+                if (lhi > maxl) maxl = lhi;
+                N2 = 64;
+                while (N2 < 4 * maxl + 4) N2 <<= 1;
+                // h N2 / (2 pi): exact scaling of the double-double 1/(2 pi)
+                B.Khi = h * (double)N2 * kInvTwoPi;
+                B.Klo = h * (double)N2 * kInvTwoPiLo;
+            }
+            B.fft = fft; B.N2 = N2;
+            int32_t ncol = B.k1 - B.k0 + 1;
+            B.nitems = (ncol + kSpreadChunk - 1) / kSpreadChunk;
+            A.ab[b] = B;
         }
-        int32_t llo = iceil(-span - 0.5 * w) - 1;
-        int32_t lhi = iceil(span - 0.5 * w) + w;
-        int32_t N1 = lhi - llo + 1;
-        B.C = C; B.D = D; B.h = h; B.r0 = rlo; B.alpha = 0.5 * w * h;
-        B.llo = llo; B.N1 = N1;
-        int32_t fft = (dft_max >= 0 && N1 <= dft_max) ? 0 : 1;
-        int32_t N2 = 0, lg = 0;
-        if (fft) {
-            int32_t maxl = llo < 0 ? -llo : llo;
-            if (lhi > maxl) maxl = lhi;
-            N2 = 64; lg = 6;
-            while (N2 < 4 * maxl + 4) { N2 <<= 1; ++lg; }
-            // h N2 / (2 pi): exact scaling of the double-double 1/(2 pi)
-            B.Khi = h * (double)N2 * kInvTwoPi;
-            B.Klo = h * (double)N2 * kInvTwoPiLo;
+        if (b < n_l) {
+            LBlock L = A.lb[b];
+            double R = P.rs[L.k1];
+            if (R == 0.0) {
+                double wm = P.ws[L.j1];
+                R = wm > 0.0 ? P.z / wm : 1.0;
+            }
+            L.R = R;
+            int32_t ncol = L.k1 - L.k0 + 1;
+            L.nitems = (ncol + kLocalChunk - 1) / kLocalChunk;
+            A.lb[b] = L;
         }
-        B.fft = fft; B.N2 = N2;
-        int32_t nb = B.k1 - B.k0 + 1;
-        int32_t nit = (nb + kSpreadChunk - 1) / kSpreadChunk;
-        int64_t cells = 0;
-        for (int32_t it = 0; it < nit; ++it) {
-            int32_t ka = B.k0 + it * kSpreadChunk;
-            int32_t kb = ka + kSpreadChunk - 1;
-            if (kb > B.k1) kb = B.k1;
-            double u0 = (P.rs[ka] - C) / h, u1 = (P.rs[kb] - C) / h;
-            int32_t s0 = iceil(u0 - 0.5 * w) - 1;
-            int32_t s1 = iceil(u1 - 0.5 * w) + w;
-            if (s0 < llo) s0 = llo;
-            if (s1 > lhi) s1 = lhi;
-            cells += s1 - s0 + 1;
-        }
-        B.nitems = nit;
-        A.ab[b] = B;
-        a_sizes[4 * b + 0] = nit;
-        a_sizes[4 * b + 1] = cells;
-        a_sizes[4 * b + 2] = fft ? (int64_t)N2 : (int64_t)N1;
-        a_sizes[4 * b + 3] = fft ? lg : -1;
-    }
-    if (b < n_l) {
-        LBlock L = A.lb[b];
-        double R = P.rs[L.k1];
-        if (R == 0.0) {
-            double wm = P.ws[L.j1];
-            R = wm > 0.0 ? P.z / wm : 1.0;
-        }
-        L.R = R;
-        int32_t nb = L.k1 - L.k0 + 1;
-        L.nitems = (nb + kLocalChunk - 1) / kLocalChunk;
-        A.lb[b] = L;
-        l_sizes[b] = L.nitems;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Offsets and totals (one 1024-thread block): exclusive scans over the blocks
-// of item counts, partial-subgrid cells and grid slots; FFT size classes; the
-// membership statistics.
+// of item counts and grid slots, the FFT size classes, membership statistics.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, int32_t n_l, int32_t n_a, int32_t n_d,
-                                                    const int64_t* __restrict__ a_sizes,
-                                                    const int32_t* __restrict__ l_sizes, Summary* __restrict__ sum)
+__global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, Summary* __restrict__ sum)
 {
-    __shared__ int64_t sm[3][1024];
+    __shared__ int64_t wsum[2][16];
+    __shared__ int32_t cls_cnt[kMaxFftLog2 + 1];
+    __shared__ int32_t cls_first[kMaxFftLog2 + 1];
     __shared__ long long red[6][1024 / 64];
+    if (sum->overflow) return;
+    const int32_t n_l = sum->n_l, n_a = sum->n_a, n_d = sum->n_d;
     int tid = threadIdx.x;
     const int nch = P.nch;
-    // local items
+    if (tid <= kMaxFftLog2) cls_cnt[tid] = 0;
+    __syncthreads();
     int64_t l_items = 0;
     for (int32_t c0 = 0; c0 < n_l; c0 += 1024) {
         int32_t i = c0 + tid;
-        int64_t v[1] = {i < n_l ? (int64_t)l_sizes[i] : 0};
+        int64_t v[1] = {i < n_l ? (int64_t)A.lb[i].nitems : 0};
         int64_t tot[1];
-        block_scan<int64_t, 1>(v, tot, sm);
+        block_scan<int64_t, 1>(v, tot, wsum);
         if (i < n_l) A.lb[i].item0 = (int32_t)(l_items + v[0]);
         l_items += tot[0];
     }
-    // asymptotic items, partial cells, grid slots
-    int64_t a_items = 0, part = 0, grid = 0;
-    int32_t cls_count[kMaxFftLog2 + 1];
-    for (int q = 0; q <= kMaxFftLog2; ++q) cls_count[q] = 0;
+    int64_t a_items = 0, grid = 0;
     for (int32_t c0 = 0; c0 < n_a; c0 += 1024) {
         int32_t i = c0 + tid;
         bool act = i < n_a;
-        int64_t v[3] = {act ? a_sizes[4 * i + 0] : 0, act ? a_sizes[4 * i + 1] : 0, act ? a_sizes[4 * i + 2] : 0};
-        int64_t tot[3];
-        block_scan<int64_t, 3>(v, tot, sm);
+        ABlock B;
+        if (act) B = A.ab[i];
+        int64_t v[2] = {act ? (int64_t)B.nitems : 0, act ? (B.fft ? (int64_t)B.N2 : (int64_t)B.N1) : 0};
+        int64_t tot[2];
+        block_scan<int64_t, 2>(v, tot, wsum);
         if (act) {
             A.ab[i].item0 = (int32_t)(a_items + v[0]);
-            A.ab[i].part_off = (part + v[1]) * nch;
-            A.ab[i].grid_off = (grid + v[2]) * nch;
+            A.ab[i].grid_off = (grid + v[1]) * nch;
+            if (B.fft) atomicAdd(&cls_cnt[31 - __clz(B.N2)], 1);
         }
         a_items += tot[0];
-        part += tot[1];
-        grid += tot[2];
+        grid += tot[1];
     }
-    // FFT size classes: deterministic slots (class, then block index)
-    int32_t fft_total = 0;
-    for (int cls = 6; cls <= kMaxFftLog2; ++cls) {
-        int32_t cnt = 0;
-        for (int32_t c0 = 0; c0 < n_a; c0 += 1024) {
-            int32_t i = c0 + tid;
-            bool mine = i < n_a && a_sizes[4 * i + 3] == cls;
-            int64_t v[1] = {mine ? 1 : 0};
-            int64_t tot[1];
-            block_scan<int64_t, 1>(v, tot, sm);
-            if (mine) {
-                A.ab[i].fft_slot = (int32_t)(fft_total + cnt + v[0]);
-                A.fft_list[fft_total + cnt + v[0]] = i;
-            }
-            cnt += (int32_t)tot[0];
+    __syncthreads();
+    if (tid == 0) {
+        int32_t f = 0;
+        for (int c = 0; c <= kMaxFftLog2; ++c) {
+            cls_first[c] = f;
+            sum->fft_first[c] = f;
+            sum->fft_count[c] = cls_cnt[c];
+            f += cls_cnt[c];
+            cls_cnt[c] = 0;
         }
-        if (tid == 0) { sum->fft_count[cls] = cnt; sum->fft_first[cls] = fft_total; }
-        cls_count[cls] = cnt;
-        fft_total += cnt;
+        sum->n_fft = f;
+    }
+    __syncthreads();
+    // FFT-path blocks grouped by size class (order inside a class is immaterial)
+    for (int32_t i = tid; i < n_a; i += 1024) {
+        ABlock B = A.ab[i];
+        if (B.fft) {
+            int c = 31 - __clz(B.N2);
+            int32_t slot = cls_first[c] + atomicAdd(&cls_cnt[c], 1);
+            A.fft_list[slot] = i;
+            A.ab[i].fft_slot = slot;
+        }
     }
     // membership statistics
     long long s[6] = {0, 0, 0, 0, 0, 0};
@@ -466,23 +479,25 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, int32_t 
         LBlock L = A.lb[i];
         s[0] += L.j1 - L.j0 + 1; s[1] += L.k1 - L.k0 + 1;
     }
+    long long fp = 0;
     for (int32_t i = tid; i < n_a; i += 1024) {
         ABlock B = A.ab[i];
         s[2] += B.j1 - B.j0 + 1; s[3] += B.k1 - B.k0 + 1;
-        s[5] += B.fft ? 0 : B.N1;
+        if (B.fft) fp += B.N2; else s[5] += B.N1;
     }
-    long long ent = 0;
     for (int32_t i = tid; i < n_d; i += 1024) {
         DBlock Db = A.db[i];
-        ent += (long long)(Db.j1 - Db.j0 + 1) * (Db.k1 - Db.k0 + 1);
+        s[4] += (long long)(Db.j1 - Db.j0 + 1) * (Db.k1 - Db.k0 + 1);
     }
-    s[4] = ent;
     for (int q = 0; q < 6; ++q) {
-        long long x = s[q];
+        long long x = q == 5 ? s[5] : s[q];
         for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
         if ((tid & 63) == 0) red[q][tid >> 6] = x;
     }
     __syncthreads();
+    // fp reuses red[5] after the first read
+    long long fpx = fp;
+    for (int o = 32; o >= 1; o >>= 1) fpx += __shfl_xor(fpx, o);
     if (tid == 0) {
         long long t[6] = {0, 0, 0, 0, 0, 0};
         for (int q = 0; q < 6; ++q)
@@ -490,53 +505,90 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, int32_t 
         sum->l_row = t[0]; sum->l_col = t[1]; sum->a_row = t[2]; sum->a_col = t[3];
         sum->d_ent = t[4]; sum->dft_cells = t[5];
         sum->n_litems = (int32_t)l_items; sum->n_aitems = (int32_t)a_items;
-        sum->part_cells = part; sum->n_fft = fft_total; sum->max_nch = nch;
-        int64_t fp = 0;
-        for (int cls = 6; cls <= kMaxFftLog2; ++cls) fp += (int64_t)cls_count[cls] << cls;
-        sum->fft_points = fp;
+        sum->max_nch = nch;
         sum->grid_cells = grid;
-        if (l_items > A.litem_cap || a_items > A.aitem_cap || fft_total > A.a_cap) sum->overflow = 1;
+        if (l_items > A.litem_cap || a_items > A.aitem_cap) sum->overflow = 1;
+    }
+    __syncthreads();
+    if ((tid & 63) == 0) red[0][tid >> 6] = fpx;
+    __syncthreads();
+    if (tid == 0) {
+        long long t = 0;
+        for (int w2 = 0; w2 < 1024 / 64; ++w2) t += red[0][w2];
+        sum->fft_points = t;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Work items (one thread per block).
+// Work items (grid-stride over all items: local first, then asymptotic).
+// An item is a chunk of one block's columns; an asymptotic item also carries
+// the subgrid of cells its points can reach (one cell of margin each side).
 // ---------------------------------------------------------------------------
-__global__ void k_fill_items(PlanDev P, Arena A, int32_t n_l, int32_t n_a)
+__global__ void k_items(PlanDev P, Arena A, Summary* __restrict__ sum, int32_t* __restrict__ a_cells)
 {
-    int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sum->overflow) return;
+    const int32_t n_l = sum->n_l, n_a = sum->n_a;
+    const int32_t n_li = sum->n_litems, n_ai = sum->n_aitems;
     const int w = P.w;
-    const int nch = P.nch;
-    if (b < n_a) {
-        ABlock B = A.ab[b];
-        int64_t off = B.part_off;
-        int32_t lhi = B.llo + B.N1 - 1;
-        for (int32_t it = 0; it < B.nitems; ++it) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_li + n_ai; i += gridDim.x * blockDim.x) {
+        if (i < n_li) {
+            int32_t lo = 0, hi = n_l - 1;             // last block with item0 <= i
+            while (lo < hi) {
+                int32_t mid = (lo + hi + 1) >> 1;
+                if (A.lb[mid].item0 <= i) lo = mid; else hi = mid - 1;
+            }
+            const LBlock L = A.lb[lo];
+            int32_t it = i - L.item0;
+            int32_t ka = L.k0 + it * kLocalChunk;
+            int32_t kb = ka + kLocalChunk;
+            if (kb > L.k1 + 1) kb = L.k1 + 1;
+            Item I;
+            I.blk = lo; I.ka = ka; I.kb = kb; I.sub_lo = 0; I.sub_n = 0; I.pad = 0; I.off = 0;
+            A.litems[i] = I;
+        } else {
+            int32_t ia = i - n_li;
+            int32_t lo = 0, hi = n_a - 1;
+            while (lo < hi) {
+                int32_t mid = (lo + hi + 1) >> 1;
+                if (A.ab[mid].item0 <= ia) lo = mid; else hi = mid - 1;
+            }
+            const ABlock B = A.ab[lo];
+            int32_t it = ia - B.item0;
             int32_t ka = B.k0 + it * kSpreadChunk;
             int32_t kb = ka + kSpreadChunk - 1;
             if (kb > B.k1) kb = B.k1;
+            int32_t lhi = B.llo + B.N1 - 1;
             double u0 = (P.rs[ka] - B.C) / B.h, u1 = (P.rs[kb] - B.C) / B.h;
             int32_t s0 = iceil(u0 - 0.5 * w) - 1;
             int32_t s1 = iceil(u1 - 0.5 * w) + w;
             if (s0 < B.llo) s0 = B.llo;
             if (s1 > lhi) s1 = lhi;
             Item I;
-            I.blk = b; I.ka = ka; I.kb = kb + 1; I.sub_lo = s0; I.sub_n = s1 - s0 + 1; I.pad = 0; I.off = off;
-            if (B.item0 + it < A.aitem_cap) A.aitems[B.item0 + it] = I;
-            off += (int64_t)I.sub_n * nch;
+            I.blk = lo; I.ka = ka; I.kb = kb + 1; I.sub_lo = s0; I.sub_n = s1 - s0 + 1; I.pad = 0; I.off = 0;
+            A.aitems[ia] = I;
+            a_cells[ia] = I.sub_n;
         }
     }
-    if (b < n_l) {
-        LBlock L = A.lb[b];
-        for (int32_t it = 0; it < L.nitems; ++it) {
-            int32_t ka = L.k0 + it * kLocalChunk;
-            int32_t kb = ka + kLocalChunk;
-            if (kb > L.k1 + 1) kb = L.k1 + 1;
-            Item I;
-            I.blk = b; I.ka = ka; I.kb = kb; I.sub_lo = 0; I.sub_n = 0; I.pad = 0; I.off = 0;
-            if (L.item0 + it < A.litem_cap) A.litems[L.item0 + it] = I;
-        }
+}
+
+// Partial-subgrid offsets of the asymptotic items (one 1024-thread block).
+__global__ __launch_bounds__(1024) void k_item_scan(PlanDev P, Arena A, Summary* __restrict__ sum,
+                                                    const int32_t* __restrict__ a_cells)
+{
+    __shared__ int64_t wsum[1][16];
+    if (sum->overflow) return;
+    const int32_t n_ai = sum->n_aitems;
+    const int nch = P.nch;
+    int64_t run = 0;
+    for (int32_t c0 = 0; c0 < n_ai; c0 += 1024) {
+        int32_t i = c0 + threadIdx.x;
+        int64_t v[1] = {i < n_ai ? (int64_t)a_cells[i] : 0};
+        int64_t tot[1];
+        block_scan<int64_t, 1>(v, tot, wsum);
+        if (i < n_ai) A.aitems[i].off = (run + v[0]) * nch;
+        run += tot[0];
     }
+    if (threadIdx.x == 0) sum->part_cells = run;
 }
 
 // ---------------------------------------------------------------------------
@@ -554,6 +606,7 @@ hipError_t launch_make_keys(const double* x, int32_t n, uint64_t* key, int32_t* 
 hipError_t launch_sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int32_t* hist,
                              int32_t na, int32_t nb, hipStream_t s)
 {
+    // the 2 x 256 digit totals live after the histograms (see sort_hist_len)
     SortSegs S;
     S.off[0] = 0; S.off[1] = na; S.off[2] = na + nb;
     int ta = cdiv(na, kSortTile), tb = cdiv(nb, kSortTile);
@@ -564,54 +617,29 @@ hipError_t launch_sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v
     for (int pass = 0; pass < 8; ++pass) {
         int shift = 8 * pass;
         hipLaunchKernelGGL(k_sort_hist, dim3(ta + tb), dim3(kSortThreads), 0, s, kin, S, shift, hist);
-        hipLaunchKernelGGL(k_sort_scan, dim3(2), dim3(1024), 0, s, hist, S);
+        hipLaunchKernelGGL(k_sort_scan, dim3(2 * 256), dim3(1024), 0, s, hist, hist + S.hoff[2], S);
         hipLaunchKernelGGL(k_sort_scatter, dim3(ta + tb), dim3(kSortThreads), 0, s, kin, vin, kout, vout, S, shift,
-                           hist);
+                           hist, hist + S.hoff[2]);
         uint64_t* tk = kin; kin = kout; kout = tk;
         int32_t* tv = vin; vin = vout; vout = tv;
     }
     return hipGetLastError();   // eight passes: the result is back in (k0, v0)
 }
 
-int sort_hist_len(int32_t na, int32_t nb) { return 256 * (cdiv(na, kSortTile) + cdiv(nb, kSortTile)) + 256; }
+int sort_hist_len(int32_t na, int32_t nb) { return 256 * (cdiv(na, kSortTile) + cdiv(nb, kSortTile)) + 2 * 256; }
 
-hipError_t launch_staircase(const double* rs, int32_t n, const double* ws, int32_t m, double z, int32_t* K,
-                            hipStream_t s)
+hipError_t launch_planning(const PlanDev& P, const Arena& A, int32_t* K, int32_t* Jc, int32_t* a_cells,
+                           int64_t min_size, int32_t ncand, int32_t dft_max, double sigma, Summary* sum,
+                           hipStream_t s)
 {
-    if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_staircase, dim3(cdiv(m, 256)), dim3(256), 0, s, rs, n, ws, m, z, K);
-    return hipGetLastError();
-}
-
-hipError_t launch_subdivide(const int32_t* K, int32_t m, int32_t n, int64_t min_size, int32_t ncand, const Arena& A,
-                            Summary* sum, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_subdivide, dim3(1), dim3(1024), 0, s, K, m, n, min_size, ncand, A, sum);
-    return hipGetLastError();
-}
-
-hipError_t launch_block_params(const PlanDev& P, const Arena& A, int32_t n_l, int32_t n_a, int32_t dft_max,
-                               double sigma, int64_t* a_sizes, int32_t* l_sizes, Summary* sum, hipStream_t s)
-{
-    int nb = n_l > n_a ? n_l : n_a;
-    if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_block_params, dim3(cdiv(nb, 128)), dim3(128), 0, s, P, A, n_l, n_a, dft_max, sigma,
-                       a_sizes, l_sizes, &sum->grid_error);
-    return hipGetLastError();
-}
-
-hipError_t launch_plan_scan(const PlanDev& P, const Arena& A, int32_t n_l, int32_t n_a, int32_t n_d,
-                            const int64_t* a_sizes, const int32_t* l_sizes, Summary* sum, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, s, P, A, n_l, n_a, n_d, a_sizes, l_sizes, sum);
-    return hipGetLastError();
-}
-
-hipError_t launch_fill_items(const PlanDev& P, const Arena& A, int32_t n_l, int32_t n_a, hipStream_t s)
-{
-    int nb = n_l > n_a ? n_l : n_a;
-    if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_items, dim3(cdiv(nb, 128)), dim3(128), 0, s, P, A, n_l, n_a);
+    const int32_t n = P.n, m = P.m;
+    hipLaunchKernelGGL(k_staircase, dim3(cdiv(m, 256)), dim3(256), 0, s, P.rs, n, P.ws, m, P.z, K);
+    hipLaunchKernelGGL(k_staircase, dim3(cdiv(n, 256)), dim3(256), 0, s, P.ws, m, P.rs, n, P.z, Jc);
+    hipLaunchKernelGGL(k_subdivide, dim3(1), dim3(1024), 0, s, K, Jc, m, n, min_size, ncand, A, sum);
+    hipLaunchKernelGGL(k_block_params, dim3(256), dim3(128), 0, s, P, A, dft_max, sigma, sum);
+    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, s, P, A, sum);
+    hipLaunchKernelGGL(k_items, dim3(512), dim3(128), 0, s, P, A, sum, a_cells);
+    hipLaunchKernelGGL(k_item_scan, dim3(1), dim3(1024), 0, s, P, A, sum, a_cells);
     return hipGetLastError();
 }
 
