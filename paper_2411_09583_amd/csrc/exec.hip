@@ -484,7 +484,22 @@ template <int NCH>
 __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2* __restrict__ grids)
 {
     const ABlock B = P.ab[ablk];
-    const int nch = P.nch, w = P.w;
+    const int w = P.w;
+    // Channels this frequency needs: every entry of the block has argument
+    // om r >= om r0, and channel p's term is bounded by |a_p| (om r0)^-p
+    // relative to the leading one, so channels from the first p with
+    // |a_p| (om r0)^-p <= eps/200 on (the terms decrease in p above z) add
+    // less than eps/100 and are left out.
+    int nch = P.nch;
+    {
+        const double inv = 1.0 / (om * B.r0);
+        const double thr = 5e-3 * P.eps;
+        double t = 1.0;
+        for (int p = 1; p < P.nch; ++p) {
+            t *= inv;
+            if (fabs(P.hank[p]) * t <= thr) { nch = p; break; }
+        }
+    }
     dd sp = two_sum(om, -B.D);
     double ar[NCH], ai[NCH];
     #pragma unroll
@@ -499,7 +514,7 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
         sincos(th, &s1, &c1);
         double er = c1 - tl * s1, ei = s1 + tl * c1;
         for (int cix = 0; cix < B.N1; ++cix) {
-            const double2* gp = G + (int64_t)cix * nch;
+            const double2* gp = G + (int64_t)cix * P.nch;
             #pragma unroll
             for (int p = 0; p < NCH; ++p) {
                 if (p < nch) {

@@ -49,6 +49,21 @@ __device__ __forceinline__ void cis_dd(double hi, double lo, double& c, double& 
     s = __builtin_fma(t.lo, cs, sn);
 }
 
+// 1/k for k < 128 (exact to the last bit: every entry is the double nearest 1/k).
+__device__ __constant__ static const double kInvInt[128] = {
+    0.0, 1.0 / 1, 1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5, 1.0 / 6, 1.0 / 7, 1.0 / 8, 1.0 / 9, 1.0 / 10, 1.0 / 11,
+    1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17, 1.0 / 18, 1.0 / 19, 1.0 / 20, 1.0 / 21, 1.0 / 22,
+    1.0 / 23, 1.0 / 24, 1.0 / 25, 1.0 / 26, 1.0 / 27, 1.0 / 28, 1.0 / 29, 1.0 / 30, 1.0 / 31, 1.0 / 32, 1.0 / 33,
+    1.0 / 34, 1.0 / 35, 1.0 / 36, 1.0 / 37, 1.0 / 38, 1.0 / 39, 1.0 / 40, 1.0 / 41, 1.0 / 42, 1.0 / 43, 1.0 / 44,
+    1.0 / 45, 1.0 / 46, 1.0 / 47, 1.0 / 48, 1.0 / 49, 1.0 / 50, 1.0 / 51, 1.0 / 52, 1.0 / 53, 1.0 / 54, 1.0 / 55,
+    1.0 / 56, 1.0 / 57, 1.0 / 58, 1.0 / 59, 1.0 / 60, 1.0 / 61, 1.0 / 62, 1.0 / 63, 1.0 / 64, 1.0 / 65, 1.0 / 66,
+    1.0 / 67, 1.0 / 68, 1.0 / 69, 1.0 / 70, 1.0 / 71, 1.0 / 72, 1.0 / 73, 1.0 / 74, 1.0 / 75, 1.0 / 76, 1.0 / 77,
+    1.0 / 78, 1.0 / 79, 1.0 / 80, 1.0 / 81, 1.0 / 82, 1.0 / 83, 1.0 / 84, 1.0 / 85, 1.0 / 86, 1.0 / 87, 1.0 / 88,
+    1.0 / 89, 1.0 / 90, 1.0 / 91, 1.0 / 92, 1.0 / 93, 1.0 / 94, 1.0 / 95, 1.0 / 96, 1.0 / 97, 1.0 / 98, 1.0 / 99,
+    1.0 / 100, 1.0 / 101, 1.0 / 102, 1.0 / 103, 1.0 / 104, 1.0 / 105, 1.0 / 106, 1.0 / 107, 1.0 / 108, 1.0 / 109,
+    1.0 / 110, 1.0 / 111, 1.0 / 112, 1.0 / 113, 1.0 / 114, 1.0 / 115, 1.0 / 116, 1.0 / 117, 1.0 / 118, 1.0 / 119,
+    1.0 / 120, 1.0 / 121, 1.0 / 122, 1.0 / 123, 1.0 / 124, 1.0 / 125, 1.0 / 126, 1.0 / 127};
+
 // Exponential-of-semicircle kernel exp(beta (sqrt(1 - x^2) - 1)) on |x| < 1.
 __device__ __forceinline__ double es_kernel(double x, double beta)
 {
@@ -77,11 +92,12 @@ __device__ __forceinline__ double eshat(const PlanDev& P, double kappa)
     return __builtin_fma(t, b1, P.eshat[0] - b2);
 }
 
-// Starting index of Miller's backward recurrence at argument y: beyond it
-// J_k(y) is below ~1e-20 of the sequence's largest value.
+// Starting index of Miller's backward recurrence at argument y: started there,
+// the recurrence reproduces J_0(y) .. J_40(y) to the FP64 rounding floor
+// (checked against 30-digit values for 0.01 <= y <= 160).
 __device__ __forceinline__ int miller_start(double y)
 {
-    return (int)(y + 14.0 * cbrt(y) + 20.0);
+    return (int)(y + 8.0 * cbrt(y) + 12.0);
 }
 
 // J_nu(x) for 0 <= x (nu >= 0) by Miller's backward recurrence
@@ -150,11 +166,12 @@ __device__ inline double besselj_full(const PlanDev& P, double xh, double xl)
 {
     if (xh >= 25.0) {
         const double mu = 4.0 * (double)P.nu * (double)P.nu;
+        const double inv8x = 0.125 / xh;
         double t = 1.0, p = 1.0, q = 0.0, prev = 1e300;
         bool ok = false;
         for (int k = 1; k < 120; ++k) {
             double f = 2.0 * k - 1.0;
-            t *= (mu - f * f) / (8.0 * k * xh);
+            t *= (mu - f * f) * inv8x * kInvInt[k];
             double at = fabs(t);
             double sg = ((k >> 1) & 1) ? -1.0 : 1.0;
             if (k & 1) q = __builtin_fma(sg, t, q); else p = __builtin_fma(sg, t, p);
@@ -171,7 +188,7 @@ __device__ inline double besselj_full(const PlanDev& P, double xh, double xl)
     }
     if (xh < 1e-30) return P.nu == 0 ? 1.0 : 0.0;
     double top = (double)(P.nu + 1) > xh ? (double)(P.nu + 1) : xh;
-    int N = (int)(top + 20.0 + 15.0 * cbrt(xh > 1.0 ? xh : 1.0));
+    int N = (int)(top + 12.0 + 8.0 * cbrt(xh > 1.0 ? xh : 1.0));
     double rec = 2.0 / xh;
     double yk1 = 0.0, yk = 1e-100, S = 0.0;
     double jm = 0.0, j0 = 0.0, jp = 0.0;
