@@ -9,6 +9,8 @@
 // Row side (one thread per frequency): walk the block tree from the root and
 //   add, level by level, the row's local, asymptotic and (at the end) direct
 //   contributions; write g once, in the caller's order.
+#include <type_traits>
+
 #include "nuht_device.h"
 #include "nuht_launch.h"
 
@@ -120,7 +122,6 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
     const int tid = threadIdx.x;
     const int np = I.kb - I.ka;
     const int w = P.w;
-    const int nch = P.nch;
     const double inv_h = 1.0 / B.h;      // exact: h is a power of two
     for (int i = tid; i < np; i += 256) {
         int k = I.ka + i;
@@ -170,12 +171,10 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
                     double q = s_q[i];
                     #pragma unroll
                     for (int p = 0; p < NCH; ++p) {
-                        if (p < nch) {
-                            ar[p] += vr;
-                            ai[p] += vi;
-                            vr *= q;
-                            vi *= q;
-                        }
+                        ar[p] += vr;
+                        ai[p] += vi;
+                        vr *= q;
+                        vi *= q;
                     }
                 }
             }
@@ -188,17 +187,19 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
             }
         }
         if (cell < sub_n && sl == 0) {
-            double2* dst = part + I.off + (int64_t)cell * nch;
+            double2* dst = part + I.off + (int64_t)cell * NCH;
             #pragma unroll
-            for (int p = 0; p < NCH; ++p)
-                if (p < nch) dst[p] = make_double2(ar[p], ai[p]);
+            for (int p = 0; p < NCH; ++p) dst[p] = make_double2(ar[p], ai[p]);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Grid assembly: each grid slot sums the item partials that cover it, in item
-// order.  Direct-sum-path grids are stored cell-major [cell][channel].  FFT
+// order, and multiplies channel p by its factor beta_p (the Hankel coefficient
+// with the sign and the factor i the combination step gives it), so that the
+// row pass only sums the channels weighted by powers of 1/(om r0).
+// Direct-sum-path grids are stored cell-major [cell][channel].  FFT
 // path: mode l of the spread grid is divided by the inner kernel's transform
 // psi^(l) = alpha2 ES^(|l| alpha2), alpha2 = w pi / N2 (the deconvolution of the
 // type-2 step) and placed at FFT index l mod N2, channel-major [channel][N2];
@@ -240,12 +241,15 @@ __global__ void k_spread_reduce(PlanDev P, const double2* __restrict__ part, dou
             si += v.y;
         }
     }
+    // channel factor: real for even p, i times real for odd p
+    double f = P.chan[p];
+    double2 v = (p & 1) ? make_double2(-si * f, sr * f) : make_double2(sr * f, si * f);
     if (B.fft) {
         double a2 = P.w * kPi / B.N2;
         double s = 1.0 / (a2 * eshat(P, fabs((double)l) * a2));
-        grids[B.grid_off + (int64_t)p * B.N2 + local] = make_double2(sr * s, si * s);
+        grids[B.grid_off + (int64_t)p * B.N2 + local] = make_double2(v.x * s, v.y * s);
     } else {
-        grids[B.grid_off + local * nch + p] = make_double2(sr, si);
+        grids[B.grid_off + local * nch + p] = v;
     }
 }
 
@@ -436,7 +440,10 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
     const int odd = nu & 1;
     const int a = odd ? (nu - 1) >> 1 : nu >> 1;
     if (y < 1e-30) return nu == 0 ? t[0] : 0.0;
-    const int N = miller_start(y);
+    // the pairing below reads J_{nu-i} for i <= nu/2, so the recurrence must
+    // have produced every index up to nu
+    int N = miller_start(y);
+    if (N < nu + 1) N = nu + 1;
     const int Bsz = nu + 1;
     const double rec = 2.0 / y;
     double yk1 = 0.0, yk = 1e-100, S2 = 0.0, dot = 0.0;
@@ -475,7 +482,12 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
 // where y_p = sum_k x_k^(p) e^{i om r_k} is the type-3 sum of channel p.  With
 // s' = om - D and theta = s' h:  y_p = e^{i om C} h F_p(theta) / phi^(s'),
 // F_p(theta) = sum_l b_l^(p) e^{i l theta} evaluated directly over the cells
-// (direct-sum path) or from the FFT by ES interpolation (FFT path).
+// (direct-sum path) or from the FFT by ES interpolation (FFT path).  The grids
+// already hold beta_p b_l^(p), so with gamma = 1/(om r0) each cell (or tap)
+// needs the single value sum_p gamma^p beta_p b_l^(p): two multiply-adds per
+// channel with the powers gamma^p kept in registers (the grid value, when it
+// comes through the scalar unit, is then a multiplicand and needs no copy into
+// vector registers), and one complex product per cell.
 // Called with a wave-uniform block index whenever every active lane of the
 // wave is in the same block (the usual case, frequencies being sorted); the
 // block's fields and its direct-sum grid are then read through the scalar
@@ -485,25 +497,13 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
 {
     const ABlock B = P.ab[ablk];
     const int w = P.w;
-    // Channels this frequency needs: every entry of the block has argument
-    // om r >= om r0, and channel p's term is bounded by |a_p| (om r0)^-p
-    // relative to the leading one, so channels from the first p with
-    // |a_p| (om r0)^-p <= eps/200 on (the terms decrease in p above z) add
-    // less than eps/100 and are left out.
-    int nch = P.nch;
-    {
-        const double inv = 1.0 / (om * B.r0);
-        const double thr = 5e-3 * P.eps;
-        double t = 1.0;
-        for (int p = 1; p < P.nch; ++p) {
-            t *= inv;
-            if (fabs(P.hank[p]) * t <= thr) { nch = p; break; }
-        }
-    }
-    dd sp = two_sum(om, -B.D);
-    double ar[NCH], ai[NCH];
+    const double gam = 1.0 / (om * B.r0);
+    double gpow[NCH];
+    gpow[0] = 1.0;
     #pragma unroll
-    for (int p = 0; p < NCH; ++p) { ar[p] = 0.0; ai[p] = 0.0; }
+    for (int p = 1; p < NCH; ++p) gpow[p] = gpow[p - 1] * gam;
+    dd sp = two_sum(om, -B.D);
+    double ar = 0.0, ai = 0.0;
     if (!B.fft) {
         const double2* G = grids + B.grid_off;
         double th = sp.hi * B.h, tl = sp.lo * B.h;
@@ -514,15 +514,18 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
         sincos(th, &s1, &c1);
         double er = c1 - tl * s1, ei = s1 + tl * c1;
         for (int cix = 0; cix < B.N1; ++cix) {
-            const double2* gp = G + (int64_t)cix * P.nch;
+            const double2* gp = G + (int64_t)cix * NCH;
+            double2 gv[NCH];
             #pragma unroll
-            for (int p = 0; p < NCH; ++p) {
-                if (p < nch) {
-                    double2 gv = gp[p];
-                    ar[p] = __builtin_fma(gv.x, zr, __builtin_fma(-gv.y, zi, ar[p]));
-                    ai[p] = __builtin_fma(gv.x, zi, __builtin_fma(gv.y, zr, ai[p]));
-                }
+            for (int p = 0; p < NCH; ++p) gv[p] = gp[p];
+            double br = gv[0].x, bi = gv[0].y;
+            #pragma unroll
+            for (int p = 1; p < NCH; ++p) {
+                br = __builtin_fma(gv[p].x, gpow[p], br);
+                bi = __builtin_fma(gv[p].y, gpow[p], bi);
             }
+            ar = __builtin_fma(br, zr, __builtin_fma(-bi, zi, ar));
+            ai = __builtin_fma(br, zi, __builtin_fma(bi, zr, ai));
             double tr = __builtin_fma(zr, er, -zi * ei);
             zi = __builtin_fma(zr, ei, zi * er);
             zr = tr;
@@ -539,18 +542,21 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
             double x = (((double)q - v.hi) - vl) * two_over_w;
             double psi = es_kernel(x, P.beta);
             int qi = q & mask;
+            double2 gv[NCH];
             #pragma unroll
-            for (int p = 0; p < NCH; ++p) {
-                if (p < nch) {
-                    double2 a = Aq[(int64_t)p * B.N2 + qi];
-                    ar[p] = __builtin_fma(psi, a.x, ar[p]);
-                    ai[p] = __builtin_fma(psi, a.y, ai[p]);
-                }
+            for (int p = 0; p < NCH; ++p) gv[p] = Aq[(int64_t)p * B.N2 + qi];
+            double br = gv[0].x, bi = gv[0].y;
+            #pragma unroll
+            for (int p = 1; p < NCH; ++p) {
+                br = __builtin_fma(gv[p].x, gpow[p], br);
+                bi = __builtin_fma(gv[p].y, gpow[p], bi);
             }
+            ar = __builtin_fma(psi, br, ar);
+            ai = __builtin_fma(psi, bi, ai);
         }
         double sc = 2.0 * kPi / B.N2;
-        #pragma unroll
-        for (int p = 0; p < NCH; ++p) { ar[p] *= sc; ai[p] *= sc; }
+        ar *= sc;
+        ai *= sc;
     }
     double kap = fabs(sp.hi) * B.alpha;
     double scale = B.h / (B.alpha * eshat(P, kap));
@@ -558,20 +564,8 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
     dd s2 = two_sum(pc.hi, P.phi_hi);
     double cr, ci;
     cis_dd(s2.hi, s2.lo + pc.lo + P.phi_lo, cr, ci);
-    double gam = 1.0 / (om * B.r0);
     double amp = sqrt(gam) * scale;
-    double zr = 0.0, zi = 0.0;
-    #pragma unroll
-    for (int p = 0; p < NCH; ++p) {
-        if (p < nch) {
-            int l = p >> 1;
-            double coef = ((l & 1) ? -P.hank[p] : P.hank[p]) * amp;
-            if (p & 1) { zr = __builtin_fma(-coef, ai[p], zr); zi = __builtin_fma(coef, ar[p], zi); }
-            else { zr = __builtin_fma(coef, ar[p], zr); zi = __builtin_fma(coef, ai[p], zi); }
-            amp *= gam;
-        }
-    }
-    return kSqrt2OverPi * __builtin_fma(cr, zr, -ci * zi);
+    return kSqrt2OverPi * amp * __builtin_fma(cr, ar, -ci * ai);
 }
 
 // Direct blocks (entry by entry, J_nu to full precision).  One 64-lane wave
@@ -689,6 +683,29 @@ static void launch_rows(const PlanDev& P, const ExecBuffers& B, double* g, hipSt
     hipLaunchKernelGGL(k_rows<NCH>, dim3(cdiv64(P.m, bs)), dim3(bs), lds, s, P, B.gd, B.lmom, B.grids, g);
 }
 
+// Calls f with std::integral_constant<int, nch>; nch is one of the instantiated
+// channel counts (every even count up to 16, multiples of 4 up to 40).
+template <class F>
+static void dispatch_channels(int nch, F&& f)
+{
+    switch (nch) {
+    case 2: f(std::integral_constant<int, 2>()); break;
+    case 4: f(std::integral_constant<int, 4>()); break;
+    case 6: f(std::integral_constant<int, 6>()); break;
+    case 8: f(std::integral_constant<int, 8>()); break;
+    case 10: f(std::integral_constant<int, 10>()); break;
+    case 12: f(std::integral_constant<int, 12>()); break;
+    case 14: f(std::integral_constant<int, 14>()); break;
+    case 16: f(std::integral_constant<int, 16>()); break;
+    case 20: f(std::integral_constant<int, 20>()); break;
+    case 24: f(std::integral_constant<int, 24>()); break;
+    case 28: f(std::integral_constant<int, 28>()); break;
+    case 32: f(std::integral_constant<int, 32>()); break;
+    case 36: f(std::integral_constant<int, 36>()); break;
+    default: f(std::integral_constant<int, 40>()); break;
+    }
+}
+
 static inline void mark(hipEvent_t* marks, int i, hipStream_t s)
 {
     if (marks) (void)hipEventRecord(marks[i], s);
@@ -710,11 +727,7 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
                            B.lpart, B.lmom);
     }
     mark(marks, 2, s);
-    if (P.nch <= 8) launch_spread<8>(P, S, B, s);
-    else if (P.nch <= 16) launch_spread<16>(P, S, B, s);
-    else if (P.nch <= 24) launch_spread<24>(P, S, B, s);
-    else if (P.nch <= 32) launch_spread<32>(P, S, B, s);
-    else launch_spread<40>(P, S, B, s);
+    dispatch_channels(P.nch, [&](auto k) { launch_spread<decltype(k)::value>(P, S, B, s); });
     mark(marks, 3, s);
     if (B.grid_cells > 0)
         hipLaunchKernelGGL(k_spread_reduce, dim3(cdiv64(B.grid_cells * P.nch, 256)), dim3(256), 0, s, P, B.part,
@@ -743,11 +756,7 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
         hipLaunchKernelGGL(k_direct_blocks, dim3(P.n_d), dim3(64), 0, s, P, B.cs, B.gd);
     }
     mark(marks, 6, s);
-    if (P.nch <= 8) launch_rows<8>(P, B, g, s);
-    else if (P.nch <= 16) launch_rows<16>(P, B, g, s);
-    else if (P.nch <= 24) launch_rows<24>(P, B, g, s);
-    else if (P.nch <= 32) launch_rows<32>(P, B, g, s);
-    else launch_rows<40>(P, B, g, s);
+    dispatch_channels(P.nch, [&](auto k) { launch_rows<decltype(k)::value>(P, B, g, s); });
     mark(marks, 7, s);
     return hipGetLastError();
 }

@@ -343,6 +343,14 @@ static hipEvent_t* prof_marks(nuht_plan_t p)
         if (r_ != NUHT_OK) return r_;                \
     } while (0)
 
+// Channel counts the spreading and row kernels are instantiated for: every
+// even count up to 16, then multiples of 4 up to 40.  2M is padded up to the
+// next instance; padding channels carry a zero factor.
+static int padded_channels(int nch)
+{
+    return nch <= 16 ? nch : ((nch + 3) / 4) * 4;
+}
+
 static void fill_params(PlanDev& P, int nu, double eps, const nuht_opts& o)
 {
     int anu = std::abs(nu);
@@ -351,12 +359,14 @@ static void fill_params(PlanDev& P, int nu, double eps, const nuht_opts& o)
     P.eps = eps;
     int M = o.M_override > 0 ? std::min(o.M_override, 20) : num_asy_terms(anu, eps);
     P.M = M;
-    P.nch = 2 * M;
+    P.nch = padded_channels(2 * M);
     P.z = crossover(anu, eps, M);
     P.L = local_rank(anu, eps, P.z);
     P.w = es_width(eps, o.precision);
     P.beta = es_beta(P.w);
     for (int p = 0; p < 2 * M + 2; ++p) P.hank[p] = hankel_coef(anu, p);
+    for (int p = 0; p < kMaxChannels; ++p)
+        P.chan[p] = p < 2 * M ? (((p >> 1) & 1) ? -P.hank[p] : P.hank[p]) : 0.0;
     phase_offset(anu, P.phi_hi, P.phi_lo);
     P.kappa_max = P.w * M_PI / 4.0 * (1.0 + 1e-9);
     P.n_eshat = 30;

@@ -87,10 +87,11 @@ struct Summary {
 // Everything the execution kernels need for one transform (device copy).
 struct PlanDev {
     int32_t n, m, nu, M, L, w;       // sizes, |order|, terms, local rank, ES width
-    int32_t nch, sign;               // 2M; (-1)^nu for negative orders, else 1
+    int32_t nch, sign;               // channels (2M padded to a kernel instance); (-1)^nu for negative orders, else 1
     double z, beta, eps;
     double phi_hi, phi_lo;           // -(2nu+1) pi/4 reduced to [0, 2pi), double-double
     double hank[2 * 20 + 2];         // a_p(nu), p = 0 .. 2M+1 (Hankel coefficients)
+    double chan[kMaxChannels];       // channel factors (-1)^(p/2) a_p(nu) for p < 2M (odd p carry a factor i), 0 above
     double eshat[32];                // Chebyshev coefficients of ES^ on [0, kappa_max]
     int32_t n_eshat, pad0;
     double kappa_max;
