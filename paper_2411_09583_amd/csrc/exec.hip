@@ -210,32 +210,59 @@ __global__ void k_spread_reduce(PlanDev P, const double2* __restrict__ part, dou
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int nch = P.nch;
-    if (t >= total_slots * nch) return;
-    int64_t slot = t / nch;
-    int p = (int)(t % nch);
-    // block owning this slot: the last block with grid_off / nch <= slot
+    const int64_t total = total_slots * nch;
+    // Block owning a slot: the last block b with gslot[b] <= slot.  The wave
+    // searches once for the slot of its first lane (uniform, through the scalar
+    // unit); a wave spans at most 64 slots, so each lane then steps forward
+    // over the few blocks that start inside that span.
+    int64_t t0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    int64_t slot0 = __builtin_amdgcn_readfirstlane((int32_t)((t0 < total ? t0 : total - 1) / nch));
     int32_t lo = 0, hi = P.n_a - 1;
     while (lo < hi) {
         int32_t mid = (lo + hi + 1) >> 1;
-        if (P.ab[mid].grid_off / nch <= slot) lo = mid; else hi = mid - 1;
+        if (P.gslot[mid] <= slot0) lo = mid; else hi = mid - 1;
     }
+    if (t >= total) return;
+    int64_t slot = t / nch;
+    int p = (int)(t % nch);
+    while (P.gslot[lo + 1] <= slot) ++lo;
     const ABlock B = P.ab[lo];
-    int64_t local = slot - B.grid_off / nch;
+    int64_t local = slot - P.gslot[lo];
     int32_t l;
     if (B.fft) l = local < B.N2 / 2 ? (int32_t)local : (int32_t)(local - B.N2);
     else l = B.llo + (int32_t)local;
     double sr = 0.0, si = 0.0;
     if (l >= B.llo && l < B.llo + B.N1) {
-        // items covering cell l: sub ranges increase with the item index
-        int32_t a = B.item0, b = B.item0 + B.nitems;   // first item whose end exceeds l
-        while (a < b) {
-            int32_t mid = (a + b) >> 1;
+        // Items covering cell l: both ends of the items' cell ranges increase
+        // with the item index, so they form one run [a, b): a is the first item
+        // ending after l, b the first starting after l.  With the run known the
+        // partials are loaded several at a time and still added in item order.
+        const int32_t i0 = B.item0, i1 = B.item0 + B.nitems;
+        int32_t a = i0, hi = i1;
+        while (a < hi) {
+            int32_t mid = (a + hi) >> 1;
             const Item& I = P.aitems[mid];
-            if (I.sub_lo + I.sub_n <= l) a = mid + 1; else b = mid;
+            if (I.sub_lo + I.sub_n <= l) a = mid + 1; else hi = mid;
         }
-        for (int32_t it = a; it < B.item0 + B.nitems; ++it) {
-            const Item I = P.aitems[it];
-            if (I.sub_lo > l) break;
+        int32_t b = a;
+        hi = i1;
+        while (b < hi) {
+            int32_t mid = (b + hi) >> 1;
+            if (P.aitems[mid].sub_lo <= l) b = mid + 1; else hi = mid;
+        }
+        int32_t it = a;
+        for (; it + 4 <= b; it += 4) {
+            double2 v[4];
+            #pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const Item& I = P.aitems[it + q];
+                v[q] = part[I.off + (int64_t)(l - I.sub_lo) * nch + p];
+            }
+            #pragma unroll
+            for (int q = 0; q < 4; ++q) { sr += v[q].x; si += v[q].y; }
+        }
+        for (; it < b; ++it) {
+            const Item& I = P.aitems[it];
             double2 v = part[I.off + (int64_t)(l - I.sub_lo) * nch + p];
             sr += v.x;
             si += v.y;

@@ -266,21 +266,79 @@ struct Partition {
         B = ExecBuffers{};
         A = Arena{};
     }
-    template <class T>
-    int alloc(T*& out, size_t count)
-    {
-        out = nullptr;
-        if (count == 0) return NUHT_OK;
-        DevBuf b;
-        int rc = dev_alloc(b, count * sizeof(T), stream);
-        if (rc != NUHT_OK) return rc;
-        bufs.push_back(b);
-        bytes += (int64_t)b.bytes;
-        out = (T*)b.p;
-        return NUHT_OK;
-    }
     ~Partition() { release(); }
 };
+
+// Several device arrays carved out of one allocation (256-byte aligned), so a
+// plan makes a handful of allocation calls instead of dozens.
+class Slab {
+public:
+    template <class T>
+    void add(T*& out, size_t count)
+    {
+        reqs_.push_back(Req{(void**)&out, count * sizeof(T)});
+    }
+    size_t bytes() const
+    {
+        size_t t = 0;
+        for (const Req& r : reqs_) t += round(r.bytes);
+        return t;
+    }
+    // Allocates on stream s into b and assigns every requested pointer (null
+    // for empty requests).
+    int commit(DevBuf& b, hipStream_t s)
+    {
+        int rc = dev_alloc(b, bytes(), s);
+        if (rc != NUHT_OK) return rc;
+        char* base = (char*)b.p;
+        for (const Req& r : reqs_) {
+            *r.out = r.bytes ? (void*)base : nullptr;
+            base += round(r.bytes);
+        }
+        return NUHT_OK;
+    }
+    int commit(Partition& Pt)
+    {
+        DevBuf b;
+        int rc = commit(b, Pt.stream);
+        if (rc != NUHT_OK) return rc;
+        if (b.p) Pt.bufs.push_back(b);
+        Pt.bytes += (int64_t)b.bytes;
+        return NUHT_OK;
+    }
+
+private:
+    struct Req {
+        void** out;
+        size_t bytes;
+    };
+    static size_t round(size_t x) { return (x + 255) & ~(size_t)255; }
+    std::vector<Req> reqs_;
+};
+
+// Pinned host staging for the plan's one device-to-host read (the planning
+// summary and the input-check flag).  Allocated once per process; a plan holds
+// the lock from the copy to the read.
+struct HostStage {
+    Summary sum;
+    int32_t flag;
+};
+
+static HostStage* host_stage(std::unique_lock<std::mutex>& lock)
+{
+    static std::mutex mu;
+    static HostStage* stage = nullptr;
+    lock = std::unique_lock<std::mutex>(mu);
+    if (!stage) {
+        void* p = nullptr;
+        if (hipHostMalloc(&p, sizeof(HostStage), hipHostMallocPortable) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        stage = (HostStage*)p;
+    }
+    return stage;
+}
 
 }  // namespace nuht
 
@@ -291,7 +349,7 @@ struct nuht_plan_s {
     double eps = 0.0;
     nuht_opts opts{};
     int64_t n = 0, m = 0;
-    DevBuf b_keys, b_vals, b_keys2, b_vals2, b_hist, b_sum, b_flag;
+    DevBuf b_geom;               // keys, values, sort scratch, summary, flag
     uint64_t* keys = nullptr;    // sorted points then sorted frequencies (bit patterns)
     int32_t* vals = nullptr;     // matching caller indices
     uint64_t* keys2 = nullptr;
@@ -299,8 +357,6 @@ struct nuht_plan_s {
     int32_t* hist = nullptr;
     Summary* d_sum = nullptr;
     int32_t* d_flag = nullptr;   // domain error flag of the input check
-    Summary* h_sum = nullptr;    // pinned
-    int32_t* h_flag = nullptr;   // pinned
     int64_t geom_bytes = 0;
     Geometry fwd, adj;
     Partition pf, pa;
@@ -394,10 +450,13 @@ static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int
     P.n = G.n; P.m = G.m;
     P.rs = G.rs; P.ws = G.ws; P.perm_r = G.perm_r; P.perm_w = G.perm_w;
     Pt.sum = Summary{};
-    *pl->h_flag = 0;
     if (G.n == 0 || G.m == 0) {
-        HIP_TRY(hipMemcpyAsync(pl->h_flag, pl->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        std::unique_lock<std::mutex> lock;
+        HostStage* h = host_stage(lock);
+        if (!h) return NUHT_ENOMEM;
+        HIP_TRY(hipMemcpyAsync(&h->flag, pl->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (h->flag) return NUHT_EDOMAIN;
         Pt.built = true;
         return NUHT_OK;
     }
@@ -418,27 +477,37 @@ static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int
         A.node_cap = cap; A.l_cap = cap; A.a_cap = cap; A.d_cap = 2 * cap; A.q_cap = cap;
         A.litem_cap = icap; A.aitem_cap = icap;
         int32_t *K = nullptr, *Jc = nullptr, *a_cells = nullptr;
-        NUHT_TRY(tmp.alloc(K, (size_t)G.m));
-        NUHT_TRY(tmp.alloc(Jc, (size_t)G.n));
-        NUHT_TRY(tmp.alloc(a_cells, (size_t)A.aitem_cap));
-        NUHT_TRY(tmp.alloc(A.nodes, (size_t)A.node_cap));
-        NUHT_TRY(tmp.alloc(A.lb, (size_t)A.l_cap));
-        NUHT_TRY(tmp.alloc(A.ab, (size_t)A.a_cap));
-        NUHT_TRY(tmp.alloc(A.db, (size_t)A.d_cap));
-        NUHT_TRY(tmp.alloc(A.q0, (size_t)A.q_cap));
-        NUHT_TRY(tmp.alloc(A.q1, (size_t)A.q_cap));
-        NUHT_TRY(tmp.alloc(A.litems, (size_t)A.litem_cap));
-        NUHT_TRY(tmp.alloc(A.aitems, (size_t)A.aitem_cap));
-        NUHT_TRY(tmp.alloc(A.fft_list, (size_t)A.a_cap));
+        Slab slab;
+        slab.add(K, (size_t)G.m);
+        slab.add(Jc, (size_t)G.n);
+        slab.add(a_cells, (size_t)A.aitem_cap);
+        slab.add(A.nodes, (size_t)A.node_cap);
+        slab.add(A.lb, (size_t)A.l_cap);
+        slab.add(A.ab, (size_t)A.a_cap);
+        slab.add(A.db, (size_t)A.d_cap);
+        slab.add(A.q0, (size_t)A.q_cap);
+        slab.add(A.q1, (size_t)A.q_cap);
+        slab.add(A.litems, (size_t)A.litem_cap);
+        slab.add(A.aitems, (size_t)A.aitem_cap);
+        slab.add(A.fft_list, (size_t)A.a_cap);
+        slab.add(A.gslot, (size_t)A.a_cap + 1);
+        NUHT_TRY(slab.commit(tmp));
         P.nodes = A.nodes; P.lb = A.lb; P.ab = A.ab; P.db = A.db;
-        P.litems = A.litems; P.aitems = A.aitems; P.fft_list = A.fft_list;
+        P.litems = A.litems; P.aitems = A.aitems; P.fft_list = A.fft_list; P.gslot = A.gslot;
         HIP_TRY(hipMemsetAsync(pl->d_sum, 0, sizeof(Summary), s));
         HIP_TRY(launch_planning(P, A, K, Jc, a_cells, min_size, ncand, dft_max, sigma, pl->d_sum, s));
-        HIP_TRY(hipMemcpyAsync(pl->h_sum, pl->d_sum, sizeof(Summary), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(pl->h_flag, pl->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        S = *pl->h_sum;
-        if (*pl->h_flag) return NUHT_EDOMAIN;
+        int32_t flag = 0;
+        {
+            std::unique_lock<std::mutex> lock;
+            HostStage* h = host_stage(lock);
+            if (!h) return NUHT_ENOMEM;
+            HIP_TRY(hipMemcpyAsync(&h->sum, pl->d_sum, sizeof(Summary), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(&h->flag, pl->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            S = h->sum;
+            flag = h->flag;
+        }
+        if (flag) return NUHT_EDOMAIN;
         if (S.overflow == 2) return NUHT_ECAPACITY;   // subdivision deeper than kMaxLevels
         if (S.grid_error) return NUHT_ECAPACITY;
         if (S.overflow) {
@@ -463,11 +532,13 @@ static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int
 
     // execution buffers
     ExecBuffers& B = Pt.B;
-    NUHT_TRY(Pt.alloc(B.cs, (size_t)G.n));
-    NUHT_TRY(Pt.alloc(B.lpart, (size_t)S.n_litems * (P.L + 1)));
-    NUHT_TRY(Pt.alloc(B.lmom, (size_t)S.n_l * (P.L + 1)));
-    NUHT_TRY(Pt.alloc(B.part, (size_t)S.part_cells * P.nch));
-    NUHT_TRY(Pt.alloc(B.grids, (size_t)S.grid_cells * P.nch));
+    Slab slab;
+    slab.add(B.cs, (size_t)G.n);
+    slab.add(B.lpart, (size_t)S.n_litems * (P.L + 1));
+    slab.add(B.lmom, (size_t)S.n_l * (P.L + 1));
+    slab.add(B.part, (size_t)S.part_cells * P.nch);
+    slab.add(B.grids, (size_t)S.grid_cells * P.nch);
+    slab.add(B.gd, (size_t)G.m);
     B.grid_cells = S.grid_cells;
     int64_t scratch = 0;
     for (int c = 6; c <= kMaxFftLog2; ++c) {
@@ -478,8 +549,8 @@ static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int
         if (c > 12) scratch += (int64_t)fc.count * P.nch << c;
         Pt.cls.push_back(fc);
     }
-    NUHT_TRY(Pt.alloc(B.scratch, (size_t)scratch));
-    NUHT_TRY(Pt.alloc(B.gd, (size_t)G.m));
+    slab.add(B.scratch, (size_t)scratch);
+    NUHT_TRY(slab.commit(Pt));
     Pt.built = true;
     return NUHT_OK;
 }
@@ -490,15 +561,7 @@ static void free_plan(nuht_plan_t p)
     prof_clear(p);
     p->pf.release();
     p->pa.release();
-    dev_free(p->b_keys);
-    dev_free(p->b_vals);
-    dev_free(p->b_keys2);
-    dev_free(p->b_vals2);
-    dev_free(p->b_hist);
-    dev_free(p->b_sum);
-    dev_free(p->b_flag);
-    if (p->h_sum) (void)hipHostFree(p->h_sum);
-    if (p->h_flag) (void)hipHostFree(p->h_flag);
+    dev_free(p->b_geom);
     delete p;
 }
 
@@ -545,23 +608,19 @@ int nuht_plan(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_d
     p->nu_req = nu; p->eps = eps; p->opts = o; p->n = n; p->m = m;
     int64_t tot = n + m;
     auto fail = [&](int code) { free_plan(p); return code; };
-    if (dev_alloc(p->b_sum, sizeof(Summary), s) != NUHT_OK) return fail(NUHT_ENOMEM);
-    if (dev_alloc(p->b_flag, sizeof(int32_t), s) != NUHT_OK) return fail(NUHT_ENOMEM);
-    p->d_sum = (Summary*)p->b_sum.p;
-    p->d_flag = (int32_t*)p->b_flag.p;
-    if (hipHostMalloc(&p->h_sum, sizeof(Summary), hipHostMallocDefault) != hipSuccess) return fail(NUHT_ENOMEM);
-    if (hipHostMalloc(&p->h_flag, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) return fail(NUHT_ENOMEM);
-    if (tot > 0) {
-        if (dev_alloc(p->b_keys, sizeof(uint64_t) * tot, s) != NUHT_OK) return fail(NUHT_ENOMEM);
-        if (dev_alloc(p->b_vals, sizeof(int32_t) * tot, s) != NUHT_OK) return fail(NUHT_ENOMEM);
-        if (dev_alloc(p->b_keys2, sizeof(uint64_t) * tot, s) != NUHT_OK) return fail(NUHT_ENOMEM);
-        if (dev_alloc(p->b_vals2, sizeof(int32_t) * tot, s) != NUHT_OK) return fail(NUHT_ENOMEM);
-        if (dev_alloc(p->b_hist, sizeof(int32_t) * sort_hist_len((int32_t)n, (int32_t)m), s) != NUHT_OK)
-            return fail(NUHT_ENOMEM);
-        p->keys = (uint64_t*)p->b_keys.p; p->vals = (int32_t*)p->b_vals.p;
-        p->keys2 = (uint64_t*)p->b_keys2.p; p->vals2 = (int32_t*)p->b_vals2.p;
-        p->hist = (int32_t*)p->b_hist.p;
-        p->geom_bytes = (int64_t)tot * 24;
+    {
+        Slab slab;
+        slab.add(p->d_sum, 1);
+        slab.add(p->d_flag, 1);
+        if (tot > 0) {
+            slab.add(p->keys, (size_t)tot);
+            slab.add(p->vals, (size_t)tot);
+            slab.add(p->keys2, (size_t)tot);
+            slab.add(p->vals2, (size_t)tot);
+            slab.add(p->hist, (size_t)sort_hist_len((int32_t)n, (int32_t)m));
+        }
+        if (slab.commit(p->b_geom, s) != NUHT_OK) return fail(NUHT_ENOMEM);
+        p->geom_bytes = (int64_t)p->b_geom.bytes;
     }
     if (hipMemsetAsync(p->d_flag, 0, sizeof(int32_t), s) != hipSuccess) return fail(NUHT_EHIP);
     if (launch_make_keys(r_dev, (int32_t)n, p->keys, p->vals, p->d_flag, s) != hipSuccess) return fail(NUHT_EHIP);

@@ -106,6 +106,7 @@ struct PlanDev {
     const Item* litems;
     const Item* aitems;
     const int32_t* fft_list;         // FFT-path blocks grouped by size class
+    const int64_t* gslot;            // first grid slot of each asymptotic block; gslot[n_a] = all slots
     int32_t n_nodes, n_l, n_a, n_d, n_litems, n_aitems, pad1, pad2;
 };
 

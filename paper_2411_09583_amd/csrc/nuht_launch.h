@@ -22,6 +22,7 @@ struct Arena {
     Item* litems;
     Item* aitems;
     int32_t* fft_list;
+    int64_t* gslot;      // first grid slot of each asymptotic block, then the total (a_cap + 1)
     int32_t node_cap, l_cap, a_cap, d_cap, q_cap, litem_cap, aitem_cap, pad;
 };
 

@@ -445,11 +445,13 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, Summary*
         if (act) {
             A.ab[i].item0 = (int32_t)(a_items + v[0]);
             A.ab[i].grid_off = (grid + v[1]) * nch;
+            A.gslot[i] = grid + v[1];
             if (B.fft) atomicAdd(&cls_cnt[31 - __clz(B.N2)], 1);
         }
         a_items += tot[0];
         grid += tot[1];
     }
+    if (tid == 0) A.gslot[n_a] = grid;
     __syncthreads();
     if (tid == 0) {
         int32_t f = 0;
