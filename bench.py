@@ -40,6 +40,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def read_traffic(kernel):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE and WRITE_SIZE counters
+    scaled by a plain copy of known size), from the committed counter summary,
+    if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_large_uniform.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("sources_sha256") != sources_sha256():
+        return None
+    return dict(fetch_bytes=rec["fetch_bytes_per_launch"], write_bytes=rec["write_bytes_per_launch"],
+                bytes=rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"],
+                source=os.path.relpath(path, ROOT))
+
+
+def sources_sha256():
+    """Digest of the HIP sources and headers the kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2411_09583_amd", "csrc")
+    for d, names in ((csrc, sorted(os.listdir(csrc))), (os.path.join(ROOT, "include"), ["nuht.h"])):
+        for name in names:
+            if name.endswith((".hip", ".h")):
+                with open(os.path.join(d, name), "rb") as f:
+                    h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
 def copy_calibration():
     import torch
     x = torch.ones(64 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
@@ -159,23 +188,30 @@ def main():
     log("per order:", json.dumps(per_order))
     log("stage ms per step:", json.dumps(stage_ms))
 
-    # roofline of the dominant kernel: spreading (k_spread) or the row pass (k_rows).
-    # Algorithmic flops: every (point, cell) pair of the spreading adds a
-    # real-weighted sample to 2M complex channels, 2 FMA = 4 flops per channel;
-    # every (frequency, tap) pair of the interpolation does the same.
-    dom = max(("spread", "rows"), key=lambda s: stage_ms[s])
-    flops = 0.0
-    for nu in ORDERS:
-        inf = infos[nu]
-        two_m = 2 * inf["M"]
-        if dom == "spread":
-            flops += inf["asy_col_members"] * inf["es_width"] * two_m * 4.0
-        else:
-            flops += inf["asy_row_members"] * inf["es_width"] * two_m * 4.0
-    achieved = flops / (stage_ms[dom] * 1e-3)
-    roofline = dict(bound="alu", kernel="k_spread" if dom == "spread" else "k_rows",
-                    achieved=achieved / 1e12, peak=PEAK_FP64 / 1e12, unit="TFLOP/s",
-                    frac=achieved / PEAK_FP64, traffic=None)
+    # Roofline of the dominant kernel among those with an algorithmic flop
+    # count (FP64 operations the method's arithmetic needs, per launch; the
+    # transcendental kernel and phase evaluations are not counted):
+    #   k_spread    every (point, cell) pair inside the kernel support (w cells
+    #               per point membership): 2M complex channels x (2 add + 2 mul)
+    #               plus the kernel-weight product: 8M + 2
+    #   k_rows_asy  every (row, cell) pair of a direct-sum-path block: channel
+    #               sum (2M-1) x 4, complex product 8, phase rotation 6: 8M + 10;
+    #               every (row, tap) pair of an FFT-path block: (2M-1) x 4 + 4 = 8M
+    def flops(stage, inf):
+        M, w = inf["M"], inf["es_width"]
+        if stage == "spread":
+            return inf["asy_col_members"] * w * (8.0 * M + 2.0)
+        return inf["dft_row_cells"] * (8.0 * M + 10.0) + inf["fft_row_members"] * w * 8.0 * M
+
+    kern = {"spread": "k_spread", "rows_asymptotic": "k_rows_asy"}
+    dom = max(kern, key=lambda st: stage_ms[st])
+    fl = sum(flops(dom, infos[nu]) for nu in ORDERS)             # one launch per order per step
+    achieved = fl / (stage_ms[dom] * 1e-3)
+    traffic = read_traffic(kern[dom])
+    roofline = dict(bound="alu", kernel=kern[dom], achieved=achieved / 1e12, peak=PEAK_FP64 / 1e12,
+                    unit="TFLOP/s", frac=achieved / PEAK_FP64, traffic=traffic,
+                    flops_per_step=fl, launches_per_step=len(ORDERS),
+                    ms_per_step={k: stage_ms[k] for k in kern})
 
     # accuracy on sampled outputs (outside the timed region)
     accuracy = None

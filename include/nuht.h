@@ -84,6 +84,8 @@ typedef struct {
     int64_t direct_entries;
     int64_t grid_cells;               /* sum of spread-grid sizes N1 over asymptotic blocks */
     int64_t fft_points;               /* sum of FFT sizes N2 over FFT-path blocks */
+    int64_t dft_row_cells;            /* sum of rows x N1 over direct-sum-path blocks */
+    int64_t fft_row_members;          /* sum of rows over FFT-path blocks */
     int64_t workspace_bytes;          /* device memory held by the plan */
 } nuht_info;
 
@@ -135,13 +137,14 @@ int nuht_plan_info(nuht_plan_t plan, nuht_info *info);
  * Stage timing (diagnostics).  nuht_profile(plan, 1) clears and starts it:
  * every later nuht_execute / nuht_adjoint on the plan records HIP events on its
  * own stream between its NUHT_NSTAGES stages (0 gather of c, 1 local moments,
- * 2 ES spreading, 3 grid assembly, 4 FFTs, 5 direct blocks, 6 row pass).
+ * 2 ES spreading, 3 grid assembly, 4 FFTs, 5 direct blocks, 6 asymptotic rows,
+ * 7 local rows and output).
  * nuht_profile(plan, 0)
  * stops it.  nuht_profile_read synchronises on the last recorded event and
  * writes the per-stage totals in milliseconds to stage_ms[NUHT_NSTAGES] and
  * the number of profiled calls to *calls (may be NULL).
  */
-#define NUHT_NSTAGES 7
+#define NUHT_NSTAGES 8
 int nuht_profile(nuht_plan_t plan, int enable);
 int nuht_profile_read(nuht_plan_t plan, double *stage_ms, int64_t *calls);
 

@@ -47,14 +47,15 @@ class NuhtInfo(ctypes.Structure):
                 ("local_row_members", ctypes.c_int64), ("local_col_members", ctypes.c_int64),
                 ("asy_row_members", ctypes.c_int64), ("asy_col_members", ctypes.c_int64),
                 ("direct_entries", ctypes.c_int64), ("grid_cells", ctypes.c_int64),
-                ("fft_points", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
+                ("fft_points", ctypes.c_int64), ("dft_row_cells", ctypes.c_int64),
+                ("fft_row_members", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
 
 
 # every symbol include/nuht.h declares
 EXPORTS = ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_plan_set_order", "nuht_plan_info",
            "nuht_destroy", "nuht_strerror", "nuht_direct", "nuht_profile", "nuht_profile_read")
 
-STAGES = ("gather", "local_moments", "spread", "grid_assembly", "fft", "direct", "rows")
+STAGES = ("gather", "local_moments", "spread", "grid_assembly", "fft", "direct", "rows_asymptotic", "rows_local")
 
 _lib = None
 

@@ -538,7 +538,7 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
         double zr, zi;
         cis_dd(a0.hi, __builtin_fma((double)B.llo, tl, a0.lo), zr, zi);
         double s1, c1;
-        sincos(th, &s1, &c1);
+        sincos_small(th, &s1, &c1);
         double er = c1 - tl * s1, ei = s1 + tl * c1;
         for (int cix = 0; cix < B.N1; ++cix) {
             const double2* gp = G + (int64_t)cix * NCH;
@@ -631,14 +631,45 @@ __global__ void k_fill_zero(double* __restrict__ x, int64_t n)
     if (i < n) x[i] = 0.0;
 }
 
-// One thread per sorted frequency: walk the tree from the root.  At a node the
-// row lies either in the local side (rows j0..js) -- local block, then the
-// upper-right child -- or in the asymptotic side -- asymptotic block, then the
-// lower-left child.  A direct child ends the walk with the row's direct sum,
-// computed beforehand by k_direct_blocks.
+// Row pass, two kernels; each has one thread per sorted frequency and walks
+// the block tree from the root.  At a node the row lies either in the local
+// side (rows j0..js) -- local block, then the upper-right child -- or in the
+// asymptotic side -- asymptotic block, then the lower-left child; a direct
+// child ends the walk.  k_rows_asy adds the row's asymptotic blocks (no LDS,
+// so it runs at the occupancy its registers allow) into ga; k_rows_local adds
+// the local blocks, the direct-block sum from k_direct_blocks and ga, and
+// writes g once in the caller's order.
 template <int NCH>
-__global__ __launch_bounds__(256) void k_rows(PlanDev P, const double* __restrict__ gd, const double* __restrict__ lmom,
-                       const double2* __restrict__ grids, double* __restrict__ g)
+__global__ __launch_bounds__(256) void k_rows_asy(PlanDev P, const double2* __restrict__ grids,
+                                                  double* __restrict__ ga)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= P.m) return;
+    double om = P.ws[j];
+    double acc = 0.0;
+    int node = P.n_nodes > 0 ? 0 : -1;
+    while (node >= 0) {
+        const Node nd = P.nodes[node];
+        int child;
+        if (j <= nd.js) {
+            child = nd.ur;
+        } else {
+            if (nd.ablk >= 0) {
+                int ab = nd.ablk;
+                int abu = __builtin_amdgcn_readfirstlane(ab);
+                if (__all(ab == abu)) acc += asym_eval<NCH>(P, abu, om, grids);
+                else acc += asym_eval<NCH>(P, ab, om, grids);
+            }
+            child = nd.ll;
+        }
+        node = child;
+    }
+    ga[j] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_rows_local(PlanDev P, const double* __restrict__ gd,
+                                                    const double* __restrict__ ga, const double* __restrict__ lmom,
+                                                    double* __restrict__ g)
 {
     extern __shared__ double ring_all[];
     int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -660,12 +691,6 @@ __global__ __launch_bounds__(256) void k_rows(PlanDev P, const double* __restric
             }
             child = nd.ur;
         } else {
-            if (nd.ablk >= 0) {
-                int ab = nd.ablk;
-                int abu = __builtin_amdgcn_readfirstlane(ab);
-                if (__all(ab == abu)) acc += asym_eval<NCH>(P, abu, om, grids);
-                else acc += asym_eval<NCH>(P, ab, om, grids);
-            }
             child = nd.ll;
         }
         if (child <= -2) {
@@ -674,7 +699,7 @@ __global__ __launch_bounds__(256) void k_rows(PlanDev P, const double* __restric
         }
         node = child;
     }
-    g[P.perm_w[j]] = P.sign * acc;
+    g[P.perm_w[j]] = P.sign * (acc + ga[j]);
 }
 
 // Brute-force reference: one thread per frequency, all points.
@@ -703,11 +728,16 @@ static void launch_spread(const PlanDev& P, const Summary& S, const ExecBuffers&
 }
 
 template <int NCH>
-static void launch_rows(const PlanDev& P, const ExecBuffers& B, double* g, hipStream_t s)
+static void launch_rows_asy(const PlanDev& P, const ExecBuffers& B, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rows_asy<NCH>, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, P, B.grids, B.ga);
+}
+
+static void launch_rows_local(const PlanDev& P, const ExecBuffers& B, double* g, hipStream_t s)
 {
     int bs = (P.nu + 1) * 256 * 8 <= 65536 ? 256 : 64;
     size_t lds = (size_t)(P.nu + 1) * bs * sizeof(double);
-    hipLaunchKernelGGL(k_rows<NCH>, dim3(cdiv64(P.m, bs)), dim3(bs), lds, s, P, B.gd, B.lmom, B.grids, g);
+    hipLaunchKernelGGL(k_rows_local, dim3(cdiv64(P.m, bs)), dim3(bs), lds, s, P, B.gd, B.ga, B.lmom, g);
 }
 
 // Calls f with std::integral_constant<int, nch>; nch is one of the instantiated
@@ -783,8 +813,10 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
         hipLaunchKernelGGL(k_direct_blocks, dim3(P.n_d), dim3(64), 0, s, P, B.cs, B.gd);
     }
     mark(marks, 6, s);
-    dispatch_channels(P.nch, [&](auto k) { launch_rows<decltype(k)::value>(P, B, g, s); });
+    dispatch_channels(P.nch, [&](auto k) { launch_rows_asy<decltype(k)::value>(P, B, s); });
     mark(marks, 7, s);
+    launch_rows_local(P, B, g, s);
+    mark(marks, 8, s);
     return hipGetLastError();
 }
 

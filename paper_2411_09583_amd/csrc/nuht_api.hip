@@ -539,6 +539,7 @@ static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int
     slab.add(B.part, (size_t)S.part_cells * P.nch);
     slab.add(B.grids, (size_t)S.grid_cells * P.nch);
     slab.add(B.gd, (size_t)G.m);
+    slab.add(B.ga, (size_t)G.m);
     B.grid_cells = S.grid_cells;
     int64_t scratch = 0;
     for (int c = 6; c <= kMaxFftLog2; ++c) {
@@ -694,6 +695,7 @@ int nuht_plan_info(nuht_plan_t p, nuht_info* info)
     info->asy_row_members = S.a_row; info->asy_col_members = S.a_col;
     info->direct_entries = S.d_ent;
     info->grid_cells = S.grid_cells; info->fft_points = S.fft_points;
+    info->dft_row_cells = S.dft_row_cells; info->fft_row_members = S.fft_rows;
     info->workspace_bytes = p->geom_bytes + p->pf.bytes + p->pa.bytes;
     return NUHT_OK;
 }

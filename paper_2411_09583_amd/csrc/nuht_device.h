@@ -32,6 +32,46 @@ constexpr double kInvTwoPiLo = -9.8393383375912433e-18;   // 1/(2 pi) - kInvTwoP
 constexpr double kPi = 3.141592653589793116;
 constexpr double kSqrt2OverPi = 0.79788456080286541;
 
+// sin x and cos x for |x| <= 64: x is reduced by the nearest multiple q of
+// pi/2 (pi/2 split into two doubles, each product taken inside an FMA), and
+// sin, cos of the remainder |r| <= pi/4 are the Taylor polynomials through
+// r^17 and r^18 (truncation below 1e-19), chosen by q mod 4.  No
+// large-argument reduction, which keeps the register footprint small.
+__device__ __forceinline__ void sincos_small(double x, double* sp, double* cp)
+{
+    constexpr double kPio2Hi = 1.5707963267948966;       // pi/2 rounded to double
+    constexpr double kPio2Lo = 6.123233995736766e-17;    // pi/2 - kPio2Hi
+    constexpr double kTwoOverPi = 0.6366197723675814;
+    double q = rint(x * kTwoOverPi);
+    double r = __builtin_fma(-q, kPio2Hi, x);
+    r = __builtin_fma(-q, kPio2Lo, r);
+    double r2 = r * r;
+    double ps = 1.0 / 355687428096000.0;                  // 1/17!
+    ps = __builtin_fma(ps, r2, -1.0 / 1307674368000.0);
+    ps = __builtin_fma(ps, r2, 1.0 / 6227020800.0);
+    ps = __builtin_fma(ps, r2, -1.0 / 39916800.0);
+    ps = __builtin_fma(ps, r2, 1.0 / 362880.0);
+    ps = __builtin_fma(ps, r2, -1.0 / 5040.0);
+    ps = __builtin_fma(ps, r2, 1.0 / 120.0);
+    ps = __builtin_fma(ps, r2, -1.0 / 6.0);
+    double sn = __builtin_fma(r * r2, ps, r);
+    double pc = -1.0 / 6402373705728000.0;                // -1/18!
+    pc = __builtin_fma(pc, r2, 1.0 / 20922789888000.0);
+    pc = __builtin_fma(pc, r2, -1.0 / 87178291200.0);
+    pc = __builtin_fma(pc, r2, 1.0 / 479001600.0);
+    pc = __builtin_fma(pc, r2, -1.0 / 3628800.0);
+    pc = __builtin_fma(pc, r2, 1.0 / 40320.0);
+    pc = __builtin_fma(pc, r2, -1.0 / 720.0);
+    pc = __builtin_fma(pc, r2, 1.0 / 24.0);
+    pc = __builtin_fma(pc, r2, -0.5);
+    double cs = __builtin_fma(r2, pc, 1.0);
+    int k = (int)q & 3;
+    double s0 = (k & 1) ? cs : sn;
+    double c0 = (k & 1) ? sn : cs;
+    *sp = (k & 2) ? -s0 : s0;
+    *cp = ((k + 1) & 2) ? -c0 : c0;
+}
+
 // (cos t, sin t) for t = hi + lo, |hi| < 2^52.  t is reduced by the nearest
 // multiple k of 2 pi: hi - k*kTwoPiHi is exact (k*kTwoPiHi is formed exactly
 // and lies within a factor two of hi), the low parts are added afterwards, and
@@ -44,7 +84,7 @@ __device__ __forceinline__ void cis_dd(double hi, double lo, double& c, double& 
     double rl = (lo - p.lo) - k * kTwoPiLo;
     dd t = two_sum(r, rl);
     double sn, cs;
-    sincos(t.hi, &sn, &cs);
+    sincos_small(t.hi, &sn, &cs);
     c = __builtin_fma(-t.lo, sn, cs);
     s = __builtin_fma(t.lo, cs, sn);
 }

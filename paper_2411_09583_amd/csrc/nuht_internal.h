@@ -78,6 +78,8 @@ struct Summary {
     int64_t dft_cells;      // sum N1 over direct-sum-path blocks
     int64_t fft_points;     // sum N2 over FFT-path blocks
     int64_t part_cells;     // sum of item subgrid sizes
+    int64_t dft_row_cells;  // sum of rows x N1 over direct-sum-path blocks
+    int64_t fft_rows;       // sum of rows over FFT-path blocks
     int32_t fft_count[kMaxFftLog2 + 1];   // FFT-path blocks per log2(N2)
     int32_t fft_first[kMaxFftLog2 + 1];   // start of each size class in the FFT list
     int32_t domain_error;

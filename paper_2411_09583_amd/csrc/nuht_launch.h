@@ -46,6 +46,7 @@ struct ExecBuffers {
     double2* grids;     // spread grids (direct-sum path) and FFT buffers (FFT path)
     double2* scratch;   // second buffer of the two-pass FFTs
     double* gd;         // per-row direct-block sums (m)
+    double* ga;         // per-row asymptotic sums (m)
     int64_t grid_cells; // grid slots (without the channel factor)
 };
 
@@ -56,7 +57,7 @@ struct FftClass {
 
 // Execution stages, timed between consecutive events of `marks` (kStages + 1
 // events, or null).
-constexpr int kStages = 7;   // gather, local moments, spread, grid assembly, FFT, direct, rows
+constexpr int kStages = 8;   // gather, local moments, spread, grid assembly, FFT, direct, asymptotic rows, local rows
 hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers& B, const FftClass* cls, int ncls,
                           const double* c, double* g, hipStream_t s, hipEvent_t* marks);
 hipError_t launch_direct(const PlanDev& P, const double* r, const double* c, int32_t n, const double* w, int32_t m,

@@ -417,7 +417,7 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, Summary*
     __shared__ int64_t wsum[2][16];
     __shared__ int32_t cls_cnt[kMaxFftLog2 + 1];
     __shared__ int32_t cls_first[kMaxFftLog2 + 1];
-    __shared__ long long red[6][1024 / 64];
+    __shared__ long long red[9][1024 / 64];
     if (sum->overflow) return;
     const int32_t n_l = sum->n_l, n_a = sum->n_a, n_d = sum->n_d;
     int tid = threadIdx.x;
@@ -475,49 +475,43 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, Summary*
             A.ab[i].fft_slot = slot;
         }
     }
-    // membership statistics
-    long long s[6] = {0, 0, 0, 0, 0, 0};
+    // membership statistics: rows / columns of local and asymptotic blocks,
+    // direct entries, grid cells and FFT points, and the row-side work of the
+    // asymptotic blocks (rows x cells on the direct-sum path, rows on the FFT path)
+    constexpr int kStats = 9;
+    long long st[kStats] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int32_t i = tid; i < n_l; i += 1024) {
         LBlock L = A.lb[i];
-        s[0] += L.j1 - L.j0 + 1; s[1] += L.k1 - L.k0 + 1;
+        st[0] += L.j1 - L.j0 + 1; st[1] += L.k1 - L.k0 + 1;
     }
-    long long fp = 0;
     for (int32_t i = tid; i < n_a; i += 1024) {
         ABlock B = A.ab[i];
-        s[2] += B.j1 - B.j0 + 1; s[3] += B.k1 - B.k0 + 1;
-        if (B.fft) fp += B.N2; else s[5] += B.N1;
+        long long rows = B.j1 - B.j0 + 1;
+        st[2] += rows; st[3] += B.k1 - B.k0 + 1;
+        if (B.fft) { st[6] += B.N2; st[8] += rows; }
+        else { st[5] += B.N1; st[7] += rows * B.N1; }
     }
     for (int32_t i = tid; i < n_d; i += 1024) {
         DBlock Db = A.db[i];
-        s[4] += (long long)(Db.j1 - Db.j0 + 1) * (Db.k1 - Db.k0 + 1);
+        st[4] += (long long)(Db.j1 - Db.j0 + 1) * (Db.k1 - Db.k0 + 1);
     }
-    for (int q = 0; q < 6; ++q) {
-        long long x = q == 5 ? s[5] : s[q];
+    for (int q = 0; q < kStats; ++q) {
+        long long x = st[q];
         for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
         if ((tid & 63) == 0) red[q][tid >> 6] = x;
     }
     __syncthreads();
-    // fp reuses red[5] after the first read
-    long long fpx = fp;
-    for (int o = 32; o >= 1; o >>= 1) fpx += __shfl_xor(fpx, o);
     if (tid == 0) {
-        long long t[6] = {0, 0, 0, 0, 0, 0};
-        for (int q = 0; q < 6; ++q)
+        long long t[kStats] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int q = 0; q < kStats; ++q)
             for (int w2 = 0; w2 < 1024 / 64; ++w2) t[q] += red[q][w2];
         sum->l_row = t[0]; sum->l_col = t[1]; sum->a_row = t[2]; sum->a_col = t[3];
-        sum->d_ent = t[4]; sum->dft_cells = t[5];
+        sum->d_ent = t[4]; sum->dft_cells = t[5]; sum->fft_points = t[6];
+        sum->dft_row_cells = t[7]; sum->fft_rows = t[8];
         sum->n_litems = (int32_t)l_items; sum->n_aitems = (int32_t)a_items;
         sum->max_nch = nch;
         sum->grid_cells = grid;
         if (l_items > A.litem_cap || a_items > A.aitem_cap) sum->overflow = 1;
-    }
-    __syncthreads();
-    if ((tid & 63) == 0) red[0][tid >> 6] = fpx;
-    __syncthreads();
-    if (tid == 0) {
-        long long t = 0;
-        for (int w2 = 0; w2 < 1024 / 64; ++w2) t += red[0][w2];
-        sum->fft_points = t;
     }
 }
 
