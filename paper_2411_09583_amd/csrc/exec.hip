@@ -102,71 +102,102 @@ __global__ void k_lmom_reduce(PlanDev P, const double* __restrict__ lpart, doubl
 // smallest point r0, times the type-3 pre-phase), placed at grid coordinate
 // u_k = (r_k - C)/h.  Cell l receives sum_k x_k^(p) ES((l - u_k) 2/w).
 //
-// Phase 1: one thread per point computes (u, weight, ratio) into LDS; the
-// offset r - C and the phase D (r - C) are kept as double-double so that the
-// kernel position and the phase are exact to FP64 relative to themselves.
-// Phase 2: threads own (cell, slice) pairs and gather the points in the cell's
-// kernel support (a contiguous range, points being sorted); slices of one
-// cell are adjacent lanes and are summed with cross-lane shuffles.
+// The points of an item are taken in sub-chunks of kSpreadSub.
+// Phase 1: one thread per point forms the offset r - C and the phase
+// D (r - C) as double-doubles (so the kernel position and the phase are exact
+// to FP64 relative to themselves), the weight and the ratio r0 / r, the first
+// cell l0 it reaches, and its w kernel values from the polynomial pieces
+// (sums of coefficients common to all lanes times powers of the point's
+// offset), all into LDS.
+// Phase 2: threads own (cell, slice) pairs; the points reaching cell l are
+// those with l - w < l0 <= l, a contiguous range (points are sorted), found by
+// binary search; slices of one cell are adjacent lanes and are summed with
+// cross-lane shuffles after the last sub-chunk.
 // ---------------------------------------------------------------------------
+constexpr int kSpreadSub = 256;
+
 template <int NCH>
-__global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restrict__ cs, double2* __restrict__ part)
+__global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restrict__ cs,
+                                                const double* __restrict__ es_poly, double2* __restrict__ part)
 {
-    __shared__ double s_uh[kSpreadChunk];
-    __shared__ double s_ul[kSpreadChunk];
-    __shared__ double s_wr[kSpreadChunk];
-    __shared__ double s_wi[kSpreadChunk];
-    __shared__ double s_q[kSpreadChunk];
+    __shared__ int32_t s_l0[kSpreadSub];
+    __shared__ double s_wr[kSpreadSub];
+    __shared__ double s_wi[kSpreadSub];
+    __shared__ double s_q[kSpreadSub];
+    __shared__ double s_k[kSpreadSub * kMaxEsWidth];
     const Item I = P.aitems[blockIdx.x];
     const ABlock B = P.ab[I.blk];
     const int tid = threadIdx.x;
-    const int np = I.kb - I.ka;
     const int w = P.w;
+    const double hw = 0.5 * w;
     const double inv_h = 1.0 / B.h;      // exact: h is a power of two
-    for (int i = tid; i < np; i += 256) {
-        int k = I.ka + i;
-        double r = P.rs[k];
-        double c = cs[k];
-        dd tp = two_sum(r, -B.C);
-        dd ph = two_prod(B.D, tp.hi);
-        double cth, sth;
-        cis_dd(ph.hi, __builtin_fma(B.D, tp.lo, ph.lo), cth, sth);
-        double q = B.r0 / r;
-        double w0 = c * sqrt(q);
-        s_uh[i] = tp.hi * inv_h;
-        s_ul[i] = tp.lo * inv_h;
-        s_wr[i] = w0 * cth;
-        s_wi[i] = w0 * sth;
-        s_q[i] = q;
-    }
-    __syncthreads();
     const int sub_n = I.sub_n;
     int slices = 1;
     while (slices < 64 && slices * 2 * sub_n <= 256) slices <<= 1;
     const int cells_par = 256 / slices;
-    const double hw = 0.5 * w;
-    const double two_over_w = 2.0 / w;
     for (int cbase = 0; cbase < sub_n; cbase += cells_par) {
-        int cell = cbase + tid / slices;
-        int sl = tid & (slices - 1);
+        const int cell = cbase + tid / slices;
+        const int sl = tid & (slices - 1);
+        const int l = I.sub_lo + cell;
         double ar[NCH], ai[NCH];
         #pragma unroll
         for (int p = 0; p < NCH; ++p) { ar[p] = 0.0; ai[p] = 0.0; }
-        if (cell < sub_n) {
-            double l = (double)(I.sub_lo + cell);
-            // first point with u > l - hw - 1 and first with u >= l + hw + 1
-            int lo = 0, hi = np;
-            double key = l - hw - 1.0;
-            while (lo < hi) { int mid = (lo + hi) >> 1; if (s_uh[mid] <= key) lo = mid + 1; else hi = mid; }
-            int first = lo;
-            lo = first; hi = np;
-            key = l + hw + 1.0;
-            while (lo < hi) { int mid = (lo + hi) >> 1; if (s_uh[mid] < key) lo = mid + 1; else hi = mid; }
-            int last = lo;
-            for (int i = first + sl; i < last; i += slices) {
-                double x = ((l - s_uh[i]) - s_ul[i]) * two_over_w;
-                if (fabs(x) < 1.0) {
-                    double phi = es_kernel(x, P.beta);
+        for (int k0 = I.ka; k0 < I.kb; k0 += kSpreadSub) {
+            const int np = (I.kb - k0) < kSpreadSub ? (I.kb - k0) : kSpreadSub;
+            __syncthreads();
+            // every thread evaluates a point (the last one when tid >= np) so
+            // that the coefficient loads below stay wave-uniform (scalar)
+            {
+                const bool own = tid < np;
+                int k = k0 + (own ? tid : np - 1);
+                double r = P.rs[k];
+                double c = cs[k];
+                dd tp = two_sum(r, -B.C);
+                dd ph = two_prod(B.D, tp.hi);
+                double cth, sth;
+                cis_dd(ph.hi, __builtin_fma(B.D, tp.lo, ph.lo), cth, sth);
+                double q = B.r0 / r;
+                double w0 = c * sqrt(q);
+                if (own) {
+                    s_wr[tid] = w0 * cth;
+                    s_wi[tid] = w0 * sth;
+                    s_q[tid] = q;
+                }
+                // u - w/2 = (tp.hi + tp.lo)/h - w/2 (scaling by h exact)
+                dd a = two_sum(tp.hi * inv_h, -hw);
+                double lo = a.lo + tp.lo * inv_h;
+                double fl = floor(a.hi);
+                double frac = (a.hi - fl) + lo;          // a.hi - fl is exact
+                if (frac < 0.0) { fl -= 1.0; frac += 1.0; }
+                else if (frac >= 1.0) { fl += 1.0; frac -= 1.0; }
+                if (own) s_l0[tid] = (int)fl + 1;
+                const double sv = 1.0 - 2.0 * frac;      // s = 2 f - 1, f = 1 - frac
+                // powers of s once per point; each piece is then sum_d c_d s^d
+                // with the (scalar) coefficient as a multiplicand
+                double spow[kEsDeg + 1];
+                spow[0] = 1.0;
+                #pragma unroll
+                for (int d = 1; d <= kEsDeg; ++d) spow[d] = spow[d - 1] * sv;
+                double* kv = s_k + tid * w;
+                for (int t = 0; t < w; ++t) {
+                    const double* cf = es_poly + t * (kEsDeg + 1);
+                    double v = cf[0];
+                    #pragma unroll
+                    for (int d = 1; d <= kEsDeg; ++d) v = __builtin_fma(cf[d], spow[d], v);
+                    if (own) kv[t] = v;
+                }
+            }
+            __syncthreads();
+            if (cell < sub_n) {
+                // points with l0 in (l - w, l]
+                int lo = 0, hi = np;
+                while (lo < hi) { int mid = (lo + hi) >> 1; if (s_l0[mid] <= l - w) lo = mid + 1; else hi = mid; }
+                int first = lo;
+                hi = np;
+                while (lo < hi) { int mid = (lo + hi) >> 1; if (s_l0[mid] <= l) lo = mid + 1; else hi = mid; }
+                int last = lo;
+                for (int i = first + sl; i < last; i += slices) {
+                    double phi = s_k[i * w + (l - s_l0[i])];
                     double vr = phi * s_wr[i], vi = phi * s_wi[i];
                     double q = s_q[i];
                     #pragma unroll
@@ -724,7 +755,7 @@ template <int NCH>
 static void launch_spread(const PlanDev& P, const Summary& S, const ExecBuffers& B, hipStream_t s)
 {
     if (S.n_aitems > 0)
-        hipLaunchKernelGGL(k_spread<NCH>, dim3(S.n_aitems), dim3(256), 0, s, P, B.cs, B.part);
+        hipLaunchKernelGGL(k_spread<NCH>, dim3(S.n_aitems), dim3(256), 0, s, P, B.cs, B.es_poly, B.part);
 }
 
 template <int NCH>

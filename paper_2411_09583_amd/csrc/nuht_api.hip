@@ -108,7 +108,7 @@ static int es_width(double eps, int precision)
 {
     int digits = (int)std::ceil(-std::log10(eps) - 1e-9);
     int w = precision == NUHT_FP32_SPREAD ? digits + 2 : digits + 3;
-    return std::min(std::max(w, 4), 18);
+    return std::min(std::max(w, 4), kMaxEsWidth);
 }
 
 static double es_beta(int w) { return 2.30 * w; }
@@ -164,6 +164,59 @@ static void eshat_chebyshev(int w, double beta, double kappa_max, double* coef, 
     }
     coef[0] *= 0.5;
     (void)w;
+}
+
+// The ES kernel as w polynomial pieces.  A point at grid coordinate u reaches
+// the w cells l0 + t (t = 0 .. w-1), l0 = floor(u - w/2) + 1; with
+// f = l0 - (u - w/2) in (0, 1], cell l0 + t sees ES((2 (t + f) - w) / w).
+// Piece t is that function of s = 2 f - 1 on [-1, 1], interpolated at the
+// kEsDeg + 1 Chebyshev points and rewritten in monomials of s, all in long
+// double; coefficients are stored [t][d] (d = 0 .. kEsDeg).  Rounded to double
+// and summed by Horner's rule they reproduce the kernel to ~6e-16 of its peak
+// for w >= 15, and below the kernel's own truncation e^-beta for smaller w.
+static void es_pieces(int w, double beta, double* coef)
+{
+    const int D = kEsDeg;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    long double node[kEsDeg + 1], val[kEsDeg + 1], a[kEsDeg + 1];
+    long double T[kEsDeg + 1][kEsDeg + 1] = {};   // T[j][i]: coefficient of s^i in T_j(s)
+    T[0][0] = 1.0L;
+    T[1][1] = 1.0L;
+    for (int j = 2; j <= D; ++j)
+        for (int i = 0; i <= j; ++i) T[j][i] = (i > 0 ? 2.0L * T[j - 1][i - 1] : 0.0L) - T[j - 2][i];
+    for (int k = 0; k <= D; ++k) node[k] = std::cos(pi * (k + 0.5L) / (D + 1));
+    for (int t = 0; t < w; ++t) {
+        for (int k = 0; k <= D; ++k) {
+            long double f = 0.5L * (node[k] + 1.0L);
+            long double x = (2.0L * (t + f) - w) / w;
+            long double r = 1.0L - x * x;
+            val[k] = r > 0.0L ? std::exp((long double)beta * (std::sqrt(r) - 1.0L)) : 0.0L;
+        }
+        for (int j = 0; j <= D; ++j) {
+            long double sm = 0.0L;
+            for (int k = 0; k <= D; ++k) sm += val[k] * std::cos(pi * j * (k + 0.5L) / (D + 1));
+            a[j] = sm * (j == 0 ? 1.0L : 2.0L) / (D + 1);
+        }
+        for (int i = 0; i <= D; ++i) {
+            long double c = 0.0L;
+            for (int j = i; j <= D; ++j) c += a[j] * T[j][i];
+            coef[t * (D + 1) + i] = (double)c;
+        }
+    }
+}
+
+// Cached per kernel width (beta follows w).
+static const double* es_pieces_cached(int w, double beta)
+{
+    static std::mutex mu;
+    static double table[kMaxEsWidth + 1][kMaxEsWidth * (kEsDeg + 1)];
+    static bool have[kMaxEsWidth + 1] = {};
+    std::lock_guard<std::mutex> lock(mu);
+    if (!have[w]) {
+        es_pieces(w, beta, table[w]);
+        have[w] = true;
+    }
+    return table[w];
 }
 
 // -(2nu+1) pi/4 modulo 2 pi as a double-double in (0, 2 pi].
@@ -551,7 +604,11 @@ static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int
         Pt.cls.push_back(fc);
     }
     slab.add(B.scratch, (size_t)scratch);
+    slab.add(B.es_poly, (size_t)P.w * (kEsDeg + 1));
     NUHT_TRY(slab.commit(Pt));
+    HIP_TRY(hipMemcpyAsync(B.es_poly, es_pieces_cached(P.w, P.beta), sizeof(double) * P.w * (kEsDeg + 1),
+                           hipMemcpyHostToDevice, s));
+    P.es_poly = B.es_poly;
     Pt.built = true;
     return NUHT_OK;
 }

@@ -14,6 +14,8 @@ constexpr int kMaxChannels = 40;       // 2M with M <= 20 (eq. num-asy-terms cap
 constexpr int kMaxFftLog2 = 26;        // largest FFT of an asymptotic block: 2^26 points
 constexpr int kLocalChunk = 4096;      // columns per local-moment work item
 constexpr int kSpreadChunk = 1024;     // points per spreading work item
+constexpr int kMaxEsWidth = 18;        // largest ES kernel width
+constexpr int kEsDeg = 16;             // degree of the per-cell polynomial pieces of the ES kernel
 constexpr int kMaxLevels = 4096;       // subdivision depth limit
 
 // A mixed block of Alg. 1 and the split chosen for it.  Rows j0..js and
@@ -109,6 +111,7 @@ struct PlanDev {
     const Item* aitems;
     const int32_t* fft_list;         // FFT-path blocks grouped by size class
     const int64_t* gslot;            // first grid slot of each asymptotic block; gslot[n_a] = all slots
+    const double* es_poly;           // ES kernel pieces, w x (kEsDeg + 1) monomial coefficients
     int32_t n_nodes, n_l, n_a, n_d, n_litems, n_aitems, pad1, pad2;
 };
 
