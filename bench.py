@@ -44,15 +44,19 @@ def read_traffic(kernel):
     """HBM bytes per launch of `kernel` (FETCH_SIZE and WRITE_SIZE counters
     scaled by a plain copy of known size), from the committed counter summary,
     if it was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_large_uniform.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_large_uniform.txt")
     if not os.path.exists(path):
         return None
+    rec = {}
     with open(path) as f:
-        rec = json.load(f)
+        for line in f:
+            if ":" in line and not line.startswith((" ", "#")):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
     if rec.get("sources_sha256") != sources_sha256():
         return None
-    return dict(fetch_bytes=rec["fetch_bytes_per_launch"], write_bytes=rec["write_bytes_per_launch"],
-                bytes=rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"],
+    fetch, write = float(rec["fetch_bytes_per_launch"]), float(rec["write_bytes_per_launch"])
+    return dict(fetch_bytes=fetch, write_bytes=write, bytes=fetch + write,
                 source=os.path.relpath(path, ROOT))
 
 
