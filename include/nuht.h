@@ -124,9 +124,30 @@ int nuht_execute(nuht_plan_t plan, const double *c_dev, double *g_dev, void *str
 int nuht_adjoint(nuht_plan_t plan, const double *y_dev, double *cbar_dev, void *stream);
 
 /*
+ * nuht_gradient -- derivatives of a loss L(g), g = A c, given gbar = dL/dg
+ * (m values in frequency order), with respect to the weights, the points and
+ * the frequencies:
+ *   dc[k]     = sum_j gbar_j J_nu(omega_j r_k)                 (A^T gbar)
+ *   dr[k]     = c_k sum_j gbar_j omega_j J_nu'(omega_j r_k)
+ *   domega[j] = gbar_j sum_k c_k r_k J_nu'(omega_j r_k)
+ * with J_nu' = (J_{nu-1} - J_{nu+1}) / 2 (J_{-1} = -J_1), so dr and domega
+ * are two transposed and two forward transforms of orders nu -+ 1 on the
+ * plan's sorted geometry (Sec. 3 applied at those orders).  Any of dc, dr,
+ * domega may be NULL (not computed); c_dev may be NULL when neither dr nor
+ * domega is asked for.  Outputs are in the caller's order and overwritten.
+ * Orders nu -+ 1 need |nu| <= 100.  The partitions of the orders used are
+ * built on the first call (one synchronisation each) and kept in the plan
+ * (up to four orders), as are two n- and two m-sized temporaries; later calls
+ * are asynchronous on `stream` and allocate nothing.
+ */
+int nuht_gradient(nuht_plan_t plan, const double *c_dev, const double *gbar_dev,
+                  double *dc_dev, double *dr_dev, double *domega_dev, void *stream);
+
+/*
  * nuht_plan_set_order -- switch the plan to order nu (same points, frequencies
- * and eps), recomputing (M, z, L) and the partition but not the sort.  Used for
- * the J_{nu+-1} transforms of the gradient.  Synchronises `stream` once.
+ * and eps): (M, z, L) and the partition of that order are computed on the
+ * sorted geometry (no new sort) the first time the order is used, which
+ * synchronises `stream` once, and kept for later switches.
  */
 int nuht_plan_set_order(nuht_plan_t plan, int nu, void *stream);
 

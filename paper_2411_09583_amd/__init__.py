@@ -52,8 +52,8 @@ class NuhtInfo(ctypes.Structure):
 
 
 # every symbol include/nuht.h declares
-EXPORTS = ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_plan_set_order", "nuht_plan_info",
-           "nuht_destroy", "nuht_strerror", "nuht_direct", "nuht_profile", "nuht_profile_read")
+EXPORTS = ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_plan_set_order",
+           "nuht_plan_info", "nuht_destroy", "nuht_strerror", "nuht_direct", "nuht_profile", "nuht_profile_read")
 
 STAGES = ("gather", "local_moments", "spread", "grid_assembly", "fft", "direct", "rows_asymptotic", "rows_local")
 
@@ -73,6 +73,7 @@ def load_library():
                               ctypes.c_int64, vp, ctypes.POINTER(NuhtOpts), vp]
     lib.nuht_execute.argtypes = [vp, vp, vp, vp]
     lib.nuht_adjoint.argtypes = [vp, vp, vp, vp]
+    lib.nuht_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.nuht_plan_set_order.argtypes = [vp, ctypes.c_int, vp]
     lib.nuht_plan_info.argtypes = [vp, ctypes.POINTER(NuhtInfo)]
     lib.nuht_destroy.argtypes = [vp]
@@ -81,7 +82,7 @@ def load_library():
     lib.nuht_direct.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, vp, vp, ctypes.c_int64, vp, vp, vp]
     lib.nuht_profile.argtypes = [vp, ctypes.c_int]
     lib.nuht_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
-    for name in ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_plan_set_order", "nuht_plan_info",
+    for name in ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_plan_set_order", "nuht_plan_info",
                  "nuht_destroy", "nuht_direct", "nuht_profile", "nuht_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -150,6 +151,27 @@ class Plan:
         _check(load_library().nuht_adjoint(self._h, _ptr(y), _ptr(cb), _stream()))
         return cb
 
+    def gradient(self, c, gbar, *, want_c=True, want_r=True, want_omega=True):
+        """(dL/dc, dL/dr, dL/domega) for g = execute(c) and gbar = dL/dg; entries
+        not wanted are None."""
+        gbar = _dev_f64(gbar, "gbar")
+        if gbar.numel() != self.m:
+            raise ValueError("gbar must have m entries")
+        if want_r or want_omega:
+            c = _dev_f64(c, "c")
+            if c.numel() != self.n:
+                raise ValueError("c must have n entries")
+        new = lambda k: torch.empty(k, dtype=torch.float64, device=self.device)
+        dc = new(self.n) if want_c else None
+        dr = new(self.n) if want_r else None
+        dw = new(self.m) if want_omega else None
+        null = ctypes.c_void_p(0)
+        _check(load_library().nuht_gradient(self._h, _ptr(c) if (want_r or want_omega) else null, _ptr(gbar),
+                                             _ptr(dc) if dc is not None else null,
+                                             _ptr(dr) if dr is not None else null,
+                                             _ptr(dw) if dw is not None else null, _stream()))
+        return dc, dr, dw
+
     def set_order(self, nu: int):
         _check(load_library().nuht_plan_set_order(self._h, int(nu), _stream()))
 
@@ -179,6 +201,33 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class NuhtFunction(torch.autograd.Function):
+    """g = A(r, omega) c, differentiable in c, r and omega.
+
+    The forward pass plans on (r, omega) (the method needs no precomputation
+    beyond the plan) and keeps the plan for the backward pass, which runs
+    nuht_gradient: A^T gbar for c, and the order nu -+ 1 transforms of
+    J_nu' = (J_{nu-1} - J_{nu+1}) / 2 for r and omega.
+    """
+
+    @staticmethod
+    def forward(ctx, c, r, omega, nu, eps=1e-12):
+        plan = Plan(r.detach(), omega.detach(), nu, eps)
+        g = plan.execute(c.detach())
+        ctx.plan = plan
+        ctx.save_for_backward(c)
+        return g
+
+    @staticmethod
+    def backward(ctx, gbar):
+        (c,) = ctx.saved_tensors
+        want = ctx.needs_input_grad
+        dc, dr, dw = ctx.plan.gradient(c.detach(), gbar.contiguous(), want_c=want[0], want_r=want[1],
+                                       want_omega=want[2])
+        ctx.plan.close()
+        return dc, dr, dw, None, None
 
 
 def nuht(c, r, omega, nu: int, eps: float = 1e-12, **opts):

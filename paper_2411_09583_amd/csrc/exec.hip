@@ -24,6 +24,23 @@ __global__ void k_gather(const double* __restrict__ c, const int32_t* __restrict
     if (k < n) cs[k] = c[perm[k]];
 }
 
+// Gather times the sorted coordinate: cs[k] = c[perm[k]] x[k].
+__global__ void k_gather_scaled(const double* __restrict__ c, const int32_t* __restrict__ perm,
+                                const double* __restrict__ x, int32_t n, double* __restrict__ cs)
+{
+    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) cs[k] = c[perm[k]] * x[k];
+}
+
+// out = w (a - b) / 2: the derivative J_nu' = (J_{nu-1} - J_{nu+1}) / 2 applied
+// to the two shifted-order transforms.
+__global__ void k_half_difference(const double* __restrict__ w, const double* __restrict__ a,
+                                  const double* __restrict__ b, double* __restrict__ out, int32_t n)
+{
+    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = 0.5 * w[k] * (a[k] - b[k]);
+}
+
 // ---------------------------------------------------------------------------
 // Local moments t_l = sum_k c_k T_{2l(+1)}(r_k / R) of one chunk of a local
 // block's columns (Sec. 3.1: T^T applied first).  The Chebyshev polynomials
@@ -800,14 +817,18 @@ static inline void mark(hipEvent_t* marks, int i, hipStream_t s)
 }
 
 hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers& B, const FftClass* cls, int ncls,
-                          const double* c, double* g, hipStream_t s, hipEvent_t* marks)
+                          const double* c, double* g, bool scale_by_points, hipStream_t s, hipEvent_t* marks)
 {
     if (P.m == 0) return hipSuccess;
-    if (P.n == 0) {
-        return hipMemsetAsync(g, 0, sizeof(double) * (size_t)P.m, s);
+    if (P.n == 0) {   // a fill kernel, not a memset node, so the call can be captured in a graph
+        hipLaunchKernelGGL(k_fill_zero, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, g, (int64_t)P.m);
+        return hipGetLastError();
     }
     mark(marks, 0, s);
-    hipLaunchKernelGGL(k_gather, dim3(cdiv64(P.n, 256)), dim3(256), 0, s, c, P.perm_r, P.n, B.cs);
+    if (scale_by_points)
+        hipLaunchKernelGGL(k_gather_scaled, dim3(cdiv64(P.n, 256)), dim3(256), 0, s, c, P.perm_r, P.rs, P.n, B.cs);
+    else
+        hipLaunchKernelGGL(k_gather, dim3(cdiv64(P.n, 256)), dim3(256), 0, s, c, P.perm_r, P.n, B.cs);
     mark(marks, 1, s);
     if (S.n_litems > 0) {
         hipLaunchKernelGGL(k_lmom, dim3(S.n_litems), dim3(256), 0, s, P, B.cs, B.lpart);
@@ -848,6 +869,14 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
     mark(marks, 7, s);
     launch_rows_local(P, B, g, s);
     mark(marks, 8, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_half_difference(const double* w, const double* a, const double* b, double* out, int32_t n,
+                                  hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_half_difference, dim3(cdiv64(n, 256)), dim3(256), 0, s, w, a, b, out, n);
     return hipGetLastError();
 }
 

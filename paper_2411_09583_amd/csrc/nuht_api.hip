@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -412,7 +413,17 @@ struct nuht_plan_s {
     int32_t* d_flag = nullptr;   // domain error flag of the input check
     int64_t geom_bytes = 0;
     Geometry fwd, adj;
-    Partition pf, pa;
+    // Partitions by order: forward and transposed, built on first use and kept
+    // (the gradient runs orders nu - 1 and nu + 1 on the same sorted geometry).
+    struct OrderParts {
+        int nu = 0;
+        uint64_t used = 0;
+        Partition f, a;
+    };
+    std::vector<std::unique_ptr<OrderParts>> orders;
+    uint64_t clock = 0;
+    DevBuf b_grad;               // gradient temporaries (two of n, two of m)
+    double* grad_t[4] = {nullptr, nullptr, nullptr, nullptr};
     // stage timing (diagnostics): kStages + 1 events per profiled call
     bool prof = false;
     std::vector<hipEvent_t> prof_events;
@@ -617,10 +628,66 @@ static void free_plan(nuht_plan_t p)
 {
     if (!p) return;
     prof_clear(p);
-    p->pf.release();
-    p->pa.release();
+    p->orders.clear();
+    dev_free(p->b_grad);
     dev_free(p->b_geom);
     delete p;
+}
+
+// At most this many orders keep their partitions; the least recently used
+// other order is dropped to make room.
+constexpr size_t kMaxOrders = 4;
+
+static nuht_plan_s::OrderParts* order_parts(nuht_plan_t p, int nu)
+{
+    for (auto& o : p->orders)
+        if (o->nu == nu) { o->used = ++p->clock; return o.get(); }
+    if (p->orders.size() >= kMaxOrders) {
+        size_t victim = p->orders.size();
+        for (size_t i = 0; i < p->orders.size(); ++i)
+            if (p->orders[i]->nu != p->nu_req &&
+                (victim == p->orders.size() || p->orders[i]->used < p->orders[victim]->used))
+                victim = i;
+        if (victim < p->orders.size()) p->orders.erase(p->orders.begin() + victim);
+    }
+    auto o = std::unique_ptr<nuht_plan_s::OrderParts>(new (std::nothrow) nuht_plan_s::OrderParts());
+    if (!o) return nullptr;
+    o->nu = nu;
+    o->used = ++p->clock;
+    p->orders.push_back(std::move(o));
+    return p->orders.back().get();
+}
+
+// The partition of order nu, forward (A) or transposed (A^T), built if needed
+// (building synchronises `s` once).
+static int get_partition(nuht_plan_t p, int nu, bool transposed, hipStream_t s, Partition** out)
+{
+    nuht_plan_s::OrderParts* o = order_parts(p, nu);
+    if (!o) return NUHT_ENOMEM;
+    Partition& Pt = transposed ? o->a : o->f;
+    if (!Pt.built) {
+        int rc = build_partition(p, Pt, transposed ? p->adj : p->fwd, nu, s);
+        if (rc != NUHT_OK) {
+            Pt.release();
+            return rc;
+        }
+    }
+    *out = &Pt;
+    return NUHT_OK;
+}
+
+static const Partition* current_forward(nuht_plan_t p)
+{
+    for (auto& o : p->orders)
+        if (o->nu == p->nu_req && o->f.built) return &o->f;
+    return nullptr;
+}
+
+static int run(nuht_plan_t p, const Partition& Pt, const double* in, double* out, bool scale, hipStream_t s)
+{
+    HIP_TRY(launch_execute(Pt.P, Pt.sum, Pt.B, Pt.cls.data(), (int)Pt.cls.size(), in, out, scale, s,
+                           prof_marks(p)));
+    return NUHT_OK;
 }
 
 static bool valid_common(int nu, double eps)
@@ -696,7 +763,9 @@ int nuht_plan(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_d
     p->adj.perm_r = p->fwd.perm_w; p->adj.perm_w = p->fwd.perm_r;
     // the one synchronisation of the plan happens inside (it also reads the
     // input check's flag)
-    int rc = build_partition(p, p->pf, p->fwd, nu, s);
+    p->nu_req = nu;
+    Partition* Pt = nullptr;
+    int rc = get_partition(p, nu, false, s, &Pt);
     if (rc != NUHT_OK) return fail(rc);
     *out = p;
     return NUHT_OK;
@@ -704,26 +773,62 @@ int nuht_plan(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_d
 
 int nuht_execute(nuht_plan_t p, const double* c_dev, double* g_dev, void* stream)
 {
-    if (!p || !p->pf.built) return NUHT_EINVAL;
+    if (!p) return NUHT_EINVAL;
+    const Partition* Pt = current_forward(p);
+    if (!Pt) return NUHT_EINVAL;
     if ((p->n > 0 && !c_dev) || (p->m > 0 && !g_dev)) return NUHT_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    const Partition& Pt = p->pf;
-    HIP_TRY(launch_execute(Pt.P, Pt.sum, Pt.B, Pt.cls.data(), (int)Pt.cls.size(), c_dev, g_dev, s, prof_marks(p)));
-    return NUHT_OK;
+    return run(p, *Pt, c_dev, g_dev, false, (hipStream_t)stream);
 }
 
 int nuht_adjoint(nuht_plan_t p, const double* y_dev, double* cbar_dev, void* stream)
 {
-    if (!p || !p->pf.built) return NUHT_EINVAL;
+    if (!p || !current_forward(p)) return NUHT_EINVAL;
     if ((p->m > 0 && !y_dev) || (p->n > 0 && !cbar_dev)) return NUHT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    if (!p->pa.built) {
-        int rc = build_partition(p, p->pa, p->adj, p->nu_req, s);
-        if (rc != NUHT_OK) return rc;
+    Partition* Pt = nullptr;
+    int rc = get_partition(p, p->nu_req, true, s, &Pt);
+    if (rc != NUHT_OK) return rc;
+    return run(p, *Pt, y_dev, cbar_dev, false, s);
+}
+
+int nuht_gradient(nuht_plan_t p, const double* c_dev, const double* gbar_dev, double* dc_dev, double* dr_dev,
+                  double* domega_dev, void* stream)
+{
+    if (!p || !current_forward(p)) return NUHT_EINVAL;
+    const bool want_r = dr_dev != nullptr, want_w = domega_dev != nullptr;
+    if (p->m > 0 && !gbar_dev) return NUHT_EINVAL;
+    if ((want_r || want_w) && p->n > 0 && !c_dev) return NUHT_EINVAL;
+    const int nu = p->nu_req;
+    if ((want_r || want_w) && std::abs(nu) + 1 > 101) return NUHT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if ((want_r || want_w) && !p->b_grad.p && p->n + p->m > 0) {
+        Slab slab;
+        slab.add(p->grad_t[0], (size_t)p->n);
+        slab.add(p->grad_t[1], (size_t)p->n);
+        slab.add(p->grad_t[2], (size_t)p->m);
+        slab.add(p->grad_t[3], (size_t)p->m);
+        if (slab.commit(p->b_grad, s) != NUHT_OK) return NUHT_ENOMEM;
     }
-    const Partition& Pt = p->pa;
-    HIP_TRY(launch_execute(Pt.P, Pt.sum, Pt.B, Pt.cls.data(), (int)Pt.cls.size(), y_dev, cbar_dev, s,
-                           prof_marks(p)));
+    Partition* Pt = nullptr;
+    int rc;
+    if (dc_dev) {                        // dL/dc = A^T gbar
+        if ((rc = get_partition(p, nu, true, s, &Pt)) != NUHT_OK) return rc;
+        if ((rc = run(p, *Pt, gbar_dev, dc_dev, false, s)) != NUHT_OK) return rc;
+    }
+    if (want_r && p->n > 0) {            // dL/dr = (c/2) (A_{nu-1}^T - A_{nu+1}^T)(omega gbar)
+        if ((rc = get_partition(p, nu - 1, true, s, &Pt)) != NUHT_OK) return rc;
+        if ((rc = run(p, *Pt, gbar_dev, p->grad_t[0], true, s)) != NUHT_OK) return rc;
+        if ((rc = get_partition(p, nu + 1, true, s, &Pt)) != NUHT_OK) return rc;
+        if ((rc = run(p, *Pt, gbar_dev, p->grad_t[1], true, s)) != NUHT_OK) return rc;
+        HIP_TRY(launch_half_difference(c_dev, p->grad_t[0], p->grad_t[1], dr_dev, (int32_t)p->n, s));
+    }
+    if (want_w && p->m > 0) {            // dL/domega = (gbar/2) (A_{nu-1} - A_{nu+1})(r c)
+        if ((rc = get_partition(p, nu - 1, false, s, &Pt)) != NUHT_OK) return rc;
+        if ((rc = run(p, *Pt, c_dev, p->grad_t[2], true, s)) != NUHT_OK) return rc;
+        if ((rc = get_partition(p, nu + 1, false, s, &Pt)) != NUHT_OK) return rc;
+        if ((rc = run(p, *Pt, c_dev, p->grad_t[3], true, s)) != NUHT_OK) return rc;
+        HIP_TRY(launch_half_difference(gbar_dev, p->grad_t[2], p->grad_t[3], domega_dev, (int32_t)p->m, s));
+    }
     return NUHT_OK;
 }
 
@@ -731,16 +836,20 @@ int nuht_plan_set_order(nuht_plan_t p, int nu, void* stream)
 {
     if (!p) return NUHT_EINVAL;
     if (!valid_common(nu, p->eps)) return NUHT_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    p->pa.release();
+    const int prev = p->nu_req;
     p->nu_req = nu;
-    return build_partition(p, p->pf, p->fwd, nu, s);
+    Partition* Pt = nullptr;
+    int rc = get_partition(p, nu, false, (hipStream_t)stream, &Pt);
+    if (rc != NUHT_OK) p->nu_req = prev;
+    return rc;
 }
 
 int nuht_plan_info(nuht_plan_t p, nuht_info* info)
 {
-    if (!p || !info || !p->pf.built) return NUHT_EINVAL;
-    const Partition& Pt = p->pf;
+    if (!p || !info) return NUHT_EINVAL;
+    const Partition* cur = current_forward(p);
+    if (!cur) return NUHT_EINVAL;
+    const Partition& Pt = *cur;
     const PlanDev& P = Pt.P;
     const Summary& S = Pt.sum;
     std::memset(info, 0, sizeof(*info));
@@ -753,7 +862,9 @@ int nuht_plan_info(nuht_plan_t p, nuht_info* info)
     info->direct_entries = S.d_ent;
     info->grid_cells = S.grid_cells; info->fft_points = S.fft_points;
     info->dft_row_cells = S.dft_row_cells; info->fft_row_members = S.fft_rows;
-    info->workspace_bytes = p->geom_bytes + p->pf.bytes + p->pa.bytes;
+    int64_t bytes = p->geom_bytes + (int64_t)p->b_grad.bytes;
+    for (auto& o : p->orders) bytes += o->f.bytes + o->a.bytes;
+    info->workspace_bytes = bytes;
     return NUHT_OK;
 }
 

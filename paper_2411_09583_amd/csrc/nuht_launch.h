@@ -59,8 +59,15 @@ struct FftClass {
 // Execution stages, timed between consecutive events of `marks` (kStages + 1
 // events, or null).
 constexpr int kStages = 8;   // gather, local moments, spread, grid assembly, FFT, direct, asymptotic rows, local rows
+// One transform with the plan's partition: out = A in (or A^T in on the
+// transposed geometry).  With scale_by_points, the input is multiplied by the
+// geometry's sorted point coordinates as it is gathered (r c for the forward
+// geometry, omega y for the transposed one).
 hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers& B, const FftClass* cls, int ncls,
-                          const double* c, double* g, hipStream_t s, hipEvent_t* marks);
+                          const double* c, double* g, bool scale_by_points, hipStream_t s, hipEvent_t* marks);
+// out[i] = w[i] (a[i] - b[i]) / 2
+hipError_t launch_half_difference(const double* w, const double* a, const double* b, double* out, int32_t n,
+                                  hipStream_t s);
 hipError_t launch_direct(const PlanDev& P, const double* r, const double* c, int32_t n, const double* w, int32_t m,
                          double* g, hipStream_t s);
 

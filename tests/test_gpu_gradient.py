@@ -1,0 +1,184 @@
+"""GPU gradient (nuht_gradient and the autograd function) against the oracle.
+
+* the three derivatives against the oracle's gradient (direct sums at orders
+  nu, nu -+ 1) on seeded inputs with a prescribed gbar, several orders
+  including nu = 0 (J_{-1} = -J_1) and a negative order; bar 1e-12 relative l2
+  and max for each derivative;
+* the autograd function against central finite differences of the GPU forward
+  on a loss 0.5 |g - y|^2;
+* the differentiation case at full size (n = m = 1e6, nu = 5) on 64 sampled
+  entries of each derivative, computed one by one by the oracle;
+* repeated calls reuse the cached partitions and give identical results.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import gradient as ograd
+from oracle import method
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def nuht():
+    import paper_2411_09583_amd as lib
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lib.load_library()
+    return lib
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def rel_max(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("nu", [0, 1, 5, -3])
+def test_gradient_against_oracle(nuht, nu):
+    # dc is one transposed transform: 1e-12 in rel-l2 and max, as the forward.
+    # dr and domega are differences of two transforms (orders nu -+ 1), each
+    # within its own entrywise bound eps; the method-exact reference built the
+    # same way already deviates from the direct sums by up to ~1.3e-12 in max
+    # norm.  Bar: rel-l2 <= 1e-12 against the direct sums, every entry within
+    # the entrywise bound eps |c_k| sum_j |gbar_j w_j| (resp.
+    # eps |gbar_j| sum_k |c_k r_k|), and agreement with the method-exact
+    # gradient at the GPU path's own rounding level.
+    r, w, c = workloads.uniform(1800, 1500, 1.0, 1500.0, seed=70 + abs(nu))
+    gbar = workloads.cotangent(w.size, seed=80 + abs(nu))
+    p = nuht.Plan(dev(r), dev(w), nu, 1e-12)
+    dc, dr, dw = (host(t) for t in p.gradient(dev(c), dev(gbar)))
+    p.close()
+    oc, orr, ow = ograd.gradient(nu, r, c, w, gbar)
+    print(nu, "dc", rel_l2(dc, oc), rel_max(dc, oc))
+    assert rel_l2(dc, oc) <= TOL and rel_max(dc, oc) <= TOL
+    gw, cr = gbar * w, c * r
+    bound_r = 1e-12 * np.abs(c) * np.sum(np.abs(gw))
+    bound_w = 1e-12 * np.abs(gbar) * np.sum(np.abs(cr))
+    m2r = 0.5 * c * (method.nufht_reference(nu - 1, 1e-12, w, gw, r) - method.nufht_reference(nu + 1, 1e-12, w, gw, r))
+    m2w = 0.5 * gbar * (method.nufht_reference(nu - 1, 1e-12, r, cr, w) - method.nufht_reference(nu + 1, 1e-12, r, cr, w))
+    for name, a, b, bnd, b2 in (("dr", dr, orr, bound_r, m2r), ("domega", dw, ow, bound_w, m2w)):
+        print(nu, name, rel_l2(a, b), rel_max(a, b), rel_l2(a, b2), rel_max(a, b2))
+        assert rel_l2(a, b) <= TOL, (name, rel_l2(a, b))
+        assert np.all(np.abs(a - b) <= bnd), name
+        assert rel_l2(a, b2) <= 2e-13 and rel_max(a, b2) <= 2e-13, name
+
+
+def test_gradient_subsets_and_repeat(nuht):
+    r, w, c = workloads.uniform(1200, 1300, 1.0, 900.0, seed=91)
+    gbar = workloads.cotangent(w.size, seed=92)
+    p = nuht.Plan(dev(r), dev(w), 2, 1e-12)
+    full = [host(t) for t in p.gradient(dev(c), dev(gbar))]
+    again = [host(t) for t in p.gradient(dev(c), dev(gbar))]
+    only_r = p.gradient(dev(c), dev(gbar), want_c=False, want_omega=False)
+    g = host(p.execute(dev(c)))              # the plan's own order is untouched
+    p.close()
+    for a, b in zip(full, again):
+        assert np.array_equal(a, b)
+    assert only_r[0] is None and only_r[2] is None
+    assert np.array_equal(host(only_r[1]), full[1])
+    from oracle import direct
+    assert rel_l2(g, direct.dht(2, r, c, w)) <= TOL
+
+
+def test_autograd_against_finite_differences(nuht):
+    r, w, c = workloads.uniform(900, 800, 1.0, 600.0, seed=93)
+    y = workloads.cotangent(w.size, seed=94)
+    nu, eps = 3, 1e-12
+    ct = dev(c).requires_grad_(True)
+    rt = dev(r).requires_grad_(True)
+    wt = dev(w).requires_grad_(True)
+    g = nuht.NuhtFunction.apply(ct, rt, wt, nu, eps)
+    loss = 0.5 * torch.sum((g - dev(y)) ** 2)
+    loss.backward()
+    gc, gr, gw = host(ct.grad), host(rt.grad), host(wt.grad)
+
+    def L(c_, r_, w_):
+        gg = host(nuht.nuht(dev(c_), dev(r_), dev(w_), nu, eps))
+        return 0.5 * float(np.sum((gg - y) ** 2))
+
+    rng = np.random.default_rng(95)
+    for arr, grad, which in ((c, gc, 0), (r, gr, 1), (w, gw, 2)):
+        for k in rng.choice(arr.size, 8, replace=False):
+            h = 1e-6 * max(1.0, abs(arr[k]))
+            e = np.zeros(arr.size); e[k] = h
+            args_p = [c, r, w]; args_m = [c, r, w]
+            args_p[which] = arr + e; args_m[which] = arr - e
+            fd = (L(*args_p) - L(*args_m)) / (2 * h)
+            scale = np.max(np.abs(grad))
+            assert abs(fd - grad[k]) <= 1e-6 * scale, (which, k, fd, grad[k])
+
+
+def test_differentiation_full_size_sampled(nuht):
+    # n = m = 1e6, nu = 5.  (a) The gradient map is linear in gbar, so it is
+    # compared with the oracle for a seeded cotangent (the loss's own cotangent
+    # g - y would need the oracle's g at full size): 64 sampled entries of each
+    # derivative, each a direct sum over all 1e6 terms at orders 4, 5, 6.
+    r, w, c, y = workloads.differentiation(seed=6)
+    nu = 5
+    gbar = workloads.cotangent(w.size, seed=97)
+    p = nuht.Plan(dev(r), dev(w), nu, 1e-12)
+    dc, dr, dw = (host(t) for t in p.gradient(dev(c), dev(gbar)))
+    p.close()
+    rng = np.random.default_rng(96)
+    ic, ir, iw = (rng.choice(1_000_000, 64, replace=False) for _ in range(3))
+    oc, orr, ow = ograd.gradient_at(nu, r, c, w, gbar, ic, ir, iw)
+    for name, a, b in (("dc", dc[ic], oc), ("dr", dr[ir], orr), ("domega", dw[iw], ow)):
+        print(name, rel_l2(a, b))
+        assert rel_l2(a, b) <= TOL, (name, rel_l2(a, b))
+
+
+def test_differentiation_full_size_finite_differences(nuht):
+    # (b) The loss 0.5 |g - y|^2 through the autograd function against central
+    # differences of the GPU forward on 64 entries per variable, step h = 1e-6.
+    # For c the loss is quadratic, so central differences are exact at any
+    # step and the step is 1.  For r the loss oscillates on the scale
+    # 1/omega_max = 1e-5, so a central difference at h carries the truncation
+    # (omega h)^2 / 6 ~ 2e-3; one Richardson step with h/2 removes the h^2
+    # term, leaving ~(omega h)^4 / 480.  For omega the scale is 1/r_max = 1.
+    r, w, c, y = workloads.differentiation(seed=6)
+    nu, eps = 5, 1e-12
+    rd, wd, cd, yd = dev(r), dev(w), dev(c), dev(y)
+    ct, rt, wt = cd.clone().requires_grad_(True), rd.clone().requires_grad_(True), wd.clone().requires_grad_(True)
+    g = nuht.NuhtFunction.apply(ct, rt, wt, nu, eps)
+    (0.5 * torch.sum((g - yd) ** 2)).backward()
+    grads = (host(ct.grad), host(rt.grad), host(wt.grad))
+
+    # L(+) - L(-) = sum_j (g+ - g-) ((g+ + g-)/2 - y), formed without
+    # subtracting the two ~1e7-sized losses (whose rounding alone is ~1e-9)
+    def central(which, k, base, step):
+        plus, minus = base.clone(), base.clone()
+        plus[k] += step
+        minus[k] -= step
+        args_p, args_m = [cd, rd, wd], [cd, rd, wd]
+        args_p[which], args_m[which] = plus, minus
+        gp = nuht.nuht(args_p[0], args_p[1], args_p[2], nu, eps)
+        gm = nuht.nuht(args_m[0], args_m[1], args_m[2], nu, eps)
+        return float(torch.sum((gp - gm) * (0.5 * (gp + gm) - yd))) / (2 * step)
+
+    rng = np.random.default_rng(98)
+    for which, (base, step, richardson, tol) in enumerate(((cd, 1.0, False, 1e-9), (rd, 1e-6, True, 1e-5),
+                                                           (wd, 1e-6, False, 1e-6))):
+        grad = grads[which]
+        idx = rng.choice(base.numel(), 64, replace=False)
+        fd = np.empty(64)
+        for q, k in enumerate(idx):
+            d1 = central(which, k, base, step)
+            fd[q] = (4.0 * central(which, k, base, step / 2) - d1) / 3.0 if richardson else d1
+        err = np.linalg.norm(fd - grad[idx]) / np.linalg.norm(grad[idx])
+        print(which, err)
+        assert err <= tol, (which, err)

@@ -81,3 +81,14 @@ def batch(count: int = 256, seed: int = 5, lo: float = 3.0, hi: float = 6.0, nu_
         c = rng.standard_normal(n)
         out.append(dict(nu=nu, r=r, w=w, c=c))
     return out
+
+
+def differentiation(seed: int = 6, n: int = 1_000_000, m: int = 1_000_000):
+    """The differentiation case: r, w, c as the large uniform case, then the
+    target y ~ N(0,1) of the loss 0.5 |g - y|^2 (drawn in that order)."""
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(0.0, 1.0, n)
+    w = rng.uniform(0.0, 1e5, m)
+    c = rng.standard_normal(n)
+    y = rng.standard_normal(m)
+    return r, w, c, y
