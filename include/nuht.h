@@ -61,6 +61,10 @@ typedef struct nuht_plan_s *nuht_plan_t;
  *                     many cells are evaluated by a direct sum over the grid
  *                     instead of an FFT and interpolation (0 -> built-in default,
  *                     negative -> always use the FFT path).
+ *   spread_chunk      points per spreading work item, 64 .. 16384 (0 -> 1024).
+ *   tune              nonzero: nuht_plan_many picks min_size, dft_max and
+ *                     spread_chunk per size class with nuht_tune (the fields
+ *                     above are then starting values).
  */
 typedef struct {
     int64_t min_size;
@@ -68,6 +72,8 @@ typedef struct {
     int32_t split_candidates;
     int32_t precision;
     int32_t dft_max;
+    int32_t spread_chunk;
+    int32_t tune;
 } nuht_opts;
 
 /*
@@ -87,6 +93,8 @@ typedef struct {
     int64_t dft_row_cells;            /* sum of rows x N1 over direct-sum-path blocks */
     int64_t fft_row_members;          /* sum of rows over FFT-path blocks */
     int64_t workspace_bytes;          /* device memory held by the plan */
+    int64_t min_size;                 /* options in use (after defaults and tuning) */
+    int32_t dft_max, spread_chunk;
 } nuht_info;
 
 /*
@@ -153,6 +161,55 @@ int nuht_plan_set_order(nuht_plan_t plan, int nu, void *stream);
 
 /* nuht_plan_info -- parameters and partition statistics of the current order. */
 int nuht_plan_info(nuht_plan_t plan, nuht_info *info);
+
+/*
+ * nuht_tune -- pick the spreading work-item size, min_size and dft_max for
+ * this plan's geometry and order: coordinate descent over a few candidates of
+ * each, every candidate planned on the plan's sorted geometry and timed over
+ * `reps` executes (0 -> 3) with HIP events on `stream` (c_dev: n weights, or
+ * NULL for all ones; the timing does not depend on the values).  The best
+ * options are written to *best (and their time per execute to *best_ms, may
+ * be NULL) and adopted by the plan, whose partitions are rebuilt.
+ * Synchronises `stream` once per candidate.
+ */
+int nuht_tune(nuht_plan_t plan, const double *c_dev, int reps, nuht_opts *best, double *best_ms,
+              void *stream);
+
+/*
+ * Batches of independent transforms (uneven n, m and order).
+ *
+ * nuht_plan_many -- plan `count` transforms: transform i maps n[i] points
+ * r_dev[i] to m[i] frequencies omega_dev[i] at order nu[i], all with
+ * tolerance eps and the options *opts (NULL: defaults).  Every argument is
+ * validated as in nuht_plan.  Their sorts and subdivisions run on the batch's
+ * own streams (four, default priority) after the work already queued on
+ * `stream`, and the whole batch synchronises once (plus once more for any
+ * transform whose tables had to grow).  With opts->tune set, the largest
+ * transform of every size class (floor(log10(n + m))) is tuned first
+ * (nuht_tune, timing with all-ones weights) and its options serve the class.
+ *
+ * nuht_execute_many -- g_dev[i] = A_i c_dev[i] for every transform (host arrays
+ * of `count` device pointers; c_dev[i] in the caller's point order, g_dev[i]
+ * overwritten in frequency order).  The first call captures every transform's
+ * execution into one HIP graph: the transforms run concurrently on the
+ * batch's streams (largest first, balanced by n + m) and read their input and
+ * output addresses from a device table.  Each call writes the table with a
+ * small kernel and replays the graph, ordered after the work already queued
+ * on `stream` and before anything queued there later.  Asynchronous; it
+ * allocates nothing after the first call.  Calls on one batch must not
+ * overlap (they share the batch's buffers).
+ *
+ * nuht_batch_info -- nuht_plan_info of transform `index`.
+ * nuht_batch_destroy -- synchronise the batch's streams and free it.
+ */
+typedef struct nuht_batch_s *nuht_batch_t;
+int nuht_plan_many(nuht_batch_t *batch, int count, const int *nu, double eps,
+                   const int64_t *n, const double *const *r_dev,
+                   const int64_t *m, const double *const *omega_dev,
+                   const nuht_opts *opts, void *stream);
+int nuht_execute_many(nuht_batch_t batch, const double *const *c_dev, double *const *g_dev, void *stream);
+int nuht_batch_info(nuht_batch_t batch, int index, nuht_info *info);
+int nuht_batch_destroy(nuht_batch_t batch);
 
 /*
  * Stage timing (diagnostics).  nuht_profile(plan, 1) clears and starts it:

@@ -35,7 +35,7 @@ class NuhtError(RuntimeError):
 class NuhtOpts(ctypes.Structure):
     _fields_ = [("min_size", ctypes.c_int64), ("M_override", ctypes.c_int32),
                 ("split_candidates", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("dft_max", ctypes.c_int32)]
+                ("dft_max", ctypes.c_int32), ("spread_chunk", ctypes.c_int32), ("tune", ctypes.c_int32)]
 
 
 class NuhtInfo(ctypes.Structure):
@@ -48,12 +48,14 @@ class NuhtInfo(ctypes.Structure):
                 ("asy_row_members", ctypes.c_int64), ("asy_col_members", ctypes.c_int64),
                 ("direct_entries", ctypes.c_int64), ("grid_cells", ctypes.c_int64),
                 ("fft_points", ctypes.c_int64), ("dft_row_cells", ctypes.c_int64),
-                ("fft_row_members", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
+                ("fft_row_members", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("min_size", ctypes.c_int64), ("dft_max", ctypes.c_int32), ("spread_chunk", ctypes.c_int32)]
 
 
 # every symbol include/nuht.h declares
 EXPORTS = ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_plan_set_order",
-           "nuht_plan_info", "nuht_destroy", "nuht_strerror", "nuht_direct", "nuht_profile", "nuht_profile_read")
+           "nuht_plan_info", "nuht_tune", "nuht_plan_many", "nuht_execute_many", "nuht_batch_info",
+           "nuht_batch_destroy", "nuht_destroy", "nuht_strerror", "nuht_direct", "nuht_profile", "nuht_profile_read")
 
 STAGES = ("gather", "local_moments", "spread", "grid_assembly", "fft", "direct", "rows_asymptotic", "rows_local")
 
@@ -74,6 +76,13 @@ def load_library():
     lib.nuht_execute.argtypes = [vp, vp, vp, vp]
     lib.nuht_adjoint.argtypes = [vp, vp, vp, vp]
     lib.nuht_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.nuht_tune.argtypes = [vp, vp, ctypes.c_int, ctypes.POINTER(NuhtOpts), ctypes.POINTER(ctypes.c_double), vp]
+    lib.nuht_plan_many.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_double,
+                                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(vp), ctypes.POINTER(NuhtOpts), vp]
+    lib.nuht_execute_many.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    lib.nuht_batch_info.argtypes = [vp, ctypes.c_int, ctypes.POINTER(NuhtInfo)]
+    lib.nuht_batch_destroy.argtypes = [vp]
     lib.nuht_plan_set_order.argtypes = [vp, ctypes.c_int, vp]
     lib.nuht_plan_info.argtypes = [vp, ctypes.POINTER(NuhtInfo)]
     lib.nuht_destroy.argtypes = [vp]
@@ -83,6 +92,7 @@ def load_library():
     lib.nuht_profile.argtypes = [vp, ctypes.c_int]
     lib.nuht_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for name in ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_plan_set_order", "nuht_plan_info",
+                 "nuht_tune", "nuht_plan_many", "nuht_execute_many", "nuht_batch_info", "nuht_batch_destroy",
                  "nuht_destroy", "nuht_direct", "nuht_profile", "nuht_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -122,14 +132,15 @@ class Plan:
     """
 
     def __init__(self, r, omega, nu: int, eps: float, *, min_size: int = 0, M: int = 0,
-                 split_candidates: int = 0, precision: int = NUHT_FP64, dft_max: int = 0):
+                 split_candidates: int = 0, precision: int = NUHT_FP64, dft_max: int = 0,
+                 spread_chunk: int = 0):
         lib = load_library()
         r = _dev_f64(r, "r")
         omega = _dev_f64(omega, "omega")
         self.n = r.numel()
         self.m = omega.numel()
         self.device = r.device
-        opts = NuhtOpts(min_size, M, split_candidates, precision, dft_max)
+        opts = NuhtOpts(min_size, M, split_candidates, precision, dft_max, spread_chunk, 0)
         h = ctypes.c_void_p()
         _check(lib.nuht_plan(ctypes.byref(h), int(nu), float(eps), self.n, _ptr(r), self.m, _ptr(omega),
                              ctypes.byref(opts), _stream()))
@@ -172,6 +183,18 @@ class Plan:
                                              _ptr(dw) if dw is not None else null, _stream()))
         return dc, dr, dw
 
+    def tune(self, c=None, reps: int = 3) -> dict:
+        """Autotune this plan's spreading item size, min_size and dft_max (see
+        nuht_tune); the plan adopts the best options.  Returns them with the
+        best time per execute in ms."""
+        best = NuhtOpts()
+        ms = ctypes.c_double()
+        cp = _ptr(_dev_f64(c, "c")) if c is not None else ctypes.c_void_p(0)
+        _check(load_library().nuht_tune(self._h, cp, int(reps), ctypes.byref(best), ctypes.byref(ms), _stream()))
+        out = {f: getattr(best, f) for f, _ in NuhtOpts._fields_}
+        out["ms"] = ms.value
+        return out
+
     def set_order(self, nu: int):
         _check(load_library().nuht_plan_set_order(self._h, int(nu), _stream()))
 
@@ -194,6 +217,66 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             load_library().nuht_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent transforms (uneven n, m and order), planned together
+    and executed as one captured graph (nuht_plan_many / nuht_execute_many)."""
+
+    def __init__(self, rs, omegas, nus, eps: float, *, tune: bool = False, min_size: int = 0,
+                 dft_max: int = 0, spread_chunk: int = 0):
+        lib = load_library()
+        if not (len(rs) == len(omegas) == len(nus)):
+            raise ValueError("rs, omegas and nus must have the same length")
+        self.count = len(rs)
+        self._keep = [(_dev_f64(r, "r"), _dev_f64(w, "omega")) for r, w in zip(rs, omegas)]
+        self.n = [r.numel() for r, _ in self._keep]
+        self.m = [w.numel() for _, w in self._keep]
+        self.device = self._keep[0][0].device if self.count else torch.device("cuda")
+        k = self.count
+        nu_a = (ctypes.c_int * k)(*[int(v) for v in nus])
+        n_a = (ctypes.c_int64 * k)(*self.n)
+        m_a = (ctypes.c_int64 * k)(*self.m)
+        r_a = (ctypes.c_void_p * k)(*[_ptr(r).value for r, _ in self._keep])
+        w_a = (ctypes.c_void_p * k)(*[_ptr(w).value for _, w in self._keep])
+        opts = NuhtOpts(min_size, 0, 0, NUHT_FP64, dft_max, spread_chunk, 1 if tune else 0)
+        h = ctypes.c_void_p()
+        _check(lib.nuht_plan_many(ctypes.byref(h), k, nu_a, float(eps), n_a, r_a, m_a, w_a, ctypes.byref(opts),
+                                  _stream()))
+        self._h = h
+        self._keep = None          # the plans hold sorted copies
+
+    def execute(self, cs, gs=None):
+        if len(cs) != self.count:
+            raise ValueError("one weight vector per transform")
+        cs = [_dev_f64(c, "c") for c in cs]
+        for c, n in zip(cs, self.n):
+            if c.numel() != n:
+                raise ValueError("weight vector of the wrong length")
+        if gs is None:
+            gs = [torch.empty(m, dtype=torch.float64, device=self.device) for m in self.m]
+        k = self.count
+        c_a = (ctypes.c_void_p * k)(*[_ptr(c).value for c in cs])
+        g_a = (ctypes.c_void_p * k)(*[_ptr(g).value for g in gs])
+        self._io = (cs, gs)        # alive until the next call
+        _check(load_library().nuht_execute_many(self._h, c_a, g_a, _stream()))
+        return gs
+
+    def info(self, i: int) -> dict:
+        inf = NuhtInfo()
+        _check(load_library().nuht_batch_info(self._h, int(i), ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in NuhtInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().nuht_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

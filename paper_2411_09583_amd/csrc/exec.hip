@@ -17,19 +17,41 @@
 namespace nuht {
 
 // ---------------------------------------------------------------------------
-__global__ void k_gather(const double* __restrict__ c, const int32_t* __restrict__ perm, int32_t n,
-                         double* __restrict__ cs)
+// cs[k] = c[perm[k]] (times x[k] when x is given); c is read from c_slot when
+// that is set.
+__global__ void k_gather(const double* c, const double* const* c_slot, const int32_t* __restrict__ perm,
+                         const double* __restrict__ x, int32_t n, double* __restrict__ cs)
 {
     int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) cs[k] = c[perm[k]];
+    if (k >= n) return;
+    const double* cp = c_slot ? *c_slot : c;
+    double v = cp[perm[k]];
+    cs[k] = x ? v * x[k] : v;
 }
 
-// Gather times the sorted coordinate: cs[k] = c[perm[k]] x[k].
-__global__ void k_gather_scaled(const double* __restrict__ c, const int32_t* __restrict__ perm,
-                                const double* __restrict__ x, int32_t n, double* __restrict__ cs)
+// A transform with no points: the output is zero.
+__global__ void k_zero_output(double* g, double* const* g_slot, int64_t m)
 {
-    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) cs[k] = c[perm[k]] * x[k];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double* gp = g_slot ? *g_slot : g;
+    gp[i] = 0.0;
+}
+
+__global__ void k_fill_value(double* __restrict__ x, int64_t n, double v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+struct PtrArgs {
+    void* p[224];
+};
+
+__global__ void k_set_pointers(void** table, PtrArgs a, int count)
+{
+    int i = threadIdx.x;
+    if (i < count) table[i] = a.p[i];
 }
 
 // out = w (a - b) / 2: the derivative J_nu' = (J_{nu-1} - J_{nu+1}) / 2 applied
@@ -717,7 +739,7 @@ __global__ __launch_bounds__(256) void k_rows_asy(PlanDev P, const double2* __re
 
 __global__ __launch_bounds__(256) void k_rows_local(PlanDev P, const double* __restrict__ gd,
                                                     const double* __restrict__ ga, const double* __restrict__ lmom,
-                                                    double* __restrict__ g)
+                                                    double* g, double* const* g_slot)
 {
     extern __shared__ double ring_all[];
     int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -747,7 +769,8 @@ __global__ __launch_bounds__(256) void k_rows_local(PlanDev P, const double* __r
         }
         node = child;
     }
-    g[P.perm_w[j]] = P.sign * (acc + ga[j]);
+    double* gp = g_slot ? *g_slot : g;
+    gp[P.perm_w[j]] = P.sign * (acc + ga[j]);
 }
 
 // Brute-force reference: one thread per frequency, all points.
@@ -781,11 +804,12 @@ static void launch_rows_asy(const PlanDev& P, const ExecBuffers& B, hipStream_t 
     hipLaunchKernelGGL(k_rows_asy<NCH>, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, P, B.grids, B.ga);
 }
 
-static void launch_rows_local(const PlanDev& P, const ExecBuffers& B, double* g, hipStream_t s)
+static void launch_rows_local(const PlanDev& P, const ExecBuffers& B, const IoArgs& io, hipStream_t s)
 {
     int bs = (P.nu + 1) * 256 * 8 <= 65536 ? 256 : 64;
     size_t lds = (size_t)(P.nu + 1) * bs * sizeof(double);
-    hipLaunchKernelGGL(k_rows_local, dim3(cdiv64(P.m, bs)), dim3(bs), lds, s, P, B.gd, B.ga, B.lmom, g);
+    hipLaunchKernelGGL(k_rows_local, dim3(cdiv64(P.m, bs)), dim3(bs), lds, s, P, B.gd, B.ga, B.lmom, io.g,
+                       io.g_slot);
 }
 
 // Calls f with std::integral_constant<int, nch>; nch is one of the instantiated
@@ -816,19 +840,34 @@ static inline void mark(hipEvent_t* marks, int i, hipStream_t s)
     if (marks) (void)hipEventRecord(marks[i], s);
 }
 
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_value, dim3(cdiv64(n, 256)), dim3(256), 0, s, x, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_pointers(void** table, const void* const* ptrs, int count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    if (count > 224) return hipErrorInvalidValue;
+    PtrArgs a;
+    for (int i = 0; i < count; ++i) a.p[i] = const_cast<void*>(ptrs[i]);
+    hipLaunchKernelGGL(k_set_pointers, dim3(1), dim3(256), 0, s, table, a, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers& B, const FftClass* cls, int ncls,
-                          const double* c, double* g, bool scale_by_points, hipStream_t s, hipEvent_t* marks)
+                          const IoArgs& io, hipStream_t s, hipEvent_t* marks)
 {
     if (P.m == 0) return hipSuccess;
     if (P.n == 0) {   // a fill kernel, not a memset node, so the call can be captured in a graph
-        hipLaunchKernelGGL(k_fill_zero, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, g, (int64_t)P.m);
+        hipLaunchKernelGGL(k_zero_output, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, io.g, io.g_slot, (int64_t)P.m);
         return hipGetLastError();
     }
     mark(marks, 0, s);
-    if (scale_by_points)
-        hipLaunchKernelGGL(k_gather_scaled, dim3(cdiv64(P.n, 256)), dim3(256), 0, s, c, P.perm_r, P.rs, P.n, B.cs);
-    else
-        hipLaunchKernelGGL(k_gather, dim3(cdiv64(P.n, 256)), dim3(256), 0, s, c, P.perm_r, P.n, B.cs);
+    hipLaunchKernelGGL(k_gather, dim3(cdiv64(P.n, 256)), dim3(256), 0, s, io.c, io.c_slot, P.perm_r,
+                       io.scale_by_points ? P.rs : nullptr, P.n, B.cs);
     mark(marks, 1, s);
     if (S.n_litems > 0) {
         hipLaunchKernelGGL(k_lmom, dim3(S.n_litems), dim3(256), 0, s, P, B.cs, B.lpart);
@@ -867,7 +906,7 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
     mark(marks, 6, s);
     dispatch_channels(P.nch, [&](auto k) { launch_rows_asy<decltype(k)::value>(P, B, s); });
     mark(marks, 7, s);
-    launch_rows_local(P, B, g, s);
+    launch_rows_local(P, B, io, s);
     mark(marks, 8, s);
     return hipGetLastError();
 }

@@ -320,6 +320,9 @@ struct Partition {
         B = ExecBuffers{};
         A = Arena{};
     }
+    Partition() = default;
+    Partition(const Partition&) = delete;             // owns device memory
+    Partition& operator=(const Partition&) = delete;
     ~Partition() { release(); }
 };
 
@@ -490,6 +493,7 @@ static void fill_params(PlanDev& P, int nu, double eps, const nuht_opts& o)
     phase_offset(anu, P.phi_hi, P.phi_lo);
     P.kappa_max = P.w * M_PI / 4.0 * (1.0 + 1e-9);
     P.n_eshat = 30;
+    P.spread_chunk = o.spread_chunk > 0 ? o.spread_chunk : kSpreadChunk;
     // the Chebyshev series depends only on the kernel width (beta follows w)
     static std::mutex mu;
     static double cache[32][32];
@@ -502,95 +506,119 @@ static void fill_params(PlanDev& P, int nu, double eps, const nuht_opts& o)
     for (int i = 0; i < P.n_eshat; ++i) P.eshat[i] = cache[P.w][i];
 }
 
-static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int nu, hipStream_t s)
+// Building a partition takes two steps around one host synchronisation:
+// part_begin fills the parameters, allocates the planning tables (with the
+// current capacity guesses), launches the planning kernels and queues the copy
+// of the summary and the input-check flag into a pinned slot; after the caller
+// has synchronised, part_finish reads the slot and either asks for another
+// attempt with larger tables or allocates the execution buffers.
+struct PendingPart {
+    Partition* Pt = nullptr;
+    const Geometry* G = nullptr;
+    hipStream_t s = nullptr;
+    int32_t cap = 0, icap = 0;
+    int attempt = 0;
+    Arena A{};
+    Partition tmp;   // the current attempt's tables
+    PendingPart() = default;
+    PendingPart(const PendingPart&) = delete;
+    PendingPart& operator=(const PendingPart&) = delete;
+};
+
+static int part_begin(nuht_plan_t pl, PendingPart& pp, Partition& Pt, const Geometry& G, int nu, hipStream_t s,
+                      HostStage* h, bool first)
 {
-    Pt.release();
-    Pt.stream = s;
-    const nuht_opts& o = pl->opts;
     PlanDev& P = Pt.P;
-    P = PlanDev{};
-    fill_params(P, nu, pl->eps, o);
-    if (P.L < 0) return NUHT_EINVAL;
-    P.n = G.n; P.m = G.m;
-    P.rs = G.rs; P.ws = G.ws; P.perm_r = G.perm_r; P.perm_w = G.perm_w;
-    Pt.sum = Summary{};
+    if (first) {
+        Pt.release();
+        Pt.stream = s;
+        P = PlanDev{};
+        fill_params(P, nu, pl->eps, pl->opts);
+        if (P.L < 0) return NUHT_EINVAL;
+        P.n = G.n; P.m = G.m;
+        P.rs = G.rs; P.ws = G.ws; P.perm_r = G.perm_r; P.perm_w = G.perm_w;
+        Pt.sum = Summary{};
+        pp.tmp.release();
+        pp.attempt = 0;
+        pp.Pt = &Pt; pp.G = &G; pp.s = s;
+        int64_t tot = (int64_t)G.n + G.m;
+        pp.cap = (int32_t)std::min<int64_t>(tot / 32 + 4096, 1 << 28);
+        pp.icap = (int32_t)std::min<int64_t>(64 * (tot / P.spread_chunk) + 2 * (int64_t)pp.cap, 1 << 28);
+    }
     if (G.n == 0 || G.m == 0) {
-        std::unique_lock<std::mutex> lock;
-        HostStage* h = host_stage(lock);
-        if (!h) return NUHT_ENOMEM;
         HIP_TRY(hipMemcpyAsync(&h->flag, pl->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (h->flag) return NUHT_EDOMAIN;
-        Pt.built = true;
         return NUHT_OK;
     }
-
+    const nuht_opts& o = pl->opts;
     int64_t min_size = o.min_size > 0 ? o.min_size : 1024;
     int ncand = o.split_candidates > 1 ? o.split_candidates : 16;
     int dft_max = o.dft_max == 0 ? 48 : o.dft_max;
     const double sigma = 2.0;
+    pp.tmp.release();
+    pp.tmp.stream = s;
+    Arena& A = pp.A;
+    A = Arena{};
+    A.node_cap = pp.cap; A.l_cap = pp.cap; A.a_cap = pp.cap; A.d_cap = 2 * pp.cap; A.q_cap = pp.cap;
+    A.litem_cap = pp.icap; A.aitem_cap = pp.icap;
+    int32_t *K = nullptr, *Jc = nullptr, *a_cells = nullptr;
+    Slab slab;
+    slab.add(K, (size_t)G.m);
+    slab.add(Jc, (size_t)G.n);
+    slab.add(a_cells, (size_t)A.aitem_cap);
+    slab.add(A.nodes, (size_t)A.node_cap);
+    slab.add(A.lb, (size_t)A.l_cap);
+    slab.add(A.ab, (size_t)A.a_cap);
+    slab.add(A.db, (size_t)A.d_cap);
+    slab.add(A.q0, (size_t)A.q_cap);
+    slab.add(A.q1, (size_t)A.q_cap);
+    slab.add(A.litems, (size_t)A.litem_cap);
+    slab.add(A.aitems, (size_t)A.aitem_cap);
+    slab.add(A.fft_list, (size_t)A.a_cap);
+    slab.add(A.gslot, (size_t)A.a_cap + 1);
+    NUHT_TRY(slab.commit(pp.tmp));
+    P.nodes = A.nodes; P.lb = A.lb; P.ab = A.ab; P.db = A.db;
+    P.litems = A.litems; P.aitems = A.aitems; P.fft_list = A.fft_list; P.gslot = A.gslot;
+    HIP_TRY(hipMemsetAsync(pl->d_sum, 0, sizeof(Summary), s));
+    HIP_TRY(launch_planning(P, A, K, Jc, a_cells, min_size, ncand, dft_max, sigma, pl->d_sum, s));
+    HIP_TRY(hipMemcpyAsync(&h->sum, pl->d_sum, sizeof(Summary), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&h->flag, pl->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    return NUHT_OK;
+}
 
-    int64_t tot = (int64_t)G.n + G.m;
-    int32_t cap = (int32_t)std::min<int64_t>(tot / 32 + 4096, 1 << 28);
-    int32_t icap = (int32_t)std::min<int64_t>(64 * (tot / kSpreadChunk) + 2 * (int64_t)cap, 1 << 28);
-    Summary& S = Pt.sum;
-    for (int attempt = 0; attempt < 6; ++attempt) {
-        Partition tmp;   // this attempt's tables; dropped on a retry
-        tmp.stream = s;
-        Arena A{};
-        A.node_cap = cap; A.l_cap = cap; A.a_cap = cap; A.d_cap = 2 * cap; A.q_cap = cap;
-        A.litem_cap = icap; A.aitem_cap = icap;
-        int32_t *K = nullptr, *Jc = nullptr, *a_cells = nullptr;
-        Slab slab;
-        slab.add(K, (size_t)G.m);
-        slab.add(Jc, (size_t)G.n);
-        slab.add(a_cells, (size_t)A.aitem_cap);
-        slab.add(A.nodes, (size_t)A.node_cap);
-        slab.add(A.lb, (size_t)A.l_cap);
-        slab.add(A.ab, (size_t)A.a_cap);
-        slab.add(A.db, (size_t)A.d_cap);
-        slab.add(A.q0, (size_t)A.q_cap);
-        slab.add(A.q1, (size_t)A.q_cap);
-        slab.add(A.litems, (size_t)A.litem_cap);
-        slab.add(A.aitems, (size_t)A.aitem_cap);
-        slab.add(A.fft_list, (size_t)A.a_cap);
-        slab.add(A.gslot, (size_t)A.a_cap + 1);
-        NUHT_TRY(slab.commit(tmp));
-        P.nodes = A.nodes; P.lb = A.lb; P.ab = A.ab; P.db = A.db;
-        P.litems = A.litems; P.aitems = A.aitems; P.fft_list = A.fft_list; P.gslot = A.gslot;
-        HIP_TRY(hipMemsetAsync(pl->d_sum, 0, sizeof(Summary), s));
-        HIP_TRY(launch_planning(P, A, K, Jc, a_cells, min_size, ncand, dft_max, sigma, pl->d_sum, s));
-        int32_t flag = 0;
-        {
-            std::unique_lock<std::mutex> lock;
-            HostStage* h = host_stage(lock);
-            if (!h) return NUHT_ENOMEM;
-            HIP_TRY(hipMemcpyAsync(&h->sum, pl->d_sum, sizeof(Summary), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(&h->flag, pl->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            S = h->sum;
-            flag = h->flag;
-        }
-        if (flag) return NUHT_EDOMAIN;
-        if (S.overflow == 2) return NUHT_ECAPACITY;   // subdivision deeper than kMaxLevels
-        if (S.grid_error) return NUHT_ECAPACITY;
-        if (S.overflow) {
-            int64_t need = std::max<int64_t>({(int64_t)S.n_nodes, (int64_t)S.n_l, (int64_t)S.n_a, (int64_t)S.n_d / 2});
-            if (need >= cap) cap = (int32_t)std::min<int64_t>(2 * need + 1024, 1 << 29);
-            int64_t ineed = std::max<int64_t>((int64_t)S.n_litems, (int64_t)S.n_aitems);
-            if (ineed >= icap) icap = (int32_t)std::min<int64_t>(2 * ineed + 1024, 1 << 29);
-            if (need < cap && ineed < icap) { cap *= 2; icap *= 2; }
-            continue;
-        }
-        // keep this attempt's tables
-        for (auto& b : tmp.bufs) Pt.bufs.push_back(b);
-        Pt.bytes += tmp.bytes;
-        tmp.bufs.clear();
-        tmp.bytes = 0;
-        Pt.A = A;
-        break;
+// After the synchronisation.  *again is set when the tables overflowed and
+// part_begin must run once more (with first = false).
+static int part_finish(PendingPart& pp, const HostStage* h, bool* again)
+{
+    *again = false;
+    Partition& Pt = *pp.Pt;
+    const Geometry& G = *pp.G;
+    PlanDev& P = Pt.P;
+    hipStream_t s = pp.s;
+    if (h->flag) return NUHT_EDOMAIN;
+    if (G.n == 0 || G.m == 0) {
+        Pt.built = true;
+        return NUHT_OK;
     }
-    if (S.overflow) return NUHT_ECAPACITY;
+    Summary& S = Pt.sum;
+    S = h->sum;
+    if (S.overflow == 2) return NUHT_ECAPACITY;   // subdivision deeper than kMaxLevels
+    if (S.grid_error) return NUHT_ECAPACITY;
+    if (S.overflow) {
+        if (++pp.attempt >= 6) return NUHT_ECAPACITY;
+        int64_t need = std::max<int64_t>({(int64_t)S.n_nodes, (int64_t)S.n_l, (int64_t)S.n_a, (int64_t)S.n_d / 2});
+        if (need >= pp.cap) pp.cap = (int32_t)std::min<int64_t>(2 * need + 1024, 1 << 29);
+        int64_t ineed = std::max<int64_t>((int64_t)S.n_litems, (int64_t)S.n_aitems);
+        if (ineed >= pp.icap) pp.icap = (int32_t)std::min<int64_t>(2 * ineed + 1024, 1 << 29);
+        if (need < pp.cap && ineed < pp.icap) { pp.cap *= 2; pp.icap *= 2; }
+        *again = true;
+        return NUHT_OK;
+    }
+    // keep this attempt's tables
+    for (auto& b : pp.tmp.bufs) Pt.bufs.push_back(b);
+    Pt.bytes += pp.tmp.bytes;
+    pp.tmp.bufs.clear();
+    pp.tmp.bytes = 0;
+    Pt.A = pp.A;
     P.n_nodes = S.n_nodes; P.n_l = S.n_l; P.n_a = S.n_a; P.n_d = S.n_d;
     P.n_litems = S.n_litems; P.n_aitems = S.n_aitems;
 
@@ -622,6 +650,25 @@ static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int
     P.es_poly = B.es_poly;
     Pt.built = true;
     return NUHT_OK;
+}
+
+// Both steps with the process-wide pinned slot; synchronises `s` once per
+// attempt (once unless the capacity guesses were too small).
+static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int nu, hipStream_t s)
+{
+    PendingPart pp;
+    bool first = true;
+    for (;;) {
+        std::unique_lock<std::mutex> lock;
+        HostStage* h = host_stage(lock);
+        if (!h) return NUHT_ENOMEM;
+        NUHT_TRY(part_begin(pl, pp, Pt, G, nu, s, h, first));
+        first = false;
+        HIP_TRY(hipStreamSynchronize(s));
+        bool again = false;
+        NUHT_TRY(part_finish(pp, h, &again));
+        if (!again) return NUHT_OK;
+    }
 }
 
 static void free_plan(nuht_plan_t p)
@@ -685,8 +732,11 @@ static const Partition* current_forward(nuht_plan_t p)
 
 static int run(nuht_plan_t p, const Partition& Pt, const double* in, double* out, bool scale, hipStream_t s)
 {
-    HIP_TRY(launch_execute(Pt.P, Pt.sum, Pt.B, Pt.cls.data(), (int)Pt.cls.size(), in, out, scale, s,
-                           prof_marks(p)));
+    IoArgs io;
+    io.c = in;
+    io.g = out;
+    io.scale_by_points = scale;
+    HIP_TRY(launch_execute(Pt.P, Pt.sum, Pt.B, Pt.cls.data(), (int)Pt.cls.size(), io, s, prof_marks(p)));
     return NUHT_OK;
 }
 
@@ -713,21 +763,27 @@ const char* nuht_strerror(int code)
     }
 }
 
-int nuht_plan(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_dev, int64_t m,
-              const double* omega_dev, const nuht_opts* opts, void* stream)
+// Validated options of a plan call.
+static int check_opts(const nuht_opts* opts, nuht_opts& o)
 {
-    if (!out) return NUHT_EINVAL;
-    *out = nullptr;
-    if (!valid_common(nu, eps)) return NUHT_EINVAL;
-    if (n < 0 || m < 0 || n > INT32_MAX / 2 || m > INT32_MAX / 2) return NUHT_EINVAL;
-    if ((n > 0 && !r_dev) || (m > 0 && !omega_dev)) return NUHT_EINVAL;
-    nuht_opts o{};
+    o = nuht_opts{};
     if (opts) o = *opts;
     if (o.precision != NUHT_FP64 && o.precision != NUHT_FP32_SPREAD) return NUHT_EINVAL;
     if (o.precision == NUHT_FP32_SPREAD) return NUHT_EPRECISION;   // FP64 path only in this build
     if (o.min_size < 0 || o.M_override < 0 || o.M_override > 20 || o.split_candidates < 0) return NUHT_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
+    if (o.spread_chunk != 0 && (o.spread_chunk < 64 || o.spread_chunk > 16384)) return NUHT_EINVAL;
+    return NUHT_OK;
+}
 
+// A plan with its geometry: storage allocated, input check and sort launched
+// on `s` (no partition yet, no synchronisation).
+static int plan_create(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_dev, int64_t m,
+                       const double* omega_dev, const nuht_opts& o, hipStream_t s)
+{
+    *out = nullptr;
+    if (!valid_common(nu, eps)) return NUHT_EINVAL;
+    if (n < 0 || m < 0 || n > INT32_MAX / 2 || m > INT32_MAX / 2) return NUHT_EINVAL;
+    if ((n > 0 && !r_dev) || (m > 0 && !omega_dev)) return NUHT_EINVAL;
     nuht_plan_s* p = new (std::nothrow) nuht_plan_s();
     if (!p) return NUHT_ENOMEM;
     p->nu_req = nu; p->eps = eps; p->opts = o; p->n = n; p->m = m;
@@ -761,12 +817,28 @@ int nuht_plan(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_d
     p->adj.n = (int32_t)m; p->adj.m = (int32_t)n;
     p->adj.rs = p->fwd.ws; p->adj.ws = p->fwd.rs;
     p->adj.perm_r = p->fwd.perm_w; p->adj.perm_w = p->fwd.perm_r;
+    *out = p;
+    return NUHT_OK;
+}
+
+int nuht_plan(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_dev, int64_t m,
+              const double* omega_dev, const nuht_opts* opts, void* stream)
+{
+    if (!out) return NUHT_EINVAL;
+    *out = nullptr;
+    nuht_opts o;
+    NUHT_TRY(check_opts(opts, o));
+    hipStream_t s = (hipStream_t)stream;
+    nuht_plan_t p = nullptr;
+    NUHT_TRY(plan_create(&p, nu, eps, n, r_dev, m, omega_dev, o, s));
     // the one synchronisation of the plan happens inside (it also reads the
     // input check's flag)
-    p->nu_req = nu;
     Partition* Pt = nullptr;
     int rc = get_partition(p, nu, false, s, &Pt);
-    if (rc != NUHT_OK) return fail(rc);
+    if (rc != NUHT_OK) {
+        free_plan(p);
+        return rc;
+    }
     *out = p;
     return NUHT_OK;
 }
@@ -844,6 +916,353 @@ int nuht_plan_set_order(nuht_plan_t p, int nu, void* stream)
     return rc;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuning: the spreading work-item size (points per item), the direct-block
+// threshold min_size and the direct-sum/FFT threshold dft_max, by coordinate
+// descent over a few candidates each, every candidate planned on the plan's
+// own sorted geometry and timed over `reps` executes (after one warm-up) with
+// HIP events on `s`.
+// ---------------------------------------------------------------------------
+static int tune_plan(nuht_plan_t p, const double* c_dev, int reps, nuht_opts* best, double* best_ms, hipStream_t s)
+{
+    if (reps < 1) reps = 3;
+    DevBuf ones, out;
+    if (!c_dev && p->n > 0) {
+        NUHT_TRY(dev_alloc(ones, sizeof(double) * (size_t)p->n, s));
+        HIP_TRY(launch_fill((double*)ones.p, p->n, 1.0, s));
+        c_dev = (const double*)ones.p;
+    }
+    if (p->m > 0) NUHT_TRY(dev_alloc(out, sizeof(double) * (size_t)p->m, s));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const nuht_opts saved = p->opts;
+    nuht_opts cur = saved;
+    if (cur.spread_chunk == 0) cur.spread_chunk = kSpreadChunk;
+    if (cur.min_size == 0) cur.min_size = 1024;
+    if (cur.dft_max == 0) cur.dft_max = 48;
+    int rc = NUHT_OK;
+    auto time_opts = [&](const nuht_opts& o, double* ms) -> int {
+        p->opts = o;
+        Partition T;
+        int r = build_partition(p, T, p->fwd, p->nu_req, s);
+        if (r != NUHT_OK) return r;
+        IoArgs io;
+        io.c = c_dev;
+        io.g = (double*)out.p;
+        HIP_TRY(launch_execute(T.P, T.sum, T.B, T.cls.data(), (int)T.cls.size(), io, s, nullptr));
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int k = 0; k < reps; ++k)
+            HIP_TRY(launch_execute(T.P, T.sum, T.B, T.cls.data(), (int)T.cls.size(), io, s, nullptr));
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        *ms = (double)t / reps;
+        return NUHT_OK;
+    };
+    double cur_ms = 0.0;
+    rc = time_opts(cur, &cur_ms);
+    const int chunks[] = {512, 1024, 2048, 4096};
+    const int64_t sizes[] = {256, 1024, 4096, 16384};
+    const int dfts[] = {24, 48, 96};
+    for (int param = 0; param < 3 && rc == NUHT_OK; ++param) {
+        int ncand = param == 0 ? 4 : (param == 1 ? 4 : 3);
+        for (int q = 0; q < ncand && rc == NUHT_OK; ++q) {
+            nuht_opts o = cur;
+            if (param == 0) { if (o.spread_chunk == chunks[q]) continue; o.spread_chunk = chunks[q]; }
+            if (param == 1) { if (o.min_size == sizes[q]) continue; o.min_size = sizes[q]; }
+            if (param == 2) { if (o.dft_max == dfts[q]) continue; o.dft_max = dfts[q]; }
+            double ms = 0.0;
+            rc = time_opts(o, &ms);
+            if (rc == NUHT_OK && ms < cur_ms) { cur = o; cur_ms = ms; }
+        }
+    }
+    p->opts = saved;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dev_free(ones);
+    dev_free(out);
+    if (rc != NUHT_OK) return rc;
+    cur.tune = 0;
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    return NUHT_OK;
+}
+
+int nuht_tune(nuht_plan_t p, const double* c_dev, int reps, nuht_opts* best, double* best_ms, void* stream)
+{
+    if (!p || !best || !current_forward(p)) return NUHT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    nuht_opts o;
+    NUHT_TRY(tune_plan(p, c_dev, reps, &o, best_ms, s));
+    // adopt the best options: the plan's partitions are rebuilt with them
+    o.precision = p->opts.precision;
+    o.M_override = p->opts.M_override;
+    o.split_candidates = p->opts.split_candidates;
+    p->opts = o;
+    p->orders.clear();
+    Partition* Pt = nullptr;
+    NUHT_TRY(get_partition(p, p->nu_req, false, s, &Pt));
+    *best = o;
+    return NUHT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches: many independent plans, planned with one synchronisation and
+// executed as one captured graph.
+// ---------------------------------------------------------------------------
+constexpr int kBatchStreams = 4;
+
+struct nuht_batch_s {
+    std::vector<nuht_plan_t> plans;
+    std::vector<int> stream_of;          // stream index of each transform
+    std::vector<int> order;              // transforms by decreasing n + m
+    hipStream_t aux[kBatchStreams] = {};
+    hipStream_t cap = nullptr;           // capture and replay stream
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, fork = nullptr, join[kBatchStreams] = {};
+    DevBuf b_ptrs;                       // device tables of input and output pointers
+    void** c_table = nullptr;
+    void** g_table = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<nuht_opts> class_opts;   // tuned options per size class (when tuned)
+};
+
+static void free_batch(nuht_batch_t b)
+{
+    if (!b) return;
+    for (hipStream_t st : b->aux) if (st) (void)hipStreamSynchronize(st);
+    if (b->cap) (void)hipStreamSynchronize(b->cap);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (nuht_plan_t p : b->plans) free_plan(p);   // stream-ordered frees on the batch's streams
+    dev_free(b->b_ptrs);
+    for (hipStream_t st : b->aux) if (st) (void)hipStreamSynchronize(st);
+    if (b->cap) (void)hipStreamSynchronize(b->cap);
+    for (hipStream_t st : b->aux) if (st) (void)hipStreamDestroy(st);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (hipEvent_t e : b->join) if (e) (void)hipEventDestroy(e);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    delete b;
+}
+
+// size class of a transform for tuning: floor(log10(n + m)), 0 .. 9
+static int size_class(int64_t tot)
+{
+    int c = 0;
+    while (tot >= 10 && c < 9) { tot /= 10; ++c; }
+    return c;
+}
+
+int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, const int64_t* n,
+                   const double* const* r_dev, const int64_t* m, const double* const* omega_dev,
+                   const nuht_opts* opts, void* stream)
+{
+    if (!out) return NUHT_EINVAL;
+    *out = nullptr;
+    if (count < 0 || count > (1 << 20)) return NUHT_EINVAL;
+    if (count > 0 && (!nu || !n || !r_dev || !m || !omega_dev)) return NUHT_EINVAL;
+    nuht_opts o;
+    NUHT_TRY(check_opts(opts, o));
+    for (int i = 0; i < count; ++i) {
+        if (!valid_common(nu[i], eps)) return NUHT_EINVAL;
+        if (n[i] < 0 || m[i] < 0 || n[i] > INT32_MAX / 2 || m[i] > INT32_MAX / 2) return NUHT_EINVAL;
+        if ((n[i] > 0 && !r_dev[i]) || (m[i] > 0 && !omega_dev[i])) return NUHT_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    nuht_batch_s* b = new (std::nothrow) nuht_batch_s();
+    if (!b) return NUHT_ENOMEM;
+    auto fail = [&](int code) { free_batch(b); return code; };
+    auto hip_ok = [](hipError_t e) { if (e != hipSuccess) { (void)hipGetLastError(); return false; } return true; };
+    for (int k = 0; k < kBatchStreams; ++k) {
+        if (!hip_ok(hipStreamCreateWithFlags(&b->aux[k], hipStreamNonBlocking))) return fail(NUHT_EHIP);
+        if (!hip_ok(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming))) return fail(NUHT_EHIP);
+    }
+    if (!hip_ok(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking))) return fail(NUHT_EHIP);
+    if (!hip_ok(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming))) return fail(NUHT_EHIP);
+    if (!hip_ok(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming))) return fail(NUHT_EHIP);
+    if (!hip_ok(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming))) return fail(NUHT_EHIP);
+    // the inputs are ready once the caller's stream reaches this point
+    if (!hip_ok(hipEventRecord(b->ev_in, s))) return fail(NUHT_EHIP);
+    for (int k = 0; k < kBatchStreams; ++k)
+        if (!hip_ok(hipStreamWaitEvent(b->aux[k], b->ev_in, 0))) return fail(NUHT_EHIP);
+    // longest-processing-time assignment of the transforms to the streams
+    b->order.resize(count);
+    for (int i = 0; i < count; ++i) b->order[i] = i;
+    std::sort(b->order.begin(), b->order.end(), [&](int x, int y) { return n[x] + m[x] > n[y] + m[y]; });
+    b->stream_of.assign(count, 0);
+    {
+        int64_t load[kBatchStreams] = {};
+        for (int t : b->order) {
+            int k = (int)(std::min_element(load, load + kBatchStreams) - load);
+            b->stream_of[t] = k;
+            load[k] += n[t] + m[t] + 20000;   // a fixed cost per transform for its launches
+        }
+    }
+    b->plans.assign(count, nullptr);
+    for (int i = 0; i < count; ++i) {
+        int rc = plan_create(&b->plans[i], nu[i], eps, n[i], r_dev[i], m[i], omega_dev[i], o,
+                             b->aux[b->stream_of[i]]);
+        if (rc != NUHT_OK) return fail(rc);
+    }
+    if (o.tune) {
+        // one representative (the largest) per size class is tuned; its options
+        // serve the whole class
+        b->class_opts.assign(10, o);
+        std::vector<int> rep(10, -1);
+        for (int t : b->order) {
+            int c = size_class(n[t] + m[t]);
+            if (rep[c] < 0) rep[c] = t;
+        }
+        for (int c = 0; c < 10; ++c) {
+            if (rep[c] < 0) continue;
+            nuht_plan_t p = b->plans[rep[c]];
+            hipStream_t st = b->aux[b->stream_of[rep[c]]];
+            Partition* Pt = nullptr;
+            int rc = get_partition(p, p->nu_req, false, st, &Pt);
+            if (rc != NUHT_OK) return fail(rc);
+            nuht_opts best;
+            rc = tune_plan(p, nullptr, 3, &best, nullptr, st);
+            if (rc != NUHT_OK) return fail(rc);
+            best.precision = o.precision; best.M_override = o.M_override;
+            best.split_candidates = o.split_candidates;
+            b->class_opts[c] = best;
+        }
+        for (int i = 0; i < count; ++i) {
+            nuht_plan_t p = b->plans[i];
+            p->opts = b->class_opts[size_class(n[i] + m[i])];
+            p->orders.clear();
+        }
+    }
+    // every partition's planning launched, then one synchronisation
+    HostStage* slots = nullptr;
+    if (count > 0 && !hip_ok(hipHostMalloc((void**)&slots, sizeof(HostStage) * (size_t)count, hipHostMallocPortable)))
+        return fail(NUHT_ENOMEM);
+    std::vector<std::unique_ptr<PendingPart>> pend(count);
+    std::vector<Partition*> parts(count, nullptr);
+    int rc = NUHT_OK;
+    for (int i = 0; i < count && rc == NUHT_OK; ++i) {
+        nuht_plan_t p = b->plans[i];
+        nuht_plan_s::OrderParts* op = order_parts(p, p->nu_req);
+        if (!op) { rc = NUHT_ENOMEM; break; }
+        parts[i] = &op->f;
+        pend[i].reset(new (std::nothrow) PendingPart());
+        if (!pend[i]) { rc = NUHT_ENOMEM; break; }
+        rc = part_begin(p, *pend[i], *parts[i], p->fwd, p->nu_req, b->aux[b->stream_of[i]], &slots[i], true);
+    }
+    for (int k = 0; k < kBatchStreams && rc == NUHT_OK; ++k)
+        if (!hip_ok(hipStreamSynchronize(b->aux[k]))) rc = NUHT_EHIP;
+    for (int i = 0; i < count && rc == NUHT_OK; ++i) {
+        bool again = false;
+        rc = part_finish(*pend[i], &slots[i], &again);
+        while (rc == NUHT_OK && again) {   // tables too small: this one again, on its own
+            hipStream_t st = b->aux[b->stream_of[i]];
+            rc = part_begin(b->plans[i], *pend[i], *parts[i], b->plans[i]->fwd, b->plans[i]->nu_req, st,
+                            &slots[i], false);
+            if (rc == NUHT_OK && !hip_ok(hipStreamSynchronize(st))) rc = NUHT_EHIP;
+            if (rc == NUHT_OK) rc = part_finish(*pend[i], &slots[i], &again);
+        }
+    }
+    pend.clear();
+    if (slots) (void)hipHostFree(slots);
+    if (rc != NUHT_OK) return fail(rc);
+    // pointer tables for the graph
+    if (count > 0) {
+        Slab slab;
+        slab.add(b->c_table, (size_t)count);
+        slab.add(b->g_table, (size_t)count);
+        if (slab.commit(b->b_ptrs, b->cap) != NUHT_OK) return fail(NUHT_ENOMEM);
+    }
+    for (int k = 0; k < kBatchStreams; ++k)
+        if (!hip_ok(hipStreamSynchronize(b->aux[k]))) return fail(NUHT_EHIP);
+    if (!hip_ok(hipStreamSynchronize(b->cap))) return fail(NUHT_EHIP);
+    *out = b;
+    return NUHT_OK;
+}
+
+// Captures every transform's execution into one graph: the transforms run on
+// the batch's streams (largest first, balanced), forked from and joined back
+// into the capture stream; inputs and outputs come from the pointer tables.
+static int capture_batch(nuht_batch_t b)
+{
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return NUHT_EHIP;
+    }
+    hipError_t e = hipEventRecord(b->fork, b->cap);
+    for (int k = 0; k < kBatchStreams && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->aux[k], b->fork, 0);
+    for (size_t q = 0; q < b->order.size() && e == hipSuccess; ++q) {
+        int t = b->order[q];
+        const Partition* Pt = current_forward(b->plans[t]);
+        if (!Pt) { e = hipErrorInvalidValue; break; }
+        IoArgs io;
+        io.c_slot = (const double* const*)(b->c_table + t);
+        io.g_slot = (double* const*)(b->g_table + t);
+        e = launch_execute(Pt->P, Pt->sum, Pt->B, Pt->cls.data(), (int)Pt->cls.size(), io, b->aux[b->stream_of[t]],
+                           nullptr);
+    }
+    for (int k = 0; k < kBatchStreams && e == hipSuccess; ++k) {
+        e = hipEventRecord(b->join[k], b->aux[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->join[k], 0);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        return NUHT_EHIP;
+    }
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphDestroy(g);
+        return NUHT_EHIP;
+    }
+    b->graph = g;
+    b->exec = x;
+    return NUHT_OK;
+}
+
+int nuht_execute_many(nuht_batch_t b, const double* const* c_dev, double* const* g_dev, void* stream)
+{
+    if (!b) return NUHT_EINVAL;
+    const int count = (int)b->plans.size();
+    if (count == 0) return NUHT_OK;
+    if (!c_dev || !g_dev) return NUHT_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        if (b->plans[i]->n > 0 && !c_dev[i]) return NUHT_EINVAL;
+        if (b->plans[i]->m > 0 && !g_dev[i]) return NUHT_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!b->exec) NUHT_TRY(capture_batch(b));
+    HIP_TRY(hipEventRecord(b->ev_in, s));
+    HIP_TRY(hipStreamWaitEvent(b->cap, b->ev_in, 0));
+    for (int off = 0; off < count; off += 224) {
+        int cnt = std::min(224, count - off);
+        HIP_TRY(launch_set_pointers(b->c_table + off, (const void* const*)(c_dev + off), cnt, b->cap));
+        HIP_TRY(launch_set_pointers(b->g_table + off, (const void* const*)(g_dev + off), cnt, b->cap));
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, b->cap));
+    HIP_TRY(hipEventRecord(b->ev_out, b->cap));
+    HIP_TRY(hipStreamWaitEvent(s, b->ev_out, 0));
+    return NUHT_OK;
+}
+
+int nuht_batch_info(nuht_batch_t b, int index, nuht_info* info)
+{
+    if (!b || index < 0 || index >= (int)b->plans.size()) return NUHT_EINVAL;
+    return nuht_plan_info(b->plans[index], info);
+}
+
+int nuht_batch_destroy(nuht_batch_t b)
+{
+    free_batch(b);
+    return NUHT_OK;
+}
+
 int nuht_plan_info(nuht_plan_t p, nuht_info* info)
 {
     if (!p || !info) return NUHT_EINVAL;
@@ -865,6 +1284,9 @@ int nuht_plan_info(nuht_plan_t p, nuht_info* info)
     int64_t bytes = p->geom_bytes + (int64_t)p->b_grad.bytes;
     for (auto& o : p->orders) bytes += o->f.bytes + o->a.bytes;
     info->workspace_bytes = bytes;
+    info->min_size = p->opts.min_size > 0 ? p->opts.min_size : 1024;
+    info->dft_max = p->opts.dft_max == 0 ? 48 : p->opts.dft_max;
+    info->spread_chunk = P.spread_chunk;
     return NUHT_OK;
 }
 

@@ -13,7 +13,7 @@ namespace nuht {
 constexpr int kMaxChannels = 40;       // 2M with M <= 20 (eq. num-asy-terms caps M at 20)
 constexpr int kMaxFftLog2 = 26;        // largest FFT of an asymptotic block: 2^26 points
 constexpr int kLocalChunk = 4096;      // columns per local-moment work item
-constexpr int kSpreadChunk = 1024;     // points per spreading work item
+constexpr int kSpreadChunk = 1024;     // default points per spreading work item (a plan option)
 constexpr int kMaxEsWidth = 18;        // largest ES kernel width
 constexpr int kEsDeg = 16;             // degree of the per-cell polynomial pieces of the ES kernel
 constexpr int kMaxLevels = 4096;       // subdivision depth limit
@@ -97,7 +97,7 @@ struct PlanDev {
     double hank[2 * 20 + 2];         // a_p(nu), p = 0 .. 2M+1 (Hankel coefficients)
     double chan[kMaxChannels];       // channel factors (-1)^(p/2) a_p(nu) for p < 2M (odd p carry a factor i), 0 above
     double eshat[32];                // Chebyshev coefficients of ES^ on [0, kappa_max]
-    int32_t n_eshat, pad0;
+    int32_t n_eshat, spread_chunk;   // Chebyshev terms of ES^; points per spreading work item
     double kappa_max;
     const double* rs;                // sorted points (n)
     const double* ws;                // sorted frequencies (m)

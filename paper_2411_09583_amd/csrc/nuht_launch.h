@@ -59,12 +59,29 @@ struct FftClass {
 // Execution stages, timed between consecutive events of `marks` (kStages + 1
 // events, or null).
 constexpr int kStages = 8;   // gather, local moments, spread, grid assembly, FFT, direct, asymptotic rows, local rows
+// Input and output of one transform.  When the slots are set, the kernels
+// read the input and output pointers from those device locations at run time
+// (so a captured graph serves any buffers); otherwise c and g are used.  With
+// scale_by_points the input is multiplied by the geometry's sorted point
+// coordinates as it is gathered (r c for the forward geometry, omega y for
+// the transposed one).
+struct IoArgs {
+    const double* c = nullptr;
+    double* g = nullptr;
+    const double* const* c_slot = nullptr;
+    double* const* g_slot = nullptr;
+    bool scale_by_points = false;
+};
+
 // One transform with the plan's partition: out = A in (or A^T in on the
-// transposed geometry).  With scale_by_points, the input is multiplied by the
-// geometry's sorted point coordinates as it is gathered (r c for the forward
-// geometry, omega y for the transposed one).
+// transposed geometry).
 hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers& B, const FftClass* cls, int ncls,
-                          const double* c, double* g, bool scale_by_points, hipStream_t s, hipEvent_t* marks);
+                          const IoArgs& io, hipStream_t s, hipEvent_t* marks);
+// x[i] = v
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
+// table[i] = ptrs[i] for i < count (count <= 224): fills a device pointer table
+// from kernel arguments
+hipError_t launch_set_pointers(void** table, const void* const* ptrs, int count, hipStream_t s);
 // out[i] = w[i] (a[i] - b[i]) / 2
 hipError_t launch_half_difference(const double* w, const double* a, const double* b, double* out, int32_t n,
                                   hipStream_t s);

@@ -390,7 +390,7 @@ __global__ void k_block_params(PlanDev P, Arena A, int32_t dft_max, double sigma
             }
             B.fft = fft; B.N2 = N2;
             int32_t ncol = B.k1 - B.k0 + 1;
-            B.nitems = (ncol + kSpreadChunk - 1) / kSpreadChunk;
+            B.nitems = (ncol + P.spread_chunk - 1) / P.spread_chunk;
             A.ab[b] = B;
         }
         if (b < n_l) {
@@ -550,8 +550,8 @@ __global__ void k_items(PlanDev P, Arena A, Summary* __restrict__ sum, int32_t* 
             }
             const ABlock B = A.ab[lo];
             int32_t it = ia - B.item0;
-            int32_t ka = B.k0 + it * kSpreadChunk;
-            int32_t kb = ka + kSpreadChunk - 1;
+            int32_t ka = B.k0 + it * P.spread_chunk;
+            int32_t kb = ka + P.spread_chunk - 1;
             if (kb > B.k1) kb = B.k1;
             int32_t lhi = B.llo + B.N1 - 1;
             double u0 = (P.rs[ka] - B.C) / B.h, u1 = (P.rs[kb] - B.C) / B.h;

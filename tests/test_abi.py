@@ -59,3 +59,35 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     assert lib.nuht_adjoint(None, None, None, None) == -1
     assert lib.nuht_destroy(None) == 0
     assert lib.nuht_direct(0, 1e-12, 5, None, None, 5, None, None, None) == -1
+
+
+def test_new_entry_points_reject_invalid_arguments_without_gpu(lib):
+    import paper_2411_09583_amd as nuht
+    h = ctypes.c_void_p()
+    # gradient, tuning and batches on a null plan / batch
+    assert lib.nuht_gradient(None, None, None, None, None, None, None) == -1
+    best = nuht.NuhtOpts()
+    assert lib.nuht_tune(None, None, 3, ctypes.byref(best), None, None) == -1
+    assert lib.nuht_execute_many(None, None, None, None) == -1
+    assert lib.nuht_batch_info(None, 0, None) == -1
+    assert lib.nuht_batch_destroy(None) == 0
+    assert lib.nuht_plan_set_order(None, 1, None) == -1
+    # batch arguments are validated before anything is created
+    many = lib.nuht_plan_many
+    one = lambda t, v: (t * 1)(v)
+    assert many(None, 0, None, 1e-12, None, None, None, None, None, None) == -1
+    assert many(ctypes.byref(h), -1, None, 1e-12, None, None, None, None, None, None) == -1
+    assert many(ctypes.byref(h), 1, None, 1e-12, None, None, None, None, None, None) == -1     # null arrays
+    vp = ctypes.c_void_p
+    nu = one(ctypes.c_int, 200)                                                                 # |nu| > 100
+    n = one(ctypes.c_int64, 0)
+    m = one(ctypes.c_int64, 0)
+    r = (vp * 1)(None)
+    w = (vp * 1)(None)
+    assert many(ctypes.byref(h), 1, nu, 1e-12, n, r, m, w, None, None) == -1
+    nu = one(ctypes.c_int, 0)
+    n = one(ctypes.c_int64, 5)                                                                  # null r with n > 0
+    assert many(ctypes.byref(h), 1, nu, 1e-12, n, r, m, w, None, None) == -1
+    o = nuht.NuhtOpts(0, 0, 0, 0, 0, 17, 0)                                                     # spread_chunk < 64
+    n = one(ctypes.c_int64, 0)
+    assert many(ctypes.byref(h), 1, nu, 1e-12, n, r, m, w, ctypes.byref(o), None) == -1
