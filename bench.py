@@ -83,6 +83,128 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": x.numel() * 8, "copies": 3}), flush=True)
 
 
+def bench_batched(torch, nuht, workloads, dev):
+    """256 independent transforms (nu ~ U{0..63}, n and m log-uniform in
+    [1e3, 1e6], omega ~ U[0, n_i), eps = 1e-12): a loop of plan + execute per
+    transform on one stream against one nuht_plan_many and graph replays of
+    nuht_execute_many."""
+    tr = workloads.batch(count=256, seed=5)
+    rs = [torch.as_tensor(t["r"], device=dev) for t in tr]
+    ws = [torch.as_tensor(t["w"], device=dev) for t in tr]
+    cs = [torch.as_tensor(t["c"], device=dev) for t in tr]
+    nus = [t["nu"] for t in tr]
+    total = sum(t["r"].size + t["w"].size for t in tr)
+    torch.cuda.synchronize()
+    log(f"batched: {len(tr)} transforms, sum(n+m) = {total:.3e}")
+
+    def looped():
+        outs = []
+        for r, w, c, nu in zip(rs, ws, cs, nus):
+            p = nuht.Plan(r, w, nu, EPS)
+            outs.append(p.execute(c))
+            p.close()
+        return outs
+
+    looped()                                   # warm-up (allocator pools, code objects)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    outs_loop = looped()
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - a
+    # execute-only loop with the plans kept
+    plans = [nuht.Plan(r, w, nu, EPS) for r, w, nu in zip(rs, ws, nus)]
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for p, c in zip(plans, cs):
+        p.execute(c)
+    torch.cuda.synchronize()
+    t_loop_exec = time.perf_counter() - a
+    for p in plans:
+        p.close()
+    del plans
+    a = time.perf_counter()
+    b = nuht.Batch(rs, ws, nus, EPS)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - a
+    gs = [torch.empty(w.numel(), dtype=torch.float64, device=dev) for w in ws]
+    b.execute(cs, gs)                          # first call captures the graph
+    torch.cuda.synchronize()
+    reps = 5
+    a = time.perf_counter()
+    for _ in range(reps):
+        b.execute(cs, gs)
+    torch.cuda.synchronize()
+    t_exec = (time.perf_counter() - a) / reps
+    same = all(torch.equal(x, y) for x, y in zip(gs, outs_loop))
+    b.close()
+    res = dict(transforms=len(tr), sum_n_plus_m=total,
+               looped_ms=1e3 * t_loop, looped_execute_ms=1e3 * t_loop_exec,
+               batched_plan_ms=1e3 * t_plan, batched_execute_ms=1e3 * t_exec,
+               batched_ms=1e3 * (t_plan + t_exec),
+               speedup_plan_and_execute=t_loop / (t_plan + t_exec),
+               speedup_execute=t_loop_exec / t_exec,
+               batched_rate=total / (t_plan + t_exec), batched_execute_rate=total / t_exec,
+               identical_to_looped=bool(same))
+    log("batched:", json.dumps(res))
+    return res
+
+
+def bench_fwd_bwd(torch, nuht, workloads, dev):
+    """n = m = 1e6, nu = 5, loss 0.5 |g - y|^2: forward plus the gradient in c,
+    r and omega (one plan; orders 4, 5, 6 on its sorted geometry) against six
+    independent transforms (forward and transposed at nu, transposed and
+    forward at nu -+ 1), each planned on its own."""
+    r, w, c, y = (torch.as_tensor(a, device=dev) for a in workloads.differentiation(seed=6))
+    nu = 5
+    torch.cuda.synchronize()
+
+    def fused():
+        p = nuht.Plan(r, w, nu, EPS)
+        g = p.execute(c)
+        grads = p.gradient(c, g - y)
+        return p, grads
+
+    p, _ = fused()                               # warm-up
+    p.close()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    p, _ = fused()
+    torch.cuda.synchronize()
+    t_cold = time.perf_counter() - a
+    reps = 3
+    a = time.perf_counter()
+    for _ in range(reps):
+        g = p.execute(c)
+        p.gradient(c, g - y)
+    torch.cuda.synchronize()
+    t_warm = (time.perf_counter() - a) / reps
+    p.close()
+
+    def independent():
+        gbar = None
+        for order, transposed, scale in ((nu, False, None), (nu, True, None), (nu - 1, True, "w"),
+                                         (nu + 1, True, "w"), (nu - 1, False, "r"), (nu + 1, False, "r")):
+            q = nuht.Plan(r, w, order, EPS)
+            if not transposed:
+                out = q.execute(c * r if scale == "r" else c)
+                if gbar is None:
+                    gbar = out - y
+            else:
+                out = q.adjoint(gbar * w if scale == "w" else gbar)
+            q.close()
+
+    independent()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    independent()
+    torch.cuda.synchronize()
+    t_ind = time.perf_counter() - a
+    res = dict(n=r.numel(), m=w.numel(), nu=nu, fused_cold_ms=1e3 * t_cold, fused_warm_ms=1e3 * t_warm,
+               independent_ms=1e3 * t_ind, speedup_cold=t_ind / t_cold, speedup_warm=t_ind / t_warm)
+    log("fwd+bwd:", json.dumps(res))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,7 +213,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="outputs of the nu=0 transform computed by the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-looped comparison")
+    ap.add_argument("--no-grad", action="store_true", help="skip the forward+backward comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 64 MiB device-to-device copy three times (a known byte count "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -217,19 +340,11 @@ def main():
                     flops_per_step=fl, launches_per_step=len(ORDERS),
                     ms_per_step={k: stage_ms[k] for k in kern})
 
-    # accuracy on sampled outputs (outside the timed region)
-    accuracy = None
-    if not args.no_check:
-        from oracle import direct as odirect
-        r, w, c = (t.cpu().numpy() for t in inputs[0])
-        g = outs[0].cpu().numpy()
-        idx = np.random.default_rng(99).choice(M_OUT, 64, replace=False)
-        ref = odirect.dht(0, r, c, w[idx])
-        accuracy = dict(nu=0, sampled_outputs=64,
-                        rel_l2=float(np.linalg.norm(g[idx] - ref) / np.linalg.norm(ref)))
-        log("accuracy", accuracy)
-
+    # CPU baseline: the oracle's direct sum, on all host cores, for a sample of
+    # the nu = 0 outputs (all 1e6 points each), extrapolated to the whole
+    # transform.  The same oracle values give the GPU output's error there.
     cpu = None
+    accuracy = None
     if not args.no_cpu_baseline:
         from oracle import direct as odirect
         r, w, c = (t.cpu().numpy() for t in inputs[0])
@@ -237,13 +352,21 @@ def main():
         idx = np.random.default_rng(7).choice(M_OUT, k, replace=False)
         threads = odirect.max_threads()
         a = time.perf_counter()
-        odirect.dht(0, r, c, w[idx], nthreads=threads)
+        ref = odirect.dht(0, r, c, w[idx], nthreads=threads)
         b = time.perf_counter()
         full_s = (b - a) * M_OUT / k
         cpu = dict(value=(N + M_OUT) / full_s, unit="(n+m)/s", cores=threads, kind="oracle",
                    sample=f"direct sum for {k} of the 1e6 outputs (all 1e6 points, nu=0), "
                           f"{b - a:.1f} s, extrapolated to the full transform")
         log("cpu baseline", cpu)
+        g = outs[0].cpu().numpy()[idx]
+        accuracy = dict(nu=0, sampled_outputs=k,
+                        rel_l2=float(np.linalg.norm(g - ref) / np.linalg.norm(ref)),
+                        rel_max=float(np.max(np.abs(g - ref)) / np.max(np.abs(ref))))
+        log("accuracy", accuracy)
+
+    batched = None if args.no_batched else bench_batched(torch, nuht, workloads, dev)
+    fwd_bwd = None if args.no_grad else bench_fwd_bwd(torch, nuht, workloads, dev)
 
     out = {
         "metric": "(n+m)/s at eps=1e-12 vs direct sum; batched and fwd+bwd speedup, HBM GB/s",
@@ -267,6 +390,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": accuracy,
+        "batched": batched,
+        "fwd_bwd": fwd_bwd,
     }
     print(json.dumps(out), flush=True)
 
