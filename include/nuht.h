@@ -45,7 +45,7 @@ extern "C" {
 
 /* Precision of the NUFFT spreading and interpolation. */
 #define NUHT_FP64        0
-#define NUHT_FP32_SPREAD 1    /* FP32 grids and kernel taps; phases stay FP64; eps >= 1e-7 */
+#define NUHT_FP32_SPREAD 1    /* FP32 spreading; eps >= 1e-7 (see nuht_opts) */
 
 typedef struct nuht_plan_s *nuht_plan_t;
 
@@ -56,7 +56,13 @@ typedef struct nuht_plan_s *nuht_plan_t;
  *                     paper's default, Sec. 4.1).
  *   M_override        number of asymptotic terms M (0 -> eq. num-asy-terms).
  *   split_candidates  equispaced candidate rows in SplitIndices (0 -> 16).
- *   precision         NUHT_FP64 or NUHT_FP32_SPREAD.
+ *   precision         NUHT_FP64, or NUHT_FP32_SPREAD: the ES spreading of
+ *                     the asymptotic blocks (step one of the type-3 NUFFTs,
+ *                     Sec. 3.2) keeps its weights, kernel values and channel
+ *                     sums in FP32 and uses a kernel one point narrower;
+ *                     positions and phases stay double-double, grids are
+ *                     assembled in FP64 and every other step is FP64.  Allowed
+ *                     for eps >= 1e-7 (else NUHT_EPRECISION).
  *   dft_max           asymptotic blocks whose spread grid has at most this
  *                     many cells are evaluated by a direct sum over the grid
  *                     instead of an FFT and interpolation (0 -> built-in default,

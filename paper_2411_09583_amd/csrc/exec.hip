@@ -155,15 +155,20 @@ __global__ void k_lmom_reduce(PlanDev P, const double* __restrict__ lpart, doubl
 // ---------------------------------------------------------------------------
 constexpr int kSpreadSub = 256;
 
-template <int NCH>
+// T is the type of the weights, kernel values and channel sums: double, or
+// float in the FP32-spreading mode (positions and phases stay double-double
+// either way); partials are stored as the matching two-component vector.
+template <int NCH, typename T>
 __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restrict__ cs,
-                                                const double* __restrict__ es_poly, double2* __restrict__ part)
+                                                const double* __restrict__ es_poly, double2* __restrict__ part_raw)
 {
+    using T2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
+    T2* part = reinterpret_cast<T2*>(part_raw);
     __shared__ int32_t s_l0[kSpreadSub];
-    __shared__ double s_wr[kSpreadSub];
-    __shared__ double s_wi[kSpreadSub];
-    __shared__ double s_q[kSpreadSub];
-    __shared__ double s_k[kSpreadSub * kMaxEsWidth];
+    __shared__ T s_wr[kSpreadSub];
+    __shared__ T s_wi[kSpreadSub];
+    __shared__ T s_q[kSpreadSub];
+    __shared__ T s_k[kSpreadSub * kMaxEsWidth];
     const Item I = P.aitems[blockIdx.x];
     const ABlock B = P.ab[I.blk];
     const int tid = threadIdx.x;
@@ -178,9 +183,9 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
         const int cell = cbase + tid / slices;
         const int sl = tid & (slices - 1);
         const int l = I.sub_lo + cell;
-        double ar[NCH], ai[NCH];
+        T ar[NCH], ai[NCH];
         #pragma unroll
-        for (int p = 0; p < NCH; ++p) { ar[p] = 0.0; ai[p] = 0.0; }
+        for (int p = 0; p < NCH; ++p) { ar[p] = T(0); ai[p] = T(0); }
         for (int k0 = I.ka; k0 < I.kb; k0 += kSpreadSub) {
             const int np = (I.kb - k0) < kSpreadSub ? (I.kb - k0) : kSpreadSub;
             __syncthreads();
@@ -198,9 +203,9 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
                 double q = B.r0 / r;
                 double w0 = c * sqrt(q);
                 if (own) {
-                    s_wr[tid] = w0 * cth;
-                    s_wi[tid] = w0 * sth;
-                    s_q[tid] = q;
+                    s_wr[tid] = (T)(w0 * cth);
+                    s_wi[tid] = (T)(w0 * sth);
+                    s_q[tid] = (T)q;
                 }
                 // u - w/2 = (tp.hi + tp.lo)/h - w/2 (scaling by h exact)
                 dd a = two_sum(tp.hi * inv_h, -hw);
@@ -217,13 +222,13 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
                 spow[0] = 1.0;
                 #pragma unroll
                 for (int d = 1; d <= kEsDeg; ++d) spow[d] = spow[d - 1] * sv;
-                double* kv = s_k + tid * w;
+                T* kv = s_k + tid * w;
                 for (int t = 0; t < w; ++t) {
                     const double* cf = es_poly + t * (kEsDeg + 1);
                     double v = cf[0];
                     #pragma unroll
                     for (int d = 1; d <= kEsDeg; ++d) v = __builtin_fma(cf[d], spow[d], v);
-                    if (own) kv[t] = v;
+                    if (own) kv[t] = (T)v;
                 }
             }
             __syncthreads();
@@ -236,9 +241,9 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
                 while (lo < hi) { int mid = (lo + hi) >> 1; if (s_l0[mid] <= l) lo = mid + 1; else hi = mid; }
                 int last = lo;
                 for (int i = first + sl; i < last; i += slices) {
-                    double phi = s_k[i * w + (l - s_l0[i])];
-                    double vr = phi * s_wr[i], vi = phi * s_wi[i];
-                    double q = s_q[i];
+                    T phi = s_k[i * w + (l - s_l0[i])];
+                    T vr = phi * s_wr[i], vi = phi * s_wi[i];
+                    T q = s_q[i];
                     #pragma unroll
                     for (int p = 0; p < NCH; ++p) {
                         ar[p] += vr;
@@ -257,9 +262,9 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
             }
         }
         if (cell < sub_n && sl == 0) {
-            double2* dst = part + I.off + (int64_t)cell * NCH;
+            T2* dst = part + I.off + (int64_t)cell * NCH;
             #pragma unroll
-            for (int p = 0; p < NCH; ++p) dst[p] = make_double2(ar[p], ai[p]);
+            for (int p = 0; p < NCH; ++p) { dst[p].x = ar[p]; dst[p].y = ai[p]; }
         }
     }
 }
@@ -275,6 +280,17 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
 // type-2 step) and placed at FFT index l mod N2, channel-major [channel][N2];
 // all other FFT inputs are zero.
 // ---------------------------------------------------------------------------
+// Partial i: double2, or float2 in the FP32-spreading mode (widened here, so
+// the grids are assembled in FP64).
+__device__ __forceinline__ double2 load_partial(const PlanDev& P, const double2* __restrict__ part, int64_t i)
+{
+    if (P.fp32) {
+        float2 f = reinterpret_cast<const float2*>(part)[i];
+        return make_double2((double)f.x, (double)f.y);
+    }
+    return part[i];
+}
+
 __global__ void k_spread_reduce(PlanDev P, const double2* __restrict__ part, double2* __restrict__ grids,
                                 int64_t total_slots)
 {
@@ -326,14 +342,14 @@ __global__ void k_spread_reduce(PlanDev P, const double2* __restrict__ part, dou
             #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const Item& I = P.aitems[it + q];
-                v[q] = part[I.off + (int64_t)(l - I.sub_lo) * nch + p];
+                v[q] = load_partial(P, part, I.off + (int64_t)(l - I.sub_lo) * nch + p);
             }
             #pragma unroll
             for (int q = 0; q < 4; ++q) { sr += v[q].x; si += v[q].y; }
         }
         for (; it < b; ++it) {
             const Item& I = P.aitems[it];
-            double2 v = part[I.off + (int64_t)(l - I.sub_lo) * nch + p];
+            double2 v = load_partial(P, part, I.off + (int64_t)(l - I.sub_lo) * nch + p);
             sr += v.x;
             si += v.y;
         }
@@ -795,7 +811,12 @@ template <int NCH>
 static void launch_spread(const PlanDev& P, const Summary& S, const ExecBuffers& B, hipStream_t s)
 {
     if (S.n_aitems > 0)
-        hipLaunchKernelGGL(k_spread<NCH>, dim3(S.n_aitems), dim3(256), 0, s, P, B.cs, B.es_poly, B.part);
+    {
+        if (P.fp32)
+            hipLaunchKernelGGL((k_spread<NCH, float>), dim3(S.n_aitems), dim3(256), 0, s, P, B.cs, B.es_poly, B.part);
+        else
+            hipLaunchKernelGGL((k_spread<NCH, double>), dim3(S.n_aitems), dim3(256), 0, s, P, B.cs, B.es_poly, B.part);
+    }
 }
 
 template <int NCH>

@@ -486,6 +486,7 @@ static void fill_params(PlanDev& P, int nu, double eps, const nuht_opts& o)
     P.z = crossover(anu, eps, M);
     P.L = local_rank(anu, eps, P.z);
     P.w = es_width(eps, o.precision);
+    P.fp32 = o.precision == NUHT_FP32_SPREAD ? 1 : 0;
     P.beta = es_beta(P.w);
     for (int p = 0; p < 2 * M + 2; ++p) P.hank[p] = hankel_coef(anu, p);
     for (int p = 0; p < kMaxChannels; ++p)
@@ -769,7 +770,7 @@ static int check_opts(const nuht_opts* opts, nuht_opts& o)
     o = nuht_opts{};
     if (opts) o = *opts;
     if (o.precision != NUHT_FP64 && o.precision != NUHT_FP32_SPREAD) return NUHT_EINVAL;
-    if (o.precision == NUHT_FP32_SPREAD) return NUHT_EPRECISION;   // FP64 path only in this build
+
     if (o.min_size < 0 || o.M_override < 0 || o.M_override > 20 || o.split_candidates < 0) return NUHT_EINVAL;
     if (o.spread_chunk != 0 && (o.spread_chunk < 64 || o.spread_chunk > 16384)) return NUHT_EINVAL;
     return NUHT_OK;
@@ -782,6 +783,7 @@ static int plan_create(nuht_plan_t* out, int nu, double eps, int64_t n, const do
 {
     *out = nullptr;
     if (!valid_common(nu, eps)) return NUHT_EINVAL;
+    if (o.precision == NUHT_FP32_SPREAD && eps < 1e-7) return NUHT_EPRECISION;
     if (n < 0 || m < 0 || n > INT32_MAX / 2 || m > INT32_MAX / 2) return NUHT_EINVAL;
     if ((n > 0 && !r_dev) || (m > 0 && !omega_dev)) return NUHT_EINVAL;
     nuht_plan_s* p = new (std::nothrow) nuht_plan_s();
@@ -1067,6 +1069,7 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
     if (count > 0 && (!nu || !n || !r_dev || !m || !omega_dev)) return NUHT_EINVAL;
     nuht_opts o;
     NUHT_TRY(check_opts(opts, o));
+    if (o.precision == NUHT_FP32_SPREAD && eps < 1e-7) return NUHT_EPRECISION;
     for (int i = 0; i < count; ++i) {
         if (!valid_common(nu[i], eps)) return NUHT_EINVAL;
         if (n[i] < 0 || m[i] < 0 || n[i] > INT32_MAX / 2 || m[i] > INT32_MAX / 2) return NUHT_EINVAL;

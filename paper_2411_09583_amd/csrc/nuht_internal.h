@@ -92,6 +92,7 @@ struct Summary {
 struct PlanDev {
     int32_t n, m, nu, M, L, w;       // sizes, |order|, terms, local rank, ES width
     int32_t nch, sign;               // channels (2M padded to a kernel instance); (-1)^nu for negative orders, else 1
+    int32_t fp32, pad_fp;            // FP32 spreading (weights, kernel values and channel sums in float)
     double z, beta, eps;
     double phi_hi, phi_lo;           // -(2nu+1) pi/4 reduced to [0, 2pi), double-double
     double hank[2 * 20 + 2];         // a_p(nu), p = 0 .. 2M+1 (Hankel coefficients)

@@ -52,7 +52,8 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     assert plan(ctypes.byref(h), 0, 1e-12, 10, None, 10, None, None, None) == -1      # null with n > 0
     assert plan(None, 0, 1e-12, 0, None, 0, None, None, None) == -1
     o = nuht.NuhtOpts(0, 0, 0, nuht.NUHT_FP32_SPREAD, 0)
-    assert plan(ctypes.byref(h), 0, 1e-12, 0, None, 0, None, ctypes.byref(o), None) == -3
+    assert plan(ctypes.byref(h), 0, 1e-12, 0, None, 0, None, ctypes.byref(o), None) == -3   # FP32 below 1e-7
+    assert plan(ctypes.byref(h), 0, 1e-8, 0, None, 0, None, ctypes.byref(o), None) == -3
     o = nuht.NuhtOpts(0, 21, 0, 0, 0)                                                 # M > 20
     assert plan(ctypes.byref(h), 0, 1e-12, 0, None, 0, None, ctypes.byref(o), None) == -1
     assert lib.nuht_execute(None, None, None, None) == -1

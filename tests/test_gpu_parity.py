@@ -97,6 +97,39 @@ def test_orders(nuht, nu):
     assert rel_max(g, g1) <= TOL
 
 
+@pytest.mark.parametrize("nu", [0, 1, 10])
+def test_fp32_spreading(nuht, nu):
+    # eps = 1e-6 with FP32 spreading.  As at 1e-12 (high orders), the paper's
+    # parameters leave the method's own truncation at up to ~1.2 eps in max
+    # norm (the method-exact reference gives 1.16e-6 at nu = 10 here), so the
+    # bar is: rel-l2 <= eps against the direct sum, every entry within
+    # eps |c|_1, and the error added by the FP32 spreading, measured against
+    # the method-exact reference, <= eps / 5.
+    eps = 1e-6
+    r, w, c = workloads.uniform(4000, 3500, 1.0, 3000.0, seed=50 + nu)
+    g32, info = run(nuht, nu, eps, r, c, w, precision=nuht.NUHT_FP32_SPREAD)
+    g64, info64 = run(nuht, nu, eps, r, c, w)
+    g1 = direct.dht(nu, r, c, w)
+    g2 = method.nufht_reference(nu, eps, r, c, w)
+    print("fp32", nu, rel_l2(g32, g1), rel_max(g32, g1), rel_l2(g32, g2), rel_max(g32, g2),
+          "fp64", rel_l2(g64, g1), rel_l2(g64, g2), info["es_width"])
+    assert info["es_width"] == info64["es_width"] - 1
+    assert rel_l2(g32, g1) <= eps and np.max(np.abs(g32 - g1)) <= eps * np.sum(np.abs(c))
+    assert rel_l2(g32, g2) <= eps / 5 and rel_max(g32, g2) <= eps / 5
+    assert rel_l2(g64, g1) <= eps
+
+
+def test_fp32_spreading_full_size_sampled(nuht):
+    # n = m = 1e6 at eps = 1e-6, FP32 spreading, nu = 0 and 10, 200 sampled outputs
+    for nu, seed in ((0, 2), (10, 4)):
+        r, w, c = workloads.large_uniform(seed=seed)
+        g, _ = run(nuht, nu, 1e-6, r, c, w, precision=nuht.NUHT_FP32_SPREAD)
+        idx = np.random.default_rng(51).choice(w.size, 200, replace=False)
+        g1 = direct.dht(nu, r, c, w[idx])
+        print("fp32 full", nu, rel_l2(g[idx], g1), rel_max(g[idx], g1))
+        assert rel_l2(g[idx], g1) <= 1e-6
+
+
 @pytest.mark.parametrize("nu", [25, 63, 100])
 def test_high_orders(nuht, nu):
     # 2M = 18, 32, 40 channels: padded and largest kernel instances; long local
