@@ -280,17 +280,16 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
 // type-2 step) and placed at FFT index l mod N2, channel-major [channel][N2];
 // all other FFT inputs are zero.
 // ---------------------------------------------------------------------------
-// Partial i: double2, or float2 in the FP32-spreading mode (widened here, so
-// the grids are assembled in FP64).
-__device__ __forceinline__ double2 load_partial(const PlanDev& P, const double2* __restrict__ part, int64_t i)
+// Partial i as double2: PT is double2, or float2 in the FP32-spreading mode
+// (widened here, so the grids are assembled in FP64).
+template <typename PT>
+__device__ __forceinline__ double2 load_partial(const double2* __restrict__ part, int64_t i)
 {
-    if (P.fp32) {
-        float2 f = reinterpret_cast<const float2*>(part)[i];
-        return make_double2((double)f.x, (double)f.y);
-    }
-    return part[i];
+    PT v = reinterpret_cast<const PT*>(part)[i];
+    return make_double2((double)v.x, (double)v.y);
 }
 
+template <typename PT>
 __global__ void k_spread_reduce(PlanDev P, const double2* __restrict__ part, double2* __restrict__ grids,
                                 int64_t total_slots)
 {
@@ -342,14 +341,14 @@ __global__ void k_spread_reduce(PlanDev P, const double2* __restrict__ part, dou
             #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const Item& I = P.aitems[it + q];
-                v[q] = load_partial(P, part, I.off + (int64_t)(l - I.sub_lo) * nch + p);
+                v[q] = load_partial<PT>(part, I.off + (int64_t)(l - I.sub_lo) * nch + p);
             }
             #pragma unroll
             for (int q = 0; q < 4; ++q) { sr += v[q].x; si += v[q].y; }
         }
         for (; it < b; ++it) {
             const Item& I = P.aitems[it];
-            double2 v = load_partial(P, part, I.off + (int64_t)(l - I.sub_lo) * nch + p);
+            double2 v = load_partial<PT>(part, I.off + (int64_t)(l - I.sub_lo) * nch + p);
             sr += v.x;
             si += v.y;
         }
@@ -899,8 +898,14 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
     dispatch_channels(P.nch, [&](auto k) { launch_spread<decltype(k)::value>(P, S, B, s); });
     mark(marks, 3, s);
     if (B.grid_cells > 0)
-        hipLaunchKernelGGL(k_spread_reduce, dim3(cdiv64(B.grid_cells * P.nch, 256)), dim3(256), 0, s, P, B.part,
-                           B.grids, B.grid_cells);
+    {
+        if (P.fp32)
+            hipLaunchKernelGGL(k_spread_reduce<float2>, dim3(cdiv64(B.grid_cells * P.nch, 256)), dim3(256), 0, s, P,
+                               B.part, B.grids, B.grid_cells);
+        else
+            hipLaunchKernelGGL(k_spread_reduce<double2>, dim3(cdiv64(B.grid_cells * P.nch, 256)), dim3(256), 0, s, P,
+                               B.part, B.grids, B.grid_cells);
+    }
     mark(marks, 4, s);
     for (int q = 0; q < ncls; ++q) {
         const FftClass& C = cls[q];

@@ -220,6 +220,30 @@ static const double* es_pieces_cached(int w, double beta)
     return table[w];
 }
 
+// The pieces of width w on the current device: uploaded once per device and
+// width and kept until the process ends (w x (kEsDeg + 1) doubles each).
+static const double* es_pieces_device(int w, double beta)
+{
+    static std::mutex mu;
+    static const double* table[64][kMaxEsWidth + 1] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) { (void)hipGetLastError(); return nullptr; }
+    const double* host = es_pieces_cached(w, beta);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!table[dev][w]) {
+        void* p = nullptr;
+        size_t bytes = sizeof(double) * (size_t)w * (kEsDeg + 1);
+        if (hipMalloc(&p, bytes) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+        if (hipMemcpy(p, host, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(p);
+            return nullptr;
+        }
+        table[dev][w] = (const double*)p;
+    }
+    return table[dev][w];
+}
+
 // -(2nu+1) pi/4 modulo 2 pi as a double-double in (0, 2 pi].
 static void phase_offset(int nu, double& hi, double& lo)
 {
@@ -594,7 +618,6 @@ static int part_finish(PendingPart& pp, const HostStage* h, bool* again)
     Partition& Pt = *pp.Pt;
     const Geometry& G = *pp.G;
     PlanDev& P = Pt.P;
-    hipStream_t s = pp.s;
     if (h->flag) return NUHT_EDOMAIN;
     if (G.n == 0 || G.m == 0) {
         Pt.built = true;
@@ -644,10 +667,9 @@ static int part_finish(PendingPart& pp, const HostStage* h, bool* again)
         Pt.cls.push_back(fc);
     }
     slab.add(B.scratch, (size_t)scratch);
-    slab.add(B.es_poly, (size_t)P.w * (kEsDeg + 1));
     NUHT_TRY(slab.commit(Pt));
-    HIP_TRY(hipMemcpyAsync(B.es_poly, es_pieces_cached(P.w, P.beta), sizeof(double) * P.w * (kEsDeg + 1),
-                           hipMemcpyHostToDevice, s));
+    B.es_poly = es_pieces_device(P.w, P.beta);
+    if (!B.es_poly) return NUHT_ENOMEM;
     P.es_poly = B.es_poly;
     Pt.built = true;
     return NUHT_OK;

@@ -47,7 +47,7 @@ struct ExecBuffers {
     double2* scratch;   // second buffer of the two-pass FFTs
     double* gd;         // per-row direct-block sums (m)
     double* ga;         // per-row asymptotic sums (m)
-    double* es_poly;    // ES kernel pieces (w x (kEsDeg + 1))
+    const double* es_poly;  // ES kernel pieces (w x (kEsDeg + 1)), shared by all plans on the device
     int64_t grid_cells; // grid slots (without the channel factor)
 };
 

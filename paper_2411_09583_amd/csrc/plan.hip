@@ -233,6 +233,57 @@ __global__ void k_staircase(const double* __restrict__ sorted, int32_t len, cons
 // a local entry, minimal mixed area, ties to the smaller row).  Numbering is
 // deterministic: nodes in level order, children in (parent, position) order.
 // ---------------------------------------------------------------------------
+// The split of one mixed node (Alg. 1) and the classes of its children.
+struct NodeSplit {
+    int32_t js, ks;
+    bool cl, ca, ur_m, ur_d, ll_m, ll_d;
+};
+
+// kj1 = K[R.j1], kj0 = K[R.j0], jc = Jc[R.k0], loaded by the caller.
+__device__ __forceinline__ NodeSplit split_node(const Rect& R, int32_t kj1, int32_t kj0, int32_t jc,
+                                                const int32_t* __restrict__ K, int64_t min_size, int32_t ncand)
+{
+    NodeSplit o;
+    int32_t js = 0, ks = 0;
+    if (kj1 >= R.k1 + 1) {              // wholly local
+        js = R.j1; ks = R.k1;
+    } else if (kj0 <= R.k0) {           // wholly asymptotic
+        js = R.j0 - 1; ks = R.k0 - 1;
+    } else {
+        // the last row holding a local entry: K[j] > k0 <=> j < Jc[k0]
+        int32_t jl = jc - 1;
+        if (jl > R.j1) jl = R.j1;
+        int64_t best = INT64_MAX;
+        int32_t span = jl - R.j0;
+        int32_t nc = span > 0 ? ncand : 1;
+        #pragma unroll 4
+        for (int32_t c = 0; c < nc; ++c) {
+            int32_t j = span > 0 ? R.j0 + (int32_t)(((int64_t)c * span) / (nc - 1)) : R.j0;
+            int32_t k = K[j] - 1;
+            if (k > R.k1) k = R.k1;
+            if (k < R.k0) k = R.k0 - 1;
+            int64_t mixed = (int64_t)(j - R.j0 + 1) * (R.k1 - k) + (int64_t)(R.j1 - j) * (k - R.k0 + 1);
+            if (mixed < best) { best = mixed; js = j; ks = k; }
+        }
+    }
+    o.js = js; o.ks = ks;
+    o.cl = ks >= R.k0 && js >= R.j0;
+    o.ca = js < R.j1 && ks < R.k1;
+    o.ur_m = o.ur_d = o.ll_m = o.ll_d = false;
+    if (ks < R.k1 && js >= R.j0) {
+        if ((int64_t)(js - R.j0 + 1) * (R.k1 - ks) > min_size) o.ur_m = true; else o.ur_d = true;
+    }
+    if (js < R.j1 && ks >= R.k0) {
+        if ((int64_t)(R.j1 - js) * (ks - R.k0 + 1) > min_size) o.ll_m = true; else o.ll_d = true;
+    }
+    return o;
+}
+
+// Nodes per thread per pass.  (Several per thread serialise their candidate
+// loads within the thread, and a pass waits for its slowest thread: one is
+// faster.)
+constexpr int kSubNpt = 1;
+
 __global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ K, const int32_t* __restrict__ Jc,
                                                     int32_t m, int32_t n, int64_t min_size, int32_t ncand, Arena A,
                                                     Summary* __restrict__ sum)
@@ -250,75 +301,73 @@ __global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ 
     while (n_cur > 0) {
         ++level;
         int32_t n_next = 0;
-        for (int32_t c0 = 0; c0 < n_cur; c0 += 1024) {
-            int32_t i = c0 + tid;
-            bool act = i < n_cur;
-            Rect R = act ? cur[i] : Rect{0, -1, 0, -1};
-            int32_t js = 0, ks = 0;
-            int32_t cl = 0, ca = 0, cd = 0, cm = 0;
-            bool ur_m = false, ur_d = false, ll_m = false, ll_d = false;
-            if (act) {
-                if (K[R.j1] >= R.k1 + 1) {          // wholly local
-                    js = R.j1; ks = R.k1;
-                } else if (K[R.j0] <= R.k0) {       // wholly asymptotic
-                    js = R.j0 - 1; ks = R.k0 - 1;
-                } else {
-                    // the last row holding a local entry: K[j] > k0 <=> j < Jc[k0]
-                    int32_t jl = Jc[R.k0] - 1;
-                    if (jl > R.j1) jl = R.j1;
-                    int64_t best = INT64_MAX;
-                    int32_t span = jl - R.j0;
-                    int32_t nc = span > 0 ? ncand : 1;
-                    for (int32_t c = 0; c < nc; ++c) {
-                        int32_t j = span > 0 ? R.j0 + (int32_t)(((int64_t)c * span) / (nc - 1)) : R.j0;
-                        int32_t k = K[j] - 1;
-                        if (k > R.k1) k = R.k1;
-                        if (k < R.k0) k = R.k0 - 1;
-                        int64_t mixed = (int64_t)(j - R.j0 + 1) * (R.k1 - k) + (int64_t)(R.j1 - j) * (k - R.k0 + 1);
-                        if (mixed < best) { best = mixed; js = j; ks = k; }
-                    }
-                }
-                cl = (ks >= R.k0 && js >= R.j0) ? 1 : 0;
-                ca = (js < R.j1 && ks < R.k1) ? 1 : 0;
-                if (ks < R.k1 && js >= R.j0) {
-                    if ((int64_t)(js - R.j0 + 1) * (R.k1 - ks) > min_size) ur_m = true; else ur_d = true;
-                }
-                if (js < R.j1 && ks >= R.k0) {
-                    if ((int64_t)(R.j1 - js) * (ks - R.k0 + 1) > min_size) ll_m = true; else ll_d = true;
-                }
-                cd = (int)ur_d + (int)ll_d;
-                cm = (int)ur_m + (int)ll_m;
+        for (int32_t c0 = 0; c0 < n_cur; c0 += 1024 * kSubNpt) {
+            const int32_t i0 = c0 + tid * kSubNpt;
+            Rect R[kSubNpt];
+            NodeSplit S[kSubNpt];
+            int32_t cnt[4] = {0, 0, 0, 0};
+            int32_t kj1[kSubNpt], kj0[kSubNpt], jc[kSubNpt];
+            #pragma unroll
+            for (int q = 0; q < kSubNpt; ++q) {
+                bool act = i0 + q < n_cur;
+                R[q] = act ? cur[i0 + q] : Rect{0, 0, 0, 0};
             }
-            int32_t v[4] = {cl, ca, cd, cm};
+            #pragma unroll
+            for (int q = 0; q < kSubNpt; ++q) {   // all header loads in flight together
+                kj1[q] = K[R[q].j1];
+                kj0[q] = K[R[q].j0];
+                jc[q] = Jc[R[q].k0];
+            }
+            #pragma unroll
+            for (int q = 0; q < kSubNpt; ++q) {
+                bool act = i0 + q < n_cur;
+                if (act) {
+                    S[q] = split_node(R[q], kj1[q], kj0[q], jc[q], K, min_size, ncand);
+                    cnt[0] += S[q].cl;
+                    cnt[1] += S[q].ca;
+                    cnt[2] += (int)S[q].ur_d + (int)S[q].ll_d;
+                    cnt[3] += (int)S[q].ur_m + (int)S[q].ll_m;
+                }
+            }
+            int32_t v[4] = {cnt[0], cnt[1], cnt[2], cnt[3]};
             int32_t tot[4];
             block_scan<int32_t, 4>(v, tot, wsum);
-            if (act) {
-                int32_t node = n_nodes + i;
-                int32_t li = cl ? n_l + v[0] : -1;
-                int32_t ai = ca ? n_a + v[1] : -1;
-                int32_t d_slot = n_d + v[2];
-                int32_t m_slot = n_next + v[3];
-                int32_t next_base = n_nodes + n_cur;   // first node index of the next level
+            int32_t l_slot = n_l + v[0], a_slot = n_a + v[1], d_slot = n_d + v[2], m_slot = n_next + v[3];
+            const int32_t next_base = n_nodes + n_cur;   // first node index of the next level
+            #pragma unroll
+            for (int q = 0; q < kSubNpt; ++q) {
+                if (i0 + q >= n_cur) continue;
+                const Rect& Rq = R[q];
+                const NodeSplit& o = S[q];
+                int32_t node = n_nodes + i0 + q;
                 Node nd;
-                nd.j0 = R.j0; nd.j1 = R.j1; nd.k0 = R.k0; nd.k1 = R.k1;
-                nd.js = js; nd.ks = ks; nd.lblk = li; nd.ablk = ai;
+                nd.j0 = Rq.j0; nd.j1 = Rq.j1; nd.k0 = Rq.k0; nd.k1 = Rq.k1;
+                nd.js = o.js; nd.ks = o.ks;
+                nd.lblk = o.cl ? l_slot : -1;
+                nd.ablk = o.ca ? a_slot : -1;
                 nd.level = level; nd.pad = 0;
                 nd.ur = -1; nd.ll = -1;
-                if (ur_m) { if (m_slot < A.q_cap) nxt[m_slot] = Rect{R.j0, js, ks + 1, R.k1}; nd.ur = next_base + m_slot; ++m_slot; }
-                if (ur_d) { if (d_slot < A.d_cap) A.db[d_slot] = DBlock{R.j0, js, ks + 1, R.k1}; nd.ur = encode_direct(d_slot); ++d_slot; }
-                if (ll_m) { if (m_slot < A.q_cap) nxt[m_slot] = Rect{js + 1, R.j1, R.k0, ks}; nd.ll = next_base + m_slot; ++m_slot; }
-                if (ll_d) { if (d_slot < A.d_cap) A.db[d_slot] = DBlock{js + 1, R.j1, R.k0, ks}; nd.ll = encode_direct(d_slot); ++d_slot; }
+                if (o.ur_m) { if (m_slot < A.q_cap) nxt[m_slot] = Rect{Rq.j0, o.js, o.ks + 1, Rq.k1}; nd.ur = next_base + m_slot; ++m_slot; }
+                if (o.ur_d) { if (d_slot < A.d_cap) A.db[d_slot] = DBlock{Rq.j0, o.js, o.ks + 1, Rq.k1}; nd.ur = encode_direct(d_slot); ++d_slot; }
+                if (o.ll_m) { if (m_slot < A.q_cap) nxt[m_slot] = Rect{o.js + 1, Rq.j1, Rq.k0, o.ks}; nd.ll = next_base + m_slot; ++m_slot; }
+                if (o.ll_d) { if (d_slot < A.d_cap) A.db[d_slot] = DBlock{o.js + 1, Rq.j1, Rq.k0, o.ks}; nd.ll = encode_direct(d_slot); ++d_slot; }
                 if (node < A.node_cap) A.nodes[node] = nd;
-                if (cl && li < A.l_cap) {
-                    LBlock b;
-                    b.j0 = R.j0; b.j1 = js; b.k0 = R.k0; b.k1 = ks;
-                    b.R = 0.0; b.item0 = 0; b.nitems = 0; b.level = level; b.pad = 0;
-                    A.lb[li] = b;
+                if (o.cl) {
+                    if (l_slot < A.l_cap) {
+                        LBlock b;
+                        b.j0 = Rq.j0; b.j1 = o.js; b.k0 = Rq.k0; b.k1 = o.ks;
+                        b.R = 0.0; b.item0 = 0; b.nitems = 0; b.level = level; b.pad = 0;
+                        A.lb[l_slot] = b;
+                    }
+                    ++l_slot;
                 }
-                if (ca && ai < A.a_cap) {
-                    ABlock b = {};
-                    b.j0 = js + 1; b.j1 = R.j1; b.k0 = ks + 1; b.k1 = R.k1; b.level = level;
-                    A.ab[ai] = b;
+                if (o.ca) {
+                    if (a_slot < A.a_cap) {
+                        ABlock b = {};
+                        b.j0 = o.js + 1; b.j1 = Rq.j1; b.k0 = o.ks + 1; b.k1 = Rq.k1; b.level = level;
+                        A.ab[a_slot] = b;
+                    }
+                    ++a_slot;
                 }
             }
             n_l += tot[0];
