@@ -158,17 +158,30 @@ constexpr int kSpreadSub = 256;
 // T is the type of the weights, kernel values and channel sums: double, or
 // float in the FP32-spreading mode (positions and phases stay double-double
 // either way); partials are stored as the matching two-component vector.
+// One point of a sub-chunk in LDS: weight (real, imaginary), ratio r0 / r and
+// first cell reached, read with two (one for float) 16-byte loads.
+template <typename T>
+struct alignas(16) SpreadPoint {
+    T wr, wi, q;
+    int32_t l0;
+};
+
+// Dynamic LDS of k_spread: kSpreadSub point records, then w kernel values per point.
+template <typename T>
+constexpr size_t spread_lds_bytes(int w)
+{
+    return (size_t)kSpreadSub * (sizeof(SpreadPoint<T>) + (size_t)w * sizeof(T));
+}
+
 template <int NCH, typename T>
 __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restrict__ cs,
                                                 const double* __restrict__ es_poly, double2* __restrict__ part_raw)
 {
     using T2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
     T2* part = reinterpret_cast<T2*>(part_raw);
-    __shared__ int32_t s_l0[kSpreadSub];
-    __shared__ T s_wr[kSpreadSub];
-    __shared__ T s_wi[kSpreadSub];
-    __shared__ T s_q[kSpreadSub];
-    __shared__ T s_k[kSpreadSub * kMaxEsWidth];
+    extern __shared__ double4 spread_lds[];
+    SpreadPoint<T>* s_pt = reinterpret_cast<SpreadPoint<T>*>(spread_lds);
+    T* s_k = reinterpret_cast<T*>(s_pt + kSpreadSub);
     const Item I = P.aitems[blockIdx.x];
     const ABlock B = P.ab[I.blk];
     const int tid = threadIdx.x;
@@ -202,11 +215,6 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
                 cis_dd(ph.hi, __builtin_fma(B.D, tp.lo, ph.lo), cth, sth);
                 double q = B.r0 / r;
                 double w0 = c * sqrt(q);
-                if (own) {
-                    s_wr[tid] = (T)(w0 * cth);
-                    s_wi[tid] = (T)(w0 * sth);
-                    s_q[tid] = (T)q;
-                }
                 // u - w/2 = (tp.hi + tp.lo)/h - w/2 (scaling by h exact)
                 dd a = two_sum(tp.hi * inv_h, -hw);
                 double lo = a.lo + tp.lo * inv_h;
@@ -214,20 +222,32 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
                 double frac = (a.hi - fl) + lo;          // a.hi - fl is exact
                 if (frac < 0.0) { fl -= 1.0; frac += 1.0; }
                 else if (frac >= 1.0) { fl += 1.0; frac -= 1.0; }
-                if (own) s_l0[tid] = (int)fl + 1;
+                if (own) {
+                    SpreadPoint<T> rec;
+                    rec.wr = (T)(w0 * cth);
+                    rec.wi = (T)(w0 * sth);
+                    rec.q = (T)q;
+                    rec.l0 = (int)fl + 1;
+                    s_pt[tid] = rec;
+                }
                 const double sv = 1.0 - 2.0 * frac;      // s = 2 f - 1, f = 1 - frac
-                // powers of s once per point; each piece is then sum_d c_d s^d
-                // with the (scalar) coefficient as a multiplicand
-                double spow[kEsDeg + 1];
+                // powers s^0 .. s^8 once per point; each piece is then
+                // sum_{d<=8} c_d s^d + s^8 sum_{d>8} c_d s^(d-8), with the
+                // (scalar) coefficients as multiplicands
+                constexpr int kHalf = kEsDeg / 2;
+                double spow[kHalf + 1];
                 spow[0] = 1.0;
                 #pragma unroll
-                for (int d = 1; d <= kEsDeg; ++d) spow[d] = spow[d - 1] * sv;
+                for (int d = 1; d <= kHalf; ++d) spow[d] = spow[d - 1] * sv;
                 T* kv = s_k + tid * w;
                 for (int t = 0; t < w; ++t) {
                     const double* cf = es_poly + t * (kEsDeg + 1);
-                    double v = cf[0];
+                    double vlo = cf[0], vhi = cf[kHalf + 1] * spow[1];
                     #pragma unroll
-                    for (int d = 1; d <= kEsDeg; ++d) v = __builtin_fma(cf[d], spow[d], v);
+                    for (int d = 1; d <= kHalf; ++d) vlo = __builtin_fma(cf[d], spow[d], vlo);
+                    #pragma unroll
+                    for (int d = kHalf + 2; d <= kEsDeg; ++d) vhi = __builtin_fma(cf[d], spow[d - kHalf], vhi);
+                    double v = __builtin_fma(spow[kHalf], vhi, vlo);
                     if (own) kv[t] = (T)v;
                 }
             }
@@ -235,15 +255,16 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
             if (cell < sub_n) {
                 // points with l0 in (l - w, l]
                 int lo = 0, hi = np;
-                while (lo < hi) { int mid = (lo + hi) >> 1; if (s_l0[mid] <= l - w) lo = mid + 1; else hi = mid; }
+                while (lo < hi) { int mid = (lo + hi) >> 1; if (s_pt[mid].l0 <= l - w) lo = mid + 1; else hi = mid; }
                 int first = lo;
                 hi = np;
-                while (lo < hi) { int mid = (lo + hi) >> 1; if (s_l0[mid] <= l) lo = mid + 1; else hi = mid; }
+                while (lo < hi) { int mid = (lo + hi) >> 1; if (s_pt[mid].l0 <= l) lo = mid + 1; else hi = mid; }
                 int last = lo;
                 for (int i = first + sl; i < last; i += slices) {
-                    T phi = s_k[i * w + (l - s_l0[i])];
-                    T vr = phi * s_wr[i], vi = phi * s_wi[i];
-                    T q = s_q[i];
+                    const SpreadPoint<T> rec = s_pt[i];
+                    T phi = s_k[i * w + (l - rec.l0)];
+                    T vr = phi * rec.wr, vi = phi * rec.wi;
+                    T q = rec.q;
                     #pragma unroll
                     for (int p = 0; p < NCH; ++p) {
                         ar[p] += vr;
@@ -812,9 +833,11 @@ static void launch_spread(const PlanDev& P, const Summary& S, const ExecBuffers&
     if (S.n_aitems > 0)
     {
         if (P.fp32)
-            hipLaunchKernelGGL((k_spread<NCH, float>), dim3(S.n_aitems), dim3(256), 0, s, P, B.cs, B.es_poly, B.part);
+            hipLaunchKernelGGL((k_spread<NCH, float>), dim3(S.n_aitems), dim3(256), spread_lds_bytes<float>(P.w), s, P,
+                               B.cs, B.es_poly, B.part);
         else
-            hipLaunchKernelGGL((k_spread<NCH, double>), dim3(S.n_aitems), dim3(256), 0, s, P, B.cs, B.es_poly, B.part);
+            hipLaunchKernelGGL((k_spread<NCH, double>), dim3(S.n_aitems), dim3(256), spread_lds_bytes<double>(P.w), s,
+                               P, B.cs, B.es_poly, B.part);
     }
 }
 
