@@ -67,22 +67,36 @@ __global__ void k_half_difference(const double* __restrict__ w, const double* __
 // Local moments t_l = sum_k c_k T_{2l(+1)}(r_k / R) of one chunk of a local
 // block's columns (Sec. 3.1: T^T applied first).  The Chebyshev polynomials
 // come from the recurrence in u = 2y^2 - 1:  T_{2(l+1)+e}(y) = 2u T_{2l+e}(y) - T_{2(l-1)+e}(y).
-// Moments are produced 32 at a time; each thread accumulates in registers and
-// the block reduces.
+// Moments are produced 32 at a time.  One 64-lane wave per item: each lane
+// accumulates its points' moments in registers (points strided over the
+// lanes), and the wave reduces them with cross-lane sums.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_lmom(PlanDev P, const double* __restrict__ cs, double* __restrict__ lpart)
+// One reduce-scatter level: v[0 .. 2H) -> v[0 .. H), lanes with bit H set
+// keeping the upper half; partner lane ^ H holds the other copy.
+template <int H>
+__device__ __forceinline__ void reduce_scatter_half(double (&v)[32], int lane)
 {
-    __shared__ double red[4][32];
+    const bool upper = (lane & H) != 0;
+    #pragma unroll
+    for (int i = 0; i < H; ++i) {
+        double keep = upper ? v[i + H] : v[i];
+        double send = upper ? v[i] : v[i + H];
+        v[i] = keep + __shfl_xor(send, H);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_lmom(PlanDev P, const double* __restrict__ cs, double* __restrict__ lpart)
+{
     const Item I = P.litems[blockIdx.x];
     const LBlock B = P.lb[I.blk];
     const int L = P.L;
     const int odd = P.nu & 1;
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x;
     for (int s0 = 0; s0 <= L; s0 += 32) {
         double acc[32];
         #pragma unroll
         for (int q = 0; q < 32; ++q) acc[q] = 0.0;
-        for (int k = I.ka + tid; k < I.kb; k += 256) {
+        for (int k = I.ka + lane; k < I.kb; k += 64) {
             double y = P.rs[k] / B.R;
             double c = cs[k];
             double u = __builtin_fma(2.0 * y, y, -1.0);
@@ -100,22 +114,18 @@ __global__ __launch_bounds__(256) void k_lmom(PlanDev P, const double* __restric
                 t0 = t1; t1 = t2;
             }
         }
-        #pragma unroll
-        for (int q = 0; q < 32; ++q) {
-            double x = acc[q];
-            for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
-            acc[q] = x;
-        }
-        if ((tid & 63) == 0) {
-            #pragma unroll
-            for (int q = 0; q < 32; ++q) red[tid >> 6][q] = acc[q];
-        }
-        __syncthreads();
-        if (tid < 32 && s0 + tid <= L) {
-            double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-            lpart[(int64_t)blockIdx.x * (L + 1) + s0 + tid] = v;
-        }
-        __syncthreads();
+        // Reduce-scatter over the wave: at offsets 16, 8, 4, 2, 1 each lane
+        // keeps the half of its values that its lane bit selects and adds its
+        // partner's copy of that half; a last exchange at offset 32 completes
+        // the sum.  Lane q (q < 32) then holds moment s0 + q: 32 exchanges
+        // instead of 32 full reductions.
+        reduce_scatter_half<16>(acc, lane);
+        reduce_scatter_half<8>(acc, lane);
+        reduce_scatter_half<4>(acc, lane);
+        reduce_scatter_half<2>(acc, lane);
+        reduce_scatter_half<1>(acc, lane);
+        double mine = acc[0] + __shfl_xor(acc[0], 32);
+        if (lane < 32 && s0 + lane <= L) lpart[(int64_t)blockIdx.x * (L + 1) + s0 + lane] = mine;
     }
 }
 
@@ -618,9 +628,10 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
 // (direct-sum path) or from the FFT by ES interpolation (FFT path).  The grids
 // already hold beta_p b_l^(p), so with gamma = 1/(om r0) each cell (or tap)
 // needs the single value sum_p gamma^p beta_p b_l^(p): two multiply-adds per
-// channel with the powers gamma^p kept in registers (the grid value, when it
-// comes through the scalar unit, is then a multiplicand and needs no copy into
-// vector registers), and one complex product per cell.
+// channel.  On the direct-sum path the powers gamma^p are kept in registers
+// (the grid value, when it comes through the scalar unit, is then a
+// multiplicand and needs no copy into vector registers); on the FFT path the
+// sum is Horner's rule in gamma.  One complex product per cell or tap.
 // Called with a wave-uniform block index whenever every active lane of the
 // wave is in the same block (the usual case, frequencies being sorted); the
 // block's fields and its direct-sum grid are then read through the scalar
@@ -675,14 +686,15 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
             double x = (((double)q - v.hi) - vl) * two_over_w;
             double psi = es_kernel(x, P.beta);
             int qi = q & mask;
-            double2 gv[NCH];
+            // Horner's rule in gamma from the highest channel: the loaded values
+            // (vector registers here) are the addends
+            double2 top = Aq[(int64_t)(NCH - 1) * B.N2 + qi];
+            double br = top.x, bi = top.y;
             #pragma unroll
-            for (int p = 0; p < NCH; ++p) gv[p] = Aq[(int64_t)p * B.N2 + qi];
-            double br = gv[0].x, bi = gv[0].y;
-            #pragma unroll
-            for (int p = 1; p < NCH; ++p) {
-                br = __builtin_fma(gv[p].x, gpow[p], br);
-                bi = __builtin_fma(gv[p].y, gpow[p], bi);
+            for (int p = NCH - 2; p >= 0; --p) {
+                double2 gv = Aq[(int64_t)p * B.N2 + qi];
+                br = __builtin_fma(br, gam, gv.x);
+                bi = __builtin_fma(bi, gam, gv.y);
             }
             ar = __builtin_fma(psi, br, ar);
             ai = __builtin_fma(psi, bi, ai);
@@ -913,7 +925,7 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
                        io.scale_by_points ? P.rs : nullptr, P.n, B.cs);
     mark(marks, 1, s);
     if (S.n_litems > 0) {
-        hipLaunchKernelGGL(k_lmom, dim3(S.n_litems), dim3(256), 0, s, P, B.cs, B.lpart);
+        hipLaunchKernelGGL(k_lmom, dim3(S.n_litems), dim3(64), 0, s, P, B.cs, B.lpart);
         hipLaunchKernelGGL(k_lmom_reduce, dim3(cdiv64((int64_t)S.n_l * (P.L + 1), 256)), dim3(256), 0, s, P,
                            B.lpart, B.lmom);
     }
