@@ -568,55 +568,124 @@ __global__ __launch_bounds__(256) void k_fft_pass_b(PlanDev P, double2* __restri
 // Local block contribution at frequency om:  sum_{l=0}^{L} C_l(om R) t_l with
 //   C_l(x) = delta_l J_{nu/2+l}(x/2) J_{nu/2-l}(x/2)        (nu even, reading x/2)
 //   C_l(x) = 2 J_{(nu+1)/2+l}(x/2) J_{(nu-1)/2-l}(x/2)       (nu odd)
-// J_k(x/2) comes from Miller's backward recurrence.  Every product pairs a low
-// index i with the partner i + nu (orders of opposite sign, J_{-i} = (-1)^i J_i)
-// or nu - i, both produced at most nu steps earlier, so a ring of nu + 1 values
-// per thread (in LDS) suffices; the normalisation J_0^2 + 2 sum J_k^2 = 1 is
-// applied to the finished sum.
+// J_k(y), y = om R / 2, comes from Miller's backward recurrence, started at N
+// and normalised at the end by J_0^2 + 2 sum_k J_k^2 = 1.  Written with
+// J_{-i} = (-1)^i J_i, the sum pairs index i with i + nu (the terms l > a,
+// a = floor(nu/2), sign (-1)^i) and with nu - i (the terms l <= a).
+//   MODE 0 (nu = 0): the products are J_i^2;
+//   MODE 1 (nu = 1): J_i J_{i+1}, i.e. the current and the previous value;
+//   MODE 2 (any nu): partners up to nu steps back, from a ring of nu + 1 values
+//   per thread in LDS.
+// In every mode the recurrence first runs alone down to the highest index a
+// product needs, then continues with the products.
+__device__ __forceinline__ void miller_rescale(double& yk, double& yk1, double& S2, double& dot)
+{
+    if (fabs(yk) > 1e100) { yk *= 1e-100; yk1 *= 1e-100; S2 *= 1e-200; dot *= 1e-200; }
+}
+
+template <int MODE>
 __device__ double local_eval(const PlanDev& P, int lblk, double om, const double* __restrict__ lmom,
                              double* __restrict__ ring, int stride)
 {
     const LBlock B = P.lb[lblk];
     double y = 0.5 * (om * B.R);
     const double* t = lmom + (int64_t)lblk * (P.L + 1);
-    const int nu = P.nu, L = P.L;
-    const int odd = nu & 1;
-    const int a = odd ? (nu - 1) >> 1 : nu >> 1;
+    const int nu = MODE == 0 ? 0 : (MODE == 1 ? 1 : P.nu), L = P.L;
     if (y < 1e-30) return nu == 0 ? t[0] : 0.0;
-    // the pairing below reads J_{nu-i} for i <= nu/2, so the recurrence must
-    // have produced every index up to nu
+    // the pairing reads J_{nu-i} for i <= nu/2, so the recurrence must have
+    // produced every index up to nu
     int N = miller_start(y);
     if (N < nu + 1) N = nu + 1;
-    const int Bsz = nu + 1;
     const double rec = 2.0 / y;
     double yk1 = 0.0, yk = 1e-100, S2 = 0.0, dot = 0.0;
-    int slot = N % Bsz;
-    for (int i = N; i >= 0; --i) {
-        S2 = __builtin_fma(i == 0 ? yk : 2.0 * yk, yk, S2);
-        ring[slot * stride] = yk;
-        int l1 = i + a;
-        if (i >= 1 && l1 <= L && i + nu <= N) {
-            double pv = ring[(slot == 0 ? Bsz - 1 : slot - 1) * stride];
-            double coef = 2.0 * t[l1];
-            dot = __builtin_fma(((i & 1) ? -coef : coef) * yk, pv, dot);
+    if (MODE == 0) {
+        // J_0^2 t_0 + sum_{i=1}^{L} 2 (-1)^i t_i J_i^2
+        int i = N;
+        for (; i > L; --i) {
+            S2 = __builtin_fma(2.0 * yk, yk, S2);
+            double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
+            yk1 = yk; yk = ykm1;
+            miller_rescale(yk, yk1, S2, dot);
         }
-        if (i <= a && a - i <= L) {
-            int l2 = a - i;
-            double pv = ring[((nu - i) % Bsz) * stride];
-            double coef = (!odd && l2 == 0) ? t[0] : 2.0 * t[l2];
-            dot = __builtin_fma(coef * yk, pv, dot);
+        for (; i >= 1; --i) {
+            double q = yk * yk;
+            S2 = __builtin_fma(2.0, q, S2);
+            double c = 2.0 * t[i];
+            dot = __builtin_fma((i & 1) ? -c : c, q, dot);
+            double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
+            yk1 = yk; yk = ykm1;
+            miller_rescale(yk, yk1, S2, dot);
         }
-        if (i == 0) break;
-        double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
-        yk1 = yk;
-        yk = ykm1;
-        slot = slot == 0 ? Bsz - 1 : slot - 1;
-        if (fabs(yk) > 1e100) {
-            yk *= 1e-100; yk1 *= 1e-100; S2 *= 1e-200; dot *= 1e-200;
-            for (int s = 0; s < Bsz; ++s) ring[s * stride] *= 1e-100;
+        S2 = __builtin_fma(yk, yk, S2);
+        dot = __builtin_fma(t[0] * yk, yk, dot);
+        return dot / S2;
+    } else if (MODE == 1) {
+        // 2 t_0 J_0 J_1 + sum_{i=1}^{L} 2 (-1)^i t_i J_i J_{i+1}; yk1 = J_{i+1}
+        int i = N;
+        for (; i > L; --i) {
+            S2 = __builtin_fma(2.0 * yk, yk, S2);
+            double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
+            yk1 = yk; yk = ykm1;
+            miller_rescale(yk, yk1, S2, dot);
         }
+        for (; i >= 1; --i) {
+            S2 = __builtin_fma(2.0 * yk, yk, S2);
+            double c = 2.0 * t[i];
+            dot = __builtin_fma(((i & 1) ? -c : c) * yk, yk1, dot);
+            double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
+            yk1 = yk; yk = ykm1;
+            miller_rescale(yk, yk1, S2, dot);
+        }
+        S2 = __builtin_fma(yk, yk, S2);
+        dot = __builtin_fma(2.0 * t[0] * yk, yk1, dot);
+        return dot / S2;
+    } else {
+        const int odd = nu & 1;
+        const int a = odd ? (nu - 1) >> 1 : nu >> 1;
+        const int Bsz = nu + 1;
+        // indices above top take part in no product (the first pairing needs
+        // i + a <= L, the second i <= a); their values still enter the ring
+        const int top = (L - a) > a ? (L - a) : a;
+        int slot = N % Bsz;
+        int i = N;
+        for (; i > top; --i) {
+            S2 = __builtin_fma(2.0 * yk, yk, S2);
+            ring[slot * stride] = yk;
+            double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
+            yk1 = yk; yk = ykm1;
+            slot = slot == 0 ? Bsz - 1 : slot - 1;
+            if (fabs(yk) > 1e100) {
+                yk *= 1e-100; yk1 *= 1e-100; S2 *= 1e-200; dot *= 1e-200;
+                for (int q = 0; q < Bsz; ++q) ring[q * stride] *= 1e-100;
+            }
+        }
+        for (; i >= 0; --i) {
+            S2 = __builtin_fma(i == 0 ? yk : 2.0 * yk, yk, S2);
+            ring[slot * stride] = yk;
+            int l1 = i + a;
+            if (i >= 1 && l1 <= L && i + nu <= N) {
+                double pv = ring[(slot == 0 ? Bsz - 1 : slot - 1) * stride];
+                double coef = 2.0 * t[l1];
+                dot = __builtin_fma(((i & 1) ? -coef : coef) * yk, pv, dot);
+            }
+            if (i <= a && a - i <= L) {
+                int l2 = a - i;
+                double pv = ring[((nu - i) % Bsz) * stride];
+                double coef = (!odd && l2 == 0) ? t[0] : 2.0 * t[l2];
+                dot = __builtin_fma(coef * yk, pv, dot);
+            }
+            if (i == 0) break;
+            double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
+            yk1 = yk;
+            yk = ykm1;
+            slot = slot == 0 ? Bsz - 1 : slot - 1;
+            if (fabs(yk) > 1e100) {
+                yk *= 1e-100; yk1 *= 1e-100; S2 *= 1e-200; dot *= 1e-200;
+                for (int q = 0; q < Bsz; ++q) ring[q * stride] *= 1e-100;
+            }
+        }
+        return dot / S2;
     }
-    return dot / S2;
 }
 
 // Asymptotic block contribution at frequency om (Sec. 3.2):
@@ -785,6 +854,7 @@ __global__ __launch_bounds__(256) void k_rows_asy(PlanDev P, const double2* __re
     ga[j] = acc;
 }
 
+template <int MODE>
 __global__ __launch_bounds__(256) void k_rows_local(PlanDev P, const double* __restrict__ gd,
                                                     const double* __restrict__ ga, const double* __restrict__ lmom,
                                                     double* g, double* const* g_slot)
@@ -804,8 +874,8 @@ __global__ __launch_bounds__(256) void k_rows_local(PlanDev P, const double* __r
             if (nd.lblk >= 0) {
                 int lb = nd.lblk;
                 int lbu = __builtin_amdgcn_readfirstlane(lb);
-                if (__all(lb == lbu)) acc += local_eval(P, lbu, om, lmom, ring, stride);
-                else acc += local_eval(P, lb, om, lmom, ring, stride);
+                if (__all(lb == lbu)) acc += local_eval<MODE>(P, lbu, om, lmom, ring, stride);
+                else acc += local_eval<MODE>(P, lb, om, lmom, ring, stride);
             }
             child = nd.ur;
         } else {
@@ -861,9 +931,14 @@ static void launch_rows_asy(const PlanDev& P, const ExecBuffers& B, hipStream_t 
 
 static void launch_rows_local(const PlanDev& P, const ExecBuffers& B, const IoArgs& io, hipStream_t s)
 {
+    if (P.nu <= 1) {   // no ring of earlier values needed
+        auto k = P.nu == 0 ? k_rows_local<0> : k_rows_local<1>;
+        hipLaunchKernelGGL(k, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, P, B.gd, B.ga, B.lmom, io.g, io.g_slot);
+        return;
+    }
     int bs = (P.nu + 1) * 256 * 8 <= 65536 ? 256 : 64;
     size_t lds = (size_t)(P.nu + 1) * bs * sizeof(double);
-    hipLaunchKernelGGL(k_rows_local, dim3(cdiv64(P.m, bs)), dim3(bs), lds, s, P, B.gd, B.ga, B.lmom, io.g,
+    hipLaunchKernelGGL(k_rows_local<2>, dim3(cdiv64(P.m, bs)), dim3(bs), lds, s, P, B.gd, B.ga, B.lmom, io.g,
                        io.g_slot);
 }
 
