@@ -130,9 +130,13 @@ __global__ __launch_bounds__(1024) void k_sort_scan(int32_t* __restrict__ hist, 
     if (threadIdx.x == 0) dtot[seg * 256 + d] = run;
 }
 
-// Stable scatter.  Within a tile, element order is (round, thread); each wave
-// ranks its keys among equal digits with ballots, waves are combined through
-// shared counters, and rounds through a running per-digit base.
+// Stable scatter through LDS.  Within a tile, element order is (round,
+// thread).  The tile's count of each digit is the difference of consecutive
+// tile offsets in the scanned histogram, so the digit's run inside the tile
+// starts at an exclusive scan of those counts.  Each round ranks its 256 keys
+// among equal digits with wave ballots and shared per-wave counters and
+// places them in LDS in digit order; the finished tile is then written out
+// with consecutive threads on consecutive addresses of each digit's run.
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* __restrict__ kin,
                                                                 const int32_t* __restrict__ vin,
                                                                 uint64_t* __restrict__ kout,
@@ -140,7 +144,11 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
                                                                 int shift, const int32_t* __restrict__ hist,
                                                                 const int32_t* __restrict__ dtot)
 {
-    __shared__ int32_t base[256];
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ int32_t sval[kSortTile];
+    __shared__ int32_t gbase[256];     // global position of the tile's first key of each digit
+    __shared__ int32_t lpos[256];      // next free LDS position of each digit
+    __shared__ int32_t lstart[256];    // LDS start of each digit's run
     __shared__ int32_t wcnt[kSortThreads / 64][256];
     int tile = blockIdx.x;
     int seg = tile_segment(S, tile);
@@ -151,21 +159,28 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
     int lane = threadIdx.x & 63;
     int wave = threadIdx.x >> 6;
     uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    // digit offsets: exclusive scan of the segment's digit totals
     {
-        int32_t t = dtot[seg * 256 + threadIdx.x];
-        int32_t incl = t;
+        const int d = threadIdx.x;
+        const int32_t* hd = hist + S.hoff[seg] + d * ntiles;
+        const int32_t tot = dtot[seg * 256 + d];
+        const int32_t mine = hd[lt];
+        const int32_t cnt = (lt + 1 < ntiles ? hd[lt + 1] : tot) - mine;
+        // exclusive scans over the digits of the segment totals and of the
+        // tile counts (256 threads = 4 waves)
+        int32_t it = tot, ic = cnt;
         #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
-            int32_t u = __shfl_up(incl, o);
-            if (lane >= o) incl += u;
+            int32_t u = __shfl_up(it, o), v = __shfl_up(ic, o);
+            if (lane >= o) { it += u; ic += v; }
         }
-        if (lane == 63) wcnt[0][wave] = incl;
+        if (lane == 63) { wcnt[0][wave] = it; wcnt[1][wave] = ic; }
         __syncthreads();
-        int32_t wb = 0;
-        for (int w2 = 0; w2 < wave; ++w2) wb += wcnt[0][w2];
+        int32_t wt = 0, wc = 0;
+        for (int w2 = 0; w2 < wave; ++w2) { wt += wcnt[0][w2]; wc += wcnt[1][w2]; }
         __syncthreads();
-        base[threadIdx.x] = S.off[seg] + wb + incl - t + hist[S.hoff[seg] + threadIdx.x * ntiles + lt];
+        gbase[d] = S.off[seg] + wt + it - tot + mine;
+        lstart[d] = wc + ic - cnt;
+        lpos[d] = wc + ic - cnt;
     }
     for (int r = 0; r < kSortRounds; ++r) {
         for (int q = threadIdx.x; q < (kSortThreads / 64) * 256; q += kSortThreads)
@@ -186,16 +201,25 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
         if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
         __syncthreads();
         if (valid) {
-            int off = base[d] + rank;
+            int off = lpos[d] + rank;
             for (int w2 = 0; w2 < wave; ++w2) off += wcnt[w2][d];
-            kout[off] = k;
-            vout[off] = v;
+            skey[off] = k;
+            sval[off] = v;
         }
         __syncthreads();
         int tot = 0;
         #pragma unroll
         for (int w2 = 0; w2 < kSortThreads / 64; ++w2) tot += wcnt[w2][threadIdx.x];
-        base[threadIdx.x] += tot;
+        lpos[threadIdx.x] += tot;
+    }
+    __syncthreads();
+    const int n_tile = (end - start) < kSortTile ? (end - start) : kSortTile;
+    for (int q = threadIdx.x; q < n_tile; q += kSortThreads) {
+        uint64_t k = skey[q];
+        int d = (int)((k >> shift) & 255);
+        int dst = gbase[d] + (q - lstart[d]);
+        kout[dst] = k;
+        vout[dst] = sval[q];
     }
 }
 
