@@ -717,12 +717,20 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
     for (int p = 1; p < NCH; ++p) gpow[p] = gpow[p - 1] * gam;
     dd sp = two_sum(om, -B.D);
     double ar = 0.0, ai = 0.0;
+    // final phase om C + phi (+ llo theta on the direct-sum path), double-double
+    dd pc = two_prod(om, B.C);
+    dd ph = two_sum(pc.hi, P.phi_hi);
+    double ph_lo = ph.lo + pc.lo + P.phi_lo;
     if (!B.fft) {
         const double2* G = grids + B.grid_off;
         double th = sp.hi * B.h, tl = sp.lo * B.h;
+        // the cell sum starts at l = llo: its factor e^{i llo theta} joins the
+        // final phase, and the rotation starts at 1
         dd a0 = two_prod((double)B.llo, th);
-        double zr, zi;
-        cis_dd(a0.hi, __builtin_fma((double)B.llo, tl, a0.lo), zr, zi);
+        dd q = two_sum(ph.hi, a0.hi);
+        ph.hi = q.hi;
+        ph_lo += q.lo + __builtin_fma((double)B.llo, tl, a0.lo);
+        double zr = 1.0, zi = 0.0;
         double s1, c1;
         sincos_small(th, &s1, &c1);
         double er = c1 - tl * s1, ei = s1 + tl * c1;
@@ -774,10 +782,8 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
     }
     double kap = fabs(sp.hi) * B.alpha;
     double scale = B.h / (B.alpha * eshat(P, kap));
-    dd pc = two_prod(om, B.C);
-    dd s2 = two_sum(pc.hi, P.phi_hi);
     double cr, ci;
-    cis_dd(s2.hi, s2.lo + pc.lo + P.phi_lo, cr, ci);
+    cis_dd(ph.hi, ph_lo, cr, ci);
     double amp = sqrt(gam) * scale;
     return kSqrt2OverPi * amp * __builtin_fma(cr, ar, -ci * ai);
 }

@@ -517,7 +517,7 @@ static void fill_params(PlanDev& P, int nu, double eps, const nuht_opts& o)
         P.chan[p] = p < 2 * M ? (((p >> 1) & 1) ? -P.hank[p] : P.hank[p]) : 0.0;
     phase_offset(anu, P.phi_hi, P.phi_lo);
     P.kappa_max = P.w * M_PI / 4.0 * (1.0 + 1e-9);
-    P.n_eshat = 30;
+    P.n_eshat = 24;   // the series reaches the quadrature's ~1e-15 floor by then (w <= 18)
     P.spread_chunk = o.spread_chunk > 0 ? o.spread_chunk : kSpreadChunk;
     // the Chebyshev series depends only on the kernel width (beta follows w)
     static std::mutex mu;
