@@ -108,8 +108,13 @@ typedef struct {
  *
  * Sorts r and omega on the device, computes (M, z, L) for (nu, eps) (Sec. 3.3),
  * and subdivides the matrix (Alg. 1).  Copies r and omega into plan-owned
- * storage, so the caller may free or change them afterwards.  Synchronises
- * `stream` once (to size the plan's workspace).  Every argument is validated:
+ * storage, so the caller may free or change them afterwards.  The planning
+ * runs on a stream of the library's, ordered after the work already queued
+ * on `stream` (which may produce r and omega); the call waits once for that
+ * planning work alone (to size the plan's workspace), not for the rest of
+ * `stream`, so a plan made on a side stream overlaps the GPU's other work.
+ * Later execute / adjoint calls may use any stream; a plan's buffers are
+ * released only after the last of them.  Every argument is validated:
  * n, m >= 0; r_dev / omega_dev non-null when n / m > 0; |nu| <= 100;
  * 1e-15 <= eps <= 1e-2; all r, omega finite and >= 0 (else NUHT_EDOMAIN).
  * n == 0 or m == 0 is valid (the transform then writes zeros).

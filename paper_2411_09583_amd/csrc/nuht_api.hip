@@ -430,6 +430,13 @@ struct nuht_plan_s {
     double eps = 0.0;
     nuht_opts opts{};
     int64_t n = 0, m = 0;
+    // Planning (sort, partitions) runs on `ps`, a stream of the library's, so
+    // it overlaps work already queued on the caller's streams; ev_use marks
+    // the last use of the plan's buffers on a caller stream, and anything the
+    // plan frees is ordered after it.
+    hipStream_t ps = nullptr;
+    hipEvent_t ev_use = nullptr;
+    bool used = false;
     DevBuf b_geom;               // keys, values, sort scratch, summary, flag
     uint64_t* keys = nullptr;    // sorted points then sorted frequencies (bit patterns)
     int32_t* vals = nullptr;     // matching caller indices
@@ -694,14 +701,43 @@ static int build_partition(nuht_plan_t pl, Partition& Pt, const Geometry& G, int
     }
 }
 
+// Frees on the plan stream happen after the last use on a caller stream.
+static void before_free(nuht_plan_t p)
+{
+    if (p->used && p->ps && p->ev_use) (void)hipStreamWaitEvent(p->ps, p->ev_use, 0);
+}
+
+static void note_use(nuht_plan_t p, hipStream_t s)
+{
+    if (p->ev_use && hipEventRecord(p->ev_use, s) == hipSuccess) p->used = true;
+    else (void)hipGetLastError();
+}
+
 static void free_plan(nuht_plan_t p)
 {
     if (!p) return;
     prof_clear(p);
+    before_free(p);
     p->orders.clear();
     dev_free(p->b_grad);
     dev_free(p->b_geom);
+    if (p->ev_use) (void)hipEventDestroy(p->ev_use);
     delete p;
+}
+
+// The library's planning stream of the current device (default priority).
+static hipStream_t plan_stream()
+{
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) { (void)hipGetLastError(); return nullptr; }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        streams[dev] = nullptr;
+    }
+    return streams[dev];
 }
 
 // At most this many orders keep their partitions; the least recently used
@@ -718,7 +754,10 @@ static nuht_plan_s::OrderParts* order_parts(nuht_plan_t p, int nu)
             if (p->orders[i]->nu != p->nu_req &&
                 (victim == p->orders.size() || p->orders[i]->used < p->orders[victim]->used))
                 victim = i;
-        if (victim < p->orders.size()) p->orders.erase(p->orders.begin() + victim);
+        if (victim < p->orders.size()) {
+            before_free(p);
+            p->orders.erase(p->orders.begin() + victim);
+        }
     }
     auto o = std::unique_ptr<nuht_plan_s::OrderParts>(new (std::nothrow) nuht_plan_s::OrderParts());
     if (!o) return nullptr;
@@ -736,7 +775,8 @@ static int get_partition(nuht_plan_t p, int nu, bool transposed, hipStream_t s, 
     if (!o) return NUHT_ENOMEM;
     Partition& Pt = transposed ? o->a : o->f;
     if (!Pt.built) {
-        int rc = build_partition(p, Pt, transposed ? p->adj : p->fwd, nu, s);
+        (void)s;
+        int rc = build_partition(p, Pt, transposed ? p->adj : p->fwd, nu, p->ps);
         if (rc != NUHT_OK) {
             Pt.release();
             return rc;
@@ -760,6 +800,7 @@ static int run(nuht_plan_t p, const Partition& Pt, const double* in, double* out
     io.g = out;
     io.scale_by_points = scale;
     HIP_TRY(launch_execute(Pt.P, Pt.sum, Pt.B, Pt.cls.data(), (int)Pt.cls.size(), io, s, prof_marks(p)));
+    note_use(p, s);
     return NUHT_OK;
 }
 
@@ -798,21 +839,41 @@ static int check_opts(const nuht_opts* opts, nuht_opts& o)
     return NUHT_OK;
 }
 
-// A plan with its geometry: storage allocated, input check and sort launched
-// on `s` (no partition yet, no synchronisation).
-static int plan_create(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_dev, int64_t m,
-                       const double* omega_dev, const nuht_opts& o, hipStream_t s)
+// Host-side checks of one plan's arguments (no HIP call).
+static int check_plan_args(int nu, double eps, int64_t n, const double* r_dev, int64_t m,
+                           const double* omega_dev, const nuht_opts& o)
 {
-    *out = nullptr;
     if (!valid_common(nu, eps)) return NUHT_EINVAL;
     if (o.precision == NUHT_FP32_SPREAD && eps < 1e-7) return NUHT_EPRECISION;
     if (n < 0 || m < 0 || n > INT32_MAX / 2 || m > INT32_MAX / 2) return NUHT_EINVAL;
     if ((n > 0 && !r_dev) || (m > 0 && !omega_dev)) return NUHT_EINVAL;
+    return NUHT_OK;
+}
+
+// A plan with its geometry: storage allocated, input check and sort launched
+// on `s` (no partition yet, no synchronisation).
+// s: the stream the plan works on (its planning stream); wait_on, if set, is
+// the caller's stream, after whose queued work the inputs are read.
+static int plan_create(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_dev, int64_t m,
+                       const double* omega_dev, const nuht_opts& o, hipStream_t s, hipStream_t wait_on)
+{
+    *out = nullptr;
+    NUHT_TRY(check_plan_args(nu, eps, n, r_dev, m, omega_dev, o));
     nuht_plan_s* p = new (std::nothrow) nuht_plan_s();
     if (!p) return NUHT_ENOMEM;
     p->nu_req = nu; p->eps = eps; p->opts = o; p->n = n; p->m = m;
+    p->ps = s;
     int64_t tot = n + m;
     auto fail = [&](int code) { free_plan(p); return code; };
+    if (hipEventCreateWithFlags(&p->ev_use, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        p->ev_use = nullptr;
+        return fail(NUHT_EHIP);
+    }
+    if (wait_on) {
+        if (hipEventRecord(p->ev_use, wait_on) != hipSuccess) return fail(NUHT_EHIP);
+        if (hipStreamWaitEvent(s, p->ev_use, 0) != hipSuccess) return fail(NUHT_EHIP);
+    }
     {
         Slab slab;
         slab.add(p->d_sum, 1);
@@ -852,9 +913,12 @@ int nuht_plan(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_d
     *out = nullptr;
     nuht_opts o;
     NUHT_TRY(check_opts(opts, o));
+    NUHT_TRY(check_plan_args(nu, eps, n, r_dev, m, omega_dev, o));
     hipStream_t s = (hipStream_t)stream;
+    hipStream_t ps = plan_stream();
+    if (!ps) return NUHT_EHIP;
     nuht_plan_t p = nullptr;
-    NUHT_TRY(plan_create(&p, nu, eps, n, r_dev, m, omega_dev, o, s));
+    NUHT_TRY(plan_create(&p, nu, eps, n, r_dev, m, omega_dev, o, ps, s));
     // the one synchronisation of the plan happens inside (it also reads the
     // input check's flag)
     Partition* Pt = nullptr;
@@ -969,7 +1033,7 @@ static int tune_plan(nuht_plan_t p, const double* c_dev, int reps, nuht_opts* be
     auto time_opts = [&](const nuht_opts& o, double* ms) -> int {
         p->opts = o;
         Partition T;
-        int r = build_partition(p, T, p->fwd, p->nu_req, s);
+        int r = build_partition(p, T, p->fwd, p->nu_req, p->ps);
         if (r != NUHT_OK) return r;
         IoArgs io;
         io.c = c_dev;
@@ -1130,7 +1194,7 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
     b->plans.assign(count, nullptr);
     for (int i = 0; i < count; ++i) {
         int rc = plan_create(&b->plans[i], nu[i], eps, n[i], r_dev[i], m[i], omega_dev[i], o,
-                             b->aux[b->stream_of[i]]);
+                             b->aux[b->stream_of[i]], nullptr);
         if (rc != NUHT_OK) return fail(rc);
     }
     if (o.tune) {
