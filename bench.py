@@ -43,9 +43,10 @@ def log(*a):
 
 
 def read_traffic(kernel):
-    """HBM bytes per launch of `kernel` (FETCH_SIZE and WRITE_SIZE counters
-    scaled by a plain copy of known size), from the committed counter summary,
-    if it was taken on the current kernel sources; else None."""
+    """HBM bytes per launch of `kernel` (for the spreading stage, its two
+    kernels together) from FETCH_SIZE and WRITE_SIZE counters scaled by a
+    plain copy of known size, read from the committed counter summary if it
+    was taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_large_uniform.txt")
     if not os.path.exists(path):
         return None
@@ -352,7 +353,8 @@ def main():
     # Roofline of the dominant kernel among those with an algorithmic flop
     # count (FP64 operations the method's arithmetic needs, per launch; the
     # transcendental kernel and phase evaluations are not counted):
-    #   k_spread    every (point, cell) pair inside the kernel support (w cells
+    #   spreading   (k_spread_mfma on dense items, k_spread on the others; one
+    #               stage) every (point, cell) pair inside the kernel support (w cells
     #               per point membership): 2M complex channels x (2 add + 2 mul)
     #               plus the kernel-weight product: 8M + 2
     #   k_rows_asy  every (row, cell) pair of a direct-sum-path block: channel
@@ -364,11 +366,12 @@ def main():
             return inf["asy_col_members"] * w * (8.0 * M + 2.0)
         return inf["dft_row_cells"] * (8.0 * M + 10.0) + inf["fft_row_members"] * w * 8.0 * M
 
-    kern = {"spread": "k_spread", "rows_asymptotic": "k_rows_asy"}
+    kern = {"spread": "k_spread_mfma+k_spread", "rows_asymptotic": "k_rows_asy"}
+    tfile = {"spread": "spread_stage", "rows_asymptotic": "k_rows_asy"}   # traffic summaries
     dom = max(kern, key=lambda st: stage_ms[st])
     fl = sum(flops(dom, infos[nu]) for nu in ORDERS)             # one launch per order per step
     achieved = fl / (stage_ms[dom] * 1e-3)
-    traffic = read_traffic(kern[dom])
+    traffic = read_traffic(tfile[dom])
     roofline = dict(bound="alu", kernel=kern[dom], achieved=achieved / 1e12, peak=PEAK_FP64 / 1e12,
                     unit="TFLOP/s", frac=achieved / PEAK_FP64, traffic=traffic,
                     flops_per_step=fl, launches_per_step=len(ORDERS),

@@ -183,6 +183,40 @@ constexpr size_t spread_lds_bytes(int w)
     return (size_t)kSpreadSub * (sizeof(SpreadPoint<T>) + (size_t)w * sizeof(T));
 }
 
+// One point of a block for spreading: weight c sqrt(r0/r) e^{i D (r - C)}
+// (real, imaginary), ratio q = r0 / r, first cell reached l0, and the kernel
+// argument s = 2 f - 1 of the polynomial pieces.  The phase is a double-double
+// product; the cell position (r - C) / h is formed from the double-double
+// difference (the scaling by h is exact).
+struct PointEval {
+    double wr, wi, q, s;
+    int l0;
+};
+
+__device__ __forceinline__ PointEval eval_point(const ABlock& B, double r, double c, double inv_h, double hw)
+{
+    dd tp = two_sum(r, -B.C);
+    dd ph = two_prod(B.D, tp.hi);
+    double cth, sth;
+    cis_dd(ph.hi, __builtin_fma(B.D, tp.lo, ph.lo), cth, sth);
+    double q = B.r0 / r;
+    double w0 = c * sqrt(q);
+    // u - w/2 = (tp.hi + tp.lo)/h - w/2
+    dd a = two_sum(tp.hi * inv_h, -hw);
+    double lo = a.lo + tp.lo * inv_h;
+    double fl = floor(a.hi);
+    double frac = (a.hi - fl) + lo;          // a.hi - fl is exact
+    if (frac < 0.0) { fl -= 1.0; frac += 1.0; }
+    else if (frac >= 1.0) { fl += 1.0; frac -= 1.0; }
+    PointEval e;
+    e.wr = w0 * cth;
+    e.wi = w0 * sth;
+    e.q = q;
+    e.l0 = (int)fl + 1;
+    e.s = 1.0 - 2.0 * frac;                  // s = 2 f - 1, f = 1 - frac
+    return e;
+}
+
 template <int NCH, typename T>
 __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restrict__ cs,
                                                 const double* __restrict__ es_poly, double2* __restrict__ part_raw)
@@ -192,7 +226,8 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
     extern __shared__ double4 spread_lds[];
     SpreadPoint<T>* s_pt = reinterpret_cast<SpreadPoint<T>*>(spread_lds);
     T* s_k = reinterpret_cast<T*>(s_pt + kSpreadSub);
-    const Item I = P.aitems[blockIdx.x];
+    // the items not spread on the matrix cores, from the back of the order
+    const Item I = P.aitems[P.alist[P.n_aitems - 1 - (int)blockIdx.x]];
     const ABlock B = P.ab[I.blk];
     const int tid = threadIdx.x;
     const int w = P.w;
@@ -216,31 +251,17 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
             // that the coefficient loads below stay wave-uniform (scalar)
             {
                 const bool own = tid < np;
-                int k = k0 + (own ? tid : np - 1);
-                double r = P.rs[k];
-                double c = cs[k];
-                dd tp = two_sum(r, -B.C);
-                dd ph = two_prod(B.D, tp.hi);
-                double cth, sth;
-                cis_dd(ph.hi, __builtin_fma(B.D, tp.lo, ph.lo), cth, sth);
-                double q = B.r0 / r;
-                double w0 = c * sqrt(q);
-                // u - w/2 = (tp.hi + tp.lo)/h - w/2 (scaling by h exact)
-                dd a = two_sum(tp.hi * inv_h, -hw);
-                double lo = a.lo + tp.lo * inv_h;
-                double fl = floor(a.hi);
-                double frac = (a.hi - fl) + lo;          // a.hi - fl is exact
-                if (frac < 0.0) { fl -= 1.0; frac += 1.0; }
-                else if (frac >= 1.0) { fl += 1.0; frac -= 1.0; }
+                const int k = k0 + (own ? tid : np - 1);
+                const PointEval e = eval_point(B, P.rs[k], cs[k], inv_h, hw);
                 if (own) {
                     SpreadPoint<T> rec;
-                    rec.wr = (T)(w0 * cth);
-                    rec.wi = (T)(w0 * sth);
-                    rec.q = (T)q;
-                    rec.l0 = (int)fl + 1;
+                    rec.wr = (T)e.wr;
+                    rec.wi = (T)e.wi;
+                    rec.q = (T)e.q;
+                    rec.l0 = e.l0;
                     s_pt[tid] = rec;
                 }
-                const double sv = 1.0 - 2.0 * frac;      // s = 2 f - 1, f = 1 - frac
+                const double sv = e.s;
                 // powers s^0 .. s^8 once per point; each piece is then
                 // sum_{d<=8} c_d s^d + s^8 sum_{d>8} c_d s^(d-8), with the
                 // (scalar) coefficients as multiplicands
@@ -298,6 +319,208 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
             for (int p = 0; p < NCH; ++p) { dst[p].x = ar[p]; dst[p].y = ai[p]; }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Spreading on the matrix cores (FP64), for items whose points reach the grid
+// from at most kSpreadAnchors first cells (dense items: many points per cell).
+// With the points of an item split by their first cell a (anchor), the
+// item's partial subgrid is
+//   G[a + t][col] = sum over anchors a, over points k with anchor a, of
+//                   phi_t(s_k) V_k[col],
+// t the tap (0 .. w-1), phi_t the kernel's polynomial piece for tap t and
+// V_k[2p + {0,1}] = (re, im) of c_k sqrt(q_k) e^{i D (r_k - C)} q_k^p.  For
+// each anchor this is a (16 taps) x (points) x (16 NCT columns) product: one
+// v_mfma_f64_16x16x4f64 per four points and column tile, accumulated per
+// anchor.  In an MFMA step, lane (row = lane % 16, k = lane / 16) supplies
+// A[row][k] = phi_row(s) of point k, evaluated in the lane with the
+// coefficients of piece `row` held in its registers, and B[k][col] =
+// V_k[col] (col = lane % 16) from LDS; element v of the accumulator is
+// D[lane / 16 + 4 v][lane % 16].  The four waves of a workgroup take turns
+// at steps of the item's points and never wait for each other until the end,
+// where they fold their anchor tiles into cells in LDS in a fixed order
+// (wave, anchor), so the result does not depend on timing.
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int NCH>
+struct SpreadMfma {
+    static constexpr int NCT = NCH <= 8 ? 1 : 2;   // 16-column tiles
+    static constexpr int NC = 16 * NCT;            // real columns of the tiles (re, im of 8 NCT channels)
+    static constexpr int VS = 2 * NCH + 1;         // LDS stride of a point's 2 NCH columns (odd: conflict-free writes)
+    static constexpr int GC = kSpreadAnchors + 15; // cells an item's anchor tiles reach
+    static constexpr size_t point_bytes = VS * sizeof(double) + sizeof(double) + sizeof(int32_t);
+    static constexpr int WPTS = 256 * point_bytes <= 65536 ? 64 : 32;   // points per wave step (LDS below 64 KiB)
+    static constexpr int PTS = 4 * WPTS;           // points held by the workgroup's four waves
+    static constexpr size_t fold_bytes = (size_t)4 * GC * NC * sizeof(double);   // per-wave cell sums, at the end
+    static constexpr size_t lds_bytes = (size_t)PTS * point_bytes > fold_bytes ? (size_t)PTS * point_bytes : fold_bytes;
+};
+
+// Orders the LDS accesses of one wave's lanes around it (the wave's region
+// is written and read by different lanes of the same wave).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Points pbeg .. pend-1 of the sub-chunk into the tiles of anchor a: two
+// groups of four points per step (two independent kernel evaluations).  Lanes
+// past pend take B = 0; with MASK, points of other anchors take A = 0.
+template <int NCH, bool MASK>
+__device__ __forceinline__ void spread_mfma_run(v4d (&acc)[SpreadMfma<NCH>::NCT], const double* s_v,
+                                                const double* s_s, const int32_t* s_d,
+                                                const double (&cf)[kEsDeg + 1], int pbeg, int pend, int col, int kq,
+                                                int a)
+{
+    constexpr int NCT = SpreadMfma<NCH>::NCT, VS = SpreadMfma<NCH>::VS;
+    for (int g = pbeg; g < pend; g += 8) {
+        const int i0 = g + kq, i1 = g + 4 + kq;
+        const bool v0 = i0 < pend, v1 = i1 < pend;
+        const int j0 = v0 ? i0 : g, j1 = v1 ? i1 : g;
+        const double s0 = s_s[j0], s1 = s_s[j1];
+        double b0[NCT], b1[NCT];
+        #pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+            const bool on = ct * 16 + 16 <= 2 * NCH || ct * 16 + col < 2 * NCH;   // columns past 2 NCH are zero
+            b0[ct] = (v0 && on) ? s_v[j0 * VS + ct * 16 + col] : 0.0;
+            b1[ct] = (v1 && on) ? s_v[j1 * VS + ct * 16 + col] : 0.0;
+        }
+        double p0 = cf[kEsDeg], p1 = cf[kEsDeg];
+        #pragma unroll
+        for (int q = kEsDeg - 1; q >= 0; --q) {
+            p0 = __builtin_fma(p0, s0, cf[q]);
+            p1 = __builtin_fma(p1, s1, cf[q]);
+        }
+        if (MASK) {
+            if (s_d[j0] != a) p0 = 0.0;
+            if (s_d[j1] != a) p1 = 0.0;
+        }
+        #pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+            acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(p0, b0[ct], acc[ct], 0, 0, 0);
+            acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(p1, b1[ct], acc[ct], 0, 0, 0);
+        }
+    }
+}
+
+template <int NCH>
+__device__ __forceinline__ void spread_mfma_item(const PlanDev& P, const double* __restrict__ cs,
+                                                 const double* __restrict__ es_poly, double2* __restrict__ part)
+{
+    using SM = SpreadMfma<NCH>;
+    constexpr int NCT = SM::NCT, NC = SM::NC, VS = SM::VS, WPTS = SM::WPTS, PTS = SM::PTS, GC = SM::GC;
+    constexpr int NA = kSpreadAnchors;
+    extern __shared__ double4 spread_lds[];
+    double* s_v = reinterpret_cast<double*>(spread_lds);
+    double* s_s = s_v + PTS * VS;
+    int32_t* s_d = reinterpret_cast<int32_t*>(s_s + PTS);
+    const Item I = P.aitems[P.alist[blockIdx.x]];
+    const ABlock B = P.ab[I.blk];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int col = lane & 15, kq = lane >> 4;
+    const int w = P.w;
+    const double hw = 0.5 * w;
+    const double inv_h = 1.0 / B.h;      // exact: h is a power of two
+    // polynomial piece of tap `col` (row col of A); rows at or beyond w are zero
+    double cf[kEsDeg + 1];
+    #pragma unroll
+    for (int d = 0; d <= kEsDeg; ++d) cf[d] = col < w ? es_poly[col * (kEsDeg + 1) + d] : 0.0;
+    v4d acc[NA][NCT];
+    #pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        #pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) acc[a][ct] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+    // The waves work independently: wave v takes the steps of WPTS points
+    // starting at ka + (4 j + v) WPTS, evaluates them into its own LDS region
+    // and multiplies them into its own tiles; the next step's point and weight
+    // are loaded while the current one is multiplied.
+    double* w_v = s_v + wave * WPTS * VS;
+    double* w_s = s_s + wave * WPTS;
+    int32_t* w_d = s_d + wave * WPTS;
+    int k0 = I.ka + wave * WPTS;
+    double r_nx = 0.0, c_nx = 0.0;
+    if (lane < WPTS && k0 + lane < I.kb) { r_nx = P.rs[k0 + lane]; c_nx = cs[k0 + lane]; }
+    for (; k0 < I.kb; k0 += 4 * WPTS) {
+        const int np = (I.kb - k0) < WPTS ? (I.kb - k0) : WPTS;
+        const double r = r_nx, c = c_nx;
+        const int kn = k0 + 4 * WPTS + lane;
+        if (lane < WPTS && kn < I.kb) { r_nx = P.rs[kn]; c_nx = cs[kn]; }
+        wave_sync();                              // the previous step's reads of the region are done
+        if (lane < np) {
+            const PointEval e = eval_point(B, r, c, inv_h, hw);
+            w_s[lane] = e.s;
+            w_d[lane] = e.l0 - I.sub_lo;
+            double vr = e.wr, vi = e.wi;
+            double* v = w_v + lane * VS;
+            #pragma unroll
+            for (int p = 0; p < NCH; ++p) {
+                v[2 * p] = vr;
+                v[2 * p + 1] = vi;
+                vr *= e.q;
+                vi *= e.q;
+            }
+        }
+        wave_sync();
+        // each anchor present in the step takes one pass over it; when the
+        // step holds several anchors (rare) a pass masks the other anchors'
+        // points out of A
+        const bool mine = lane < np;
+        const int dm = mine ? w_d[lane] : -1;
+        const int d0 = __builtin_amdgcn_readfirstlane(dm);          // lane 0: the step's first point
+        const bool one = __ballot(mine && dm != d0) == 0;
+        #pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            if (__ballot(mine && dm == a) != 0) {
+                if (one) spread_mfma_run<NCH, false>(acc[a], w_v, w_s, w_d, cf, 0, np, col, kq, a);
+                else spread_mfma_run<NCH, true>(acc[a], w_v, w_s, w_d, cf, 0, np, col, kq, a);
+            }
+        }
+    }
+    // fold: the wave's tile of anchor a, row t, goes to cell a + t of the
+    // wave's own cell sums; anchors one after the other
+    __syncthreads();
+    double* s_g = s_v;
+    for (int e = tid; e < 4 * GC * NC; e += 256) s_g[e] = 0.0;
+    __syncthreads();
+    double* gw = s_g + wave * GC * NC;
+    #pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        #pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+            #pragma unroll
+            for (int v = 0; v < 4; ++v) gw[(a + kq + 4 * v) * NC + ct * 16 + col] += acc[a][ct][v];
+        }
+        __syncthreads();   // the next anchor's cells overlap this one's in other lanes
+    }
+    // item partial [cell][channel] (re, im): waves summed in order
+    double* out = reinterpret_cast<double*>(part + I.off);
+    constexpr int row_len = 2 * NCH;
+    for (int e = tid; e < I.sub_n * row_len; e += 256) {
+        const int cell = e / row_len, c = e - cell * row_len;
+        const int k = cell * NC + c;
+        out[e] = ((s_g[k] + s_g[GC * NC + k]) + s_g[2 * GC * NC + k]) + s_g[3 * GC * NC + k];
+    }
+}
+
+// Up to 8 channels the kernel fits three waves per SIMD; above, the register
+// cap would spill.
+template <int NCH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_spread_mfma(
+    PlanDev P, const double* __restrict__ cs, const double* __restrict__ es_poly, double2* __restrict__ part)
+{
+    spread_mfma_item<NCH>(P, cs, es_poly, part);
+}
+
+template <int NCH>
+__global__ __launch_bounds__(256) void k_spread_mfma_wide(PlanDev P, const double* __restrict__ cs,
+                                                          const double* __restrict__ es_poly,
+                                                          double2* __restrict__ part)
+{
+    spread_mfma_item<NCH>(P, cs, es_poly, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -918,14 +1141,24 @@ static inline int cdiv64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); 
 template <int NCH>
 static void launch_spread(const PlanDev& P, const Summary& S, const ExecBuffers& B, hipStream_t s)
 {
-    if (S.n_aitems > 0)
-    {
+    const int32_t n_dense = S.n_adense, n_rest = S.n_aitems - S.n_adense;
+    if constexpr (NCH <= 16) {
+        if (n_dense > 0) {
+            if constexpr (SpreadMfma<NCH>::NCT == 1)
+                hipLaunchKernelGGL((k_spread_mfma<NCH>), dim3(n_dense), dim3(256), SpreadMfma<NCH>::lds_bytes, s, P,
+                                   B.cs, B.es_poly, B.part);
+            else
+                hipLaunchKernelGGL((k_spread_mfma_wide<NCH>), dim3(n_dense), dim3(256), SpreadMfma<NCH>::lds_bytes, s,
+                                   P, B.cs, B.es_poly, B.part);
+        }
+    }
+    if (n_rest > 0) {
         if (P.fp32)
-            hipLaunchKernelGGL((k_spread<NCH, float>), dim3(S.n_aitems), dim3(256), spread_lds_bytes<float>(P.w), s, P,
+            hipLaunchKernelGGL((k_spread<NCH, float>), dim3(n_rest), dim3(256), spread_lds_bytes<float>(P.w), s, P,
                                B.cs, B.es_poly, B.part);
         else
-            hipLaunchKernelGGL((k_spread<NCH, double>), dim3(S.n_aitems), dim3(256), spread_lds_bytes<double>(P.w), s,
-                               P, B.cs, B.es_poly, B.part);
+            hipLaunchKernelGGL((k_spread<NCH, double>), dim3(n_rest), dim3(256), spread_lds_bytes<double>(P.w), s, P,
+                               B.cs, B.es_poly, B.part);
     }
 }
 

@@ -518,6 +518,7 @@ static void fill_params(PlanDev& P, int nu, double eps, const nuht_opts& o)
     P.L = local_rank(anu, eps, P.z);
     P.w = es_width(eps, o.precision);
     P.fp32 = o.precision == NUHT_FP32_SPREAD ? 1 : 0;
+    P.mfma = (!P.fp32 && P.w <= 16 && P.nch <= 16) ? 1 : 0;
     P.beta = es_beta(P.w);
     for (int p = 0; p < 2 * M + 2; ++p) P.hank[p] = hankel_coef(anu, p);
     for (int p = 0; p < kMaxChannels; ++p)
@@ -605,11 +606,12 @@ static int part_begin(nuht_plan_t pl, PendingPart& pp, Partition& Pt, const Geom
     slab.add(A.q1, (size_t)A.q_cap);
     slab.add(A.litems, (size_t)A.litem_cap);
     slab.add(A.aitems, (size_t)A.aitem_cap);
+    slab.add(A.alist, (size_t)A.aitem_cap);
     slab.add(A.fft_list, (size_t)A.a_cap);
     slab.add(A.gslot, (size_t)A.a_cap + 1);
     NUHT_TRY(slab.commit(pp.tmp));
     P.nodes = A.nodes; P.lb = A.lb; P.ab = A.ab; P.db = A.db;
-    P.litems = A.litems; P.aitems = A.aitems; P.fft_list = A.fft_list; P.gslot = A.gslot;
+    P.litems = A.litems; P.aitems = A.aitems; P.alist = A.alist; P.fft_list = A.fft_list; P.gslot = A.gslot;
     HIP_TRY(hipMemsetAsync(pl->d_sum, 0, sizeof(Summary), s));
     HIP_TRY(launch_planning(P, A, K, Jc, a_cells, min_size, ncand, dft_max, sigma, pl->d_sum, s));
     HIP_TRY(hipMemcpyAsync(&h->sum, pl->d_sum, sizeof(Summary), hipMemcpyDeviceToHost, s));
@@ -651,7 +653,7 @@ static int part_finish(PendingPart& pp, const HostStage* h, bool* again)
     pp.tmp.bytes = 0;
     Pt.A = pp.A;
     P.n_nodes = S.n_nodes; P.n_l = S.n_l; P.n_a = S.n_a; P.n_d = S.n_d;
-    P.n_litems = S.n_litems; P.n_aitems = S.n_aitems;
+    P.n_litems = S.n_litems; P.n_aitems = S.n_aitems; P.n_adense = S.n_adense;
 
     // execution buffers
     ExecBuffers& B = Pt.B;

@@ -16,6 +16,7 @@ constexpr int kLocalChunk = 4096;      // columns per local-moment work item
 constexpr int kSpreadChunk = 1024;     // default points per spreading work item (a plan option)
 constexpr int kMaxEsWidth = 18;        // largest ES kernel width
 constexpr int kEsDeg = 16;             // degree of the per-cell polynomial pieces of the ES kernel
+constexpr int kSpreadAnchors = 6;      // first cells (anchors) one matrix-core spreading item may hold
 constexpr int kMaxLevels = 4096;       // subdivision depth limit
 
 // A mixed block of Alg. 1 and the split chosen for it.  Rows j0..js and
@@ -65,7 +66,8 @@ struct Item {
     int32_t blk;
     int32_t ka, kb;       // columns ka .. kb-1
     int32_t sub_lo, sub_n;  // spread items: subgrid cells sub_lo .. sub_lo + sub_n - 1
-    int32_t pad;
+    int32_t dense;        // spread items: 1 if spread on the matrix cores (its points' first cells
+                          // lie in sub_lo .. sub_lo + kSpreadAnchors - 1), else 0
     int64_t off;          // spread items: partial-subgrid offset (complex elements)
 };
 
@@ -75,6 +77,7 @@ struct Summary {
     int32_t levels, overflow;
     int32_t n_litems, n_aitems;
     int32_t n_fft, max_nch;
+    int32_t n_adense, pad;  // spread items on the matrix cores (the first n_adense of the item list)
     int64_t l_row, l_col, a_row, a_col, d_ent;
     int64_t grid_cells;     // sum N1 (all asymptotic blocks)
     int64_t dft_cells;      // sum N1 over direct-sum-path blocks
@@ -92,7 +95,8 @@ struct Summary {
 struct PlanDev {
     int32_t n, m, nu, M, L, w;       // sizes, |order|, terms, local rank, ES width
     int32_t nch, sign;               // channels (2M padded to a kernel instance); (-1)^nu for negative orders, else 1
-    int32_t fp32, pad_fp;            // FP32 spreading (weights, kernel values and channel sums in float)
+    int32_t fp32;                    // FP32 spreading (weights, kernel values and channel sums in float)
+    int32_t mfma;                    // dense spreading items go to the matrix cores (FP64, w <= 16, nch <= 16)
     double z, beta, eps;
     double phi_hi, phi_lo;           // -(2nu+1) pi/4 reduced to [0, 2pi), double-double
     double hank[2 * 20 + 2];         // a_p(nu), p = 0 .. 2M+1 (Hankel coefficients)
@@ -110,10 +114,11 @@ struct PlanDev {
     const DBlock* db;
     const Item* litems;
     const Item* aitems;
+    const int32_t* alist;            // spreading order: dense items from the front, the others from the back
     const int32_t* fft_list;         // FFT-path blocks grouped by size class
     const int64_t* gslot;            // first grid slot of each asymptotic block; gslot[n_a] = all slots
     const double* es_poly;           // ES kernel pieces, w x (kEsDeg + 1) monomial coefficients
-    int32_t n_nodes, n_l, n_a, n_d, n_litems, n_aitems, pad1, pad2;
+    int32_t n_nodes, n_l, n_a, n_d, n_litems, n_aitems, n_adense, pad1;
 };
 
 }  // namespace nuht

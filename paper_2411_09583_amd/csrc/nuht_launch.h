@@ -21,6 +21,7 @@ struct Arena {
     Rect* q1;
     Item* litems;
     Item* aitems;
+    int32_t* alist;      // spreading order of the asymptotic items (aitem_cap)
     int32_t* fft_list;
     int64_t* gslot;      // first grid slot of each asymptotic block, then the total (a_cap + 1)
     int32_t node_cap, l_cap, a_cap, d_cap, q_cap, litem_cap, aitem_cap, pad;

@@ -612,7 +612,7 @@ __global__ void k_items(PlanDev P, Arena A, Summary* __restrict__ sum, int32_t* 
             int32_t kb = ka + kLocalChunk;
             if (kb > L.k1 + 1) kb = L.k1 + 1;
             Item I;
-            I.blk = lo; I.ka = ka; I.kb = kb; I.sub_lo = 0; I.sub_n = 0; I.pad = 0; I.off = 0;
+            I.blk = lo; I.ka = ka; I.kb = kb; I.sub_lo = 0; I.sub_n = 0; I.dense = 0; I.off = 0;
             A.litems[i] = I;
         } else {
             int32_t ia = i - n_li;
@@ -633,31 +633,45 @@ __global__ void k_items(PlanDev P, Arena A, Summary* __restrict__ sum, int32_t* 
             if (s0 < B.llo) s0 = B.llo;
             if (s1 > lhi) s1 = lhi;
             Item I;
-            I.blk = lo; I.ka = ka; I.kb = kb + 1; I.sub_lo = s0; I.sub_n = s1 - s0 + 1; I.pad = 0; I.off = 0;
+            I.blk = lo; I.ka = ka; I.kb = kb + 1; I.sub_lo = s0; I.sub_n = s1 - s0 + 1; I.off = 0;
+            // first cells of the points lie in s0 .. s1 - w + 1 (one cell of
+            // margin each side for rounding): dense if at most kSpreadAnchors
+            I.dense = (P.mfma && I.sub_n - w + 1 <= kSpreadAnchors) ? 1 : 0;
             A.aitems[ia] = I;
             a_cells[ia] = I.sub_n;
         }
     }
 }
 
-// Partial-subgrid offsets of the asymptotic items (one 1024-thread block).
+// Partial-subgrid offsets of the asymptotic items, and the spreading order:
+// dense items at alist[0 ..) and the others at alist[n_ai - 1], alist[n_ai - 2],
+// ..., each list in item order (one 1024-thread block).
 __global__ __launch_bounds__(1024) void k_item_scan(PlanDev P, Arena A, Summary* __restrict__ sum,
                                                     const int32_t* __restrict__ a_cells)
 {
-    __shared__ int64_t wsum[1][16];
+    __shared__ int64_t wsum[2][16];
     if (sum->overflow) return;
     const int32_t n_ai = sum->n_aitems;
     const int nch = P.nch;
-    int64_t run = 0;
+    int64_t run = 0, run_dense = 0;
     for (int32_t c0 = 0; c0 < n_ai; c0 += 1024) {
         int32_t i = c0 + threadIdx.x;
-        int64_t v[1] = {i < n_ai ? (int64_t)a_cells[i] : 0};
-        int64_t tot[1];
-        block_scan<int64_t, 1>(v, tot, wsum);
-        if (i < n_ai) A.aitems[i].off = (run + v[0]) * nch;
+        int64_t v[2] = {i < n_ai ? (int64_t)a_cells[i] : 0, i < n_ai ? (int64_t)A.aitems[i].dense : 0};
+        const int64_t dense = v[1];
+        int64_t tot[2];
+        block_scan<int64_t, 2>(v, tot, wsum);
+        if (i < n_ai) {
+            A.aitems[i].off = (run + v[0]) * nch;
+            int64_t nd_before = run_dense + v[1];
+            A.alist[dense ? nd_before : n_ai - 1 - (i - nd_before)] = i;
+        }
         run += tot[0];
+        run_dense += tot[1];
     }
-    if (threadIdx.x == 0) sum->part_cells = run;
+    if (threadIdx.x == 0) {
+        sum->part_cells = run;
+        sum->n_adense = (int32_t)run_dense;
+    }
 }
 
 // ---------------------------------------------------------------------------
