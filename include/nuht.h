@@ -71,6 +71,12 @@ typedef struct nuht_plan_s *nuht_plan_t;
  *   tune              nonzero: nuht_plan_many picks min_size, dft_max and
  *                     spread_chunk per size class with nuht_tune (the fields
  *                     above are then starting values).
+ *   vector_spread     nonzero: every spreading work item runs on the vector
+ *                     units.  By default, in FP64 with an ES width of at most
+ *                     16 and at most 16 channels, items whose points reach the
+ *                     grid from at most 6 first cells (many points per cell)
+ *                     are spread on the matrix cores; the two give the same
+ *                     sums up to rounding order.
  */
 typedef struct {
     int64_t min_size;
@@ -80,6 +86,7 @@ typedef struct {
     int32_t dft_max;
     int32_t spread_chunk;
     int32_t tune;
+    int32_t vector_spread;
 } nuht_opts;
 
 /*
@@ -101,6 +108,8 @@ typedef struct {
     int64_t workspace_bytes;          /* device memory held by the plan */
     int64_t min_size;                 /* options in use (after defaults and tuning) */
     int32_t dft_max, spread_chunk;
+    int32_t spread_items;             /* spreading work items of the asymptotic blocks */
+    int32_t dense_items;              /* of which spread on the matrix cores */
 } nuht_info;
 
 /*

@@ -35,7 +35,8 @@ class NuhtError(RuntimeError):
 class NuhtOpts(ctypes.Structure):
     _fields_ = [("min_size", ctypes.c_int64), ("M_override", ctypes.c_int32),
                 ("split_candidates", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("dft_max", ctypes.c_int32), ("spread_chunk", ctypes.c_int32), ("tune", ctypes.c_int32)]
+                ("dft_max", ctypes.c_int32), ("spread_chunk", ctypes.c_int32), ("tune", ctypes.c_int32),
+                ("vector_spread", ctypes.c_int32)]
 
 
 class NuhtInfo(ctypes.Structure):
@@ -49,7 +50,8 @@ class NuhtInfo(ctypes.Structure):
                 ("direct_entries", ctypes.c_int64), ("grid_cells", ctypes.c_int64),
                 ("fft_points", ctypes.c_int64), ("dft_row_cells", ctypes.c_int64),
                 ("fft_row_members", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
-                ("min_size", ctypes.c_int64), ("dft_max", ctypes.c_int32), ("spread_chunk", ctypes.c_int32)]
+                ("min_size", ctypes.c_int64), ("dft_max", ctypes.c_int32), ("spread_chunk", ctypes.c_int32),
+                ("spread_items", ctypes.c_int32), ("dense_items", ctypes.c_int32)]
 
 
 # every symbol include/nuht.h declares
@@ -133,14 +135,15 @@ class Plan:
 
     def __init__(self, r, omega, nu: int, eps: float, *, min_size: int = 0, M: int = 0,
                  split_candidates: int = 0, precision: int = NUHT_FP64, dft_max: int = 0,
-                 spread_chunk: int = 0):
+                 spread_chunk: int = 0, vector_spread: bool = False):
         lib = load_library()
         r = _dev_f64(r, "r")
         omega = _dev_f64(omega, "omega")
         self.n = r.numel()
         self.m = omega.numel()
         self.device = r.device
-        opts = NuhtOpts(min_size, M, split_candidates, precision, dft_max, spread_chunk, 0)
+        opts = NuhtOpts(min_size, M, split_candidates, precision, dft_max, spread_chunk, 0,
+                        1 if vector_spread else 0)
         h = ctypes.c_void_p()
         _check(lib.nuht_plan(ctypes.byref(h), int(nu), float(eps), self.n, _ptr(r), self.m, _ptr(omega),
                              ctypes.byref(opts), _stream()))
@@ -246,7 +249,7 @@ class Batch:
         m_a = (ctypes.c_int64 * k)(*self.m)
         r_a = (ctypes.c_void_p * k)(*[_ptr(r).value for r, _ in self._keep])
         w_a = (ctypes.c_void_p * k)(*[_ptr(w).value for _, w in self._keep])
-        opts = NuhtOpts(min_size, 0, 0, NUHT_FP64, dft_max, spread_chunk, 1 if tune else 0)
+        opts = NuhtOpts(min_size, 0, 0, NUHT_FP64, dft_max, spread_chunk, 1 if tune else 0, 0)
         h = ctypes.c_void_p()
         _check(lib.nuht_plan_many(ctypes.byref(h), k, nu_a, float(eps), n_a, r_a, m_a, w_a, ctypes.byref(opts),
                                   _stream()))

@@ -518,7 +518,7 @@ static void fill_params(PlanDev& P, int nu, double eps, const nuht_opts& o)
     P.L = local_rank(anu, eps, P.z);
     P.w = es_width(eps, o.precision);
     P.fp32 = o.precision == NUHT_FP32_SPREAD ? 1 : 0;
-    P.mfma = (!P.fp32 && P.w <= 16 && P.nch <= 16) ? 1 : 0;
+    P.mfma = (!P.fp32 && P.w <= 16 && P.nch <= 16 && !o.vector_spread) ? 1 : 0;
     P.beta = es_beta(P.w);
     for (int p = 0; p < 2 * M + 2; ++p) P.hank[p] = hankel_coef(anu, p);
     for (int p = 0; p < kMaxChannels; ++p)
@@ -1378,6 +1378,8 @@ int nuht_plan_info(nuht_plan_t p, nuht_info* info)
     info->min_size = p->opts.min_size > 0 ? p->opts.min_size : 1024;
     info->dft_max = p->opts.dft_max == 0 ? 48 : p->opts.dft_max;
     info->spread_chunk = P.spread_chunk;
+    info->spread_items = S.n_aitems;
+    info->dense_items = S.n_adense;
     return NUHT_OK;
 }
 

@@ -92,3 +92,31 @@ def test_new_entry_points_reject_invalid_arguments_without_gpu(lib):
     o = nuht.NuhtOpts(0, 0, 0, 0, 0, 17, 0)                                                     # spread_chunk < 64
     n = one(ctypes.c_int64, 0)
     assert many(ctypes.byref(h), 1, nu, 1e-12, n, r, m, w, ctypes.byref(o), None) == -1
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    # The binding's ctypes mirrors of nuht_opts and nuht_info must have the
+    # C layout: a C program compiled against include/nuht.h prints the size
+    # and every field offset, which are compared with ctypes' own.
+    import shutil
+    import subprocess
+    import paper_2411_09583_amd as nuht
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include "nuht.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void) {"]
+    for cname, cls in (("nuht_opts", nuht.NuhtOpts), ("nuht_info", nuht.NuhtInfo)):
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'    printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in (("nuht_opts", nuht.NuhtOpts), ("nuht_info", nuht.NuhtInfo)):
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
