@@ -1056,7 +1056,7 @@ __global__ void k_fill_zero(double* __restrict__ x, int64_t n)
 // the local blocks, the direct-block sum from k_direct_blocks and ga, and
 // writes g once in the caller's order.
 template <int NCH>
-__global__ __launch_bounds__(256) void k_rows_asy(PlanDev P, const double2* __restrict__ grids,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_rows_asy(PlanDev P, const double2* __restrict__ grids,
                                                   double* __restrict__ ga)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x;

@@ -199,25 +199,50 @@ __device__ __forceinline__ double besselj_eps(const PlanDev& P, double xh, doubl
     return xh > P.z ? besselj_hankel(P, xh, xl) : besselj_miller(P.nu, xh, xl);
 }
 
+// One step k -> k-1 of Miller's backward recurrence y_{k-1} = (2k/x) y_k - y_{k+1}
+// (kd = k as a double, rec = 2/x), adding 2 y_k^2 to the normalisation sum
+// S = y_0^2 + 2 sum_{k>=1} y_k^2.  When y_k grows past 2^332 everything held
+// (the recurrence pair, S and the values kept so far) is scaled by 2^-332,
+// exactly, so the result does not depend on where the scaling happens.
+__device__ __forceinline__ void miller_step(double kd, double rec, double& yk, double& yk1, double& S,
+                                            double& a, double& b, double& c)
+{
+    S = __builtin_fma(yk + yk, yk, S);
+    const double ykm1 = __builtin_fma(kd * rec, yk, -yk1);
+    yk1 = yk;
+    yk = ykm1;
+    if (fabs(yk) > 0x1p332) {
+        yk *= 0x1p-332; yk1 *= 0x1p-332; S *= 0x1p-664;
+        a *= 0x1p-332; b *= 0x1p-332; c *= 0x1p-332;
+    }
+}
+
 // J_nu(x) to full FP64 accuracy: Hankel's expansion summed until its terms
 // fall below 1e-17 where it converges that far (x >= 25, terms never above
 // 1e3), Miller's recurrence otherwise.  Used for the direct blocks.
 __device__ inline double besselj_full(const PlanDev& P, double xh, double xl)
 {
     if (xh >= 25.0) {
+        // terms t_k = prod_{i<=k} (mu - (2i-1)^2) / (8 x i); odd k go to Q, even
+        // k to P, with sign (-1)^floor(k/2): one odd and one even term per step
         const double mu = 4.0 * (double)P.nu * (double)P.nu;
         const double inv8x = 0.125 / xh;
         double t = 1.0, p = 1.0, q = 0.0, prev = 1e300;
         bool ok = false;
-        for (int k = 1; k < 120; ++k) {
-            double f = 2.0 * k - 1.0;
-            t *= (mu - f * f) * inv8x * kInvInt[k];
-            double at = fabs(t);
-            double sg = ((k >> 1) & 1) ? -1.0 : 1.0;
-            if (k & 1) q = __builtin_fma(sg, t, q); else p = __builtin_fma(sg, t, p);
-            if (at < 1e-17) { ok = true; break; }
-            if ((at > prev && k > 2) || at > 1e3) break;
-            prev = at;
+        for (int k = 1; k < 119; k += 2) {
+            const double f1 = 2.0 * k - 1.0, f2 = f1 + 2.0;
+            const double sg = ((k >> 1) & 1) ? -1.0 : 1.0;       // (-1)^floor(k/2); the even term k+1 has -sg
+            const double t1 = t * ((mu - f1 * f1) * inv8x * kInvInt[k]);
+            const double t2 = t1 * ((mu - f2 * f2) * inv8x * kInvInt[k + 1]);
+            const double a1 = fabs(t1), a2 = fabs(t2);
+            q = __builtin_fma(sg, t1, q);
+            if (a1 < 1e-17) { ok = true; break; }
+            if ((a1 > prev && k > 2) || a1 > 1e3) break;
+            p = __builtin_fma(-sg, t2, p);
+            if (a2 < 1e-17) { ok = true; break; }
+            if ((k > 1 && a2 > a1) || a2 > 1e3) break;
+            prev = a2;
+            t = t2;
         }
         if (ok) {
             dd ph = two_sum(xh, P.phi_hi);
@@ -227,27 +252,27 @@ __device__ inline double besselj_full(const PlanDev& P, double xh, double xl)
         }
     }
     if (xh < 1e-30) return P.nu == 0 ? 1.0 : 0.0;
-    double top = (double)(P.nu + 1) > xh ? (double)(P.nu + 1) : xh;
-    int N = (int)(top + 12.0 + 8.0 * cbrt(xh > 1.0 ? xh : 1.0));
-    double rec = 2.0 / xh;
+    const int nu = P.nu;
+    const double top = (double)(nu + 1) > xh ? (double)(nu + 1) : xh;
+    const int N = (int)(top + 12.0 + 8.0 * cbrt(xh > 1.0 ? xh : 1.0));   // >= nu + 13
+    const double rec = 2.0 / xh;
     double yk1 = 0.0, yk = 1e-100, S = 0.0;
     double jm = 0.0, j0 = 0.0, jp = 0.0;
-    const int nu = P.nu;
-    for (int k = N; k >= 0; --k) {
-        if (k == nu + 1) jp = yk;
-        if (k == nu) j0 = yk;
-        if (k == nu - 1) jm = yk;
-        S = __builtin_fma(k == 0 ? yk : 2.0 * yk, yk, S);
-        if (k == 0) break;
-        double ykm1 = __builtin_fma((double)k * rec, yk, -yk1);
-        yk1 = yk;
-        yk = ykm1;
-        if (fabs(yk) > 1e100) {
-            yk *= 1e-100; yk1 *= 1e-100; S *= 1e-200;
-            jm *= 1e-100; j0 *= 1e-100; jp *= 1e-100;
-        }
+    double kd = (double)N;
+    // k = N .. nu + 2: nothing kept
+    for (int k = N; k > nu + 1; --k, kd -= 1.0) miller_step(kd, rec, yk, yk1, S, jm, j0, jp);
+    jp = yk;                                                     // y_{nu+1}
+    miller_step(kd, rec, yk, yk1, S, jm, j0, jp);
+    kd -= 1.0;
+    j0 = yk;                                                     // y_nu
+    if (nu > 0) {
+        miller_step(kd, rec, yk, yk1, S, jm, j0, jp);
+        kd -= 1.0;
+        jm = yk;                                                 // y_{nu-1}
+        for (int k = nu - 1; k > 0; --k, kd -= 1.0) miller_step(kd, rec, yk, yk1, S, jm, j0, jp);
     }
-    double d = nu == 0 ? -jp : 0.5 * (jm - jp);
+    S = __builtin_fma(yk, yk, S);                                // k = 0 counts once
+    const double d = nu == 0 ? -jp : 0.5 * (jm - jp);
     return __builtin_fma(xl, d, j0) / sqrt(S);
 }
 

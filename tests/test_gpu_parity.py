@@ -281,3 +281,25 @@ def test_repeatable(nuht):
     b = host(p.execute(dev(c)))
     p.close()
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("nu", [0, 1, 2, 5, 13, 40, 100])
+def test_gpu_besselj_pointwise(nuht, nu):
+    # The library's full-precision J_nu (used by the direct blocks) entry by
+    # entry: with one point r = 1 and weight 1, the direct sum returns
+    # J_nu(omega_j).  Arguments span 1e-8 .. 3e3, with a dense band around 25
+    # (Hankel series above, Miller below) and around nu.  Bar: |error| <=
+    # 1e-13 max(|J|, env(x)), env = min(1, sqrt(2 / (pi x))) the large-x
+    # envelope: near zeros of J the error is set by rounding at the scale of
+    # the envelope (largest seen: 2.4e-14 env, order 100 at x = 242, where the
+    # series diverges and Miller's recurrence runs ~300 steps).
+    x = np.concatenate([np.logspace(-8, np.log10(3e3), 400), np.linspace(20.0, 30.0, 101),
+                        np.linspace(max(nu - 5.0, 0.5), nu + 5.0, 51)])
+    g = host(nuht.direct(dev(np.ones(1)), dev(np.ones(1)), dev(x), nu, 1e-12))
+    ref = direct.besselj(nu, x)
+    env = np.minimum(1.0, np.sqrt(2.0 / (np.pi * x)))
+    err = np.abs(g - ref)
+    bound = 1e-13 * np.maximum(np.abs(ref), env)
+    worst = np.argmax(err / bound)
+    print(nu, "worst x", x[worst], "err", err[worst], "J", ref[worst])
+    assert np.all(err <= bound), (x[worst], g[worst], ref[worst])
