@@ -96,22 +96,27 @@ __global__ __launch_bounds__(64) void k_lmom(PlanDev P, const double* __restrict
         double acc[32];
         #pragma unroll
         for (int q = 0; q < 32; ++q) acc[q] = 0.0;
-        for (int k = I.ka + lane; k < I.kb; k += 64) {
-            double y = P.rs[k] / B.R;
-            double c = cs[k];
-            double u = __builtin_fma(2.0 * y, y, -1.0);
-            double u2 = 2.0 * u;
-            double t0, t1;
-            if (odd) { t0 = y; t1 = y * (u2 - 1.0); } else { t0 = 1.0; t1 = u; }
+        // two points per lane per step (the second with weight 0 past the end):
+        // both loads issue together and the recurrences are independent chains
+        for (int k = I.ka + lane; k < I.kb; k += 128) {
+            const bool two = k + 64 < I.kb;
+            const int k2 = two ? k + 64 : k;
+            const double ya = P.rs[k] / B.R, yb = P.rs[k2] / B.R;
+            const double ca = cs[k], cb = two ? cs[k2] : 0.0;
+            const double ua2 = 2.0 * __builtin_fma(2.0 * ya, ya, -1.0);
+            const double ub2 = 2.0 * __builtin_fma(2.0 * yb, yb, -1.0);
+            double a0, a1, b0, b1;
+            if (odd) { a0 = ya; a1 = ya * (ua2 - 1.0); b0 = yb; b1 = yb * (ub2 - 1.0); }
+            else { a0 = 1.0; a1 = 0.5 * ua2; b0 = 1.0; b1 = 0.5 * ub2; }
             for (int l = 0; l < s0; ++l) {
-                double t2 = __builtin_fma(u2, t1, -t0);
-                t0 = t1; t1 = t2;
+                const double a2 = __builtin_fma(ua2, a1, -a0), b2 = __builtin_fma(ub2, b1, -b0);
+                a0 = a1; a1 = a2; b0 = b1; b1 = b2;
             }
             #pragma unroll
             for (int q = 0; q < 32; ++q) {
-                acc[q] = __builtin_fma(c, t0, acc[q]);
-                double t2 = __builtin_fma(u2, t1, -t0);
-                t0 = t1; t1 = t2;
+                acc[q] = __builtin_fma(cb, b0, __builtin_fma(ca, a0, acc[q]));
+                const double a2 = __builtin_fma(ua2, a1, -a0), b2 = __builtin_fma(ub2, b1, -b0);
+                a0 = a1; a1 = a2; b0 = b1; b1 = b2;
             }
         }
         // Reduce-scatter over the wave: at offsets 16, 8, 4, 2, 1 each lane
@@ -953,11 +958,11 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
         dd q = two_sum(ph.hi, a0.hi);
         ph.hi = q.hi;
         ph_lo += q.lo + __builtin_fma((double)B.llo, tl, a0.lo);
-        double zr = 1.0, zi = 0.0;
         double s1, c1;
         sincos_small(th, &s1, &c1);
-        double er = c1 - tl * s1, ei = s1 + tl * c1;
-        for (int cix = 0; cix < B.N1; ++cix) {
+        const double er = c1 - tl * s1, ei = s1 + tl * c1;
+        // Horner's rule in e^{i theta} from the last cell down
+        for (int cix = B.N1 - 1; cix >= 0; --cix) {
             const double2* gp = G + (int64_t)cix * NCH;
             double2 gv[NCH];
             #pragma unroll
@@ -968,11 +973,9 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
                 br = __builtin_fma(gv[p].x, gpow[p], br);
                 bi = __builtin_fma(gv[p].y, gpow[p], bi);
             }
-            ar = __builtin_fma(br, zr, __builtin_fma(-bi, zi, ar));
-            ai = __builtin_fma(br, zi, __builtin_fma(bi, zr, ai));
-            double tr = __builtin_fma(zr, er, -zi * ei);
-            zi = __builtin_fma(zr, ei, zi * er);
-            zr = tr;
+            const double tr = __builtin_fma(ar, er, __builtin_fma(-ai, ei, br));
+            ai = __builtin_fma(ar, ei, __builtin_fma(ai, er, bi));
+            ar = tr;
         }
     } else {
         const double2* Aq = grids + B.grid_off;
