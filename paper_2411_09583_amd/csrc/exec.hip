@@ -713,19 +713,43 @@ __device__ void lds_fft(double2* sm, int N, int logN, int lines, int ls, int es)
     }
 }
 
-// One transform of N <= 4096 points per block (block = (FFT-list slot, channel)).
-__global__ __launch_bounds__(256) void k_fft_small(PlanDev P, double2* __restrict__ grids, int first, int logN)
+// Transforms of N <= 4096 points, every size class in one launch: workgroup
+// g belongs to class c when wg0[c] <= g < wg0[c + 1], and within it to the
+// FFT-list slot (g - wg0[c]) / nch of the class and channel (g - wg0[c]) % nch.
+struct SmallFfts {
+    int32_t n;                 // classes
+    int32_t log2n[8], first[8];
+    int32_t wg0[9];
+};
+
+__global__ __launch_bounds__(256) void k_fft_small(PlanDev P, double2* __restrict__ grids, SmallFfts F)
 {
     extern __shared__ double2 sm[];
-    const int N = 1 << logN;
+    const int g = blockIdx.x;
+    int c = 0;
+    while (c + 1 < F.n && g >= F.wg0[c + 1]) ++c;
+    const int logN = F.log2n[c], N = 1 << logN;
     const int nch = P.nch;
-    int slot = blockIdx.x / nch, ch = blockIdx.x % nch;
-    const ABlock B = P.ab[P.fft_list[first + slot]];
+    const int loc = g - F.wg0[c];
+    const int slot = loc / nch, ch = loc % nch;
+    const ABlock B = P.ab[P.fft_list[F.first[c] + slot]];
     double2* x = grids + B.grid_off + (int64_t)ch * N;
     for (int i = threadIdx.x; i < N; i += blockDim.x) sm[i] = x[i];
     __syncthreads();
     lds_fft(sm, N, logN, 1, 0, 1);
     for (int i = threadIdx.x; i < N; i += blockDim.x) x[i] = sm[i];
+}
+
+// Points per workgroup in the two passes (lines x line length).
+constexpr int kFftTile = 1024;
+
+// Lines of length len per workgroup in a pass over `count` lines: as many as
+// fill kFftTile points (len <= 4096, so at least one).
+__host__ __device__ inline int fft_lines(int len, int count)
+{
+    int l = kFftTile / len;
+    if (l < 1) l = 1;
+    return l < count ? l : count;
 }
 
 // Two-pass FFT for N = N1 * N2 > 4096 (four-step): pass A transforms the N2
@@ -738,7 +762,7 @@ __global__ __launch_bounds__(256) void k_fft_pass_a(PlanDev P, double2* __restri
     extern __shared__ double2 sm[];
     const int N = 1 << logN, N1 = 1 << logN1, N2 = N >> logN1;
     const int nch = P.nch;
-    const int lines = (4096 / N1) < N2 ? (4096 / N1) : N2;
+    const int lines = fft_lines(N1, N2);
     const int groups = N2 / lines;
     int tr = blockIdx.x / groups, grp = blockIdx.x % groups;
     int slot = tr / nch, ch = tr % nch;
@@ -769,7 +793,7 @@ __global__ __launch_bounds__(256) void k_fft_pass_b(PlanDev P, double2* __restri
     const int N = 1 << logN, N1 = 1 << logN1, N2 = N >> logN1;
     const int logN2 = logN - logN1;
     const int nch = P.nch;
-    const int lines = (4096 / N2) < N1 ? (4096 / N2) : N1;
+    const int lines = fft_lines(N2, N1);
     const int groups = N1 / lines;
     int tr = blockIdx.x / groups, grp = blockIdx.x % groups;
     int slot = tr / nch, ch = tr % nch;
@@ -1259,17 +1283,29 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
                                B.part, B.grids, B.grid_cells);
     }
     mark(marks, 4, s);
+    SmallFfts small{};
+    int small_wg = 0, small_log = 0;
+    for (int q = 0; q < ncls; ++q) {
+        const FftClass& C = cls[q];
+        if (C.log2n > 12 || small.n == 8) continue;
+        small.log2n[small.n] = C.log2n;
+        small.first[small.n] = C.first;
+        small.wg0[small.n] = small_wg;
+        small_wg += C.count * P.nch;
+        small_log = C.log2n > small_log ? C.log2n : small_log;
+        ++small.n;
+    }
+    small.wg0[small.n] = small_wg;
+    if (small_wg > 0)
+        hipLaunchKernelGGL(k_fft_small, dim3(small_wg), dim3(256), sizeof(double2) << small_log, s, P, B.grids, small);
     for (int q = 0; q < ncls; ++q) {
         const FftClass& C = cls[q];
         int ntr = C.count * P.nch;
-        if (C.log2n <= 12) {
-            hipLaunchKernelGGL(k_fft_small, dim3(ntr), dim3(256), sizeof(double2) << C.log2n, s, P, B.grids,
-                               C.first, C.log2n);
-        } else {
+        if (C.log2n > 12) {
             int logN1 = C.log2n / 2;
             int N1 = 1 << logN1, N2 = 1 << (C.log2n - logN1);
-            int la = (4096 / N1) < N2 ? (4096 / N1) : N2;
-            int lb = (4096 / N2) < N1 ? (4096 / N2) : N1;
+            int la = fft_lines(N1, N2);
+            int lb = fft_lines(N2, N1);
             hipLaunchKernelGGL(k_fft_pass_a, dim3(ntr * (N2 / la)), dim3(256), sizeof(double2) * N1 * la, s, P,
                                B.grids, B.scratch, C.first, C.log2n, logN1, C.scratch_off);
             hipLaunchKernelGGL(k_fft_pass_b, dim3(ntr * (N1 / lb)), dim3(256), sizeof(double2) * N2 * lb, s, P,

@@ -11,7 +11,7 @@
 namespace nuht {
 
 constexpr int kMaxChannels = 40;       // 2M with M <= 20 (eq. num-asy-terms caps M at 20)
-constexpr int kMaxFftLog2 = 26;        // largest FFT of an asymptotic block: 2^26 points
+constexpr int kMaxFftLog2 = 24;        // largest FFT of an asymptotic block: 2^24 = 4096^2 points (two passes)
 constexpr int kLocalChunk = 4096;      // columns per local-moment work item
 constexpr int kSpreadChunk = 1024;     // default points per spreading work item (a plan option)
 constexpr int kMaxEsWidth = 18;        // largest ES kernel width

@@ -303,3 +303,25 @@ def test_gpu_besselj_pointwise(nuht, nu):
     worst = np.argmax(err / bound)
     print(nu, "worst x", x[worst], "err", err[worst], "J", ref[worst])
     assert np.all(err <= bound), (x[worst], g[worst], ref[worst])
+
+
+def test_largest_fft_and_grid_limit(nuht):
+    # One wholly asymptotic block (every omega r > z) whose spread grid needs
+    # the largest two-pass FFT (2^23 .. 2^24 points per channel): r in [1, 2],
+    # omega in [1e3, 1e7].  Then omega up to 1e9: the grid would exceed 2^24
+    # points, and planning must fail with the capacity error, not launch.
+    rng = np.random.default_rng(130)
+    r = rng.uniform(1.0, 2.0, 200)
+    c = rng.standard_normal(200)
+    w = np.sort(rng.uniform(1.0e3, 1.0e7, 2000))
+    p = nuht.Plan(dev(r), dev(w), 0, 1e-12)
+    info = p.info()
+    g = host(p.execute(dev(c)))
+    p.close()
+    print("fft points", info["fft_points"], "blocks", info["n_asy"], info["n_local"], info["n_direct"])
+    assert info["n_fft_blocks"] >= 1 and info["fft_points"] >= 2 ** 23
+    assert rel_l2(g, direct.dht(0, r, c, w)) <= TOL
+    w_big = np.sort(rng.uniform(1.0e3, 1.0e9, 2000))
+    with pytest.raises(nuht.NuhtError) as err:
+        nuht.Plan(dev(r), dev(w_big), 0, 1e-12)
+    assert err.value.code == -6
