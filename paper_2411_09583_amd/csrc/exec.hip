@@ -566,11 +566,16 @@ __global__ void k_spread_reduce(PlanDev P, const double2* __restrict__ part, dou
         int32_t mid = (lo + hi + 1) >> 1;
         if (P.gslot[mid] <= slot0) lo = mid; else hi = mid - 1;
     }
+    // the wave's last slot: when it lies in the same block as the first, the
+    // block's fields are read once through the scalar unit
+    const int64_t tl = t0 + 63 < total ? t0 + 63 : total - 1;
+    const int64_t slot_last = __builtin_amdgcn_readfirstlane((int32_t)(tl / nch));
+    const bool one_block = P.gslot[lo + 1] > slot_last;
     if (t >= total) return;
     int64_t slot = t / nch;
     int p = (int)(t % nch);
     while (P.gslot[lo + 1] <= slot) ++lo;
-    const ABlock B = P.ab[lo];
+    const ABlock B = one_block ? P.ab[__builtin_amdgcn_readfirstlane(lo)] : P.ab[lo];
     int64_t local = slot - P.gslot[lo];
     int32_t l;
     if (B.fft) l = local < B.N2 / 2 ? (int32_t)local : (int32_t)(local - B.N2);
@@ -595,6 +600,16 @@ __global__ void k_spread_reduce(PlanDev P, const double2* __restrict__ part, dou
             if (P.aitems[mid].sub_lo <= l) b = mid + 1; else hi = mid;
         }
         int32_t it = a;
+        for (; it + 16 <= b; it += 16) {
+            double2 v[16];
+            #pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const Item& I = P.aitems[it + q];
+                v[q] = load_partial<PT>(part, I.off + (int64_t)(l - I.sub_lo) * nch + p);
+            }
+            #pragma unroll
+            for (int q = 0; q < 16; ++q) { sr += v[q].x; si += v[q].y; }
+        }
         for (; it + 4 <= b; it += 4) {
             double2 v[4];
             #pragma unroll
