@@ -358,13 +358,14 @@ def main():
     #               per point membership): 2M complex channels x (2 add + 2 mul)
     #               plus the kernel-weight product: 8M + 2
     #   k_rows_asy  every (row, cell) pair of a direct-sum-path block: channel
-    #               sum (2M-1) x 4, complex product 8, phase rotation 6: 8M + 10;
-    #               every (row, tap) pair of an FFT-path block: (2M-1) x 4 + 4 = 8M
+    #               sum (2M-1) x 4, one complex multiply-add of Horner's rule over
+    #               the cells 8: 8M + 4; every (row, tap) pair of an FFT-path
+    #               block: (2M-1) x 4 + 4 = 8M
     def flops(stage, inf):
         M, w = inf["M"], inf["es_width"]
         if stage == "spread":
             return inf["asy_col_members"] * w * (8.0 * M + 2.0)
-        return inf["dft_row_cells"] * (8.0 * M + 10.0) + inf["fft_row_members"] * w * 8.0 * M
+        return inf["dft_row_cells"] * (8.0 * M + 4.0) + inf["fft_row_members"] * w * 8.0 * M
 
     kern = {"spread": "k_spread_mfma+k_spread", "rows_asymptotic": "k_rows_asy"}
     tfile = {"spread": "spread_stage", "rows_asymptotic": "k_rows_asy"}   # traffic summaries

@@ -126,7 +126,10 @@ typedef struct {
  * released only after the last of them.  Every argument is validated:
  * n, m >= 0; r_dev / omega_dev non-null when n / m > 0; |nu| <= 100;
  * 1e-15 <= eps <= 1e-2; all r, omega finite and >= 0 (else NUHT_EDOMAIN).
- * n == 0 or m == 0 is valid (the transform then writes zeros).
+ * n == 0 or m == 0 is valid (the transform then writes zeros).  An
+ * asymptotic block whose spread grid would need an FFT of more than 2^24
+ * points per channel (a block spanning a product of point range and
+ * frequency range above about 3e6) makes the call fail with NUHT_ECAPACITY.
  */
 int nuht_plan(nuht_plan_t *plan, int nu, double eps,
               int64_t n, const double *r_dev, int64_t m, const double *omega_dev,
