@@ -128,8 +128,9 @@ typedef struct {
  * 1e-15 <= eps <= 1e-2; all r, omega finite and >= 0 (else NUHT_EDOMAIN).
  * n == 0 or m == 0 is valid (the transform then writes zeros).  An
  * asymptotic block whose spread grid would need an FFT of more than 2^24
- * points per channel (a block spanning a product of point range and
- * frequency range above about 3e6) makes the call fail with NUHT_ECAPACITY.
+ * points per channel (half its point range times half its frequency range
+ * above about 1.6e6 to 3.3e6, the grid spacing being a power of two) makes
+ * the call fail with NUHT_ECAPACITY.
  */
 int nuht_plan(nuht_plan_t *plan, int nu, double eps,
               int64_t n, const double *r_dev, int64_t m, const double *omega_dev,
