@@ -850,6 +850,11 @@ __device__ __forceinline__ void miller_rescale(double& yk, double& yk1, double& 
     if (fabs(yk) > 1e100) { yk *= 1e-100; yk1 *= 1e-100; S2 *= 1e-200; dot *= 1e-200; }
 }
 
+// Four consecutive local moments (8-byte aligned, read as one block).
+struct Moments4 {
+    double v[4];
+};
+
 template <int MODE>
 __device__ double local_eval(const PlanDev& P, int lblk, double om, const double* __restrict__ lmom,
                              double* __restrict__ ring, int stride)
@@ -860,9 +865,17 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
     const int nu = MODE == 0 ? 0 : (MODE == 1 ? 1 : P.nu), L = P.L;
     if (y < 1e-30) return nu == 0 ? t[0] : 0.0;
     // the pairing reads J_{nu-i} for i <= nu/2, so the recurrence must have
-    // produced every index up to nu
+    // produced every index up to nu; it also starts above every index a
+    // product needs, so that the product phase runs over the same indices in
+    // every lane (its index, and with it the moment loads, stay wave-uniform;
+    // a higher start only makes the recurrence more accurate)
     int N = miller_start(y);
     if (N < nu + 1) N = nu + 1;
+    {
+        const int a_ = (MODE == 2 && (nu & 1)) ? (nu - 1) >> 1 : nu >> 1;
+        const int top_ = MODE == 2 ? ((L - a_) > a_ ? (L - a_) : a_) : L;
+        if (N < top_ + 1) N = top_ + 1;
+    }
     const double rec = 2.0 / y;
     double yk1 = 0.0, yk = 1e-100, S2 = 0.0, dot = 0.0;
     if (MODE == 0) {
@@ -874,14 +887,22 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
             yk1 = yk; yk = ykm1;
             miller_rescale(yk, yk1, S2, dot);
         }
-        for (; i >= 1; --i) {
+        // i = L .. 1 in every lane (the start is above L): L mod 4 single
+        // steps, then groups of four whose moments t[i-3 .. i] are read together
+        auto step = [&](int k, double tk) {
             double q = yk * yk;
             S2 = __builtin_fma(2.0, q, S2);
-            double c = 2.0 * t[i];
-            dot = __builtin_fma((i & 1) ? -c : c, q, dot);
-            double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
+            double c = 2.0 * tk;
+            dot = __builtin_fma((k & 1) ? -c : c, q, dot);
+            double ykm1 = __builtin_fma((double)k * rec, yk, -yk1);
             yk1 = yk; yk = ykm1;
             miller_rescale(yk, yk1, S2, dot);
+        };
+        for (int u = L & 3; u > 0; --u, --i) step(i, t[i]);
+        for (; i >= 4; i -= 4) {
+            Moments4 q;
+            __builtin_memcpy(&q, t + i - 3, sizeof q);     // t[i-3 .. i] in one read
+            step(i, q.v[3]); step(i - 1, q.v[2]); step(i - 2, q.v[1]); step(i - 3, q.v[0]);
         }
         S2 = __builtin_fma(yk, yk, S2);
         dot = __builtin_fma(t[0] * yk, yk, dot);
@@ -895,13 +916,19 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
             yk1 = yk; yk = ykm1;
             miller_rescale(yk, yk1, S2, dot);
         }
-        for (; i >= 1; --i) {
+        auto step = [&](int k, double tk) {
             S2 = __builtin_fma(2.0 * yk, yk, S2);
-            double c = 2.0 * t[i];
-            dot = __builtin_fma(((i & 1) ? -c : c) * yk, yk1, dot);
-            double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
+            double c = 2.0 * tk;
+            dot = __builtin_fma(((k & 1) ? -c : c) * yk, yk1, dot);
+            double ykm1 = __builtin_fma((double)k * rec, yk, -yk1);
             yk1 = yk; yk = ykm1;
             miller_rescale(yk, yk1, S2, dot);
+        };
+        for (int u = L & 3; u > 0; --u, --i) step(i, t[i]);
+        for (; i >= 4; i -= 4) {
+            Moments4 q;
+            __builtin_memcpy(&q, t + i - 3, sizeof q);     // t[i-3 .. i] in one read
+            step(i, q.v[3]); step(i - 1, q.v[2]); step(i - 2, q.v[1]); step(i - 3, q.v[0]);
         }
         S2 = __builtin_fma(yk, yk, S2);
         dot = __builtin_fma(2.0 * t[0] * yk, yk1, dot);
