@@ -999,12 +999,35 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
 // wave is in the same block (the usual case, frequencies being sorted); the
 // block's fields and its direct-sum grid are then read through the scalar
 // unit and broadcast to all lanes.
+// 1/sqrt(x) and 1/x for positive normal x: the hardware estimate refined by two
+// Newton steps (to within an ulp or two; cheaper than IEEE division and sqrt).
+__device__ __forceinline__ double rsqrt_refined(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    #pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double h = 0.5 * x * y;
+        y = __builtin_fma(y, __builtin_fma(-h, y, 0.5), y);    // y (3/2 - x y^2 / 2)
+    }
+    return y;
+}
+
+__device__ __forceinline__ double rcp_refined(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    #pragma unroll
+    for (int k = 0; k < 2; ++k) y = __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+    return y;
+}
+
 template <int NCH>
 __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2* __restrict__ grids)
 {
     const ABlock B = P.ab[ablk];
     const int w = P.w;
-    const double gam = 1.0 / (om * B.r0);
+    // gamma = 1/(om r0) and its square root (om r0 > z > 0 on an asymptotic block)
+    const double rs = rsqrt_refined(om * B.r0);
+    const double gam = rs * rs;
     double gpow[NCH];
     gpow[0] = 1.0;
     #pragma unroll
@@ -1073,10 +1096,10 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
         ai *= sc;
     }
     double kap = fabs(sp.hi) * B.alpha;
-    double scale = B.h / (B.alpha * eshat(P, kap));
+    double scale = B.h * rcp_refined(B.alpha * eshat(P, kap));
     double cr, ci;
     cis_dd(ph.hi, ph_lo, cr, ci);
-    double amp = sqrt(gam) * scale;
+    double amp = rs * scale;
     return kSqrt2OverPi * amp * __builtin_fma(cr, ar, -ci * ai);
 }
 
