@@ -182,14 +182,25 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
         lstart[d] = wc + ic - cnt;
         lpos[d] = wc + ic - cnt;
     }
+    // the tile's keys and values, all loaded before the first round (one
+    // memory round trip per tile instead of one per round)
+    uint64_t kr[kSortRounds];
+    int32_t vr[kSortRounds];
+    #pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int i = start + r * kSortThreads + threadIdx.x;
+        kr[r] = i < end ? kin[i] : 0ull;
+        vr[r] = i < end ? vin[i] : 0;
+    }
+    #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
         for (int q = threadIdx.x; q < (kSortThreads / 64) * 256; q += kSortThreads)
             (&wcnt[0][0])[q] = 0;
         __syncthreads();
         int i = start + r * kSortThreads + threadIdx.x;
         bool valid = i < end;
-        uint64_t k = valid ? kin[i] : 0ull;
-        int32_t v = valid ? vin[i] : 0;
+        uint64_t k = kr[r];
+        int32_t v = vr[r];
         int d = (int)((k >> shift) & 255);
         uint64_t peers = __ballot(valid);
         #pragma unroll
