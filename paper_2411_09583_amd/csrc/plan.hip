@@ -274,6 +274,9 @@ struct NodeSplit {
     bool cl, ca, ur_m, ur_d, ll_m, ll_d;
 };
 
+// Candidate counts up to this are evaluated with all their loads in flight.
+constexpr int32_t kSplitUnroll = 16;
+
 // kj1 = K[R.j1], kj0 = K[R.j0], jc = Jc[R.k0], loaded by the caller.
 __device__ __forceinline__ NodeSplit split_node(const Rect& R, int32_t kj1, int32_t kj0, int32_t jc,
                                                 const int32_t* __restrict__ K, int64_t min_size, int32_t ncand)
@@ -291,14 +294,35 @@ __device__ __forceinline__ NodeSplit split_node(const Rect& R, int32_t kj1, int3
         int64_t best = INT64_MAX;
         int32_t span = jl - R.j0;
         int32_t nc = span > 0 ? ncand : 1;
-        #pragma unroll 4
-        for (int32_t c = 0; c < nc; ++c) {
-            int32_t j = span > 0 ? R.j0 + (int32_t)(((int64_t)c * span) / (nc - 1)) : R.j0;
-            int32_t k = K[j] - 1;
+        // candidate c is row j0 + floor(c span / (nc - 1)); the quotient is
+        // formed in double, exactly: c span < 2^53, and a non-integer quotient
+        // is at least 1/(nc-1) away from an integer
+        auto row_of = [&](int32_t c) {
+            return span > 0 ? R.j0 + (int32_t)floor((double)c * (double)span / (double)(nc - 1)) : R.j0;
+        };
+        auto consider = [&](int32_t j, int32_t kraw) {
+            int32_t k = kraw - 1;
             if (k > R.k1) k = R.k1;
             if (k < R.k0) k = R.k0 - 1;
             int64_t mixed = (int64_t)(j - R.j0 + 1) * (R.k1 - k) + (int64_t)(R.j1 - j) * (k - R.k0 + 1);
             if (mixed < best) { best = mixed; js = j; ks = k; }
+        };
+        if (nc <= kSplitUnroll) {
+            // all candidate loads in flight together, then taken in order
+            int32_t jv[kSplitUnroll], kv[kSplitUnroll];
+            #pragma unroll
+            for (int32_t c = 0; c < kSplitUnroll; ++c) {
+                jv[c] = row_of(c < nc ? c : 0);
+                kv[c] = K[jv[c]];
+            }
+            #pragma unroll
+            for (int32_t c = 0; c < kSplitUnroll; ++c)
+                if (c < nc) consider(jv[c], kv[c]);
+        } else {
+            for (int32_t c = 0; c < nc; ++c) {
+                const int32_t j = row_of(c);
+                consider(j, K[j]);
+            }
         }
     }
     o.js = js; o.ks = ks;
