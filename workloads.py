@@ -92,3 +92,42 @@ def differentiation(seed: int = 6, n: int = 1_000_000, m: int = 1_000_000):
     c = rng.standard_normal(n)
     y = rng.standard_normal(m)
     return r, w, c, y
+
+
+def random_case(seed: int):
+    """A seeded random transform for broad parity checks.
+
+    Returns (nu, eps, r, w, c, kind): n, m log-uniform in [1, 4000]; order
+    nu in [-8, 20]; eps in {1e-4, 1e-6, 1e-8, 1e-10, 1e-12}; the product range
+    rmax * wmax log-uniform in [10, 2e4]; kind picks the distributions:
+    'uniform' (r ~ U[0, rmax), w ~ U[0, wmax)), 'clustered' (r ~ |N(rmax/2,
+    rmax/20)|, w ~ U[wmax/2, wmax)), 'log' (log-uniform r and w over three
+    decades below their maxima), 'dups' (r drawn from 10 distinct values),
+    'zeros' (uniform with a tenth of r and of w set to 0).  c ~ N(0, 1).
+    """
+    rng = np.random.default_rng(1000 + seed)
+    n = int(round(10 ** rng.uniform(0.0, np.log10(4000.0))))
+    m = int(round(10 ** rng.uniform(0.0, np.log10(4000.0))))
+    nu = int(rng.integers(-8, 21))
+    eps = float(rng.choice([1e-4, 1e-6, 1e-8, 1e-10, 1e-12]))
+    prod = 10 ** rng.uniform(1.0, np.log10(2e4))
+    rmax = 10 ** rng.uniform(-1.0, 1.0)
+    wmax = prod / rmax
+    kind = str(rng.choice(["uniform", "clustered", "log", "dups", "zeros"]))
+    if kind == "clustered":
+        r = np.abs(rng.normal(0.5 * rmax, 0.05 * rmax, n))
+        w = rng.uniform(0.5 * wmax, wmax, m)
+    elif kind == "log":
+        r = rmax * 10 ** rng.uniform(-3.0, 0.0, n)
+        w = wmax * 10 ** rng.uniform(-3.0, 0.0, m)
+    elif kind == "dups":
+        r = rng.choice(rng.uniform(0.0, rmax, 10), n)
+        w = rng.uniform(0.0, wmax, m)
+    else:
+        r = rng.uniform(0.0, rmax, n)
+        w = rng.uniform(0.0, wmax, m)
+        if kind == "zeros":
+            r[rng.random(n) < 0.1] = 0.0
+            w[rng.random(m) < 0.1] = 0.0
+    c = rng.standard_normal(n)
+    return nu, eps, r, w, c, kind
