@@ -17,6 +17,11 @@ benchmark configurations:
 * ``sparse_c``      c with a fixed number of N(0, 1) nonzeros at random indices
                     (the accuracy study of Sec. 5.1.3)
 * ``batch``         many independent transforms with uneven n, m and order
+* ``fourier_bessel`` the Fourier-Bessel case of the p = O(n) study (Sec. 5.1):
+                    w_j = j_{nu,j}, r_k = j_{nu,k} / j_{nu,n+1} (the scaled
+                    zeros of J_nu, from ``bessel_zeros``), n = m
+* ``exponential``   the exponentially distributed case of the same study:
+                    w_j = r_j log-spaced over [n^(-1/2), n^(1/2)], n = m
 """
 import numpy as np
 
@@ -131,3 +136,34 @@ def random_case(seed: int):
             w[rng.random(m) < 0.1] = 0.0
     c = rng.standard_normal(n)
     return nu, eps, r, w, c, kind
+
+
+def bessel_zeros(nu: int, count: int) -> np.ndarray:
+    """The first ``count`` positive zeros j_{|nu|,1} < j_{|nu|,2} < ... of J_nu
+    (J_{-nu} = (-1)^nu J_nu has the same zeros), computed by SciPy's
+    ``special.jn_zeros``.  Used only to place points and frequencies."""
+    from scipy import special
+    if count <= 0:
+        return np.zeros(0)
+    return np.asarray(special.jn_zeros(abs(int(nu)), int(count)), dtype=np.float64)
+
+
+def fourier_bessel(n: int, nu: int, seed: int):
+    """w_j = j_{nu,j} (j = 1..n), r_k = j_{nu,k} / j_{nu,n+1} (k = 1..n), c ~ N(0, 1)."""
+    z = bessel_zeros(nu, n + 1)
+    r = z[:n] / z[n]
+    w = z[:n].copy()
+    c = np.random.default_rng(seed).standard_normal(n)
+    return r, w, c
+
+
+def exponential(n: int, seed: int):
+    """w_j = r_j = 10^(log10(n) (j-1)/(n-1) - log10(n)/2), j = 1..n: log-spaced
+    over [n^(-1/2), n^(1/2)], so the products w r span [1/n, n]; c ~ N(0, 1)."""
+    if n == 1:
+        x = np.ones(1)
+    else:
+        lg = np.log10(n)
+        x = 10.0 ** (lg * np.arange(n) / (n - 1) - 0.5 * lg)
+    c = np.random.default_rng(seed).standard_normal(n)
+    return x.copy(), x.copy(), c
