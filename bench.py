@@ -233,6 +233,45 @@ def bench_fwd_bwd(torch, nuht, workloads, dev):
     return res
 
 
+def bench_pn(torch, nuht, workloads, dev, reps=3):
+    """The p = O(n) study at n = m = 1e6, nu = 0, eps = 1e-8 (the configuration of
+    the paper's runtime figure for this study): Fourier-Bessel points and
+    frequencies (scaled zeros of J_0) and the exponentially distributed case
+    (the worst case for the partition).  Plan + execute per transform."""
+    n, nu, eps = 1_000_000, 0, 1e-8
+    res = {}
+    for kind in ("fourier_bessel", "exponential"):
+        if kind == "fourier_bessel":
+            arrs = workloads.fourier_bessel(n, nu, seed=160)
+        else:
+            arrs = workloads.exponential(n, seed=161)
+        r, w, c = (torch.as_tensor(a, device=dev) for a in arrs)
+        p = nuht.Plan(r, w, nu, eps)                 # warm-up
+        p.execute(c)
+        inf = p.info()
+        p.close()
+        torch.cuda.synchronize()
+        t_plan = t_exec = 0.0
+        for _ in range(reps):
+            a = time.perf_counter()
+            p = nuht.Plan(r, w, nu, eps)
+            torch.cuda.synchronize()
+            b = time.perf_counter()
+            p.execute(c)
+            torch.cuda.synchronize()
+            e = time.perf_counter()
+            p.close()
+            t_plan += b - a
+            t_exec += e - b
+        t_plan /= reps
+        t_exec /= reps
+        res[kind] = dict(n=n, m=n, nu=nu, eps=eps, plan_ms=1e3 * t_plan, execute_ms=1e3 * t_exec,
+                         value=2 * n / (t_plan + t_exec), execute_rate=2 * n / t_exec, levels=inf["levels"],
+                         blocks=[inf["n_local"], inf["n_asy"], inf["n_direct"]], M=inf["M"], L=inf["L"])
+        log("p=O(n):", kind, json.dumps(res[kind]))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +283,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-looped comparison")
     ap.add_argument("--no-grad", action="store_true", help="skip the forward+backward comparison")
     ap.add_argument("--no-loose", action="store_true", help="skip the eps = 1e-6 (FP64 and FP32 spreading) runs")
+    ap.add_argument("--no-pn", action="store_true",
+                    help="skip the p = O(n) study (Fourier-Bessel and exponential points at n = m = 1e6)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 64 MiB device-to-device copy three times (a known byte count "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -411,6 +452,7 @@ def main():
 
     batched = None if args.no_batched else bench_batched(torch, nuht, workloads, dev)
     fwd_bwd = None if args.no_grad else bench_fwd_bwd(torch, nuht, workloads, dev)
+    pn = None if args.no_pn else bench_pn(torch, nuht, workloads, dev)
 
     out = {
         "metric": "(n+m)/s at eps=1e-12 vs direct sum; batched and fwd+bwd speedup, HBM GB/s",
@@ -437,6 +479,7 @@ def main():
         "batched": batched,
         "fwd_bwd": fwd_bwd,
         "eps_1e-6": loose,
+        "p_equals_n": pn,
     }
     if loose is not None:
         for mode in ("fp64", "fp32_spread"):
