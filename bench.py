@@ -237,14 +237,12 @@ def bench_pn(torch, nuht, workloads, dev, reps=3):
     """The p = O(n) study at n = m = 1e6, nu = 0, eps = 1e-8 (the configuration of
     the paper's runtime figure for this study): Fourier-Bessel points and
     frequencies (scaled zeros of J_0) and the exponentially distributed case
-    (the worst case for the partition).  Plan + execute per transform."""
-    n, nu, eps = 1_000_000, 0, 1e-8
-    res = {}
-    for kind in ("fourier_bessel", "exponential"):
-        if kind == "fourier_bessel":
-            arrs = workloads.fourier_bessel(n, nu, seed=160)
-        else:
-            arrs = workloads.exponential(n, seed=161)
+    (the worst case for the partition).  Then the figure's order sweep
+    (nu = 10, 100 at eps = 1e-8) and tolerance sweep (eps = 1e-4 ... 1e-15 at
+    nu = 0), Fourier-Bessel only.  Plan + execute per transform."""
+    n = 1_000_000
+
+    def timed(arrs, nu, eps):
         r, w, c = (torch.as_tensor(a, device=dev) for a in arrs)
         p = nuht.Plan(r, w, nu, eps)                 # warm-up
         p.execute(c)
@@ -265,10 +263,24 @@ def bench_pn(torch, nuht, workloads, dev, reps=3):
             t_exec += e - b
         t_plan /= reps
         t_exec /= reps
-        res[kind] = dict(n=n, m=n, nu=nu, eps=eps, plan_ms=1e3 * t_plan, execute_ms=1e3 * t_exec,
-                         value=2 * n / (t_plan + t_exec), execute_rate=2 * n / t_exec, levels=inf["levels"],
-                         blocks=[inf["n_local"], inf["n_asy"], inf["n_direct"]], M=inf["M"], L=inf["L"])
+        return dict(n=n, m=n, nu=nu, eps=eps, plan_ms=1e3 * t_plan, execute_ms=1e3 * t_exec,
+                    value=2 * n / (t_plan + t_exec), execute_rate=2 * n / t_exec, levels=inf["levels"],
+                    blocks=[inf["n_local"], inf["n_asy"], inf["n_direct"]], M=inf["M"], L=inf["L"])
+
+    fb0 = workloads.fourier_bessel(n, 0, seed=160)
+    res = {"fourier_bessel": timed(fb0, 0, 1e-8),
+           "exponential": timed(workloads.exponential(n, seed=161), 0, 1e-8)}
+    for kind in ("fourier_bessel", "exponential"):
         log("p=O(n):", kind, json.dumps(res[kind]))
+    sweep = []
+    for eps in (1e-4, 1e-6, 1e-10, 1e-12, 1e-15):
+        sweep.append(timed(fb0, 0, eps))
+    for nu in (10, 100):
+        sweep.append(timed(workloads.fourier_bessel(n, nu, seed=160 + nu), nu, 1e-8))
+    keep = ("nu", "eps", "plan_ms", "execute_ms", "value", "M", "L", "levels")
+    res["fourier_bessel_sweep"] = [{k: d[k] for k in keep} for d in sweep]
+    for d in res["fourier_bessel_sweep"]:
+        log("p=O(n): fourier_bessel sweep", json.dumps(d))
     return res
 
 

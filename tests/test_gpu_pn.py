@@ -7,6 +7,9 @@ points and frequencies, against the oracle's direct sum.
   entry within 2 eps |c|_1 (the exponential case gives the deepest partition);
 * both at n = m = 1e6, nu = 0, eps = 1e-8 (the configuration of the paper's
   runtime figure) on 64 sampled outputs, each a direct sum over all points;
+* Fourier-Bessel at n = m = 1e6 at the ends of the runtime study's order sweep
+  (nu = 10, 100 at eps = 1e-8) and tolerance sweep (eps = 1e-4, 1e-15 at
+  nu = 0), sampled the same way;
 * the accuracy study: Fourier-Bessel, n = m = 1e5, c with 1000 N(0, 1)
   nonzeros, reference = the direct sum over the nonzeros only, for eps from
   1e-4 to 1e-14: relative l2 <= max(eps, 1.5e-14).  Seen: 1.4e-5, 4.6e-7,
@@ -104,3 +107,23 @@ def test_accuracy_study(nuht):
         print("eps", eps, "rel_l2", errs[eps])
     for eps, e in errs.items():
         assert e <= max(eps, 1.5e-14), (eps, e)
+
+
+# The order and tolerance sweeps of the runtime study (Sec. 5.1, Fourier-Bessel
+# only): the two ends of each sweep at full size, on sampled outputs.
+SWEEP = [(10, 1e-8), (100, 1e-8), (0, 1e-4), (0, 1e-15)]
+
+
+@pytest.mark.parametrize("nu,eps", SWEEP)
+def test_fourier_bessel_sweep_full_size_sampled(nuht, nu, eps):
+    n = 1_000_000
+    r, w, c = workloads.fourier_bessel(n, nu, seed=180 + nu)
+    g, info = run(nuht, nu, eps, r, c, w)
+    idx = np.random.default_rng(181).choice(n, 64, replace=False)
+    g1 = direct.dht(nu, r, c, w[idx])
+    bar = max(eps, 2e-14)
+    print("nu", nu, "eps", eps, "M", info["M"], "L", info["L"], "levels", info["levels"],
+          "blocks", info["n_local"], info["n_asy"], info["n_direct"], "rel_l2", rel_l2(g[idx], g1),
+          "max/|c|_1", np.abs(g[idx] - g1).max() / np.sum(np.abs(c)))
+    assert rel_l2(g[idx], g1) <= 2.0 * bar
+    assert np.all(np.abs(g[idx] - g1) <= 2.0 * bar * np.sum(np.abs(c)))
