@@ -841,8 +841,9 @@ __global__ __launch_bounds__(256) void k_fft_pass_b(PlanDev P, double2* __restri
 // a = floor(nu/2), sign (-1)^i) and with nu - i (the terms l <= a).
 //   MODE 0 (nu = 0): the products are J_i^2;
 //   MODE 1 (nu = 1): J_i J_{i+1}, i.e. the current and the previous value;
-//   MODE 2 (any nu): partners up to nu steps back, from a ring of nu + 1 values
-//   per thread in LDS.
+//   MODE 2 (any nu): the partner nu steps back from a second copy of the
+//   recurrence running behind the first; the floor(nu/2) + 1 partners of the
+//   l <= a terms from LDS.
 // In every mode the recurrence first runs alone down to the highest index a
 // product needs, then continues with the products.
 __device__ __forceinline__ void miller_rescale(double& yk, double& yk1, double& S2, double& dot)
@@ -934,48 +935,67 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
         dot = __builtin_fma(2.0 * t[0] * yk, yk1, dot);
         return dot / S2;
     } else {
+        // Part one pairs i with i + nu (1 <= i <= L - a, weight 2 (-1)^i t_{a+i});
+        // part two pairs i with nu - i (0 <= i <= a, weight t_{a-i}, doubled
+        // except the l = 0 term of an even order).  J_{i+nu} comes from a second
+        // copy of the recurrence run nu steps behind the first: the same
+        // operations on the same state give the same values, so the lagging
+        // copy is started from the leading copy's state at s0 = min(N, L-a+nu)
+        // and the two run as independent chains.  Part two's partners
+        // J_{a2..nu} (a2 = nu - a) are kept per thread in LDS as the leading
+        // copy passes them.  Both copies rescale by exact powers of two; the
+        // leading copy's rescales since the lagging copy's state (d) set the
+        // factor 2^(-332 d) between the two scales.
         const int odd = nu & 1;
-        const int a = odd ? (nu - 1) >> 1 : nu >> 1;
-        const int Bsz = nu + 1;
-        // indices above top take part in no product (the first pairing needs
-        // i + a <= L, the second i <= a); their values still enter the ring
-        const int top = (L - a) > a ? (L - a) : a;
-        int slot = N % Bsz;
+        const int a = nu >> 1;
+        const int a2 = nu - a;
+        const int hi1 = L - a;
+        const int top = hi1 > nu ? hi1 : nu;
+        const int s0 = N < hi1 + nu ? N : hi1 + nu;
+        const int act = s0 - nu;
+        const double up = 0x1p332, down = 0x1p-332, down2 = 0x1p-664;
+        double syk = yk, syk1 = 0.0;          // leading copy's state at s0
+        double lyk = 0.0, lyk1 = 0.0, lsc = 1.0;
+        int d = 0;
         int i = N;
         for (; i > top; --i) {
+            if (i == s0) { syk = yk; syk1 = yk1; d = 0; lsc = 1.0; }
             S2 = __builtin_fma(2.0 * yk, yk, S2);
-            ring[slot * stride] = yk;
             double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
             yk1 = yk; yk = ykm1;
-            slot = slot == 0 ? Bsz - 1 : slot - 1;
-            if (fabs(yk) > 1e100) {
-                yk *= 1e-100; yk1 *= 1e-100; S2 *= 1e-200; dot *= 1e-200;
-                for (int q = 0; q < Bsz; ++q) ring[q * stride] *= 1e-100;
+            if (fabs(yk) > up) {
+                yk *= down; yk1 *= down; S2 *= down2; dot *= down2;
+                ++d; lsc = __builtin_amdgcn_ldexp(1.0, -332 * d);
             }
         }
+        // i = top .. 0 in every lane
         for (; i >= 0; --i) {
+            if (i == act) { lyk = syk; lyk1 = syk1; }
             S2 = __builtin_fma(i == 0 ? yk : 2.0 * yk, yk, S2);
-            ring[slot * stride] = yk;
-            int l1 = i + a;
-            if (i >= 1 && l1 <= L && i + nu <= N) {
-                double pv = ring[(slot == 0 ? Bsz - 1 : slot - 1) * stride];
-                double coef = 2.0 * t[l1];
-                dot = __builtin_fma(((i & 1) ? -coef : coef) * yk, pv, dot);
+            if (i >= a2 && i <= nu) ring[(i - a2) * stride] = yk;
+            if (i >= 1 && i <= hi1) {
+                double coef = 2.0 * t[a + i];
+                dot = __builtin_fma(((i & 1) ? -coef : coef) * yk, lyk * lsc, dot);
             }
             if (i <= a && a - i <= L) {
                 int l2 = a - i;
-                double pv = ring[((nu - i) % Bsz) * stride];
+                double pv = ring[(nu - i - a2) * stride];
                 double coef = (!odd && l2 == 0) ? t[0] : 2.0 * t[l2];
                 dot = __builtin_fma(coef * yk, pv, dot);
             }
             if (i == 0) break;
             double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
-            yk1 = yk;
-            yk = ykm1;
-            slot = slot == 0 ? Bsz - 1 : slot - 1;
-            if (fabs(yk) > 1e100) {
-                yk *= 1e-100; yk1 *= 1e-100; S2 *= 1e-200; dot *= 1e-200;
-                for (int q = 0; q < Bsz; ++q) ring[q * stride] *= 1e-100;
+            yk1 = yk; yk = ykm1;
+            double lykm1 = __builtin_fma((double)(i + nu) * rec, lyk, -lyk1);
+            lyk1 = lyk; lyk = lykm1;
+            if (fabs(yk) > up) {
+                yk *= down; yk1 *= down; S2 *= down2; dot *= down2;
+                ++d; lsc = __builtin_amdgcn_ldexp(1.0, -332 * d);
+                for (int q = (i > a2 ? i : a2) - a2; q <= nu - a2; ++q) ring[q * stride] *= down;
+            }
+            if (fabs(lyk) > up) {
+                lyk *= down; lyk1 *= down;
+                --d; lsc = __builtin_amdgcn_ldexp(1.0, -332 * d);
             }
         }
         return dot / S2;
@@ -1267,8 +1287,10 @@ static void launch_rows_local(const PlanDev& P, const ExecBuffers& B, const IoAr
         hipLaunchKernelGGL(k, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, P, B.gd, B.ga, B.lmom, io.g, io.g_slot);
         return;
     }
-    int bs = (P.nu + 1) * 256 * 8 <= 65536 ? 256 : 64;
-    size_t lds = (size_t)(P.nu + 1) * bs * sizeof(double);
+    // local_eval keeps J_{nu-a .. nu}, a = floor(nu/2), per thread in LDS
+    const int slots = (P.nu >> 1) + 1;
+    int bs = slots * 256 * 8 <= 65536 ? 256 : 64;
+    size_t lds = (size_t)slots * bs * sizeof(double);
     hipLaunchKernelGGL(k_rows_local<2>, dim3(cdiv64(P.m, bs)), dim3(bs), lds, s, P, B.gd, B.ga, B.lmom, io.g,
                        io.g_slot);
 }
