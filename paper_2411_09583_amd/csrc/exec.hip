@@ -755,76 +755,210 @@ __global__ __launch_bounds__(256) void k_fft_small(PlanDev P, double2* __restric
     for (int i = threadIdx.x; i < N; i += blockDim.x) x[i] = sm[i];
 }
 
-// Points per workgroup in the two passes (lines x line length).
-constexpr int kFftTile = 1024;
+// Transforms of N = 2^13 .. 2^24 points run as two or three passes, each a
+// batch of transforms of length L <= 256 done in LDS.  A workgroup holds a
+// tile of `lines` batches side by side (lines * L <= kFftTilePts), chosen so
+// that every global read and write moves runs of `lines` consecutive elements
+// (128 B or more) even where the transform itself is strided.
+//
+// With n = n1 + N1 n2 and k = k2 + N2 k1 (N = N1 N2),
+//   X[k2 + N2 k1] = sum_n1 w_N1^(n1 k1) w_N^(n1 k2) sum_n2 x[n1 + N1 n2] w_N2^(n2 k2),
+// w_M = e^(2 pi i / M).  The inner transform over n2 is a column pass (batches
+// n1 at unit stride, the transform at stride N1) that also applies
+// w_N^(n1 k2); the outer one is a row pass (the transform contiguous, output
+// written at stride N2).  When N2 = Na Nb is longer than 256 it is split the
+// same way (n2 = na + Na nb, k2 = kb + Nb ka) into two column passes: over nb
+// with w_N2^(na kb), in place, then over na, which applies w_N^(n1 k2) and
+// writes n1 + N1 k2.  Column passes read the grid and the second writes the
+// scratch buffer; the row pass reads the scratch buffer and writes the grid.
+constexpr int kFftTilePts = 2048;
+constexpr int kFftMaxLines = 16;
 
-// Lines of length len per workgroup in a pass over `count` lines: as many as
-// fill kFftTile points (len <= 4096, so at least one).
-__host__ __device__ inline int fft_lines(int len, int count)
+// Twiddles, kept per device: entries 0..4095 hold e^(2 pi i j / 4096) and
+// entries 4096..8191 hold e^(2 pi i j / 2^24), so that
+// w_N^e = T[E >> 12] T[4096 + (E & 4095)] with E = (e mod N) 2^(24 - log2 N).
+__device__ __forceinline__ double2 fft_twiddle(const double2* __restrict__ T, int64_t e, int logN)
 {
-    int l = kFftTile / len;
-    if (l < 1) l = 1;
-    return l < count ? l : count;
+    int64_t E = (e & ((int64_t(1) << logN) - 1)) << (kMaxFftLog2 - logN);
+    return cmul(T[E >> 12], T[4096 + (E & 4095)]);
 }
 
-// Two-pass FFT for N = N1 * N2 > 4096 (four-step): pass A transforms the N2
-// strided columns of length N1 and applies the twiddles e^{2 pi i n2 k1 / N};
-// pass B transforms the N1 rows of length N2 and writes X[k1 + N1 k2].
-__global__ __launch_bounds__(256) void k_fft_pass_a(PlanDev P, double2* __restrict__ grids,
-                                                    double2* __restrict__ scratch, int first, int logN, int logN1,
-                                                    int64_t scratch_off)
+// In-LDS transforms of the tile's lines, Stockham radix 4 (one radix-2 stage
+// first when log2 L is odd); element (line, n) at sm[line * ls + n].  tw holds
+// w_L^j for j < L.
+__device__ void lds_fft_lines(double2* sm, int logL, int lines, int ls, const double2* tw)
 {
-    extern __shared__ double2 sm[];
-    const int N = 1 << logN, N1 = 1 << logN1, N2 = N >> logN1;
-    const int nch = P.nch;
-    const int lines = fft_lines(N1, N2);
-    const int groups = N2 / lines;
-    int tr = blockIdx.x / groups, grp = blockIdx.x % groups;
-    int slot = tr / nch, ch = tr % nch;
-    const ABlock B = P.ab[P.fft_list[first + slot]];
-    double2* x = grids + B.grid_off + (int64_t)ch * N;
-    double2* y = scratch + scratch_off + (int64_t)tr * N;
-    int n2_0 = grp * lines;
-    for (int e = threadIdx.x; e < N1 * lines; e += blockDim.x) {
-        int n1 = e / lines, li = e - n1 * lines;
-        sm[n1 * lines + li] = x[(int64_t)n1 * N2 + n2_0 + li];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int L = 1 << logL;
+    int Ns = 1, logNs = 0;
+    if (logL & 1) {
+        const int half = L >> 1, nb = lines * half;
+        double2 v[kFftTilePts / 2 / 256][2];
+        #pragma unroll
+        for (int c = 0; c < kFftTilePts / 2 / 256; ++c) {
+            int b = tid + c * nt;
+            if (b < nb) {
+                int line = b >> (logL - 1), j = b & (half - 1);
+                v[c][0] = sm[line * ls + j];
+                v[c][1] = sm[line * ls + j + half];
+            }
+        }
+        __syncthreads();
+        #pragma unroll
+        for (int c = 0; c < kFftTilePts / 2 / 256; ++c) {
+            int b = tid + c * nt;
+            if (b < nb) {
+                int line = b >> (logL - 1), j = b & (half - 1);
+                double2 a = v[c][0], d = v[c][1];
+                sm[line * ls + 2 * j] = make_double2(a.x + d.x, a.y + d.y);
+                sm[line * ls + 2 * j + 1] = make_double2(a.x - d.x, a.y - d.y);
+            }
+        }
+        __syncthreads();
+        Ns = 2; logNs = 1;
     }
-    __syncthreads();
-    lds_fft(sm, N1, logN1, lines, 1, lines);
-    for (int e = threadIdx.x; e < N1 * lines; e += blockDim.x) {
-        int k1 = e / lines, li = e - k1 * lines;
-        int n2 = n2_0 + li;
-        double s, c;
-        sincospi(2.0 * (double)((int64_t)n2 * k1) / (double)N, &s, &c);
-        y[(int64_t)k1 * N2 + n2] = cmul(sm[k1 * lines + li], make_double2(c, s));
+    const int q4 = L >> 2, nb = lines * q4;
+    while (Ns < L) {
+        double2 v[kFftTilePts / 4 / 256][4];
+        #pragma unroll
+        for (int c = 0; c < kFftTilePts / 4 / 256; ++c) {
+            int b = tid + c * nt;
+            if (b < nb) {
+                int line = b >> (logL - 2), j = b & (q4 - 1);
+                #pragma unroll
+                for (int r = 0; r < 4; ++r) v[c][r] = sm[line * ls + j + r * q4];
+            }
+        }
+        __syncthreads();
+        #pragma unroll
+        for (int c = 0; c < kFftTilePts / 4 / 256; ++c) {
+            int b = tid + c * nt;
+            if (b < nb) {
+                int line = b >> (logL - 2), j = b & (q4 - 1);
+                int k = j & (Ns - 1);
+                int ti = k << (logL - 2 - logNs);          // w1 = e^(2 pi i k / (4 Ns)) = w_L^ti
+                double2 w1 = tw[ti], w2 = tw[2 * ti], w3 = tw[3 * ti];
+                double2 x0 = v[c][0];
+                double2 x1 = cmul(v[c][1], w1);
+                double2 x2 = cmul(v[c][2], w2);
+                double2 x3 = cmul(v[c][3], w3);
+                double2 a0 = make_double2(x0.x + x2.x, x0.y + x2.y);
+                double2 a1 = make_double2(x0.x - x2.x, x0.y - x2.y);
+                double2 a2 = make_double2(x1.x + x3.x, x1.y + x3.y);
+                double2 a3 = make_double2(-(x1.y - x3.y), x1.x - x3.x);   // i (x1 - x3)
+                int d0 = (j - k) * 4 + k;
+                sm[line * ls + d0] = make_double2(a0.x + a2.x, a0.y + a2.y);
+                sm[line * ls + d0 + Ns] = make_double2(a1.x + a3.x, a1.y + a3.y);
+                sm[line * ls + d0 + 2 * Ns] = make_double2(a0.x - a2.x, a0.y - a2.y);
+                sm[line * ls + d0 + 3 * Ns] = make_double2(a1.x - a3.x, a1.y - a3.y);
+            }
+        }
+        __syncthreads();
+        Ns <<= 2; logNs += 2;
     }
 }
 
-__global__ __launch_bounds__(256) void k_fft_pass_b(PlanDev P, double2* __restrict__ grids,
-                                                    const double2* __restrict__ scratch, int first, int logN,
-                                                    int logN1, int64_t scratch_off)
+// A column pass.  Batch (b_lo, b_hi), b_lo < blo at unit stride; input element
+// t at b_lo + b_hi in_hs + t in_es, output element k at
+// b_lo + b_hi out_hs + k out_es, multiplied by w_N^e,
+// e = (b_lo & lo_mask) (b_hi + kmul k).
+struct FftCol {
+    int32_t logL, logLines, logBlo, to_scratch;
+    int64_t in_es, in_hs, out_es, out_hs, lo_mask, kmul;
+};
+
+__device__ __forceinline__ void fft_stage_twiddles(double2* tw, const double2* __restrict__ T, int logL)
+{
+    for (int j = threadIdx.x; j < (1 << logL); j += blockDim.x) tw[j] = T[j << (12 - logL)];
+}
+
+__global__ __launch_bounds__(256) void k_fft_col(PlanDev P, double2* __restrict__ grids,
+                                                 double2* __restrict__ scratch, const double2* __restrict__ T,
+                                                 int first, int logN, int64_t scratch_off, FftCol C)
 {
     extern __shared__ double2 sm[];
-    const int N = 1 << logN, N1 = 1 << logN1, N2 = N >> logN1;
-    const int logN2 = logN - logN1;
+    const int L = 1 << C.logL, lines = 1 << C.logLines, ls = L + 1;
+    double2* tw = sm + lines * ls;
+    const int tile = lines << C.logL;
+    const int64_t N = int64_t(1) << logN;
+    const int groups = (int)(N >> (C.logL + C.logLines));
     const int nch = P.nch;
-    const int lines = fft_lines(N2, N1);
-    const int groups = N1 / lines;
-    int tr = blockIdx.x / groups, grp = blockIdx.x % groups;
-    int slot = tr / nch, ch = tr % nch;
+    int tr = blockIdx.x / groups, grp = blockIdx.x - tr * groups;
+    int slot = tr / nch, ch = tr - slot * nch;
     const ABlock B = P.ab[P.fft_list[first + slot]];
-    double2* x = grids + B.grid_off + (int64_t)ch * N;
-    const double2* y = scratch + scratch_off + (int64_t)tr * N;
-    int k1_0 = grp * lines;
-    for (int e = threadIdx.x; e < N2 * lines; e += blockDim.x) {
-        int li = e / N2, n2 = e - li * N2;
-        sm[li * N2 + n2] = y[(int64_t)(k1_0 + li) * N2 + n2];
+    const double2* x = grids + B.grid_off + (int64_t)ch * N;
+    double2* y = C.to_scratch ? scratch + scratch_off + (int64_t)tr * N : grids + B.grid_off + (int64_t)ch * N;
+    const int64_t bb = (int64_t)grp << C.logLines;
+    const int64_t blo0 = bb & ((int64_t(1) << C.logBlo) - 1), bhi = bb >> C.logBlo;
+    const double2* xs = x + blo0 + bhi * C.in_hs;
+    constexpr int kPer = kFftTilePts / 256;
+    double2 v[kPer];
+    #pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        int e = threadIdx.x + u * 256;
+        if (e < tile) v[u] = xs[(int64_t)(e >> C.logLines) * C.in_es + (e & (lines - 1))];
+    }
+    fft_stage_twiddles(tw, T, C.logL);
+    #pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        int e = threadIdx.x + u * 256;
+        if (e < tile) sm[(e & (lines - 1)) * ls + (e >> C.logLines)] = v[u];
     }
     __syncthreads();
-    lds_fft(sm, N2, logN2, lines, N2, 1);
-    for (int e = threadIdx.x; e < N2 * lines; e += blockDim.x) {
-        int k2 = e / lines, li = e - k2 * lines;
-        x[(int64_t)k1_0 + li + (int64_t)N1 * k2] = sm[li * N2 + k2];
+    lds_fft_lines(sm, C.logL, lines, ls, tw);
+    double2* ys = y + blo0 + bhi * C.out_hs;
+    #pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        int e = threadIdx.x + u * 256;
+        if (e < tile) {
+            int k = e >> C.logLines, li = e & (lines - 1);
+            double2 w = fft_twiddle(T, ((blo0 + li) & C.lo_mask) * (bhi + C.kmul * k), logN);
+            ys[(int64_t)k * C.out_es + li] = cmul(sm[li * ls + k], w);
+        }
+    }
+}
+
+// The row pass: batch k2 < N2 of length L = N1 read contiguously at k2 N1 from
+// the scratch buffer; output k1 written to the grid at k2 + N2 k1.
+__global__ __launch_bounds__(256) void k_fft_row(PlanDev P, double2* __restrict__ grids,
+                                                 const double2* __restrict__ scratch, const double2* __restrict__ T,
+                                                 int first, int logN, int64_t scratch_off, int logL, int logLines)
+{
+    extern __shared__ double2 sm[];
+    const int L = 1 << logL, lines = 1 << logLines, ls = L + 1;
+    double2* tw = sm + lines * ls;
+    const int tile = lines << logL;
+    const int64_t N = int64_t(1) << logN, N2 = N >> logL;
+    const int groups = (int)(N2 >> logLines);
+    const int nch = P.nch;
+    int tr = blockIdx.x / groups, grp = blockIdx.x - tr * groups;
+    int slot = tr / nch, ch = tr - slot * nch;
+    const ABlock B = P.ab[P.fft_list[first + slot]];
+    const int64_t k20 = (int64_t)grp << logLines;
+    const double2* xs = scratch + scratch_off + (int64_t)tr * N + (k20 << logL);
+    double2* ys = grids + B.grid_off + (int64_t)ch * N + k20;
+    constexpr int kPer = kFftTilePts / 256;
+    double2 v[kPer];
+    #pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        int e = threadIdx.x + u * 256;
+        if (e < tile) v[u] = xs[e];
+    }
+    fft_stage_twiddles(tw, T, logL);
+    #pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        int e = threadIdx.x + u * 256;
+        if (e < tile) sm[(e >> logL) * ls + (e & (L - 1))] = v[u];
+    }
+    __syncthreads();
+    lds_fft_lines(sm, logL, lines, ls, tw);
+    #pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        int e = threadIdx.x + u * 256;
+        if (e < tile) {
+            int k1 = e >> logLines, li = e & (lines - 1);
+            ys[(int64_t)k1 * N2 + li] = sm[li * ls + k1];
+        }
     }
 }
 
@@ -1340,6 +1474,58 @@ hipError_t launch_set_pointers(void** table, const void* const* ptrs, int count,
     return hipGetLastError();
 }
 
+// Lines per tile for transforms of length 2^logL.
+static int fft_log_lines(int logL)
+{
+    int l = 0;
+    while ((1 << (l + 1)) <= kFftMaxLines && (1 << (l + 1 + logL)) <= kFftTilePts) ++l;
+    return l;
+}
+
+static size_t fft_lds_bytes(int logL, int logLines)
+{
+    return sizeof(double2) * ((size_t)((1 << logL) + 1) * (1 << logLines) + (1 << logL));
+}
+
+// Two passes for N <= 2^16 (N1 = 2^floor(logN/2)), three beyond; every pass
+// length is at most 2^8 and at least 2^6 for the sizes that reach here.
+static void launch_fft_large(const PlanDev& P, const ExecBuffers& B, const FftClass& C, hipStream_t s)
+{
+    const int logN = C.log2n;
+    const int ntr = C.count * P.nch;
+    int logN1, logNa, logNb;
+    if (logN <= 16) {
+        logN1 = logN / 2; logNa = logN - logN1; logNb = 0;
+    } else {
+        logN1 = logN / 3; logNa = (logN - logN1) / 2; logNb = logN - logN1 - logNa;
+    }
+    const int64_t N1 = int64_t(1) << logN1, Na = int64_t(1) << logNa, Nb = int64_t(1) << logNb;
+    if (logNb > 0) {
+        FftCol c{};
+        c.logL = logNb; c.logLines = fft_log_lines(logNb); c.logBlo = logN1 + logNa; c.to_scratch = 0;
+        c.in_es = N1 * Na; c.in_hs = 0; c.out_es = N1 * Na; c.out_hs = 0;
+        c.lo_mask = ~(N1 - 1); c.kmul = 1;
+        int blocks = ntr * (int)((int64_t(1) << logN) >> (c.logL + c.logLines));
+        hipLaunchKernelGGL(k_fft_col, dim3(blocks), dim3(256), fft_lds_bytes(c.logL, c.logLines), s, P, B.grids,
+                           B.scratch, B.fft_tw, C.first, logN, C.scratch_off, c);
+    }
+    {
+        FftCol c{};
+        c.logL = logNa; c.logLines = fft_log_lines(logNa); c.logBlo = logN1; c.to_scratch = 1;
+        c.in_es = N1; c.in_hs = N1 * Na; c.out_es = N1 * Nb; c.out_hs = N1;
+        c.lo_mask = ~int64_t(0); c.kmul = Nb;
+        int blocks = ntr * (int)((int64_t(1) << logN) >> (c.logL + c.logLines));
+        hipLaunchKernelGGL(k_fft_col, dim3(blocks), dim3(256), fft_lds_bytes(c.logL, c.logLines), s, P, B.grids,
+                           B.scratch, B.fft_tw, C.first, logN, C.scratch_off, c);
+    }
+    {
+        int logLines = fft_log_lines(logN1);
+        int blocks = ntr * (int)((int64_t(1) << (logN - logN1)) >> logLines);
+        hipLaunchKernelGGL(k_fft_row, dim3(blocks), dim3(256), fft_lds_bytes(logN1, logLines), s, P, B.grids,
+                           B.scratch, B.fft_tw, C.first, logN, C.scratch_off, logN1, logLines);
+    }
+}
+
 hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers& B, const FftClass* cls, int ncls,
                           const IoArgs& io, hipStream_t s, hipEvent_t* marks)
 {
@@ -1387,17 +1573,7 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
         hipLaunchKernelGGL(k_fft_small, dim3(small_wg), dim3(256), sizeof(double2) << small_log, s, P, B.grids, small);
     for (int q = 0; q < ncls; ++q) {
         const FftClass& C = cls[q];
-        int ntr = C.count * P.nch;
-        if (C.log2n > 12) {
-            int logN1 = C.log2n / 2;
-            int N1 = 1 << logN1, N2 = 1 << (C.log2n - logN1);
-            int la = fft_lines(N1, N2);
-            int lb = fft_lines(N2, N1);
-            hipLaunchKernelGGL(k_fft_pass_a, dim3(ntr * (N2 / la)), dim3(256), sizeof(double2) * N1 * la, s, P,
-                               B.grids, B.scratch, C.first, C.log2n, logN1, C.scratch_off);
-            hipLaunchKernelGGL(k_fft_pass_b, dim3(ntr * (N1 / lb)), dim3(256), sizeof(double2) * N2 * lb, s, P,
-                               B.grids, B.scratch, C.first, C.log2n, logN1, C.scratch_off);
-        }
+        if (C.log2n > 12) launch_fft_large(P, B, C, s);
     }
     mark(marks, 5, s);
     if (P.n_d > 0) {

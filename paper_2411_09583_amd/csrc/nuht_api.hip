@@ -244,6 +244,38 @@ static const double* es_pieces_device(int w, double beta)
     return table[dev][w];
 }
 
+// FFT twiddles of the large-transform passes, one table per device:
+// entries 0..4095 hold e^(2 pi i j / 4096) and entries 4096..8191 hold
+// e^(2 pi i j / 2^24), each rounded from an extended-precision evaluation.
+static const double2* fft_twiddles_device()
+{
+    static std::mutex mu;
+    static const double2* table[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) { (void)hipGetLastError(); return nullptr; }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!table[dev]) {
+        std::vector<double2> host(8192);
+        const long double two_pi = 6.283185307179586476925286766559005768L;
+        for (int j = 0; j < 4096; ++j) {
+            long double a = two_pi * (long double)j / 4096.0L;
+            long double b = two_pi * (long double)j / 16777216.0L;
+            host[j] = make_double2((double)cosl(a), (double)sinl(a));
+            host[4096 + j] = make_double2((double)cosl(b), (double)sinl(b));
+        }
+        void* p = nullptr;
+        size_t bytes = sizeof(double2) * host.size();
+        if (hipMalloc(&p, bytes) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+        if (hipMemcpy(p, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(p);
+            return nullptr;
+        }
+        table[dev] = (const double2*)p;
+    }
+    return table[dev];
+}
+
 // -(2nu+1) pi/4 modulo 2 pi as a double-double in (0, 2 pi].
 static void phase_offset(int nu, double& hi, double& lo)
 {
@@ -679,6 +711,8 @@ static int part_finish(PendingPart& pp, const HostStage* h, bool* again)
     NUHT_TRY(slab.commit(Pt));
     B.es_poly = es_pieces_device(P.w, P.beta);
     if (!B.es_poly) return NUHT_ENOMEM;
+    B.fft_tw = fft_twiddles_device();
+    if (!B.fft_tw) return NUHT_ENOMEM;
     P.es_poly = B.es_poly;
     Pt.built = true;
     return NUHT_OK;

@@ -49,6 +49,7 @@ struct ExecBuffers {
     double* gd;         // per-row direct-block sums (m)
     double* ga;         // per-row asymptotic sums (m)
     const double* es_poly;  // ES kernel pieces (w x (kEsDeg + 1)), shared by all plans on the device
+    const double2* fft_tw;  // FFT twiddles (8192 entries), shared by all plans on the device
     int64_t grid_cells; // grid slots (without the channel factor)
 };
 
