@@ -267,10 +267,10 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
                     s_pt[tid] = rec;
                 }
                 const double sv = e.s;
-                // powers s^0 .. s^8 once per point; each piece is then
-                // sum_{d<=8} c_d s^d + s^8 sum_{d>8} c_d s^(d-8), with the
-                // (scalar) coefficients as multiplicands
-                constexpr int kHalf = kEsDeg / 2;
+                // powers s^0 .. s^h once per point (h = ceil(kEsDeg / 2));
+                // each piece is then sum_{d<=h} c_d s^d + s^h sum_{d>h} c_d
+                // s^(d-h), with the (scalar) coefficients as multiplicands
+                constexpr int kHalf = (kEsDeg + 1) / 2;
                 double spow[kHalf + 1];
                 spow[0] = 1.0;
                 #pragma unroll
@@ -336,33 +336,41 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
 // t the tap (0 .. w-1), phi_t the kernel's polynomial piece for tap t and
 // V_k[2p + {0,1}] = (re, im) of c_k sqrt(q_k) e^{i D (r_k - C)} q_k^p.  For
 // each anchor this is a (16 taps) x (points) x (16 NCT columns) product: one
-// v_mfma_f64_16x16x4f64 per four points and column tile, accumulated per
-// anchor.  In an MFMA step, lane (row = lane % 16, k = lane / 16) supplies
-// A[row][k] = phi_row(s) of point k, evaluated in the lane with the
-// coefficients of piece `row` held in its registers, and B[k][col] =
-// V_k[col] (col = lane % 16) from LDS; element v of the accumulator is
-// D[lane / 16 + 4 v][lane % 16].  The four waves of a workgroup take turns
-// at steps of the item's points and never wait for each other until the end,
-// where they fold their anchor tiles into cells in LDS in a fixed order
-// (wave, anchor), so the result does not depend on timing.
+// v_mfma_f64_16x16x4f64 per four points and column tile.  In an MFMA step,
+// lane (row = lane % 16, k = lane / 16) supplies A[row][k] = phi_row(s) of
+// point k, evaluated in the lane with the coefficients of piece `row` held in
+// its registers, and B[k][col] = V_k[col] (col = lane % 16) from LDS; element
+// v of the accumulator is D[lane / 16 + 4 v][lane % 16].
+//
+// The four waves of a workgroup share one item: wave v takes the steps of 64
+// points starting at ka + (4 j + v) 64.  Points are sorted, so the anchors a
+// wave meets only increase: it keeps one tile for its current anchor and adds
+// it into its own cell sums in LDS when the anchor changes.  At the end the
+// four waves' cell sums are added in a fixed order, so the result does not
+// depend on timing.
 // ---------------------------------------------------------------------------
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// 16-column tiles of the channel columns (re, im of 8 channels each)
+template <int NCH>
+constexpr int kSpreadTiles = NCH <= 8 ? 1 : 2;
+
 template <int NCH>
 struct SpreadMfma {
-    static constexpr int NCT = NCH <= 8 ? 1 : 2;   // 16-column tiles
+    static constexpr int NCT = kSpreadTiles<NCH>;
     static constexpr int NC = 16 * NCT;            // real columns of the tiles (re, im of 8 NCT channels)
     static constexpr int VS = 2 * NCH + 1;         // LDS stride of a point's 2 NCH columns (odd: conflict-free writes)
     static constexpr int GC = kSpreadAnchors + 15; // cells an item's anchor tiles reach
-    static constexpr size_t point_bytes = VS * sizeof(double) + sizeof(double) + sizeof(int32_t);
-    static constexpr int WPTS = 256 * point_bytes <= 65536 ? 64 : 32;   // points per wave step (LDS below 64 KiB)
-    static constexpr int PTS = 4 * WPTS;           // points held by the workgroup's four waves
-    static constexpr size_t fold_bytes = (size_t)4 * GC * NC * sizeof(double);   // per-wave cell sums, at the end
-    static constexpr size_t lds_bytes = (size_t)PTS * point_bytes > fold_bytes ? (size_t)PTS * point_bytes : fold_bytes;
+    static constexpr int WPTS = 64;                // points per step
+    // a point: its columns, its s and its anchor
+    static constexpr size_t point_bytes = (VS + 1) * sizeof(double) + sizeof(int32_t);
+    static constexpr size_t fold_bytes = (size_t)GC * NC * sizeof(double);   // the wave's cell sums
+    static constexpr size_t wave_bytes = ((size_t)WPTS * point_bytes + 15) / 16 * 16 + fold_bytes;
+    static constexpr size_t lds_bytes = 4 * wave_bytes;   // the workgroup's four waves
 };
 
-// Orders the LDS accesses of one wave's lanes around it (the wave's region
-// is written and read by different lanes of the same wave).
+// Orders the LDS accesses of the wave's lanes around it (the region is
+// written and read by different lanes of the same wave).
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -370,21 +378,19 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Points pbeg .. pend-1 of the sub-chunk into the tiles of anchor a: two
-// groups of four points per step (two independent kernel evaluations).  Lanes
-// past pend take B = 0; with MASK, points of other anchors take A = 0.
+// Points 0 .. np-1 of the step into the tile of anchor a, two groups of four
+// points per iteration (two independent kernel evaluations).  Lanes past np
+// take B = 0; with MASK, points of other anchors take A = 0.
 template <int NCH, bool MASK>
-__device__ __forceinline__ void spread_mfma_run(v4d (&acc)[SpreadMfma<NCH>::NCT], const double* s_v,
+__device__ __forceinline__ void spread_mfma_run(v4d (&acc)[kSpreadTiles<NCH>], const double* s_v,
                                                 const double* s_s, const int32_t* s_d,
-                                                const double (&cf)[kEsDeg + 1], int pbeg, int pend, int col, int kq,
-                                                int a)
+                                                const double (&cf)[kEsDeg + 1], int np, int col, int kq, int a)
 {
     constexpr int NCT = SpreadMfma<NCH>::NCT, VS = SpreadMfma<NCH>::VS;
-    for (int g = pbeg; g < pend; g += 8) {
+    for (int g = 0; g < np; g += 8) {
         const int i0 = g + kq, i1 = g + 4 + kq;
-        const bool v0 = i0 < pend, v1 = i1 < pend;
+        const bool v0 = i0 < np, v1 = i1 < np;
         const int j0 = v0 ? i0 : g, j1 = v1 ? i1 : g;
-        const double s0 = s_s[j0], s1 = s_s[j1];
         double b0[NCT], b1[NCT];
         #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) {
@@ -392,6 +398,7 @@ __device__ __forceinline__ void spread_mfma_run(v4d (&acc)[SpreadMfma<NCH>::NCT]
             b0[ct] = (v0 && on) ? s_v[j0 * VS + ct * 16 + col] : 0.0;
             b1[ct] = (v1 && on) ? s_v[j1 * VS + ct * 16 + col] : 0.0;
         }
+        const double s0 = s_s[j0], s1 = s_s[j1];
         double p0 = cf[kEsDeg], p1 = cf[kEsDeg];
         #pragma unroll
         for (int q = kEsDeg - 1; q >= 0; --q) {
@@ -410,21 +417,37 @@ __device__ __forceinline__ void spread_mfma_run(v4d (&acc)[SpreadMfma<NCH>::NCT]
     }
 }
 
+// Adds the finished tile of anchor a into the wave's cell sums (row t of the
+// tile to cell a + t) and clears it.
+template <int NCH>
+__device__ __forceinline__ void spread_mfma_flush(v4d (&acc)[kSpreadTiles<NCH>], double* s_g, int col, int kq, int a)
+{
+    constexpr int NCT = SpreadMfma<NCH>::NCT, NC = SpreadMfma<NCH>::NC;
+    #pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+        #pragma unroll
+        for (int v = 0; v < 4; ++v) s_g[(a + kq + 4 * v) * NC + ct * 16 + col] += acc[ct][v];
+        acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+    wave_sync();   // the next anchor's cells overlap this one's in other lanes
+}
+
 template <int NCH>
 __device__ __forceinline__ void spread_mfma_item(const PlanDev& P, const double* __restrict__ cs,
                                                  const double* __restrict__ es_poly, double2* __restrict__ part)
 {
     using SM = SpreadMfma<NCH>;
-    constexpr int NCT = SM::NCT, NC = SM::NC, VS = SM::VS, WPTS = SM::WPTS, PTS = SM::PTS, GC = SM::GC;
-    constexpr int NA = kSpreadAnchors;
+    constexpr int NCT = SM::NCT, NC = SM::NC, VS = SM::VS, WPTS = SM::WPTS, GC = SM::GC;
     extern __shared__ double4 spread_lds[];
-    double* s_v = reinterpret_cast<double*>(spread_lds);
-    double* s_s = s_v + PTS * VS;
-    int32_t* s_d = reinterpret_cast<int32_t*>(s_s + PTS);
-    const Item I = P.aitems[P.alist[blockIdx.x]];
-    const ABlock B = P.ab[I.blk];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    char* base = reinterpret_cast<char*>(spread_lds) + wave * SM::wave_bytes;
+    double* s_v = reinterpret_cast<double*>(base);
+    double* s_s = s_v + WPTS * VS;
+    int32_t* s_d = reinterpret_cast<int32_t*>(s_s + WPTS);
+    double* s_g = reinterpret_cast<double*>(base + SM::wave_bytes - SM::fold_bytes);
+    const Item I = P.aitems[P.alist[blockIdx.x]];
+    const ABlock B = P.ab[I.blk];
     const int col = lane & 15, kq = lane >> 4;
     const int w = P.w;
     const double hw = 0.5 * w;
@@ -433,34 +456,30 @@ __device__ __forceinline__ void spread_mfma_item(const PlanDev& P, const double*
     double cf[kEsDeg + 1];
     #pragma unroll
     for (int d = 0; d <= kEsDeg; ++d) cf[d] = col < w ? es_poly[col * (kEsDeg + 1) + d] : 0.0;
-    v4d acc[NA][NCT];
+    for (int e = lane; e < GC * NC; e += 64) s_g[e] = 0.0;
+    v4d acc[NCT];
     #pragma unroll
-    for (int a = 0; a < NA; ++a) {
-        #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) acc[a][ct] = v4d{0.0, 0.0, 0.0, 0.0};
-    }
-    // The waves work independently: wave v takes the steps of WPTS points
-    // starting at ka + (4 j + v) WPTS, evaluates them into its own LDS region
-    // and multiplies them into its own tiles; the next step's point and weight
-    // are loaded while the current one is multiplied.
-    double* w_v = s_v + wave * WPTS * VS;
-    double* w_s = s_s + wave * WPTS;
-    int32_t* w_d = s_d + wave * WPTS;
+    for (int ct = 0; ct < NCT; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+    int cur = -1;                              // anchor of the tile in acc
+    // the next step's point and weight are loaded while the current one is
+    // multiplied
     int k0 = I.ka + wave * WPTS;
     double r_nx = 0.0, c_nx = 0.0;
-    if (lane < WPTS && k0 + lane < I.kb) { r_nx = P.rs[k0 + lane]; c_nx = cs[k0 + lane]; }
+    if (k0 + lane < I.kb) { r_nx = P.rs[k0 + lane]; c_nx = cs[k0 + lane]; }
     for (; k0 < I.kb; k0 += 4 * WPTS) {
         const int np = (I.kb - k0) < WPTS ? (I.kb - k0) : WPTS;
         const double r = r_nx, c = c_nx;
         const int kn = k0 + 4 * WPTS + lane;
-        if (lane < WPTS && kn < I.kb) { r_nx = P.rs[kn]; c_nx = cs[kn]; }
+        if (kn < I.kb) { r_nx = P.rs[kn]; c_nx = cs[kn]; }
         wave_sync();                              // the previous step's reads of the region are done
+        int dm = 0;
         if (lane < np) {
             const PointEval e = eval_point(B, r, c, inv_h, hw);
-            w_s[lane] = e.s;
-            w_d[lane] = e.l0 - I.sub_lo;
+            dm = e.l0 - I.sub_lo;
+            s_d[lane] = dm;
+            s_s[lane] = e.s;
             double vr = e.wr, vi = e.wi;
-            double* v = w_v + lane * VS;
+            double* v = s_v + lane * VS;
             #pragma unroll
             for (int p = 0; p < NCH; ++p) {
                 v[2 * p] = vr;
@@ -470,60 +489,46 @@ __device__ __forceinline__ void spread_mfma_item(const PlanDev& P, const double*
             }
         }
         wave_sync();
-        // each anchor present in the step takes one pass over it; when the
-        // step holds several anchors (rare) a pass masks the other anchors'
-        // points out of A
-        const bool mine = lane < np;
-        const int dm = mine ? w_d[lane] : -1;
-        const int d0 = __builtin_amdgcn_readfirstlane(dm);          // lane 0: the step's first point
-        const bool one = __ballot(mine && dm != d0) == 0;
-        #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-            if (__ballot(mine && dm == a) != 0) {
-                if (one) spread_mfma_run<NCH, false>(acc[a], w_v, w_s, w_d, cf, 0, np, col, kq, a);
-                else spread_mfma_run<NCH, true>(acc[a], w_v, w_s, w_d, cf, 0, np, col, kq, a);
+        // the step's anchors run from its first point's to its last point's
+        const int a_lo = __builtin_amdgcn_readfirstlane(dm);
+        const int a_hi = __builtin_amdgcn_readlane(dm, np - 1);
+        if (a_lo == a_hi) {
+            if (a_lo != cur) {
+                if (cur >= 0) spread_mfma_flush<NCH>(acc, s_g, col, kq, cur);
+                cur = a_lo;
+            }
+            spread_mfma_run<NCH, false>(acc, s_v, s_s, s_d, cf, np, col, kq, cur);
+        } else {
+            for (int a = a_lo; a <= a_hi; ++a) {
+                if (__ballot(lane < np && dm == a) == 0) continue;
+                if (a != cur) {
+                    if (cur >= 0) spread_mfma_flush<NCH>(acc, s_g, col, kq, cur);
+                    cur = a;
+                }
+                spread_mfma_run<NCH, true>(acc, s_v, s_s, s_d, cf, np, col, kq, a);
             }
         }
     }
-    // fold: the wave's tile of anchor a, row t, goes to cell a + t of the
-    // wave's own cell sums; anchors one after the other
+    if (cur >= 0) spread_mfma_flush<NCH>(acc, s_g, col, kq, cur);
     __syncthreads();
-    double* s_g = s_v;
-    for (int e = tid; e < 4 * GC * NC; e += 256) s_g[e] = 0.0;
-    __syncthreads();
-    double* gw = s_g + wave * GC * NC;
-    #pragma unroll
-    for (int a = 0; a < NA; ++a) {
-        #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
-            #pragma unroll
-            for (int v = 0; v < 4; ++v) gw[(a + kq + 4 * v) * NC + ct * 16 + col] += acc[a][ct][v];
-        }
-        __syncthreads();   // the next anchor's cells overlap this one's in other lanes
-    }
     // item partial [cell][channel] (re, im): waves summed in order
+    const double* g0 = reinterpret_cast<const double*>(reinterpret_cast<char*>(spread_lds) + SM::wave_bytes -
+                                                       SM::fold_bytes);
+    constexpr size_t wstride = SM::wave_bytes / sizeof(double);
     double* out = reinterpret_cast<double*>(part + I.off);
     constexpr int row_len = 2 * NCH;
     for (int e = tid; e < I.sub_n * row_len; e += 256) {
         const int cell = e / row_len, c = e - cell * row_len;
         const int k = cell * NC + c;
-        out[e] = ((s_g[k] + s_g[GC * NC + k]) + s_g[2 * GC * NC + k]) + s_g[3 * GC * NC + k];
+        out[e] = ((g0[k] + g0[wstride + k]) + g0[2 * wstride + k]) + g0[3 * wstride + k];
     }
 }
 
-// Up to 8 channels the kernel fits three waves per SIMD; above, the register
-// cap would spill.
+// Up to 8 channels (one column tile) the kernel fits four waves per SIMD,
+// with two tiles three.
 template <int NCH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_spread_mfma(
-    PlanDev P, const double* __restrict__ cs, const double* __restrict__ es_poly, double2* __restrict__ part)
-{
-    spread_mfma_item<NCH>(P, cs, es_poly, part);
-}
-
-template <int NCH>
-__global__ __launch_bounds__(256) void k_spread_mfma_wide(PlanDev P, const double* __restrict__ cs,
-                                                          const double* __restrict__ es_poly,
-                                                          double2* __restrict__ part)
+__global__ __launch_bounds__(256) void k_spread_mfma(PlanDev P, const double* __restrict__ cs,
+                                                     const double* __restrict__ es_poly, double2* __restrict__ part)
 {
     spread_mfma_item<NCH>(P, cs, es_poly, part);
 }
@@ -1390,12 +1395,8 @@ static void launch_spread(const PlanDev& P, const Summary& S, const ExecBuffers&
     const int32_t n_dense = S.n_adense, n_rest = S.n_aitems - S.n_adense;
     if constexpr (NCH <= 16) {
         if (n_dense > 0) {
-            if constexpr (SpreadMfma<NCH>::NCT == 1)
-                hipLaunchKernelGGL((k_spread_mfma<NCH>), dim3(n_dense), dim3(256), SpreadMfma<NCH>::lds_bytes, s, P,
-                                   B.cs, B.es_poly, B.part);
-            else
-                hipLaunchKernelGGL((k_spread_mfma_wide<NCH>), dim3(n_dense), dim3(256), SpreadMfma<NCH>::lds_bytes, s,
-                                   P, B.cs, B.es_poly, B.part);
+            hipLaunchKernelGGL((k_spread_mfma<NCH>), dim3(n_dense), dim3(256), SpreadMfma<NCH>::lds_bytes, s, P,
+                               B.cs, B.es_poly, B.part);
         }
     }
     if (n_rest > 0) {
