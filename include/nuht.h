@@ -267,6 +267,47 @@ const char *nuht_strerror(int code);
 int nuht_direct(int nu, double eps, int64_t n, const double *r_dev, const double *c_dev,
                 int64_t m, const double *omega_dev, double *g_dev, void *stream);
 
+/*
+ * Fourier-Bessel expansions on the unit disk and the Helmholtz solver on them
+ * (Sec. 5.3).  A solver object holds the polar grid and the transforms of
+ * orders 0 .. L between the radii and the zeros of J_l, planned once.
+ *
+ * nuht_fb_plan -- the grid: m radii r_dev in (0, 1] with radial weights wr_dev
+ * (a quadrature rule for int_0^1 g(r) dr, e.g. Gauss-Legendre mapped to
+ * [0, 1]) and t equispaced angles theta_s = 2 pi s / t (t a power of two,
+ * 2 <= t <= 4096); orders l = -L .. L with 0 <= L <= 100 and 2L + 1 <= t; J
+ * radial modes per order, zeros_dev holding (L + 1) x J values, row l being
+ * j_{l,1} < ... < j_{l,J}, the first J positive zeros of J_l (the caller's;
+ * the library does not compute them).  eps is the tolerance of every
+ * transform.  The arrays are copied; planning synchronises `stream`.
+ *
+ * nuht_fb_analysis -- the coefficients of eq. FB-coef with the grid's rules,
+ * the angular integral taken as a mean (the eigenfunctions' squared norm being
+ * pi J_{l+1}(j_{l,j})^2), so that f = sum alpha_jl J_l(j_{l,j} r) e^{i l theta}:
+ *   alpha_jl = 2 / J_{l+1}(j_{l,j})^2 sum_k wr_k r_k J_l(j_{l,j} r_k)
+ *              (1 / t) sum_s f(r_k, theta_s) e^{-i l theta_s}.
+ *   f_dev: m x t real samples, row k = f(r_k, theta_0 .. theta_{t-1}).
+ *   alpha_dev: (2L + 1) x J complex (re, im interleaved), row l + L.
+ * nuht_fb_synthesis -- the expansion on the grid:
+ *   u(r_k, theta_s) = Re sum_{l=-L..L} sum_j beta_jl J_l(j_{l,j} r_k) e^{i l theta_s},
+ *   beta_dev as alpha_dev, u_dev as f_dev.
+ * nuht_fb_helmholtz -- (Delta + kappa^2) u = f on the disk, u = 0 on the
+ *   circle: analysis, beta_jl = alpha_jl / (kappa^2 - j_{l,j}^2) (the
+ *   Dirichlet eigenvalues being -j_{l,j}^2), synthesis.  alpha_dev and
+ *   beta_dev may be NULL (kept in the solver's own buffers); kappa^2 must not
+ *   be an eigenvalue.
+ * All three are asynchronous on `stream` and allocate nothing; calls on one
+ * solver must not overlap.  nuht_fb_destroy synchronises and frees.
+ */
+typedef struct nuht_fb_s *nuht_fb_t;
+int nuht_fb_plan(nuht_fb_t *fb, int32_t L, int64_t m, const double *r_dev, const double *wr_dev, int64_t t,
+                 int64_t J, const double *zeros_dev, double eps, void *stream);
+int nuht_fb_analysis(nuht_fb_t fb, const double *f_dev, double *alpha_dev, void *stream);
+int nuht_fb_synthesis(nuht_fb_t fb, const double *beta_dev, double *u_dev, void *stream);
+int nuht_fb_helmholtz(nuht_fb_t fb, double kappa, const double *f_dev, double *alpha_dev, double *beta_dev,
+                      double *u_dev, void *stream);
+int nuht_fb_destroy(nuht_fb_t fb);
+
 #ifdef __cplusplus
 }
 #endif

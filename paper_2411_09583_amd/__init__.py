@@ -57,7 +57,8 @@ class NuhtInfo(ctypes.Structure):
 # every symbol include/nuht.h declares
 EXPORTS = ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_plan_set_order",
            "nuht_plan_info", "nuht_tune", "nuht_plan_many", "nuht_execute_many", "nuht_batch_info",
-           "nuht_batch_destroy", "nuht_destroy", "nuht_strerror", "nuht_direct", "nuht_profile", "nuht_profile_read")
+           "nuht_batch_destroy", "nuht_destroy", "nuht_strerror", "nuht_direct", "nuht_profile", "nuht_profile_read",
+           "nuht_fb_plan", "nuht_fb_analysis", "nuht_fb_synthesis", "nuht_fb_helmholtz", "nuht_fb_destroy")
 
 STAGES = ("gather", "local_moments", "spread", "grid_assembly", "fft", "direct", "rows_asymptotic", "rows_local")
 
@@ -93,9 +94,16 @@ def load_library():
     lib.nuht_direct.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, vp, vp, ctypes.c_int64, vp, vp, vp]
     lib.nuht_profile.argtypes = [vp, ctypes.c_int]
     lib.nuht_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.nuht_fb_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int64, vp, vp, ctypes.c_int64,
+                                 ctypes.c_int64, vp, ctypes.c_double, vp]
+    lib.nuht_fb_analysis.argtypes = [vp, vp, vp, vp]
+    lib.nuht_fb_synthesis.argtypes = [vp, vp, vp, vp]
+    lib.nuht_fb_helmholtz.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp, vp]
+    lib.nuht_fb_destroy.argtypes = [vp]
     for name in ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_plan_set_order", "nuht_plan_info",
                  "nuht_tune", "nuht_plan_many", "nuht_execute_many", "nuht_batch_info", "nuht_batch_destroy",
-                 "nuht_destroy", "nuht_direct", "nuht_profile", "nuht_profile_read"):
+                 "nuht_destroy", "nuht_direct", "nuht_profile", "nuht_profile_read", "nuht_fb_plan",
+                 "nuht_fb_analysis", "nuht_fb_synthesis", "nuht_fb_helmholtz", "nuht_fb_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -280,6 +288,78 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             load_library().nuht_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DiskSolver:
+    """Fourier-Bessel expansions and the Helmholtz solver on the unit disk
+    (nuht_fb_*): m radii r with radial weights wr, t equispaced angles, orders
+    -L .. L and J radial modes per order; zeros is an (L + 1) x J tensor of the
+    first J positive zeros of J_0 .. J_L."""
+
+    def __init__(self, r, wr, t: int, zeros, eps: float):
+        lib = load_library()
+        r = _dev_f64(r, "r")
+        wr = _dev_f64(wr, "wr")
+        if zeros.dim() != 2 or zeros.device.type != "cuda" or zeros.dtype != torch.float64:
+            raise TypeError("zeros must be an (L + 1) x J float64 tensor on the GPU")
+        zeros = zeros.contiguous()
+        self.L, self.J = zeros.shape[0] - 1, zeros.shape[1]
+        self.m, self.t = r.numel(), int(t)
+        if wr.numel() != self.m:
+            raise ValueError("r and wr must have the same length")
+        self.device = r.device
+        h = ctypes.c_void_p()
+        _check(lib.nuht_fb_plan(ctypes.byref(h), self.L, self.m, _ptr(r), _ptr(wr), self.t, self.J, _ptr(zeros),
+                                float(eps), _stream()))
+        self._h = h
+
+    def _grid(self, f, name):
+        if f.shape != (self.m, self.t) or f.device.type != "cuda" or f.dtype != torch.float64:
+            raise ValueError(f"{name} must be an m x t float64 tensor on the GPU")
+        return f.contiguous()
+
+    def _coef(self, a, name):
+        if a.shape != (2 * self.L + 1, self.J) or a.device.type != "cuda" or a.dtype != torch.complex128:
+            raise ValueError(f"{name} must be a (2L + 1) x J complex128 tensor on the GPU")
+        return a.contiguous()
+
+    def analysis(self, f):
+        """alpha[l + L, j - 1]: the Fourier-Bessel coefficients of the samples f."""
+        f = self._grid(f, "f")
+        alpha = torch.empty((2 * self.L + 1, self.J), dtype=torch.complex128, device=self.device)
+        _check(load_library().nuht_fb_analysis(self._h, _ptr(f), _ptr(alpha), _stream()))
+        return alpha
+
+    def synthesis(self, beta):
+        """The real part of the expansion with coefficients beta on the grid."""
+        beta = self._coef(beta, "beta")
+        u = torch.empty((self.m, self.t), dtype=torch.float64, device=self.device)
+        _check(load_library().nuht_fb_synthesis(self._h, _ptr(beta), _ptr(u), _stream()))
+        return u
+
+    def helmholtz(self, kappa: float, f, return_coefficients: bool = False):
+        """u with (Delta + kappa^2) u = f on the disk and u = 0 on the circle."""
+        f = self._grid(f, "f")
+        u = torch.empty((self.m, self.t), dtype=torch.float64, device=self.device)
+        alpha = beta = None
+        if return_coefficients:
+            alpha = torch.empty((2 * self.L + 1, self.J), dtype=torch.complex128, device=self.device)
+            beta = torch.empty_like(alpha)
+        _check(load_library().nuht_fb_helmholtz(self._h, float(kappa), _ptr(f),
+                                                _ptr(alpha) if alpha is not None else None,
+                                                _ptr(beta) if beta is not None else None, _ptr(u), _stream()))
+        return (u, alpha, beta) if return_coefficients else u
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().nuht_fb_destroy(self._h)
             self._h = None
 
     def __del__(self):

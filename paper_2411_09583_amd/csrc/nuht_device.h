@@ -276,4 +276,94 @@ __device__ inline double besselj_full(const PlanDev& P, double xh, double xl)
     return __builtin_fma(xl, d, j0) / sqrt(S);
 }
 
+// ---------------------------------------------------------------------------
+// FFT: X[k] = sum_n x[n] e^{+2 pi i n k / N}, N a power of two, in LDS.
+// Stockham autosort, radix 4 (one radix-2 stage first when log2 N is odd).
+// Element (line, n) of the tile lives at sm[line * ls + n * es].  The tile
+// holds at most 4096 points and the block 256 threads, so a thread carries at
+// most 8 radix-2 or 4 radix-4 butterflies per stage.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(__builtin_fma(a.x, b.x, -a.y * b.y), __builtin_fma(a.x, b.y, a.y * b.x));
+}
+
+__device__ inline void lds_fft(double2* sm, int N, int logN, int lines, int ls, int es)
+{
+    const int tid = threadIdx.x;
+    const int nt = blockDim.x;
+    int Ns = 1;
+    if (logN & 1) {
+        const int half = N >> 1;
+        const int nb = lines * half;
+        double2 v[8][2];
+        #pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            int b = tid + c * nt;
+            if (b < nb) {
+                int line = b / half, j = b - line * half;
+                v[c][0] = sm[line * ls + j * es];
+                v[c][1] = sm[line * ls + (j + half) * es];
+            }
+        }
+        __syncthreads();
+        #pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            int b = tid + c * nt;
+            if (b < nb) {
+                int line = b / half, j = b - line * half;
+                double2 a = v[c][0], d = v[c][1];
+                sm[line * ls + (2 * j) * es] = make_double2(a.x + d.x, a.y + d.y);
+                sm[line * ls + (2 * j + 1) * es] = make_double2(a.x - d.x, a.y - d.y);
+            }
+        }
+        __syncthreads();
+        Ns = 2;
+    }
+    const int q4 = N >> 2;
+    while (Ns < N) {
+        const int nb = lines * q4;
+        double2 v[4][4];
+        #pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            int b = tid + c * nt;
+            if (b < nb) {
+                int line = b / q4, j = b - line * q4;
+                #pragma unroll
+                for (int r = 0; r < 4; ++r) v[c][r] = sm[line * ls + (j + r * q4) * es];
+            }
+        }
+        __syncthreads();
+        #pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            int b = tid + c * nt;
+            if (b < nb) {
+                int line = b / q4, j = b - line * q4;
+                int k = j & (Ns - 1);
+                double s, co;
+                sincospi(2.0 * (double)k / (double)(4 * Ns), &s, &co);
+                double2 w1 = make_double2(co, s);
+                double2 w2 = cmul(w1, w1);
+                double2 w3 = cmul(w2, w1);
+                double2 x0 = v[c][0];
+                double2 x1 = cmul(v[c][1], w1);
+                double2 x2 = cmul(v[c][2], w2);
+                double2 x3 = cmul(v[c][3], w3);
+                double2 a0 = make_double2(x0.x + x2.x, x0.y + x2.y);
+                double2 a1 = make_double2(x0.x - x2.x, x0.y - x2.y);
+                double2 a2 = make_double2(x1.x + x3.x, x1.y + x3.y);
+                double2 a3 = make_double2(-(x1.y - x3.y), x1.x - x3.x);   // i (x1 - x3)
+                int d0 = (j - k) * 4 + k;
+                sm[line * ls + (d0) * es] = make_double2(a0.x + a2.x, a0.y + a2.y);
+                sm[line * ls + (d0 + Ns) * es] = make_double2(a1.x + a3.x, a1.y + a3.y);
+                sm[line * ls + (d0 + 2 * Ns) * es] = make_double2(a0.x - a2.x, a0.y - a2.y);
+                sm[line * ls + (d0 + 3 * Ns) * es] = make_double2(a1.x - a3.x, a1.y - a3.y);
+            }
+        }
+        __syncthreads();
+        Ns <<= 2;
+    }
+}
+
+
 }  // namespace nuht

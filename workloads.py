@@ -22,6 +22,11 @@ benchmark configurations:
                     zeros of J_nu, from ``bessel_zeros``), n = m
 * ``exponential``   the exponentially distributed case of the same study:
                     w_j = r_j log-spaced over [n^(-1/2), n^(1/2)], n = m
+* ``disk``          the Helmholtz solver on the unit disk (Sec. 5.3): m
+                    Gauss-Legendre radii on [0, 1] with their weights, t
+                    equispaced angles, the first J zeros of J_0 .. J_L, and a
+                    random smooth forcing that vanishes with its derivatives
+                    at r = 1 (Gaussian bumps times (1 - r^2)^6)
 """
 import numpy as np
 
@@ -167,3 +172,32 @@ def exponential(n: int, seed: int):
         x = 10.0 ** (lg * np.arange(n) / (n - 1) - 0.5 * lg)
     c = np.random.default_rng(seed).standard_normal(n)
     return x.copy(), x.copy(), c
+
+
+def disk(m: int, t: int, L: int, J: int, seed: int, bumps: int = 8):
+    """Polar grid, zeros and forcing of the disk solver.
+
+    Returns (r, wr, zeros, f): r, wr the m Gauss-Legendre nodes and weights
+    mapped to [0, 1] (ascending r); zeros an (L + 1) x J array, row l the
+    first J positive zeros of J_l; f an m x t array of samples
+    f(r_k, 2 pi s / t) of (1 - r^2)^6 sum_i a_i exp(-|x - x_i|^2 / (2 s_i^2)),
+    a_i ~ N(0, 1), centres x_i uniform in the disk of radius 0.7, widths
+    s_i ~ U[0.08, 0.2]."""
+    x, wx = np.polynomial.legendre.leggauss(m)
+    r = 0.5 * (x + 1.0)
+    wr = 0.5 * wx
+    zeros = np.stack([bessel_zeros(l, J) for l in range(L + 1)]) if J > 0 else np.zeros((L + 1, 0))
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal(bumps)
+    rad = 0.7 * np.sqrt(rng.uniform(0.0, 1.0, bumps))
+    ang = rng.uniform(0.0, 2.0 * np.pi, bumps)
+    sw = rng.uniform(0.08, 0.2, bumps)
+    theta = 2.0 * np.pi * np.arange(t) / t
+    X = r[:, None] * np.cos(theta)[None, :]
+    Y = r[:, None] * np.sin(theta)[None, :]
+    f = np.zeros((m, t))
+    for i in range(bumps):
+        d2 = (X - rad[i] * np.cos(ang[i])) ** 2 + (Y - rad[i] * np.sin(ang[i])) ** 2
+        f += a[i] * np.exp(-d2 / (2.0 * sw[i] ** 2))
+    f *= ((1.0 - r * r) ** 6)[:, None]
+    return r, wr, zeros, f
