@@ -284,6 +284,48 @@ def bench_pn(torch, nuht, workloads, dev, reps=3):
     return res
 
 
+def bench_disk(torch, nuht, workloads, dev, reps=5):
+    """The Helmholtz solver on the unit disk (Sec. 5.3) at the paper's example
+    kappa = 25, eps = 1e-8: m = 512 Gauss-Legendre radii, t = 256 angles,
+    orders -100 .. 100, J = 128 radial modes per order, a random smooth
+    forcing.  Solver planning once, then analysis, synthesis and the whole
+    solve (analysis, division by the eigenvalues, synthesis), each timed over
+    `reps` calls.  A solve runs 8 (L + 1) transforms (real and imaginary
+    parts of orders +-l, both directions) of n + m = 512 + 128 each."""
+    m, t, L, J, eps, kappa = 512, 256, 100, 128, 1e-8, 25.0
+    r, wr, zeros, f = workloads.disk(m, t, L, J, seed=190)
+    rd, wrd, zd, fd = (torch.as_tensor(a, device=dev) for a in (r, wr, zeros, f))
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    s = nuht.DiskSolver(rd, wrd, t, zd, eps)
+    torch.cuda.synchronize()
+    plan_ms = 1e3 * (time.perf_counter() - a)
+    alpha = s.analysis(fd)
+    beta = alpha.clone()
+    s.synthesis(beta)
+    s.helmholtz(kappa, fd)                       # warm-up of every path
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / reps
+
+    an_ms = timed(lambda: s.analysis(fd))
+    sy_ms = timed(lambda: s.synthesis(beta))
+    he_ms = timed(lambda: s.helmholtz(kappa, fd))
+    s.close()
+    transforms = 8 * (L + 1)
+    res = dict(m=m, t=t, L=L, J=J, eps=eps, kappa=kappa, plan_ms=plan_ms, analysis_ms=an_ms, synthesis_ms=sy_ms,
+               solve_ms=he_ms, transforms_per_solve=transforms,
+               transform_rate=transforms * (m + J) / (he_ms * 1e-3))
+    log("disk solver:", json.dumps(res))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,6 +337,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-looped comparison")
     ap.add_argument("--no-grad", action="store_true", help="skip the forward+backward comparison")
     ap.add_argument("--no-loose", action="store_true", help="skip the eps = 1e-6 (FP64 and FP32 spreading) runs")
+    ap.add_argument("--no-disk", action="store_true", help="skip the disk Helmholtz solver leg")
     ap.add_argument("--no-pn", action="store_true",
                     help="skip the p = O(n) study (Fourier-Bessel and exponential points at n = m = 1e6)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -465,6 +508,7 @@ def main():
     batched = None if args.no_batched else bench_batched(torch, nuht, workloads, dev)
     fwd_bwd = None if args.no_grad else bench_fwd_bwd(torch, nuht, workloads, dev)
     pn = None if args.no_pn else bench_pn(torch, nuht, workloads, dev)
+    disk = None if args.no_disk else bench_disk(torch, nuht, workloads, dev)
 
     out = {
         "metric": "(n+m)/s at eps=1e-12 vs direct sum; batched and fwd+bwd speedup, HBM GB/s",
@@ -492,6 +536,7 @@ def main():
         "fwd_bwd": fwd_bwd,
         "eps_1e-6": loose,
         "p_equals_n": pn,
+        "disk_helmholtz": disk,
     }
     if loose is not None:
         for mode in ("fp64", "fp32_spread"):

@@ -1178,14 +1178,16 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
 // as fit), the lanes of a row sum strided entries and combine by shuffles.  A
 // row lies in at most one direct block (the last block of its path down the
 // subdivision tree), so the per-row sums are stored, not accumulated.
-__global__ __launch_bounds__(64) void k_direct_blocks(PlanDev P, const double* __restrict__ cs,
-                                                      double* __restrict__ gd)
+constexpr int kDirectThreads = 256;
+
+__global__ __launch_bounds__(kDirectThreads) void k_direct_blocks(PlanDev P, const double* __restrict__ cs,
+                                                                  double* __restrict__ gd)
 {
     const DBlock D = P.db[blockIdx.x];
     const int mb = D.j1 - D.j0 + 1, nb = D.k1 - D.k0 + 1;
     int G = 1;
-    while (G < 64 && 2 * G * mb <= 64) G <<= 1;
-    const int rows_per_pass = 64 / G;
+    while (G < 64 && 2 * G * mb <= kDirectThreads) G <<= 1;
+    const int rows_per_pass = kDirectThreads / G;
     const int lane = threadIdx.x;
     const int grp = lane / G, gl = lane & (G - 1);
     for (int r0 = 0; r0 < mb; r0 += rows_per_pass) {
@@ -1490,7 +1492,7 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
     mark(marks, 5, s);
     if (P.n_d > 0) {
         hipLaunchKernelGGL(k_fill_zero, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, B.gd, (int64_t)P.m);
-        hipLaunchKernelGGL(k_direct_blocks, dim3(P.n_d), dim3(64), 0, s, P, B.cs, B.gd);
+        hipLaunchKernelGGL(k_direct_blocks, dim3(P.n_d), dim3(kDirectThreads), 0, s, P, B.cs, B.gd);
     }
     mark(marks, 6, s);
     dispatch_channels(P.nch, [&](auto k) { launch_rows_asy<decltype(k)::value>(P, B, s); });
