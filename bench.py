@@ -326,6 +326,34 @@ def bench_disk(torch, nuht, workloads, dev, reps=5):
     return res
 
 
+def bench_split(torch, nuht, r, w, c, reps=5):
+    """Exact against quasi-optimal SplitIndices (Sec. 4.1) at the large uniform
+    workload, nu = 0, eps = 1e-12: plan and execute times and the partition's
+    direct area for 16 candidate rows per split (the default) and for every
+    row (split_candidates = -1)."""
+    res = {}
+    for name, cand in (("quasi_16", 0), ("exact", -1)):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        p = nuht.Plan(r, w, 0, EPS, split_candidates=cand)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        p.execute(c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            p.execute(c)
+        torch.cuda.synchronize()
+        ex = 1e3 * (time.perf_counter() - t0) / reps
+        inf = p.info()
+        p.close()
+        res[name] = dict(plan_ms=1e3 * (b - a), execute_ms=ex, levels=inf["levels"],
+                         blocks=[inf["n_local"], inf["n_asy"], inf["n_direct"]], direct_entries=inf["direct_entries"],
+                         asy_col_members=inf["asy_col_members"], local_row_members=inf["local_row_members"])
+    log("split:", json.dumps(res))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -338,6 +366,7 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the forward+backward comparison")
     ap.add_argument("--no-loose", action="store_true", help="skip the eps = 1e-6 (FP64 and FP32 spreading) runs")
     ap.add_argument("--no-disk", action="store_true", help="skip the disk Helmholtz solver leg")
+    ap.add_argument("--no-split", action="store_true", help="skip the exact-split comparison")
     ap.add_argument("--no-pn", action="store_true",
                     help="skip the p = O(n) study (Fourier-Bessel and exponential points at n = m = 1e6)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -509,6 +538,7 @@ def main():
     fwd_bwd = None if args.no_grad else bench_fwd_bwd(torch, nuht, workloads, dev)
     pn = None if args.no_pn else bench_pn(torch, nuht, workloads, dev)
     disk = None if args.no_disk else bench_disk(torch, nuht, workloads, dev)
+    split = None if args.no_split else bench_split(torch, nuht, *inputs[0])
 
     out = {
         "metric": "(n+m)/s at eps=1e-12 vs direct sum; batched and fwd+bwd speedup, HBM GB/s",
@@ -537,6 +567,7 @@ def main():
         "eps_1e-6": loose,
         "p_equals_n": pn,
         "disk_helmholtz": disk,
+        "split_exact": split,
     }
     if loose is not None:
         for mode in ("fp64", "fp32_spread"):

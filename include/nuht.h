@@ -55,7 +55,9 @@ typedef struct nuht_plan_s *nuht_plan_t;
  *                     of area <= min_size is applied directly (0 -> 1024, the
  *                     paper's default, Sec. 4.1).
  *   M_override        number of asymptotic terms M (0 -> eq. num-asy-terms).
- *   split_candidates  equispaced candidate rows in SplitIndices (0 -> 16).
+ *   split_candidates  equispaced candidate rows in SplitIndices (0 -> 16);
+ *                     -1: every row of a block (the exact optimum of the
+ *                     split objective, Sec. 4.1; O(rows) per split on one lane).
  *   precision         NUHT_FP64, or NUHT_FP32_SPREAD: the ES spreading of
  *                     the asymptotic blocks (step one of the type-3 NUFFTs,
  *                     Sec. 3.2) keeps its weights, kernel values and channel

@@ -60,7 +60,9 @@ def split_indices(K, j0: int, j1: int, k0: int, k1: int, ncand: int = 16):
 
     The candidate rows are equispaced over j0 .. jl, jl being the last row of
     the block that holds a local entry (K is nonincreasing in j, so jl is found
-    by bisection); rows below jl cannot hold the split point."""
+    by bisection); rows below jl cannot hold the split point.  ncand = 0 takes
+    every row j0 .. jl: the exact optimum of the objective (Sec. 4.1 notes an
+    O(j1 - j0 + k1 - k0) exact solve)."""
     lo, hi = j0, j1
     while lo < hi:
         mid = lo + (hi - lo + 1) // 2
@@ -70,7 +72,9 @@ def split_indices(K, j0: int, j1: int, k0: int, k1: int, ncand: int = 16):
             hi = mid - 1
     jl = lo
     best = None
-    if jl > j0:
+    if jl > j0 and ncand == 0:
+        cands = range(j0, jl + 1)
+    elif jl > j0:
         cands = [j0 + (c * (jl - j0)) // (ncand - 1) for c in range(ncand)]
     else:
         cands = [j0]

@@ -617,7 +617,8 @@ static int part_begin(nuht_plan_t pl, PendingPart& pp, Partition& Pt, const Geom
     }
     const nuht_opts& o = pl->opts;
     int64_t min_size = o.min_size > 0 ? o.min_size : 1024;
-    int ncand = o.split_candidates > 1 ? o.split_candidates : 16;
+    // -1: every row of a block is a candidate (the exact split optimum)
+    int ncand = o.split_candidates == -1 ? INT32_MAX : (o.split_candidates > 1 ? o.split_candidates : 16);
     int dft_max = o.dft_max == 0 ? 48 : o.dft_max;
     const double sigma = 2.0;
     pp.tmp.release();
@@ -871,7 +872,7 @@ static int check_opts(const nuht_opts* opts, nuht_opts& o)
     if (opts) o = *opts;
     if (o.precision != NUHT_FP64 && o.precision != NUHT_FP32_SPREAD) return NUHT_EINVAL;
 
-    if (o.min_size < 0 || o.M_override < 0 || o.M_override > 20 || o.split_candidates < 0) return NUHT_EINVAL;
+    if (o.min_size < 0 || o.M_override < 0 || o.M_override > 20 || o.split_candidates < -1) return NUHT_EINVAL;
     if (o.spread_chunk != 0 && (o.spread_chunk < 64 || o.spread_chunk > 16384)) return NUHT_EINVAL;
     return NUHT_OK;
 }

@@ -293,11 +293,13 @@ __device__ __forceinline__ NodeSplit split_node(const Rect& R, int32_t kj1, int3
         if (jl > R.j1) jl = R.j1;
         int64_t best = INT64_MAX;
         int32_t span = jl - R.j0;
-        int32_t nc = span > 0 ? ncand : 1;
+        // more candidates than rows is every row (the exact optimum)
+        int32_t nc = span > 0 ? (ncand <= span ? ncand : span + 1) : 1;
         // candidate c is row j0 + floor(c span / (nc - 1)); the quotient is
         // formed in double, exactly: c span < 2^53, and a non-integer quotient
         // is at least 1/(nc-1) away from an integer
         auto row_of = [&](int32_t c) {
+            if (nc == span + 1) return R.j0 + c;            // every row
             return span > 0 ? R.j0 + (int32_t)floor((double)c * (double)span / (double)(nc - 1)) : R.j0;
         };
         auto consider = [&](int32_t j, int32_t kraw) {
@@ -319,9 +321,17 @@ __device__ __forceinline__ NodeSplit split_node(const Rect& R, int32_t kj1, int3
             for (int32_t c = 0; c < kSplitUnroll; ++c)
                 if (c < nc) consider(jv[c], kv[c]);
         } else {
-            for (int32_t c = 0; c < nc; ++c) {
-                const int32_t j = row_of(c);
-                consider(j, K[j]);
+            // batches of kSplitUnroll candidates with their loads in flight
+            for (int32_t c0 = 0; c0 < nc; c0 += kSplitUnroll) {
+                int32_t jv[kSplitUnroll], kv[kSplitUnroll];
+                #pragma unroll
+                for (int32_t c = 0; c < kSplitUnroll; ++c) {
+                    jv[c] = row_of(c0 + c < nc ? c0 + c : c0);
+                    kv[c] = K[jv[c]];
+                }
+                #pragma unroll
+                for (int32_t c = 0; c < kSplitUnroll; ++c)
+                    if (c0 + c < nc) consider(jv[c], kv[c]);
             }
         }
     }

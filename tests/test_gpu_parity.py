@@ -325,3 +325,33 @@ def test_largest_fft_and_grid_limit(nuht):
     with pytest.raises(nuht.NuhtError) as err:
         nuht.Plan(dev(r), dev(w_big), 0, 1e-12)
     assert err.value.code == -6
+
+
+@pytest.mark.parametrize("kind", ["small_dense", "exponential"])
+def test_exact_split_matches_oracle(nuht, kind):
+    """split_candidates = -1 (every row a candidate): the partition is the
+    oracle's exact-split partition block for block in its statistics, and the
+    transform still meets the direct-sum bar."""
+    if kind == "small_dense":
+        r, w, c = workloads.small_dense(seed=5)
+    else:
+        r, w, c = workloads.exponential(3000, seed=6)
+    p = nuht.Plan(dev(r), dev(w), 0, 1e-12, split_candidates=-1)
+    g = host(p.execute(dev(c)))
+    info = p.info()
+    p.close()
+    M, z, L = oparams.parameters(0, 1e-12)
+    K = direct.staircase(np.sort(r), np.sort(w), z)
+    st = partition.stats(partition.subdivide(K, w.size, r.size, ncand=0))
+    quasi = partition.stats(partition.subdivide(K, w.size, r.size))
+    print(kind, "exact: levels", st["levels"], "mixed-free area local", st["L"]["area"], "asy", st["A"]["area"],
+          "direct", st["D"]["area"], "| quasi direct", quasi["D"]["area"])
+    assert info["n_local"] == st["L"]["count"]
+    assert info["n_asy"] == st["A"]["count"]
+    assert info["n_direct"] == st["D"]["count"]
+    assert info["levels"] == st["levels"]
+    assert info["local_row_members"] == st["L"]["row_members"]
+    assert info["asy_col_members"] == st["A"]["col_members"]
+    assert info["direct_entries"] == st["D"]["area"]
+    g1 = direct.dht(0, r, c, w)
+    assert rel_l2(g, g1) <= TOL

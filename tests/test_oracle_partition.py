@@ -108,3 +108,41 @@ def test_depth_stays_small_with_many_equal_points():
     assert partition.stats(blocks)['levels'] < 20
     blocks = _check_partition(np.full(1000, 0.3), w, 31.5, 64)
     assert partition.stats(blocks)['levels'] <= 3
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_exact_split_is_the_brute_force_optimum(seed):
+    """ncand = 0 (every row) returns the argmin of the mixed area over all rows
+    of the block, ties to the smaller row, computed here by brute force over
+    every (j, k) with k the block's last local column in row j; and it is
+    never worse than the 16-candidate split."""
+    rng = np.random.default_rng(200 + seed)
+    rs = np.sort(rng.uniform(0, 1, 700) ** rng.uniform(0.5, 2))
+    ws = np.sort(rng.uniform(0, 1500, 600))
+    K = direct.staircase(rs, ws, 31.5)
+    m, n = ws.size, rs.size
+    for (j0, j1, k0, k1) in ((0, m - 1, 0, n - 1), (50, 400, 100, 650), (10, 200, 0, 300)):
+        objective = []
+        for j in range(j0, j1 + 1):
+            k = min(int(K[j]) - 1, k1)
+            if k < k0:
+                k = k0 - 1
+            objective.append(((j - j0 + 1) * (k1 - k) + (j1 - j) * (k - k0 + 1), j, k))
+        best = min(objective)                       # smallest area, then smallest j
+        je, ke = partition.split_indices(K, j0, j1, k0, k1, ncand=0)
+        area = lambda j, k: (j - j0 + 1) * (k1 - k) + (j1 - j) * (k - k0 + 1)
+        assert area(je, ke) == best[0]
+        assert (je, ke) == (best[1], best[2]) or area(je, ke) == best[0]
+        jq, kq = partition.split_indices(K, j0, j1, k0, k1)
+        assert area(je, ke) <= area(jq, kq)
+
+
+def test_exact_split_partition_valid():
+    rng = np.random.default_rng(11)
+    r = rng.uniform(0, 1, 300)
+    w = rng.uniform(0, 2000, 250)
+    rs, ws = np.sort(r), np.sort(w)
+    K = direct.staircase(rs, ws, 31.5)
+    blocks = partition.subdivide(K, ws.size, rs.size, 64, ncand=0)
+    cov = partition.coverage(blocks, ws.size, rs.size)
+    assert cov.min() == 1 and cov.max() == 1
