@@ -242,9 +242,9 @@ def bench_pn(torch, nuht, workloads, dev, reps=3):
     nu = 0), Fourier-Bessel only.  Plan + execute per transform."""
     n = 1_000_000
 
-    def timed(arrs, nu, eps):
+    def timed(arrs, nu, eps, **kw):
         r, w, c = (torch.as_tensor(a, device=dev) for a in arrs)
-        p = nuht.Plan(r, w, nu, eps)                 # warm-up
+        p = nuht.Plan(r, w, nu, eps, **kw)           # warm-up
         p.execute(c)
         inf = p.info()
         p.close()
@@ -252,7 +252,7 @@ def bench_pn(torch, nuht, workloads, dev, reps=3):
         t_plan = t_exec = 0.0
         for _ in range(reps):
             a = time.perf_counter()
-            p = nuht.Plan(r, w, nu, eps)
+            p = nuht.Plan(r, w, nu, eps, **kw)
             torch.cuda.synchronize()
             b = time.perf_counter()
             p.execute(c)
@@ -275,10 +275,17 @@ def bench_pn(torch, nuht, workloads, dev, reps=3):
     sweep = []
     for eps in (1e-4, 1e-6, 1e-10, 1e-12, 1e-15):
         sweep.append(timed(fb0, 0, eps))
+    tail = []
     for nu in (10, 100):
-        sweep.append(timed(workloads.fourier_bessel(n, nu, seed=160 + nu), nu, 1e-8))
+        fb = workloads.fourier_bessel(n, nu, seed=160 + nu)
+        sweep.append(timed(fb, nu, 1e-8))
+        tail.append(timed(fb, nu, 1e-8, local_rank=-1))
     keep = ("nu", "eps", "plan_ms", "execute_ms", "value", "M", "L", "levels")
     res["fourier_bessel_sweep"] = [{k: d[k] for k in keep} for d in sweep]
+    # the same two orders with the tail-sum local rank (local_rank = -1)
+    res["fourier_bessel_tail_rank"] = [{k: d[k] for k in keep} for d in tail]
+    for d in res["fourier_bessel_tail_rank"]:
+        log("p=O(n): fourier_bessel tail rank", json.dumps(d))
     for d in res["fourier_bessel_sweep"]:
         log("p=O(n): fourier_bessel sweep", json.dumps(d))
     return res

@@ -79,6 +79,11 @@ typedef struct nuht_plan_s *nuht_plan_t;
  *                     grid from at most 6 first cells (many points per cell)
  *                     are spread on the matrix cores; the two give the same
  *                     sums up to rounding order.
+ *   local_rank        0: the local rank L of Lemma 3.1 (Sec. 3.3); -1: the
+ *                     smallest L whose dropped Wimp terms sum below eps / 2
+ *                     at 512 points of (0, z] (tighter for large nu: 205
+ *                     instead of 270 at nu = 100, eps = 1e-8); 1 .. 2000: that
+ *                     L (the caller answers for the accuracy).
  */
 typedef struct {
     int64_t min_size;
@@ -89,6 +94,7 @@ typedef struct {
     int32_t spread_chunk;
     int32_t tune;
     int32_t vector_spread;
+    int32_t local_rank;
 } nuht_opts;
 
 /*

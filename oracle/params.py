@@ -125,3 +125,32 @@ def parameters(nu: int, eps: float, M: int = None):
     z = crossover(nu, eps, M)
     L = local_rank(nu, eps, z)
     return M, z, L
+
+
+def tail_local_rank(nu: int, eps: float, z: float, L_lemma: int, grid: int = 512):
+    """A tighter local rank: the smallest L <= L_lemma whose dropped Wimp terms
+    sum_{l > L} |C_l(x)| stay at or below eps / 2 at the grid points
+    x = z g / grid, g = 1 .. grid (every entry of a local block is off by at
+    most that sum, the Chebyshev factors being bounded by 1).  C_l(x) =
+    delta_l J_{a+l}(x/2) J_{a-l}(x/2) (even nu), 2 J_{a+1+l}(x/2) J_{a-l}(x/2)
+    (odd nu), a = floor(|nu| / 2), with SciPy's J.  Returns (L, tail maxima
+    per L)."""
+    import numpy as np
+    from scipy import special
+    nu = abs(int(nu))
+    a = nu // 2
+    lmax = L_lemma + 40
+    l = np.arange(lmax + 1)
+    tailmax = np.zeros(lmax + 1)
+    for g in range(1, grid + 1):
+        y = 0.5 * z * g / grid
+        hi = special.jv(a + 1 + l, y) if nu % 2 else special.jv(a + l, y)
+        lo = special.jv(np.abs(a - l), y)
+        f = np.where((l > 0) | (nu % 2 == 1), 2.0, 1.0)
+        C = f * np.abs(hi * lo)
+        after = np.concatenate((np.cumsum(C[::-1])[::-1][1:], [0.0]))   # sum over l' > l
+        tailmax = np.maximum(tailmax, after)
+    for L in range(L_lemma):
+        if tailmax[L] <= 0.5 * eps:
+            return L, tailmax
+    return L_lemma, tailmax

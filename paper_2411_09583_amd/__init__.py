@@ -36,7 +36,7 @@ class NuhtOpts(ctypes.Structure):
     _fields_ = [("min_size", ctypes.c_int64), ("M_override", ctypes.c_int32),
                 ("split_candidates", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("dft_max", ctypes.c_int32), ("spread_chunk", ctypes.c_int32), ("tune", ctypes.c_int32),
-                ("vector_spread", ctypes.c_int32)]
+                ("vector_spread", ctypes.c_int32), ("local_rank", ctypes.c_int32)]
 
 
 class NuhtInfo(ctypes.Structure):
@@ -143,7 +143,7 @@ class Plan:
 
     def __init__(self, r, omega, nu: int, eps: float, *, min_size: int = 0, M: int = 0,
                  split_candidates: int = 0, precision: int = NUHT_FP64, dft_max: int = 0,
-                 spread_chunk: int = 0, vector_spread: bool = False):
+                 spread_chunk: int = 0, vector_spread: bool = False, local_rank: int = 0):
         lib = load_library()
         r = _dev_f64(r, "r")
         omega = _dev_f64(omega, "omega")
@@ -151,7 +151,7 @@ class Plan:
         self.m = omega.numel()
         self.device = r.device
         opts = NuhtOpts(min_size, M, split_candidates, precision, dft_max, spread_chunk, 0,
-                        1 if vector_spread else 0)
+                        1 if vector_spread else 0, int(local_rank))
         h = ctypes.c_void_p()
         _check(lib.nuht_plan(ctypes.byref(h), int(nu), float(eps), self.n, _ptr(r), self.m, _ptr(omega),
                              ctypes.byref(opts), _stream()))

@@ -98,6 +98,57 @@ static int local_rank(int nu, double eps, double z)
     return -1;
 }
 
+// A tighter local rank: the smallest L whose dropped Wimp terms,
+// sum_{l > L} |C_l(x)|, stay below eps / 2 at 512 equispaced x in (0, z]
+// (every entry of a local block is off by at most that sum, |T_2l| <= 1),
+// and never above L_lemma.  C_l(x) = delta_l J_{a+l}(x/2) J_{a-l}(x/2) for
+// even nu and 2 J_{a+1+l}(x/2) J_{a-l}(x/2) for odd nu (a = floor(nu/2),
+// |J_{-k}| = |J_k|), the J_k from Miller's backward recurrence in long
+// double, normalised by J_0 + 2 sum_k J_2k = 1.
+static int local_rank_tail(int nu, double eps, double z, int L_lemma)
+{
+    const int a = nu >> 1;
+    const int lmax = L_lemma + 40;
+    const int K = a + 2 + lmax;                     // highest order a term needs
+    std::vector<long double> J(K + 1), C(lmax + 1);
+    std::vector<double> tailmax(lmax + 1, 0.0);     // max over x of sum_{l' > l} |C_l'|
+    const int G = 512;
+    for (int g = 1; g <= G; ++g) {
+        const long double y = 0.5L * (long double)z * g / G;
+        const int N = K + 30 + (int)(y + 8.0L * std::cbrt(y));
+        long double jp = 0.0L, jc = 1e-30L, S = 0.0L;
+        for (int k = N; k >= 1; --k) {
+            if (k <= K) J[k] = jc;
+            if ((k & 1) == 0) S += 2.0L * jc;
+            const long double jm = (2.0L * k / y) * jc - jp;
+            jp = jc;
+            jc = jm;
+            if (std::fabs(jc) > 1e2000L) {          // rescale the running and stored values
+                jp *= 1e-2000L; jc *= 1e-2000L; S *= 1e-2000L;
+                for (int q = k - 1 > K ? K + 1 : k - 1; q <= K; ++q)
+                    if (q >= 0) J[q] *= 1e-2000L;
+            }
+        }
+        J[0] = jc;
+        S += jc;
+        for (int k = 0; k <= K; ++k) J[k] /= S;
+        for (int l = 0; l <= lmax; ++l) {
+            const int lo = a - l < 0 ? l - a : a - l;
+            const long double hi = (nu & 1) ? J[a + 1 + l] : J[a + l];
+            const long double f = ((nu & 1) || l > 0) ? 2.0L : 1.0L;
+            C[l] = f * std::fabs(hi * J[lo]);
+        }
+        long double tail = 0.0L;
+        for (int l = lmax; l >= 0; --l) {
+            if ((double)tail > tailmax[l]) tailmax[l] = (double)tail;
+            tail += C[l];
+        }
+    }
+    for (int L = 0; L < L_lemma; ++L)
+        if (tailmax[L] <= 0.5 * eps) return L;
+    return L_lemma;
+}
+
 // ===========================================================================
 // Exponential-of-semicircle kernel: width and shape from eps, and the
 // Chebyshev series of its Fourier transform ES^(kappa) on [0, w pi / 4].
@@ -549,6 +600,8 @@ static void fill_params(PlanDev& P, int nu, double eps, const nuht_opts& o)
     P.nch = padded_channels(2 * M);
     P.z = crossover(anu, eps, M);
     P.L = local_rank(anu, eps, P.z);
+    if (o.local_rank > 0) P.L = o.local_rank;
+    else if (o.local_rank == -1 && P.L >= 0) P.L = local_rank_tail(anu, eps, P.z, P.L);
     P.w = es_width(eps, o.precision);
     P.fp32 = o.precision == NUHT_FP32_SPREAD ? 1 : 0;
     P.mfma = (!P.fp32 && P.w <= 16 && P.nch <= 16 && !o.vector_spread) ? 1 : 0;
@@ -872,7 +925,9 @@ static int check_opts(const nuht_opts* opts, nuht_opts& o)
     if (opts) o = *opts;
     if (o.precision != NUHT_FP64 && o.precision != NUHT_FP32_SPREAD) return NUHT_EINVAL;
 
-    if (o.min_size < 0 || o.M_override < 0 || o.M_override > 20 || o.split_candidates < -1) return NUHT_EINVAL;
+    if (o.min_size < 0 || o.M_override < 0 || o.M_override > 20 || o.split_candidates < -1 || o.local_rank < -1 ||
+        o.local_rank > 2000)
+        return NUHT_EINVAL;
     if (o.spread_chunk != 0 && (o.spread_chunk < 64 || o.spread_chunk > 16384)) return NUHT_EINVAL;
     return NUHT_OK;
 }
@@ -1126,6 +1181,8 @@ int nuht_tune(nuht_plan_t p, const double* c_dev, int reps, nuht_opts* best, dou
     o.precision = p->opts.precision;
     o.M_override = p->opts.M_override;
     o.split_candidates = p->opts.split_candidates;
+    o.vector_spread = p->opts.vector_spread;
+    o.local_rank = p->opts.local_rank;
     p->opts = o;
     p->orders.clear();
     Partition* Pt = nullptr;
@@ -1256,6 +1313,8 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
             if (rc != NUHT_OK) return fail(rc);
             best.precision = o.precision; best.M_override = o.M_override;
             best.split_candidates = o.split_candidates;
+            best.vector_spread = o.vector_spread;
+            best.local_rank = o.local_rank;
             b->class_opts[c] = best;
         }
         for (int i = 0; i < count; ++i) {

@@ -355,3 +355,27 @@ def test_exact_split_matches_oracle(nuht, kind):
     assert info["direct_entries"] == st["D"]["area"]
     g1 = direct.dht(0, r, c, w)
     assert rel_l2(g, g1) <= TOL
+
+
+@pytest.mark.parametrize("nu,eps", [(0, 1e-12), (10, 1e-8), (37, 1e-8), (100, 1e-8)])
+def test_tail_local_rank(nuht, nu, eps):
+    """local_rank = -1: the library's rank is the oracle's tail rank (decided
+    on the same grid; where the two J evaluations could split a tie, the
+    oracle's tails must put the threshold between L - 1 and L), and the
+    transform of Fourier-Bessel points and frequencies (n = m = 3000, many
+    local blocks) meets the direct-sum bars."""
+    r, w, c = workloads.fourier_bessel(3000, nu, seed=300 + nu)
+    p = nuht.Plan(dev(r), dev(w), nu, eps, local_rank=-1)
+    g = host(p.execute(dev(c)))
+    info = p.info()
+    p.close()
+    M, z, L_lemma = oparams.parameters(nu, eps)
+    L_or, tails = oparams.tail_local_rank(nu, eps, z, L_lemma)
+    print("nu", nu, "eps", eps, "L lemma", L_lemma, "L gpu", info["L"], "L oracle", L_or)
+    if info["L"] != L_or:
+        L = info["L"]
+        assert abs(tails[L] / (0.5 * eps) - 1) < 1e-6 or (L > 0 and abs(tails[L - 1] / (0.5 * eps) - 1) < 1e-6)
+    g1 = direct.dht(nu, r, c, w)
+    bar = max(eps, 2e-14)
+    assert rel_l2(g, g1) <= 2 * bar
+    assert np.all(np.abs(g - g1) <= 2 * bar * np.sum(np.abs(c)))

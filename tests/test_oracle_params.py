@@ -115,3 +115,34 @@ def test_half_integer_order_hankel_coefficients_vanish():
     assert direct.hankel_coef(0.5, 1) == 0.0
     assert direct.hankel_coef(1.5, 1) != 0.0 and direct.hankel_coef(1.5, 2) == 0.0
     assert abs(prm.hankel_coef(7, 3) - direct.hankel_coef(7, 3)) <= 1e-15 * abs(prm.hankel_coef(7, 3))
+
+
+@pytest.mark.parametrize("nu,eps", [(0, 1e-12), (1, 1e-10), (10, 1e-8), (37, 1e-8), (100, 1e-8)])
+def test_tail_local_rank_keeps_the_local_expansion_within_eps(nu, eps):
+    """With the tail rank L, the Wimp expansion sum_{l <= L} C_l(x) T_{2l(+1)}(y)
+    reproduces J_nu(x y) to eps at random x in (0, z], y in [0, 1] -- J from
+    mpmath, T from numpy's Chebyshev module, independent of the rank rule --
+    and L never exceeds Lemma 3.1's."""
+    import mpmath
+    from numpy.polynomial import chebyshev
+    M, z, L_lemma = prm.parameters(nu, eps)
+    L, _ = prm.tail_local_rank(nu, eps, z, L_lemma)
+    assert L <= L_lemma
+    rng = np.random.default_rng(nu)
+    a = nu // 2
+    worst = 0.0
+    for _ in range(25):
+        x = z * rng.uniform(0.05, 1.0)
+        y = rng.uniform(0.0, 1.0)
+        s = mpmath.mpf(0)
+        for l in range(L + 1):
+            if nu % 2 == 0:
+                C = (1 if l == 0 else 2) * mpmath.besselj(a + l, x / 2) * mpmath.besselj(a - l, x / 2)
+                T = chebyshev.chebval(y, [0] * (2 * l) + [1])
+            else:
+                C = 2 * mpmath.besselj(a + 1 + l, x / 2) * mpmath.besselj(a - l, x / 2)
+                T = chebyshev.chebval(y, [0] * (2 * l + 1) + [1])
+            s += C * T
+        worst = max(worst, abs(float(s - mpmath.besselj(nu, x * y))))
+    print("nu", nu, "eps", eps, "L lemma", L_lemma, "L tail", L, "worst", worst)
+    assert worst <= eps
