@@ -1173,9 +1173,10 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
     return kSqrt2OverPi * amp * __builtin_fma(cr, ar, -ci * ai);
 }
 
-// Direct blocks (entry by entry, J_nu to full precision).  One 64-lane wave
-// per block: each row of the block is given G lanes (G a power of two, as many
-// as fit), the lanes of a row sum strided entries and combine by shuffles.  A
+// Direct blocks (entry by entry, J_nu to full precision).  One workgroup of
+// kDirectThreads lanes per block: each row of the block is given G lanes (G a
+// power of two up to 64, as many as fit), the lanes of a row sum strided
+// entries and combine by shuffles.  A
 // row lies in at most one direct block (the last block of its path down the
 // subdivision tree), so the per-row sums are stored, not accumulated.
 constexpr int kDirectThreads = 256;
