@@ -145,7 +145,8 @@ __global__ void k_lmom_reduce(PlanDev P, const double* __restrict__ lpart, doubl
     const LBlock B = P.lb[b];
     double s = 0.0;
     for (int32_t it = 0; it < B.nitems; ++it) s += lpart[(int64_t)(B.item0 + it) * Lp + l];
-    lmom[t] = s;
+    // stored as the row pass uses them: u_0 = t_0, u_l = 2 (-1)^l t_l
+    lmom[t] = l == 0 ? s : ((l & 1) ? -2.0 * s : 2.0 * s);
 }
 
 // ---------------------------------------------------------------------------
@@ -901,6 +902,16 @@ __device__ __forceinline__ void miller_rescale(double& yk, double& yk1, double& 
     if (fabs(yk) > 1e100) { yk *= 1e-100; yk1 *= 1e-100; S2 *= 1e-200; dot *= 1e-200; }
 }
 
+// Once per four steps, for waves whose arguments are all >= kMillerGroupY: a
+// step multiplies the values by at most 2N / y + 1 < 4.2e6 (start N <= 2048,
+// the largest local rank allowed plus one), four steps by less than 3.1e26,
+// so the values stay below 3.1e126 and their squares and sums finite.
+constexpr double kMillerGroupY = 1e-3;
+__device__ __forceinline__ void miller_rescale_group(double& yk, double& yk1, double& S2, double& dot)
+{
+    if (fmax(fabs(yk), fabs(yk1)) > 1e100) { yk *= 1e-100; yk1 *= 1e-100; S2 *= 1e-200; dot *= 1e-200; }
+}
+
 // Four consecutive local moments (8-byte aligned, read as one block).
 struct Moments4 {
     double v[4];
@@ -939,21 +950,35 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
             miller_rescale(yk, yk1, S2, dot);
         }
         // i = L .. 1 in every lane (the start is above L): L mod 4 single
-        // steps, then groups of four whose moments t[i-3 .. i] are read together
-        auto step = [&](int k, double tk) {
+        // steps, then groups of four whose moments u[i-3 .. i] are read
+        // together (u_i = 2 (-1)^i t_i)
+        auto step = [&](int k, double uk, bool check) {
             double q = yk * yk;
             S2 = __builtin_fma(2.0, q, S2);
-            double c = 2.0 * tk;
-            dot = __builtin_fma((k & 1) ? -c : c, q, dot);
+            dot = __builtin_fma(uk, q, dot);
             double ykm1 = __builtin_fma((double)k * rec, yk, -yk1);
             yk1 = yk; yk = ykm1;
-            miller_rescale(yk, yk1, S2, dot);
+            if (check) miller_rescale(yk, yk1, S2, dot);
         };
-        for (int u = L & 3; u > 0; --u, --i) step(i, t[i]);
-        for (; i >= 4; i -= 4) {
-            Moments4 q;
-            __builtin_memcpy(&q, t + i - 3, sizeof q);     // t[i-3 .. i] in one read
-            step(i, q.v[3]); step(i - 1, q.v[2]); step(i - 2, q.v[1]); step(i - 3, q.v[0]);
+        for (int u = L & 3; u > 0; --u, --i) step(i, t[i], true);
+        if (__all(y >= kMillerGroupY)) {
+            // four steps grow the values by less than 1e27: one rescale test
+            // per group, and the next group's moments in flight
+            Moments4 nx;
+            if (i >= 4) __builtin_memcpy(&nx, t + i - 3, sizeof nx);
+            for (; i >= 4; i -= 4) {
+                const Moments4 q = nx;
+                if (i >= 8) __builtin_memcpy(&nx, t + i - 7, sizeof nx);
+                step(i, q.v[3], false); step(i - 1, q.v[2], false);
+                step(i - 2, q.v[1], false); step(i - 3, q.v[0], false);
+                miller_rescale_group(yk, yk1, S2, dot);
+            }
+        } else {
+            for (; i >= 4; i -= 4) {
+                Moments4 q;
+                __builtin_memcpy(&q, t + i - 3, sizeof q);
+                step(i, q.v[3], true); step(i - 1, q.v[2], true); step(i - 2, q.v[1], true); step(i - 3, q.v[0], true);
+            }
         }
         S2 = __builtin_fma(yk, yk, S2);
         dot = __builtin_fma(t[0] * yk, yk, dot);
@@ -967,19 +992,30 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
             yk1 = yk; yk = ykm1;
             miller_rescale(yk, yk1, S2, dot);
         }
-        auto step = [&](int k, double tk) {
+        auto step = [&](int k, double uk, bool check) {
             S2 = __builtin_fma(2.0 * yk, yk, S2);
-            double c = 2.0 * tk;
-            dot = __builtin_fma(((k & 1) ? -c : c) * yk, yk1, dot);
+            dot = __builtin_fma(uk * yk, yk1, dot);
             double ykm1 = __builtin_fma((double)k * rec, yk, -yk1);
             yk1 = yk; yk = ykm1;
-            miller_rescale(yk, yk1, S2, dot);
+            if (check) miller_rescale(yk, yk1, S2, dot);
         };
-        for (int u = L & 3; u > 0; --u, --i) step(i, t[i]);
-        for (; i >= 4; i -= 4) {
-            Moments4 q;
-            __builtin_memcpy(&q, t + i - 3, sizeof q);     // t[i-3 .. i] in one read
-            step(i, q.v[3]); step(i - 1, q.v[2]); step(i - 2, q.v[1]); step(i - 3, q.v[0]);
+        for (int u = L & 3; u > 0; --u, --i) step(i, t[i], true);
+        if (__all(y >= kMillerGroupY)) {
+            Moments4 nx;
+            if (i >= 4) __builtin_memcpy(&nx, t + i - 3, sizeof nx);
+            for (; i >= 4; i -= 4) {
+                const Moments4 q = nx;
+                if (i >= 8) __builtin_memcpy(&nx, t + i - 7, sizeof nx);
+                step(i, q.v[3], false); step(i - 1, q.v[2], false);
+                step(i - 2, q.v[1], false); step(i - 3, q.v[0], false);
+                miller_rescale_group(yk, yk1, S2, dot);
+            }
+        } else {
+            for (; i >= 4; i -= 4) {
+                Moments4 q;
+                __builtin_memcpy(&q, t + i - 3, sizeof q);
+                step(i, q.v[3], true); step(i - 1, q.v[2], true); step(i - 2, q.v[1], true); step(i - 3, q.v[0], true);
+            }
         }
         S2 = __builtin_fma(yk, yk, S2);
         dot = __builtin_fma(2.0 * t[0] * yk, yk1, dot);
@@ -999,6 +1035,7 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
         const int odd = nu & 1;
         const int a = nu >> 1;
         const int a2 = nu - a;
+        const double sa = (a & 1) ? -1.0 : 1.0;
         const int hi1 = L - a;
         const int top = hi1 > nu ? hi1 : nu;
         const int s0 = N < hi1 + nu ? N : hi1 + nu;
@@ -1024,13 +1061,14 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
             S2 = __builtin_fma(i == 0 ? yk : 2.0 * yk, yk, S2);
             if (i >= a2 && i <= nu) ring[(i - a2) * stride] = yk;
             if (i >= 1 && i <= hi1) {
-                double coef = 2.0 * t[a + i];
-                dot = __builtin_fma(((i & 1) ? -coef : coef) * yk, lyk * lsc, dot);
+                // 2 (-1)^i t_{a+i} = (-1)^a u_{a+i}
+                dot = __builtin_fma(sa * t[a + i] * yk, lyk * lsc, dot);
             }
             if (i <= a && a - i <= L) {
                 int l2 = a - i;
                 double pv = ring[(nu - i - a2) * stride];
-                double coef = (!odd && l2 == 0) ? t[0] : 2.0 * t[l2];
+                // 2 t_l2 = (-1)^l2 u_l2 (l2 >= 1); t_0 = u_0
+                double coef = l2 == 0 ? (odd ? 2.0 * t[0] : t[0]) : ((l2 & 1) ? -t[l2] : t[l2]);
                 dot = __builtin_fma(coef * yk, pv, dot);
             }
             if (i == 0) break;
