@@ -1055,8 +1055,10 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
                 ++d; lsc = __builtin_amdgcn_ldexp(1.0, -332 * d);
             }
         }
-        // i = top .. 0 in every lane
-        for (; i >= 0; --i) {
+        // i = top .. 0 in every lane.  stepB takes the products at index i and
+        // (i > 0) moves both copies one index down; rescaleB follows a step
+        // whose last products were at index il (stored partners: indices il .. nu).
+        auto stepB = [&](int i) {
             if (i == act) { lyk = syk; lyk1 = syk1; }
             S2 = __builtin_fma(i == 0 ? yk : 2.0 * yk, yk, S2);
             if (i >= a2 && i <= nu) ring[(i - a2) * stride] = yk;
@@ -1071,20 +1073,38 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
                 double coef = l2 == 0 ? (odd ? 2.0 * t[0] : t[0]) : ((l2 & 1) ? -t[l2] : t[l2]);
                 dot = __builtin_fma(coef * yk, pv, dot);
             }
-            if (i == 0) break;
-            double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
-            yk1 = yk; yk = ykm1;
-            double lykm1 = __builtin_fma((double)(i + nu) * rec, lyk, -lyk1);
-            lyk1 = lyk; lyk = lykm1;
-            if (fabs(yk) > up) {
+            if (i > 0) {
+                double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
+                yk1 = yk; yk = ykm1;
+                double lykm1 = __builtin_fma((double)(i + nu) * rec, lyk, -lyk1);
+                lyk1 = lyk; lyk = lykm1;
+            }
+        };
+        auto rescaleB = [&](int il, bool group) {
+            const double ml = group ? fmax(fabs(yk), fabs(yk1)) : fabs(yk);
+            if (ml > up) {
                 yk *= down; yk1 *= down; S2 *= down2; dot *= down2;
                 ++d; lsc = __builtin_amdgcn_ldexp(1.0, -332 * d);
-                for (int q = (i > a2 ? i : a2) - a2; q <= nu - a2; ++q) ring[q * stride] *= down;
+                for (int q = (il > a2 ? il : a2) - a2; q <= nu - a2; ++q) ring[q * stride] *= down;
             }
-            if (fabs(lyk) > up) {
+            const double mg = group ? fmax(fabs(lyk), fabs(lyk1)) : fabs(lyk);
+            if (mg > up) {
                 lyk *= down; lyk1 *= down;
                 --d; lsc = __builtin_amdgcn_ldexp(1.0, -332 * d);
             }
+        };
+        if (__all(y >= kMillerGroupY)) {
+            // one rescale test per four steps (growth below 3.1e26 per group);
+            // the copies may rescale at different indices, d counts both
+            for (; i >= 4; i -= 4) {
+                stepB(i); stepB(i - 1); stepB(i - 2); stepB(i - 3);
+                rescaleB(i - 3, true);
+            }
+        }
+        for (; i >= 0; --i) {
+            stepB(i);
+            if (i == 0) break;
+            rescaleB(i, false);
         }
         return dot / S2;
     }
