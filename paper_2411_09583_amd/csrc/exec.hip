@@ -67,14 +67,15 @@ __global__ void k_half_difference(const double* __restrict__ w, const double* __
 // Local moments t_l = sum_k c_k T_{2l(+1)}(r_k / R) of one chunk of a local
 // block's columns (Sec. 3.1: T^T applied first).  The Chebyshev polynomials
 // come from the recurrence in u = 2y^2 - 1:  T_{2(l+1)+e}(y) = 2u T_{2l+e}(y) - T_{2(l-1)+e}(y).
-// Moments are produced 32 at a time.  One 64-lane wave per item: each lane
-// accumulates its points' moments in registers (points strided over the
-// lanes), and the wave reduces them with cross-lane sums.
+// Moments are produced in passes of 32 (the last of 16 or 8 when no more are
+// left).  One 64-lane wave per item: each lane accumulates its points'
+// moments in registers (points strided over the lanes), and the wave reduces
+// them with cross-lane sums.
 // ---------------------------------------------------------------------------
 // One reduce-scatter level: v[0 .. 2H) -> v[0 .. H), lanes with bit H set
 // keeping the upper half; partner lane ^ H holds the other copy.
-template <int H>
-__device__ __forceinline__ void reduce_scatter_half(double (&v)[32], int lane)
+template <int H, int NQ>
+__device__ __forceinline__ void reduce_scatter_half(double (&v)[NQ], int lane)
 {
     const bool upper = (lane & H) != 0;
     #pragma unroll
@@ -85,52 +86,66 @@ __device__ __forceinline__ void reduce_scatter_half(double (&v)[32], int lane)
     }
 }
 
+// Moments s0 .. s0 + NQ - 1 of the item (those up to L are stored).
+template <int NQ>
+__device__ __forceinline__ void lmom_pass(const PlanDev& P, const Item& I, const LBlock& B, const double* __restrict__ cs,
+                                          double* __restrict__ lpart, int s0, int lane)
+{
+    const int L = P.L;
+    const int odd = P.nu & 1;
+    double acc[NQ];
+    #pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    // two points per lane per step (the second with weight 0 past the end):
+    // both loads issue together and the recurrences are independent chains
+    for (int k = I.ka + lane; k < I.kb; k += 128) {
+        const bool two = k + 64 < I.kb;
+        const int k2 = two ? k + 64 : k;
+        const double ya = P.rs[k] / B.R, yb = P.rs[k2] / B.R;
+        const double ca = cs[k], cb = two ? cs[k2] : 0.0;
+        const double ua2 = 2.0 * __builtin_fma(2.0 * ya, ya, -1.0);
+        const double ub2 = 2.0 * __builtin_fma(2.0 * yb, yb, -1.0);
+        double a0, a1, b0, b1;
+        if (odd) { a0 = ya; a1 = ya * (ua2 - 1.0); b0 = yb; b1 = yb * (ub2 - 1.0); }
+        else { a0 = 1.0; a1 = 0.5 * ua2; b0 = 1.0; b1 = 0.5 * ub2; }
+        for (int l = 0; l < s0; ++l) {
+            const double a2 = __builtin_fma(ua2, a1, -a0), b2 = __builtin_fma(ub2, b1, -b0);
+            a0 = a1; a1 = a2; b0 = b1; b1 = b2;
+        }
+        #pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            acc[q] = __builtin_fma(cb, b0, __builtin_fma(ca, a0, acc[q]));
+            const double a2 = __builtin_fma(ua2, a1, -a0), b2 = __builtin_fma(ub2, b1, -b0);
+            a0 = a1; a1 = a2; b0 = b1; b1 = b2;
+        }
+    }
+    // Reduce-scatter over the wave: at offsets NQ/2 .. 1 each lane keeps the
+    // half of its values that its lane bit selects and adds its partner's
+    // copy of that half, so lane q holds moment s0 + (q mod NQ); exchanges at
+    // offsets NQ .. 32 complete the sums.
+    if constexpr (NQ >= 32) reduce_scatter_half<16>(acc, lane);
+    if constexpr (NQ >= 16) reduce_scatter_half<8>(acc, lane);
+    reduce_scatter_half<4>(acc, lane);
+    reduce_scatter_half<2>(acc, lane);
+    reduce_scatter_half<1>(acc, lane);
+    double mine = acc[0];
+    #pragma unroll
+    for (int o = NQ; o < 64; o <<= 1) mine += __shfl_xor(mine, o);
+    if (lane < NQ && s0 + lane <= L) lpart[(int64_t)blockIdx.x * (L + 1) + s0 + lane] = mine;
+}
+
 __global__ __launch_bounds__(64) void k_lmom(PlanDev P, const double* __restrict__ cs, double* __restrict__ lpart)
 {
     const Item I = P.litems[blockIdx.x];
     const LBlock B = P.lb[I.blk];
     const int L = P.L;
-    const int odd = P.nu & 1;
     const int lane = threadIdx.x;
-    for (int s0 = 0; s0 <= L; s0 += 32) {
-        double acc[32];
-        #pragma unroll
-        for (int q = 0; q < 32; ++q) acc[q] = 0.0;
-        // two points per lane per step (the second with weight 0 past the end):
-        // both loads issue together and the recurrences are independent chains
-        for (int k = I.ka + lane; k < I.kb; k += 128) {
-            const bool two = k + 64 < I.kb;
-            const int k2 = two ? k + 64 : k;
-            const double ya = P.rs[k] / B.R, yb = P.rs[k2] / B.R;
-            const double ca = cs[k], cb = two ? cs[k2] : 0.0;
-            const double ua2 = 2.0 * __builtin_fma(2.0 * ya, ya, -1.0);
-            const double ub2 = 2.0 * __builtin_fma(2.0 * yb, yb, -1.0);
-            double a0, a1, b0, b1;
-            if (odd) { a0 = ya; a1 = ya * (ua2 - 1.0); b0 = yb; b1 = yb * (ub2 - 1.0); }
-            else { a0 = 1.0; a1 = 0.5 * ua2; b0 = 1.0; b1 = 0.5 * ub2; }
-            for (int l = 0; l < s0; ++l) {
-                const double a2 = __builtin_fma(ua2, a1, -a0), b2 = __builtin_fma(ub2, b1, -b0);
-                a0 = a1; a1 = a2; b0 = b1; b1 = b2;
-            }
-            #pragma unroll
-            for (int q = 0; q < 32; ++q) {
-                acc[q] = __builtin_fma(cb, b0, __builtin_fma(ca, a0, acc[q]));
-                const double a2 = __builtin_fma(ua2, a1, -a0), b2 = __builtin_fma(ub2, b1, -b0);
-                a0 = a1; a1 = a2; b0 = b1; b1 = b2;
-            }
-        }
-        // Reduce-scatter over the wave: at offsets 16, 8, 4, 2, 1 each lane
-        // keeps the half of its values that its lane bit selects and adds its
-        // partner's copy of that half; a last exchange at offset 32 completes
-        // the sum.  Lane q (q < 32) then holds moment s0 + q: 32 exchanges
-        // instead of 32 full reductions.
-        reduce_scatter_half<16>(acc, lane);
-        reduce_scatter_half<8>(acc, lane);
-        reduce_scatter_half<4>(acc, lane);
-        reduce_scatter_half<2>(acc, lane);
-        reduce_scatter_half<1>(acc, lane);
-        double mine = acc[0] + __shfl_xor(acc[0], 32);
-        if (lane < 32 && s0 + lane <= L) lpart[(int64_t)blockIdx.x * (L + 1) + s0 + lane] = mine;
+    // passes of 32 moments; the last one as narrow as what is left allows
+    for (int s0 = 0; s0 <= L;) {
+        const int rem = L + 1 - s0;
+        if (rem > 16) { lmom_pass<32>(P, I, B, cs, lpart, s0, lane); s0 += 32; }
+        else if (rem > 8) { lmom_pass<16>(P, I, B, cs, lpart, s0, lane); s0 += 16; }
+        else { lmom_pass<8>(P, I, B, cs, lpart, s0, lane); s0 += 8; }
     }
 }
 
