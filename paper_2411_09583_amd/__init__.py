@@ -71,7 +71,7 @@ def load_library():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2411_09583_amd.build")
     lib = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
     lib.nuht_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_double, ctypes.c_int64, vp,
