@@ -31,6 +31,15 @@ constexpr int kSortThreads = 256;
 constexpr int kSortRounds = 16;
 constexpr int kSortTile = kSortThreads * kSortRounds;
 
+// Orders one wave's LDS accesses around it (lanes read a counter that one
+// lane of the same wave then updates).
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 struct SortSegs {
     int32_t off[3];      // element offsets of segments 0, 1 and the end
     int32_t tile0[3];    // tile offsets
@@ -130,13 +139,19 @@ __global__ __launch_bounds__(1024) void k_sort_scan(int32_t* __restrict__ hist, 
     if (threadIdx.x == 0) dtot[seg * 256 + d] = run;
 }
 
-// Stable scatter through LDS.  Within a tile, element order is (round,
-// thread).  The tile's count of each digit is the difference of consecutive
-// tile offsets in the scanned histogram, so the digit's run inside the tile
-// starts at an exclusive scan of those counts.  Each round ranks its 256 keys
-// among equal digits with wave ballots and shared per-wave counters and
-// places them in LDS in digit order; the finished tile is then written out
-// with consecutive threads on consecutive addresses of each digit's run.
+// Stable scatter through LDS.  Wave v of the block owns the tile's keys
+// v * 1024 .. v * 1024 + 1023 (in order), taken 64 at a time: each key is
+// ranked among the equal digits of its 64 with wave ballots, plus the count
+// of that digit in the wave's earlier keys (a wave-private counter in LDS, so
+// no block barrier per round).  One block step then turns the four waves'
+// digit counts into the LDS start of each (wave, digit), after the digit's
+// start in the tile (an exclusive scan of the tile's counts, which are the
+// differences of consecutive tile offsets in the scanned histogram).  The
+// finished tile is written out with consecutive threads on consecutive
+// addresses of each digit's run.
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kSortWaveRounds = kSortTile / kSortThreads;   // 64-key rounds per wave (= kSortRounds)
+
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* __restrict__ kin,
                                                                 const int32_t* __restrict__ vin,
                                                                 uint64_t* __restrict__ kout,
@@ -147,9 +162,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
     __shared__ uint64_t skey[kSortTile];
     __shared__ int32_t sval[kSortTile];
     __shared__ int32_t gbase[256];     // global position of the tile's first key of each digit
-    __shared__ int32_t lpos[256];      // next free LDS position of each digit
     __shared__ int32_t lstart[256];    // LDS start of each digit's run
-    __shared__ int32_t wcnt[kSortThreads / 64][256];
+    __shared__ int32_t wcnt[kSortWaves][256];   // keys of each digit per wave (running, then final)
+    __shared__ int32_t tsum[2][kSortWaves];
     int tile = blockIdx.x;
     int seg = tile_segment(S, tile);
     int lt = tile - S.tile0[seg];
@@ -159,6 +174,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
     int lane = threadIdx.x & 63;
     int wave = threadIdx.x >> 6;
     uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // the wave's keys and values, all loaded first (one memory round trip)
+    const int wbase = start + wave * 64 * kSortWaveRounds;
+    uint64_t kr[kSortWaveRounds];
+    int32_t vr[kSortWaveRounds];
+    #pragma unroll
+    for (int r = 0; r < kSortWaveRounds; ++r) {
+        const int i = wbase + r * 64 + lane;
+        kr[r] = i < end ? kin[i] : 0ull;
+        vr[r] = i < end ? vin[i] : 0;
+    }
     {
         const int d = threadIdx.x;
         const int32_t* hd = hist + S.hoff[seg] + d * ntiles;
@@ -173,55 +198,58 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
             int32_t u = __shfl_up(it, o), v = __shfl_up(ic, o);
             if (lane >= o) { it += u; ic += v; }
         }
-        if (lane == 63) { wcnt[0][wave] = it; wcnt[1][wave] = ic; }
+        if (lane == 63) { tsum[0][wave] = it; tsum[1][wave] = ic; }
+        #pragma unroll
+        for (int w2 = 0; w2 < kSortWaves; ++w2) wcnt[w2][d] = 0;
         __syncthreads();
         int32_t wt = 0, wc = 0;
-        for (int w2 = 0; w2 < wave; ++w2) { wt += wcnt[0][w2]; wc += wcnt[1][w2]; }
-        __syncthreads();
+        for (int w2 = 0; w2 < wave; ++w2) { wt += tsum[0][w2]; wc += tsum[1][w2]; }
         gbase[d] = S.off[seg] + wt + it - tot + mine;
         lstart[d] = wc + ic - cnt;
-        lpos[d] = wc + ic - cnt;
     }
-    // the tile's keys and values, all loaded before the first round (one
-    // memory round trip per tile instead of one per round)
-    uint64_t kr[kSortRounds];
-    int32_t vr[kSortRounds];
+    // ranks within the wave, in key order
+    int32_t rk[kSortWaveRounds];
+    int dg[kSortWaveRounds];
+    int32_t* cw = wcnt[wave];
     #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
-        const int i = start + r * kSortThreads + threadIdx.x;
-        kr[r] = i < end ? kin[i] : 0ull;
-        vr[r] = i < end ? vin[i] : 0;
-    }
-    #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
-        for (int q = threadIdx.x; q < (kSortThreads / 64) * 256; q += kSortThreads)
-            (&wcnt[0][0])[q] = 0;
-        __syncthreads();
-        int i = start + r * kSortThreads + threadIdx.x;
-        bool valid = i < end;
-        uint64_t k = kr[r];
-        int32_t v = vr[r];
-        int d = (int)((k >> shift) & 255);
+    for (int r = 0; r < kSortWaveRounds; ++r) {
+        const int i = wbase + r * 64 + lane;
+        const bool valid = i < end;
+        const int d = (int)((kr[r] >> shift) & 255);
         uint64_t peers = __ballot(valid);
         #pragma unroll
         for (int b = 0; b < 8; ++b) {
             uint64_t m = __ballot((d >> b) & 1);
             peers &= ((d >> b) & 1) ? m : ~m;
         }
-        int rank = __popcll(peers & lt_mask);
-        if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            int off = lpos[d] + rank;
-            for (int w2 = 0; w2 < wave; ++w2) off += wcnt[w2][d];
-            skey[off] = k;
-            sval[off] = v;
-        }
-        __syncthreads();
-        int tot = 0;
+        const int rank = __popcll(peers & lt_mask);
+        const int32_t before = valid ? cw[d] : 0;
+        wave_sync_lds();
+        if (valid && rank == 0) cw[d] = before + __popcll(peers);
+        wave_sync_lds();
+        rk[r] = before + rank;
+        dg[r] = valid ? d : -1;
+    }
+    __syncthreads();
+    // LDS start of (wave, digit): the digit's start plus the earlier waves' counts
+    {
+        const int d = threadIdx.x;
+        int32_t run = lstart[d];
         #pragma unroll
-        for (int w2 = 0; w2 < kSortThreads / 64; ++w2) tot += wcnt[w2][threadIdx.x];
-        lpos[threadIdx.x] += tot;
+        for (int w2 = 0; w2 < kSortWaves; ++w2) {
+            const int32_t c = wcnt[w2][d];
+            wcnt[w2][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    #pragma unroll
+    for (int r = 0; r < kSortWaveRounds; ++r) {
+        if (dg[r] >= 0) {
+            const int off = cw[dg[r]] + rk[r];
+            skey[off] = kr[r];
+            sval[off] = vr[r];
+        }
     }
     __syncthreads();
     const int n_tile = (end - start) < kSortTile ? (end - start) : kSortTile;
