@@ -291,20 +291,22 @@ def bench_pn(torch, nuht, workloads, dev, reps=3):
     return res
 
 
-def bench_disk(torch, nuht, workloads, dev, reps=5):
+def bench_disk(torch, nuht, workloads, dev, reps=5, method="transform"):
     """The Helmholtz solver on the unit disk (Sec. 5.3) at the paper's example
     kappa = 25, eps = 1e-8: m = 512 Gauss-Legendre radii, t = 256 angles,
     orders -100 .. 100, J = 128 radial modes per order, a random smooth
     forcing.  Solver planning once, then analysis, synthesis and the whole
     solve (analysis, division by the eigenvalues, synthesis), each timed over
-    `reps` calls.  A solve runs 8 (L + 1) transforms (real and imaginary
-    parts of orders +-l, both directions) of n + m = 512 + 128 each."""
+    `reps` calls.  With the transform method a solve runs 8 (L + 1) transforms
+    (real and imaginary parts of orders +-l, both directions) of
+    n + m = 512 + 128 each; the direct method takes the same sums term by
+    term, 2 (L + 1) m J Bessel evaluations per solve."""
     m, t, L, J, eps, kappa = 512, 256, 100, 128, 1e-8, 25.0
     r, wr, zeros, f = workloads.disk(m, t, L, J, seed=190)
     rd, wrd, zd, fd = (torch.as_tensor(a, device=dev) for a in (r, wr, zeros, f))
     torch.cuda.synchronize()
     a = time.perf_counter()
-    s = nuht.DiskSolver(rd, wrd, t, zd, eps)
+    s = nuht.DiskSolver(rd, wrd, t, zd, eps, method=method)
     torch.cuda.synchronize()
     plan_ms = 1e3 * (time.perf_counter() - a)
     alpha = s.analysis(fd)
@@ -326,9 +328,12 @@ def bench_disk(torch, nuht, workloads, dev, reps=5):
     he_ms = timed(lambda: s.helmholtz(kappa, fd))
     s.close()
     transforms = 8 * (L + 1)
-    res = dict(m=m, t=t, L=L, J=J, eps=eps, kappa=kappa, plan_ms=plan_ms, analysis_ms=an_ms, synthesis_ms=sy_ms,
-               solve_ms=he_ms, transforms_per_solve=transforms,
-               transform_rate=transforms * (m + J) / (he_ms * 1e-3))
+    res = dict(method=method, m=m, t=t, L=L, J=J, eps=eps, kappa=kappa, plan_ms=plan_ms, analysis_ms=an_ms,
+               synthesis_ms=sy_ms, solve_ms=he_ms)
+    if method == "transform":
+        res.update(transforms_per_solve=transforms, transform_rate=transforms * (m + J) / (he_ms * 1e-3))
+    else:
+        res.update(bessel_per_solve=2 * (L + 1) * m * J)
     log("disk solver:", json.dumps(res))
     return res
 
@@ -544,7 +549,8 @@ def main():
     batched = None if args.no_batched else bench_batched(torch, nuht, workloads, dev)
     fwd_bwd = None if args.no_grad else bench_fwd_bwd(torch, nuht, workloads, dev)
     pn = None if args.no_pn else bench_pn(torch, nuht, workloads, dev)
-    disk = None if args.no_disk else bench_disk(torch, nuht, workloads, dev)
+    disk = None if args.no_disk else {meth: bench_disk(torch, nuht, workloads, dev, method=meth)
+                                      for meth in ("transform", "direct")}
     split = None if args.no_split else bench_split(torch, nuht, *inputs[0])
 
     out = {

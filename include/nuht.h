@@ -287,7 +287,14 @@ int nuht_direct(int nu, double eps, int64_t n, const double *r_dev, const double
  * radial modes per order, zeros_dev holding (L + 1) x J values, row l being
  * j_{l,1} < ... < j_{l,J}, the first J positive zeros of J_l (the caller's;
  * the library does not compute them).  eps is the tolerance of every
- * transform.  The arrays are copied; planning synchronises `stream`.
+ * transform.  method selects how the radial sums are taken:
+ *   NUHT_FB_TRANSFORM (0): the transforms of this library, planned here for
+ *     orders 0 .. L in both directions; cost O((L + 1)(m + J) log) per solve;
+ *   NUHT_FB_DIRECT (1): the sums over m J terms per order, each J_l evaluated
+ *     in place to full FP64 accuracy (eps is then unused but still checked);
+ *     nothing is planned; cost O((L + 1) m J) Bessel evaluations per solve,
+ *     the faster choice while m J is small (a few 10^5).
+ * The arrays are copied; planning synchronises `stream`.
  *
  * nuht_fb_analysis -- the coefficients of eq. FB-coef with the grid's rules,
  * the angular integral taken as a mean (the eigenfunctions' squared norm being
@@ -308,8 +315,10 @@ int nuht_direct(int nu, double eps, int64_t n, const double *r_dev, const double
  * solver must not overlap.  nuht_fb_destroy synchronises and frees.
  */
 typedef struct nuht_fb_s *nuht_fb_t;
+#define NUHT_FB_TRANSFORM 0
+#define NUHT_FB_DIRECT 1
 int nuht_fb_plan(nuht_fb_t *fb, int32_t L, int64_t m, const double *r_dev, const double *wr_dev, int64_t t,
-                 int64_t J, const double *zeros_dev, double eps, void *stream);
+                 int64_t J, const double *zeros_dev, double eps, int32_t method, void *stream);
 int nuht_fb_analysis(nuht_fb_t fb, const double *f_dev, double *alpha_dev, void *stream);
 int nuht_fb_synthesis(nuht_fb_t fb, const double *beta_dev, double *u_dev, void *stream);
 int nuht_fb_helmholtz(nuht_fb_t fb, double kappa, const double *f_dev, double *alpha_dev, double *beta_dev,

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libnuht.so")
 NUHT_OK = 0
 NUHT_FP64 = 0
 NUHT_FP32_SPREAD = 1
+NUHT_FB_TRANSFORM = 0
+NUHT_FB_DIRECT = 1
 
 _ERRORS = {
     -1: "NUHT_EINVAL", -2: "NUHT_EDOMAIN", -3: "NUHT_EPRECISION", -4: "NUHT_ENOMEM",
@@ -95,7 +97,7 @@ def load_library():
     lib.nuht_profile.argtypes = [vp, ctypes.c_int]
     lib.nuht_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.nuht_fb_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int64, vp, vp, ctypes.c_int64,
-                                 ctypes.c_int64, vp, ctypes.c_double, vp]
+                                 ctypes.c_int64, vp, ctypes.c_double, ctypes.c_int32, vp]
     lib.nuht_fb_analysis.argtypes = [vp, vp, vp, vp]
     lib.nuht_fb_synthesis.argtypes = [vp, vp, vp, vp]
     lib.nuht_fb_helmholtz.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp, vp]
@@ -301,9 +303,15 @@ class DiskSolver:
     """Fourier-Bessel expansions and the Helmholtz solver on the unit disk
     (nuht_fb_*): m radii r with radial weights wr, t equispaced angles, orders
     -L .. L and J radial modes per order; zeros is an (L + 1) x J tensor of the
-    first J positive zeros of J_0 .. J_L."""
+    first J positive zeros of J_0 .. J_L.  method "transform" (the default)
+    takes the radial sums with this library's transforms, "direct" sums the
+    m J terms per order with J_l evaluated in place."""
 
-    def __init__(self, r, wr, t: int, zeros, eps: float):
+    METHODS = {"transform": NUHT_FB_TRANSFORM, "direct": NUHT_FB_DIRECT}
+
+    def __init__(self, r, wr, t: int, zeros, eps: float, method: str = "transform"):
+        if method not in self.METHODS:
+            raise ValueError(f"method must be one of {sorted(self.METHODS)}")
         lib = load_library()
         r = _dev_f64(r, "r")
         wr = _dev_f64(wr, "wr")
@@ -317,8 +325,9 @@ class DiskSolver:
         self.device = r.device
         h = ctypes.c_void_p()
         _check(lib.nuht_fb_plan(ctypes.byref(h), self.L, self.m, _ptr(r), _ptr(wr), self.t, self.J, _ptr(zeros),
-                                float(eps), _stream()))
+                                float(eps), self.METHODS[method], _stream()))
         self._h = h
+        self.method = method
 
     def _grid(self, f, name):
         if f.shape != (self.m, self.t) or f.device.type != "cuda" or f.dtype != torch.float64:

@@ -32,6 +32,7 @@
 
 #include "nuht.h"
 #include "nuht_device.h"
+#include "nuht_launch.h"
 
 namespace nuht {
 
@@ -141,6 +142,81 @@ __global__ __launch_bounds__(256) void k_fb_angular_inv(const double* __restrict
     for (int s = threadIdx.x; s < t; s += blockDim.x) uk[s] = sm[s].x;
 }
 
+// The direct method: the same radial sums with every J_l(j_{l,j} r_k)
+// evaluated in place (full FP64 accuracy), shared by the four weight vectors
+// of order l.  A workgroup of 16 waves owns 64 outputs of one order (one per
+// lane); its waves take every 16th term of the sum, and the 16 partial sums
+// are added in wave order.  Lanes past the end evaluate J at x = 0 and write
+// nothing.
+constexpr int kFbWaves = 16;
+
+// Analysis: G[(4 l + q) J + j] = sum_k C[(4 l + q) m + k] J_l(z_{l,j} r_k).
+__global__ __launch_bounds__(1024) void k_fb_direct_fwd(const double* __restrict__ C, const double* __restrict__ r,
+                                                        int64_t m, const double* __restrict__ zeros, int64_t J,
+                                                        const double* __restrict__ phi, double* __restrict__ G)
+{
+    __shared__ double red[kFbWaves][4][64];
+    const int l = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+    const double z = j < J ? zeros[(int64_t)l * J + j] : 0.0;
+    const double ph = phi[2 * l], pl = phi[2 * l + 1];
+    const double* c0 = C + 4 * (int64_t)l * m;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int64_t k = w; k < m; k += kFbWaves) {
+        const double rk = r[k];
+        const double x = z * rk;
+        const double v = besselj_core(l, ph, pl, x, __builtin_fma(z, rk, -x));
+        a0 = __builtin_fma(c0[k], v, a0);
+        a1 = __builtin_fma(c0[m + k], v, a1);
+        a2 = __builtin_fma(c0[2 * m + k], v, a2);
+        a3 = __builtin_fma(c0[3 * m + k], v, a3);
+    }
+    red[w][0][lane] = a0; red[w][1][lane] = a1; red[w][2][lane] = a2; red[w][3][lane] = a3;
+    __syncthreads();
+    if (threadIdx.x < 256) {
+        const int q = threadIdx.x >> 6;
+        double s = 0.0;
+        #pragma unroll
+        for (int v = 0; v < kFbWaves; ++v) s += red[v][q][lane];
+        if (j < J) G[(4 * (int64_t)l + q) * J + j] = s;
+    }
+}
+
+// Synthesis: U[(4 l + q) m + k] = sum_j B[(4 l + q) J + j] J_l(z_{l,j} r_k).
+__global__ __launch_bounds__(1024) void k_fb_direct_inv(const double* __restrict__ B, const double* __restrict__ r,
+                                                        int64_t m, const double* __restrict__ zeros, int64_t J,
+                                                        const double* __restrict__ phi, double* __restrict__ U)
+{
+    __shared__ double red[kFbWaves][4][64];
+    const int l = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t k = (int64_t)blockIdx.x * 64 + lane;
+    const double rk = k < m ? r[k] : 0.0;
+    const double ph = phi[2 * l], pl = phi[2 * l + 1];
+    const double* b0 = B + 4 * (int64_t)l * J;
+    const double* zl = zeros + (int64_t)l * J;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int64_t j = w; j < J; j += kFbWaves) {
+        const double z = zl[j];
+        const double x = z * rk;
+        const double v = besselj_core(l, ph, pl, x, __builtin_fma(z, rk, -x));
+        a0 = __builtin_fma(b0[j], v, a0);
+        a1 = __builtin_fma(b0[J + j], v, a1);
+        a2 = __builtin_fma(b0[2 * J + j], v, a2);
+        a3 = __builtin_fma(b0[3 * J + j], v, a3);
+    }
+    red[w][0][lane] = a0; red[w][1][lane] = a1; red[w][2][lane] = a2; red[w][3][lane] = a3;
+    __syncthreads();
+    if (threadIdx.x < 256) {
+        const int q = threadIdx.x >> 6;
+        double s = 0.0;
+        #pragma unroll
+        for (int v = 0; v < kFbWaves; ++v) s += red[v][q][lane];
+        if (k < m) U[(4 * (int64_t)l + q) * m + k] = s;
+    }
+}
+
 // 2 / J^2 in place.
 __global__ void k_fb_norm(double* __restrict__ v, int64_t n)
 {
@@ -169,7 +245,9 @@ struct nuht_fb_s {
     double* U = nullptr;        // 4 (L + 1) x m synthesis outputs
     double2* A = nullptr;       // (2L + 1) x J coefficients (Helmholtz temporaries)
     double2* Bc = nullptr;      // (2L + 1) x J
-    nuht_batch_t fwd = nullptr; // orders 0 .. L: r -> zeros_l
+    double* phi = nullptr;      // 2 (L + 1): phase offsets of orders 0 .. L (direct method)
+    int method = NUHT_FB_TRANSFORM;
+    nuht_batch_t fwd = nullptr; // orders 0 .. L: r -> zeros_l (transform method)
     nuht_batch_t inv = nullptr; // orders 0 .. L: zeros_l -> r
 };
 
@@ -181,7 +259,7 @@ void fb_free(nuht_fb_s* fb)
     if (fb->fwd) nuht_batch_destroy(fb->fwd);
     if (fb->inv) nuht_batch_destroy(fb->inv);
     for (void* p : {(void*)fb->r, (void*)fb->wr, (void*)fb->zeros, (void*)fb->nrm, (void*)fb->C, (void*)fb->G,
-                    (void*)fb->U, (void*)fb->A, (void*)fb->Bc})
+                    (void*)fb->U, (void*)fb->A, (void*)fb->Bc, (void*)fb->phi})
         if (p) (void)hipFree(p);
     delete fb;
 }
@@ -219,8 +297,14 @@ int fb_analysis(nuht_fb_s* fb, const double* f, double2* alpha, hipStream_t s)
     hipLaunchKernelGGL(k_fb_angular_fwd, dim3((unsigned)fb->m), dim3(256), sizeof(double2) * fb->t, s, f, fb->m,
                        fb->logt, fb->L, fb->r, fb->wr, fb->C);
     if (hipGetLastError() != hipSuccess) return NUHT_EHIP;
-    int rc = fb_run(fb->fwd, fb->L, fb->C, fb->m, fb->G, fb->J, s);
-    if (rc != NUHT_OK) return rc;
+    if (fb->method == NUHT_FB_DIRECT) {
+        hipLaunchKernelGGL(k_fb_direct_fwd, dim3((unsigned)((fb->J + 63) / 64), (unsigned)(fb->L + 1)),
+                           dim3(64 * kFbWaves), 0, s, fb->C, fb->r, fb->m, fb->zeros, fb->J, fb->phi, fb->G);
+        if (hipGetLastError() != hipSuccess) return NUHT_EHIP;
+    } else {
+        int rc = fb_run(fb->fwd, fb->L, fb->C, fb->m, fb->G, fb->J, s);
+        if (rc != NUHT_OK) return rc;
+    }
     const int64_t total = (int64_t)(2 * fb->L + 1) * fb->J;
     hipLaunchKernelGGL(k_fb_scale, dim3(blocks_for(total)), dim3(256), 0, s, fb->G, fb->nrm, fb->L, fb->J, alpha);
     return hipGetLastError() == hipSuccess ? NUHT_OK : NUHT_EHIP;
@@ -231,8 +315,14 @@ int fb_synthesis(nuht_fb_s* fb, const double2* beta, double* u, hipStream_t s)
     const int64_t total = (int64_t)(2 * fb->L + 1) * fb->J;
     hipLaunchKernelGGL(k_fb_split, dim3(blocks_for(total)), dim3(256), 0, s, beta, fb->L, fb->J, fb->G);
     if (hipGetLastError() != hipSuccess) return NUHT_EHIP;
-    int rc = fb_run(fb->inv, fb->L, fb->G, fb->J, fb->U, fb->m, s);
-    if (rc != NUHT_OK) return rc;
+    if (fb->method == NUHT_FB_DIRECT) {
+        hipLaunchKernelGGL(k_fb_direct_inv, dim3((unsigned)((fb->m + 63) / 64), (unsigned)(fb->L + 1)),
+                           dim3(64 * kFbWaves), 0, s, fb->G, fb->r, fb->m, fb->zeros, fb->J, fb->phi, fb->U);
+        if (hipGetLastError() != hipSuccess) return NUHT_EHIP;
+    } else {
+        int rc = fb_run(fb->inv, fb->L, fb->G, fb->J, fb->U, fb->m, s);
+        if (rc != NUHT_OK) return rc;
+    }
     hipLaunchKernelGGL(k_fb_angular_inv, dim3((unsigned)fb->m), dim3(256), sizeof(double2) * fb->t, s, fb->U,
                        fb->m, fb->logt, fb->L, u);
     return hipGetLastError() == hipSuccess ? NUHT_OK : NUHT_EHIP;
@@ -243,7 +333,7 @@ int fb_synthesis(nuht_fb_s* fb, const double2* beta, double* u, hipStream_t s)
 extern "C" {
 
 int nuht_fb_plan(nuht_fb_t* out, int32_t L, int64_t m, const double* r_dev, const double* wr_dev, int64_t t,
-                 int64_t J, const double* zeros_dev, double eps, void* stream)
+                 int64_t J, const double* zeros_dev, double eps, int32_t method, void* stream)
 {
     if (!out) return NUHT_EINVAL;
     *out = nullptr;
@@ -251,15 +341,16 @@ int nuht_fb_plan(nuht_fb_t* out, int32_t L, int64_t m, const double* r_dev, cons
     if (t < 2 || t > 4096 || (t & (t - 1)) != 0 || 2 * (int64_t)L + 1 > t) return NUHT_EINVAL;
     if (!r_dev || !wr_dev || !zeros_dev) return NUHT_EINVAL;
     if (!(eps >= 1e-15 && eps <= 1e-2)) return NUHT_EINVAL;
+    if (method != NUHT_FB_TRANSFORM && method != NUHT_FB_DIRECT) return NUHT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     nuht_fb_s* fb = new (std::nothrow) nuht_fb_s;
     if (!fb) return NUHT_ENOMEM;
-    fb->L = L; fb->m = m; fb->t = t; fb->J = J;
+    fb->L = L; fb->m = m; fb->t = t; fb->J = J; fb->method = method;
     while ((int64_t(1) << fb->logt) < t) ++fb->logt;
     const int64_t nl = L + 1, no = 2 * (int64_t)L + 1;
     if (!fb_alloc(fb->r, m) || !fb_alloc(fb->wr, m) || !fb_alloc(fb->zeros, nl * J) || !fb_alloc(fb->nrm, nl * J) ||
         !fb_alloc(fb->C, 4 * nl * m) || !fb_alloc(fb->G, 4 * nl * J) || !fb_alloc(fb->U, 4 * nl * m) ||
-        !fb_alloc(fb->A, no * J) || !fb_alloc(fb->Bc, no * J)) {
+        !fb_alloc(fb->A, no * J) || !fb_alloc(fb->Bc, no * J) || !fb_alloc(fb->phi, 2 * nl)) {
         fb_free(fb);
         return NUHT_ENOMEM;
     }
@@ -273,16 +364,23 @@ int nuht_fb_plan(nuht_fb_t* out, int32_t L, int64_t m, const double* r_dev, cons
     std::vector<int> nu(nl);
     std::vector<int64_t> nn(nl), nm(nl);
     std::vector<const double*> pr(nl), pz(nl);
+    std::vector<double> ph(2 * nl);
     for (int l = 0; l <= L; ++l) {
         nu[l] = l;
         nn[l] = m;
         nm[l] = J;
         pr[l] = fb->r;
         pz[l] = fb->zeros + (int64_t)l * J;
+        phase_offset_dd(l, &ph[2 * l], &ph[2 * l + 1]);
     }
-    int rc = nuht_plan_many(&fb->fwd, (int)nl, nu.data(), eps, nn.data(), pr.data(), nm.data(), pz.data(), nullptr,
+    int rc = NUHT_OK;
+    if (hipMemcpyAsync(fb->phi, ph.data(), sizeof(double) * 2 * nl, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        rc = NUHT_EHIP;
+    if (rc == NUHT_OK && method == NUHT_FB_TRANSFORM)
+        rc = nuht_plan_many(&fb->fwd, (int)nl, nu.data(), eps, nn.data(), pr.data(), nm.data(), pz.data(), nullptr,
                             stream);
-    if (rc == NUHT_OK)
+    if (rc == NUHT_OK && method == NUHT_FB_TRANSFORM)
         rc = nuht_plan_many(&fb->inv, (int)nl, nu.data(), eps, nm.data(), pz.data(), nn.data(), pr.data(), nullptr,
                             stream);
     // normalisation: J_{|l|-1} (J_1 for l = 0) at the zeros, by the direct sum

@@ -339,6 +339,8 @@ static void phase_offset(int nu, double& hi, double& lo)
     lo = k * q_lo;
 }
 
+void phase_offset_dd(int nu, double* hi, double* lo) { phase_offset(nu, *hi, *lo); }
+
 // ===========================================================================
 // Plan.
 // ===========================================================================

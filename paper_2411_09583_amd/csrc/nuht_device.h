@@ -217,15 +217,16 @@ __device__ __forceinline__ void miller_step(double kd, double rec, double& yk, d
     }
 }
 
-// J_nu(x) to full FP64 accuracy: Hankel's expansion summed until its terms
+// J_nu(x) (nu >= 0, phase offset -(2 nu + 1) pi / 4 as phi_hi + phi_lo) to
+// full FP64 accuracy: Hankel's expansion summed until its terms
 // fall below 1e-17 where it converges that far (x >= 25, terms never above
 // 1e3), Miller's recurrence otherwise.  Used for the direct blocks.
-__device__ inline double besselj_full(const PlanDev& P, double xh, double xl)
+__device__ inline double besselj_core(int nu, double phi_hi, double phi_lo, double xh, double xl)
 {
     if (xh >= 25.0) {
         // terms t_k = prod_{i<=k} (mu - (2i-1)^2) / (8 x i); odd k go to Q, even
         // k to P, with sign (-1)^floor(k/2): one odd and one even term per step
-        const double mu = 4.0 * (double)P.nu * (double)P.nu;
+        const double mu = 4.0 * (double)nu * (double)nu;
         const double inv8x = 0.125 / xh;
         double t = 1.0, p = 1.0, q = 0.0, prev = 1e300;
         bool ok = false;
@@ -245,14 +246,13 @@ __device__ inline double besselj_full(const PlanDev& P, double xh, double xl)
             t = t2;
         }
         if (ok) {
-            dd ph = two_sum(xh, P.phi_hi);
+            dd ph = two_sum(xh, phi_hi);
             double c, s;
-            cis_dd(ph.hi, ph.lo + xl + P.phi_lo, c, s);
+            cis_dd(ph.hi, ph.lo + xl + phi_lo, c, s);
             return sqrt(2.0 / (kPi * xh)) * __builtin_fma(p, c, -q * s);
         }
     }
-    if (xh < 1e-30) return P.nu == 0 ? 1.0 : 0.0;
-    const int nu = P.nu;
+    if (xh < 1e-30) return nu == 0 ? 1.0 : 0.0;
     const double top = (double)(nu + 1) > xh ? (double)(nu + 1) : xh;
     const int N = (int)(top + 12.0 + 8.0 * cbrt(xh > 1.0 ? xh : 1.0));   // >= nu + 13
     const double rec = 2.0 / xh;
@@ -274,6 +274,12 @@ __device__ inline double besselj_full(const PlanDev& P, double xh, double xl)
     S = __builtin_fma(yk, yk, S);                                // k = 0 counts once
     const double d = nu == 0 ? -jp : 0.5 * (jm - jp);
     return __builtin_fma(xl, d, j0) / sqrt(S);
+}
+
+// The same for the plan's order and phase offset.
+__device__ __forceinline__ double besselj_full(const PlanDev& P, double xh, double xl)
+{
+    return besselj_core(P.nu, P.phi_hi, P.phi_lo, xh, xl);
 }
 
 // ---------------------------------------------------------------------------

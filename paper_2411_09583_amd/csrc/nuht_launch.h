@@ -81,6 +81,8 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
                           const IoArgs& io, hipStream_t s, hipEvent_t* marks);
 // x[i] = v
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
+// -(2 nu + 1) pi / 4 modulo 2 pi as a double-double (the Hankel phase offset).
+void phase_offset_dd(int nu, double* hi, double* lo);
 // table[i] = ptrs[i] for i < count (count <= 224): fills a device pointer table
 // from kernel arguments
 hipError_t launch_set_pointers(void** table, const void* const* ptrs, int count, hipStream_t s);

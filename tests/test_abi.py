@@ -98,17 +98,19 @@ def test_disk_solver_rejects_invalid_arguments_without_gpu(lib):
     h = ctypes.c_void_p()
     p = ctypes.c_void_p(8)              # a non-null stand-in, never dereferenced
     fbp = lib.nuht_fb_plan
-    assert fbp(None, 2, 8, p, p, 8, 4, p, 1e-10, None) == -1                       # no handle
-    assert fbp(ctypes.byref(h), -1, 8, p, p, 8, 4, p, 1e-10, None) == -1           # L < 0
-    assert fbp(ctypes.byref(h), 101, 8, p, p, 256, 4, p, 1e-10, None) == -1        # L > 100
-    assert fbp(ctypes.byref(h), 2, 0, p, p, 8, 4, p, 1e-10, None) == -1            # m = 0
-    assert fbp(ctypes.byref(h), 2, 8, p, p, 12, 4, p, 1e-10, None) == -1           # t not a power of two
-    assert fbp(ctypes.byref(h), 2, 8, p, p, 8192, 4, p, 1e-10, None) == -1         # t > 4096
-    assert fbp(ctypes.byref(h), 4, 8, p, p, 8, 4, p, 1e-10, None) == -1            # 2L + 1 > t
-    assert fbp(ctypes.byref(h), 2, 8, p, p, 8, 0, p, 1e-10, None) == -1            # J = 0
-    assert fbp(ctypes.byref(h), 2, 8, None, p, 8, 4, p, 1e-10, None) == -1         # null radii
-    assert fbp(ctypes.byref(h), 2, 8, p, p, 8, 4, None, 1e-10, None) == -1         # null zeros
-    assert fbp(ctypes.byref(h), 2, 8, p, p, 8, 4, p, 1e-16, None) == -1            # eps out of range
+    assert fbp(None, 2, 8, p, p, 8, 4, p, 1e-10, 0, None) == -1                       # no handle
+    assert fbp(ctypes.byref(h), -1, 8, p, p, 8, 4, p, 1e-10, 0, None) == -1           # L < 0
+    assert fbp(ctypes.byref(h), 101, 8, p, p, 256, 4, p, 1e-10, 0, None) == -1        # L > 100
+    assert fbp(ctypes.byref(h), 2, 0, p, p, 8, 4, p, 1e-10, 0, None) == -1            # m = 0
+    assert fbp(ctypes.byref(h), 2, 8, p, p, 12, 4, p, 1e-10, 0, None) == -1           # t not a power of two
+    assert fbp(ctypes.byref(h), 2, 8, p, p, 8192, 4, p, 1e-10, 0, None) == -1         # t > 4096
+    assert fbp(ctypes.byref(h), 4, 8, p, p, 8, 4, p, 1e-10, 0, None) == -1            # 2L + 1 > t
+    assert fbp(ctypes.byref(h), 2, 8, p, p, 8, 0, p, 1e-10, 0, None) == -1            # J = 0
+    assert fbp(ctypes.byref(h), 2, 8, None, p, 8, 4, p, 1e-10, 0, None) == -1         # null radii
+    assert fbp(ctypes.byref(h), 2, 8, p, p, 8, 4, None, 1e-10, 0, None) == -1         # null zeros
+    assert fbp(ctypes.byref(h), 2, 8, p, p, 8, 4, p, 1e-16, 0, None) == -1            # eps out of range
+    assert fbp(ctypes.byref(h), 2, 8, p, p, 8, 4, p, 1e-10, 2, None) == -1            # unknown method
+    assert fbp(ctypes.byref(h), 2, 8, p, p, 8, 4, p, 1e-10, -1, None) == -1
     assert h.value is None
     assert lib.nuht_fb_analysis(None, p, p, None) == -1
     assert lib.nuht_fb_synthesis(None, p, p, None) == -1

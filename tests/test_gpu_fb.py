@@ -1,4 +1,6 @@
-"""The disk solver (Sec. 5.3) on the GPU against the oracle and closed forms.
+"""The disk solver (Sec. 5.3) on the GPU against the oracle and closed forms,
+for both ways of taking the radial sums (the library's transforms, and the
+direct sums with J_l evaluated in place):
 
 * analysis of a random smooth forcing (m = 64 Gauss-Legendre radii, t = 64
   angles, L = 20, J = 24) against the oracle's direct sums: every alpha_jl
@@ -14,7 +16,8 @@
   oracle's solve of a random forcing;
 * the largest orders (L = 100, t = 256, m = 256, J = 128, eps = 1e-8) on
   sampled orders against the oracle;
-* edge cases: L = 0 with t = 2, J = 1, and t = 4096.
+* edge cases: L = 0 with t = 2, J = 1, t = 4096, and m, J not multiples of
+  the direct kernels' 64-wide tiles (ragged tails).
 """
 import numpy as np
 import pytest
@@ -65,11 +68,15 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+METHODS = ["transform", "direct"]
+
+
+@pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("eps", [1e-12, 1e-8])
-def test_analysis_against_oracle(nuht, eps):
+def test_analysis_against_oracle(nuht, eps, method):
     m, t, L, J = 64, 64, 20, 24
     r, wr, zeros, f = workloads.disk(m, t, L, J, seed=11)
-    s = nuht.DiskSolver(dev(r), dev(wr), t, dev(zeros), eps)
+    s = nuht.DiskSolver(dev(r), dev(wr), t, dev(zeros), eps, method=method)
     a = host(s.analysis(dev(f)))
     s.close()
     a1 = fb.analysis(L, r, wr, f, zeros)
@@ -79,13 +86,14 @@ def test_analysis_against_oracle(nuht, eps):
     assert np.all(err <= alpha_bar(L, r, wr, f, zeros, eps))
 
 
-def test_synthesis_against_oracle(nuht):
+@pytest.mark.parametrize("method", METHODS)
+def test_synthesis_against_oracle(nuht, method):
     m, t, L, J, eps = 64, 64, 20, 24, 1e-12
     r, wr, zeros, _ = workloads.disk(m, t, L, J, seed=12)
     rng = np.random.default_rng(13)
     decay = np.exp(-0.1 * np.abs(np.arange(-L, L + 1)))[:, None] * np.exp(-0.1 * np.arange(J))[None, :]
     beta = (rng.standard_normal((2 * L + 1, J)) + 1j * rng.standard_normal((2 * L + 1, J))) * decay
-    s = nuht.DiskSolver(dev(r), dev(wr), t, dev(zeros), eps)
+    s = nuht.DiskSolver(dev(r), dev(wr), t, dev(zeros), eps, method=method)
     u = host(s.synthesis(dev(beta)))
     s.close()
     u1 = fb.synthesis(L, r, t, beta, zeros)
@@ -115,10 +123,11 @@ def planted(m, t, L, J, seed):
     return r, wr, zeros, beta, u, f
 
 
-def test_helmholtz_planted_modes(nuht):
+@pytest.mark.parametrize("method", METHODS)
+def test_helmholtz_planted_modes(nuht, method):
     m, t, L, J, eps = 64, 32, 10, 16, 1e-12
     r, wr, zeros, beta, u, f = planted(m, t, L, J, seed=14)
-    s = nuht.DiskSolver(dev(r), dev(wr), t, dev(zeros), eps)
+    s = nuht.DiskSolver(dev(r), dev(wr), t, dev(zeros), eps, method=method)
     ug, ag, bg = s.helmholtz(KAPPA, dev(f), return_coefficients=True)
     ug, bg = host(ug), host(bg)
     s.close()
@@ -127,10 +136,11 @@ def test_helmholtz_planted_modes(nuht):
     assert np.abs(ug - u).max() <= 1e-9 * np.abs(u).max()
 
 
-def test_helmholtz_against_oracle(nuht):
+@pytest.mark.parametrize("method", METHODS)
+def test_helmholtz_against_oracle(nuht, method):
     m, t, L, J, eps = 48, 32, 12, 20, 1e-12
     r, wr, zeros, f = workloads.disk(m, t, L, J, seed=15)
-    s = nuht.DiskSolver(dev(r), dev(wr), t, dev(zeros), eps)
+    s = nuht.DiskSolver(dev(r), dev(wr), t, dev(zeros), eps, method=method)
     ug, ag, bg = s.helmholtz(KAPPA, dev(f), return_coefficients=True)
     ug, ag, bg = host(ug), host(ag), host(bg)
     s.close()
@@ -141,10 +151,11 @@ def test_helmholtz_against_oracle(nuht):
     assert rel_l2(ug, u1) <= 1e-11
 
 
-def test_largest_orders_sampled(nuht):
+@pytest.mark.parametrize("method", METHODS)
+def test_largest_orders_sampled(nuht, method):
     m, t, L, J, eps = 256, 256, 100, 128, 1e-8
     r, wr, zeros, f = workloads.disk(m, t, L, J, seed=16)
-    s = nuht.DiskSolver(dev(r), dev(wr), t, dev(zeros), eps)
+    s = nuht.DiskSolver(dev(r), dev(wr), t, dev(zeros), eps, method=method)
     a = host(s.analysis(dev(f)))
     s.close()
     theta = 2.0 * np.pi * np.arange(t) / t
@@ -161,11 +172,12 @@ def test_largest_orders_sampled(nuht):
         assert np.all(err <= bar)
 
 
-@pytest.mark.parametrize("m,t,L,J", [(16, 2, 0, 1), (24, 4, 1, 3), (32, 4096, 30, 8)])
-def test_edge_sizes(nuht, m, t, L, J):
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("m,t,L,J", [(16, 2, 0, 1), (24, 4, 1, 3), (32, 4096, 30, 8), (100, 128, 40, 70)])
+def test_edge_sizes(nuht, m, t, L, J, method):
     eps = 1e-12
     r, wr, zeros, f = workloads.disk(m, t, L, J, seed=17)
-    s = nuht.DiskSolver(dev(r), dev(wr), t, dev(zeros), eps)
+    s = nuht.DiskSolver(dev(r), dev(wr), t, dev(zeros), eps, method=method)
     a = host(s.analysis(dev(f)))
     u = host(s.helmholtz(3.0, dev(f)))
     s.close()
