@@ -14,8 +14,8 @@ direct sums with J_l evaluated in place):
 * the Helmholtz solve (kappa = 25, the paper's example) of the planted-mode
   forcing returns the planted field and coefficients, and agrees with the
   oracle's solve of a random forcing;
-* the largest orders (L = 100, t = 256, m = 256, J = 128, eps = 1e-8) on
-  sampled orders against the oracle;
+* the largest orders (L = 100, t = 256, m = 256 and the benchmarked m = 512,
+  J = 128, eps = 1e-8) on sampled orders against the oracle;
 * edge cases: L = 0 with t = 2, J = 1, t = 4096, and m, J not multiples of
   the direct kernels' 64-wide tiles (ragged tails).
 """
@@ -152,9 +152,10 @@ def test_helmholtz_against_oracle(nuht, method):
 
 
 @pytest.mark.parametrize("method", METHODS)
-def test_largest_orders_sampled(nuht, method):
-    m, t, L, J, eps = 256, 256, 100, 128, 1e-8
-    r, wr, zeros, f = workloads.disk(m, t, L, J, seed=16)
+@pytest.mark.parametrize("m,seed", [(256, 16), (512, 190)])   # the second is the benchmarked solve
+def test_largest_orders_sampled(nuht, method, m, seed):
+    t, L, J, eps = 256, 100, 128, 1e-8
+    r, wr, zeros, f = workloads.disk(m, t, L, J, seed=seed)
     s = nuht.DiskSolver(dev(r), dev(wr), t, dev(zeros), eps, method=method)
     a = host(s.analysis(dev(f)))
     s.close()
