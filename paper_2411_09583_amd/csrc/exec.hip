@@ -238,6 +238,9 @@ __device__ __forceinline__ PointEval eval_point(const ABlock& B, double r, doubl
     return e;
 }
 
+__device__ __forceinline__ double typed_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float typed_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 template <int NCH, typename T>
 __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restrict__ cs,
                                                 const double* __restrict__ es_poly, double2* __restrict__ part_raw)
@@ -315,14 +318,15 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
                 for (int i = first + sl; i < last; i += slices) {
                     const SpreadPoint<T> rec = s_pt[i];
                     T phi = s_k[i * w + (l - rec.l0)];
-                    T vr = phi * rec.wr, vi = phi * rec.wi;
-                    T q = rec.q;
+                    const T vr = phi * rec.wr, vi = phi * rec.wi;
+                    const T q = rec.q;
+                    // one chain of powers q^p serves both parts
+                    T qp = T(1);
                     #pragma unroll
                     for (int p = 0; p < NCH; ++p) {
-                        ar[p] += vr;
-                        ai[p] += vi;
-                        vr *= q;
-                        vi *= q;
+                        ar[p] = typed_fma(vr, qp, ar[p]);
+                        ai[p] = typed_fma(vi, qp, ai[p]);
+                        qp *= q;
                     }
                 }
             }
