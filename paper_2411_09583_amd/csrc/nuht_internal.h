@@ -15,7 +15,7 @@ constexpr int kMaxFftLog2 = 24;        // largest FFT of an asymptotic block: 2^
 constexpr int kLocalChunk = 4096;      // columns per local-moment work item
 constexpr int kSpreadChunk = 1024;     // default points per spreading work item (a plan option)
 constexpr int kMaxEsWidth = 18;        // largest ES kernel width
-constexpr int kEsDeg = 15;             // degree of the per-cell polynomial pieces of the ES kernel
+constexpr int kEsDeg = 13;             // degree of the per-cell polynomial pieces of the ES kernel
 constexpr int kSpreadAnchors = 6;      // first cells (anchors) one matrix-core spreading item may hold
 constexpr int kMaxLevels = 4096;       // subdivision depth limit
 
