@@ -381,7 +381,9 @@ struct SpreadMfma {
     static constexpr int NC = 16 * NCT;            // real columns of the tiles (re, im of 8 NCT channels)
     static constexpr int VS = 2 * NCH + 1;         // LDS stride of a point's 2 NCH columns (odd: conflict-free writes)
     static constexpr int GC = kSpreadAnchors + 15; // cells an item's anchor tiles reach
-    static constexpr int WPTS = 64;                // points per step
+    // points per step: 64, or 32 with two column tiles, so that the wider
+    // point records still let three workgroups share a compute unit's LDS
+    static constexpr int WPTS = NCT > 1 ? 32 : 64;
     // a point: its columns, its s and its anchor
     static constexpr size_t point_bytes = (VS + 1) * sizeof(double) + sizeof(int32_t);
     static constexpr size_t fold_bytes = (size_t)GC * NC * sizeof(double);   // the wave's cell sums
