@@ -63,6 +63,26 @@ def read_traffic(kernel):
                 source=os.path.relpath(path, ROOT))
 
 
+def read_step_traffic():
+    """HBM bytes of one whole step (every kernel of the three plans and
+    executions) from FETCH_SIZE and WRITE_SIZE counters scaled by a plain copy
+    of known size, read from the committed counter summary if it was taken
+    on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "step_traffic_large_uniform.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith((" ", "#")):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("sources_sha256") != sources_sha256():
+        return None
+    return dict(bytes_per_step=float(rec["bytes_per_step"]), fetch_bytes_per_step=float(rec["fetch_bytes_per_step"]),
+                write_bytes_per_step=float(rec["write_bytes_per_step"]), source=os.path.relpath(path, ROOT))
+
+
 def sources_sha256():
     """Digest of the HIP sources and headers the kernels are built from."""
     import hashlib
@@ -86,32 +106,71 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": x.numel() * 8, "copies": 3}), flush=True)
 
 
-def bench_loose(torch, nuht, inputs, steps=3):
+def make_step(torch, nuht, inputs, side, eps, **opts):
+    """One step: the three transforms, each planned on the side stream (so its
+    sort and subdivision overlap the previous transform's execution) and
+    executed on the current stream.  keep: a list collecting (nu, plan) with
+    stage profiling on, or None (plans closed after their execution)."""
+    def step(keep=None):
+        outs = {}
+        for nu in ORDERS:
+            r, w, c = inputs[nu]
+            with torch.cuda.stream(side):
+                p = nuht.Plan(r, w, nu, eps, **opts)
+            if keep is not None:
+                p.profile(True)
+            outs[nu] = p.execute(c)
+            if keep is not None:
+                keep.append((nu, p))
+            else:
+                p.close()
+        return outs
+    return step
+
+
+def bench_loose(torch, nuht, inputs, side, steps=5, warmup=2):
     """The same three transforms at eps = 1e-6, in FP64 and with FP32
-    spreading: plan + execute throughput, (n+m)/s."""
+    spreading, timed like the headline (plans on the side stream overlapping
+    the executions): plan + execute throughput, (n+m)/s."""
     res = {}
     for mode, prec in (("fp64", nuht.NUHT_FP64), ("fp32_spread", nuht.NUHT_FP32_SPREAD)):
-        def step():
-            outs = {}
-            for nu in ORDERS:
-                r, w, c = inputs[nu]
-                p = nuht.Plan(r, w, nu, 1e-6, precision=prec)
-                outs[nu] = p.execute(c)
-                p.close()
-            return outs
-        step()
+        step = make_step(torch, nuht, inputs, side, 1e-6, precision=prec)
+        for _ in range(warmup):
+            step()
         torch.cuda.synchronize()
         a = time.perf_counter()
         for _ in range(steps):
             outs = step()
         torch.cuda.synchronize()
         t = (time.perf_counter() - a) / steps
-        res[mode] = dict(ms_per_step=1e3 * t, value=len(ORDERS) * (N + M_OUT) / t, _g0=outs[0])
-    log("eps 1e-6:", {k: {kk: vv for kk, vv in v.items() if kk != "_g0"} for k, v in res.items()})
+        res[mode] = dict(ms_per_step=1e3 * t, value=len(ORDERS) * (N + M_OUT) / t, _outs=outs)
+    log("eps 1e-6:", {k: {kk: vv for kk, vv in v.items() if kk != "_outs"} for k, v in res.items()})
     return res
 
 
-def bench_batched(torch, nuht, workloads, dev):
+def sampled_error(g_dev, ref, idx):
+    """Relative l2 and normwise max error of the GPU output at the sampled
+    outputs idx against the oracle's values ref there."""
+    g = g_dev.cpu().numpy()[idx]
+    return dict(rel_l2=float(np.linalg.norm(g - ref) / np.linalg.norm(ref)),
+                rel_max=float(np.max(np.abs(g - ref)) / np.max(np.abs(ref))))
+
+
+def host_cpu():
+    """The host's CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(model=model, logical_cpus=os.cpu_count(), usable_cpus=len(os.sched_getaffinity(0)))
+
+
+def bench_batched(torch, nuht, workloads, dev, oracle=None):
     """256 independent transforms (nu ~ U{0..63}, n and m log-uniform in
     [1e3, 1e6], omega ~ U[0, n_i), eps = 1e-12): a loop of plan + execute per
     transform on one stream against one nuht_plan_many and graph replays of
@@ -165,6 +224,17 @@ def bench_batched(torch, nuht, workloads, dev):
     t_exec = (time.perf_counter() - a) / reps
     same = all(torch.equal(x, y) for x, y in zip(gs, outs_loop))
     b.close()
+    acc = None
+    if oracle is not None:
+        rng = np.random.default_rng(8)
+        worst = dict(rel_l2=0.0, rel_max=0.0)
+        a = time.perf_counter()
+        for t, g in zip(tr, gs):
+            i = rng.choice(t["w"].size, min(16, t["w"].size), replace=False)
+            e = sampled_error(g, oracle.dht(t["nu"], t["r"], t["c"], t["w"][i]), i)
+            worst = {k: max(worst[k], e[k]) for k in worst}
+        acc = dict(sampled_outputs_per_transform=16, worst_rel_l2=worst["rel_l2"], worst_rel_max=worst["rel_max"],
+                   oracle_s=time.perf_counter() - a)
     res = dict(transforms=len(tr), sum_n_plus_m=total,
                looped_ms=1e3 * t_loop, looped_execute_ms=1e3 * t_loop_exec,
                batched_plan_ms=1e3 * t_plan, batched_execute_ms=1e3 * t_exec,
@@ -172,7 +242,7 @@ def bench_batched(torch, nuht, workloads, dev):
                speedup_plan_and_execute=t_loop / (t_plan + t_exec),
                speedup_execute=t_loop_exec / t_exec,
                batched_rate=total / (t_plan + t_exec), batched_execute_rate=total / t_exec,
-               identical_to_looped=bool(same))
+               identical_to_looped=bool(same), accuracy=acc)
     log("batched:", json.dumps(res))
     return res
 
@@ -338,6 +408,42 @@ def bench_disk(torch, nuht, workloads, dev, reps=5, method="transform"):
     return res
 
 
+def bench_radial(torch, nuht, workloads, dev, oracle=None, reps=5):
+    """The radial 2-D Fourier-transform workload at its full size (n = m = 1e6
+    Chebyshev-clustered points, c = r w exp(-40 r^2) cos(30 r), log-spaced
+    frequencies on [1e-2, 1e5], nu = 0, eps = 1e-12), the stand-in for the
+    study of Sec. 5.2 and the most direct-heavy configuration: plan and
+    execute times and (n+m)/s, and the error on 256 sampled outputs."""
+    r_np, w_np, c_np = workloads.radial_2d()
+    r, w, c = (torch.as_tensor(a, device=dev) for a in (r_np, w_np, c_np))
+    p = nuht.Plan(r, w, 0, EPS)
+    g = p.execute(c)
+    inf = p.info()
+    p.close()
+    torch.cuda.synchronize()
+    t_plan = t_exec = 0.0
+    for _ in range(reps):
+        a = time.perf_counter()
+        p = nuht.Plan(r, w, 0, EPS)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        g = p.execute(c)
+        torch.cuda.synchronize()
+        e = time.perf_counter()
+        p.close()
+        t_plan += (b - a) / reps
+        t_exec += (e - b) / reps
+    n = r.numel() + w.numel()
+    res = dict(n=r.numel(), m=w.numel(), nu=0, eps=EPS, plan_ms=1e3 * t_plan, execute_ms=1e3 * t_exec,
+               value=n / (t_plan + t_exec), execute_rate=n / t_exec, levels=inf["levels"],
+               blocks=[inf["n_local"], inf["n_asy"], inf["n_direct"]], direct_entries=inf["direct_entries"])
+    if oracle is not None:
+        idx = np.random.default_rng(9).choice(w_np.size, 256, replace=False)
+        res["accuracy"] = dict(sampled_outputs=256, **sampled_error(g, oracle.dht(0, r_np, c_np, w_np[idx]), idx))
+    log("radial 2-D:", json.dumps(res))
+    return res
+
+
 def bench_split(torch, nuht, r, w, c, reps=5):
     """Exact against quasi-optimal SplitIndices (Sec. 4.1) at the large uniform
     workload, nu = 0, eps = 1e-12: plan and execute times and the partition's
@@ -379,8 +485,11 @@ def main():
     ap.add_argument("--no-loose", action="store_true", help="skip the eps = 1e-6 (FP64 and FP32 spreading) runs")
     ap.add_argument("--no-disk", action="store_true", help="skip the disk Helmholtz solver leg")
     ap.add_argument("--no-split", action="store_true", help="skip the exact-split comparison")
+    ap.add_argument("--no-radial", action="store_true", help="skip the radial 2-D workload at n = m = 1e6")
     ap.add_argument("--no-pn", action="store_true",
                     help="skip the p = O(n) study (Fourier-Bessel and exponential points at n = m = 1e6)")
+    ap.add_argument("--steps-only", action="store_true",
+                    help="only the warmup and timed headline steps (for hardware-counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 64 MiB device-to-device copy three times (a known byte count "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -410,21 +519,7 @@ def main():
     # sort and subdivision overlap the previous transform's execution on the
     # main stream; the plan is complete when Plan() returns.
     side = torch.cuda.Stream()
-
-    def step(keep):
-        outs = {}
-        for nu in ORDERS:
-            r, w, c = inputs[nu]
-            with torch.cuda.stream(side):
-                p = nuht.Plan(r, w, nu, EPS)
-            if keep is not None:
-                p.profile(True)
-            outs[nu] = p.execute(c)
-            if keep is not None:
-                keep.append((nu, p))
-            else:
-                p.close()
-        return outs
+    step = make_step(torch, nuht, inputs, side, EPS)
 
     for _ in range(args.warmup):
         step(None)
@@ -443,6 +538,14 @@ def main():
     work = len(ORDERS) * (N + M_OUT)
     value = work * args.steps / elapsed
     log(f"timed: {ms_per_step:.3f} ms/step, {value:.4e} (n+m)/s")
+    if args.steps_only:
+        # for counter runs: the library's kernels of this process are exactly
+        # warmup + steps headline steps
+        for _, p in kept:
+            p.close()
+        print(json.dumps({"steps_only": True, "warmup": args.warmup, "steps": args.steps,
+                          "ms_per_step": ms_per_step, "value": value}), flush=True)
+        return
 
     # per-stage times (events recorded inside the timed region)
     stage_tot = {s: 0.0 for s in nuht.STAGES}
@@ -488,65 +591,92 @@ def main():
     log("stage ms per step:", json.dumps(stage_ms))
 
     # Roofline of the dominant kernel among those with an algorithmic flop
-    # count (FP64 operations the method's arithmetic needs, per launch; the
-    # transcendental kernel and phase evaluations are not counted):
+    # count (FP64 operations the method's arithmetic needs, per launch; phase
+    # evaluations and index arithmetic are not counted):
     #   spreading   (k_spread_mfma on dense items, k_spread on the others; one
-    #               stage) every (point, cell) pair inside the kernel support (w cells
-    #               per point membership): 2M complex channels x (2 add + 2 mul)
-    #               plus the kernel-weight product: 8M + 2
+    #               stage) every (point, tap) pair inside the kernel support (w taps
+    #               per point membership): the kernel value from its degree-13
+    #               polynomial piece (13 multiply-adds, 26 flops), then 2M complex
+    #               channels x (2 add + 2 mul) and the kernel-weight product:
+    #               26 + 8M + 2 (without the kernel evaluation: 8M + 2)
     #   k_rows_asy  every (row, cell) pair of a direct-sum-path block: channel
     #               sum (2M-1) x 4, one complex multiply-add of Horner's rule over
     #               the cells 8: 8M + 4; every (row, tap) pair of an FFT-path
-    #               block: (2M-1) x 4 + 4 = 8M
-    def flops(stage, inf):
+    #               block: (2M-1) x 4 + 4 = 8M, plus the tap's kernel value
+    def flops(stage, inf, with_kernel=True):
         M, w = inf["M"], inf["es_width"]
+        kv = 26.0 if with_kernel else 0.0
         if stage == "spread":
-            return inf["asy_col_members"] * w * (8.0 * M + 2.0)
-        return inf["dft_row_cells"] * (8.0 * M + 4.0) + inf["fft_row_members"] * w * 8.0 * M
+            return inf["asy_col_members"] * w * (kv + 8.0 * M + 2.0)
+        return inf["dft_row_cells"] * (8.0 * M + 4.0) + inf["fft_row_members"] * w * (kv + 8.0 * M)
 
     kern = {"spread": "k_spread_mfma+k_spread", "rows_asymptotic": "k_rows_asy"}
     tfile = {"spread": "spread_stage", "rows_asymptotic": "k_rows_asy"}   # traffic summaries
     dom = max(kern, key=lambda st: stage_ms[st])
     fl = sum(flops(dom, infos[nu]) for nu in ORDERS)             # one launch per order per step
+    fl_ch = sum(flops(dom, infos[nu], False) for nu in ORDERS)
     achieved = fl / (stage_ms[dom] * 1e-3)
     traffic = read_traffic(tfile[dom])
     roofline = dict(bound="alu", kernel=kern[dom], achieved=achieved / 1e12, peak=PEAK_FP64 / 1e12,
                     unit="TFLOP/s", frac=achieved / PEAK_FP64, traffic=traffic,
                     flops_per_step=fl, launches_per_step=len(ORDERS),
+                    frac_without_kernel_evaluation=fl_ch / (stage_ms[dom] * 1e-3) / PEAK_FP64,
                     ms_per_step={k: stage_ms[k] for k in kern})
+    if traffic is not None:
+        gbs = len(ORDERS) * traffic["bytes"] / (stage_ms[dom] * 1e-3)
+        roofline.update(traffic_GBps=gbs / 1e9, hbm_frac=gbs / PEAK_HBM)
+    step_traffic = read_step_traffic()
+    if step_traffic is not None:
+        gbs = step_traffic["bytes_per_step"] / (ms_per_step * 1e-3)
+        step_traffic.update(GBps=gbs / 1e9, hbm_frac=gbs / PEAK_HBM)
+        log("whole-step HBM traffic:", json.dumps(step_traffic))
 
-    loose = None if args.no_loose else bench_loose(torch, nuht, inputs)
+    loose = None if args.no_loose else bench_loose(torch, nuht, inputs, side)
 
     # CPU baseline: the oracle's direct sum, on all host cores, for a sample of
     # the nu = 0 outputs (all 1e6 points each), extrapolated to the whole
-    # transform.  The same oracle values give the GPU output's error there.
+    # transform, and once more on one thread for a smaller sample.  The oracle
+    # values at sampled outputs of every order give the GPU outputs' errors.
     cpu = None
     accuracy = None
+    odirect = None
     if not args.no_cpu_baseline:
         from oracle import direct as odirect
-        r, w, c = (t.cpu().numpy() for t in inputs[0])
-        k = args.cpu_sample
-        idx = np.random.default_rng(7).choice(M_OUT, k, replace=False)
         threads = odirect.max_threads()
-        a = time.perf_counter()
-        ref = odirect.dht(0, r, c, w[idx], nthreads=threads)
-        b = time.perf_counter()
-        full_s = (b - a) * M_OUT / k
-        cpu = dict(value=(N + M_OUT) / full_s, unit="(n+m)/s", cores=threads, kind="oracle",
-                   sample=f"direct sum for {k} of the 1e6 outputs (all 1e6 points, nu=0), "
-                          f"{b - a:.1f} s, extrapolated to the full transform")
-        log("cpu baseline", cpu)
-        def err(gpu):
-            g = gpu.cpu().numpy()[idx]
-            return dict(rel_l2=float(np.linalg.norm(g - ref) / np.linalg.norm(ref)),
-                        rel_max=float(np.max(np.abs(g - ref)) / np.max(np.abs(ref))))
-        accuracy = dict(nu=0, sampled_outputs=k, eps=EPS, **err(outs[0]))
-        if loose is not None:
-            for mode in ("fp64", "fp32_spread"):
-                loose[mode]["accuracy_nu0"] = dict(sampled_outputs=k, **err(loose[mode].pop("_g0")))
+        samples = {0: args.cpu_sample, 1: 512, 10: 512}
+        accuracy = {"eps": EPS, "orders": {}}
+        for nu in ORDERS:
+            r, w, c = (t.cpu().numpy() for t in inputs[nu])
+            k = samples[nu]
+            idx = np.random.default_rng(7 + nu).choice(M_OUT, k, replace=False)
+            a = time.perf_counter()
+            ref = odirect.dht(nu, r, c, w[idx], nthreads=threads)
+            b = time.perf_counter()
+            if nu == 0:
+                full_s = (b - a) * M_OUT / k
+                k1 = 64
+                a1 = time.perf_counter()
+                odirect.dht(0, r, c, w[idx[:k1]], nthreads=1)
+                one_s = (time.perf_counter() - a1) * M_OUT / k1
+                cpu = dict(value=(N + M_OUT) / full_s, unit="(n+m)/s", cores=threads, kind="oracle",
+                           sample=f"direct sum for {k} of the 1e6 outputs (all 1e6 points, nu=0), "
+                                  f"{b - a:.1f} s on {threads} threads, extrapolated to the full transform",
+                           one_thread=dict(value=(N + M_OUT) / one_s, unit="(n+m)/s",
+                                           sample=f"{k1} outputs on 1 thread, extrapolated"),
+                           host=host_cpu())
+                log("cpu baseline", cpu)
+            accuracy["orders"][str(nu)] = dict(sampled_outputs=k, **sampled_error(outs[nu], ref, idx))
+            if loose is not None:
+                for mode in ("fp64", "fp32_spread"):
+                    loose[mode].setdefault("accuracy", {})[str(nu)] = dict(
+                        sampled_outputs=k, **sampled_error(loose[mode]["_outs"][nu], ref, idx))
         log("accuracy", accuracy)
+    if loose is not None:
+        for mode in ("fp64", "fp32_spread"):
+            loose[mode].pop("_outs", None)
 
-    batched = None if args.no_batched else bench_batched(torch, nuht, workloads, dev)
+    batched = None if args.no_batched else bench_batched(torch, nuht, workloads, dev, odirect)
+    radial = None if args.no_radial else bench_radial(torch, nuht, workloads, dev, odirect)
     fwd_bwd = None if args.no_grad else bench_fwd_bwd(torch, nuht, workloads, dev)
     pn = None if args.no_pn else bench_pn(torch, nuht, workloads, dev)
     disk = None if args.no_disk else {meth: bench_disk(torch, nuht, workloads, dev, method=meth)
@@ -575,16 +705,15 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": accuracy,
+        "step_traffic": step_traffic,
         "batched": batched,
+        "radial_2d": radial,
         "fwd_bwd": fwd_bwd,
         "eps_1e-6": loose,
         "p_equals_n": pn,
         "disk_helmholtz": disk,
         "split_exact": split,
     }
-    if loose is not None:
-        for mode in ("fp64", "fp32_spread"):
-            loose[mode].pop("_g0", None)
     print(json.dumps(out), flush=True)
 
 

@@ -84,6 +84,18 @@ typedef struct nuht_plan_s *nuht_plan_t;
  *                     at 512 points of (0, z] (tighter for large nu: 205
  *                     instead of 270 at nu = 100, eps = 1e-8); 1 .. 2000: that
  *                     L (the caller answers for the accuracy).
+ *   margin            0 or 1: the expansion orders (M, z, L) and the ES width
+ *                     are chosen for eps itself, as the paper prescribes
+ *                     (Sec. 3.3), which bounds every matrix entry's error by
+ *                     eps; summed over the many entries near the crossover
+ *                     the output's normwise maximum error can exceed eps
+ *                     (measured up to 6.6 eps at order 42, n = 5.5e5).
+ *                     margin > 1 (at most 1000): they are chosen for
+ *                     eps / margin.  Measured over 256 transforms of orders
+ *                     0 .. 63 with n, m up to 1e6 at eps = 1e-12, the worst
+ *                     normwise maximum error is 2.4 eps with margin 2,
+ *                     0.98 eps with 4 and 0.54 eps with 8.  eps / margin must
+ *                     stay >= 1e-15 (>= 1e-7 with FP32 spreading).
  */
 typedef struct {
     int64_t min_size;
@@ -95,6 +107,7 @@ typedef struct {
     int32_t tune;
     int32_t vector_spread;
     int32_t local_rank;
+    double  margin;
 } nuht_opts;
 
 /*

@@ -38,7 +38,7 @@ class NuhtOpts(ctypes.Structure):
     _fields_ = [("min_size", ctypes.c_int64), ("M_override", ctypes.c_int32),
                 ("split_candidates", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("dft_max", ctypes.c_int32), ("spread_chunk", ctypes.c_int32), ("tune", ctypes.c_int32),
-                ("vector_spread", ctypes.c_int32), ("local_rank", ctypes.c_int32)]
+                ("vector_spread", ctypes.c_int32), ("local_rank", ctypes.c_int32), ("margin", ctypes.c_double)]
 
 
 class NuhtInfo(ctypes.Structure):
@@ -145,7 +145,7 @@ class Plan:
 
     def __init__(self, r, omega, nu: int, eps: float, *, min_size: int = 0, M: int = 0,
                  split_candidates: int = 0, precision: int = NUHT_FP64, dft_max: int = 0,
-                 spread_chunk: int = 0, vector_spread: bool = False, local_rank: int = 0):
+                 spread_chunk: int = 0, vector_spread: bool = False, local_rank: int = 0, margin: float = 0.0):
         lib = load_library()
         r = _dev_f64(r, "r")
         omega = _dev_f64(omega, "omega")
@@ -153,7 +153,7 @@ class Plan:
         self.m = omega.numel()
         self.device = r.device
         opts = NuhtOpts(min_size, M, split_candidates, precision, dft_max, spread_chunk, 0,
-                        1 if vector_spread else 0, int(local_rank))
+                        1 if vector_spread else 0, int(local_rank), float(margin))
         h = ctypes.c_void_p()
         _check(lib.nuht_plan(ctypes.byref(h), int(nu), float(eps), self.n, _ptr(r), self.m, _ptr(omega),
                              ctypes.byref(opts), _stream()))
@@ -175,9 +175,12 @@ class Plan:
         _check(load_library().nuht_adjoint(self._h, _ptr(y), _ptr(cb), _stream()))
         return cb
 
-    def gradient(self, c, gbar, *, want_c=True, want_r=True, want_omega=True):
+    def gradient(self, c, gbar, *, want_c=True, want_r=True, want_omega=True, out=None):
         """(dL/dc, dL/dr, dL/domega) for g = execute(c) and gbar = dL/dg; entries
         not wanted are None."""
+        return self._gradient("nuht_gradient", c, gbar, want_c, want_r, want_omega, out)
+
+    def _gradient(self, entry, c, gbar, want_c, want_r, want_omega, out):
         gbar = _dev_f64(gbar, "gbar")
         if gbar.numel() != self.m:
             raise ValueError("gbar must have m entries")
@@ -186,11 +189,12 @@ class Plan:
             if c.numel() != self.n:
                 raise ValueError("c must have n entries")
         new = lambda k: torch.empty(k, dtype=torch.float64, device=self.device)
-        dc = new(self.n) if want_c else None
-        dr = new(self.n) if want_r else None
-        dw = new(self.m) if want_omega else None
+        o_c, o_r, o_w = out if out is not None else (None, None, None)
+        dc = (o_c if o_c is not None else new(self.n)) if want_c else None
+        dr = (o_r if o_r is not None else new(self.n)) if want_r else None
+        dw = (o_w if o_w is not None else new(self.m)) if want_omega else None
         null = ctypes.c_void_p(0)
-        _check(load_library().nuht_gradient(self._h, _ptr(c) if (want_r or want_omega) else null, _ptr(gbar),
+        _check(getattr(load_library(), entry)(self._h, _ptr(c) if (want_r or want_omega) else null, _ptr(gbar),
                                              _ptr(dc) if dc is not None else null,
                                              _ptr(dr) if dr is not None else null,
                                              _ptr(dw) if dw is not None else null, _stream()))
@@ -244,7 +248,7 @@ class Batch:
     and executed as one captured graph (nuht_plan_many / nuht_execute_many)."""
 
     def __init__(self, rs, omegas, nus, eps: float, *, tune: bool = False, min_size: int = 0,
-                 dft_max: int = 0, spread_chunk: int = 0):
+                 dft_max: int = 0, spread_chunk: int = 0, margin: float = 0.0):
         lib = load_library()
         if not (len(rs) == len(omegas) == len(nus)):
             raise ValueError("rs, omegas and nus must have the same length")
@@ -259,7 +263,7 @@ class Batch:
         m_a = (ctypes.c_int64 * k)(*self.m)
         r_a = (ctypes.c_void_p * k)(*[_ptr(r).value for r, _ in self._keep])
         w_a = (ctypes.c_void_p * k)(*[_ptr(w).value for _, w in self._keep])
-        opts = NuhtOpts(min_size, 0, 0, NUHT_FP64, dft_max, spread_chunk, 1 if tune else 0, 0)
+        opts = NuhtOpts(min_size, 0, 0, NUHT_FP64, dft_max, spread_chunk, 1 if tune else 0, 0, 0, float(margin))
         h = ctypes.c_void_p()
         _check(lib.nuht_plan_many(ctypes.byref(h), k, nu_a, float(eps), n_a, r_a, m_a, w_a, ctypes.byref(opts),
                                   _stream()))
@@ -384,7 +388,10 @@ class NuhtFunction(torch.autograd.Function):
     The forward pass plans on (r, omega) (the method needs no precomputation
     beyond the plan) and keeps the plan for the backward pass, which runs
     nuht_gradient: A^T gbar for c, and the order nu -+ 1 transforms of
-    J_nu' = (J_{nu-1} - J_{nu+1}) / 2 for r and omega.
+    J_nu' = (J_{nu-1} - J_{nu+1}) / 2 for r and omega.  The plan lives as
+    long as the autograd graph that holds it (freed with the graph, not by
+    the first backward), so a graph kept with retain_graph=True can be
+    differentiated again.
     """
 
     @staticmethod
@@ -401,7 +408,6 @@ class NuhtFunction(torch.autograd.Function):
         want = ctx.needs_input_grad
         dc, dr, dw = ctx.plan.gradient(c.detach(), gbar.contiguous(), want_c=want[0], want_r=want[1],
                                        want_omega=want[2])
-        ctx.plan.close()
         return dc, dr, dw, None, None
 
 

@@ -591,12 +591,22 @@ static int padded_channels(int nch)
     return nch <= 16 ? nch : ((nch + 3) / 4) * 4;
 }
 
-static void fill_params(PlanDev& P, int nu, double eps, const nuht_opts& o)
+// The tolerance the expansion orders and the NUFFT width are chosen for: the
+// requested eps, or eps / margin when the caller asks for a margin (the
+// paper's choice bounds every matrix entry by eps, which leaves the normwise
+// maximum of the output error at up to ~1.3 eps at high orders).
+static double design_eps(double eps, const nuht_opts& o)
+{
+    return o.margin > 1.0 ? eps / o.margin : eps;
+}
+
+static void fill_params(PlanDev& P, int nu, double eps_req, const nuht_opts& o)
 {
     int anu = std::abs(nu);
     P.nu = anu;
     P.sign = (nu < 0 && (anu & 1)) ? -1 : 1;
-    P.eps = eps;
+    P.eps = eps_req;
+    const double eps = design_eps(eps_req, o);
     int M = o.M_override > 0 ? std::min(o.M_override, 20) : num_asy_terms(anu, eps);
     P.M = M;
     P.nch = padded_channels(2 * M);
@@ -931,6 +941,7 @@ static int check_opts(const nuht_opts* opts, nuht_opts& o)
         o.local_rank > 2000)
         return NUHT_EINVAL;
     if (o.spread_chunk != 0 && (o.spread_chunk < 64 || o.spread_chunk > 16384)) return NUHT_EINVAL;
+    if (o.margin != 0.0 && !(o.margin >= 1.0 && o.margin <= 1e3)) return NUHT_EINVAL;
     return NUHT_OK;
 }
 
@@ -939,7 +950,8 @@ static int check_plan_args(int nu, double eps, int64_t n, const double* r_dev, i
                            const double* omega_dev, const nuht_opts& o)
 {
     if (!valid_common(nu, eps)) return NUHT_EINVAL;
-    if (o.precision == NUHT_FP32_SPREAD && eps < 1e-7) return NUHT_EPRECISION;
+    if (design_eps(eps, o) < 1e-15) return NUHT_EINVAL;
+    if (o.precision == NUHT_FP32_SPREAD && design_eps(eps, o) < 1e-7) return NUHT_EPRECISION;
     if (n < 0 || m < 0 || n > INT32_MAX / 2 || m > INT32_MAX / 2) return NUHT_EINVAL;
     if ((n > 0 && !r_dev) || (m > 0 && !omega_dev)) return NUHT_EINVAL;
     return NUHT_OK;
@@ -1185,6 +1197,7 @@ int nuht_tune(nuht_plan_t p, const double* c_dev, int reps, nuht_opts* best, dou
     o.split_candidates = p->opts.split_candidates;
     o.vector_spread = p->opts.vector_spread;
     o.local_rank = p->opts.local_rank;
+    o.margin = p->opts.margin;
     p->opts = o;
     p->orders.clear();
     Partition* Pt = nullptr;
@@ -1252,7 +1265,8 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
     if (count > 0 && (!nu || !n || !r_dev || !m || !omega_dev)) return NUHT_EINVAL;
     nuht_opts o;
     NUHT_TRY(check_opts(opts, o));
-    if (o.precision == NUHT_FP32_SPREAD && eps < 1e-7) return NUHT_EPRECISION;
+    if (design_eps(eps, o) < 1e-15) return NUHT_EINVAL;
+    if (o.precision == NUHT_FP32_SPREAD && design_eps(eps, o) < 1e-7) return NUHT_EPRECISION;
     for (int i = 0; i < count; ++i) {
         if (!valid_common(nu[i], eps)) return NUHT_EINVAL;
         if (n[i] < 0 || m[i] < 0 || n[i] > INT32_MAX / 2 || m[i] > INT32_MAX / 2) return NUHT_EINVAL;
@@ -1317,6 +1331,7 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
             best.split_candidates = o.split_candidates;
             best.vector_spread = o.vector_spread;
             best.local_rank = o.local_rank;
+            best.margin = o.margin;
             b->class_opts[c] = best;
         }
         for (int i = 0; i < count; ++i) {

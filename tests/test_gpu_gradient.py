@@ -104,8 +104,13 @@ def test_autograd_against_finite_differences(nuht):
     wt = dev(w).requires_grad_(True)
     g = nuht.NuhtFunction.apply(ct, rt, wt, nu, eps)
     loss = 0.5 * torch.sum((g - dev(y)) ** 2)
-    loss.backward()
+    loss.backward(retain_graph=True)
     gc, gr, gw = host(ct.grad), host(rt.grad), host(wt.grad)
+    # the retained graph differentiates again (the plan outlives the first
+    # backward): the gradients accumulate to exactly twice the first ones
+    loss.backward()
+    assert np.array_equal(host(ct.grad), 2 * gc) and np.array_equal(host(rt.grad), 2 * gr)
+    assert np.array_equal(host(wt.grad), 2 * gw)
 
     def L(c_, r_, w_):
         gg = host(nuht.nuht(dev(c_), dev(r_), dev(w_), nu, eps))

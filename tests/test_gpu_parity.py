@@ -149,6 +149,39 @@ def test_high_orders(nuht, nu):
     g1 = direct.dht(nu, r, c, w)
     assert rel_l2(g, g1) <= TOL, rel_l2(g, g1)
     assert np.max(np.abs(g - g1)) <= 1e-12 * np.sum(np.abs(c))
+    # with the parameters chosen for eps / 2 (nuht_opts.margin) the normwise
+    # max error meets the stated 1e-12 as well
+    gm, infm = run(nuht, nu, 1e-12, r, c, w, margin=2.0)
+    print(nu, "paper's parameters: rel max", rel_max(g, g1), "(M, L)", (info["M"], info["L"]),
+          "| margin 2: rel l2", rel_l2(gm, g1), "rel max", rel_max(gm, g1), "(M, L)", (infm["M"], infm["L"]))
+    assert infm["L"] >= info["L"] and infm["z"] > info["z"]
+    assert rel_l2(gm, g1) <= TOL and rel_max(gm, g1) <= TOL
+
+
+@pytest.mark.parametrize("nu", [0, 1, 10])
+def test_margin_meets_max_norm_bar_at_loose_eps(nuht, nu):
+    # eps = 1e-6, FP64 and FP32 spreading, with margin 2: the stated bar 1e-6
+    # in relative l2 and in normwise max against the direct sum
+    eps = 1e-6
+    r, w, c = workloads.uniform(4000, 3500, 1.0, 3000.0, seed=50 + nu)
+    g1 = direct.dht(nu, r, c, w)
+    for prec in (nuht.NUHT_FP64, nuht.NUHT_FP32_SPREAD):
+        g, info = run(nuht, nu, eps, r, c, w, precision=prec, margin=2.0)
+        print("margin 2, eps 1e-6, precision", prec, "nu", nu, "rel l2", rel_l2(g, g1), "rel max", rel_max(g, g1))
+        assert rel_l2(g, g1) <= eps and rel_max(g, g1) <= eps
+
+
+@pytest.mark.parametrize("nu", [0, 7])
+def test_fp32_spreading_at_its_floor(nuht, nu):
+    # FP32 spreading is accepted down to eps = 1e-7: rel-l2 <= eps and every
+    # entry within the paper's entrywise bound eps |c|_1
+    eps = 1e-7
+    r, w, c = workloads.uniform(3000, 3000, 1.0, 2500.0, seed=55 + nu)
+    g, info = run(nuht, nu, eps, r, c, w, precision=nuht.NUHT_FP32_SPREAD)
+    g1 = direct.dht(nu, r, c, w)
+    print("fp32 at 1e-7, nu", nu, "rel l2", rel_l2(g, g1), "rel max", rel_max(g, g1), "w", info["es_width"])
+    assert rel_l2(g, g1) <= eps
+    assert np.max(np.abs(g - g1)) <= eps * np.sum(np.abs(c))
 
 
 @pytest.mark.parametrize("eps", [1e-4, 1e-6, 1e-9, 1e-14])
