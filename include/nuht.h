@@ -42,6 +42,7 @@ extern "C" {
 #define NUHT_ENOMEM      -4   /* device allocation failed */
 #define NUHT_EHIP        -5   /* a HIP runtime call failed */
 #define NUHT_ECAPACITY   -6   /* the partition exceeds an internal table limit */
+#define NUHT_ENOTREADY   -7   /* nuht_gradient_noalloc: a partition it needs is not built yet */
 
 /* Precision of the NUFFT spreading and interpolation. */
 #define NUHT_FP64        0
@@ -195,6 +196,28 @@ int nuht_adjoint(nuht_plan_t plan, const double *y_dev, double *cbar_dev, void *
  */
 int nuht_gradient(nuht_plan_t plan, const double *c_dev, const double *gbar_dev,
                   double *dc_dev, double *dr_dev, double *domega_dev, void *stream);
+
+/*
+ * nuht_gradient_noalloc -- nuht_gradient for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, outputs and ordering as
+ * nuht_gradient (the same kernels in the same order, so the same values), but
+ * the call allocates nothing and never builds a partition:
+ *  - the four temporaries of dr and domega (two of n and two of m doubles)
+ *    live in one library-wide device array of 64 MiB (8 388 608 doubles), one
+ *    copy per device, held until the process ends, instead of in the plan;
+ *    dr or domega requested with 2 (n + m) > 8 388 608 gives NUHT_ECAPACITY;
+ *  - the partitions it runs (order nu transposed for dc; orders nu -+ 1,
+ *    transposed for dr and forward for domega) must already be in the plan,
+ *    built by an earlier nuht_gradient, nuht_adjoint or nuht_plan_set_order
+ *    call, else NUHT_ENOTREADY and nothing is enqueued.
+ * Every call on one device shares the array and overwrites it entirely before
+ * reading it (nothing carries over from an earlier call); calls that overlap
+ * on one device (different streams or threads without ordering) race on it.
+ * The first call on a device looks up the array's address (no allocation).
+ */
+int nuht_gradient_noalloc(nuht_plan_t plan, const double *c_dev, const double *gbar_dev,
+                          double *dc_dev, double *dr_dev, double *domega_dev, void *stream);
 
 /*
  * nuht_plan_set_order -- switch the plan to order nu (same points, frequencies

@@ -24,7 +24,7 @@ NUHT_FB_DIRECT = 1
 
 _ERRORS = {
     -1: "NUHT_EINVAL", -2: "NUHT_EDOMAIN", -3: "NUHT_EPRECISION", -4: "NUHT_ENOMEM",
-    -5: "NUHT_EHIP", -6: "NUHT_ECAPACITY",
+    -5: "NUHT_EHIP", -6: "NUHT_ECAPACITY", -7: "NUHT_ENOTREADY",
 }
 
 
@@ -57,7 +57,8 @@ class NuhtInfo(ctypes.Structure):
 
 
 # every symbol include/nuht.h declares
-EXPORTS = ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_plan_set_order",
+EXPORTS = ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_gradient_noalloc",
+           "nuht_plan_set_order",
            "nuht_plan_info", "nuht_tune", "nuht_plan_many", "nuht_execute_many", "nuht_batch_info",
            "nuht_batch_destroy", "nuht_destroy", "nuht_strerror", "nuht_direct", "nuht_profile", "nuht_profile_read",
            "nuht_fb_plan", "nuht_fb_analysis", "nuht_fb_synthesis", "nuht_fb_helmholtz", "nuht_fb_destroy")
@@ -81,6 +82,7 @@ def load_library():
     lib.nuht_execute.argtypes = [vp, vp, vp, vp]
     lib.nuht_adjoint.argtypes = [vp, vp, vp, vp]
     lib.nuht_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.nuht_gradient_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.nuht_tune.argtypes = [vp, vp, ctypes.c_int, ctypes.POINTER(NuhtOpts), ctypes.POINTER(ctypes.c_double), vp]
     lib.nuht_plan_many.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_double,
                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64),
@@ -102,7 +104,8 @@ def load_library():
     lib.nuht_fb_synthesis.argtypes = [vp, vp, vp, vp]
     lib.nuht_fb_helmholtz.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp, vp]
     lib.nuht_fb_destroy.argtypes = [vp]
-    for name in ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_plan_set_order", "nuht_plan_info",
+    for name in ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_gradient_noalloc",
+                 "nuht_plan_set_order", "nuht_plan_info",
                  "nuht_tune", "nuht_plan_many", "nuht_execute_many", "nuht_batch_info", "nuht_batch_destroy",
                  "nuht_destroy", "nuht_direct", "nuht_profile", "nuht_profile_read", "nuht_fb_plan",
                  "nuht_fb_analysis", "nuht_fb_synthesis", "nuht_fb_helmholtz", "nuht_fb_destroy"):
@@ -179,6 +182,14 @@ class Plan:
         """(dL/dc, dL/dr, dL/domega) for g = execute(c) and gbar = dL/dg; entries
         not wanted are None."""
         return self._gradient("nuht_gradient", c, gbar, want_c, want_r, want_omega, out)
+
+    def gradient_noalloc(self, c, gbar, *, want_c=True, want_r=True, want_omega=True, out=None):
+        """The same through nuht_gradient_noalloc: no device allocation inside
+        the library (the temporaries live in its per-device array; the
+        partitions must have been built by an earlier gradient, adjoint or
+        set_order call).  ``out`` = (dc, dr, domega) preallocated tensors (None
+        entries are allocated here by torch)."""
+        return self._gradient("nuht_gradient_noalloc", c, gbar, want_c, want_r, want_omega, out)
 
     def _gradient(self, entry, c, gbar, want_c, want_r, want_omega, out):
         gbar = _dev_f64(gbar, "gbar")

@@ -926,6 +926,7 @@ const char* nuht_strerror(int code)
         case NUHT_ENOMEM: return "device allocation failed";
         case NUHT_EHIP: return "HIP runtime error";
         case NUHT_ECAPACITY: return "partition exceeds internal table limits";
+        case NUHT_ENOTREADY: return "a partition the call needs has not been built";
         default: return "unknown error";
     }
 }
@@ -1096,6 +1097,96 @@ int nuht_gradient(nuht_plan_t p, const double* c_dev, const double* gbar_dev, do
         if ((rc = run(p, *Pt, c_dev, p->grad_t[3], true, s)) != NUHT_OK) return rc;
         HIP_TRY(launch_half_difference(gbar_dev, p->grad_t[2], p->grad_t[3], domega_dev, (int32_t)p->m, s));
     }
+    return NUHT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The gradient without allocation: its four temporaries (two of n, two of m
+// doubles) live in `scratch`, one array per device for the whole process,
+// instead of the plan's own buffer.  Host code never passes the array's name
+// to a kernel (in host code it is only a stand-in for the symbol); it uses the
+// device address hipGetSymbolAddress returns, looked up once per device.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocDoubles = size_t(8) << 20;     // 64 MiB: n + m <= 4 194 304
+
+static __device__ __align__(256) __attribute__((used)) double scratch[kNoAllocDoubles];
+
+// Device address of this device's copy of `scratch`, or null on failure.
+static double* scratch_address()
+{
+    static std::mutex mu;
+    static double* addr[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) { (void)hipGetLastError(); return nullptr; }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        addr[dev] = (double*)ptr;
+    }
+    return addr[dev];
+}
+
+// The partition of order nu (forward or transposed) if it is already built;
+// never builds one.
+static const Partition* built_partition(nuht_plan_t p, int nu, bool transposed)
+{
+    for (auto& o : p->orders) {
+        if (o->nu != nu) continue;
+        const Partition& Pt = transposed ? o->a : o->f;
+        return Pt.built ? &Pt : nullptr;
+    }
+    return nullptr;
+}
+
+int nuht_gradient_noalloc(nuht_plan_t p, const double* c_dev, const double* gbar_dev, double* dc_dev,
+                          double* dr_dev, double* domega_dev, void* stream)
+{
+    if (!p || !current_forward(p)) return NUHT_EINVAL;
+    const bool want_r = dr_dev != nullptr, want_w = domega_dev != nullptr;
+    if (p->m > 0 && !gbar_dev) return NUHT_EINVAL;
+    if ((want_r || want_w) && p->n > 0 && !c_dev) return NUHT_EINVAL;
+    const int nu = p->nu_req;
+    if ((want_r || want_w) && std::abs(nu) + 1 > 101) return NUHT_EINVAL;
+    if ((want_r || want_w) && 2 * (p->n + p->m) > (int64_t)kNoAllocDoubles) return NUHT_ECAPACITY;
+    // every partition the call runs must exist already: building one allocates
+    const Partition *pc = nullptr, *pr0 = nullptr, *pr1 = nullptr, *pw0 = nullptr, *pw1 = nullptr;
+    if (dc_dev && !(pc = built_partition(p, nu, true))) return NUHT_ENOTREADY;
+    if (want_r && p->n > 0) {
+        if (!(pr0 = built_partition(p, nu - 1, true)) || !(pr1 = built_partition(p, nu + 1, true)))
+            return NUHT_ENOTREADY;
+    }
+    if (want_w && p->m > 0) {
+        if (!(pw0 = built_partition(p, nu - 1, false)) || !(pw1 = built_partition(p, nu + 1, false)))
+            return NUHT_ENOTREADY;
+    }
+    double* t = (want_r || want_w) ? scratch_address() : nullptr;
+    if ((want_r || want_w) && !t) return NUHT_EHIP;
+    hipStream_t s = (hipStream_t)stream;
+    auto go = [&](const Partition* Pt, const double* in, double* out, bool scale) -> int {
+        IoArgs io;
+        io.c = in;
+        io.g = out;
+        io.scale_by_points = scale;
+        HIP_TRY(launch_execute(Pt->P, Pt->sum, Pt->B, Pt->cls.data(), (int)Pt->cls.size(), io, s, nullptr));
+        return NUHT_OK;
+    };
+    if (pc) NUHT_TRY(go(pc, gbar_dev, dc_dev, false));
+    if (pr0) {                           // t[0 .. n) and t[n .. 2n): the two transposed transforms
+        NUHT_TRY(go(pr0, gbar_dev, t, true));
+        NUHT_TRY(go(pr1, gbar_dev, t + p->n, true));
+        HIP_TRY(launch_half_difference(c_dev, t, t + p->n, dr_dev, (int32_t)p->n, s));
+    }
+    if (pw0) {                           // t[2n .. 2n + m) and t[2n + m .. 2n + 2m)
+        double* a = t + 2 * p->n;
+        NUHT_TRY(go(pw0, c_dev, a, true));
+        NUHT_TRY(go(pw1, c_dev, a + p->m, true));
+        HIP_TRY(launch_half_difference(gbar_dev, a, a + p->m, domega_dev, (int32_t)p->m, s));
+    }
+    note_use(p, s);
     return NUHT_OK;
 }
 

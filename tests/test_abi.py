@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_strerror(lib):
     assert lib.nuht_strerror(0) == b"success"
-    for code in (-1, -2, -3, -4, -5, -6):
+    for code in (-1, -2, -3, -4, -5, -6, -7):
         assert lib.nuht_strerror(code) != b"unknown error"
 
 
@@ -67,6 +67,7 @@ def test_new_entry_points_reject_invalid_arguments_without_gpu(lib):
     h = ctypes.c_void_p()
     # gradient, tuning and batches on a null plan / batch
     assert lib.nuht_gradient(None, None, None, None, None, None, None) == -1
+    assert lib.nuht_gradient_noalloc(None, None, None, None, None, None, None) == -1
     best = nuht.NuhtOpts()
     assert lib.nuht_tune(None, None, 3, ctypes.byref(best), None, None) == -1
     assert lib.nuht_execute_many(None, None, None, None) == -1
