@@ -367,10 +367,10 @@ def bench_disk(torch, nuht, workloads, dev, reps=5, method="transform"):
     orders -100 .. 100, J = 128 radial modes per order, a random smooth
     forcing.  Solver planning once, then analysis, synthesis and the whole
     solve (analysis, division by the eigenvalues, synthesis), each timed over
-    `reps` calls.  With the transform method a solve runs 8 (L + 1) transforms
-    (real and imaginary parts of orders +-l, both directions) of
-    n + m = 512 + 128 each; the direct method takes the same sums term by
-    term, 2 (L + 1) m J Bessel evaluations per solve."""
+    `reps` calls.  With the transform method a solve runs 4 (L + 1) transforms
+    (real and imaginary parts per order |l|, both directions; orders -l and l
+    share them) of n + m = 512 + 128 each; the direct method takes the same
+    sums term by term, 2 (L + 1) m J Bessel evaluations per solve."""
     m, t, L, J, eps, kappa = 512, 256, 100, 128, 1e-8, 25.0
     r, wr, zeros, f = workloads.disk(m, t, L, J, seed=190)
     rd, wrd, zd, fd = (torch.as_tensor(a, device=dev) for a in (r, wr, zeros, f))
@@ -397,7 +397,7 @@ def bench_disk(torch, nuht, workloads, dev, reps=5, method="transform"):
     sy_ms = timed(lambda: s.synthesis(beta))
     he_ms = timed(lambda: s.helmholtz(kappa, fd))
     s.close()
-    transforms = 8 * (L + 1)
+    transforms = 4 * (L + 1)
     res = dict(method=method, m=m, t=t, L=L, J=J, eps=eps, kappa=kappa, plan_ms=plan_ms, analysis_ms=an_ms,
                synthesis_ms=sy_ms, solve_ms=he_ms)
     if method == "transform":

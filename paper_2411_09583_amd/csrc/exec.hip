@@ -9,7 +9,11 @@
 // Row side (one thread per frequency): walk the block tree from the root and
 //   add, level by level, the row's local, asymptotic and (at the end) direct
 //   contributions; write g once, in the caller's order.
+#include <algorithm>
+#include <cstring>
 #include <type_traits>
+#include <utility>
+#include <vector>
 
 #include "nuht_device.h"
 #include "nuht_launch.h"
@@ -17,16 +21,63 @@
 namespace nuht {
 
 // ---------------------------------------------------------------------------
-// cs[k] = c[perm[k]] (times x[k] when x is given); c is read from c_slot when
-// that is set.
-__global__ void k_gather(const double* c, const double* const* c_slot, const int32_t* __restrict__ perm,
-                         const double* __restrict__ x, int32_t n, double* __restrict__ cs)
+// Every execution kernel is a body taking the transform (P) and the index of
+// its workgroup within that transform's work.  A single transform's kernel
+// passes P by value and blockIdx.x; a batched kernel covers every transform
+// of a batch in one launch: its workgroup finds its transform in a table of
+// segments (WorkSeg, ascending g0) and runs the body on that transform's
+// PlanDev, kept in device memory, as its workgroup blockIdx.x - g0.
+// ---------------------------------------------------------------------------
+// A batch's PlanDev array is written once, before the graph that reads it is
+// recorded, and never while a batched kernel runs: it is read through the
+// constant address space, like a kernel argument, so that the compiler may
+// load its fields through the scalar unit.
+typedef const __attribute__((address_space(4))) PlanDev ConstPlanDev;
+__device__ __forceinline__ const PlanDev& plan_of(const PlanDev* plans, int t)
 {
-    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const double* cp = c_slot ? *c_slot : c;
-    double v = cp[perm[k]];
-    cs[k] = x ? v * x[k] : v;
+    return *(const PlanDev*)((ConstPlanDev*)plans + t);
+}
+
+// The segment of this workgroup (the last one with g0 <= blockIdx.x).
+template <class Seg>
+__device__ __forceinline__ int find_seg_index(const Seg* __restrict__ segs, int nseg)
+{
+    const int g = blockIdx.x;
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].g0 <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// The transform of this workgroup and the workgroup's index within it.
+__device__ __forceinline__ WorkSeg find_seg(const WorkSeg* __restrict__ segs, int nseg)
+{
+    const int s = find_seg_index(segs, nseg);
+    return WorkSeg{segs[s].t, (int32_t)blockIdx.x - segs[s].g0};
+}
+
+// cs[k] = c[perm[k]] (times the sorted point r_k when scale is set).
+__device__ __forceinline__ void gather_body(const PlanDev& P, int bid, const double* c, bool scale)
+{
+    const int32_t k = bid * blockDim.x + threadIdx.x;
+    if (k >= P.n) return;
+    const double v = c[P.perm_r[k]];
+    P.cs[k] = scale ? v * P.rs[k] : v;
+}
+
+// c is read from c_slot when that is set.
+__global__ void k_gather(PlanDev P, const double* c, const double* const* c_slot, int scale)
+{
+    gather_body(P, blockIdx.x, c_slot ? *c_slot : c, scale != 0);
+}
+
+__global__ void k_gather_many(const PlanDev* __restrict__ plans, const WorkSeg* __restrict__ segs, int nseg,
+                              const double* const* c_table)
+{
+    const WorkSeg w = find_seg(segs, nseg);
+    gather_body(plan_of(plans, w.t), w.g0, c_table[w.t], false);
 }
 
 // A transform with no points: the output is zero.
@@ -36,6 +87,23 @@ __global__ void k_zero_output(double* g, double* const* g_slot, int64_t m)
     if (i >= m) return;
     double* gp = g_slot ? *g_slot : g;
     gp[i] = 0.0;
+}
+
+__global__ void k_zero_output_many(const PlanDev* __restrict__ plans, const WorkSeg* __restrict__ segs, int nseg,
+                                   double* const* g_table)
+{
+    const WorkSeg w = find_seg(segs, nseg);
+    const int64_t i = (int64_t)w.g0 * blockDim.x + threadIdx.x;
+    if (i < plan_of(plans, w.t).m) g_table[w.t][i] = 0.0;
+}
+
+// gd = 0 ahead of the direct blocks.
+__global__ void k_zero_gd_many(const PlanDev* __restrict__ plans, const WorkSeg* __restrict__ segs, int nseg)
+{
+    const WorkSeg w = find_seg(segs, nseg);
+    const PlanDev& P = plan_of(plans, w.t);
+    const int64_t i = (int64_t)w.g0 * blockDim.x + threadIdx.x;
+    if (i < P.m) P.gd[i] = 0.0;
 }
 
 __global__ void k_fill_value(double* __restrict__ x, int64_t n, double v)
@@ -89,7 +157,7 @@ __device__ __forceinline__ void reduce_scatter_half(double (&v)[NQ], int lane)
 // Moments s0 .. s0 + NQ - 1 of the item (those up to L are stored).
 template <int NQ>
 __device__ __forceinline__ void lmom_pass(const PlanDev& P, const Item& I, const LBlock& B, const double* __restrict__ cs,
-                                          double* __restrict__ lpart, int s0, int lane)
+                                          double* __restrict__ lpart, int s0, int lane, int bid)
 {
     const int L = P.L;
     const int odd = P.nu & 1;
@@ -131,37 +199,57 @@ __device__ __forceinline__ void lmom_pass(const PlanDev& P, const Item& I, const
     double mine = acc[0];
     #pragma unroll
     for (int o = NQ; o < 64; o <<= 1) mine += __shfl_xor(mine, o);
-    if (lane < NQ && s0 + lane <= L) lpart[(int64_t)blockIdx.x * (L + 1) + s0 + lane] = mine;
+    if (lane < NQ && s0 + lane <= L) lpart[(int64_t)bid * (L + 1) + s0 + lane] = mine;
 }
 
-__global__ __launch_bounds__(64) void k_lmom(PlanDev P, const double* __restrict__ cs, double* __restrict__ lpart)
+__device__ __forceinline__ void lmom_body(const PlanDev& P, int bid)
 {
-    const Item I = P.litems[blockIdx.x];
+    const Item I = P.litems[bid];
     const LBlock B = P.lb[I.blk];
     const int L = P.L;
     const int lane = threadIdx.x;
+    const double* __restrict__ cs = P.cs;
+    double* __restrict__ lpart = P.lpart;
     // passes of 32 moments; the last one as narrow as what is left allows
     for (int s0 = 0; s0 <= L;) {
         const int rem = L + 1 - s0;
-        if (rem > 16) { lmom_pass<32>(P, I, B, cs, lpart, s0, lane); s0 += 32; }
-        else if (rem > 8) { lmom_pass<16>(P, I, B, cs, lpart, s0, lane); s0 += 16; }
-        else { lmom_pass<8>(P, I, B, cs, lpart, s0, lane); s0 += 8; }
+        if (rem > 16) { lmom_pass<32>(P, I, B, cs, lpart, s0, lane, bid); s0 += 32; }
+        else if (rem > 8) { lmom_pass<16>(P, I, B, cs, lpart, s0, lane, bid); s0 += 16; }
+        else { lmom_pass<8>(P, I, B, cs, lpart, s0, lane, bid); s0 += 8; }
     }
 }
 
-// Sum of a local block's item partials, in item order.
-__global__ void k_lmom_reduce(PlanDev P, const double* __restrict__ lpart, double* __restrict__ lmom)
+__global__ __launch_bounds__(64) void k_lmom(PlanDev P) { lmom_body(P, blockIdx.x); }
+
+__global__ __launch_bounds__(64) void k_lmom_many(const PlanDev* __restrict__ plans,
+                                                  const WorkSeg* __restrict__ segs, int nseg)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const WorkSeg w = find_seg(segs, nseg);
+    lmom_body(plan_of(plans, w.t), w.g0);
+}
+
+// Sum of a local block's item partials, in item order.
+__device__ __forceinline__ void lmom_reduce_body(const PlanDev& P, int bid)
+{
+    int64_t t = (int64_t)bid * blockDim.x + threadIdx.x;
     const int Lp = P.L + 1;
     if (t >= (int64_t)P.n_l * Lp) return;
     int32_t b = (int32_t)(t / Lp);
     int32_t l = (int32_t)(t % Lp);
     const LBlock B = P.lb[b];
+    const double* __restrict__ lpart = P.lpart;
     double s = 0.0;
     for (int32_t it = 0; it < B.nitems; ++it) s += lpart[(int64_t)(B.item0 + it) * Lp + l];
     // stored as the row pass uses them: u_0 = t_0, u_l = 2 (-1)^l t_l
-    lmom[t] = l == 0 ? s : ((l & 1) ? -2.0 * s : 2.0 * s);
+    P.lmom[t] = l == 0 ? s : ((l & 1) ? -2.0 * s : 2.0 * s);
+}
+
+__global__ void k_lmom_reduce(PlanDev P) { lmom_reduce_body(P, blockIdx.x); }
+
+__global__ void k_lmom_reduce_many(const PlanDev* __restrict__ plans, const WorkSeg* __restrict__ segs, int nseg)
+{
+    const WorkSeg w = find_seg(segs, nseg);
+    lmom_reduce_body(plan_of(plans, w.t), w.g0);
 }
 
 // ---------------------------------------------------------------------------
@@ -242,16 +330,17 @@ __device__ __forceinline__ double typed_fma(double a, double b, double c) { retu
 __device__ __forceinline__ float typed_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 template <int NCH, typename T>
-__global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restrict__ cs,
-                                                const double* __restrict__ es_poly, double2* __restrict__ part_raw)
+__device__ __forceinline__ void spread_body(const PlanDev& P, int bid)
 {
     using T2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
-    T2* part = reinterpret_cast<T2*>(part_raw);
+    T2* part = reinterpret_cast<T2*>(P.part);
+    const double* __restrict__ cs = P.cs;
+    const double* __restrict__ es_poly = P.es_poly;
     extern __shared__ double4 spread_lds[];
     SpreadPoint<T>* s_pt = reinterpret_cast<SpreadPoint<T>*>(spread_lds);
     T* s_k = reinterpret_cast<T*>(s_pt + kSpreadSub);
     // the items not spread on the matrix cores, from the back of the order
-    const Item I = P.aitems[P.alist[P.n_aitems - 1 - (int)blockIdx.x]];
+    const Item I = P.aitems[P.alist[P.n_aitems - 1 - bid]];
     const ABlock B = P.ab[I.blk];
     const int tid = threadIdx.x;
     const int w = P.w;
@@ -344,6 +433,20 @@ __global__ __launch_bounds__(256) void k_spread(PlanDev P, const double* __restr
             for (int p = 0; p < NCH; ++p) { dst[p].x = ar[p]; dst[p].y = ai[p]; }
         }
     }
+}
+
+template <int NCH, typename T>
+__global__ __launch_bounds__(256) void k_spread(PlanDev P)
+{
+    spread_body<NCH, T>(P, blockIdx.x);
+}
+
+template <int NCH, typename T>
+__global__ __launch_bounds__(256) void k_spread_many(const PlanDev* __restrict__ plans,
+                                                     const WorkSeg* __restrict__ segs, int nseg)
+{
+    const WorkSeg w = find_seg(segs, nseg);
+    spread_body<NCH, T>(plan_of(plans, w.t), w.g0);
 }
 
 // ---------------------------------------------------------------------------
@@ -455,9 +558,11 @@ __device__ __forceinline__ void spread_mfma_flush(v4d (&acc)[kSpreadTiles<NCH>],
 }
 
 template <int NCH>
-__device__ __forceinline__ void spread_mfma_item(const PlanDev& P, const double* __restrict__ cs,
-                                                 const double* __restrict__ es_poly, double2* __restrict__ part)
+__device__ __forceinline__ void spread_mfma_item(const PlanDev& P, int bid)
 {
+    const double* __restrict__ cs = P.cs;
+    const double* __restrict__ es_poly = P.es_poly;
+    double2* __restrict__ part = P.part;
     using SM = SpreadMfma<NCH>;
     constexpr int NCT = SM::NCT, NC = SM::NC, VS = SM::VS, WPTS = SM::WPTS, GC = SM::GC;
     extern __shared__ double4 spread_lds[];
@@ -468,7 +573,7 @@ __device__ __forceinline__ void spread_mfma_item(const PlanDev& P, const double*
     double* s_s = s_v + WPTS * VS;
     int32_t* s_d = reinterpret_cast<int32_t*>(s_s + WPTS);
     double* s_g = reinterpret_cast<double*>(base + SM::wave_bytes - SM::fold_bytes);
-    const Item I = P.aitems[P.alist[blockIdx.x]];
+    const Item I = P.aitems[P.alist[bid]];
     const ABlock B = P.ab[I.blk];
     const int col = lane & 15, kq = lane >> 4;
     const int w = P.w;
@@ -549,10 +654,17 @@ __device__ __forceinline__ void spread_mfma_item(const PlanDev& P, const double*
 // Up to 8 channels (one column tile) the kernel fits four waves per SIMD,
 // with two tiles three.
 template <int NCH>
-__global__ __launch_bounds__(256) void k_spread_mfma(PlanDev P, const double* __restrict__ cs,
-                                                     const double* __restrict__ es_poly, double2* __restrict__ part)
+__global__ __launch_bounds__(256) void k_spread_mfma(PlanDev P)
 {
-    spread_mfma_item<NCH>(P, cs, es_poly, part);
+    spread_mfma_item<NCH>(P, blockIdx.x);
+}
+
+template <int NCH>
+__global__ __launch_bounds__(256) void k_spread_mfma_many(const PlanDev* __restrict__ plans,
+                                                          const WorkSeg* __restrict__ segs, int nseg)
+{
+    const WorkSeg w = find_seg(segs, nseg);
+    spread_mfma_item<NCH>(plan_of(plans, w.t), w.g0);
 }
 
 // ---------------------------------------------------------------------------
@@ -576,17 +688,18 @@ __device__ __forceinline__ double2 load_partial(const double2* __restrict__ part
 }
 
 template <typename PT>
-__global__ void k_spread_reduce(PlanDev P, const double2* __restrict__ part, double2* __restrict__ grids,
-                                int64_t total_slots)
+__device__ __forceinline__ void spread_reduce_body(const PlanDev& P, int bid)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double2* __restrict__ part = P.part;
+    double2* __restrict__ grids = P.grids;
+    int64_t t = (int64_t)bid * blockDim.x + threadIdx.x;
     const int nch = P.nch;
-    const int64_t total = total_slots * nch;
+    const int64_t total = P.grid_cells * nch;
     // Block owning a slot: the last block b with gslot[b] <= slot.  The wave
     // searches once for the slot of its first lane (uniform, through the scalar
     // unit); a wave spans at most 64 slots, so each lane then steps forward
     // over the few blocks that start inside that span.
-    int64_t t0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    int64_t t0 = (int64_t)bid * blockDim.x + (threadIdx.x & ~63);
     int64_t slot0 = __builtin_amdgcn_readfirstlane((int32_t)((t0 < total ? t0 : total - 1) / nch));
     int32_t lo = 0, hi = P.n_a - 1;
     while (lo < hi) {
@@ -666,19 +779,26 @@ __global__ void k_spread_reduce(PlanDev P, const double2* __restrict__ part, dou
     }
 }
 
-// Transforms of N <= 4096 points, every size class in one launch: workgroup
-// g belongs to class c when wg0[c] <= g < wg0[c + 1], and within it to the
-// FFT-list slot (g - wg0[c]) / nch of the class and channel (g - wg0[c]) % nch.
-struct SmallFfts {
-    int32_t n;                 // classes
-    int32_t log2n[8], first[8];
-    int32_t wg0[9];
-};
+template <typename PT>
+__global__ void k_spread_reduce(PlanDev P)
+{
+    spread_reduce_body<PT>(P, blockIdx.x);
+}
 
-__global__ __launch_bounds__(256) void k_fft_small(PlanDev P, double2* __restrict__ grids, SmallFfts F)
+template <typename PT>
+__global__ void k_spread_reduce_many(const PlanDev* __restrict__ plans, const WorkSeg* __restrict__ segs, int nseg)
+{
+    const WorkSeg w = find_seg(segs, nseg);
+    spread_reduce_body<PT>(plan_of(plans, w.t), w.g0);
+}
+
+// Transforms of N <= 4096 points, every size class of the transform in one
+// launch (P.small).
+__device__ __forceinline__ void fft_small_body(const PlanDev& P, int g)
 {
     extern __shared__ double2 sm[];
-    const int g = blockIdx.x;
+    const SmallFfts& F = P.small;
+    double2* __restrict__ grids = P.grids;
     int c = 0;
     while (c + 1 < F.n && g >= F.wg0[c + 1]) ++c;
     const int logN = F.log2n[c], N = 1 << logN;
@@ -691,6 +811,15 @@ __global__ __launch_bounds__(256) void k_fft_small(PlanDev P, double2* __restric
     __syncthreads();
     lds_fft(sm, N, logN, 1, 0, 1);
     for (int i = threadIdx.x; i < N; i += blockDim.x) x[i] = sm[i];
+}
+
+__global__ __launch_bounds__(256) void k_fft_small(PlanDev P) { fft_small_body(P, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_fft_small_many(const PlanDev* __restrict__ plans,
+                                                        const WorkSeg* __restrict__ segs, int nseg)
+{
+    const WorkSeg w = find_seg(segs, nseg);
+    fft_small_body(plan_of(plans, w.t), w.g0);
 }
 
 // Transforms of N = 2^13 .. 2^24 points run as two or three passes, each a
@@ -805,15 +934,34 @@ struct FftCol {
     int64_t in_es, in_hs, out_es, out_hs, lo_mask, kmul;
 };
 
+// One pass over one size class of a transform: the class's first FFT-list
+// slot, log2 of its FFT size, its offset in the scratch buffer, and the pass
+// (for the row pass only C.logL = log2 N1 and C.logLines are used).
+struct FftPass {
+    int32_t first, logN;
+    int64_t scratch_off;
+    FftCol C;
+};
+
+// A transform's share of a batched FFT pass launch.
+struct FftSeg {
+    int32_t t, g0;
+    FftPass F;
+};
+
 __device__ __forceinline__ void fft_stage_twiddles(double2* tw, const double2* __restrict__ T, int logL)
 {
     for (int j = threadIdx.x; j < (1 << logL); j += blockDim.x) tw[j] = T[j << (12 - logL)];
 }
 
-__global__ __launch_bounds__(256) void k_fft_col(PlanDev P, double2* __restrict__ grids,
-                                                 double2* __restrict__ scratch, const double2* __restrict__ T,
-                                                 int first, int logN, int64_t scratch_off, FftCol C)
+__device__ __forceinline__ void fft_col_body(const PlanDev& P, int bid, const FftPass& F)
 {
+    double2* __restrict__ grids = P.grids;
+    double2* __restrict__ scratch = P.scratch;
+    const double2* __restrict__ T = P.fft_tw;
+    const int first = F.first, logN = F.logN;
+    const int64_t scratch_off = F.scratch_off;
+    const FftCol& C = F.C;
     extern __shared__ double2 sm[];
     const int L = 1 << C.logL, lines = 1 << C.logLines, ls = L + 1;
     double2* tw = sm + lines * ls;
@@ -821,7 +969,7 @@ __global__ __launch_bounds__(256) void k_fft_col(PlanDev P, double2* __restrict_
     const int64_t N = int64_t(1) << logN;
     const int groups = (int)(N >> (C.logL + C.logLines));
     const int nch = P.nch;
-    int tr = blockIdx.x / groups, grp = blockIdx.x - tr * groups;
+    int tr = bid / groups, grp = bid - tr * groups;
     int slot = tr / nch, ch = tr - slot * nch;
     const ABlock B = P.ab[P.fft_list[first + slot]];
     const double2* x = grids + B.grid_off + (int64_t)ch * N;
@@ -856,12 +1004,24 @@ __global__ __launch_bounds__(256) void k_fft_col(PlanDev P, double2* __restrict_
     }
 }
 
+__global__ __launch_bounds__(256) void k_fft_col(PlanDev P, FftPass F) { fft_col_body(P, blockIdx.x, F); }
+
+__global__ __launch_bounds__(256) void k_fft_col_many(const PlanDev* __restrict__ plans,
+                                                      const FftSeg* __restrict__ segs, int nseg)
+{
+    const int s = find_seg_index(segs, nseg);
+    fft_col_body(plan_of(plans, segs[s].t), (int)blockIdx.x - segs[s].g0, segs[s].F);
+}
+
 // The row pass: batch k2 < N2 of length L = N1 read contiguously at k2 N1 from
 // the scratch buffer; output k1 written to the grid at k2 + N2 k1.
-__global__ __launch_bounds__(256) void k_fft_row(PlanDev P, double2* __restrict__ grids,
-                                                 const double2* __restrict__ scratch, const double2* __restrict__ T,
-                                                 int first, int logN, int64_t scratch_off, int logL, int logLines)
+__device__ __forceinline__ void fft_row_body(const PlanDev& P, int bid, const FftPass& F)
 {
+    double2* __restrict__ grids = P.grids;
+    const double2* __restrict__ scratch = P.scratch;
+    const double2* __restrict__ T = P.fft_tw;
+    const int first = F.first, logN = F.logN, logL = F.C.logL, logLines = F.C.logLines;
+    const int64_t scratch_off = F.scratch_off;
     extern __shared__ double2 sm[];
     const int L = 1 << logL, lines = 1 << logLines, ls = L + 1;
     double2* tw = sm + lines * ls;
@@ -869,7 +1029,7 @@ __global__ __launch_bounds__(256) void k_fft_row(PlanDev P, double2* __restrict_
     const int64_t N = int64_t(1) << logN, N2 = N >> logL;
     const int groups = (int)(N2 >> logLines);
     const int nch = P.nch;
-    int tr = blockIdx.x / groups, grp = blockIdx.x - tr * groups;
+    int tr = bid / groups, grp = bid - tr * groups;
     int slot = tr / nch, ch = tr - slot * nch;
     const ABlock B = P.ab[P.fft_list[first + slot]];
     const int64_t k20 = (int64_t)grp << logLines;
@@ -898,6 +1058,15 @@ __global__ __launch_bounds__(256) void k_fft_row(PlanDev P, double2* __restrict_
             ys[(int64_t)k1 * N2 + li] = sm[li * ls + k1];
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_fft_row(PlanDev P, FftPass F) { fft_row_body(P, blockIdx.x, F); }
+
+__global__ __launch_bounds__(256) void k_fft_row_many(const PlanDev* __restrict__ plans,
+                                                      const FftSeg* __restrict__ segs, int nseg)
+{
+    const int s = find_seg_index(segs, nseg);
+    fft_row_body(plan_of(plans, segs[s].t), (int)blockIdx.x - segs[s].g0, segs[s].F);
 }
 
 // ---------------------------------------------------------------------------
@@ -1260,10 +1429,11 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
 // subdivision tree), so the per-row sums are stored, not accumulated.
 constexpr int kDirectThreads = 256;
 
-__global__ __launch_bounds__(kDirectThreads) void k_direct_blocks(PlanDev P, const double* __restrict__ cs,
-                                                                  double* __restrict__ gd)
+__device__ __forceinline__ void direct_body(const PlanDev& P, int bid)
 {
-    const DBlock D = P.db[blockIdx.x];
+    const double* __restrict__ cs = P.cs;
+    double* __restrict__ gd = P.gd;
+    const DBlock D = P.db[bid];
     const int mb = D.j1 - D.j0 + 1, nb = D.k1 - D.k0 + 1;
     int G = 1;
     while (G < 64 && 2 * G * mb <= kDirectThreads) G <<= 1;
@@ -1285,6 +1455,15 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct_blocks(PlanDev P, con
     }
 }
 
+__global__ __launch_bounds__(kDirectThreads) void k_direct_blocks(PlanDev P) { direct_body(P, blockIdx.x); }
+
+__global__ __launch_bounds__(kDirectThreads) void k_direct_blocks_many(const PlanDev* __restrict__ plans,
+                                                                       const WorkSeg* __restrict__ segs, int nseg)
+{
+    const WorkSeg w = find_seg(segs, nseg);
+    direct_body(plan_of(plans, w.t), w.g0);
+}
+
 __global__ void k_fill_zero(double* __restrict__ x, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1300,10 +1479,10 @@ __global__ void k_fill_zero(double* __restrict__ x, int64_t n)
 // the local blocks, the direct-block sum from k_direct_blocks and ga, and
 // writes g once in the caller's order.
 template <int NCH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_rows_asy(PlanDev P, const double2* __restrict__ grids,
-                                                  double* __restrict__ ga)
+__device__ __forceinline__ void rows_asy_body(const PlanDev& P, int bid)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const double2* __restrict__ grids = P.grids;
+    int j = bid * blockDim.x + threadIdx.x;
     if (j >= P.m) return;
     double om = P.ws[j];
     double acc = 0.0;
@@ -1324,16 +1503,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
         node = child;
     }
-    ga[j] = acc;
+    P.ga[j] = acc;
+}
+
+template <int NCH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_rows_asy(PlanDev P)
+{
+    rows_asy_body<NCH>(P, blockIdx.x);
+}
+
+template <int NCH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_rows_asy_many(
+    const PlanDev* __restrict__ plans, const WorkSeg* __restrict__ segs, int nseg)
+{
+    const WorkSeg w = find_seg(segs, nseg);
+    rows_asy_body<NCH>(plan_of(plans, w.t), w.g0);
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_rows_local(PlanDev P, const double* __restrict__ gd,
-                                                    const double* __restrict__ ga, const double* __restrict__ lmom,
-                                                    double* g, double* const* g_slot)
+__device__ __forceinline__ void rows_local_body(const PlanDev& P, int bid, double* g)
 {
+    const double* __restrict__ gd = P.gd;
+    const double* __restrict__ ga = P.ga;
+    const double* __restrict__ lmom = P.lmom;
     extern __shared__ double ring_all[];
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = bid * blockDim.x + threadIdx.x;
     if (j >= P.m) return;
     double* ring = ring_all + threadIdx.x;
     const int stride = blockDim.x;
@@ -1360,8 +1554,22 @@ __global__ __launch_bounds__(256) void k_rows_local(PlanDev P, const double* __r
         }
         node = child;
     }
-    double* gp = g_slot ? *g_slot : g;
-    gp[P.perm_w[j]] = P.sign * (acc + ga[j]);
+    g[P.perm_w[j]] = P.sign * (acc + ga[j]);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_rows_local(PlanDev P, double* g, double* const* g_slot)
+{
+    rows_local_body<MODE>(P, blockIdx.x, g_slot ? *g_slot : g);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_rows_local_many(const PlanDev* __restrict__ plans,
+                                                         const WorkSeg* __restrict__ segs, int nseg,
+                                                         double* const* g_table)
+{
+    const WorkSeg w = find_seg(segs, nseg);
+    rows_local_body<MODE>(plan_of(plans, w.t), w.g0, g_table[w.t]);
 }
 
 // Brute-force reference: one thread per frequency, all points.
@@ -1383,43 +1591,49 @@ __global__ void k_direct_all(PlanDev P, const double* __restrict__ r, const doub
 static inline int cdiv64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 template <int NCH>
-static void launch_spread(const PlanDev& P, const Summary& S, const ExecBuffers& B, hipStream_t s)
+static void launch_spread(const PlanDev& P, const Summary& S, hipStream_t s)
 {
     const int32_t n_dense = S.n_adense, n_rest = S.n_aitems - S.n_adense;
     if constexpr (NCH <= 16) {
-        if (n_dense > 0) {
-            hipLaunchKernelGGL((k_spread_mfma<NCH>), dim3(n_dense), dim3(256), SpreadMfma<NCH>::lds_bytes, s, P,
-                               B.cs, B.es_poly, B.part);
-        }
+        if (n_dense > 0)
+            hipLaunchKernelGGL((k_spread_mfma<NCH>), dim3(n_dense), dim3(256), SpreadMfma<NCH>::lds_bytes, s, P);
     }
     if (n_rest > 0) {
         if (P.fp32)
-            hipLaunchKernelGGL((k_spread<NCH, float>), dim3(n_rest), dim3(256), spread_lds_bytes<float>(P.w), s, P,
-                               B.cs, B.es_poly, B.part);
+            hipLaunchKernelGGL((k_spread<NCH, float>), dim3(n_rest), dim3(256), spread_lds_bytes<float>(P.w), s, P);
         else
-            hipLaunchKernelGGL((k_spread<NCH, double>), dim3(n_rest), dim3(256), spread_lds_bytes<double>(P.w), s, P,
-                               B.cs, B.es_poly, B.part);
+            hipLaunchKernelGGL((k_spread<NCH, double>), dim3(n_rest), dim3(256), spread_lds_bytes<double>(P.w), s, P);
     }
 }
 
 template <int NCH>
-static void launch_rows_asy(const PlanDev& P, const ExecBuffers& B, hipStream_t s)
+static void launch_rows_asy(const PlanDev& P, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rows_asy<NCH>, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, P, B.grids, B.ga);
+    hipLaunchKernelGGL(k_rows_asy<NCH>, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, P);
 }
 
-static void launch_rows_local(const PlanDev& P, const ExecBuffers& B, const IoArgs& io, hipStream_t s)
+// local_eval keeps J_{nu-a .. nu}, a = floor(nu/2), per thread in LDS: the
+// block size and LDS bytes of the local-row kernel of order nu (MODE 2).
+static int rows_local_block(int nu)
+{
+    const int slots = (nu >> 1) + 1;
+    return slots * 256 * 8 <= 65536 ? 256 : 64;
+}
+
+static size_t rows_local_lds(int nu, int bs)
+{
+    return nu <= 1 ? 0 : (size_t)((nu >> 1) + 1) * bs * sizeof(double);
+}
+
+static void launch_rows_local(const PlanDev& P, const IoArgs& io, hipStream_t s)
 {
     if (P.nu <= 1) {   // no ring of earlier values needed
         auto k = P.nu == 0 ? k_rows_local<0> : k_rows_local<1>;
-        hipLaunchKernelGGL(k, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, P, B.gd, B.ga, B.lmom, io.g, io.g_slot);
+        hipLaunchKernelGGL(k, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, P, io.g, io.g_slot);
         return;
     }
-    // local_eval keeps J_{nu-a .. nu}, a = floor(nu/2), per thread in LDS
-    const int slots = (P.nu >> 1) + 1;
-    int bs = slots * 256 * 8 <= 65536 ? 256 : 64;
-    size_t lds = (size_t)slots * bs * sizeof(double);
-    hipLaunchKernelGGL(k_rows_local<2>, dim3(cdiv64(P.m, bs)), dim3(bs), lds, s, P, B.gd, B.ga, B.lmom, io.g,
+    const int bs = rows_local_block(P.nu);
+    hipLaunchKernelGGL(k_rows_local<2>, dim3(cdiv64(P.m, bs)), dim3(bs), rows_local_lds(P.nu, bs), s, P, io.g,
                        io.g_slot);
 }
 
@@ -1483,10 +1697,13 @@ static size_t fft_lds_bytes(int logL, int logLines)
 
 // Two passes for N <= 2^16 (N1 = 2^floor(logN/2)), three beyond; every pass
 // length is at most 2^8 and at least 2^6 for the sizes that reach here.
-static void launch_fft_large(const PlanDev& P, const ExecBuffers& B, const FftClass& C, hipStream_t s)
+// pass 0: the inner column pass over nb (three-pass sizes only), 1: the
+// column pass over na, 2: the row pass.  Returns false when the size class
+// has no such pass; else its arguments, workgroups and LDS bytes.
+static bool fft_pass(const FftClass& K, int nch, int pass, FftPass& F, int& blocks, size_t& lds)
 {
-    const int logN = C.log2n;
-    const int ntr = C.count * P.nch;
+    const int logN = K.log2n;
+    const int ntr = K.count * nch;
     int logN1, logNa, logNb;
     if (logN <= 16) {
         logN1 = logN / 2; logNa = logN - logN1; logNb = 0;
@@ -1494,29 +1711,40 @@ static void launch_fft_large(const PlanDev& P, const ExecBuffers& B, const FftCl
         logN1 = logN / 3; logNa = (logN - logN1) / 2; logNb = logN - logN1 - logNa;
     }
     const int64_t N1 = int64_t(1) << logN1, Na = int64_t(1) << logNa, Nb = int64_t(1) << logNb;
-    if (logNb > 0) {
-        FftCol c{};
+    F = FftPass{};
+    F.first = K.first;
+    F.logN = logN;
+    F.scratch_off = K.scratch_off;
+    FftCol& c = F.C;
+    if (pass == 0) {
+        if (logNb == 0) return false;
         c.logL = logNb; c.logLines = fft_log_lines(logNb); c.logBlo = logN1 + logNa; c.to_scratch = 0;
         c.in_es = N1 * Na; c.in_hs = 0; c.out_es = N1 * Na; c.out_hs = 0;
         c.lo_mask = ~(N1 - 1); c.kmul = 1;
-        int blocks = ntr * (int)((int64_t(1) << logN) >> (c.logL + c.logLines));
-        hipLaunchKernelGGL(k_fft_col, dim3(blocks), dim3(256), fft_lds_bytes(c.logL, c.logLines), s, P, B.grids,
-                           B.scratch, B.fft_tw, C.first, logN, C.scratch_off, c);
-    }
-    {
-        FftCol c{};
+    } else if (pass == 1) {
         c.logL = logNa; c.logLines = fft_log_lines(logNa); c.logBlo = logN1; c.to_scratch = 1;
         c.in_es = N1; c.in_hs = N1 * Na; c.out_es = N1 * Nb; c.out_hs = N1;
         c.lo_mask = ~int64_t(0); c.kmul = Nb;
-        int blocks = ntr * (int)((int64_t(1) << logN) >> (c.logL + c.logLines));
-        hipLaunchKernelGGL(k_fft_col, dim3(blocks), dim3(256), fft_lds_bytes(c.logL, c.logLines), s, P, B.grids,
-                           B.scratch, B.fft_tw, C.first, logN, C.scratch_off, c);
+    } else {
+        c.logL = logN1; c.logLines = fft_log_lines(logN1);
+        blocks = ntr * (int)((int64_t(1) << (logN - logN1)) >> c.logLines);
+        lds = fft_lds_bytes(c.logL, c.logLines);
+        return true;
     }
-    {
-        int logLines = fft_log_lines(logN1);
-        int blocks = ntr * (int)((int64_t(1) << (logN - logN1)) >> logLines);
-        hipLaunchKernelGGL(k_fft_row, dim3(blocks), dim3(256), fft_lds_bytes(logN1, logLines), s, P, B.grids,
-                           B.scratch, B.fft_tw, C.first, logN, C.scratch_off, logN1, logLines);
+    blocks = ntr * (int)((int64_t(1) << logN) >> (c.logL + c.logLines));
+    lds = fft_lds_bytes(c.logL, c.logLines);
+    return true;
+}
+
+static void launch_fft_large(const PlanDev& P, const FftClass& K, hipStream_t s)
+{
+    for (int pass = 0; pass < 3; ++pass) {
+        FftPass F;
+        int blocks = 0;
+        size_t lds = 0;
+        if (!fft_pass(K, P.nch, pass, F, blocks, lds)) continue;
+        if (pass < 2) hipLaunchKernelGGL(k_fft_col, dim3(blocks), dim3(256), lds, s, P, F);
+        else hipLaunchKernelGGL(k_fft_row, dim3(blocks), dim3(256), lds, s, P, F);
     }
 }
 
@@ -1529,56 +1757,255 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
         return hipGetLastError();
     }
     mark(marks, 0, s);
-    hipLaunchKernelGGL(k_gather, dim3(cdiv64(P.n, 256)), dim3(256), 0, s, io.c, io.c_slot, P.perm_r,
-                       io.scale_by_points ? P.rs : nullptr, P.n, B.cs);
+    hipLaunchKernelGGL(k_gather, dim3(cdiv64(P.n, 256)), dim3(256), 0, s, P, io.c, io.c_slot,
+                       io.scale_by_points ? 1 : 0);
     mark(marks, 1, s);
     if (S.n_litems > 0) {
-        hipLaunchKernelGGL(k_lmom, dim3(S.n_litems), dim3(64), 0, s, P, B.cs, B.lpart);
-        hipLaunchKernelGGL(k_lmom_reduce, dim3(cdiv64((int64_t)S.n_l * (P.L + 1), 256)), dim3(256), 0, s, P,
-                           B.lpart, B.lmom);
+        hipLaunchKernelGGL(k_lmom, dim3(S.n_litems), dim3(64), 0, s, P);
+        hipLaunchKernelGGL(k_lmom_reduce, dim3(cdiv64((int64_t)S.n_l * (P.L + 1), 256)), dim3(256), 0, s, P);
     }
     mark(marks, 2, s);
-    dispatch_channels(P.nch, [&](auto k) { launch_spread<decltype(k)::value>(P, S, B, s); });
+    dispatch_channels(P.nch, [&](auto k) { launch_spread<decltype(k)::value>(P, S, s); });
     mark(marks, 3, s);
-    if (B.grid_cells > 0)
-    {
+    if (P.grid_cells > 0) {
         if (P.fp32)
-            hipLaunchKernelGGL(k_spread_reduce<float2>, dim3(cdiv64(B.grid_cells * P.nch, 256)), dim3(256), 0, s, P,
-                               B.part, B.grids, B.grid_cells);
+            hipLaunchKernelGGL(k_spread_reduce<float2>, dim3(cdiv64(P.grid_cells * P.nch, 256)), dim3(256), 0, s, P);
         else
-            hipLaunchKernelGGL(k_spread_reduce<double2>, dim3(cdiv64(B.grid_cells * P.nch, 256)), dim3(256), 0, s, P,
-                               B.part, B.grids, B.grid_cells);
+            hipLaunchKernelGGL(k_spread_reduce<double2>, dim3(cdiv64(P.grid_cells * P.nch, 256)), dim3(256), 0, s, P);
     }
     mark(marks, 4, s);
-    SmallFfts small{};
-    int small_wg = 0, small_log = 0;
-    for (int q = 0; q < ncls; ++q) {
-        const FftClass& C = cls[q];
-        if (C.log2n > 12 || small.n == 8) continue;
-        small.log2n[small.n] = C.log2n;
-        small.first[small.n] = C.first;
-        small.wg0[small.n] = small_wg;
-        small_wg += C.count * P.nch;
-        small_log = C.log2n > small_log ? C.log2n : small_log;
-        ++small.n;
-    }
-    small.wg0[small.n] = small_wg;
-    if (small_wg > 0)
-        hipLaunchKernelGGL(k_fft_small, dim3(small_wg), dim3(256), sizeof(double2) << small_log, s, P, B.grids, small);
-    for (int q = 0; q < ncls; ++q) {
-        const FftClass& C = cls[q];
-        if (C.log2n > 12) launch_fft_large(P, B, C, s);
-    }
+    if (P.small.n > 0 && P.small.wg0[P.small.n] > 0)
+        hipLaunchKernelGGL(k_fft_small, dim3(P.small.wg0[P.small.n]), dim3(256),
+                           sizeof(double2) << P.small.max_log2n, s, P);
+    for (int q = 0; q < ncls; ++q)
+        if (cls[q].log2n > 12) launch_fft_large(P, cls[q], s);
     mark(marks, 5, s);
     if (P.n_d > 0) {
-        hipLaunchKernelGGL(k_fill_zero, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, B.gd, (int64_t)P.m);
-        hipLaunchKernelGGL(k_direct_blocks, dim3(P.n_d), dim3(kDirectThreads), 0, s, P, B.cs, B.gd);
+        hipLaunchKernelGGL(k_fill_zero, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, P.gd, (int64_t)P.m);
+        hipLaunchKernelGGL(k_direct_blocks, dim3(P.n_d), dim3(kDirectThreads), 0, s, P);
     }
     mark(marks, 6, s);
-    dispatch_channels(P.nch, [&](auto k) { launch_rows_asy<decltype(k)::value>(P, B, s); });
+    dispatch_channels(P.nch, [&](auto k) { launch_rows_asy<decltype(k)::value>(P, s); });
     mark(marks, 7, s);
-    launch_rows_local(P, B, io, s);
+    launch_rows_local(P, io, s);
     mark(marks, 8, s);
+    return hipGetLastError();
+}
+
+void small_fft_table(PlanDev& P, const FftClass* cls, int ncls)
+{
+    SmallFfts& F = P.small;
+    F = SmallFfts{};
+    int wg = 0;
+    for (int q = 0; q < ncls; ++q) {
+        const FftClass& C = cls[q];
+        if (C.log2n > 12 || F.n == 8) continue;
+        F.log2n[F.n] = C.log2n;
+        F.first[F.n] = C.first;
+        F.wg0[F.n] = wg;
+        wg += C.count * P.nch;
+        F.max_log2n = C.log2n > F.max_log2n ? C.log2n : F.max_log2n;
+        ++F.n;
+    }
+    F.wg0[F.n] = wg;
+}
+
+// ---------------------------------------------------------------------------
+// Batches: the launch list.  Kinds in execution order; a launch's variant is
+// its channel count (spreading, grid rows) or local-row mode.
+// ---------------------------------------------------------------------------
+enum BatchKind : int32_t {
+    kZeroOut, kGather, kLmom, kLmomReduce, kSpreadMfma, kSpreadVec, kSpreadReduce, kFftSmall,
+    kFftPass0, kFftPass1, kFftPass2, kZeroGd, kDirect, kRowsAsy, kRowsLocal
+};
+
+void build_batch_schedule(const BatchTransform* tr, int count, const int* order, BatchSchedule& out)
+{
+    out = BatchSchedule{};
+    std::vector<WorkSeg> segs;
+    std::vector<FftSeg> fsegs;
+    // one launch of `kind` over the transforms accepted by `take`, which gives
+    // a transform's workgroups (0: none) and may raise the launch's LDS bytes
+    auto add = [&](int32_t kind, int32_t variant, int32_t fp32, int32_t threads, auto&& take) {
+        BatchLaunch L{};
+        L.kind = kind; L.variant = variant; L.fp32 = fp32; L.threads = threads;
+        L.seg0 = (int32_t)segs.size();
+        int64_t g = 0;
+        for (int q = 0; q < count; ++q) {
+            const int t = order[q];
+            size_t lds = 0;
+            const int64_t wg = take(tr[t], lds);
+            if (wg <= 0) continue;
+            segs.push_back(WorkSeg{t, (int32_t)g});
+            g += wg;
+            if (lds > L.lds) L.lds = lds;
+        }
+        L.nseg = (int32_t)segs.size() - L.seg0;
+        L.blocks = (int32_t)g;
+        if (L.nseg > 0) out.launches.push_back(L);
+    };
+    auto live = [](const PlanDev& P) { return P.n > 0 && P.m > 0; };
+    add(kZeroOut, 0, 0, 256, [&](const BatchTransform& T, size_t&) -> int64_t {
+        return (T.P->n == 0 && T.P->m > 0) ? cdiv64(T.P->m, 256) : 0;
+    });
+    add(kGather, 0, 0, 256, [&](const BatchTransform& T, size_t&) -> int64_t {
+        return live(*T.P) ? cdiv64(T.P->n, 256) : 0;
+    });
+    add(kLmom, 0, 0, 64, [&](const BatchTransform& T, size_t&) -> int64_t {
+        return live(*T.P) ? T.S->n_litems : 0;
+    });
+    add(kLmomReduce, 0, 0, 256, [&](const BatchTransform& T, size_t&) -> int64_t {
+        return live(*T.P) && T.S->n_litems > 0 ? cdiv64((int64_t)T.S->n_l * (T.P->L + 1), 256) : 0;
+    });
+    // the channel counts and precisions present
+    std::vector<std::pair<int, int>> variants;
+    for (int t = 0; t < count; ++t) {
+        const std::pair<int, int> v{tr[t].P->nch, tr[t].P->fp32};
+        if (live(*tr[t].P) && std::find(variants.begin(), variants.end(), v) == variants.end()) variants.push_back(v);
+    }
+    std::sort(variants.begin(), variants.end());
+    for (const auto& v : variants) {
+        const int nch = v.first, fp32 = v.second;
+        auto same = [&](const PlanDev& P) { return live(P) && P.nch == nch && P.fp32 == fp32; };
+        if (nch <= 16)
+            add(kSpreadMfma, nch, fp32, 256, [&](const BatchTransform& T, size_t& lds) -> int64_t {
+                if (!same(*T.P) || T.S->n_adense <= 0) return 0;
+                dispatch_channels(nch, [&](auto k) { lds = SpreadMfma<decltype(k)::value>::lds_bytes; });
+                return T.S->n_adense;
+            });
+        add(kSpreadVec, nch, fp32, 256, [&](const BatchTransform& T, size_t& lds) -> int64_t {
+            if (!same(*T.P)) return 0;
+            lds = fp32 ? spread_lds_bytes<float>(T.P->w) : spread_lds_bytes<double>(T.P->w);
+            return T.S->n_aitems - T.S->n_adense;
+        });
+    }
+    for (int fp32 = 0; fp32 <= 1; ++fp32)
+        add(kSpreadReduce, 0, fp32, 256, [&](const BatchTransform& T, size_t&) -> int64_t {
+            return live(*T.P) && T.P->fp32 == fp32 ? cdiv64(T.P->grid_cells * T.P->nch, 256) : 0;
+        });
+    add(kFftSmall, 0, 0, 256, [&](const BatchTransform& T, size_t& lds) -> int64_t {
+        const SmallFfts& F = T.P->small;
+        if (!live(*T.P) || F.n == 0) return 0;
+        lds = sizeof(double2) << F.max_log2n;
+        return F.wg0[F.n];
+    });
+    for (int pass = 0; pass < 3; ++pass) {
+        BatchLaunch L{};
+        L.kind = kFftPass0 + pass;
+        L.threads = 256;
+        L.seg0 = (int32_t)fsegs.size();
+        int64_t g = 0;
+        for (int q = 0; q < count; ++q) {
+            const int t = order[q];
+            if (!live(*tr[t].P)) continue;
+            for (int c = 0; c < tr[t].ncls; ++c) {
+                const FftClass& K = tr[t].cls[c];
+                if (K.log2n <= 12) continue;
+                FftSeg f{};
+                int blocks = 0;
+                size_t lds = 0;
+                if (!fft_pass(K, tr[t].P->nch, pass, f.F, blocks, lds) || blocks <= 0) continue;
+                f.t = t;
+                f.g0 = (int32_t)g;
+                fsegs.push_back(f);
+                g += blocks;
+                if (lds > L.lds) L.lds = lds;
+            }
+        }
+        L.nseg = (int32_t)fsegs.size() - L.seg0;
+        L.blocks = (int32_t)g;
+        if (L.nseg > 0) out.launches.push_back(L);
+    }
+    add(kZeroGd, 0, 0, 256, [&](const BatchTransform& T, size_t&) -> int64_t {
+        return live(*T.P) && T.P->n_d > 0 ? cdiv64(T.P->m, 256) : 0;
+    });
+    add(kDirect, 0, 0, kDirectThreads, [&](const BatchTransform& T, size_t&) -> int64_t {
+        return live(*T.P) ? T.P->n_d : 0;
+    });
+    std::vector<int> chans;
+    for (const auto& v : variants)
+        if (std::find(chans.begin(), chans.end(), v.first) == chans.end()) chans.push_back(v.first);
+    for (int nch : chans)
+        add(kRowsAsy, nch, 0, 256, [&](const BatchTransform& T, size_t&) -> int64_t {
+            return live(*T.P) && T.P->nch == nch ? cdiv64(T.P->m, 256) : 0;
+        });
+    // local rows: orders 0 and 1, then the general mode at 256 and at 64 lanes
+    for (int mode = 0; mode < 4; ++mode) {
+        const int bs = mode == 3 ? 64 : 256;
+        add(kRowsLocal, mode < 2 ? mode : 2, 0, bs, [&](const BatchTransform& T, size_t& lds) -> int64_t {
+            const int nu = T.P->nu;
+            if (!live(*T.P)) return 0;
+            if (mode < 2 ? nu != mode : (nu <= 1 || rows_local_block(nu) != bs)) return 0;
+            lds = rows_local_lds(nu, bs);
+            return cdiv64(T.P->m, bs);
+        });
+    }
+    // the device tables: PlanDev[count], WorkSeg[], FftSeg[] (each 256-byte aligned)
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    out.segs_off = align(sizeof(PlanDev) * (size_t)count);
+    out.fsegs_off = out.segs_off + align(sizeof(WorkSeg) * segs.size());
+    out.table.assign(out.fsegs_off + sizeof(FftSeg) * fsegs.size(), 0);
+    for (int t = 0; t < count; ++t) std::memcpy(out.table.data() + sizeof(PlanDev) * t, tr[t].P, sizeof(PlanDev));
+    if (!segs.empty()) std::memcpy(out.table.data() + out.segs_off, segs.data(), sizeof(WorkSeg) * segs.size());
+    if (!fsegs.empty()) std::memcpy(out.table.data() + out.fsegs_off, fsegs.data(), sizeof(FftSeg) * fsegs.size());
+}
+
+hipError_t launch_execute_many(const BatchSchedule& S, const void* table_dev, void* const* c_table,
+                               void* const* g_table, hipStream_t s)
+{
+    const char* base = (const char*)table_dev;
+    const PlanDev* plans = (const PlanDev*)base;
+    const WorkSeg* segs = (const WorkSeg*)(base + S.segs_off);
+    const FftSeg* fsegs = (const FftSeg*)(base + S.fsegs_off);
+    const double* const* cin = (const double* const*)c_table;
+    double* const* gout = (double* const*)g_table;
+    for (const BatchLaunch& L : S.launches) {
+        const dim3 grid(L.blocks), block(L.threads);
+        const WorkSeg* sg = segs + L.seg0;
+        const FftSeg* fs = fsegs + L.seg0;
+        switch (L.kind) {
+        case kZeroOut: hipLaunchKernelGGL(k_zero_output_many, grid, block, 0, s, plans, sg, L.nseg, gout); break;
+        case kGather: hipLaunchKernelGGL(k_gather_many, grid, block, 0, s, plans, sg, L.nseg, cin); break;
+        case kLmom: hipLaunchKernelGGL(k_lmom_many, grid, block, 0, s, plans, sg, L.nseg); break;
+        case kLmomReduce: hipLaunchKernelGGL(k_lmom_reduce_many, grid, block, 0, s, plans, sg, L.nseg); break;
+        case kSpreadMfma:
+            dispatch_channels(L.variant, [&](auto k) {
+                constexpr int NCH = decltype(k)::value;
+                if constexpr (NCH <= 16)
+                    hipLaunchKernelGGL((k_spread_mfma_many<NCH>), grid, block, L.lds, s, plans, sg, L.nseg);
+            });
+            break;
+        case kSpreadVec:
+            dispatch_channels(L.variant, [&](auto k) {
+                constexpr int NCH = decltype(k)::value;
+                if (L.fp32) hipLaunchKernelGGL((k_spread_many<NCH, float>), grid, block, L.lds, s, plans, sg, L.nseg);
+                else hipLaunchKernelGGL((k_spread_many<NCH, double>), grid, block, L.lds, s, plans, sg, L.nseg);
+            });
+            break;
+        case kSpreadReduce:
+            if (L.fp32) hipLaunchKernelGGL(k_spread_reduce_many<float2>, grid, block, 0, s, plans, sg, L.nseg);
+            else hipLaunchKernelGGL(k_spread_reduce_many<double2>, grid, block, 0, s, plans, sg, L.nseg);
+            break;
+        case kFftSmall: hipLaunchKernelGGL(k_fft_small_many, grid, block, L.lds, s, plans, sg, L.nseg); break;
+        case kFftPass0:
+        case kFftPass1: hipLaunchKernelGGL(k_fft_col_many, grid, block, L.lds, s, plans, fs, L.nseg); break;
+        case kFftPass2: hipLaunchKernelGGL(k_fft_row_many, grid, block, L.lds, s, plans, fs, L.nseg); break;
+        case kZeroGd: hipLaunchKernelGGL(k_zero_gd_many, grid, block, 0, s, plans, sg, L.nseg); break;
+        case kDirect: hipLaunchKernelGGL(k_direct_blocks_many, grid, block, 0, s, plans, sg, L.nseg); break;
+        case kRowsAsy:
+            dispatch_channels(L.variant, [&](auto k) {
+                hipLaunchKernelGGL((k_rows_asy_many<decltype(k)::value>), grid, block, 0, s, plans, sg, L.nseg);
+            });
+            break;
+        case kRowsLocal:
+            if (L.variant == 0) hipLaunchKernelGGL(k_rows_local_many<0>, grid, block, L.lds, s, plans, sg, L.nseg, gout);
+            else if (L.variant == 1)
+                hipLaunchKernelGGL(k_rows_local_many<1>, grid, block, L.lds, s, plans, sg, L.nseg, gout);
+            else hipLaunchKernelGGL(k_rows_local_many<2>, grid, block, L.lds, s, plans, sg, L.nseg, gout);
+            break;
+        default: return hipErrorInvalidValue;
+        }
+    }
     return hipGetLastError();
 }
 

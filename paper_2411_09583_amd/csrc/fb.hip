@@ -22,7 +22,14 @@
 // frequencies r):
 //   U_l(r_k)  = sum_j beta_jl J_l(j_{l,j} r_k)
 //   u(r_k, theta_s) = Re sum_l U_l(r_k) e^{i l theta_s}                  (t-point FFT per radius)
-// Real and imaginary parts of the complex weights are separate transforms.
+// Real and imaginary parts of the complex weights are separate transforms,
+// two per order |l| = a in each direction:
+//  - f is real, so F_{-a} = conj(F_a) and a_{j,-a} = (-1)^a conj(a_{j,a}):
+//    the analysis transforms (re, im) of F_a alone;
+//  - only the real part of the synthesis is kept, and
+//    Re(U_a e^{i a theta} + U_{-a} e^{-i a theta}) = Re(V_a e^{i a theta}) with
+//    V_a = U_a + conj(U_{-a}) = sum_j (beta_{j,a} + (-1)^a conj(beta_{j,-a})) J_a(j_{a,j} r),
+//    one complex sum of order a (V_0 = U_0).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -37,10 +44,9 @@
 namespace nuht {
 
 // One radius per workgroup: the t real samples f(r_k, .) in LDS, the FFT
-// (e^{+}), then for |l| <= L the weights wr_k r_k F_l(r_k),
-// F_l = (1 / t) conj(X[l mod t]) (f real), written as four weight vectors
-// per order |l|: C[(4 |l| + q) m + k], q = 0 (re, +l), 1 (im, +l), 2 (re, -l),
-// 3 (im, -l).
+// (e^{+}), then for 0 <= l <= L the weights wr_k r_k F_l(r_k),
+// F_l = (1 / t) conj(X[l]) (f real), written as two weight vectors per order:
+// C[(2 l + q) m + k], q = 0 (re), 1 (im).
 __global__ __launch_bounds__(256) void k_fb_angular_fwd(const double* __restrict__ f, int64_t m, int logt, int L,
                                                         const double* __restrict__ r, const double* __restrict__ wr,
                                                         double* __restrict__ C)
@@ -55,18 +61,15 @@ __global__ __launch_bounds__(256) void k_fb_angular_fwd(const double* __restrict
     __syncthreads();
     const double scale = wr[k] * r[k] / t;
     for (int l = threadIdx.x; l <= L; l += blockDim.x) {
-        const double2 xp = sm[l];              // X[l]:  F_l  = scale conj(X[l])
-        const double2 xm = sm[(t - l) & (t - 1)];  // X[-l]: F_-l = scale conj(X[-l])
-        C[(4 * (int64_t)l + 0) * m + k] = scale * xp.x;
-        C[(4 * (int64_t)l + 1) * m + k] = -scale * xp.y;
-        C[(4 * (int64_t)l + 2) * m + k] = scale * xm.x;
-        C[(4 * (int64_t)l + 3) * m + k] = -scale * xm.y;
+        const double2 xp = sm[l];              // X[l]: F_l = scale conj(X[l])
+        C[(2 * (int64_t)l + 0) * m + k] = scale * xp.x;
+        C[(2 * (int64_t)l + 1) * m + k] = -scale * xp.y;
     }
 }
 
 // alpha[(l + L) J + j] (complex) from the transform outputs
-// G[(4 |l| + q) J + j] and the factors nrm[|l| J + j] = 2 / J_{l+1}(j_{l,j})^2;
-// order -l carries (-1)^l.
+// G[(2 |l| + q) J + j] and the factors nrm[|l| J + j] = 2 / J_{l+1}(j_{l,j})^2;
+// order -l is (-1)^l times the conjugate of order l.
 __global__ void k_fb_scale(const double* __restrict__ G, const double* __restrict__ nrm, int L, int64_t J,
                            double2* __restrict__ alpha)
 {
@@ -76,10 +79,10 @@ __global__ void k_fb_scale(const double* __restrict__ G, const double* __restric
     const int li = (int)(e / J);
     const int64_t j = e - (int64_t)li * J;
     const int l = li - L, a = l < 0 ? -l : l;
-    const int q = l < 0 ? 2 : 0;
     const double sg = (l < 0 && (a & 1)) ? -1.0 : 1.0;
     const double s = sg * nrm[(int64_t)a * J + j];
-    alpha[e] = make_double2(s * G[(4 * (int64_t)a + q) * J + j], s * G[(4 * (int64_t)a + q + 1) * J + j]);
+    const double im = G[(2 * (int64_t)a + 1) * J + j];
+    alpha[e] = make_double2(s * G[2 * (int64_t)a * J + j], l < 0 ? -s * im : s * im);
 }
 
 // beta = alpha / (kappa^2 - j_{|l|,j}^2).
@@ -98,25 +101,29 @@ __global__ void k_fb_helmholtz(const double2* __restrict__ alpha, const double* 
     beta[e] = make_double2(v.x * d, v.y * d);
 }
 
-// The synthesis weights: B[(4 |l| + q) J + j] = (-1)^l (re, im) of
-// beta[(l + L) J + j] for order -l, unchanged for order l.
+// The synthesis weights of order a = 0 .. L: B[(2 a + q) J + j] = (re, im) of
+// beta_{j,a} + (-1)^a conj(beta_{j,-a}) (beta_{j,0} for a = 0), from
+// beta[(l + L) J + j].
 __global__ void k_fb_split(const double2* __restrict__ beta, int L, int64_t J, double* __restrict__ Bw)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)(2 * L + 1) * J;
+    const int64_t total = (int64_t)(L + 1) * J;
     if (e >= total) return;
-    const int li = (int)(e / J);
-    const int64_t j = e - (int64_t)li * J;
-    const int l = li - L, a = l < 0 ? -l : l;
-    const int q = l < 0 ? 2 : 0;
-    const double sg = (l < 0 && (a & 1)) ? -1.0 : 1.0;
-    const double2 v = beta[e];
-    Bw[(4 * (int64_t)a + q) * J + j] = sg * v.x;
-    Bw[(4 * (int64_t)a + q + 1) * J + j] = sg * v.y;
+    const int a = (int)(e / J);
+    const int64_t j = e - (int64_t)a * J;
+    double2 v = beta[(int64_t)(L + a) * J + j];
+    if (a > 0) {
+        const double2 w = beta[(int64_t)(L - a) * J + j];
+        const double sg = (a & 1) ? -1.0 : 1.0;
+        v.x += sg * w.x;
+        v.y -= sg * w.y;
+    }
+    Bw[2 * (int64_t)a * J + j] = v.x;
+    Bw[(2 * (int64_t)a + 1) * J + j] = v.y;
 }
 
-// One radius per workgroup: the spectrum S[l mod t] = U_l(r_k) for |l| <= L
-// (zero elsewhere) from U[(4 |l| + q) m + k], the FFT (e^{+}), and
+// One radius per workgroup: the spectrum S[a] = V_a(r_k) for 0 <= a <= L
+// (zero elsewhere) from U[(2 a + q) m + k], the FFT (e^{+}), and
 // u(r_k, theta_s) = Re X[s].
 __global__ __launch_bounds__(256) void k_fb_angular_inv(const double* __restrict__ U, int64_t m, int logt, int L,
                                                         double* __restrict__ u)
@@ -126,15 +133,8 @@ __global__ __launch_bounds__(256) void k_fb_angular_inv(const double* __restrict
     const int64_t k = blockIdx.x;
     for (int s = threadIdx.x; s < t; s += blockDim.x) sm[s] = make_double2(0.0, 0.0);
     __syncthreads();
-    for (int l = threadIdx.x; l <= L; l += blockDim.x) {
-        const double pr = U[(4 * (int64_t)l + 0) * m + k], pi = U[(4 * (int64_t)l + 1) * m + k];
-        if (l == 0) {
-            sm[0] = make_double2(pr, pi);
-        } else {
-            sm[l] = make_double2(pr, pi);
-            sm[t - l] = make_double2(U[(4 * (int64_t)l + 2) * m + k], U[(4 * (int64_t)l + 3) * m + k]);
-        }
-    }
+    for (int l = threadIdx.x; l <= L; l += blockDim.x)
+        sm[l] = make_double2(U[(2 * (int64_t)l + 0) * m + k], U[(2 * (int64_t)l + 1) * m + k]);
     __syncthreads();
     lds_fft(sm, t, logt, 1, 0, 1);
     __syncthreads();
@@ -143,77 +143,73 @@ __global__ __launch_bounds__(256) void k_fb_angular_inv(const double* __restrict
 }
 
 // The direct method: the same radial sums with every J_l(j_{l,j} r_k)
-// evaluated in place (full FP64 accuracy), shared by the four weight vectors
+// evaluated in place (full FP64 accuracy), shared by the two weight vectors
 // of order l.  A workgroup of 16 waves owns 64 outputs of one order (one per
 // lane); its waves take every 16th term of the sum, and the 16 partial sums
 // are added in wave order.  Lanes past the end evaluate J at x = 0 and write
 // nothing.
 constexpr int kFbWaves = 16;
 
-// Analysis: G[(4 l + q) J + j] = sum_k C[(4 l + q) m + k] J_l(z_{l,j} r_k).
+// Analysis: G[(2 l + q) J + j] = sum_k C[(2 l + q) m + k] J_l(z_{l,j} r_k).
 __global__ __launch_bounds__(1024) void k_fb_direct_fwd(const double* __restrict__ C, const double* __restrict__ r,
                                                         int64_t m, const double* __restrict__ zeros, int64_t J,
                                                         const double* __restrict__ phi, double* __restrict__ G)
 {
-    __shared__ double red[kFbWaves][4][64];
+    __shared__ double red[kFbWaves][2][64];
     const int l = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t j = (int64_t)blockIdx.x * 64 + lane;
     const double z = j < J ? zeros[(int64_t)l * J + j] : 0.0;
     const double ph = phi[2 * l], pl = phi[2 * l + 1];
-    const double* c0 = C + 4 * (int64_t)l * m;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const double* c0 = C + 2 * (int64_t)l * m;
+    double a0 = 0.0, a1 = 0.0;
     for (int64_t k = w; k < m; k += kFbWaves) {
         const double rk = r[k];
         const double x = z * rk;
         const double v = besselj_core(l, ph, pl, x, __builtin_fma(z, rk, -x));
         a0 = __builtin_fma(c0[k], v, a0);
         a1 = __builtin_fma(c0[m + k], v, a1);
-        a2 = __builtin_fma(c0[2 * m + k], v, a2);
-        a3 = __builtin_fma(c0[3 * m + k], v, a3);
     }
-    red[w][0][lane] = a0; red[w][1][lane] = a1; red[w][2][lane] = a2; red[w][3][lane] = a3;
+    red[w][0][lane] = a0; red[w][1][lane] = a1;
     __syncthreads();
-    if (threadIdx.x < 256) {
+    if (threadIdx.x < 128) {
         const int q = threadIdx.x >> 6;
         double s = 0.0;
         #pragma unroll
         for (int v = 0; v < kFbWaves; ++v) s += red[v][q][lane];
-        if (j < J) G[(4 * (int64_t)l + q) * J + j] = s;
+        if (j < J) G[(2 * (int64_t)l + q) * J + j] = s;
     }
 }
 
-// Synthesis: U[(4 l + q) m + k] = sum_j B[(4 l + q) J + j] J_l(z_{l,j} r_k).
+// Synthesis: U[(2 l + q) m + k] = sum_j B[(2 l + q) J + j] J_l(z_{l,j} r_k).
 __global__ __launch_bounds__(1024) void k_fb_direct_inv(const double* __restrict__ B, const double* __restrict__ r,
                                                         int64_t m, const double* __restrict__ zeros, int64_t J,
                                                         const double* __restrict__ phi, double* __restrict__ U)
 {
-    __shared__ double red[kFbWaves][4][64];
+    __shared__ double red[kFbWaves][2][64];
     const int l = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t k = (int64_t)blockIdx.x * 64 + lane;
     const double rk = k < m ? r[k] : 0.0;
     const double ph = phi[2 * l], pl = phi[2 * l + 1];
-    const double* b0 = B + 4 * (int64_t)l * J;
+    const double* b0 = B + 2 * (int64_t)l * J;
     const double* zl = zeros + (int64_t)l * J;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double a0 = 0.0, a1 = 0.0;
     for (int64_t j = w; j < J; j += kFbWaves) {
         const double z = zl[j];
         const double x = z * rk;
         const double v = besselj_core(l, ph, pl, x, __builtin_fma(z, rk, -x));
         a0 = __builtin_fma(b0[j], v, a0);
         a1 = __builtin_fma(b0[J + j], v, a1);
-        a2 = __builtin_fma(b0[2 * J + j], v, a2);
-        a3 = __builtin_fma(b0[3 * J + j], v, a3);
     }
-    red[w][0][lane] = a0; red[w][1][lane] = a1; red[w][2][lane] = a2; red[w][3][lane] = a3;
+    red[w][0][lane] = a0; red[w][1][lane] = a1;
     __syncthreads();
-    if (threadIdx.x < 256) {
+    if (threadIdx.x < 128) {
         const int q = threadIdx.x >> 6;
         double s = 0.0;
         #pragma unroll
         for (int v = 0; v < kFbWaves; ++v) s += red[v][q][lane];
-        if (k < m) U[(4 * (int64_t)l + q) * m + k] = s;
+        if (k < m) U[(2 * (int64_t)l + q) * m + k] = s;
     }
 }
 
@@ -240,9 +236,9 @@ struct nuht_fb_s {
     double* wr = nullptr;       // m radial weights
     double* zeros = nullptr;    // (L + 1) x J
     double* nrm = nullptr;      // (L + 1) x J: 2 / J_{l+1}(j_{l,j})^2
-    double* C = nullptr;        // 4 (L + 1) x m analysis weights
-    double* G = nullptr;        // 4 (L + 1) x J analysis outputs / synthesis weights
-    double* U = nullptr;        // 4 (L + 1) x m synthesis outputs
+    double* C = nullptr;        // 2 (L + 1) x m analysis weights
+    double* G = nullptr;        // 2 (L + 1) x J analysis outputs / synthesis weights
+    double* U = nullptr;        // 2 (L + 1) x m synthesis outputs
     double2* A = nullptr;       // (2L + 1) x J coefficients (Helmholtz temporaries)
     double2* Bc = nullptr;      // (2L + 1) x J
     double* phi = nullptr;      // 2 (L + 1): phase offsets of orders 0 .. L (direct method)
@@ -275,16 +271,16 @@ bool fb_alloc(T*& p, int64_t count)
     return true;
 }
 
-// Four executions of a batch (q = 0 .. 3): input rows in[(4 l + q) nin], output
-// rows out[(4 l + q) nout].
+// Two executions of a batch (q = 0, 1: real and imaginary parts): input rows
+// in[(2 l + q) nin], output rows out[(2 l + q) nout].
 int fb_run(nuht_batch_t b, int L, const double* in, int64_t nin, double* out, int64_t nout, hipStream_t s)
 {
     std::vector<const double*> cp(L + 1);
     std::vector<double*> gp(L + 1);
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 2; ++q) {
         for (int l = 0; l <= L; ++l) {
-            cp[l] = in + (4 * (int64_t)l + q) * nin;
-            gp[l] = out + (4 * (int64_t)l + q) * nout;
+            cp[l] = in + (2 * (int64_t)l + q) * nin;
+            gp[l] = out + (2 * (int64_t)l + q) * nout;
         }
         int rc = nuht_execute_many(b, cp.data(), gp.data(), s);
         if (rc != NUHT_OK) return rc;
@@ -312,7 +308,7 @@ int fb_analysis(nuht_fb_s* fb, const double* f, double2* alpha, hipStream_t s)
 
 int fb_synthesis(nuht_fb_s* fb, const double2* beta, double* u, hipStream_t s)
 {
-    const int64_t total = (int64_t)(2 * fb->L + 1) * fb->J;
+    const int64_t total = (int64_t)(fb->L + 1) * fb->J;
     hipLaunchKernelGGL(k_fb_split, dim3(blocks_for(total)), dim3(256), 0, s, beta, fb->L, fb->J, fb->G);
     if (hipGetLastError() != hipSuccess) return NUHT_EHIP;
     if (fb->method == NUHT_FB_DIRECT) {
@@ -349,7 +345,7 @@ int nuht_fb_plan(nuht_fb_t* out, int32_t L, int64_t m, const double* r_dev, cons
     while ((int64_t(1) << fb->logt) < t) ++fb->logt;
     const int64_t nl = L + 1, no = 2 * (int64_t)L + 1;
     if (!fb_alloc(fb->r, m) || !fb_alloc(fb->wr, m) || !fb_alloc(fb->zeros, nl * J) || !fb_alloc(fb->nrm, nl * J) ||
-        !fb_alloc(fb->C, 4 * nl * m) || !fb_alloc(fb->G, 4 * nl * J) || !fb_alloc(fb->U, 4 * nl * m) ||
+        !fb_alloc(fb->C, 2 * nl * m) || !fb_alloc(fb->G, 2 * nl * J) || !fb_alloc(fb->U, 2 * nl * m) ||
         !fb_alloc(fb->A, no * J) || !fb_alloc(fb->Bc, no * J) || !fb_alloc(fb->phi, 2 * nl)) {
         fb_free(fb);
         return NUHT_ENOMEM;

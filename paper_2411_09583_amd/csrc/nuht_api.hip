@@ -781,6 +781,10 @@ static int part_finish(PendingPart& pp, const HostStage* h, bool* again)
     B.fft_tw = fft_twiddles_device();
     if (!B.fft_tw) return NUHT_ENOMEM;
     P.es_poly = B.es_poly;
+    P.cs = B.cs; P.lpart = B.lpart; P.lmom = B.lmom; P.part = B.part; P.grids = B.grids;
+    P.scratch = B.scratch; P.gd = B.gd; P.ga = B.ga; P.fft_tw = B.fft_tw;
+    P.grid_cells = B.grid_cells;
+    small_fft_table(P, Pt.cls.data(), (int)Pt.cls.size());
     Pt.built = true;
     return NUHT_OK;
 }
@@ -1305,14 +1309,16 @@ constexpr int kBatchStreams = 4;
 
 struct nuht_batch_s {
     std::vector<nuht_plan_t> plans;
-    std::vector<int> stream_of;          // stream index of each transform
+    std::vector<int> stream_of;          // planning stream of each transform
     std::vector<int> order;              // transforms by decreasing n + m
     hipStream_t aux[kBatchStreams] = {};
     hipStream_t cap = nullptr;           // capture and replay stream
-    hipEvent_t ev_in = nullptr, ev_out = nullptr, fork = nullptr, join[kBatchStreams] = {};
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
     DevBuf b_ptrs;                       // device tables of input and output pointers
     void** c_table = nullptr;
     void** g_table = nullptr;
+    BatchSchedule sched;                 // the batched launches, stage by stage
+    DevBuf b_table;                      // their device tables (PlanDev array, segments)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<nuht_opts> class_opts;   // tuned options per size class (when tuned)
@@ -1327,14 +1333,13 @@ static void free_batch(nuht_batch_t b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (nuht_plan_t p : b->plans) free_plan(p);   // stream-ordered frees on the batch's streams
     dev_free(b->b_ptrs);
+    dev_free(b->b_table);
     for (hipStream_t st : b->aux) if (st) (void)hipStreamSynchronize(st);
     if (b->cap) (void)hipStreamSynchronize(b->cap);
     for (hipStream_t st : b->aux) if (st) (void)hipStreamDestroy(st);
     if (b->cap) (void)hipStreamDestroy(b->cap);
-    for (hipEvent_t e : b->join) if (e) (void)hipEventDestroy(e);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
-    if (b->fork) (void)hipEventDestroy(b->fork);
     delete b;
 }
 
@@ -1370,12 +1375,10 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
     auto hip_ok = [](hipError_t e) { if (e != hipSuccess) { (void)hipGetLastError(); return false; } return true; };
     for (int k = 0; k < kBatchStreams; ++k) {
         if (!hip_ok(hipStreamCreateWithFlags(&b->aux[k], hipStreamNonBlocking))) return fail(NUHT_EHIP);
-        if (!hip_ok(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming))) return fail(NUHT_EHIP);
     }
     if (!hip_ok(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking))) return fail(NUHT_EHIP);
     if (!hip_ok(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming))) return fail(NUHT_EHIP);
     if (!hip_ok(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming))) return fail(NUHT_EHIP);
-    if (!hip_ok(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming))) return fail(NUHT_EHIP);
     // the inputs are ready once the caller's stream reaches this point
     if (!hip_ok(hipEventRecord(b->ev_in, s))) return fail(NUHT_EHIP);
     for (int k = 0; k < kBatchStreams; ++k)
@@ -1470,6 +1473,22 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
         slab.add(b->g_table, (size_t)count);
         if (slab.commit(b->b_ptrs, b->cap) != NUHT_OK) return fail(NUHT_ENOMEM);
     }
+    // the launch list and its device tables
+    {
+        std::vector<BatchTransform> tr(count);
+        for (int i = 0; i < count; ++i) {
+            const Partition* Pt = current_forward(b->plans[i]);
+            if (!Pt) return fail(NUHT_EINVAL);
+            tr[i] = BatchTransform{&Pt->P, &Pt->sum, Pt->cls.data(), (int)Pt->cls.size()};
+        }
+        build_batch_schedule(tr.data(), count, b->order.data(), b->sched);
+        if (!b->sched.launches.empty()) {
+            if (dev_alloc(b->b_table, b->sched.table.size(), b->cap) != NUHT_OK) return fail(NUHT_ENOMEM);
+            if (!hip_ok(hipMemcpyAsync(b->b_table.p, b->sched.table.data(), b->sched.table.size(),
+                                       hipMemcpyHostToDevice, b->cap)))
+                return fail(NUHT_EHIP);
+        }
+    }
     for (int k = 0; k < kBatchStreams; ++k)
         if (!hip_ok(hipStreamSynchronize(b->aux[k]))) return fail(NUHT_EHIP);
     if (!hip_ok(hipStreamSynchronize(b->cap))) return fail(NUHT_EHIP);
@@ -1477,31 +1496,16 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
     return NUHT_OK;
 }
 
-// Captures every transform's execution into one graph: the transforms run on
-// the batch's streams (largest first, balanced), forked from and joined back
-// into the capture stream; inputs and outputs come from the pointer tables.
+// Captures the batch's execution into one graph: the batched launches, stage
+// by stage, on the capture stream alone (each launch covers every transform
+// with work in its stage); inputs and outputs come from the pointer tables.
 static int capture_batch(nuht_batch_t b)
 {
     if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipGetLastError();
         return NUHT_EHIP;
     }
-    hipError_t e = hipEventRecord(b->fork, b->cap);
-    for (int k = 0; k < kBatchStreams && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->aux[k], b->fork, 0);
-    for (size_t q = 0; q < b->order.size() && e == hipSuccess; ++q) {
-        int t = b->order[q];
-        const Partition* Pt = current_forward(b->plans[t]);
-        if (!Pt) { e = hipErrorInvalidValue; break; }
-        IoArgs io;
-        io.c_slot = (const double* const*)(b->c_table + t);
-        io.g_slot = (double* const*)(b->g_table + t);
-        e = launch_execute(Pt->P, Pt->sum, Pt->B, Pt->cls.data(), (int)Pt->cls.size(), io, b->aux[b->stream_of[t]],
-                           nullptr);
-    }
-    for (int k = 0; k < kBatchStreams && e == hipSuccess; ++k) {
-        e = hipEventRecord(b->join[k], b->aux[k]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->join[k], 0);
-    }
+    hipError_t e = launch_execute_many(b->sched, b->b_table.p, b->c_table, b->g_table, b->cap);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -1531,6 +1535,7 @@ int nuht_execute_many(nuht_batch_t b, const double* const* c_dev, double* const*
         if (b->plans[i]->m > 0 && !g_dev[i]) return NUHT_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
+    if (b->sched.launches.empty()) return NUHT_OK;   // every transform has m = 0
     if (!b->exec) NUHT_TRY(capture_batch(b));
     HIP_TRY(hipEventRecord(b->ev_in, s));
     HIP_TRY(hipStreamWaitEvent(b->cap, b->ev_in, 0));

@@ -91,7 +91,19 @@ struct Summary {
     int32_t grid_error;     // an asymptotic block needs an FFT larger than 2^kMaxFftLog2
 };
 
-// Everything the execution kernels need for one transform (device copy).
+// FFT-path grids of at most 4096 points, every size class in one launch:
+// workgroup g belongs to class c when wg0[c] <= g < wg0[c + 1], and within it
+// to the FFT-list slot (g - wg0[c]) / nch of the class and channel
+// (g - wg0[c]) % nch.
+struct SmallFfts {
+    int32_t n;                 // classes
+    int32_t log2n[8], first[8];
+    int32_t wg0[9];            // wg0[n]: workgroups of the launch
+    int32_t max_log2n;         // largest class (its transform sets the launch's LDS)
+};
+
+// Everything the execution kernels need for one transform (passed by value to
+// the kernels of a single transform; kept in a device array for a batch).
 struct PlanDev {
     int32_t n, m, nu, M, L, w;       // sizes, |order|, terms, local rank, ES width
     int32_t nch, sign;               // channels (2M padded to a kernel instance); (-1)^nu for negative orders, else 1
@@ -119,6 +131,24 @@ struct PlanDev {
     const int64_t* gslot;            // first grid slot of each asymptotic block; gslot[n_a] = all slots
     const double* es_poly;           // ES kernel pieces, w x (kEsDeg + 1) monomial coefficients
     int32_t n_nodes, n_l, n_a, n_d, n_litems, n_aitems, n_adense, pad1;
+    // execution buffers of the partition
+    double* cs;                      // weights gathered into sorted point order (n)
+    double* lpart;                   // local-moment partial sums (items x (L + 1))
+    double* lmom;                    // local moments (local blocks x (L + 1))
+    double2* part;                   // spread partial subgrids
+    double2* grids;                  // spread grids (direct-sum path) and FFT buffers (FFT path)
+    double2* scratch;                // second buffer of the multi-pass FFTs
+    double* gd;                      // per-row direct-block sums (m)
+    double* ga;                      // per-row asymptotic sums (m)
+    const double2* fft_tw;           // FFT twiddles (8192 entries)
+    int64_t grid_cells;              // grid slots (without the channel factor)
+    SmallFfts small;                 // the FFT size classes up to 4096 points
+};
+
+// One transform's share of a batched launch: workgroups g0 .. (next g0) - 1
+// of the launch work on transform t, as its workgroups 0, 1, ...
+struct WorkSeg {
+    int32_t t, g0;
 };
 
 }  // namespace nuht

@@ -1,6 +1,8 @@
 // nuht_launch.h -- device tables of a partition and the host-side launchers.
 #pragma once
 
+#include <vector>
+
 #include "nuht_internal.h"
 
 namespace nuht {
@@ -79,6 +81,38 @@ struct IoArgs {
 // transposed geometry).
 hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers& B, const FftClass* cls, int ncls,
                           const IoArgs& io, hipStream_t s, hipEvent_t* marks);
+// Fills P.small, the FFT size classes of at most 4096 points, from the
+// partition's classes.
+void small_fft_table(PlanDev& P, const FftClass* cls, int ncls);
+
+// A batch of transforms executed stage by stage: every stage (and kernel
+// variant: channel count, precision, local-row mode) is one launch over all
+// transforms with work in it, each workgroup finding its transform in a table
+// of segments.  Built once on the host; its device tables (the transforms'
+// PlanDev array, the segments) are one block of bytes, `table`, that the
+// caller copies to device memory and passes to launch_execute_many.
+struct BatchTransform {
+    const PlanDev* P;
+    const Summary* S;
+    const FftClass* cls;
+    int ncls;
+};
+struct BatchLaunch {
+    int32_t kind, variant, fp32;
+    int32_t seg0, nseg;          // segments seg0 .. seg0 + nseg - 1 (WorkSeg or FFT segments by kind)
+    int32_t blocks, threads;
+    size_t lds;
+};
+struct BatchSchedule {
+    std::vector<BatchLaunch> launches;
+    std::vector<char> table;     // PlanDev[count], then the WorkSeg segments, then the FFT segments
+    size_t segs_off = 0, fsegs_off = 0;
+};
+// `order`: the transforms in the order their workgroups are laid out in every
+// launch (largest first).
+void build_batch_schedule(const BatchTransform* tr, int count, const int* order, BatchSchedule& out);
+hipError_t launch_execute_many(const BatchSchedule& S, const void* table_dev, void* const* c_table,
+                               void* const* g_table, hipStream_t s);
 // x[i] = v
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
 // -(2 nu + 1) pi / 4 modulo 2 pi as a double-double (the Hankel phase offset).
