@@ -71,9 +71,9 @@ typedef struct nuht_plan_s *nuht_plan_t;
  *                     instead of an FFT and interpolation (0 -> built-in default,
  *                     negative -> always use the FFT path).
  *   spread_chunk      points per spreading work item, 64 .. 16384 (0 -> 1024).
- *   tune              nonzero: nuht_plan_many picks min_size, dft_max and
- *                     spread_chunk per size class with nuht_tune (the fields
- *                     above are then starting values).
+ *   tune              nonzero: nuht_plan_many picks min_size, dft_max,
+ *                     spread_chunk and split_candidates per size class with
+ *                     nuht_tune (the fields above are then starting values).
  *   vector_spread     nonzero: every spreading work item runs on the vector
  *                     units.  By default, in FP64 with an ES width of at most
  *                     16 and at most 16 channels, items whose points reach the
@@ -97,6 +97,15 @@ typedef struct nuht_plan_s *nuht_plan_t;
  *                     normwise maximum error is 2.4 eps with margin 2,
  *                     0.98 eps with 4 and 0.54 eps with 8.  eps / margin must
  *                     stay >= 1e-15 (>= 1e-7 with FP32 spreading).
+ *   tune_cache        NULL, or the path of a tuning cache file (JSON, one
+ *                     entry per tuned key: size class floor(log10(n + m)),
+ *                     channel count, local rank, ES width, precision, exact
+ *                     split).  nuht_tune and the tuning of nuht_plan_many read
+ *                     a key's options from it instead of timing candidates,
+ *                     and write the options they time; the file is created
+ *                     when missing and rewritten through a temporary file
+ *                     (path + ".tmp") and a rename.  The string is read during
+ *                     the call only (the plan keeps its own copy).
  */
 typedef struct {
     int64_t min_size;
@@ -109,6 +118,7 @@ typedef struct {
     int32_t vector_spread;
     int32_t local_rank;
     double  margin;
+    const char *tune_cache;
 } nuht_opts;
 
 /*
@@ -132,6 +142,8 @@ typedef struct {
     int32_t dft_max, spread_chunk;
     int32_t spread_items;             /* spreading work items of the asymptotic blocks */
     int32_t dense_items;              /* of which spread on the matrix cores */
+    int32_t split_candidates;         /* candidate rows of SplitIndices in use (-1: exact) */
+    int32_t pad;
 } nuht_info;
 
 /*
@@ -231,14 +243,17 @@ int nuht_plan_set_order(nuht_plan_t plan, int nu, void *stream);
 int nuht_plan_info(nuht_plan_t plan, nuht_info *info);
 
 /*
- * nuht_tune -- pick the spreading work-item size, min_size and dft_max for
- * this plan's geometry and order: coordinate descent over a few candidates of
- * each, every candidate planned on the plan's sorted geometry and timed over
- * `reps` executes (0 -> 3) with HIP events on `stream` (c_dev: n weights, or
- * NULL for all ones; the timing does not depend on the values).  The best
- * options are written to *best (and their time per execute to *best_ms, may
- * be NULL) and adopted by the plan, whose partitions are rebuilt.
- * Synchronises `stream` once per candidate.
+ * nuht_tune -- pick the spreading work-item size, min_size, dft_max and (unless
+ * the plan uses the exact split) split_candidates for this plan's geometry and
+ * order: coordinate descent over a few candidates of each, every candidate
+ * planned on the plan's sorted geometry and timed over `reps` executes
+ * (0 -> 3) with HIP events on `stream` (c_dev: n weights, or NULL for all
+ * ones; the timing does not depend on the values).  With a tuning cache (the
+ * plan's opts.tune_cache) holding the plan's key, its options are taken
+ * without timing; otherwise the timed result is added to the cache.  The best
+ * options are written to *best (tune_cache NULL; their time per execute to
+ * *best_ms, may be NULL) and adopted by the plan, whose partitions are
+ * rebuilt.  Synchronises `stream` once per candidate.
  */
 int nuht_tune(nuht_plan_t plan, const double *c_dev, int reps, nuht_opts *best, double *best_ms,
               void *stream);

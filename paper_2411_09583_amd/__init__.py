@@ -38,7 +38,8 @@ class NuhtOpts(ctypes.Structure):
     _fields_ = [("min_size", ctypes.c_int64), ("M_override", ctypes.c_int32),
                 ("split_candidates", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("dft_max", ctypes.c_int32), ("spread_chunk", ctypes.c_int32), ("tune", ctypes.c_int32),
-                ("vector_spread", ctypes.c_int32), ("local_rank", ctypes.c_int32), ("margin", ctypes.c_double)]
+                ("vector_spread", ctypes.c_int32), ("local_rank", ctypes.c_int32), ("margin", ctypes.c_double),
+                ("tune_cache", ctypes.c_char_p)]
 
 
 class NuhtInfo(ctypes.Structure):
@@ -53,7 +54,8 @@ class NuhtInfo(ctypes.Structure):
                 ("fft_points", ctypes.c_int64), ("dft_row_cells", ctypes.c_int64),
                 ("fft_row_members", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("min_size", ctypes.c_int64), ("dft_max", ctypes.c_int32), ("spread_chunk", ctypes.c_int32),
-                ("spread_items", ctypes.c_int32), ("dense_items", ctypes.c_int32)]
+                ("spread_items", ctypes.c_int32), ("dense_items", ctypes.c_int32),
+                ("split_candidates", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 # every symbol include/nuht.h declares
@@ -148,7 +150,8 @@ class Plan:
 
     def __init__(self, r, omega, nu: int, eps: float, *, min_size: int = 0, M: int = 0,
                  split_candidates: int = 0, precision: int = NUHT_FP64, dft_max: int = 0,
-                 spread_chunk: int = 0, vector_spread: bool = False, local_rank: int = 0, margin: float = 0.0):
+                 spread_chunk: int = 0, vector_spread: bool = False, local_rank: int = 0, margin: float = 0.0,
+                 tune_cache: str = None):
         lib = load_library()
         r = _dev_f64(r, "r")
         omega = _dev_f64(omega, "omega")
@@ -156,7 +159,8 @@ class Plan:
         self.m = omega.numel()
         self.device = r.device
         opts = NuhtOpts(min_size, M, split_candidates, precision, dft_max, spread_chunk, 0,
-                        1 if vector_spread else 0, int(local_rank), float(margin))
+                        1 if vector_spread else 0, int(local_rank), float(margin),
+                        os.fsencode(tune_cache) if tune_cache else None)
         h = ctypes.c_void_p()
         _check(lib.nuht_plan(ctypes.byref(h), int(nu), float(eps), self.n, _ptr(r), self.m, _ptr(omega),
                              ctypes.byref(opts), _stream()))
@@ -219,7 +223,7 @@ class Plan:
         ms = ctypes.c_double()
         cp = _ptr(_dev_f64(c, "c")) if c is not None else ctypes.c_void_p(0)
         _check(load_library().nuht_tune(self._h, cp, int(reps), ctypes.byref(best), ctypes.byref(ms), _stream()))
-        out = {f: getattr(best, f) for f, _ in NuhtOpts._fields_}
+        out = {f: getattr(best, f) for f, _ in NuhtOpts._fields_ if f != "tune_cache"}
         out["ms"] = ms.value
         return out
 
@@ -259,7 +263,7 @@ class Batch:
     and executed as one captured graph (nuht_plan_many / nuht_execute_many)."""
 
     def __init__(self, rs, omegas, nus, eps: float, *, tune: bool = False, min_size: int = 0,
-                 dft_max: int = 0, spread_chunk: int = 0, margin: float = 0.0):
+                 dft_max: int = 0, spread_chunk: int = 0, margin: float = 0.0, tune_cache: str = None):
         lib = load_library()
         if not (len(rs) == len(omegas) == len(nus)):
             raise ValueError("rs, omegas and nus must have the same length")
@@ -274,7 +278,8 @@ class Batch:
         m_a = (ctypes.c_int64 * k)(*self.m)
         r_a = (ctypes.c_void_p * k)(*[_ptr(r).value for r, _ in self._keep])
         w_a = (ctypes.c_void_p * k)(*[_ptr(w).value for _, w in self._keep])
-        opts = NuhtOpts(min_size, 0, 0, NUHT_FP64, dft_max, spread_chunk, 1 if tune else 0, 0, 0, float(margin))
+        opts = NuhtOpts(min_size, 0, 0, NUHT_FP64, dft_max, spread_chunk, 1 if tune else 0, 0, 0, float(margin),
+                        os.fsencode(tune_cache) if tune_cache else None)
         h = ctypes.c_void_p()
         _check(lib.nuht_plan_many(ctypes.byref(h), k, nu_a, float(eps), n_a, r_a, m_a, w_a, ctypes.byref(opts),
                                   _stream()))

@@ -2,10 +2,13 @@
 // kernel set-up, plan construction (sort, staircase, Alg. 1) and the C ABI.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "nuht.h"
@@ -514,7 +517,8 @@ using namespace nuht;
 struct nuht_plan_s {
     int nu_req = 0;
     double eps = 0.0;
-    nuht_opts opts{};
+    nuht_opts opts{};            // opts.tune_cache is not kept (see cache_path)
+    std::string cache_path;      // the tuning cache file, empty for none
     int64_t n = 0, m = 0;
     // Planning (sort, partitions) runs on `ps`, a stream of the library's, so
     // it overlaps work already queued on the caller's streams; ev_use marks
@@ -974,6 +978,8 @@ static int plan_create(nuht_plan_t* out, int nu, double eps, int64_t n, const do
     nuht_plan_s* p = new (std::nothrow) nuht_plan_s();
     if (!p) return NUHT_ENOMEM;
     p->nu_req = nu; p->eps = eps; p->opts = o; p->n = n; p->m = m;
+    if (o.tune_cache) p->cache_path = o.tune_cache;
+    p->opts.tune_cache = nullptr;
     p->ps = s;
     int64_t tot = n + m;
     auto fail = [&](int code) { free_plan(p); return code; };
@@ -1208,10 +1214,11 @@ int nuht_plan_set_order(nuht_plan_t p, int nu, void* stream)
 
 // ---------------------------------------------------------------------------
 // Autotuning: the spreading work-item size (points per item), the direct-block
-// threshold min_size and the direct-sum/FFT threshold dft_max, by coordinate
-// descent over a few candidates each, every candidate planned on the plan's
-// own sorted geometry and timed over `reps` executes (after one warm-up) with
-// HIP events on `s`.
+// threshold min_size, the direct-sum/FFT threshold dft_max and the number of
+// candidate rows of SplitIndices (unless the exact split was asked for), by
+// coordinate descent over a few candidates each, every candidate planned on
+// the plan's own sorted geometry and timed over `reps` executes (after one
+// warm-up) with HIP events on `s`.
 // ---------------------------------------------------------------------------
 static int tune_plan(nuht_plan_t p, const double* c_dev, int reps, nuht_opts* best, double* best_ms, hipStream_t s)
 {
@@ -1231,6 +1238,7 @@ static int tune_plan(nuht_plan_t p, const double* c_dev, int reps, nuht_opts* be
     if (cur.spread_chunk == 0) cur.spread_chunk = kSpreadChunk;
     if (cur.min_size == 0) cur.min_size = 1024;
     if (cur.dft_max == 0) cur.dft_max = 48;
+    if (cur.split_candidates == 0) cur.split_candidates = 16;
     int rc = NUHT_OK;
     auto time_opts = [&](const nuht_opts& o, double* ms) -> int {
         p->opts = o;
@@ -1256,13 +1264,16 @@ static int tune_plan(nuht_plan_t p, const double* c_dev, int reps, nuht_opts* be
     const int chunks[] = {512, 1024, 2048, 4096};
     const int64_t sizes[] = {256, 1024, 4096, 16384};
     const int dfts[] = {24, 48, 96};
-    for (int param = 0; param < 3 && rc == NUHT_OK; ++param) {
-        int ncand = param == 0 ? 4 : (param == 1 ? 4 : 3);
+    const int splits[] = {8, 16, 32};
+    const int nparam = cur.split_candidates == -1 ? 3 : 4;
+    for (int param = 0; param < nparam && rc == NUHT_OK; ++param) {
+        int ncand = (param == 0 || param == 1) ? 4 : 3;
         for (int q = 0; q < ncand && rc == NUHT_OK; ++q) {
             nuht_opts o = cur;
             if (param == 0) { if (o.spread_chunk == chunks[q]) continue; o.spread_chunk = chunks[q]; }
             if (param == 1) { if (o.min_size == sizes[q]) continue; o.min_size = sizes[q]; }
             if (param == 2) { if (o.dft_max == dfts[q]) continue; o.dft_max = dfts[q]; }
+            if (param == 3) { if (o.split_candidates == splits[q]) continue; o.split_candidates = splits[q]; }
             double ms = 0.0;
             rc = time_opts(o, &ms);
             if (rc == NUHT_OK && ms < cur_ms) { cur = o; cur_ms = ms; }
@@ -1280,19 +1291,152 @@ static int tune_plan(nuht_plan_t p, const double* c_dev, int reps, nuht_opts* be
     return NUHT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// The tuning cache: a JSON file of tuned options by key, so that a size class
+// is timed once (the paper builds its parameter tables once, when the library
+// is installed) and later plans and batches read the result.  The key is what
+// the tuned options depend on: the size class floor(log10(n + m)), the channel
+// count, the local rank, the ES width, the spreading precision and whether
+// the split is exact.  One entry per line:
+//   {"key": "...", "spread_chunk": 1024, "min_size": 1024, "dft_max": 48,
+//    "split_candidates": 16, "ms": 0.93}
+// The file is read whole and rewritten through a temporary file and a rename;
+// an unreadable file counts as empty, and a failed write only loses the entry.
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+    std::string key;
+    int64_t spread_chunk = 0, min_size = 0, dft_max = 0, split_candidates = 0;
+    double ms = 0.0;
+};
+
+static std::mutex& cache_mutex()
+{
+    static std::mutex mu;
+    return mu;
+}
+
+static std::string tune_key(const nuht_plan_s* p, const PlanDev& P)
+{
+    int cls = 0;
+    for (int64_t t = p->n + p->m; t >= 10 && cls < 9; t /= 10) ++cls;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "v1 class %d nch %d L %d w %d fp32 %d exact %d", cls, P.nch, P.L, P.w, P.fp32,
+                  p->opts.split_candidates == -1 ? 1 : 0);
+    return buf;
+}
+
+static std::vector<TuneEntry> cache_read(const std::string& path)
+{
+    std::vector<TuneEntry> out;
+    FILE* f = std::fopen(path.c_str(), "rb");
+    if (!f) return out;
+    std::string text;
+    char chunk[4096];
+    size_t got;
+    while ((got = std::fread(chunk, 1, sizeof chunk, f)) > 0) text.append(chunk, got);
+    std::fclose(f);
+    const std::string tag = "{\"key\": \"";
+    for (size_t at = text.find(tag); at != std::string::npos; at = text.find(tag, at + 1)) {
+        const size_t k0 = at + tag.size(), k1 = text.find('"', k0), end = text.find('}', k0);
+        if (k1 == std::string::npos || end == std::string::npos || k1 > end) break;
+        TuneEntry e;
+        e.key = text.substr(k0, k1 - k0);
+        auto num = [&](const char* name, double* v) {
+            const std::string pat = std::string("\"") + name + "\": ";
+            const size_t q = text.find(pat, k1);
+            if (q == std::string::npos || q > end) return false;
+            *v = std::strtod(text.c_str() + q + pat.size(), nullptr);
+            return true;
+        };
+        double a, b, c, d, ms;
+        if (num("spread_chunk", &a) && num("min_size", &b) && num("dft_max", &c) && num("split_candidates", &d) &&
+            num("ms", &ms)) {
+            e.spread_chunk = (int64_t)a; e.min_size = (int64_t)b; e.dft_max = (int64_t)c;
+            e.split_candidates = (int64_t)d; e.ms = ms;
+            out.push_back(e);
+        }
+    }
+    return out;
+}
+
+static bool cache_lookup(const std::string& path, const std::string& key, TuneEntry& hit)
+{
+    std::lock_guard<std::mutex> lock(cache_mutex());
+    for (const TuneEntry& e : cache_read(path))
+        if (e.key == key) { hit = e; return true; }
+    return false;
+}
+
+static void cache_store(const std::string& path, const TuneEntry& entry)
+{
+    std::lock_guard<std::mutex> lock(cache_mutex());
+    std::vector<TuneEntry> all = cache_read(path);
+    bool found = false;
+    for (TuneEntry& e : all)
+        if (e.key == entry.key) { e = entry; found = true; }
+    if (!found) all.push_back(entry);
+    std::sort(all.begin(), all.end(), [](const TuneEntry& x, const TuneEntry& y) { return x.key < y.key; });
+    const std::string tmp = path + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return;
+    std::fprintf(f, "{\"format\": \"libnuht tuning cache 1\", \"entries\": [\n");
+    for (size_t i = 0; i < all.size(); ++i) {
+        const TuneEntry& e = all[i];
+        std::fprintf(f, "{\"key\": \"%s\", \"spread_chunk\": %lld, \"min_size\": %lld, \"dft_max\": %lld, "
+                        "\"split_candidates\": %lld, \"ms\": %.6g}%s\n",
+                     e.key.c_str(), (long long)e.spread_chunk, (long long)e.min_size, (long long)e.dft_max,
+                     (long long)e.split_candidates, e.ms, i + 1 < all.size() ? "," : "");
+    }
+    std::fprintf(f, "]}\n");
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) (void)std::remove(tmp.c_str());
+}
+
+// The tuned options of plan p: from the cache when it holds p's key, else by
+// tune_plan (then stored).  The options that are not tuned come from p.
+static int tune_cached(nuht_plan_t p, const double* c_dev, int reps, nuht_opts* best, double* best_ms, hipStream_t s)
+{
+    const Partition* cur = current_forward(p);
+    if (!cur) return NUHT_EINVAL;
+    const std::string key = tune_key(p, cur->P);
+    nuht_opts o = p->opts;
+    TuneEntry e;
+    if (!p->cache_path.empty() && cache_lookup(p->cache_path, key, e)) {
+        o.spread_chunk = (int32_t)e.spread_chunk;
+        o.min_size = e.min_size;
+        o.dft_max = (int32_t)e.dft_max;
+        if (o.split_candidates != -1) o.split_candidates = (int32_t)e.split_candidates;
+        o.tune = 0;
+        *best = o;
+        if (best_ms) *best_ms = e.ms;
+        return NUHT_OK;
+    }
+    double ms = 0.0;
+    NUHT_TRY(tune_plan(p, c_dev, reps, &o, &ms, s));
+    if (!p->cache_path.empty()) {
+        e.key = key;
+        e.spread_chunk = o.spread_chunk; e.min_size = o.min_size; e.dft_max = o.dft_max;
+        e.split_candidates = o.split_candidates; e.ms = ms;
+        cache_store(p->cache_path, e);
+    }
+    *best = o;
+    if (best_ms) *best_ms = ms;
+    return NUHT_OK;
+}
+
 int nuht_tune(nuht_plan_t p, const double* c_dev, int reps, nuht_opts* best, double* best_ms, void* stream)
 {
     if (!p || !best || !current_forward(p)) return NUHT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     nuht_opts o;
-    NUHT_TRY(tune_plan(p, c_dev, reps, &o, best_ms, s));
+    NUHT_TRY(tune_cached(p, c_dev, reps, &o, best_ms, s));
     // adopt the best options: the plan's partitions are rebuilt with them
     o.precision = p->opts.precision;
     o.M_override = p->opts.M_override;
-    o.split_candidates = p->opts.split_candidates;
     o.vector_spread = p->opts.vector_spread;
     o.local_rank = p->opts.local_rank;
     o.margin = p->opts.margin;
+    o.tune_cache = nullptr;
     p->opts = o;
     p->orders.clear();
     Partition* Pt = nullptr;
@@ -1405,7 +1549,9 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
     if (o.tune) {
         // one representative (the largest) per size class is tuned; its options
         // serve the whole class
-        b->class_opts.assign(10, o);
+        nuht_opts oc = o;
+        oc.tune_cache = nullptr;
+        b->class_opts.assign(10, oc);
         std::vector<int> rep(10, -1);
         for (int t : b->order) {
             int c = size_class(n[t] + m[t]);
@@ -1419,11 +1565,11 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
             int rc = get_partition(p, p->nu_req, false, st, &Pt);
             if (rc != NUHT_OK) return fail(rc);
             nuht_opts best;
-            rc = tune_plan(p, nullptr, 3, &best, nullptr, st);
+            rc = tune_cached(p, nullptr, 3, &best, nullptr, st);
             if (rc != NUHT_OK) return fail(rc);
             best.precision = o.precision; best.M_override = o.M_override;
-            best.split_candidates = o.split_candidates;
             best.vector_spread = o.vector_spread;
+            best.tune_cache = nullptr;
             best.local_rank = o.local_rank;
             best.margin = o.margin;
             b->class_opts[c] = best;
@@ -1588,6 +1734,8 @@ int nuht_plan_info(nuht_plan_t p, nuht_info* info)
     info->spread_chunk = P.spread_chunk;
     info->spread_items = S.n_aitems;
     info->dense_items = S.n_adense;
+    info->split_candidates = p->opts.split_candidates == -1 ? -1
+                             : (p->opts.split_candidates > 1 ? p->opts.split_candidates : 16);
     return NUHT_OK;
 }
 

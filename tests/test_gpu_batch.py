@@ -118,7 +118,8 @@ def test_tuned_batch_and_plan(nuht):
         idx = rng.choice(t["w"].size, min(48, t["w"].size), replace=False)
         ref = direct.dht(t["nu"], t["r"], t["c"], t["w"][idx])
         # the method-exact reference with the options the tuner chose
-        ref2 = method.nufht_reference_rows(t["nu"], 1e-12, t["r"], t["c"], t["w"], idx, min_size=inf["min_size"])
+        ref2 = method.nufht_reference_rows(t["nu"], 1e-12, t["r"], t["c"], t["w"], idx, min_size=inf["min_size"],
+                                           ncand=inf["split_candidates"])
         assert np.linalg.norm(g[idx] - ref2) / np.linalg.norm(ref2) <= 2e-13
         if abs(t["nu"]) <= 10:
             assert np.linalg.norm(g[idx] - ref) / np.linalg.norm(ref) <= TOL
@@ -132,4 +133,50 @@ def test_tuned_batch_and_plan(nuht):
     p.close()
     idx = rng.choice(w.size, 64, replace=False)
     ref = direct.dht(4, r, c, w[idx])
+    assert np.linalg.norm(g[idx] - ref) / np.linalg.norm(ref) <= TOL
+
+
+def test_tuning_cache(nuht, tmp_path):
+    """A tuned batch writes its options to the cache file (valid JSON, one
+    entry per tuned key); a second batch over the same transforms reads them
+    instead of timing candidates (same options, bit-identical outputs), and a
+    plan's tune() on a cached key returns the stored options and time."""
+    import json
+    path = str(tmp_path / "tune.json")
+    tr = workloads.batch(count=5, seed=15, lo=3.0, hi=4.2, nu_max=12)
+    args = ([dev(t["r"]) for t in tr], [dev(t["w"]) for t in tr], [t["nu"] for t in tr], 1e-12)
+    b1 = nuht.Batch(*args, tune=True, tune_cache=path)
+    g1 = [host(g) for g in b1.execute([dev(t["c"]) for t in tr])]
+    i1 = [b1.info(i) for i in range(len(tr))]
+    b1.close()
+    doc = json.load(open(path))
+    keys = [e["key"] for e in doc["entries"]]
+    assert keys and len(keys) == len(set(keys))
+    for e in doc["entries"]:
+        assert e["spread_chunk"] in (512, 1024, 2048, 4096) and e["split_candidates"] in (8, 16, 32)
+    b2 = nuht.Batch(*args, tune=True, tune_cache=path)
+    g2 = [host(g) for g in b2.execute([dev(t["c"]) for t in tr])]
+    i2 = [b2.info(i) for i in range(len(tr))]
+    b2.close()
+    assert json.load(open(path)) == doc                 # nothing re-timed, nothing rewritten
+    for a, b, x, y in zip(i1, i2, g1, g2):
+        assert (a["min_size"], a["dft_max"], a["spread_chunk"]) == (b["min_size"], b["dft_max"], b["spread_chunk"])
+        assert np.array_equal(x, y)
+    # a plan: the first tune() times and stores, the second reads
+    path2 = str(tmp_path / "tune_plan.json")
+    r, w, c = workloads.uniform(12000, 9000, 1.0, 1e4, seed=16)
+    p = nuht.Plan(dev(r), dev(w), 3, 1e-12, tune_cache=path2)
+    first = p.tune(dev(c))
+    p.close()
+    stored = json.load(open(path2))["entries"]
+    assert len(stored) == 1 and stored[0]["spread_chunk"] == first["spread_chunk"]
+    q = nuht.Plan(dev(r), dev(w), 3, 1e-12, tune_cache=path2)
+    second = q.tune(dev(c))
+    g = host(q.execute(dev(c)))
+    q.close()
+    for k in ("spread_chunk", "min_size", "dft_max", "split_candidates"):
+        assert second[k] == first[k], k
+    assert second["ms"] == stored[0]["ms"]
+    idx = np.random.default_rng(17).choice(w.size, 48, replace=False)
+    ref = direct.dht(3, r, c, w[idx])
     assert np.linalg.norm(g[idx] - ref) / np.linalg.norm(ref) <= TOL
