@@ -27,6 +27,15 @@
  * (Hankel: in the phase; the other branches: through J_n').
  *
  * Negative integer orders use J_{-n} = (-1)^n J_n.
+ *
+ * Half-integer orders nu = n + 1/2 (n >= 0; the radial Fourier transform in
+ * odd dimension d has nu = d/2 - 1) go through the spherical Bessel function,
+ * J_{n+1/2}(x) = sqrt(2x/pi) j_n(x) (DLMF 10.47.3), in long double:
+ *   x > n + 1         upward recurrence j_{k+1} = ((2k+1)/x) j_k - j_{k-1} from
+ *                     j_{-1} = cos x / x and j_0 = sin x / x (stable while k < x)
+ *   otherwise         Miller's backward recurrence with the same relation,
+ *                     normalised by sum_k (2k+1) j_k^2 = 1 (DLMF 10.60.11)
+ * and the low part of the argument through J_nu' = J_{nu-1} - (nu/x) J_nu.
  */
 #include <math.h>
 #include <stdint.h>
@@ -179,9 +188,66 @@ static double besselj_int(int nu, double xh, double xl)
     return ((-nu) & 1) ? -v : v;
 }
 
+/* J_{n+1/2}(xh + xl) for n >= 0, xh >= 0 (see the header). */
+static double besselj_half(int n, double xh, double xl)
+{
+    if (xh == 0.0 && xl == 0.0) return 0.0;
+    const long double x = (long double)xh;
+    const long double sx = sinl(x), cx = cosl(x);
+    long double jn, jnm1;                      /* j_n(x), j_{n-1}(x) */
+    if (x > (long double)n + 1.0L) {
+        long double jm = cx / x, j = sx / x;   /* j_{-1}, j_0 */
+        for (int k = 0; k < n; ++k) {
+            const long double jp = ((long double)(2 * k + 1) / x) * j - jm;
+            jm = j;
+            j = jp;
+        }
+        jn = j;
+        jnm1 = jm;
+    } else {
+        const int N = (int)((long double)n + x + 30.0L + 15.0L * cbrtl(x > 1.0L ? x : 1.0L));
+        long double yk1 = 0.0L, yk = 1e-300L, S = 0.0L, rn = 0.0L, rnm1 = 0.0L;
+        for (int k = N; k >= 0; --k) {
+            if (k == n) rn = yk;
+            if (k == n - 1) rnm1 = yk;
+            S += (long double)(2 * k + 1) * yk * yk;
+            if (k == 0) break;
+            const long double ykm1 = ((long double)(2 * k + 1) / x) * yk - yk1;
+            yk1 = yk;
+            yk = ykm1;
+            if (fabsl(yk) > 1e1000L) {
+                const long double f = 1e-1000L;
+                yk *= f; yk1 *= f; S *= f * f; rn *= f; rnm1 *= f;
+            }
+        }
+        const long double lam = sqrtl(S);
+        jn = rn / lam;
+        jnm1 = n == 0 ? cx / x : rnm1 / lam;
+    }
+    const long double amp = sqrtl(2.0L * x / 3.141592653589793238462643383279502884L);
+    const long double J = amp * jn;
+    const long double dJ = amp * (jnm1 - (((long double)n + 0.5L) / x) * jn);
+    return (double)(J + (long double)xl * dJ);
+}
+
+/* J_{nu2/2}: integer orders for even nu2, n + 1/2 (n = (nu2 - 1) / 2 >= 0) for odd nu2 >= 1. */
+static double besselj_twice(int nu2, double xh, double xl)
+{
+    if ((nu2 & 1) == 0) return besselj_int(nu2 / 2, xh, xl);
+    return besselj_half((nu2 - 1) / 2, xh, xl);
+}
+
 /* ======================================================================== */
 /* Exported entry points (called through ctypes).                           */
 /* ======================================================================== */
+
+/* out[i] = J_{nu2/2}(xh[i] + xl[i]): integer or half-integer (nu2 odd, >= 1) orders. */
+void orc_besselj_twice(int nu2, const double *xh, const double *xl, int64_t n, double *out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = besselj_twice(nu2, xh[i], xl ? xl[i] : 0.0);
+}
 
 /* out[i] = J_nu(xh[i] + xl[i]). */
 void orc_besselj(int nu, const double *xh, const double *xl, int64_t n, double *out)
@@ -218,8 +284,8 @@ double orc_hankel_coef(double nu, int k)
  * with exact double-double arguments and Neumaier-compensated summation.
  * Parallel over outputs; nthreads <= 0 uses the OpenMP default.
  */
-void orc_dht(int nu, int64_t n, const double *r, const double *c,
-             int64_t m, const double *w, double *g, int nthreads)
+void orc_dht_twice(int nu2, int64_t n, const double *r, const double *c,
+                   int64_t m, const double *w, double *g, int nthreads)
 {
     if (nthreads > 0) omp_set_num_threads(nthreads);
     #pragma omp parallel for schedule(dynamic, 4)
@@ -229,13 +295,20 @@ void orc_dht(int nu, int64_t n, const double *r, const double *c,
             if (c[k] == 0.0) continue;
             double xh, xl;
             two_prod(w[j], r[k], &xh, &xl);
-            double t = c[k] * besselj_int(nu, xh, xl);
+            double t = c[k] * besselj_twice(nu2, xh, xl);
             double s = sum + t;
             if (fabs(sum) >= fabs(t)) comp += (sum - s) + t; else comp += (t - s) + sum;
             sum = s;
         }
         g[j] = sum + comp;
     }
+}
+
+/* The same for integer orders. */
+void orc_dht(int nu, int64_t n, const double *r, const double *c,
+             int64_t m, const double *w, double *g, int nthreads)
+{
+    orc_dht_twice(2 * nu, n, r, c, m, w, g, nthreads);
 }
 
 /* Number of OpenMP threads a parallel region would use. */
@@ -276,19 +349,19 @@ void orc_exact_le(const double *w, const double *r, int64_t n, double z, int32_t
 }
 
 /*
- * M-term Hankel approximation of one matrix block, applied to a vector by
- * direct summation (the asymptotic block formula of Sec. 3.2, eq. asy-error,
- * written entry-wise):
+ * M-term Hankel approximation of one matrix block (integer or half-integer
+ * order nu), applied to a vector by direct summation (the asymptotic block
+ * formula of Sec. 3.2, eq. asy-error, written entry-wise):
  *   H_M(x) = sqrt(2/pi) sum_{l<M} (-1)^l [ a_{2l} x^{-2l-1/2} cos(x+phi)
  *                                        - a_{2l+1} x^{-2l-3/2} sin(x+phi) ],
  *   g[i] += sum_k c[k] H_M(w[i] r[k]),  x = w r formed exactly.
  */
-void orc_asy_block(int nu, int M, int64_t mb, const double *w, int64_t nb,
+void orc_asy_block(double nu, int M, int64_t mb, const double *w, int64_t nb,
                    const double *r, const double *c, double *g)
 {
     double a[64];
-    for (int k = 0; k < 2 * M && k < 64; ++k) a[k] = orc_hankel_coef((double)nu, k);
-    double phi = -fmod(2.0 * (double)nu + 1.0, 8.0) * ORC_PI / 4.0;
+    for (int k = 0; k < 2 * M && k < 64; ++k) a[k] = orc_hankel_coef(nu, k);
+    double phi = -fmod(2.0 * nu + 1.0, 8.0) * ORC_PI / 4.0;
     double cp = cos(phi), sp = sin(phi);
     #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < mb; ++i) {

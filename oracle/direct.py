@@ -5,6 +5,8 @@ TEST INFRASTRUCTURE ONLY (see :mod:`oracle`).
 g_j = sum_k c_k J_nu(w_j r_k)   (Sec. 1, eq. DHT; Sec. 2 writes it as g = A c
 with A(j,k) = J_nu(w_j r_k)).  The sum is evaluated entry by entry in C
 (``bessel.c``) with exact double-double arguments and compensated summation.
+Orders are integers or positive half-integers (nu = n + 1/2, the radial
+Fourier transform in odd dimensions).
 """
 import ctypes
 import os
@@ -29,6 +31,8 @@ def _load():
         build()
     lib = ctypes.CDLL(_LIB_PATH)
     lib.orc_besselj.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int64, _dp]
+    lib.orc_besselj_twice.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int64, _dp]
+    lib.orc_dht_twice.argtypes = [ctypes.c_int, ctypes.c_int64, _dp, _dp, ctypes.c_int64, _dp, _dp, ctypes.c_int]
     lib.orc_hankel_series.argtypes = [ctypes.c_double, _dp, ctypes.c_int64, ctypes.c_int, _dp]
     lib.orc_hankel_coef.argtypes = [ctypes.c_double, ctypes.c_int]
     lib.orc_hankel_coef.restype = ctypes.c_double
@@ -36,7 +40,7 @@ def _load():
     lib.orc_max_threads.restype = ctypes.c_int
     lib.orc_staircase.argtypes = [ctypes.c_int64, _dp, ctypes.c_int64, _dp, ctypes.c_double, _i64p]
     lib.orc_exact_le.argtypes = [_dp, _dp, ctypes.c_int64, ctypes.c_double, _i32p]
-    lib.orc_asy_block.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _dp,
+    lib.orc_asy_block.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int64, _dp,
                                   ctypes.c_int64, _dp, _dp, _dp]
     _lib = lib
     return lib
@@ -66,13 +70,25 @@ def two_prod(a, b):
     return hi, lo
 
 
-def besselj(nu: int, x, x_lo=None):
-    """J_nu(x + x_lo) for integer nu (any sign) and x >= 0, elementwise."""
+def twice_order(nu) -> int:
+    """2 nu for an integer order (any sign) or a positive half-integer order."""
+    t = 2.0 * float(nu)
+    if t != round(t):
+        raise ValueError(f"order {nu} is neither an integer nor a half-integer")
+    t = int(round(t))
+    if t % 2 == 1 and t < 1:
+        raise ValueError("negative half-integer orders are not supported")
+    return t
+
+
+def besselj(nu, x, x_lo=None):
+    """J_nu(x + x_lo) for integer nu (any sign) or half-integer nu > 0, x >= 0,
+    elementwise."""
     lib = _load()
     xh = _f64(np.atleast_1d(x))
     xl = _f64(np.zeros_like(xh) if x_lo is None else np.broadcast_to(x_lo, xh.shape))
     out = np.empty_like(xh)
-    lib.orc_besselj(int(nu), _ptr(xh), _ptr(xl), xh.size, _ptr(out))
+    lib.orc_besselj_twice(twice_order(nu), _ptr(xh), _ptr(xl), xh.size, _ptr(out))
     return out.reshape(np.shape(x)) if np.ndim(x) else out[0]
 
 
@@ -91,7 +107,7 @@ def hankel_coef(nu: float, k: int) -> float:
     return _load().orc_hankel_coef(float(nu), int(k))
 
 
-def dht(nu: int, r, c, w, nthreads: int = 0):
+def dht(nu, r, c, w, nthreads: int = 0):
     """O1: g_j = sum_k c_k J_nu(w_j r_k) by direct summation (Sec. 1, eq. DHT).
 
     r, c: the n points and their weights; w: the m frequencies.  Any order of
@@ -105,7 +121,7 @@ def dht(nu: int, r, c, w, nthreads: int = 0):
     w = _f64(w)
     g = np.zeros(w.shape[0], dtype=np.float64)
     if r.size and w.size:
-        lib.orc_dht(int(nu), r.size, _ptr(r), _ptr(c), w.size, _ptr(w), _ptr(g), int(nthreads))
+        lib.orc_dht_twice(twice_order(nu), r.size, _ptr(r), _ptr(c), w.size, _ptr(w), _ptr(g), int(nthreads))
     return g
 
 
@@ -134,7 +150,7 @@ def exact_le(w, r, z: float):
     return out.astype(bool)
 
 
-def asy_block_apply(nu: int, M: int, w_rows, r_cols, c_cols):
+def asy_block_apply(nu, M: int, w_rows, r_cols, c_cols):
     """sum_k c_k H_M(w_i r_k) for each row i, with H_M the M-term Hankel
     approximation of J_nu (Sec. 3.2, eq. asy-error), summed directly."""
     lib = _load()
@@ -143,6 +159,6 @@ def asy_block_apply(nu: int, M: int, w_rows, r_cols, c_cols):
     c_cols = _f64(c_cols)
     g = np.zeros(w_rows.size, dtype=np.float64)
     if w_rows.size and r_cols.size:
-        lib.orc_asy_block(int(nu), int(M), w_rows.size, _ptr(w_rows), r_cols.size,
+        lib.orc_asy_block(float(nu), int(M), w_rows.size, _ptr(w_rows), r_cols.size,
                           _ptr(r_cols), _ptr(c_cols), _ptr(g))
     return g

@@ -17,6 +17,10 @@ directly*, entry by entry, with no NUFFT:
   entry (``direct.asy_block_apply``);
 * direct block: J_nu itself (``direct.dht``).
 
+Half-integer orders nu = n + 1/2 take their parameters from
+``params.half_parameters`` and local blocks from ``half_local_block_apply``
+(J_{n+1/2}(x y) = sqrt(y) sqrt(2x/pi) j_n(x y), j_n's Chebyshev series in y).
+
 The difference O2 - O1 is therefore pure truncation error of the expansions,
 bounded entrywise by eps, so |O2_j - O1_j| <= eps * sum_k |c_k|.
 
@@ -65,6 +69,59 @@ def wimp_coefficients(nu: int, L: int, x: np.ndarray, x_lo: np.ndarray = None) -
     return C
 
 
+def spherical_jn(n: int, t: np.ndarray) -> np.ndarray:
+    """j_n(t) = sqrt(pi / (2 t)) J_{n+1/2}(t) (DLMF 10.47.3) for real t, with
+    the oracle's J, j_n(-t) = (-1)^n j_n(t) and j_n(0) = [n == 0]."""
+    t = np.asarray(t, dtype=np.float64)
+    a = np.abs(t)
+    out = np.where(a > 0, 0.0, 1.0 if n == 0 else 0.0)
+    pos = a > 0
+    if np.any(pos):
+        out[pos] = np.sqrt(np.pi / (2.0 * a[pos])) * direct.besselj(n + 0.5, a[pos])
+    return np.where(t < 0, (-1.0) ** n * out, out)
+
+
+def half_coefficients(n: int, L: int, x: np.ndarray) -> np.ndarray:
+    """beta_{e+2l}(x), l = 0..L (e = n mod 2): the Chebyshev coefficients of
+    y -> j_n(x y) on [-1, 1], by the discrete Chebyshev transform at Q
+    Chebyshev points (Q well above the degrees involved, so the aliased
+    coefficients are below the rounding level).  Shape (L+1, len(x))."""
+    x = np.atleast_1d(np.asarray(x, dtype=np.float64))
+    e = n % 2
+    kmax = 2 * L + e
+    Q = int(kmax + 2 * np.max(x, initial=0.0) + 64)
+    odd = 2 * np.arange(Q) + 1                            # theta_q = pi (2q + 1) / (2Q)
+    ks = np.arange(e, kmax + 1, 2)
+    F = spherical_jn(n, np.outer(x, np.cos(np.pi * odd / (2 * Q))))          # (len(x), Q)
+    # cos(k theta_q) with the integer k (2q + 1) reduced modulo 4Q first, so
+    # large k do not magnify the rounding of theta_q
+    C = np.cos(np.pi * (np.outer(odd, ks) % (4 * Q)) / (2 * Q))             # (Q, L+1)
+    beta = (F @ C) * (2.0 / Q)
+    beta[:, ks == 0] *= 0.5
+    return beta.T
+
+
+def half_local_block_apply(nu: float, L: int, z: float, w_rows, r_cols, c_cols) -> np.ndarray:
+    """One local block at the half-integer order nu = n + 1/2:
+        g_j += sqrt(2 x_j / pi) sum_l beta_{e+2l}(x_j) sum_k c_k sqrt(y_k) T_{e+2l}(y_k),
+    x_j = w_j R, y_k = r_k / R, from J_{n+1/2}(x y) = sqrt(y) sqrt(2x/pi) j_n(x y)."""
+    n = int(round(nu - 0.5))
+    w_rows = np.asarray(w_rows, dtype=np.float64)
+    r_cols = np.asarray(r_cols, dtype=np.float64)
+    c_cols = np.asarray(c_cols, dtype=np.float64)
+    R = float(r_cols[-1])
+    if R == 0.0:
+        wmax = float(w_rows[-1])
+        R = z / wmax if wmax > 0.0 else 1.0
+    y = r_cols / R
+    e = n % 2
+    T = chebyshev_t(2 * L + e, y)
+    t = T[e::2] @ (c_cols * np.sqrt(y))                   # moments, length L+1
+    x = w_rows * R
+    B = half_coefficients(n, L, x)                        # (L+1, rows)
+    return np.sqrt(2.0 * x / np.pi) * (t @ B)
+
+
 def local_block_apply(nu: int, L: int, z: float, w_rows, r_cols, c_cols) -> np.ndarray:
     """Rank-(L+1) Wimp product for one local block: C (T^T c)  (Sec. 3.1)."""
     w_rows = np.asarray(w_rows, dtype=np.float64)
@@ -83,16 +140,24 @@ def local_block_apply(nu: int, L: int, z: float, w_rows, r_cols, c_cols) -> np.n
     return t @ C
 
 
-def nufht_reference(nu: int, eps: float, r, c, w, min_size: int = 1024,
+def _order(nu):
+    """(sign, order used, local-block routine): negative integer orders through
+    J_{-nu} = (-1)^nu J_nu; half-integer orders with their own local form."""
+    if prm.is_half(nu):
+        return 1.0, float(nu), half_local_block_apply
+    nu = int(nu)
+    return (-1.0 if (nu < 0 and (-nu) % 2 == 1) else 1.0), abs(nu), local_block_apply
+
+
+def nufht_reference(nu, eps: float, r, c, w, min_size: int = 1024,
                     ncand: int = 16, M: int = None, return_blocks: bool = False):
     """Alg. 2 with every block's expansion summed directly.  Output follows the
     order of w."""
     r = np.asarray(r, dtype=np.float64)
     c = np.asarray(c, dtype=np.float64)
     w = np.asarray(w, dtype=np.float64)
-    sign = -1.0 if (nu < 0 and (-nu) % 2 == 1) else 1.0
-    anu = abs(nu)
-    M, z, L = prm.parameters(anu, eps, M)
+    sign, anu, local = _order(nu)
+    M, z, L = prm.any_parameters(anu, eps, M)
     pr = np.argsort(r, kind='stable')
     pw = np.argsort(w, kind='stable')
     rs, cs, ws = r[pr], c[pr], w[pw]
@@ -103,7 +168,7 @@ def nufht_reference(nu: int, eps: float, r, c, w, min_size: int = 1024,
         rows = slice(b.j0, b.j1 + 1)
         cols = slice(b.k0, b.k1 + 1)
         if b.kind == 'L':
-            gs[rows] += local_block_apply(anu, L, z, ws[rows], rs[cols], cs[cols])
+            gs[rows] += local(anu, L, z, ws[rows], rs[cols], cs[cols])
         elif b.kind == 'A':
             gs[rows] += direct.asy_block_apply(anu, M, ws[rows], rs[cols], cs[cols])
         else:
@@ -115,7 +180,7 @@ def nufht_reference(nu: int, eps: float, r, c, w, min_size: int = 1024,
     return g
 
 
-def nufht_reference_rows(nu: int, eps: float, r, c, w, rows, min_size: int = 1024,
+def nufht_reference_rows(nu, eps: float, r, c, w, rows, min_size: int = 1024,
                          ncand: int = 16, M: int = None):
     """O2 at selected outputs only: the same partition and expansions as
     :func:`nufht_reference`, summed for the outputs w[rows] (caller order).
@@ -124,9 +189,8 @@ def nufht_reference_rows(nu: int, eps: float, r, c, w, rows, min_size: int = 102
     c = np.asarray(c, dtype=np.float64)
     w = np.asarray(w, dtype=np.float64)
     rows = np.asarray(rows, dtype=np.int64)
-    sign = -1.0 if (nu < 0 and (-nu) % 2 == 1) else 1.0
-    anu = abs(nu)
-    M, z, L = prm.parameters(anu, eps, M)
+    sign, anu, local = _order(nu)
+    M, z, L = prm.any_parameters(anu, eps, M)
     pr = np.argsort(r, kind='stable')
     pw = np.argsort(w, kind='stable')
     rs, cs, ws = r[pr], c[pr], w[pw]
@@ -144,7 +208,7 @@ def nufht_reference_rows(nu: int, eps: float, r, c, w, rows, min_size: int = 102
         js = sel[lo:hi]
         cols = slice(b.k0, b.k1 + 1)
         if b.kind == 'L':
-            v = local_block_apply(anu, L, z, ws[js], rs[cols], cs[cols])
+            v = local(anu, L, z, ws[js], rs[cols], cs[cols])
         elif b.kind == 'A':
             v = direct.asy_block_apply(anu, M, ws[js], rs[cols], cs[cols])
         else:

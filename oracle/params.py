@@ -20,6 +20,24 @@ Readings of the paper taken here (each listed in the design doc):
 * Outside the Lemma's hypotheses (a Siegel argument >= 1, or a non-convergent
   geometric tail) the bound is taken as +inf, so that L grows until they hold.
 * Negative orders use |nu| (J_{-nu} = (-1)^nu J_nu).
+
+Half-integer orders nu = n + 1/2 (n >= 0; the paper treats integer orders only):
+* Hankel's expansion terminates after a_n (a_l(nu) = 0 for l > n), so with
+  2M >= n + 1 terms it is exact: M is the eq. num-asy-terms value capped at
+  ceil((n + 1) / 2).  With an exact expansion B^asy = 0 and the crossover is
+  set by conditioning instead: z is the smallest z >= 1 at which the retained
+  terms' magnitudes sum_{k < min(2M, n+1)} |a_k| z^-k are at most 10 (an
+  asymptotic entry, omega r > z, then amplifies the type-3 transforms' error,
+  about eps / 10, by at most 10).
+  When 2M < n + 1 the crossover is Newton's root as for integer orders (at
+  least 1).
+* Local blocks use J_{n+1/2}(x y) = sqrt(y) sqrt(2x/pi) j_n(x y) with the
+  Chebyshev series of the entire function y -> j_n(x y) (parity (-1)^n):
+  beta_k(x), k = n mod 2, n mod 2 + 2, ...  L is the smallest integer with
+  B(L) = 2 sqrt(2z/pi) sum_{k > 2L + e, k = e mod 2} exp(k psi(z/k)) < eps,
+  from |beta_k(x)| <= 2 max_{t <= x} |J_k(t)| and the Siegel bound
+  |J_k(k p)| <= exp(k psi(p)) that Lemma 3.1 also uses (DLMF 10.14.5); +inf
+  while some k <= z.
 """
 import math
 
@@ -154,3 +172,80 @@ def tail_local_rank(nu: int, eps: float, z: float, L_lemma: int, grid: int = 512
         if tailmax[L] <= 0.5 * eps:
             return L, tailmax
     return L_lemma, tailmax
+
+
+# ---------------------------------------------------------------------------
+# Half-integer orders.
+# ---------------------------------------------------------------------------
+def is_half(nu) -> bool:
+    """nu = n + 1/2 with n >= 0."""
+    t = 2.0 * float(nu)
+    return t == round(t) and int(round(t)) % 2 == 1 and t > 0
+
+
+def half_num_asy_terms(nu: float, eps: float) -> int:
+    """M for nu = n + 1/2: eq. num-asy-terms, capped where the expansion ends."""
+    n = int(round(nu - 0.5))
+    return min(num_asy_terms(nu, eps), (n + 2) // 2)
+
+
+def half_crossover(nu: float, eps: float, M: int) -> float:
+    """z for nu = n + 1/2 (see the module notes): conditioning when the M-term
+    expansion is exact, else Newton's root; at least 1."""
+    n = int(round(nu - 0.5))
+    if 2 * M < n + 1:
+        return max(crossover(nu, eps, M), 1.0)
+    a = [abs(hankel_coef(nu, k)) for k in range(n + 1)]
+    S = lambda z: sum(ak * z ** -k for k, ak in enumerate(a))
+    if S(1.0) <= 10.0:
+        return 1.0
+    lo, hi = 1.0, 2.0
+    while S(hi) > 10.0:
+        hi *= 2.0
+    for _ in range(200):                 # bisection: S decreases on z > 0
+        mid = 0.5 * (lo + hi)
+        if S(mid) > 10.0:
+            lo = mid
+        else:
+            hi = mid
+        if hi - lo <= 1e-15 * hi:
+            break
+    return hi
+
+
+def half_local_bound(nu: float, L: int, z: float) -> float:
+    """B(L) for the half-integer local expansion with Chebyshev terms of
+    degree up to 2L + e (see the module notes)."""
+    n = int(round(nu - 0.5))
+    e = n % 2
+    k = 2 * L + 2 + e
+    if k <= z:
+        return math.inf
+    total = 0.0
+    for _ in range(100000):
+        term = math.exp(k * psi(z / k))
+        total += term
+        if term <= 1e-20 * total:
+            break
+        k += 2
+    return 2.0 * math.sqrt(2.0 * z / math.pi) * total
+
+
+def half_local_rank(nu: float, eps: float, z: float, L_max: int = 100000) -> int:
+    for L in range(0, L_max):
+        if half_local_bound(nu, L, z) < eps:
+            return L
+    raise ValueError("no local rank below L_max")
+
+
+def half_parameters(nu: float, eps: float, M: int = None):
+    """(M, z, L) for nu = n + 1/2."""
+    if M is None:
+        M = half_num_asy_terms(nu, eps)
+    z = half_crossover(nu, eps, M)
+    return M, z, half_local_rank(nu, eps, z)
+
+
+def any_parameters(nu, eps: float, M: int = None):
+    """(M, z, L) for an integer or half-integer order."""
+    return half_parameters(float(nu), eps, M) if is_half(nu) else parameters(int(nu), eps, M)
