@@ -143,7 +143,7 @@ typedef struct {
     int32_t spread_items;             /* spreading work items of the asymptotic blocks */
     int32_t dense_items;              /* of which spread on the matrix cores */
     int32_t split_candidates;         /* candidate rows of SplitIndices in use (-1: exact) */
-    int32_t pad;
+    int32_t half_order;               /* 1: the order is nu + 1/2 (nuht_plan_half) */
 } nuht_info;
 
 /*
@@ -169,6 +169,34 @@ typedef struct {
 int nuht_plan(nuht_plan_t *plan, int nu, double eps,
               int64_t n, const double *r_dev, int64_t m, const double *omega_dev,
               const nuht_opts *opts, void *stream);
+
+/*
+ * nuht_plan_half -- nuht_plan for integer or half-integer orders, the order
+ * given twice: nu = nu2 / 2.  Even nu2 (|nu2| <= 200) is the integer order
+ * nu2 / 2, exactly as nuht_plan.  Odd nu2 with 1 <= nu2 <= 199 is the
+ * half-integer order nu = n + 1/2, n = (nu2 - 1) / 2 (the radial Fourier
+ * transform in odd dimension d has nu = d/2 - 1).  The paper treats integer
+ * orders (Sec. 3); at half-integers the same method runs with:
+ *  - Hankel's expansion (Sec. 3.2), which ends at a_n (a_l = 0 for l > n):
+ *    M is eq. num-asy-terms capped at ceil((n + 1) / 2); when the M terms
+ *    are the whole expansion the crossover z is the smallest z >= 1 where
+ *    the terms' magnitudes sum_k |a_k| z^-k are at most 10, else Newton's
+ *    root of the bound of eq. asy-error (at least 1);
+ *  - the local form J_{n+1/2}(omega r) = sqrt(r/R) sqrt(2x/pi)
+ *    sum_l beta_{e+2l}(x) T_{e+2l}(r/R), x = omega R, e = n mod 2, the
+ *    Chebyshev series of the spherical Bessel function j_n(x y) in y, with L
+ *    from the Siegel bound of Lemma 3.1 applied to its coefficients
+ *    (opts->local_rank = -1 is the same as 0 here);
+ *  - J_{n+1/2} to full precision in the direct blocks.
+ * Negative half-integer orders (the Y functions, singular at 0) are not
+ * supported (NUHT_EINVAL).  nuht_gradient's dr and domega need nu >= 3/2
+ * (orders nu -+ 1 are half-integers too).  All other entry points act on a
+ * half-integer plan as on an integer one; nuht_plan_set_order and the
+ * batches (nuht_plan_many) take integer orders.
+ */
+int nuht_plan_half(nuht_plan_t *plan, int nu2, double eps,
+                   int64_t n, const double *r_dev, int64_t m, const double *omega_dev,
+                   const nuht_opts *opts, void *stream);
 
 /*
  * nuht_execute -- g = A c (forward transform, Alg. 2).

@@ -55,11 +55,11 @@ class NuhtInfo(ctypes.Structure):
                 ("fft_row_members", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("min_size", ctypes.c_int64), ("dft_max", ctypes.c_int32), ("spread_chunk", ctypes.c_int32),
                 ("spread_items", ctypes.c_int32), ("dense_items", ctypes.c_int32),
-                ("split_candidates", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("split_candidates", ctypes.c_int32), ("half_order", ctypes.c_int32)]
 
 
 # every symbol include/nuht.h declares
-EXPORTS = ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_gradient_noalloc",
+EXPORTS = ("nuht_plan", "nuht_plan_half", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_gradient_noalloc",
            "nuht_plan_set_order",
            "nuht_plan_info", "nuht_tune", "nuht_plan_many", "nuht_execute_many", "nuht_batch_info",
            "nuht_batch_destroy", "nuht_destroy", "nuht_strerror", "nuht_direct", "nuht_profile", "nuht_profile_read",
@@ -81,6 +81,7 @@ def load_library():
     vp = ctypes.c_void_p
     lib.nuht_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_double, ctypes.c_int64, vp,
                               ctypes.c_int64, vp, ctypes.POINTER(NuhtOpts), vp]
+    lib.nuht_plan_half.argtypes = lib.nuht_plan.argtypes
     lib.nuht_execute.argtypes = [vp, vp, vp, vp]
     lib.nuht_adjoint.argtypes = [vp, vp, vp, vp]
     lib.nuht_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -106,7 +107,7 @@ def load_library():
     lib.nuht_fb_synthesis.argtypes = [vp, vp, vp, vp]
     lib.nuht_fb_helmholtz.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp, vp]
     lib.nuht_fb_destroy.argtypes = [vp]
-    for name in ("nuht_plan", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_gradient_noalloc",
+    for name in ("nuht_plan", "nuht_plan_half", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_gradient_noalloc",
                  "nuht_plan_set_order", "nuht_plan_info",
                  "nuht_tune", "nuht_plan_many", "nuht_execute_many", "nuht_batch_info", "nuht_batch_destroy",
                  "nuht_destroy", "nuht_direct", "nuht_profile", "nuht_profile_read", "nuht_fb_plan",
@@ -140,7 +141,8 @@ def _ptr(t):
 
 
 class Plan:
-    """A planned transform r (n points) -> omega (m frequencies) of order nu.
+    """A planned transform r (n points) -> omega (m frequencies) of order nu
+    (an integer, or a positive half-integer such as 0.5 or 1.5).
 
     The plan sorts and subdivides once; ``execute`` and ``adjoint`` then run
     asynchronously on the current stream.  ``execute(c)`` returns
@@ -161,9 +163,13 @@ class Plan:
         opts = NuhtOpts(min_size, M, split_candidates, precision, dft_max, spread_chunk, 0,
                         1 if vector_spread else 0, int(local_rank), float(margin),
                         os.fsencode(tune_cache) if tune_cache else None)
+        nu2 = 2.0 * float(nu)
+        if nu2 != round(nu2):
+            raise ValueError("the order must be an integer or a half-integer")
+        self.nu = nu
         h = ctypes.c_void_p()
-        _check(lib.nuht_plan(ctypes.byref(h), int(nu), float(eps), self.n, _ptr(r), self.m, _ptr(omega),
-                             ctypes.byref(opts), _stream()))
+        _check(lib.nuht_plan_half(ctypes.byref(h), int(round(nu2)), float(eps), self.n, _ptr(r), self.m,
+                                  _ptr(omega), ctypes.byref(opts), _stream()))
         self._h = h
 
     def execute(self, c, out=None):

@@ -170,7 +170,11 @@ __device__ __forceinline__ void lmom_pass(const PlanDev& P, const Item& I, const
         const bool two = k + 64 < I.kb;
         const int k2 = two ? k + 64 : k;
         const double ya = P.rs[k] / B.R, yb = P.rs[k2] / B.R;
-        const double ca = cs[k], cb = two ? cs[k2] : 0.0;
+        double ca = cs[k], cb = two ? cs[k2] : 0.0;
+        if (P.half) {          // half-integer orders: weights c sqrt(r / R)
+            ca *= sqrt(ya);
+            cb *= sqrt(yb);
+        }
         const double ua2 = 2.0 * __builtin_fma(2.0 * ya, ya, -1.0);
         const double ub2 = 2.0 * __builtin_fma(2.0 * yb, yb, -1.0);
         double a0, a1, b0, b1;
@@ -240,8 +244,9 @@ __device__ __forceinline__ void lmom_reduce_body(const PlanDev& P, int bid)
     const double* __restrict__ lpart = P.lpart;
     double s = 0.0;
     for (int32_t it = 0; it < B.nitems; ++it) s += lpart[(int64_t)(B.item0 + it) * Lp + l];
-    // stored as the row pass uses them: u_0 = t_0, u_l = 2 (-1)^l t_l
-    P.lmom[t] = l == 0 ? s : ((l & 1) ? -2.0 * s : 2.0 * s);
+    // stored as the row pass uses them: u_0 = t_0, u_l = 2 (-1)^l t_l (integer
+    // orders), t_l itself (half-integer orders: the factors are in the table)
+    P.lmom[t] = (l == 0 || P.half) ? s : ((l & 1) ? -2.0 * s : 2.0 * s);
 }
 
 __global__ void k_lmom_reduce(PlanDev P) { lmom_reduce_body(P, blockIdx.x); }
@@ -1300,6 +1305,34 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
     }
 }
 
+// Local block contribution at a half-integer order nu = n + 1/2, x = om R in
+// [0, z]: from J_{n+1/2}(x y) = sqrt(y) sqrt(2x/pi) sum_l beta_{e+2l}(x) T_{e+2l}(y),
+//   sqrt(2x/pi) sum_{l=0}^{L} beta_{e+2l}(x) t_l,   t_l = sum_k c_k sqrt(y_k) T_{e+2l}(y_k),
+// with beta from the plan's table: panel p = floor(x / h), Horner's rule in the
+// panel variable tau = 2 (x / h - p) - 1 for each l; the leading panels
+// (below x = n + 10) hold beta / x^n, accurate relative to beta itself there.
+__device__ double local_eval_half(const PlanDev& P, int lblk, double om, const double* __restrict__ lmom)
+{
+    const LBlock B = P.lb[lblk];
+    const double x = om * B.R;
+    const double* t = lmom + (int64_t)lblk * (P.L + 1);
+    const double u = x * P.half_inv_h;
+    int pn = (int)u;
+    if (pn > P.half_np - 1) pn = P.half_np - 1;
+    const double tau = 2.0 * (u - pn) - 1.0;
+    const double* tab = P.half_tab + (int64_t)pn * (P.L + 1) * (kHalfDeg + 1);
+    double acc = 0.0;
+    for (int l = 0; l <= P.L; ++l) {
+        const double* cf = tab + l * (kHalfDeg + 1);
+        double b = cf[kHalfDeg];
+        #pragma unroll
+        for (int d = kHalfDeg - 1; d >= 0; --d) b = __builtin_fma(b, tau, cf[d]);
+        acc = __builtin_fma(b, t[l], acc);
+    }
+    if (pn < P.half_ns && P.nu > 0) acc *= pow(x, (double)P.nu);
+    return sqrt(2.0 * x / kPi) * acc;
+}
+
 // Asymptotic block contribution at frequency om (Sec. 3.2):
 //   sqrt(2/pi) Re( e^{i phi} sum_p beta_p om^(-p-1/2) y_p ),
 //   beta_{2l} = (-1)^l a_{2l},  beta_{2l+1} = i (-1)^l a_{2l+1},
@@ -1541,8 +1574,13 @@ __device__ __forceinline__ void rows_local_body(const PlanDev& P, int bid, doubl
             if (nd.lblk >= 0) {
                 int lb = nd.lblk;
                 int lbu = __builtin_amdgcn_readfirstlane(lb);
-                if (__all(lb == lbu)) acc += local_eval<MODE>(P, lbu, om, lmom, ring, stride);
-                else acc += local_eval<MODE>(P, lb, om, lmom, ring, stride);
+                if constexpr (MODE == 3) {
+                    if (__all(lb == lbu)) acc += local_eval_half(P, lbu, om, lmom);
+                    else acc += local_eval_half(P, lb, om, lmom);
+                } else {
+                    if (__all(lb == lbu)) acc += local_eval<MODE>(P, lbu, om, lmom, ring, stride);
+                    else acc += local_eval<MODE>(P, lb, om, lmom, ring, stride);
+                }
             }
             child = nd.ur;
         } else {
@@ -1627,6 +1665,10 @@ static size_t rows_local_lds(int nu, int bs)
 
 static void launch_rows_local(const PlanDev& P, const IoArgs& io, hipStream_t s)
 {
+    if (P.half) {      // half-integer orders: coefficients from the table
+        hipLaunchKernelGGL(k_rows_local<3>, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, P, io.g, io.g_slot);
+        return;
+    }
     if (P.nu <= 1) {   // no ring of earlier values needed
         auto k = P.nu == 0 ? k_rows_local<0> : k_rows_local<1>;
         hipLaunchKernelGGL(k, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, P, io.g, io.g_slot);
@@ -1929,14 +1971,16 @@ void build_batch_schedule(const BatchTransform* tr, int count, const int* order,
         add(kRowsAsy, nch, 0, 256, [&](const BatchTransform& T, size_t&) -> int64_t {
             return live(*T.P) && T.P->nch == nch ? cdiv64(T.P->m, 256) : 0;
         });
-    // local rows: orders 0 and 1, then the general mode at 256 and at 64 lanes
-    for (int mode = 0; mode < 4; ++mode) {
+    // local rows: orders 0 and 1, the general mode at 256 and at 64 lanes,
+    // half-integer orders
+    for (int mode = 0; mode < 5; ++mode) {
         const int bs = mode == 3 ? 64 : 256;
-        add(kRowsLocal, mode < 2 ? mode : 2, 0, bs, [&](const BatchTransform& T, size_t& lds) -> int64_t {
+        const int variant = mode < 2 ? mode : (mode == 4 ? 3 : 2);
+        add(kRowsLocal, variant, 0, bs, [&](const BatchTransform& T, size_t& lds) -> int64_t {
             const int nu = T.P->nu;
-            if (!live(*T.P)) return 0;
-            if (mode < 2 ? nu != mode : (nu <= 1 || rows_local_block(nu) != bs)) return 0;
-            lds = rows_local_lds(nu, bs);
+            if (!live(*T.P) || (T.P->half != 0) != (mode == 4)) return 0;
+            if (mode < 2 ? nu != mode : (mode < 4 && (nu <= 1 || rows_local_block(nu) != bs))) return 0;
+            lds = mode == 4 ? 0 : rows_local_lds(nu, bs);
             return cdiv64(T.P->m, bs);
         });
     }
@@ -2001,6 +2045,8 @@ hipError_t launch_execute_many(const BatchSchedule& S, const void* table_dev, vo
             if (L.variant == 0) hipLaunchKernelGGL(k_rows_local_many<0>, grid, block, L.lds, s, plans, sg, L.nseg, gout);
             else if (L.variant == 1)
                 hipLaunchKernelGGL(k_rows_local_many<1>, grid, block, L.lds, s, plans, sg, L.nseg, gout);
+            else if (L.variant == 3)
+                hipLaunchKernelGGL(k_rows_local_many<3>, grid, block, L.lds, s, plans, sg, L.nseg, gout);
             else hipLaunchKernelGGL(k_rows_local_many<2>, grid, block, L.lds, s, plans, sg, L.nseg, gout);
             break;
         default: return hipErrorInvalidValue;

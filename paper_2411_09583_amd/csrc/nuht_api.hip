@@ -1,6 +1,7 @@
 // nuht_api.hip -- host side of libnuht: expansion parameters (Sec. 3.3), ES
 // kernel set-up, plan construction (sort, staircase, Alg. 1) and the C ABI.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -9,6 +10,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "nuht.h"
@@ -21,9 +23,9 @@ namespace nuht {
 // ===========================================================================
 
 // M = min(floor(1 + nu/5 - log10(eps)/4), 20)   (eq. num-asy-terms)
-static int num_asy_terms(int nu, double eps)
+static int num_asy_terms(double nu, double eps)
 {
-    int M = (int)std::floor(1.0 + std::fabs((double)nu) / 5.0 - std::log10(eps) / 4.0);
+    int M = (int)std::floor(1.0 + std::fabs(nu) / 5.0 - std::log10(eps) / 4.0);
     return std::min(std::max(M, 1), 20);
 }
 
@@ -41,7 +43,7 @@ static double hankel_coef(double nu, int l)
 // Newton's method on xi(z) = B^asy(z) - eps, B^asy the first-neglected-terms
 // bound of eq. asy-error.  xi is convex and decreasing; the iteration starts at
 // the root of the first term alone, left of the root, and increases to it.
-static double crossover(int nu, double eps, int M)
+static double crossover(double nu, double eps, int M)
 {
     const double s2p = std::sqrt(2.0 / M_PI);
     double a0 = s2p * std::fabs(hankel_coef(nu, 2 * M));
@@ -150,6 +152,281 @@ static int local_rank_tail(int nu, double eps, double z, int L_lemma)
     for (int L = 0; L < L_lemma; ++L)
         if (tailmax[L] <= 0.5 * eps) return L;
     return L_lemma;
+}
+
+// ===========================================================================
+// Half-integer orders nu = n + 1/2 (n >= 0).  The paper covers integer orders;
+// for half-integers:
+//  - Hankel's expansion ends at a_n (a_l(n + 1/2) = 0 for l > n), so M is the
+//    eq. num-asy-terms value capped at ceil((n + 1) / 2); with 2M >= n + 1 the
+//    expansion is exact and the crossover is set by conditioning: the smallest
+//    z >= 1 where the retained terms' magnitudes sum_k |a_k| z^-k are at most
+//    10 (the type-3 transforms run about a decade below eps); otherwise
+//    Newton's root of B^asy = eps, at least 1;
+//  - local blocks use J_{n+1/2}(x y) = sqrt(y) sqrt(2x/pi) j_n(x y), j_n the
+//    spherical Bessel function (DLMF 10.47.3), expanded in Chebyshev
+//    polynomials of y (j_n(x y) is entire in y with parity (-1)^n):
+//      j_n(x y) = sum_l beta_{e+2l}(x) T_{e+2l}(y),  e = n mod 2,
+//      beta_k(x) = eps_k (-1)^((k-n)/2) int_0^1 P_n(s) J_k(x s) ds
+//    (from j_n(t) = (1/2) (-i)^n int_{-1}^{1} e^{i t s} P_n(s) ds and the
+//    Jacobi-Anger expansion of e^{i x s cos theta}; eps_0 = 1, else 2);
+//  - L is the smallest integer with
+//      2 sqrt(2z/pi) sum_{k > 2L+e, k = e mod 2} exp(k psi(z/k)) < eps,
+//    from |beta_k(x)| <= 2 max_{t<=x} |J_k(t)| and the Siegel bound
+//    |J_k(k p)| <= exp(k psi(p)) of Lemma 3.1 (+inf while some k <= z).
+// The beta_k are tabulated on panels of x in [0, z] (kHalfWidth wide, Chebyshev
+// interpolants of degree kHalfDeg rewritten as monomials in the panel
+// variable tau in [-1, 1]), computed on the host in long double: on the first
+// panel by their power series, on the others by the Chebyshev transform of
+// samples of j_n; the panels below x = n + 10 hold beta_k / x^n.
+// ===========================================================================
+static double half_crossover(double nu, double eps, int M)
+{
+    const int n = (int)(nu - 0.5 + 0.25);
+    if (2 * M < n + 1) return std::max(crossover(nu, eps, M), 1.0);
+    std::vector<double> a(n + 1);
+    for (int k = 0; k <= n; ++k) a[k] = std::fabs(hankel_coef(nu, k));
+    auto S = [&](double z) {          // sum_k a_k z^-k by Horner in 1/z
+        double v = 0.0;
+        for (int k = n; k >= 0; --k) v = v / z + a[k];
+        return v;
+    };
+    auto dS = [&](double z) {         // S'(z) = -sum_k k a_k z^-k-1
+        double v = 0.0;
+        for (int k = n; k >= 1; --k) v = v / z + k * a[k];
+        return -v / (z * z);
+    };
+    if (S(1.0) <= 10.0) return 1.0;
+    // S is convex and decreasing: Newton from the left of the root increases
+    // to it; the left start is 1 (S(1) > 10)
+    double z = 1.0;
+    for (int it = 0; it < 200; ++it) {
+        const double zn = z - (S(z) - 10.0) / dS(z);
+        if (std::fabs(zn - z) <= 1e-15 * zn) return zn;
+        z = zn;
+    }
+    return z;
+}
+
+static double half_local_bound(int n, int L, double z)
+{
+    const int e = n & 1;
+    int k = 2 * L + 2 + e;
+    if (k <= z) return INFINITY;
+    double total = 0.0;
+    for (int i = 0; i < 100000; ++i, k += 2) {
+        const double p = z / k, r = std::sqrt(1.0 - p * p);
+        const double term = std::exp(k * (std::log(p) + r - std::log1p(r)));
+        total += term;
+        if (term <= 1e-20 * total) break;
+    }
+    return 2.0 * std::sqrt(2.0 * z / M_PI) * total;
+}
+
+static int half_local_rank(int n, double eps, double z)
+{
+    for (int L = 0; L < 100000; ++L)
+        if (half_local_bound(n, L, z) < eps) return L;
+    return -1;
+}
+
+// j_n(t) (spherical Bessel) in long double for t >= 0: upward recurrence from
+// j_{-1} = cos t / t, j_0 = sin t / t above the turning point (t > n + 1),
+// Miller's backward recurrence normalised by sum_k (2k+1) j_k^2 = 1 below it.
+static long double sph_jn_ld(int n, long double t)
+{
+    if (t == 0.0L) return n == 0 ? 1.0L : 0.0L;
+    if (t > n + 1.0L) {
+        long double jm = cosl(t) / t, j = sinl(t) / t;
+        for (int k = 0; k < n; ++k) {
+            const long double jp = ((2.0L * k + 1.0L) / t) * j - jm;
+            jm = j;
+            j = jp;
+        }
+        return j;
+    }
+    const int N = (int)(n + t + 30.0L + 15.0L * cbrtl(t > 1.0L ? t : 1.0L));
+    long double yk1 = 0.0L, yk = 1e-300L, S = 0.0L, rn = 0.0L;
+    for (int k = N; k >= 0; --k) {
+        if (k == n) rn = yk;
+        S += (2.0L * k + 1.0L) * yk * yk;
+        if (k == 0) break;
+        const long double ykm1 = ((2.0L * k + 1.0L) / t) * yk - yk1;
+        yk1 = yk;
+        yk = ykm1;
+        if (fabsl(yk) > 1e1000L) { yk *= 1e-1000L; yk1 *= 1e-1000L; S *= 1e-2000L; rn *= 1e-1000L; }
+    }
+    return rn / sqrtl(S);
+}
+
+// beta_{e+2l}(x) by the discrete Chebyshev transform of y -> j_n(x y) at the Q
+// points y_q = cos theta_q, theta_q = pi (2q + 1) / (2Q), Q above the degrees
+// involved; cos(k theta_q) from the integer k (2q + 1) reduced modulo 4Q.
+// Every sample is accurate relative to itself, so the coefficients are
+// accurate relative to the largest sample even when all are tiny (x < n); a
+// quadrature of the integral form cancels there instead.
+static void half_beta_dct(int n, int L, long double x, long double* beta)
+{
+    const int e = n & 1, K = e + 2 * L;
+    const int Q = K + 2 * (int)x + 64;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<long double> f(Q), cs(4 * Q);
+    for (int i = 0; i < 4 * Q; ++i) cs[i] = cosl(pi * i / (2.0L * Q));
+    for (int q = 0; q < Q; ++q) {
+        const long double t = x * cs[2 * q + 1];
+        const long double v = sph_jn_ld(n, fabsl(t));
+        f[q] = (t < 0.0L && (n & 1)) ? -v : v;
+    }
+    for (int l = 0; l <= L; ++l) {
+        const int k = e + 2 * l;
+        long double sm = 0.0L;
+        for (int q = 0; q < Q; ++q) sm += f[q] * cs[(int)(((int64_t)k * (2 * q + 1)) % (4 * Q))];
+        beta[l] = sm * (k == 0 ? 1.0L : 2.0L) / Q;
+    }
+}
+
+// gamma_{e+2l}(x) = beta_{e+2l}(x) / x^n, l = 0 .. L, for small x by the power
+// series of J_k, with the moments mu_m = int_0^1 s^m P_n(s) ds: zero for
+// m < n (the terms that cancel in the integral), else
+// 2^n m! ((m+n)/2)! / (((m-n)/2)! (m+n+1)!) (m + n even):
+//   beta_k(x) = eps_k (-1)^((k-n)/2) sum_j (-1)^j (x/2)^(k+2j) mu_{k+2j} / (j! (k+j)!).
+// beta_k is O(x^n), so gamma is entire and known to full relative accuracy at
+// small x, where the quadrature's cancellation would leave only absolute
+// accuracy.  Used on the first panel, x <= kHalfWidth.
+static void half_gamma(int n, int L, long double x, long double* gam)
+{
+    const int e = n & 1;
+    const long double h = 0.5L * x;
+    for (int l = 0; l <= L; ++l) {
+        const int k = e + 2 * l;
+        int j = k >= n ? 0 : (n - k) / 2;            // first term with k + 2j >= n
+        int m = k + 2 * j;
+        // log of 2^-n (x/2)^(m-n) mu_m / (j! (k+j)!), the first term without its sign
+        auto log_mu = [&](int mm) {
+            return n * logl(2.0L) + lgammal(mm + 1.0L) + lgammal((mm + n) / 2 + 1.0L) -
+                   lgammal((mm - n) / 2 + 1.0L) - lgammal(mm + n + 2.0L);
+        };
+        long double term;
+        if (x == 0.0L) {
+            term = m == n ? expl(-n * logl(2.0L) + log_mu(m) - lgammal(j + 1.0L) - lgammal(k + j + 1.0L)) : 0.0L;
+        } else {
+            term = expl(-n * logl(2.0L) + (m - n) * logl(h) + log_mu(m) - lgammal(j + 1.0L) -
+                        lgammal(k + j + 1.0L));
+        }
+        if (j & 1) term = -term;
+        long double sum = term;
+        for (int it = 0; it < 4000 && x != 0.0L; ++it) {
+            // mu_{m+2} / mu_m and the factorials' ratio
+            const long double r = (long double)(m + 2) * (m + 1) * ((m + n) / 2 + 1) /
+                                  ((long double)((m - n) / 2 + 1) * (m + n + 3) * (m + n + 2));
+            term *= -h * h * r / ((long double)(j + 1) * (k + j + 1));
+            ++j;
+            m += 2;
+            sum += term;
+            if (fabsl(term) <= 1e-24L * fabsl(sum)) break;
+        }
+        const long double sg = (((k - n) / 2) & 1) ? -1.0L : 1.0L;
+        gam[l] = (k == 0 ? 1.0L : 2.0L) * sg * sum;
+    }
+}
+
+// The leading panels tabulated as beta / x^n: every panel below x = n + 10
+// (there beta grows like x^n, by many orders of magnitude across a panel at
+// large n, while beta / x^n varies slowly), at least the first.
+static int half_scaled_panels(int n) { return std::max(1, (int)((n + 10.0) / kHalfWidth)); }
+
+// The table: panels p = 0 .. np-1 covering [p h, (p+1) h], h = kHalfWidth,
+// np = ceil(z / h); entry [p][l][d] = coefficient of tau^d in the degree
+// kHalfDeg interpolant, at the panel's Chebyshev points, of gamma_{e+2l} =
+// beta_{e+2l} / x^n on the leading half_scaled_panels(n) panels and of
+// beta_{e+2l} on the others.
+static void half_table(int n, int L, double z, std::vector<double>& tab, int& np)
+{
+    const int D = kHalfDeg;
+    np = std::max(1, (int)std::ceil(z / kHalfWidth));
+    const int ns = half_scaled_panels(n);
+    tab.assign((size_t)np * (L + 1) * (D + 1), 0.0);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    long double T[kHalfDeg + 1][kHalfDeg + 1] = {};   // T[j][i]: coefficient of tau^i in T_j(tau)
+    T[0][0] = 1.0L;
+    T[1][1] = 1.0L;
+    for (int j = 2; j <= D; ++j)
+        for (int i = 0; i <= j; ++i) T[j][i] = (i > 0 ? 2.0L * T[j - 1][i - 1] : 0.0L) - T[j - 2][i];
+    auto panel = [&](int p) {
+        std::vector<long double> val((size_t)(D + 1) * (L + 1)), a(D + 1);
+        for (int i = 0; i <= D; ++i) {
+            const long double t = cosl(pi * (i + 0.5L) / (D + 1));
+            const long double x = (p + 0.5L * (t + 1.0L)) * (long double)kHalfWidth;
+            long double* v = &val[(size_t)i * (L + 1)];
+            if (p == 0) {
+                half_gamma(n, L, x, v);
+            } else {
+                half_beta_dct(n, L, x, v);
+                if (p < ns) {
+                    const long double inv = powl(x, -(long double)n);
+                    for (int l = 0; l <= L; ++l) v[l] *= inv;
+                }
+            }
+        }
+        for (int l = 0; l <= L; ++l) {
+            for (int j = 0; j <= D; ++j) {
+                long double sm = 0.0L;
+                for (int i = 0; i <= D; ++i)
+                    sm += val[(size_t)i * (L + 1) + l] * cosl(pi * j * (i + 0.5L) / (D + 1));
+                a[j] = sm * (j == 0 ? 1.0L : 2.0L) / (D + 1);
+            }
+            double* out = &tab[((size_t)p * (L + 1) + l) * (D + 1)];
+            for (int i = 0; i <= D; ++i) {
+                long double c = 0.0L;
+                for (int j = i; j <= D; ++j) c += a[j] * T[j][i];
+                out[i] = (double)c;
+            }
+        }
+    };
+    const int nt = std::max(1, std::min({np, 16, (int)std::thread::hardware_concurrency()}));
+    std::vector<std::thread> pool;
+    std::atomic<int> next{0};
+    for (int t = 0; t < nt; ++t)
+        pool.emplace_back([&]() { for (int p; (p = next++) < np;) panel(p); });
+    for (auto& th : pool) th.join();
+}
+
+// The table of (n, L, z) on the current device: built and uploaded once per
+// device and key, kept until the process ends.
+static const double* half_table_device(int n, int L, double z, int* np_out, int* ns_out)
+{
+    struct Entry {
+        int dev, n, L;
+        double z;
+        int np;
+        const double* p;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Entry& e : cache)
+        if (e.dev == dev && e.n == n && e.L == L && e.z == z) {
+            *np_out = e.np;
+            *ns_out = half_scaled_panels(n);
+            return e.p;
+        }
+    std::vector<double> host;
+    int np = 0;
+    half_table(n, L, z, host, np);
+    void* p = nullptr;
+    const size_t bytes = sizeof(double) * host.size();
+    if (hipMalloc(&p, bytes) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+    if (hipMemcpy(p, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(p);
+        return nullptr;
+    }
+    cache.push_back(Entry{dev, n, L, z, np, (const double*)p});
+    *np_out = np;
+    *ns_out = half_scaled_panels(n);
+    return (const double*)p;
 }
 
 // ===========================================================================
@@ -331,10 +608,11 @@ static const double2* fft_twiddles_device()
     return table[dev];
 }
 
-// -(2nu+1) pi/4 modulo 2 pi as a double-double in (0, 2 pi].
-static void phase_offset(int nu, double& hi, double& lo)
+// -(2nu+1) pi/4 modulo 2 pi as a double-double in (0, 2 pi], from the
+// integer t = 2 nu + 1 (odd for integer orders, even for half-integers).
+static void phase_offset2(int t, double& hi, double& lo)
 {
-    int k = 8 - ((2 * nu + 1) % 8);           // -(2nu+1) = k - 8(...)  (mod 8)
+    int k = 8 - (t % 8);                      // -(2nu+1) = k - 8(...)  (mod 8)
     const double q_hi = 0.78539816339744827900;   // pi/4 rounded
     const double q_lo = 3.0616169978683830e-17;   // pi/4 - q_hi
     double p = k * q_hi;                           // exact: k <= 8
@@ -342,7 +620,7 @@ static void phase_offset(int nu, double& hi, double& lo)
     lo = k * q_lo;
 }
 
-void phase_offset_dd(int nu, double* hi, double* lo) { phase_offset(nu, *hi, *lo); }
+void phase_offset_dd(int nu, double* hi, double* lo) { phase_offset2(2 * nu + 1, *hi, *lo); }
 
 // ===========================================================================
 // Plan.
@@ -515,7 +793,7 @@ static HostStage* host_stage(std::unique_lock<std::mutex>& lock)
 using namespace nuht;
 
 struct nuht_plan_s {
-    int nu_req = 0;
+    int nu2_req = 0;             // twice the order (odd: a half-integer order)
     double eps = 0.0;
     nuht_opts opts{};            // opts.tune_cache is not kept (see cache_path)
     std::string cache_path;      // the tuning cache file, empty for none
@@ -604,28 +882,47 @@ static double design_eps(double eps, const nuht_opts& o)
     return o.margin > 1.0 ? eps / o.margin : eps;
 }
 
-static void fill_params(PlanDev& P, int nu, double eps_req, const nuht_opts& o)
+// nu2 = 2 nu: even for integer orders (any sign), odd (>= 1) for nu = n + 1/2.
+// Returns NUHT_ENOMEM if the half-integer table could not be made.
+static int fill_params(PlanDev& P, int nu2, double eps_req, const nuht_opts& o)
 {
-    int anu = std::abs(nu);
+    const bool half = (nu2 & 1) != 0;
+    const int anu = half ? (nu2 - 1) / 2 : std::abs(nu2 / 2);
+    const double nu = half ? anu + 0.5 : (double)anu;
     P.nu = anu;
-    P.sign = (nu < 0 && (anu & 1)) ? -1 : 1;
+    P.half = half ? 1 : 0;
+    P.sign = (!half && nu2 < 0 && (anu & 1)) ? -1 : 1;
     P.eps = eps_req;
     const double eps = design_eps(eps_req, o);
-    int M = o.M_override > 0 ? std::min(o.M_override, 20) : num_asy_terms(anu, eps);
+    int M = o.M_override > 0 ? std::min(o.M_override, 20) : num_asy_terms(nu, eps);
+    if (half && o.M_override <= 0) M = std::min(M, (anu + 2) / 2);
     P.M = M;
     P.nch = padded_channels(2 * M);
-    P.z = crossover(anu, eps, M);
-    P.L = local_rank(anu, eps, P.z);
-    if (o.local_rank > 0) P.L = o.local_rank;
-    else if (o.local_rank == -1 && P.L >= 0) P.L = local_rank_tail(anu, eps, P.z, P.L);
+    if (half) {
+        P.z = half_crossover(nu, eps, M);
+        P.L = o.local_rank > 0 ? o.local_rank : half_local_rank(anu, eps, P.z);
+        if (P.L >= 0) {
+            int np = 0, ns = 0;
+            P.half_tab = half_table_device(anu, P.L, P.z, &np, &ns);
+            if (!P.half_tab) return NUHT_ENOMEM;
+            P.half_np = np;
+            P.half_ns = ns;
+            P.half_inv_h = 1.0 / kHalfWidth;
+        }
+    } else {
+        P.z = crossover(anu, eps, M);
+        P.L = local_rank(anu, eps, P.z);
+        if (o.local_rank > 0) P.L = o.local_rank;
+        else if (o.local_rank == -1 && P.L >= 0) P.L = local_rank_tail(anu, eps, P.z, P.L);
+    }
     P.w = es_width(eps, o.precision);
     P.fp32 = o.precision == NUHT_FP32_SPREAD ? 1 : 0;
     P.mfma = (!P.fp32 && P.w <= 16 && P.nch <= 16 && !o.vector_spread) ? 1 : 0;
     P.beta = es_beta(P.w);
-    for (int p = 0; p < 2 * M + 2; ++p) P.hank[p] = hankel_coef(anu, p);
+    for (int p = 0; p < 2 * M + 2; ++p) P.hank[p] = hankel_coef(nu, p);
     for (int p = 0; p < kMaxChannels; ++p)
         P.chan[p] = p < 2 * M ? (((p >> 1) & 1) ? -P.hank[p] : P.hank[p]) : 0.0;
-    phase_offset(anu, P.phi_hi, P.phi_lo);
+    phase_offset2(half ? nu2 + 1 : 2 * anu + 1, P.phi_hi, P.phi_lo);
     P.kappa_max = P.w * M_PI / 4.0 * (1.0 + 1e-9);
     P.n_eshat = 24;   // the series reaches the quadrature's ~1e-15 floor by then (w <= 18)
     P.spread_chunk = o.spread_chunk > 0 ? o.spread_chunk : kSpreadChunk;
@@ -639,6 +936,7 @@ static void fill_params(PlanDev& P, int nu, double eps_req, const nuht_opts& o)
         have[P.w] = true;
     }
     for (int i = 0; i < P.n_eshat; ++i) P.eshat[i] = cache[P.w][i];
+    return NUHT_OK;
 }
 
 // Building a partition takes two steps around one host synchronisation:
@@ -668,7 +966,7 @@ static int part_begin(nuht_plan_t pl, PendingPart& pp, Partition& Pt, const Geom
         Pt.release();
         Pt.stream = s;
         P = PlanDev{};
-        fill_params(P, nu, pl->eps, pl->opts);
+        NUHT_TRY(fill_params(P, nu, pl->eps, pl->opts));
         if (P.L < 0) return NUHT_EINVAL;
         P.n = G.n; P.m = G.m;
         P.rs = G.rs; P.ws = G.ws; P.perm_r = G.perm_r; P.perm_w = G.perm_w;
@@ -862,7 +1160,7 @@ static nuht_plan_s::OrderParts* order_parts(nuht_plan_t p, int nu)
     if (p->orders.size() >= kMaxOrders) {
         size_t victim = p->orders.size();
         for (size_t i = 0; i < p->orders.size(); ++i)
-            if (p->orders[i]->nu != p->nu_req &&
+            if (p->orders[i]->nu != p->nu2_req &&
                 (victim == p->orders.size() || p->orders[i]->used < p->orders[victim]->used))
                 victim = i;
         if (victim < p->orders.size()) {
@@ -900,7 +1198,7 @@ static int get_partition(nuht_plan_t p, int nu, bool transposed, hipStream_t s, 
 static const Partition* current_forward(nuht_plan_t p)
 {
     for (auto& o : p->orders)
-        if (o->nu == p->nu_req && o->f.built) return &o->f;
+        if (o->nu == p->nu2_req && o->f.built) return &o->f;
     return nullptr;
 }
 
@@ -915,11 +1213,16 @@ static int run(nuht_plan_t p, const Partition& Pt, const double* in, double* out
     return NUHT_OK;
 }
 
-static bool valid_common(int nu, double eps)
+static bool valid_eps(double eps) { return eps >= 1e-15 && eps <= 1e-2; }
+
+static bool valid_common(int nu, double eps) { return nu >= -100 && nu <= 100 && valid_eps(eps); }
+
+// An order given as twice its value: integers |nu| <= 100, half-integers
+// 1/2 <= nu <= 199/2.
+static bool valid_order2(int nu2)
 {
-    if (nu < -100 || nu > 100) return false;
-    if (!(eps >= 1e-15 && eps <= 1e-2)) return false;
-    return true;
+    if (nu2 & 1) return nu2 >= 1 && nu2 <= 199;
+    return nu2 >= -200 && nu2 <= 200;
 }
 
 extern "C" {
@@ -955,10 +1258,10 @@ static int check_opts(const nuht_opts* opts, nuht_opts& o)
 }
 
 // Host-side checks of one plan's arguments (no HIP call).
-static int check_plan_args(int nu, double eps, int64_t n, const double* r_dev, int64_t m,
+static int check_plan_args(int nu2, double eps, int64_t n, const double* r_dev, int64_t m,
                            const double* omega_dev, const nuht_opts& o)
 {
-    if (!valid_common(nu, eps)) return NUHT_EINVAL;
+    if (!valid_order2(nu2) || !valid_eps(eps)) return NUHT_EINVAL;
     if (design_eps(eps, o) < 1e-15) return NUHT_EINVAL;
     if (o.precision == NUHT_FP32_SPREAD && design_eps(eps, o) < 1e-7) return NUHT_EPRECISION;
     if (n < 0 || m < 0 || n > INT32_MAX / 2 || m > INT32_MAX / 2) return NUHT_EINVAL;
@@ -970,14 +1273,14 @@ static int check_plan_args(int nu, double eps, int64_t n, const double* r_dev, i
 // on `s` (no partition yet, no synchronisation).
 // s: the stream the plan works on (its planning stream); wait_on, if set, is
 // the caller's stream, after whose queued work the inputs are read.
-static int plan_create(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_dev, int64_t m,
+static int plan_create(nuht_plan_t* out, int nu2, double eps, int64_t n, const double* r_dev, int64_t m,
                        const double* omega_dev, const nuht_opts& o, hipStream_t s, hipStream_t wait_on)
 {
     *out = nullptr;
-    NUHT_TRY(check_plan_args(nu, eps, n, r_dev, m, omega_dev, o));
+    NUHT_TRY(check_plan_args(nu2, eps, n, r_dev, m, omega_dev, o));
     nuht_plan_s* p = new (std::nothrow) nuht_plan_s();
     if (!p) return NUHT_ENOMEM;
-    p->nu_req = nu; p->eps = eps; p->opts = o; p->n = n; p->m = m;
+    p->nu2_req = nu2; p->eps = eps; p->opts = o; p->n = n; p->m = m;
     if (o.tune_cache) p->cache_path = o.tune_cache;
     p->opts.tune_cache = nullptr;
     p->ps = s;
@@ -1024,29 +1327,38 @@ static int plan_create(nuht_plan_t* out, int nu, double eps, int64_t n, const do
     return NUHT_OK;
 }
 
-int nuht_plan(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_dev, int64_t m,
-              const double* omega_dev, const nuht_opts* opts, void* stream)
+int nuht_plan_half(nuht_plan_t* out, int nu2, double eps, int64_t n, const double* r_dev, int64_t m,
+                   const double* omega_dev, const nuht_opts* opts, void* stream)
 {
     if (!out) return NUHT_EINVAL;
     *out = nullptr;
     nuht_opts o;
     NUHT_TRY(check_opts(opts, o));
-    NUHT_TRY(check_plan_args(nu, eps, n, r_dev, m, omega_dev, o));
+    NUHT_TRY(check_plan_args(nu2, eps, n, r_dev, m, omega_dev, o));
     hipStream_t s = (hipStream_t)stream;
     hipStream_t ps = plan_stream();
     if (!ps) return NUHT_EHIP;
     nuht_plan_t p = nullptr;
-    NUHT_TRY(plan_create(&p, nu, eps, n, r_dev, m, omega_dev, o, ps, s));
+    NUHT_TRY(plan_create(&p, nu2, eps, n, r_dev, m, omega_dev, o, ps, s));
     // the one synchronisation of the plan happens inside (it also reads the
     // input check's flag)
     Partition* Pt = nullptr;
-    int rc = get_partition(p, nu, false, s, &Pt);
+    int rc = get_partition(p, nu2, false, s, &Pt);
     if (rc != NUHT_OK) {
         free_plan(p);
         return rc;
     }
     *out = p;
     return NUHT_OK;
+}
+
+int nuht_plan(nuht_plan_t* out, int nu, double eps, int64_t n, const double* r_dev, int64_t m,
+              const double* omega_dev, const nuht_opts* opts, void* stream)
+{
+    if (!out) return NUHT_EINVAL;
+    *out = nullptr;
+    if (nu < -100 || nu > 100) return NUHT_EINVAL;
+    return nuht_plan_half(out, 2 * nu, eps, n, r_dev, m, omega_dev, opts, stream);
 }
 
 int nuht_execute(nuht_plan_t p, const double* c_dev, double* g_dev, void* stream)
@@ -1064,7 +1376,7 @@ int nuht_adjoint(nuht_plan_t p, const double* y_dev, double* cbar_dev, void* str
     if ((p->m > 0 && !y_dev) || (p->n > 0 && !cbar_dev)) return NUHT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     Partition* Pt = nullptr;
-    int rc = get_partition(p, p->nu_req, true, s, &Pt);
+    int rc = get_partition(p, p->nu2_req, true, s, &Pt);
     if (rc != NUHT_OK) return rc;
     return run(p, *Pt, y_dev, cbar_dev, false, s);
 }
@@ -1076,8 +1388,8 @@ int nuht_gradient(nuht_plan_t p, const double* c_dev, const double* gbar_dev, do
     const bool want_r = dr_dev != nullptr, want_w = domega_dev != nullptr;
     if (p->m > 0 && !gbar_dev) return NUHT_EINVAL;
     if ((want_r || want_w) && p->n > 0 && !c_dev) return NUHT_EINVAL;
-    const int nu = p->nu_req;
-    if ((want_r || want_w) && std::abs(nu) + 1 > 101) return NUHT_EINVAL;
+    const int nu = p->nu2_req;       // twice the order; orders nu -+ 1 are nu -+ 2 here
+    if ((want_r || want_w) && !(valid_order2(nu - 2) && valid_order2(nu + 2))) return NUHT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     if ((want_r || want_w) && !p->b_grad.p && p->n + p->m > 0) {
         Slab slab;
@@ -1094,16 +1406,16 @@ int nuht_gradient(nuht_plan_t p, const double* c_dev, const double* gbar_dev, do
         if ((rc = run(p, *Pt, gbar_dev, dc_dev, false, s)) != NUHT_OK) return rc;
     }
     if (want_r && p->n > 0) {            // dL/dr = (c/2) (A_{nu-1}^T - A_{nu+1}^T)(omega gbar)
-        if ((rc = get_partition(p, nu - 1, true, s, &Pt)) != NUHT_OK) return rc;
+        if ((rc = get_partition(p, nu - 2, true, s, &Pt)) != NUHT_OK) return rc;
         if ((rc = run(p, *Pt, gbar_dev, p->grad_t[0], true, s)) != NUHT_OK) return rc;
-        if ((rc = get_partition(p, nu + 1, true, s, &Pt)) != NUHT_OK) return rc;
+        if ((rc = get_partition(p, nu + 2, true, s, &Pt)) != NUHT_OK) return rc;
         if ((rc = run(p, *Pt, gbar_dev, p->grad_t[1], true, s)) != NUHT_OK) return rc;
         HIP_TRY(launch_half_difference(c_dev, p->grad_t[0], p->grad_t[1], dr_dev, (int32_t)p->n, s));
     }
     if (want_w && p->m > 0) {            // dL/domega = (gbar/2) (A_{nu-1} - A_{nu+1})(r c)
-        if ((rc = get_partition(p, nu - 1, false, s, &Pt)) != NUHT_OK) return rc;
+        if ((rc = get_partition(p, nu - 2, false, s, &Pt)) != NUHT_OK) return rc;
         if ((rc = run(p, *Pt, c_dev, p->grad_t[2], true, s)) != NUHT_OK) return rc;
-        if ((rc = get_partition(p, nu + 1, false, s, &Pt)) != NUHT_OK) return rc;
+        if ((rc = get_partition(p, nu + 2, false, s, &Pt)) != NUHT_OK) return rc;
         if ((rc = run(p, *Pt, c_dev, p->grad_t[3], true, s)) != NUHT_OK) return rc;
         HIP_TRY(launch_half_difference(gbar_dev, p->grad_t[2], p->grad_t[3], domega_dev, (int32_t)p->m, s));
     }
@@ -1159,18 +1471,18 @@ int nuht_gradient_noalloc(nuht_plan_t p, const double* c_dev, const double* gbar
     const bool want_r = dr_dev != nullptr, want_w = domega_dev != nullptr;
     if (p->m > 0 && !gbar_dev) return NUHT_EINVAL;
     if ((want_r || want_w) && p->n > 0 && !c_dev) return NUHT_EINVAL;
-    const int nu = p->nu_req;
-    if ((want_r || want_w) && std::abs(nu) + 1 > 101) return NUHT_EINVAL;
+    const int nu = p->nu2_req;       // twice the order
+    if ((want_r || want_w) && !(valid_order2(nu - 2) && valid_order2(nu + 2))) return NUHT_EINVAL;
     if ((want_r || want_w) && 2 * (p->n + p->m) > (int64_t)kNoAllocDoubles) return NUHT_ECAPACITY;
     // every partition the call runs must exist already: building one allocates
     const Partition *pc = nullptr, *pr0 = nullptr, *pr1 = nullptr, *pw0 = nullptr, *pw1 = nullptr;
     if (dc_dev && !(pc = built_partition(p, nu, true))) return NUHT_ENOTREADY;
     if (want_r && p->n > 0) {
-        if (!(pr0 = built_partition(p, nu - 1, true)) || !(pr1 = built_partition(p, nu + 1, true)))
+        if (!(pr0 = built_partition(p, nu - 2, true)) || !(pr1 = built_partition(p, nu + 2, true)))
             return NUHT_ENOTREADY;
     }
     if (want_w && p->m > 0) {
-        if (!(pw0 = built_partition(p, nu - 1, false)) || !(pw1 = built_partition(p, nu + 1, false)))
+        if (!(pw0 = built_partition(p, nu - 2, false)) || !(pw1 = built_partition(p, nu + 2, false)))
             return NUHT_ENOTREADY;
     }
     double* t = (want_r || want_w) ? scratch_address() : nullptr;
@@ -1204,11 +1516,11 @@ int nuht_plan_set_order(nuht_plan_t p, int nu, void* stream)
 {
     if (!p) return NUHT_EINVAL;
     if (!valid_common(nu, p->eps)) return NUHT_EINVAL;
-    const int prev = p->nu_req;
-    p->nu_req = nu;
+    const int prev = p->nu2_req;
+    p->nu2_req = 2 * nu;
     Partition* Pt = nullptr;
-    int rc = get_partition(p, nu, false, (hipStream_t)stream, &Pt);
-    if (rc != NUHT_OK) p->nu_req = prev;
+    int rc = get_partition(p, 2 * nu, false, (hipStream_t)stream, &Pt);
+    if (rc != NUHT_OK) p->nu2_req = prev;
     return rc;
 }
 
@@ -1243,7 +1555,7 @@ static int tune_plan(nuht_plan_t p, const double* c_dev, int reps, nuht_opts* be
     auto time_opts = [&](const nuht_opts& o, double* ms) -> int {
         p->opts = o;
         Partition T;
-        int r = build_partition(p, T, p->fwd, p->nu_req, p->ps);
+        int r = build_partition(p, T, p->fwd, p->nu2_req, p->ps);
         if (r != NUHT_OK) return r;
         IoArgs io;
         io.c = c_dev;
@@ -1320,8 +1632,8 @@ static std::string tune_key(const nuht_plan_s* p, const PlanDev& P)
     int cls = 0;
     for (int64_t t = p->n + p->m; t >= 10 && cls < 9; t /= 10) ++cls;
     char buf[160];
-    std::snprintf(buf, sizeof buf, "v1 class %d nch %d L %d w %d fp32 %d exact %d", cls, P.nch, P.L, P.w, P.fp32,
-                  p->opts.split_candidates == -1 ? 1 : 0);
+    std::snprintf(buf, sizeof buf, "v1 class %d nch %d L %d w %d fp32 %d exact %d%s", cls, P.nch, P.L, P.w, P.fp32,
+                  p->opts.split_candidates == -1 ? 1 : 0, P.half ? " half" : "");
     return buf;
 }
 
@@ -1440,7 +1752,7 @@ int nuht_tune(nuht_plan_t p, const double* c_dev, int reps, nuht_opts* best, dou
     p->opts = o;
     p->orders.clear();
     Partition* Pt = nullptr;
-    NUHT_TRY(get_partition(p, p->nu_req, false, s, &Pt));
+    NUHT_TRY(get_partition(p, p->nu2_req, false, s, &Pt));
     *best = o;
     return NUHT_OK;
 }
@@ -1542,7 +1854,7 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
     }
     b->plans.assign(count, nullptr);
     for (int i = 0; i < count; ++i) {
-        int rc = plan_create(&b->plans[i], nu[i], eps, n[i], r_dev[i], m[i], omega_dev[i], o,
+        int rc = plan_create(&b->plans[i], 2 * nu[i], eps, n[i], r_dev[i], m[i], omega_dev[i], o,
                              b->aux[b->stream_of[i]], nullptr);
         if (rc != NUHT_OK) return fail(rc);
     }
@@ -1562,7 +1874,7 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
             nuht_plan_t p = b->plans[rep[c]];
             hipStream_t st = b->aux[b->stream_of[rep[c]]];
             Partition* Pt = nullptr;
-            int rc = get_partition(p, p->nu_req, false, st, &Pt);
+            int rc = get_partition(p, p->nu2_req, false, st, &Pt);
             if (rc != NUHT_OK) return fail(rc);
             nuht_opts best;
             rc = tune_cached(p, nullptr, 3, &best, nullptr, st);
@@ -1589,12 +1901,12 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
     int rc = NUHT_OK;
     for (int i = 0; i < count && rc == NUHT_OK; ++i) {
         nuht_plan_t p = b->plans[i];
-        nuht_plan_s::OrderParts* op = order_parts(p, p->nu_req);
+        nuht_plan_s::OrderParts* op = order_parts(p, p->nu2_req);
         if (!op) { rc = NUHT_ENOMEM; break; }
         parts[i] = &op->f;
         pend[i].reset(new (std::nothrow) PendingPart());
         if (!pend[i]) { rc = NUHT_ENOMEM; break; }
-        rc = part_begin(p, *pend[i], *parts[i], p->fwd, p->nu_req, b->aux[b->stream_of[i]], &slots[i], true);
+        rc = part_begin(p, *pend[i], *parts[i], p->fwd, p->nu2_req, b->aux[b->stream_of[i]], &slots[i], true);
     }
     for (int k = 0; k < kBatchStreams && rc == NUHT_OK; ++k)
         if (!hip_ok(hipStreamSynchronize(b->aux[k]))) rc = NUHT_EHIP;
@@ -1603,7 +1915,7 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
         rc = part_finish(*pend[i], &slots[i], &again);
         while (rc == NUHT_OK && again) {   // tables too small: this one again, on its own
             hipStream_t st = b->aux[b->stream_of[i]];
-            rc = part_begin(b->plans[i], *pend[i], *parts[i], b->plans[i]->fwd, b->plans[i]->nu_req, st,
+            rc = part_begin(b->plans[i], *pend[i], *parts[i], b->plans[i]->fwd, b->plans[i]->nu2_req, st,
                             &slots[i], false);
             if (rc == NUHT_OK && !hip_ok(hipStreamSynchronize(st))) rc = NUHT_EHIP;
             if (rc == NUHT_OK) rc = part_finish(*pend[i], &slots[i], &again);
@@ -1717,7 +2029,8 @@ int nuht_plan_info(nuht_plan_t p, nuht_info* info)
     const PlanDev& P = Pt.P;
     const Summary& S = Pt.sum;
     std::memset(info, 0, sizeof(*info));
-    info->nu = p->nu_req; info->M = P.M; info->L = P.L; info->es_width = P.w;
+    info->nu = p->nu2_req >> 1; info->M = P.M; info->L = P.L; info->es_width = P.w;
+    info->half_order = p->nu2_req & 1;
     info->eps = P.eps; info->z = P.z; info->es_beta = P.beta;
     info->levels = S.levels; info->n_nodes = S.n_nodes; info->n_local = S.n_l; info->n_asy = S.n_a;
     info->n_direct = S.n_d; info->n_fft_blocks = S.n_fft;
@@ -1780,7 +2093,7 @@ int nuht_direct(int nu, double eps, int64_t n, const double* r_dev, const double
     hipStream_t s = (hipStream_t)stream;
     PlanDev P{};
     nuht_opts o{};
-    fill_params(P, nu, eps, o);
+    NUHT_TRY(fill_params(P, 2 * nu, eps, o));
     if (m == 0) return NUHT_OK;
     if (n == 0) { HIP_TRY(hipMemsetAsync(g_dev, 0, sizeof(double) * (size_t)m, s)); return NUHT_OK; }
     HIP_TRY(launch_direct(P, r_dev, c_dev, (int32_t)n, omega_dev, (int32_t)m, g_dev, s));

@@ -276,9 +276,85 @@ __device__ inline double besselj_core(int nu, double phi_hi, double phi_lo, doub
     return __builtin_fma(xl, d, j0) / sqrt(S);
 }
 
+// J_{n+1/2}(x) (n >= 0, phase offset -(n+1) pi/2 as phi_hi + phi_lo) to full
+// FP64 accuracy through the spherical Bessel function, J_{n+1/2}(x) =
+// sqrt(2x/pi) j_n(x) (DLMF 10.47.3):
+//   x >= 25 with Hankel's terms never above 1e3: Hankel's expansion, which ends
+//     at a_n at half-integer orders and is then exact;
+//   x > n + 1: the upward recurrence j_{k+1} = ((2k+1)/x) j_k - j_{k-1} from
+//     j_{-1} = cos x / x, j_0 = sin x / x (stable while k < x; the low part of
+//     x enters through the double-double sine and cosine);
+//   otherwise: Miller's backward recurrence with the same relation, normalised
+//     by sum_k (2k+1) j_k^2 = 1 (DLMF 10.60.11), scaled by exact powers of two,
+//     and the low part through J' = sqrt(2x/pi) (j_{n-1} - ((n + 1/2)/x) j_n).
+__device__ inline double besselj_half_core(int n, double phi_hi, double phi_lo, double xh, double xl)
+{
+    if (xh < 1e-300) return 0.0;
+    if (xh >= 25.0) {
+        const double mu = (2.0 * n + 1.0) * (2.0 * n + 1.0);
+        const double inv8x = 0.125 / xh;
+        double t = 1.0, p = 1.0, q = 0.0;
+        bool ok = true;
+        for (int k = 1; k <= n; ++k) {
+            const double f = 2.0 * k - 1.0;
+            t *= (mu - f * f) * inv8x * kInvInt[k];
+            if (fabs(t) > 1e3) { ok = false; break; }
+            const double sg = ((k >> 1) & 1) ? -1.0 : 1.0;       // (-1)^floor(k/2)
+            if (k & 1) q = __builtin_fma(sg, t, q);
+            else p = __builtin_fma(sg, t, p);
+        }
+        if (ok) {
+            dd ph = two_sum(xh, phi_hi);
+            double c, s;
+            cis_dd(ph.hi, ph.lo + xl + phi_lo, c, s);
+            return sqrt(2.0 / (kPi * xh)) * __builtin_fma(p, c, -q * s);
+        }
+    }
+    const double amp = sqrt(2.0 * xh / kPi);
+    const double inv = 1.0 / xh;
+    if (xh > n + 1.0) {
+        double c, s;
+        cis_dd(xh, xl, c, s);
+        double jm = c * inv, j = s * inv;                        // j_{-1}, j_0
+        for (int k = 0; k < n; ++k) {
+            const double jp = __builtin_fma((2.0 * k + 1.0) * inv, j, -jm);
+            jm = j;
+            j = jp;
+        }
+        return amp * j;
+    }
+    const int N = (int)(n + xh + 20.0 + 8.0 * cbrt(xh > 1.0 ? xh : 1.0));
+    double yk1 = 0.0, yk = 1e-100, S = 0.0, rn = 0.0, rnm1 = 0.0;
+    for (int k = N; k >= 0; --k) {
+        if (k == n) rn = yk;
+        if (k == n - 1) rnm1 = yk;
+        S = __builtin_fma((2.0 * k + 1.0) * yk, yk, S);
+        if (k == 0) break;
+        const double ykm1 = __builtin_fma((2.0 * k + 1.0) * inv, yk, -yk1);
+        yk1 = yk;
+        yk = ykm1;
+        if (fabs(yk) > 0x1p332) {
+            yk *= 0x1p-332; yk1 *= 0x1p-332; S *= 0x1p-664; rn *= 0x1p-332; rnm1 *= 0x1p-332;
+        }
+    }
+    const double lam = 1.0 / sqrt(S);
+    const double jn = rn * lam;
+    double jnm1;
+    if (n == 0) {
+        double c, s;
+        sincos_small(xh, &s, &c);                                // xh <= 1 here
+        jnm1 = c * inv;
+    } else {
+        jnm1 = rnm1 * lam;
+    }
+    const double d = amp * __builtin_fma(-(n + 0.5) * inv, jn, jnm1);
+    return __builtin_fma(xl, d, amp * jn);
+}
+
 // The same for the plan's order and phase offset.
 __device__ __forceinline__ double besselj_full(const PlanDev& P, double xh, double xl)
 {
+    if (P.half) return besselj_half_core(P.nu, P.phi_hi, P.phi_lo, xh, xl);
     return besselj_core(P.nu, P.phi_hi, P.phi_lo, xh, xl);
 }
 

@@ -18,6 +18,8 @@ constexpr int kMaxEsWidth = 18;        // largest ES kernel width
 constexpr int kEsDeg = 13;             // degree of the per-cell polynomial pieces of the ES kernel
 constexpr int kSpreadAnchors = 6;      // first cells (anchors) one matrix-core spreading item may hold
 constexpr int kMaxLevels = 4096;       // subdivision depth limit
+constexpr int kHalfDeg = 20;           // degree of the half-integer local coefficients on a panel
+constexpr double kHalfWidth = 4.0;     // panel width (in omega R) of those coefficients
 
 // A mixed block of Alg. 1 and the split chosen for it.  Rows j0..js and
 // columns k0..ks are the local (upper-left) side.  A wholly local block is
@@ -105,7 +107,9 @@ struct SmallFfts {
 // Everything the execution kernels need for one transform (passed by value to
 // the kernels of a single transform; kept in a device array for a batch).
 struct PlanDev {
-    int32_t n, m, nu, M, L, w;       // sizes, |order|, terms, local rank, ES width
+    int32_t n, m, nu, M, L, w;       // sizes, |order| (its integer part when half), terms, local rank, ES width
+    int32_t half, half_np;           // half = 1: the order is nu + 1/2; panels of the local coefficient table
+    int32_t half_ns, pad0;           // leading panels holding the coefficients divided by x^nu
     int32_t nch, sign;               // channels (2M padded to a kernel instance); (-1)^nu for negative orders, else 1
     int32_t fp32;                    // FP32 spreading (weights, kernel values and channel sums in float)
     int32_t mfma;                    // dense spreading items go to the matrix cores (FP64, w <= 16, nch <= 16)
@@ -130,6 +134,8 @@ struct PlanDev {
     const int32_t* fft_list;         // FFT-path blocks grouped by size class
     const int64_t* gslot;            // first grid slot of each asymptotic block; gslot[n_a] = all slots
     const double* es_poly;           // ES kernel pieces, w x (kEsDeg + 1) monomial coefficients
+    const double* half_tab;          // half-integer orders: [panel][l][degree] local coefficients
+    double half_inv_h;               // 1 / panel width
     int32_t n_nodes, n_l, n_a, n_d, n_litems, n_aitems, n_adense, pad1;
     // execution buffers of the partition
     double* cs;                      // weights gathered into sorted point order (n)

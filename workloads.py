@@ -14,6 +14,10 @@ benchmark configurations:
                     Chebyshev-clustered r on [0, 1], trapezoid weights w_k,
                     c_k = r_k w_k exp(-40 r_k^2) cos(30 r_k), log-spaced w on
                     [1e-2, 1e5] (stands in for the radial-FT study of Sec. 5.2)
+* ``radial_3d``     the radial Fourier transform in three dimensions (order
+                    1/2): the same points and frequencies, c_k = r_k^(3/2) w_k
+                    exp(-40 r_k^2) cos(30 r_k)  (F(omega) = (2 pi)^(3/2)
+                    omega^(-1/2) sum_k c_k J_{1/2}(omega r_k))
 * ``sparse_c``      c with a fixed number of N(0, 1) nonzeros at random indices
                     (the accuracy study of Sec. 5.1.3)
 * ``batch``         many independent transforms with uneven n, m and order
@@ -58,6 +62,20 @@ def radial_2d(n: int = 1_000_000, m: int = 1_000_000):
     wt[-1] = 0.5 * (r[-1] - r[-2])
     wt[1:-1] = 0.5 * (r[2:] - r[:-2])
     c = r * wt * np.exp(-40.0 * r * r) * np.cos(30.0 * r)
+    k = np.arange(m, dtype=np.float64)
+    w = 10.0 ** (-2.0 + 7.0 * k / (m - 1))
+    return r, w, c
+
+
+def radial_3d(n: int = 1_000_000, m: int = 1_000_000):
+    """Deterministic radial 3-D Fourier-transform workload (order 1/2)."""
+    i = np.arange(n, dtype=np.float64)
+    r = 0.5 * (1.0 - np.cos(np.pi * i / (n - 1)))
+    wt = np.empty(n)
+    wt[0] = 0.5 * (r[1] - r[0])
+    wt[-1] = 0.5 * (r[-1] - r[-2])
+    wt[1:-1] = 0.5 * (r[2:] - r[:-2])
+    c = r ** 1.5 * wt * np.exp(-40.0 * r * r) * np.cos(30.0 * r)
     k = np.arange(m, dtype=np.float64)
     w = 10.0 ** (-2.0 + 7.0 * k / (m - 1))
     return r, w, c
