@@ -1454,6 +1454,39 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
     return kSqrt2OverPi * amp * __builtin_fma(cr, ar, -ci * ai);
 }
 
+// ---------------------------------------------------------------------------
+// J_nu for the direct blocks.  Their entries lie along the curve omega r = z
+// (every direct block straddles it at the finest subdivision level), so the
+// plan carries a table of J_nu on panels of width kJtabWidth around z (built
+// on the host in extended precision): per panel the degree-15 Chebyshev
+// interpolant at the 16 Chebyshev points, stored as monomial coefficients in
+// the panel coordinate u in [-1, 1].  Arguments outside the table take
+// besselj_full.
+// ---------------------------------------------------------------------------
+// J_nu(xh + xl) from the table where it covers xh, else besselj_full.
+__device__ __forceinline__ double besselj_direct(const PlanDev& P, double xh, double xl)
+{
+    const double t = (xh - P.jtab_x0) * (1.0 / kJtabWidth);
+    if (t >= 0.0 && t < (double)P.jtab_np) {
+        const int p = (int)t;
+        // the panel's left end (exact), and xh - xs exactly (xs = 0 or xs <= xh <= 2 xs)
+        const double xs = __builtin_fma((double)p, kJtabWidth, P.jtab_x0);
+        const double u = ((xh - xs) - 1.0) + xl;
+        const double2* __restrict__ c = (const double2*)(P.jtab + (int64_t)p * kJtabCoef);
+        double2 a[kJtabCoef / 2];
+        #pragma unroll
+        for (int q = 0; q < kJtabCoef / 2; ++q) a[q] = c[q];
+        double v = a[kJtabCoef / 2 - 1].y;
+        #pragma unroll
+        for (int q = kJtabCoef / 2 - 1; q >= 0; --q) {
+            if (q < kJtabCoef / 2 - 1) v = __builtin_fma(v, u, a[q].y);
+            v = __builtin_fma(v, u, a[q].x);
+        }
+        return v;
+    }
+    return besselj_full(P, xh, xl);
+}
+
 // Direct blocks (entry by entry, J_nu to full precision).  One workgroup of
 // kDirectThreads lanes per block: each row of the block is given G lanes (G a
 // power of two up to 64, as many as fit), the lanes of a row sum strided
@@ -1480,7 +1513,7 @@ __device__ __forceinline__ void direct_body(const PlanDev& P, int bid)
             double om = P.ws[D.j0 + i];
             for (int k = gl; k < nb; k += G) {
                 dd x = two_prod(om, P.rs[D.k0 + k]);
-                acc = __builtin_fma(cs[D.k0 + k], besselj_full(P, x.hi, x.lo), acc);
+                acc = __builtin_fma(cs[D.k0 + k], besselj_direct(P, x.hi, x.lo), acc);
             }
         }
         for (int o = G >> 1; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);

@@ -391,6 +391,108 @@ static void half_table(int n, int L, double z, std::vector<double>& tab, int& np
     for (auto& th : pool) th.join();
 }
 
+// J_n(x), integer n >= 0, x >= 0, in extended precision: Miller's backward
+// recurrence J_{k-1} = (2k/x) J_k - J_{k+1} started well above max(x, n),
+// normalised by J_0^2 + 2 sum_{k>=1} J_k^2 = 1 (DLMF 10.23.3 with the
+// addition theorem at zero angle), rescaled by exact powers of ten before it
+// can overflow.
+static long double besselj_ld(int n, long double x)
+{
+    if (x == 0.0L) return n == 0 ? 1.0L : 0.0L;
+    const long double top = x > n ? x : (long double)n;
+    const int N = (int)(top + 30.0L + 15.0L * cbrtl(x > 1.0L ? x : 1.0L));
+    long double yk1 = 0.0L, yk = 1e-300L, S = 0.0L, jn = 0.0L;
+    for (int k = N; k >= 0; --k) {
+        if (k == n) jn = yk;
+        S += (k == 0 ? 1.0L : 2.0L) * yk * yk;
+        if (k == 0) break;
+        const long double ykm1 = (2.0L * k / x) * yk - yk1;
+        yk1 = yk;
+        yk = ykm1;
+        if (fabsl(yk) > 1e1000L) { yk *= 1e-1000L; yk1 *= 1e-1000L; S *= 1e-2000L; jn *= 1e-1000L; }
+    }
+    return jn / sqrtl(S);
+}
+
+// The direct-block table of order nu2 / 2 (nu2 odd: the half-integer order,
+// through J_{n+1/2}(x) = sqrt(2x/pi) j_n(x)): np panels of width kJtabWidth
+// from x0; entry [p][j] = coefficient of u^j, u in [-1, 1] across the panel,
+// of the degree kJtabCoef - 1 interpolant at the panel's Chebyshev points,
+// from samples, DCT and the change of basis in extended precision.
+static void jtab_host(int nu2, double x0, int np, std::vector<double>& tab)
+{
+    const int D = kJtabCoef;
+    const bool half = (nu2 & 1) != 0;
+    const int n = half ? (nu2 - 1) / 2 : std::abs(nu2 / 2);
+    tab.assign((size_t)np * D, 0.0);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    long double cs[4 * kJtabCoef];                   // cos(pi i / (2 D))
+    for (int i = 0; i < 4 * D; ++i) cs[i] = cosl(pi * i / (2.0L * D));
+    long double T[kJtabCoef][kJtabCoef] = {};        // T[k][j]: coefficient of u^j in T_k(u)
+    T[0][0] = 1.0L;
+    T[1][1] = 1.0L;
+    for (int k = 2; k < D; ++k)
+        for (int j = 0; j <= k; ++j) T[k][j] = (j > 0 ? 2.0L * T[k - 1][j - 1] : 0.0L) - T[k - 2][j];
+    auto panel = [&](int p) {
+        long double f[kJtabCoef], c[kJtabCoef];
+        const long double centre = (long double)x0 + kJtabWidth * (p + 0.5L);
+        for (int l = 0; l < D; ++l) {
+            const long double x = centre + 0.5L * kJtabWidth * cs[2 * l + 1];
+            f[l] = half ? sqrtl(2.0L * x / pi) * sph_jn_ld(n, x) : besselj_ld(n, x);
+        }
+        for (int k = 0; k < D; ++k) {
+            long double sm = 0.0L;
+            for (int l = 0; l < D; ++l) sm += f[l] * cs[(k * (2 * l + 1)) % (4 * D)];
+            c[k] = sm * (k == 0 ? 1.0L : 2.0L) / D;
+        }
+        for (int j = 0; j < D; ++j) {
+            long double a = 0.0L;
+            for (int k = D - 1; k >= j; --k) a += c[k] * T[k][j];
+            tab[(size_t)p * D + j] = (double)a;
+        }
+    };
+    const int nt = std::max(1, std::min({np / 8, 16, (int)std::thread::hardware_concurrency()}));
+    if (nt == 1) {
+        for (int p = 0; p < np; ++p) panel(p);
+        return;
+    }
+    std::vector<std::thread> pool;
+    std::atomic<int> next{0};
+    for (int t = 0; t < nt; ++t)
+        pool.emplace_back([&]() { for (int p; (p = next++) < np;) panel(p); });
+    for (auto& th : pool) th.join();
+}
+
+// The direct-block table of (nu2, x0, np) on the current device: built and
+// uploaded once per device and key, kept until the process ends.
+static const double* jtab_device(int nu2, double x0, int np)
+{
+    struct Entry {
+        int dev, nu2, np;
+        double x0;
+        const double* p;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Entry& e : cache)
+        if (e.dev == dev && e.nu2 == nu2 && e.np == np && e.x0 == x0) return e.p;
+    std::vector<double> host;
+    jtab_host(nu2, x0, np, host);
+    void* p = nullptr;
+    const size_t bytes = sizeof(double) * host.size();
+    if (hipMalloc(&p, bytes) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+    if (hipMemcpy(p, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(p);
+        return nullptr;
+    }
+    cache.push_back(Entry{dev, nu2, np, x0, (const double*)p});
+    return (const double*)p;
+}
+
 // The table of (n, L, z) on the current device: built and uploaded once per
 // device and key, kept until the process ends.
 static const double* half_table_device(int n, int L, double z, int* np_out, int* ns_out)
@@ -939,6 +1041,26 @@ static int fill_params(PlanDev& P, int nu2, double eps_req, const nuht_opts& o)
     return NUHT_OK;
 }
 
+// The direct-block J_nu table of P: panels of width kJtabWidth covering
+// [0.8 z - 8, 1.2 z + 8] rounded out to multiples of 32 (a direct block holds
+// entries on both sides of z, and at the finest subdivision level its entries
+// lie within a few percent of z; the rounding lets plans of nearby z share a
+// table); half-integer orders start at x = 8 or above, away from the branch
+// point of J at 0.
+static int direct_table(PlanDev& P)
+{
+    constexpr double q = 32.0;
+    double lo = std::max(0.0, std::floor((0.8 * P.z - 8.0) / q) * q);
+    if (P.half) lo = std::max(lo, 8.0);
+    const double hi = std::ceil((1.2 * P.z + 8.0) / q) * q;
+    P.jtab_x0 = lo;
+    P.jtab_np = hi > lo ? (int32_t)((hi - lo) / kJtabWidth) : 0;
+    P.jtab = nullptr;
+    if (P.jtab_np == 0) return NUHT_OK;
+    P.jtab = jtab_device(P.half ? 2 * P.nu + 1 : 2 * P.nu, lo, P.jtab_np);
+    return P.jtab ? NUHT_OK : NUHT_ENOMEM;
+}
+
 // Building a partition takes two steps around one host synchronisation:
 // part_begin fills the parameters, allocates the planning tables (with the
 // current capacity guesses), launches the planning kernels and queues the copy
@@ -968,6 +1090,7 @@ static int part_begin(nuht_plan_t pl, PendingPart& pp, Partition& Pt, const Geom
         P = PlanDev{};
         NUHT_TRY(fill_params(P, nu, pl->eps, pl->opts));
         if (P.L < 0) return NUHT_EINVAL;
+        NUHT_TRY(direct_table(P));
         P.n = G.n; P.m = G.m;
         P.rs = G.rs; P.ws = G.ws; P.perm_r = G.perm_r; P.perm_w = G.perm_w;
         Pt.sum = Summary{};

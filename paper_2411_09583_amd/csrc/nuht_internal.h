@@ -20,6 +20,8 @@ constexpr int kSpreadAnchors = 6;      // first cells (anchors) one matrix-core 
 constexpr int kMaxLevels = 4096;       // subdivision depth limit
 constexpr int kHalfDeg = 20;           // degree of the half-integer local coefficients on a panel
 constexpr double kHalfWidth = 4.0;     // panel width (in omega R) of those coefficients
+constexpr int kJtabCoef = 16;          // coefficients per panel of the direct-block J_nu table (degree 15)
+constexpr double kJtabWidth = 2.0;     // panel width (in x = omega r) of that table
 
 // A mixed block of Alg. 1 and the split chosen for it.  Rows j0..js and
 // columns k0..ks are the local (upper-left) side.  A wholly local block is
@@ -136,6 +138,10 @@ struct PlanDev {
     const double* es_poly;           // ES kernel pieces, w x (kEsDeg + 1) monomial coefficients
     const double* half_tab;          // half-integer orders: [panel][l][degree] local coefficients
     double half_inv_h;               // 1 / panel width
+    const double* jtab;              // J_nu on [jtab_x0, jtab_x0 + jtab_np kJtabWidth): per panel the
+                                     // monomial coefficients in u in [-1, 1] of its Chebyshev interpolant
+    double jtab_x0;
+    int32_t jtab_np, pad2;
     int32_t n_nodes, n_l, n_a, n_d, n_litems, n_aitems, n_adense, pad1;
     // execution buffers of the partition
     double* cs;                      // weights gathered into sorted point order (n)

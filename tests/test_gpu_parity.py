@@ -338,6 +338,53 @@ def test_gpu_besselj_pointwise(nuht, nu):
     assert np.all(err <= bound), (x[worst], g[worst], ref[worst])
 
 
+@pytest.mark.parametrize("nu", [0, 1, 10, 63, 100, 0.5, 3.5, 40.5])
+def test_direct_block_besselj(nuht, nu):
+    # Entries of direct blocks one by one: one point r = 1 with weight 1 and
+    # frequencies omega_0 = z / 4 (local) then x > z, with min_size above m,
+    # make every row after the first one direct block's row, so
+    # g_j = J_nu(omega_j) as the direct blocks evaluate it: from the plan's
+    # table (Chebyshev interpolants of J_nu on width-2 panels, built in
+    # extended precision) on [0.8 z - 8, 1.2 z + 8] rounded out to multiples
+    # of 32 (from 8 up at half-integer orders), beyond it from the
+    # full-precision routine.  Bars, env = min(1, sqrt(2 / (pi x))): inside
+    # the table |error| <= 1e-15 max(|J|, env) against mpmath (30 digits) on
+    # 300 sampled entries, and <= 2e-14 max(|J|, env) against the oracle's J
+    # on all (the oracle's own error reaches 1e-14 at order 63); outside it
+    # 2e-13 max(|J|, env) against the oracle (where Hankel's terms grow to
+    # ~1e3 before converging, the routine's error reaches ~1e-13 at order 100).
+    import mpmath as mp
+    M, z, L = oparams.any_parameters(nu, 1e-12)
+    rng = np.random.default_rng(int(2 * nu) + 77)
+    x = np.sort(np.concatenate([rng.uniform(z * (1 + 1e-9), 1.5 * z + 40.0, 3000),
+                                np.linspace(z * (1 + 1e-9), 1.25 * z + 8.0, 400),
+                                rng.uniform(1.5 * z + 40.0, 4.0 * z + 50.0, 200)]))
+    w = np.concatenate([[z / 4.0], x])
+    p = nuht.Plan(dev(np.ones(1)), dev(w), nu, 1e-12, min_size=10 ** 6)
+    g = host(p.execute(dev(np.ones(1))))[1:]
+    info = p.info()
+    p.close()
+    assert info["n_direct"] == 1 and info["n_asy"] == 0 and info["direct_entries"] == x.size
+    ref = direct.besselj(nu, x)
+    env = np.minimum(1.0, np.sqrt(2.0 / (np.pi * x)))
+    lo = max(0.0, np.floor((0.8 * z - 8.0) / 32.0) * 32.0)
+    if nu != int(nu):
+        lo = max(lo, 8.0)
+    hi = np.ceil((1.2 * z + 8.0) / 32.0) * 32.0
+    inside = (x >= lo) & (x < hi)
+    assert inside.sum() > 100 and (~inside).sum() > 100
+    err = np.abs(g - ref) / np.maximum(np.abs(ref), env)
+    sub = rng.choice(np.nonzero(inside)[0], 300, replace=False)
+    mp.mp.dps = 30
+    exact = np.array([float(mp.besselj(mp.mpf(int(2 * nu)) / 2, mp.mpf(v))) for v in x[sub]])
+    err_mp = np.abs(g[sub] - exact) / np.maximum(np.abs(exact), env[sub])
+    print(nu, "z", z, "inside", int(inside.sum()), "worst vs mpmath", err_mp.max(),
+          "worst inside vs oracle", err[inside].max(), "worst outside", err[~inside].max())
+    assert np.all(err_mp <= 1e-15), x[sub][np.argmax(err_mp)]
+    assert np.all(err[inside] <= 2e-14)
+    assert np.all(err[~inside] <= 2e-13)
+
+
 def test_largest_fft_and_grid_limit(nuht):
     # One wholly asymptotic block (every omega r > z) whose spread grid needs
     # the largest two-pass FFT (2^23 .. 2^24 points per channel): r in [1, 2],
