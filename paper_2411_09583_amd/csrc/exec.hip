@@ -1403,6 +1403,10 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
         const double er = c1 - tl * s1, ei = s1 + tl * c1;
         // Horner's rule in e^{i theta} from the last cell down
         for (int cix = B.N1 - 1; cix >= 0; --cix) {
+            // the channel sum with the powers of gamma as multiplicands (where
+            // the block is uniform across the wave the grid values come in
+            // scalar registers, and a scalar operand fits an FMA's
+            // multiplicand with no copy)
             const double2* gp = G + (int64_t)cix * NCH;
             double2 gv[NCH];
             #pragma unroll
@@ -1423,11 +1427,19 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
         double vl = v.lo + (sp.lo * B.Khi + sp.hi * B.Klo);
         int q0 = (int)ceil(v.hi - 0.5 * w);
         const int mask = B.N2 - 1;
-        const double two_over_w = 2.0 / w;
+        // tap t sits at offset t + f0 - w/2 from the target, f0 in [0, 1): its
+        // kernel value is piece t of the ES kernel at f0 (the pieces the
+        // spreading uses, w x (kEsDeg + 1) monomial coefficients in 2 f - 1;
+        // the table is uniform across the wave, so the coefficients are
+        // scalar operands)
+        const double* __restrict__ es_poly = P.es_poly;
+        const double sf = 2.0 * ((((double)q0 - v.hi) - vl) + 0.5 * w) - 1.0;
         for (int tap = 0; tap < w; ++tap) {
             int q = q0 + tap;
-            double x = (((double)q - v.hi) - vl) * two_over_w;
-            double psi = es_kernel(x, P.beta);
+            const double* cf = es_poly + tap * (kEsDeg + 1);
+            double psi = cf[kEsDeg];
+            #pragma unroll
+            for (int d = kEsDeg - 1; d >= 0; --d) psi = __builtin_fma(psi, sf, cf[d]);
             int qi = q & mask;
             // Horner's rule in gamma from the highest channel: the loaded values
             // (vector registers here) are the addends

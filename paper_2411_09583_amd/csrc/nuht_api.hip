@@ -803,6 +803,14 @@ struct Partition {
     int64_t bytes = 0;
     hipStream_t stream = nullptr;   // where this partition's memory lives
 
+    // Hands the device buffers to `out` (whoever frees them) and resets.
+    void take_bufs(std::vector<DevBuf>& out)
+    {
+        for (auto& b : bufs) out.push_back(b);
+        bufs.clear();
+        release();
+    }
+
     void release()
     {
         for (auto& b : bufs) dev_free(b);
@@ -1245,16 +1253,83 @@ static void note_use(nuht_plan_t p, hipStream_t s)
     else (void)hipGetLastError();
 }
 
+static hipStream_t plan_stream();
+
+// Memory of plans released while their last use on a caller stream may still
+// be running: kept with that use's event and freed, on the library's planning
+// stream, once the event has completed (checked whenever a plan is made or
+// released).  Ordering the frees behind the use on the planning stream
+// instead would make the next plan's work wait for this execution.
+struct Retired {
+    int dev = 0;
+    hipEvent_t ev = nullptr;
+    hipStream_t stream = nullptr;
+    std::vector<DevBuf> bufs;
+};
+
+static std::mutex retired_mu;
+static std::vector<Retired> retired;
+
+static void reap_retired()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); return; }
+    std::lock_guard<std::mutex> lock(retired_mu);
+    for (size_t i = 0; i < retired.size();) {
+        Retired& r = retired[i];
+        // anything but "not ready" ends the wait (an error leaves nothing to protect)
+        const bool done = r.dev == dev && hipEventQuery(r.ev) != hipErrorNotReady;
+        (void)hipGetLastError();
+        if (!done) { ++i; continue; }
+        for (DevBuf& b : r.bufs) {
+            if (b.p) {
+                if (b.stream || device_pool()) (void)hipFreeAsync(b.p, r.stream);
+                else (void)hipFree(b.p);
+            }
+        }
+        (void)hipEventDestroy(r.ev);
+        retired[i] = std::move(retired.back());
+        retired.pop_back();
+    }
+}
+
 static void free_plan(nuht_plan_t p)
 {
     if (!p) return;
     prof_clear(p);
+    hipStream_t ls = nullptr;
+    if (p->used && p->ev_use && hipEventQuery(p->ev_use) == hipErrorNotReady && (ls = plan_stream()) != nullptr) {
+        (void)hipGetLastError();
+        Retired r;
+        (void)hipGetDevice(&r.dev);
+        r.ev = p->ev_use;
+        r.stream = ls;
+        for (auto& o : p->orders) {
+            o->f.take_bufs(r.bufs);
+            o->a.take_bufs(r.bufs);
+        }
+        for (DevBuf* b : {&p->b_grad, &p->b_geom}) {
+            if (b->p) r.bufs.push_back(*b);
+            *b = DevBuf{};
+        }
+        p->ev_use = nullptr;
+        p->orders.clear();
+        {
+            std::lock_guard<std::mutex> lock(retired_mu);
+            retired.push_back(std::move(r));
+        }
+        delete p;
+        reap_retired();
+        return;
+    }
+    (void)hipGetLastError();
     before_free(p);
     p->orders.clear();
     dev_free(p->b_grad);
     dev_free(p->b_geom);
     if (p->ev_use) (void)hipEventDestroy(p->ev_use);
     delete p;
+    reap_retired();
 }
 
 // The library's planning stream of the current device (default priority).
@@ -1401,6 +1476,7 @@ static int plan_create(nuht_plan_t* out, int nu2, double eps, int64_t n, const d
 {
     *out = nullptr;
     NUHT_TRY(check_plan_args(nu2, eps, n, r_dev, m, omega_dev, o));
+    reap_retired();
     nuht_plan_s* p = new (std::nothrow) nuht_plan_s();
     if (!p) return NUHT_ENOMEM;
     p->nu2_req = nu2; p->eps = eps; p->opts = o; p->n = n; p->m = m;

@@ -28,8 +28,10 @@ __global__ void k_make_keys(const double* __restrict__ x, int32_t n, uint64_t* _
 // Segment s owns tiles [tile0[s], tile0[s+1]) and elements [off[s], off[s+1]).
 // ---------------------------------------------------------------------------
 constexpr int kSortThreads = 256;
-constexpr int kSortRounds = 16;
+constexpr int kSortRounds = 8;
 constexpr int kSortTile = kSortThreads * kSortRounds;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kSortWaveRounds = kSortTile / kSortThreads;   // 64-key rounds per wave (= kSortRounds)
 
 // Orders one wave's LDS accesses around it (lanes read a counter that one
 // lane of the same wave then updates).
@@ -51,24 +53,51 @@ __device__ __forceinline__ int tile_segment(const SortSegs& S, int tile)
     return tile >= S.tile0[1] ? 1 : 0;
 }
 
+// Lanes of the wave whose digit d equals the calling lane's (8 ballots, one
+// per bit), among the lanes with `valid` set.
+__device__ __forceinline__ uint64_t digit_peers(int d, bool valid)
+{
+    uint64_t peers = __ballot(valid);
+    #pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        uint64_t m = __ballot((d >> b) & 1);
+        peers &= ((d >> b) & 1) ? m : ~m;
+    }
+    return peers;
+}
+
+// Digit counts of one tile.  Wave v counts the keys v * 512 .. v * 512 + 511
+// of the tile, all loaded first; in each 64-key round the lowest lane of each
+// group of equal digits adds the group's size, so a digit shared by the whole
+// round (the high bytes of clustered keys) costs one LDS atomic, not 64.
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t* __restrict__ key, SortSegs S,
                                                              int shift, int32_t* __restrict__ hist)
 {
     __shared__ int32_t h[256];
-    int tile = blockIdx.x;
-    int seg = tile_segment(S, tile);
-    int lt = tile - S.tile0[seg];
-    int ntiles = S.tile0[seg + 1] - S.tile0[seg];
-    int base = S.off[seg] + lt * kSortTile;
-    int end = S.off[seg + 1];
+    const int tile = blockIdx.x;
+    const int seg = tile_segment(S, tile);
+    const int lt = tile - S.tile0[seg];
+    const int ntiles = S.tile0[seg + 1] - S.tile0[seg];
+    const int end = S.off[seg + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wbase = S.off[seg] + lt * kSortTile + wave * 64 * kSortWaveRounds;
+    int dg[kSortWaveRounds];
+    #pragma unroll
+    for (int r = 0; r < kSortWaveRounds; ++r) {
+        const int i = wbase + r * 64 + lane;
+        dg[r] = i < end ? (int)((key[i] >> shift) & 255) : -1;
+    }
     h[threadIdx.x] = 0;
     __syncthreads();
-    for (int r = 0; r < kSortRounds; ++r) {
-        int i = base + r * kSortThreads + threadIdx.x;
-        if (i < end) atomicAdd(&h[(key[i] >> shift) & 255], 1);
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    #pragma unroll
+    for (int r = 0; r < kSortWaveRounds; ++r) {
+        const bool valid = dg[r] >= 0;
+        const uint64_t peers = digit_peers(dg[r], valid);
+        if (valid && (peers & lt_mask) == 0) atomicAdd(&h[dg[r]], (int32_t)__popcll(peers));
     }
     __syncthreads();
-    hist[S.hoff[seg] + threadIdx.x * ntiles + lt] = h[threadIdx.x];
+    hist[S.hoff[seg] + lt * 256 + threadIdx.x] = h[threadIdx.x];   // tile-major: one contiguous row
 }
 
 // ---------------------------------------------------------------------------
@@ -118,29 +147,43 @@ __device__ void block_scan(T (&v)[NV], T (&tot)[NV], T (*wsum)[16])
     __syncthreads();
 }
 
-// Per-digit scan of the tile counts: one block per (segment, digit) turns the
-// digit's row of tile counts into exclusive offsets within the digit and
-// stores the digit's total; the scatter adds the digits' own offsets.
-__global__ __launch_bounds__(1024) void k_sort_scan(int32_t* __restrict__ hist, int32_t* __restrict__ dtot,
-                                                    SortSegs S)
+// Per-digit scan of the tile counts (stored tile-major: each tile's 256
+// counts are one contiguous row, written and read whole by the tile's own
+// histogram and scatter workgroups): one wave per (segment, digit) turns the
+// digit's column of tile counts into exclusive offsets within the digit and
+// stores the digit's total; the scatter adds the digits' own offsets.  The
+// column is read 64 tiles at a time, all chunks' loads issued first.
+constexpr int kScanChunks = 16;   // rows up to 1024 tiles in registers; longer rows loop
+
+__global__ __launch_bounds__(256) void k_sort_scan(int32_t* __restrict__ hist, int32_t* __restrict__ dtot,
+                                                   SortSegs S)
 {
-    __shared__ int32_t wsum[1][16];
-    int seg = blockIdx.x >> 8, d = blockIdx.x & 255;
-    int ntiles = S.tile0[seg + 1] - S.tile0[seg];
-    int32_t* h = hist + S.hoff[seg] + d * ntiles;
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);   // seg * 256 + digit
+    const int seg = row >> 8, d = row & 255;
+    const int ntiles = S.tile0[seg + 1] - S.tile0[seg];
+    int32_t* h = hist + S.hoff[seg] + d;     // tile i's count at h[256 i]
     int32_t run = 0;
-    for (int c0 = 0; c0 < ntiles; c0 += 1024) {
-        int i = c0 + threadIdx.x;
-        int32_t v[1] = {i < ntiles ? h[i] : 0}, tot[1];
-        block_scan<int32_t, 1>(v, tot, wsum);
-        if (i < ntiles) h[i] = run + v[0];
-        run += tot[0];
+    for (int c0 = 0; c0 < ntiles; c0 += 64 * kScanChunks) {
+        int32_t v[kScanChunks];
+        #pragma unroll
+        for (int q = 0; q < kScanChunks; ++q) {
+            const int i = c0 + q * 64 + lane;
+            v[q] = i < ntiles ? h[(int64_t)i * 256] : 0;
+        }
+        #pragma unroll
+        for (int q = 0; q < kScanChunks; ++q) {
+            const int i = c0 + q * 64 + lane;
+            const int32_t incl = wave_incl_scan(v[q]);
+            if (i < ntiles) h[(int64_t)i * 256] = run + incl - v[q];
+            run += __shfl(incl, 63);
+        }
     }
-    if (threadIdx.x == 0) dtot[seg * 256 + d] = run;
+    if (lane == 0) dtot[row] = run;
 }
 
 // Stable scatter through LDS.  Wave v of the block owns the tile's keys
-// v * 1024 .. v * 1024 + 1023 (in order), taken 64 at a time: each key is
+// v * 512 .. v * 512 + 511 (in order), taken 64 at a time: each key is
 // ranked among the equal digits of its 64 with wave ballots, plus the count
 // of that digit in the wave's earlier keys (a wave-private counter in LDS, so
 // no block barrier per round).  One block step then turns the four waves'
@@ -149,9 +192,6 @@ __global__ __launch_bounds__(1024) void k_sort_scan(int32_t* __restrict__ hist, 
 // differences of consecutive tile offsets in the scanned histogram).  The
 // finished tile is written out with consecutive threads on consecutive
 // addresses of each digit's run.
-constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kSortWaveRounds = kSortTile / kSortThreads;   // 64-key rounds per wave (= kSortRounds)
-
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* __restrict__ kin,
                                                                 const int32_t* __restrict__ vin,
                                                                 uint64_t* __restrict__ kout,
@@ -186,10 +226,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
     }
     {
         const int d = threadIdx.x;
-        const int32_t* hd = hist + S.hoff[seg] + d * ntiles;
+        const int32_t* hd = hist + S.hoff[seg] + (int64_t)lt * 256 + d;
         const int32_t tot = dtot[seg * 256 + d];
-        const int32_t mine = hd[lt];
-        const int32_t cnt = (lt + 1 < ntiles ? hd[lt + 1] : tot) - mine;
+        const int32_t mine = hd[0];
+        const int32_t cnt = (lt + 1 < ntiles ? hd[256] : tot) - mine;
         // exclusive scans over the digits of the segment totals and of the
         // tile counts (256 threads = 4 waves)
         int32_t it = tot, ic = cnt;
@@ -216,12 +256,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
         const int i = wbase + r * 64 + lane;
         const bool valid = i < end;
         const int d = (int)((kr[r] >> shift) & 255);
-        uint64_t peers = __ballot(valid);
-        #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            uint64_t m = __ballot((d >> b) & 1);
-            peers &= ((d >> b) & 1) ? m : ~m;
-        }
+        const uint64_t peers = digit_peers(d, valid);
         const int rank = __popcll(peers & lt_mask);
         const int32_t before = valid ? cw[d] : 0;
         wave_sync_lds();
@@ -275,15 +310,47 @@ __device__ __forceinline__ bool exact_le(double a, double b, double z)
     return p.lo <= 0.0;
 }
 
-__global__ void k_staircase(const double* __restrict__ sorted, int32_t len, const double* __restrict__ q, int32_t nq,
-                            double z, int32_t* __restrict__ out)
+// One wave per 64 consecutive queries.  The queries are sorted, so the counts
+// are nonincreasing along the wave: the counts of the wave's first and last
+// queries come first, each from a 32-ary search by one half of the wave (32
+// probes per step split the range into 33 parts), then every lane finishes
+// with a binary search inside that bracket (a few steps where the sorted
+// points are spread evenly).
+__global__ __launch_bounds__(256) void k_staircase(const double* __restrict__ sorted, int32_t len,
+                                                   const double* __restrict__ q, int32_t nq, double z,
+                                                   int32_t* __restrict__ out)
 {
-    int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nq) return;
-    double w = q[j];
+    const int lane = threadIdx.x & 63;
+    const int32_t j0 = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) & ~63u);
+    if (j0 >= nq) return;                              // the whole wave
+    const int32_t jl = j0 + 63 < nq ? j0 + 63 : nq - 1;
+    const int half = lane >> 5, hl = lane & 31;
+    const double wt = q[half ? jl : j0];
+    // the count (first index whose product exceeds z) lies in [lo, hi]
     int32_t lo = 0, hi = len;
+    while (hi - lo > 32) {
+        const int64_t span = hi - lo;
+        const int32_t pos = lo + (int32_t)(((int64_t)(hl + 1) * span) / 33);   // lo < pos < hi
+        const uint64_t b = __ballot(exact_le(wt, sorted[pos], z));
+        const int c = __popc(half ? (uint32_t)(b >> 32) : (uint32_t)b);        // probes at or below z
+        const int32_t nlo = c > 0 ? lo + (int32_t)(((int64_t)c * span) / 33) + 1 : lo;
+        const int32_t nhi = c < 32 ? lo + (int32_t)(((int64_t)(c + 1) * span) / 33) : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    {
+        const int32_t pos = lo + hl;
+        const uint64_t b = __ballot(pos < hi && exact_le(wt, sorted[pos], z));
+        lo += __popc(half ? (uint32_t)(b >> 32) : (uint32_t)b);
+    }
+    const int32_t top = __shfl(lo, 0), bottom = __shfl(lo, 32);
+    const int32_t j = j0 + lane;
+    if (j > jl) return;
+    const double w = q[j];
+    lo = bottom;
+    hi = top;
     while (lo < hi) {
-        int32_t mid = lo + ((hi - lo) >> 1);
+        const int32_t mid = lo + ((hi - lo) >> 1);
         if (exact_le(w, sorted[mid], z)) lo = mid + 1; else hi = mid;
     }
     out[j] = lo;
@@ -773,7 +840,7 @@ hipError_t launch_sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v
     for (int pass = 0; pass < 8; ++pass) {
         int shift = 8 * pass;
         hipLaunchKernelGGL(k_sort_hist, dim3(ta + tb), dim3(kSortThreads), 0, s, kin, S, shift, hist);
-        hipLaunchKernelGGL(k_sort_scan, dim3(2 * 256), dim3(1024), 0, s, hist, hist + S.hoff[2], S);
+        hipLaunchKernelGGL(k_sort_scan, dim3(2 * 256 / 4), dim3(256), 0, s, hist, hist + S.hoff[2], S);
         hipLaunchKernelGGL(k_sort_scatter, dim3(ta + tb), dim3(kSortThreads), 0, s, kin, vin, kout, vout, S, shift,
                            hist, hist + S.hoff[2]);
         uint64_t* tk = kin; kin = kout; kout = tk;
