@@ -1427,19 +1427,26 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
         double vl = v.lo + (sp.lo * B.Khi + sp.hi * B.Klo);
         int q0 = (int)ceil(v.hi - 0.5 * w);
         const int mask = B.N2 - 1;
-        // tap t sits at offset t + f0 - w/2 from the target, f0 in [0, 1): its
-        // kernel value is piece t of the ES kernel at f0 (the pieces the
-        // spreading uses, w x (kEsDeg + 1) monomial coefficients in 2 f - 1;
-        // the table is uniform across the wave, so the coefficients are
-        // scalar operands)
+        // Tap t sits at offset t + f0 - w/2 from the target, f0 in [0, 1).  At
+        // ten channels and more its kernel value is piece t of the ES kernel at
+        // f0 (the pieces the spreading uses, w x (kEsDeg + 1) monomial
+        // coefficients in 2 f - 1, scalar operands as the table is uniform):
+        // that frees the registers the exponential needs, which would spill
+        // there.  Below ten channels nothing spills and exp is the faster.
         const double* __restrict__ es_poly = P.es_poly;
         const double sf = 2.0 * ((((double)q0 - v.hi) - vl) + 0.5 * w) - 1.0;
+        const double two_over_w = 2.0 / w;
         for (int tap = 0; tap < w; ++tap) {
             int q = q0 + tap;
-            const double* cf = es_poly + tap * (kEsDeg + 1);
-            double psi = cf[kEsDeg];
-            #pragma unroll
-            for (int d = kEsDeg - 1; d >= 0; --d) psi = __builtin_fma(psi, sf, cf[d]);
+            double psi;
+            if constexpr (NCH >= 10) {
+                const double* cf = es_poly + tap * (kEsDeg + 1);
+                psi = cf[kEsDeg];
+                #pragma unroll
+                for (int d = kEsDeg - 1; d >= 0; --d) psi = __builtin_fma(psi, sf, cf[d]);
+            } else {
+                psi = es_kernel((((double)q - v.hi) - vl) * two_over_w, P.beta);
+            }
             int qi = q & mask;
             // Horner's rule in gamma from the highest channel: the loaded values
             // (vector registers here) are the addends

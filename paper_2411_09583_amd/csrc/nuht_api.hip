@@ -771,11 +771,61 @@ static hipMemPool_t device_pool()
     return pools[dev];
 }
 
+// Device blocks of released plans whose every use has completed, kept for
+// reuse by later plans: taking one costs no HIP call, where an allocation from
+// the stream-ordered pool costs tens of microseconds of host time (a plan
+// makes three).  A request takes the smallest cached block of at least its
+// size and at most twice it (plus 64 MiB); at most kBlockCacheCap bytes are
+// kept, blocks beyond that go back to the pool.
+struct CachedBlock {
+    int dev;
+    void* p;
+    size_t bytes;
+};
+static std::mutex block_mu;
+static std::vector<CachedBlock> block_cache;
+static size_t block_cached = 0;
+constexpr size_t kBlockCacheCap = size_t(16) << 30;
+
+static bool block_take(int dev, size_t bytes, void** p, size_t* got)
+{
+    std::lock_guard<std::mutex> lock(block_mu);
+    size_t best = block_cache.size();
+    for (size_t i = 0; i < block_cache.size(); ++i) {
+        const CachedBlock& c = block_cache[i];
+        if (c.dev != dev || c.bytes < bytes || c.bytes > 2 * bytes + (size_t(64) << 20)) continue;
+        if (best == block_cache.size() || c.bytes < block_cache[best].bytes) best = i;
+    }
+    if (best == block_cache.size()) return false;
+    *p = block_cache[best].p;
+    *got = block_cache[best].bytes;
+    block_cached -= *got;
+    block_cache[best] = block_cache.back();
+    block_cache.pop_back();
+    return true;
+}
+
+static bool block_put(int dev, void* p, size_t bytes)
+{
+    std::lock_guard<std::mutex> lock(block_mu);
+    if (block_cached + bytes > kBlockCacheCap) return false;
+    block_cache.push_back(CachedBlock{dev, p, bytes});
+    block_cached += bytes;
+    return true;
+}
+
 static int dev_alloc(DevBuf& b, size_t bytes, hipStream_t s)
 {
     b = DevBuf{};
     if (bytes == 0) return NUHT_OK;
     void* p = nullptr;
+    int dev = 0;
+    size_t got = 0;
+    if (hipGetDevice(&dev) == hipSuccess && block_take(dev, bytes, &p, &got)) {
+        b.p = p; b.bytes = got; b.stream = s;   // every earlier use has completed
+        return NUHT_OK;
+    }
+    (void)hipGetLastError();
     hipMemPool_t pool = device_pool();
     hipError_t e = pool ? hipMallocFromPoolAsync(&p, bytes, pool, s) : hipMalloc(&p, bytes);
     if (e != hipSuccess) { (void)hipGetLastError(); return NUHT_ENOMEM; }
@@ -914,6 +964,7 @@ struct nuht_plan_s {
     // plan frees is ordered after it.
     hipStream_t ps = nullptr;
     hipEvent_t ev_use = nullptr;
+    hipEvent_t ev_plan = nullptr;  // marks the planning stream's queued work when the plan is released
     bool used = false;
     DevBuf b_geom;               // keys, values, sort scratch, summary, flag
     uint64_t* keys = nullptr;    // sorted points then sorted frequencies (bit patterns)
@@ -922,7 +973,9 @@ struct nuht_plan_s {
     int32_t* vals2 = nullptr;
     int32_t* hist = nullptr;
     Summary* d_sum = nullptr;
-    int32_t* d_flag = nullptr;   // domain error flag of the input check
+    int32_t* d_flag = nullptr;   // domain error flag of the input check (plans with n = 0 or m = 0)
+    int32_t* errs = nullptr;     // per sort tile: 1 if the tile holds an invalid input
+    int32_t n_errs = 0;
     int64_t geom_bytes = 0;
     Geometry fwd, adj;
     // Partitions by order: forward and transposed, built on first use and kept
@@ -1110,7 +1163,12 @@ static int part_begin(nuht_plan_t pl, PendingPart& pp, Partition& Pt, const Geom
         pp.icap = (int32_t)std::min<int64_t>(64 * (tot / P.spread_chunk) + 2 * (int64_t)pp.cap, 1 << 28);
     }
     if (G.n == 0 || G.m == 0) {
-        HIP_TRY(hipMemcpyAsync(&h->flag, pl->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (pl->n_errs > 0) {
+            HIP_TRY(launch_reduce_errs(pl->errs, pl->n_errs, pl->d_flag, s));
+            HIP_TRY(hipMemcpyAsync(&h->flag, pl->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        } else {
+            h->flag = 0;
+        }
         return NUHT_OK;
     }
     const nuht_opts& o = pl->opts;
@@ -1144,10 +1202,9 @@ static int part_begin(nuht_plan_t pl, PendingPart& pp, Partition& Pt, const Geom
     NUHT_TRY(slab.commit(pp.tmp));
     P.nodes = A.nodes; P.lb = A.lb; P.ab = A.ab; P.db = A.db;
     P.litems = A.litems; P.aitems = A.aitems; P.alist = A.alist; P.fft_list = A.fft_list; P.gslot = A.gslot;
-    HIP_TRY(hipMemsetAsync(pl->d_sum, 0, sizeof(Summary), s));
-    HIP_TRY(launch_planning(P, A, K, Jc, a_cells, min_size, ncand, dft_max, sigma, pl->d_sum, s));
+    HIP_TRY(launch_planning(P, A, K, Jc, a_cells, min_size, ncand, dft_max, sigma, pl->d_sum, pl->errs, pl->n_errs,
+                            s));
     HIP_TRY(hipMemcpyAsync(&h->sum, pl->d_sum, sizeof(Summary), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&h->flag, pl->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     return NUHT_OK;
 }
 
@@ -1159,11 +1216,12 @@ static int part_finish(PendingPart& pp, const HostStage* h, bool* again)
     Partition& Pt = *pp.Pt;
     const Geometry& G = *pp.G;
     PlanDev& P = Pt.P;
-    if (h->flag) return NUHT_EDOMAIN;
     if (G.n == 0 || G.m == 0) {
+        if (h->flag) return NUHT_EDOMAIN;
         Pt.built = true;
         return NUHT_OK;
     }
+    if (h->sum.domain_error) return NUHT_EDOMAIN;
     Summary& S = Pt.sum;
     S = h->sum;
     if (S.overflow == 2) return NUHT_ECAPACITY;   // subdivision deeper than kMaxLevels
@@ -1255,15 +1313,16 @@ static void note_use(nuht_plan_t p, hipStream_t s)
 
 static hipStream_t plan_stream();
 
-// Memory of plans released while their last use on a caller stream may still
-// be running: kept with that use's event and freed, on the library's planning
-// stream, once the event has completed (checked whenever a plan is made or
-// released).  Ordering the frees behind the use on the planning stream
-// instead would make the next plan's work wait for this execution.
+// Memory of released plans: kept with the events that mark its last uses
+// (the last execution on a caller stream, the work queued on the planning
+// stream) and, once both have completed, put in the block cache (or freed on
+// the library's planning stream).  Releasing a plan therefore never makes the
+// planning stream wait for an execution, and the next plan reuses the memory
+// without an allocation call.  Completion is checked whenever a plan is made
+// or released.
 struct Retired {
     int dev = 0;
-    hipEvent_t ev = nullptr;
-    hipStream_t stream = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
     std::vector<DevBuf> bufs;
 };
 
@@ -1274,36 +1333,51 @@ static void reap_retired()
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); return; }
+    hipStream_t ls = plan_stream();
     std::lock_guard<std::mutex> lock(retired_mu);
     for (size_t i = 0; i < retired.size();) {
         Retired& r = retired[i];
-        // anything but "not ready" ends the wait (an error leaves nothing to protect)
-        const bool done = r.dev == dev && hipEventQuery(r.ev) != hipErrorNotReady;
+        // anything but "not ready" ends a wait (an error leaves nothing to protect)
+        bool done = r.dev == dev;
+        for (hipEvent_t e : r.ev)
+            if (done && e && hipEventQuery(e) == hipErrorNotReady) done = false;
         (void)hipGetLastError();
         if (!done) { ++i; continue; }
         for (DevBuf& b : r.bufs) {
-            if (b.p) {
-                if (b.stream || device_pool()) (void)hipFreeAsync(b.p, r.stream);
-                else (void)hipFree(b.p);
-            }
+            if (!b.p || block_put(r.dev, b.p, b.bytes)) continue;
+            if (b.stream || device_pool()) (void)hipFreeAsync(b.p, ls);
+            else (void)hipFree(b.p);
         }
-        (void)hipEventDestroy(r.ev);
+        for (hipEvent_t e : r.ev)
+            if (e) (void)hipEventDestroy(e);
         retired[i] = std::move(retired.back());
         retired.pop_back();
     }
+    (void)hipGetLastError();
 }
 
 static void free_plan(nuht_plan_t p)
 {
     if (!p) return;
     prof_clear(p);
-    hipStream_t ls = nullptr;
-    if (p->used && p->ev_use && hipEventQuery(p->ev_use) == hipErrorNotReady && (ls = plan_stream()) != nullptr) {
-        (void)hipGetLastError();
-        Retired r;
-        (void)hipGetDevice(&r.dev);
-        r.ev = p->ev_use;
-        r.stream = ls;
+    Retired r;
+    bool retire = hipGetDevice(&r.dev) == hipSuccess && plan_stream() != nullptr;
+    if (retire && p->ps) {
+        // the planning stream's queued work (none after a completed plan, but a
+        // plan that failed midway may leave some)
+        if (p->ev_plan && hipEventRecord(p->ev_plan, p->ps) == hipSuccess) {
+            r.ev[0] = p->ev_plan;
+            p->ev_plan = nullptr;
+        } else if (hipStreamSynchronize(p->ps) != hipSuccess) {
+            retire = false;
+        }
+    }
+    (void)hipGetLastError();
+    if (retire) {
+        if (p->used && p->ev_use) {
+            r.ev[1] = p->ev_use;
+            p->ev_use = nullptr;
+        }
         for (auto& o : p->orders) {
             o->f.take_bufs(r.bufs);
             o->a.take_bufs(r.bufs);
@@ -1312,22 +1386,23 @@ static void free_plan(nuht_plan_t p)
             if (b->p) r.bufs.push_back(*b);
             *b = DevBuf{};
         }
-        p->ev_use = nullptr;
         p->orders.clear();
+        if (p->ev_use) (void)hipEventDestroy(p->ev_use);
+        if (p->ev_plan) (void)hipEventDestroy(p->ev_plan);
+        delete p;
         {
             std::lock_guard<std::mutex> lock(retired_mu);
             retired.push_back(std::move(r));
         }
-        delete p;
         reap_retired();
         return;
     }
-    (void)hipGetLastError();
     before_free(p);
     p->orders.clear();
     dev_free(p->b_grad);
     dev_free(p->b_geom);
     if (p->ev_use) (void)hipEventDestroy(p->ev_use);
+    if (p->ev_plan) (void)hipEventDestroy(p->ev_plan);
     delete p;
     reap_retired();
 }
@@ -1490,6 +1565,11 @@ static int plan_create(nuht_plan_t* out, int nu2, double eps, int64_t n, const d
         p->ev_use = nullptr;
         return fail(NUHT_EHIP);
     }
+    if (hipEventCreateWithFlags(&p->ev_plan, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        p->ev_plan = nullptr;
+        return fail(NUHT_EHIP);
+    }
     if (wait_on) {
         if (hipEventRecord(p->ev_use, wait_on) != hipSuccess) return fail(NUHT_EHIP);
         if (hipStreamWaitEvent(s, p->ev_use, 0) != hipSuccess) return fail(NUHT_EHIP);
@@ -1498,6 +1578,8 @@ static int plan_create(nuht_plan_t* out, int nu2, double eps, int64_t n, const d
         Slab slab;
         slab.add(p->d_sum, 1);
         slab.add(p->d_flag, 1);
+        p->n_errs = sort_tiles((int32_t)n, (int32_t)m);
+        slab.add(p->errs, (size_t)p->n_errs);
         if (tot > 0) {
             slab.add(p->keys, (size_t)tot);
             slab.add(p->vals, (size_t)tot);
@@ -1508,11 +1590,8 @@ static int plan_create(nuht_plan_t* out, int nu2, double eps, int64_t n, const d
         if (slab.commit(p->b_geom, s) != NUHT_OK) return fail(NUHT_ENOMEM);
         p->geom_bytes = (int64_t)p->b_geom.bytes;
     }
-    if (hipMemsetAsync(p->d_flag, 0, sizeof(int32_t), s) != hipSuccess) return fail(NUHT_EHIP);
-    if (launch_make_keys(r_dev, (int32_t)n, p->keys, p->vals, p->d_flag, s) != hipSuccess) return fail(NUHT_EHIP);
-    if (launch_make_keys(omega_dev, (int32_t)m, p->keys + n, p->vals + n, p->d_flag, s) != hipSuccess)
-        return fail(NUHT_EHIP);
-    if (launch_sort_pairs(p->keys, p->vals, p->keys2, p->vals2, p->hist, (int32_t)n, (int32_t)m, s) != hipSuccess)
+    if (launch_keys_and_sort(r_dev, (int32_t)n, omega_dev, (int32_t)m, p->keys, p->vals, p->keys2, p->vals2, p->hist,
+                             p->errs, s) != hipSuccess)
         return fail(NUHT_EHIP);
     p->fwd.n = (int32_t)n; p->fwd.m = (int32_t)m;
     p->fwd.rs = (const double*)p->keys;

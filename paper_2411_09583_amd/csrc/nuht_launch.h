@@ -30,15 +30,23 @@ struct Arena {
 };
 
 // planning (plan.hip)
-hipError_t launch_make_keys(const double* x, int32_t n, uint64_t* key, int32_t* val, int32_t* err, hipStream_t s);
-hipError_t launch_sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int32_t* hist, int32_t na,
-                             int32_t nb, hipStream_t s);
+// Keys (bit patterns) of r (na values) and w (nb values) sorted into (k0, v0)
+// with their caller indices, (k1, v1) and hist (sort_hist_len ints) as
+// scratch; errs[t] (sort_tiles entries) = 1 for each tile of the inputs that
+// holds a negative, NaN or infinite value, else 0.
+hipError_t launch_keys_and_sort(const double* r, int32_t na, const double* w, int32_t nb, uint64_t* k0, int32_t* v0,
+                                uint64_t* k1, int32_t* v1, int32_t* hist, int32_t* errs, hipStream_t s);
+int sort_tiles(int32_t na, int32_t nb);
 int sort_hist_len(int32_t na, int32_t nb);
+// *flag = 1 if any of errs[0 .. n-1] is set, else 0
+hipError_t launch_reduce_errs(const int32_t* errs, int32_t n, int32_t* flag, hipStream_t s);
 // Staircases, subdivision (Alg. 1), block parameters, work items and their
 // offsets, all on the device; counts and totals are left in *sum.
+// The summary is cleared first; its domain_error is set from the input
+// check's tile flags (errs, n_errs entries).
 hipError_t launch_planning(const PlanDev& P, const Arena& A, int32_t* K, int32_t* Jc, int32_t* a_cells,
                            int64_t min_size, int32_t ncand, int32_t dft_max, double sigma, Summary* sum,
-                           hipStream_t s);
+                           const int32_t* errs, int32_t n_errs, hipStream_t s);
 
 // execution (exec.hip)
 struct ExecBuffers {

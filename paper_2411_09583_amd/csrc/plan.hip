@@ -7,25 +7,11 @@
 namespace nuht {
 
 // ---------------------------------------------------------------------------
-// Keys: a nonnegative double's bit pattern, read as an unsigned integer, is
-// monotone in its value, so sorting the bits sorts the values.  -0.0 maps to 0.
-// Any negative, NaN or infinite input raises the domain flag.
-// ---------------------------------------------------------------------------
-__global__ void k_make_keys(const double* __restrict__ x, int32_t n, uint64_t* __restrict__ key,
-                            int32_t* __restrict__ val, int32_t* __restrict__ err)
-{
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double v = x[i];
-    bool ok = (v >= 0.0) && (v <= 1.7976931348623157e308);
-    if (!ok) atomicOr(err, 1);
-    key[i] = (v == 0.0 || !ok) ? 0ull : (uint64_t)__double_as_longlong(v);
-    val[i] = i;
-}
-
-// ---------------------------------------------------------------------------
-// LSD radix sort, 8-bit digits, of up to two independent segments at once.
-// Segment s owns tiles [tile0[s], tile0[s+1]) and elements [off[s], off[s+1]).
+// LSD radix sort, 8-bit digits, of two independent segments at once (the
+// points and the frequencies).  Segment s owns tiles [tile0[s], tile0[s+1])
+// and elements [off[s], off[s+1]).  Launches: the keys with the first pass's
+// per-tile digit counts, then per pass the counts (from the second pass on),
+// their scan and the scatter.
 // ---------------------------------------------------------------------------
 constexpr int kSortThreads = 256;
 constexpr int kSortRounds = 8;
@@ -66,29 +52,13 @@ __device__ __forceinline__ uint64_t digit_peers(int d, bool valid)
     return peers;
 }
 
-// Digit counts of one tile.  Wave v counts the keys v * 512 .. v * 512 + 511
-// of the tile, all loaded first; in each 64-key round the lowest lane of each
-// group of equal digits adds the group's size, so a digit shared by the whole
-// round (the high bytes of clustered keys) costs one LDS atomic, not 64.
-__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t* __restrict__ key, SortSegs S,
-                                                             int shift, int32_t* __restrict__ hist)
+// Digit counts of a tile's keys held 64 per round by the waves of the block
+// (digit -1: no key): in each round the lowest lane of each group of equal
+// digits adds the group's size, so a digit shared by the whole round (the
+// high bytes of clustered keys) costs one LDS atomic, not 64.
+__device__ __forceinline__ void tile_digit_counts(const int (&dg)[kSortWaveRounds], int32_t* h)
 {
-    __shared__ int32_t h[256];
-    const int tile = blockIdx.x;
-    const int seg = tile_segment(S, tile);
-    const int lt = tile - S.tile0[seg];
-    const int ntiles = S.tile0[seg + 1] - S.tile0[seg];
-    const int end = S.off[seg + 1];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wbase = S.off[seg] + lt * kSortTile + wave * 64 * kSortWaveRounds;
-    int dg[kSortWaveRounds];
-    #pragma unroll
-    for (int r = 0; r < kSortWaveRounds; ++r) {
-        const int i = wbase + r * 64 + lane;
-        dg[r] = i < end ? (int)((key[i] >> shift) & 255) : -1;
-    }
-    h[threadIdx.x] = 0;
-    __syncthreads();
+    const int lane = threadIdx.x & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     #pragma unroll
     for (int r = 0; r < kSortWaveRounds; ++r) {
@@ -96,8 +66,86 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t* __re
         const uint64_t peers = digit_peers(dg[r], valid);
         if (valid && (peers & lt_mask) == 0) atomicAdd(&h[dg[r]], (int32_t)__popcll(peers));
     }
+}
+
+// Keys of both segments (the points, then the frequencies) in the sort's
+// tiles: a nonnegative double's bit pattern, read as an unsigned integer, is
+// monotone in its value, so sorting the bits sorts the values (-0.0 maps to
+// 0).  Values are the caller indices within the segment.  Each tile also
+// stores its digit counts for the first pass (tile-major, one row of 256 per
+// tile) and errs[tile] = 1 if it holds a negative, NaN or infinite input
+// (else 0).  Wave v of a tile takes its keys v * 512 .. v * 512 + 511.
+__global__ __launch_bounds__(kSortThreads) void k_make_keys(const double* __restrict__ r,
+                                                             const double* __restrict__ w, SortSegs S,
+                                                             uint64_t* __restrict__ key, int32_t* __restrict__ val,
+                                                             int32_t* __restrict__ hist, int32_t* __restrict__ errs)
+{
+    __shared__ int32_t h[256];
+    const int tile = blockIdx.x;
+    const int seg = tile_segment(S, tile);
+    const int lt = tile - S.tile0[seg];
+    const int base = S.off[seg], end = S.off[seg + 1];
+    const double* __restrict__ x = seg ? w : r;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wbase = base + lt * kSortTile + wave * 64 * kSortWaveRounds;
+    int dg[kSortWaveRounds];
+    bool bad = false;
+    #pragma unroll
+    for (int q = 0; q < kSortWaveRounds; ++q) {
+        const int i = wbase + q * 64 + lane;
+        dg[q] = -1;
+        if (i < end) {
+            const double v = x[i - base];
+            const bool ok = (v >= 0.0) && (v <= 1.7976931348623157e308);
+            bad |= !ok;
+            const uint64_t k = (v == 0.0 || !ok) ? 0ull : (uint64_t)__double_as_longlong(v);
+            key[i] = k;
+            val[i] = i - base;
+            dg[q] = (int)(k & 255);
+        }
+    }
+    h[threadIdx.x] = 0;
     __syncthreads();
-    hist[S.hoff[seg] + lt * 256 + threadIdx.x] = h[threadIdx.x];   // tile-major: one contiguous row
+    tile_digit_counts(dg, h);
+    const int any_bad = __syncthreads_or(bad ? 1 : 0);
+    hist[S.hoff[seg] + lt * 256 + threadIdx.x] = h[threadIdx.x];
+    if (threadIdx.x == 0) errs[tile] = any_bad ? 1 : 0;
+}
+
+// Digit counts of one tile for a later pass (tile-major, one row of 256 per
+// tile); wave v takes the tile's keys v * 512 .. v * 512 + 511, all loaded
+// first.
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t* __restrict__ key, SortSegs S,
+                                                             int shift, int32_t* __restrict__ hist)
+{
+    __shared__ int32_t h[256];
+    const int tile = blockIdx.x;
+    const int seg = tile_segment(S, tile);
+    const int lt = tile - S.tile0[seg];
+    const int end = S.off[seg + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wbase = S.off[seg] + lt * kSortTile + wave * 64 * kSortWaveRounds;
+    int dg[kSortWaveRounds];
+    #pragma unroll
+    for (int q = 0; q < kSortWaveRounds; ++q) {
+        const int i = wbase + q * 64 + lane;
+        dg[q] = i < end ? (int)((key[i] >> shift) & 255) : -1;
+    }
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    tile_digit_counts(dg, h);
+    __syncthreads();
+    hist[S.hoff[seg] + lt * 256 + threadIdx.x] = h[threadIdx.x];
+}
+
+// 1 in *flag if any of the n tile flags is set, else 0 (one block).
+__global__ __launch_bounds__(256) void k_reduce_errs(const int32_t* __restrict__ errs, int32_t n,
+                                                     int32_t* __restrict__ flag)
+{
+    int any = 0;
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) any |= errs[i];
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) *flag = any ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -145,6 +193,30 @@ __device__ void block_scan(T (&v)[NV], T (&tot)[NV], T (*wsum)[16])
         v[q] = base + incl[q] - v[q];
     }
     __syncthreads();
+}
+
+// Exclusive scan over the block of VPT consecutive values per thread (NV
+// independent sequences): each thread's own running sums, then a block scan of
+// the thread totals.  tot receives the block totals.
+template <int NV, int VPT>
+__device__ void block_scan_vpt(int64_t (&v)[VPT][NV], int64_t (&tot)[NV], int64_t (*wsum)[16])
+{
+    int64_t t[NV];
+    #pragma unroll
+    for (int q = 0; q < NV; ++q) t[q] = 0;
+    #pragma unroll
+    for (int k = 0; k < VPT; ++k)
+        #pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const int64_t x = v[k][q];
+            v[k][q] = t[q];
+            t[q] += x;
+        }
+    block_scan<int64_t, NV>(t, tot, wsum);
+    #pragma unroll
+    for (int k = 0; k < VPT; ++k)
+        #pragma unroll
+        for (int q = 0; q < NV; ++q) v[k][q] += t[q];
 }
 
 // Per-digit scan of the tile counts (stored tile-major: each tile's 256
@@ -447,17 +519,33 @@ __device__ __forceinline__ NodeSplit split_node(const Rect& R, int32_t kj1, int3
 // loads within the thread, and a pass waits for its slowest thread: one is
 // faster.)
 constexpr int kSubNpt = 1;
+// The first entries of each level's queue live in LDS (the queue of the next
+// level is written while the current one is read, so two buffers); entries
+// past them go to the global queues at the same index.
+constexpr int kSubLds = 1920;
 
 __global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ K, const int32_t* __restrict__ Jc,
                                                     int32_t m, int32_t n, int64_t min_size, int32_t ncand, Arena A,
-                                                    Summary* __restrict__ sum)
+                                                    Summary* __restrict__ sum, const int32_t* __restrict__ errs,
+                                                    int32_t n_errs)
 {
     __shared__ int32_t wsum[4][16];
+    __shared__ Rect lq[2][kSubLds];
     int tid = threadIdx.x;
+    // the summary starts clear (this is the first planning kernel to use it),
+    // with the input check's verdict
+    int bad = 0;
+    for (int32_t i = tid; i < n_errs; i += 1024) bad |= errs[i];
+    bad = __syncthreads_or(bad);
+    if (tid == 0) {
+        *sum = Summary{};
+        sum->domain_error = bad ? 1 : 0;
+    }
     Rect* cur = A.q0;
     Rect* nxt = A.q1;
+    int cb = 0;                                      // LDS buffer of the current level
     int32_t n_cur = (m > 0 && n > 0) ? 1 : 0;
-    if (tid == 0 && n_cur) cur[0] = Rect{0, m - 1, 0, n - 1};
+    if (tid == 0 && n_cur) lq[0][0] = Rect{0, m - 1, 0, n - 1};
     int32_t n_nodes = 0, n_l = 0, n_a = 0, n_d = 0;
     int32_t overflow = 0;
     int32_t level = 0;
@@ -474,7 +562,7 @@ __global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ 
             #pragma unroll
             for (int q = 0; q < kSubNpt; ++q) {
                 bool act = i0 + q < n_cur;
-                R[q] = act ? cur[i0 + q] : Rect{0, 0, 0, 0};
+                R[q] = act ? (i0 + q < kSubLds ? lq[cb][i0 + q] : cur[i0 + q]) : Rect{0, 0, 0, 0};
             }
             #pragma unroll
             for (int q = 0; q < kSubNpt; ++q) {   // all header loads in flight together
@@ -511,9 +599,21 @@ __global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ 
                 nd.ablk = o.ca ? a_slot : -1;
                 nd.level = level; nd.pad = 0;
                 nd.ur = -1; nd.ll = -1;
-                if (o.ur_m) { if (m_slot < A.q_cap) nxt[m_slot] = Rect{Rq.j0, o.js, o.ks + 1, Rq.k1}; nd.ur = next_base + m_slot; ++m_slot; }
+                if (o.ur_m) {
+                    const Rect c = Rect{Rq.j0, o.js, o.ks + 1, Rq.k1};
+                    if (m_slot < kSubLds) lq[cb ^ 1][m_slot] = c;
+                    else if (m_slot < A.q_cap) nxt[m_slot] = c;
+                    nd.ur = next_base + m_slot;
+                    ++m_slot;
+                }
                 if (o.ur_d) { if (d_slot < A.d_cap) A.db[d_slot] = DBlock{Rq.j0, o.js, o.ks + 1, Rq.k1}; nd.ur = encode_direct(d_slot); ++d_slot; }
-                if (o.ll_m) { if (m_slot < A.q_cap) nxt[m_slot] = Rect{o.js + 1, Rq.j1, Rq.k0, o.ks}; nd.ll = next_base + m_slot; ++m_slot; }
+                if (o.ll_m) {
+                    const Rect c = Rect{o.js + 1, Rq.j1, Rq.k0, o.ks};
+                    if (m_slot < kSubLds) lq[cb ^ 1][m_slot] = c;
+                    else if (m_slot < A.q_cap) nxt[m_slot] = c;
+                    nd.ll = next_base + m_slot;
+                    ++m_slot;
+                }
                 if (o.ll_d) { if (d_slot < A.d_cap) A.db[d_slot] = DBlock{o.js + 1, Rq.j1, Rq.k0, o.ks}; nd.ll = encode_direct(d_slot); ++d_slot; }
                 if (node < A.node_cap) A.nodes[node] = nd;
                 if (o.cl) {
@@ -546,6 +646,7 @@ __global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ 
         }
         if (level >= kMaxLevels) overflow = 2;
         Rect* t = cur; cur = nxt; nxt = t;
+        cb ^= 1;
         n_cur = overflow ? 0 : n_next;
         __syncthreads();
     }
@@ -637,29 +738,69 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, Summary*
     const int nch = P.nch;
     if (tid <= kMaxFftLog2) cls_cnt[tid] = 0;
     __syncthreads();
+    // membership statistics: rows / columns of local and asymptotic blocks,
+    // direct entries, grid cells and FFT points, and the row-side work of the
+    // asymptotic blocks (rows x cells on the direct-sum path, rows on the FFT
+    // path), gathered in the same passes
+    constexpr int kStats = 9;
+    long long st[kStats] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    constexpr int kVpt = 8;                          // blocks per thread per pass (8192 per pass)
     int64_t l_items = 0;
-    for (int32_t c0 = 0; c0 < n_l; c0 += 1024) {
-        int32_t i = c0 + tid;
-        int64_t v[1] = {i < n_l ? (int64_t)A.lb[i].nitems : 0};
+    for (int32_t c0 = 0; c0 < n_l; c0 += 1024 * kVpt) {
+        const int32_t i0 = c0 + tid * kVpt;
+        int64_t v[kVpt][1];
+        #pragma unroll
+        for (int k = 0; k < kVpt; ++k) {
+            v[k][0] = 0;
+            if (i0 + k < n_l) {
+                const LBlock L = A.lb[i0 + k];
+                v[k][0] = L.nitems;
+                st[0] += L.j1 - L.j0 + 1;
+                st[1] += L.k1 - L.k0 + 1;
+            }
+        }
         int64_t tot[1];
-        block_scan<int64_t, 1>(v, tot, wsum);
-        if (i < n_l) A.lb[i].item0 = (int32_t)(l_items + v[0]);
+        block_scan_vpt<1, kVpt>(v, tot, wsum);
+        #pragma unroll
+        for (int k = 0; k < kVpt; ++k)
+            if (i0 + k < n_l) A.lb[i0 + k].item0 = (int32_t)(l_items + v[k][0]);
         l_items += tot[0];
     }
     int64_t a_items = 0, grid = 0;
-    for (int32_t c0 = 0; c0 < n_a; c0 += 1024) {
-        int32_t i = c0 + tid;
-        bool act = i < n_a;
-        ABlock B;
-        if (act) B = A.ab[i];
-        int64_t v[2] = {act ? (int64_t)B.nitems : 0, act ? (B.fft ? (int64_t)B.N2 : (int64_t)B.N1) : 0};
+    for (int32_t c0 = 0; c0 < n_a; c0 += 1024 * kVpt) {
+        const int32_t i0 = c0 + tid * kVpt;
+        int64_t v[kVpt][2];
+        bool fft[kVpt];
+        int32_t n2[kVpt];
+        #pragma unroll
+        for (int k = 0; k < kVpt; ++k) {
+            v[k][0] = v[k][1] = 0;
+            fft[k] = false;
+            n2[k] = 0;
+            if (i0 + k < n_a) {
+                const ABlock B = A.ab[i0 + k];
+                v[k][0] = B.nitems;
+                v[k][1] = B.fft ? (int64_t)B.N2 : (int64_t)B.N1;
+                fft[k] = B.fft != 0;
+                n2[k] = B.N2;
+                const long long rows = B.j1 - B.j0 + 1;
+                st[2] += rows;
+                st[3] += B.k1 - B.k0 + 1;
+                if (B.fft) { st[6] += B.N2; st[8] += rows; }
+                else { st[5] += B.N1; st[7] += rows * B.N1; }
+            }
+        }
         int64_t tot[2];
-        block_scan<int64_t, 2>(v, tot, wsum);
-        if (act) {
-            A.ab[i].item0 = (int32_t)(a_items + v[0]);
-            A.ab[i].grid_off = (grid + v[1]) * nch;
-            A.gslot[i] = grid + v[1];
-            if (B.fft) atomicAdd(&cls_cnt[31 - __clz(B.N2)], 1);
+        block_scan_vpt<2, kVpt>(v, tot, wsum);
+        #pragma unroll
+        for (int k = 0; k < kVpt; ++k) {
+            const int32_t i = i0 + k;
+            if (i < n_a) {
+                A.ab[i].item0 = (int32_t)(a_items + v[k][0]);
+                A.ab[i].grid_off = (grid + v[k][1]) * nch;
+                A.gslot[i] = grid + v[k][1];
+                if (fft[k]) atomicAdd(&cls_cnt[31 - __clz(n2[k])], 1);
+            }
         }
         a_items += tot[0];
         grid += tot[1];
@@ -687,22 +828,6 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, Summary*
             A.fft_list[slot] = i;
             A.ab[i].fft_slot = slot;
         }
-    }
-    // membership statistics: rows / columns of local and asymptotic blocks,
-    // direct entries, grid cells and FFT points, and the row-side work of the
-    // asymptotic blocks (rows x cells on the direct-sum path, rows on the FFT path)
-    constexpr int kStats = 9;
-    long long st[kStats] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int32_t i = tid; i < n_l; i += 1024) {
-        LBlock L = A.lb[i];
-        st[0] += L.j1 - L.j0 + 1; st[1] += L.k1 - L.k0 + 1;
-    }
-    for (int32_t i = tid; i < n_a; i += 1024) {
-        ABlock B = A.ab[i];
-        long long rows = B.j1 - B.j0 + 1;
-        st[2] += rows; st[3] += B.k1 - B.k0 + 1;
-        if (B.fft) { st[6] += B.N2; st[8] += rows; }
-        else { st[5] += B.N1; st[7] += rows * B.N1; }
     }
     for (int32_t i = tid; i < n_d; i += 1024) {
         DBlock Db = A.db[i];
@@ -793,17 +918,29 @@ __global__ __launch_bounds__(1024) void k_item_scan(PlanDev P, Arena A, Summary*
     if (sum->overflow) return;
     const int32_t n_ai = sum->n_aitems;
     const int nch = P.nch;
+    constexpr int kVpt = 8;                          // items per thread per pass (8192 per pass)
     int64_t run = 0, run_dense = 0;
-    for (int32_t c0 = 0; c0 < n_ai; c0 += 1024) {
-        int32_t i = c0 + threadIdx.x;
-        int64_t v[2] = {i < n_ai ? (int64_t)a_cells[i] : 0, i < n_ai ? (int64_t)A.aitems[i].dense : 0};
-        const int64_t dense = v[1];
+    for (int32_t c0 = 0; c0 < n_ai; c0 += 1024 * kVpt) {
+        const int32_t i0 = c0 + threadIdx.x * kVpt;
+        int64_t v[kVpt][2];
+        bool dense[kVpt];
+        #pragma unroll
+        for (int k = 0; k < kVpt; ++k) {
+            const bool act = i0 + k < n_ai;
+            v[k][0] = act ? (int64_t)a_cells[i0 + k] : 0;
+            dense[k] = act && A.aitems[i0 + k].dense;
+            v[k][1] = dense[k] ? 1 : 0;
+        }
         int64_t tot[2];
-        block_scan<int64_t, 2>(v, tot, wsum);
-        if (i < n_ai) {
-            A.aitems[i].off = (run + v[0]) * nch;
-            int64_t nd_before = run_dense + v[1];
-            A.alist[dense ? nd_before : n_ai - 1 - (i - nd_before)] = i;
+        block_scan_vpt<2, kVpt>(v, tot, wsum);
+        #pragma unroll
+        for (int k = 0; k < kVpt; ++k) {
+            const int32_t i = i0 + k;
+            if (i < n_ai) {
+                A.aitems[i].off = (run + v[k][0]) * nch;
+                const int64_t nd_before = run_dense + v[k][1];
+                A.alist[dense[k] ? nd_before : n_ai - 1 - (i - nd_before)] = i;
+            }
         }
         run += tot[0];
         run_dense += tot[1];
@@ -819,46 +956,56 @@ __global__ __launch_bounds__(1024) void k_item_scan(PlanDev P, Arena A, Summary*
 // ---------------------------------------------------------------------------
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
-hipError_t launch_make_keys(const double* x, int32_t n, uint64_t* key, int32_t* val, int32_t* err, hipStream_t s)
+static SortSegs sort_segs(int32_t na, int32_t nb)
 {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_make_keys, dim3(cdiv(n, 256)), dim3(256), 0, s, x, n, key, val, err);
-    return hipGetLastError();
-}
-
-hipError_t launch_sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int32_t* hist,
-                             int32_t na, int32_t nb, hipStream_t s)
-{
-    // the 2 x 256 digit totals live after the histograms (see sort_hist_len)
     SortSegs S;
     S.off[0] = 0; S.off[1] = na; S.off[2] = na + nb;
-    int ta = cdiv(na, kSortTile), tb = cdiv(nb, kSortTile);
+    const int ta = cdiv(na, kSortTile), tb = cdiv(nb, kSortTile);
     S.tile0[0] = 0; S.tile0[1] = ta; S.tile0[2] = ta + tb;
     S.hoff[0] = 0; S.hoff[1] = 256 * ta; S.hoff[2] = 256 * (ta + tb);
-    if (ta + tb == 0) return hipSuccess;
+    return S;
+}
+
+hipError_t launch_keys_and_sort(const double* r, int32_t na, const double* w, int32_t nb, uint64_t* k0, int32_t* v0,
+                                uint64_t* k1, int32_t* v1, int32_t* hist, int32_t* errs, hipStream_t s)
+{
+    const SortSegs S = sort_segs(na, nb);
+    const int tiles = S.tile0[2];
+    if (tiles == 0) return hipSuccess;
+    // the per-tile counts, then the 2 x 256 digit totals
+    int32_t* dtot = hist + S.hoff[2];
+    hipLaunchKernelGGL(k_make_keys, dim3(tiles), dim3(kSortThreads), 0, s, r, w, S, k0, v0, hist, errs);
     uint64_t* kin = k0; int32_t* vin = v0; uint64_t* kout = k1; int32_t* vout = v1;
     for (int pass = 0; pass < 8; ++pass) {
-        int shift = 8 * pass;
-        hipLaunchKernelGGL(k_sort_hist, dim3(ta + tb), dim3(kSortThreads), 0, s, kin, S, shift, hist);
-        hipLaunchKernelGGL(k_sort_scan, dim3(2 * 256 / 4), dim3(256), 0, s, hist, hist + S.hoff[2], S);
-        hipLaunchKernelGGL(k_sort_scatter, dim3(ta + tb), dim3(kSortThreads), 0, s, kin, vin, kout, vout, S, shift,
-                           hist, hist + S.hoff[2]);
+        if (pass > 0)   // the first pass's counts come with the keys
+            hipLaunchKernelGGL(k_sort_hist, dim3(tiles), dim3(kSortThreads), 0, s, kin, S, 8 * pass, hist);
+        hipLaunchKernelGGL(k_sort_scan, dim3(2 * 256 / 4), dim3(256), 0, s, hist, dtot, S);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(tiles), dim3(kSortThreads), 0, s, kin, vin, kout, vout, S, 8 * pass,
+                           hist, dtot);
         uint64_t* tk = kin; kin = kout; kout = tk;
         int32_t* tv = vin; vin = vout; vout = tv;
     }
     return hipGetLastError();   // eight passes: the result is back in (k0, v0)
 }
 
-int sort_hist_len(int32_t na, int32_t nb) { return 256 * (cdiv(na, kSortTile) + cdiv(nb, kSortTile)) + 2 * 256; }
+hipError_t launch_reduce_errs(const int32_t* errs, int32_t n, int32_t* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_errs, dim3(1), dim3(256), 0, s, errs, n, flag);
+    return hipGetLastError();
+}
+
+int sort_tiles(int32_t na, int32_t nb) { return cdiv(na, kSortTile) + cdiv(nb, kSortTile); }
+
+int sort_hist_len(int32_t na, int32_t nb) { return 256 * sort_tiles(na, nb) + 2 * 256; }
 
 hipError_t launch_planning(const PlanDev& P, const Arena& A, int32_t* K, int32_t* Jc, int32_t* a_cells,
                            int64_t min_size, int32_t ncand, int32_t dft_max, double sigma, Summary* sum,
-                           hipStream_t s)
+                           const int32_t* errs, int32_t n_errs, hipStream_t s)
 {
     const int32_t n = P.n, m = P.m;
     hipLaunchKernelGGL(k_staircase, dim3(cdiv(m, 256)), dim3(256), 0, s, P.rs, n, P.ws, m, P.z, K);
     hipLaunchKernelGGL(k_staircase, dim3(cdiv(n, 256)), dim3(256), 0, s, P.ws, m, P.rs, n, P.z, Jc);
-    hipLaunchKernelGGL(k_subdivide, dim3(1), dim3(1024), 0, s, K, Jc, m, n, min_size, ncand, A, sum);
+    hipLaunchKernelGGL(k_subdivide, dim3(1), dim3(1024), 0, s, K, Jc, m, n, min_size, ncand, A, sum, errs, n_errs);
     hipLaunchKernelGGL(k_block_params, dim3(256), dim3(128), 0, s, P, A, dft_max, sigma, sum);
     hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, s, P, A, sum);
     hipLaunchKernelGGL(k_items, dim3(512), dim3(128), 0, s, P, A, sum, a_cells);
