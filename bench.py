@@ -106,22 +106,51 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": x.numel() * 8, "copies": 3}), flush=True)
 
 
+class StageProfile:
+    """Per-stage times of profiled executions, read from each plan once its
+    execution is a step behind (its events have completed by then, so the
+    read does not stall the pipeline) and the plan released: at most a step's
+    worth of plans stays alive."""
+
+    def __init__(self, nuht):
+        import collections
+        self.pending = collections.deque()
+        self.total = {s: 0.0 for s in nuht.STAGES}
+        self.calls = 0
+        self.infos = {}
+
+    def add(self, nu, p):
+        self.pending.append((nu, p))
+        self.drain(len(ORDERS))
+
+    def drain(self, keep=0):
+        while len(self.pending) > keep:
+            nu, p = self.pending.popleft()
+            st, nc = p.profile_read()
+            for k, v in st.items():
+                self.total[k] += v
+            self.calls += nc
+            self.infos.setdefault(nu, p.info())
+            p.close()
+
+
 def make_step(torch, nuht, inputs, side, eps, **opts):
     """One step: the three transforms, each planned on the side stream (so its
     sort and subdivision overlap the previous transform's execution) and
-    executed on the current stream.  keep: a list collecting (nu, plan) with
-    stage profiling on, or None (plans closed after their execution)."""
-    def step(keep=None):
+    executed on the current stream.  prof: a StageProfile taking the plans
+    with stage profiling on, or None (plans released once their execution is
+    queued)."""
+    def step(prof=None):
         outs = {}
         for nu in ORDERS:
             r, w, c = inputs[nu]
             with torch.cuda.stream(side):
                 p = nuht.Plan(r, w, nu, eps, **opts)
-            if keep is not None:
+            if prof is not None:
                 p.profile(True)
             outs[nu] = p.execute(c)
-            if keep is not None:
-                keep.append((nu, p))
+            if prof is not None:
+                prof.add(nu, p)
             else:
                 p.close()
         return outs
@@ -526,13 +555,14 @@ def main():
     torch.cuda.synchronize()
     log("warmup done")
 
-    kept = []
+    prof = StageProfile(nuht)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        outs = step(kept)
+        outs = step(prof)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    prof.drain()
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
     work = len(ORDERS) * (N + M_OUT)
@@ -541,26 +571,13 @@ def main():
     if args.steps_only:
         # for counter runs: the library's kernels of this process are exactly
         # warmup + steps headline steps
-        for _, p in kept:
-            p.close()
         print(json.dumps({"steps_only": True, "warmup": args.warmup, "steps": args.steps,
                           "ms_per_step": ms_per_step, "value": value}), flush=True)
         return
 
     # per-stage times (events recorded inside the timed region)
-    stage_tot = {s: 0.0 for s in nuht.STAGES}
-    calls = 0
-    infos = {}
-    for nu, p in kept:
-        st, nc = p.profile_read()
-        for k, v in st.items():
-            stage_tot[k] += v
-        calls += nc
-        infos[nu] = p.info()
-    for _, p in kept:
-        p.close()
-    kept.clear()
-    stage_ms = {k: v / args.steps for k, v in stage_tot.items()}   # per step (3 transforms)
+    infos = prof.infos
+    stage_ms = {k: v / args.steps for k, v in prof.total.items()}   # per step (3 transforms)
 
     # execute-only and plan-only times per order
     per_order = {}
