@@ -642,6 +642,22 @@ def main():
     if traffic is not None:
         gbs = len(ORDERS) * traffic["bytes"] / (stage_ms[dom] * 1e-3)
         roofline.update(traffic_GBps=gbs / 1e9, hbm_frac=gbs / PEAK_HBM)
+    # The other stages with an algorithmic count, each over its own event-timed
+    # duration in the same steps: the asymptotic rows (as above); the direct
+    # blocks at 200 flops per entry (one J_nu(omega r) and its multiply-add,
+    # the survey's per-entry estimate; the table evaluation spends ~34); the
+    # local moments at 4 (L + 1) flops per local column membership (a
+    # Chebyshev step and a multiply-add per moment).
+    stage_flops = {
+        "spread": fl,
+        "rows_asymptotic": sum(flops("rows_asymptotic", infos[nu]) for nu in ORDERS),
+        "direct": sum(200.0 * infos[nu]["direct_entries"] for nu in ORDERS),
+        "local_moments": sum(4.0 * (infos[nu]["L"] + 1) * infos[nu]["local_col_members"] for nu in ORDERS),
+    }
+    roofline["stages"] = {
+        st: dict(flops_per_step=f, ms_per_step=stage_ms[st], achieved=f / (stage_ms[st] * 1e-3) / 1e12,
+                 frac=f / (stage_ms[st] * 1e-3) / PEAK_FP64)
+        for st, f in stage_flops.items() if stage_ms[st] > 0}
     step_traffic = read_step_traffic()
     if step_traffic is not None:
         gbs = step_traffic["bytes_per_step"] / (ms_per_step * 1e-3)
