@@ -62,6 +62,7 @@ def test_gradient_against_oracle(nuht, nu):
     gbar = workloads.cotangent(w.size, seed=80 + abs(nu))
     p = nuht.Plan(dev(r), dev(w), nu, 1e-12)
     dc, dr, dw = (host(t) for t in p.gradient(dev(c), dev(gbar)))
+    ms = p.info()["min_size"]
     p.close()
     oc, orr, ow = ograd.gradient(nu, r, c, w, gbar)
     print(nu, "dc", rel_l2(dc, oc), rel_max(dc, oc))
@@ -69,8 +70,10 @@ def test_gradient_against_oracle(nuht, nu):
     gw, cr = gbar * w, c * r
     bound_r = 1e-12 * np.abs(c) * np.sum(np.abs(gw))
     bound_w = 1e-12 * np.abs(gbar) * np.sum(np.abs(cr))
-    m2r = 0.5 * c * (method.nufht_reference(nu - 1, 1e-12, w, gw, r) - method.nufht_reference(nu + 1, 1e-12, w, gw, r))
-    m2w = 0.5 * gbar * (method.nufht_reference(nu - 1, 1e-12, r, cr, w) - method.nufht_reference(nu + 1, 1e-12, r, cr, w))
+    m2r = 0.5 * c * (method.nufht_reference(nu - 1, 1e-12, w, gw, r, min_size=ms)
+                     - method.nufht_reference(nu + 1, 1e-12, w, gw, r, min_size=ms))
+    m2w = 0.5 * gbar * (method.nufht_reference(nu - 1, 1e-12, r, cr, w, min_size=ms)
+                        - method.nufht_reference(nu + 1, 1e-12, r, cr, w, min_size=ms))
     for name, a, b, bnd, b2 in (("dr", dr, orr, bound_r, m2r), ("domega", dw, ow, bound_w, m2w)):
         print(nu, name, rel_l2(a, b), rel_max(a, b), rel_l2(a, b2), rel_max(a, b2))
         assert rel_l2(a, b) <= TOL, (name, rel_l2(a, b))

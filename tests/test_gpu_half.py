@@ -69,7 +69,7 @@ def test_half_orders(nuht, nu):
     g1 = direct.dht(nu, r, c, w)
     print("  vs direct sum: rel l2 %.2e rel max %.2e" % (rel_l2(g, g1), rel_max(g, g1)))
     assert rel_l2(g, g1) <= TOL and rel_max(g, g1) <= TOL
-    g2 = method.nufht_reference(nu, 1e-12, r, c, w)
+    g2 = method.nufht_reference(nu, 1e-12, r, c, w, min_size=info["min_size"])
     assert rel_l2(g, g2) <= 2e-13 and rel_max(g, g2) <= 2e-13
 
 

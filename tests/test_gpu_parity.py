@@ -70,7 +70,7 @@ def test_partition_matches_oracle(nuht):
     M, z, L = oparams.parameters(0, 1e-12)
     assert abs(info["z"] - z) <= 1e-14 * z
     K = direct.staircase(np.sort(r), np.sort(w), z)
-    st = partition.stats(partition.subdivide(K, w.size, r.size))
+    st = partition.stats(partition.subdivide(K, w.size, r.size, info["min_size"]))
     assert info["n_local"] == st["L"]["count"]
     assert info["n_asy"] == st["A"]["count"]
     assert info["n_direct"] == st["D"]["count"]
@@ -83,8 +83,8 @@ def test_partition_matches_oracle(nuht):
 def test_against_method_exact_reference(nuht):
     # GPU - O2 isolates the NUFFT and rounding error of the GPU path
     r, w, c = workloads.uniform(3000, 2500, 1.0, 1500.0, seed=3)
-    g, _ = run(nuht, 0, 1e-12, r, c, w)
-    g2 = method.nufht_reference(0, 1e-12, r, c, w)
+    g, info = run(nuht, 0, 1e-12, r, c, w)
+    g2 = method.nufht_reference(0, 1e-12, r, c, w, min_size=info["min_size"])
     assert rel_l2(g, g2) <= 3e-13
 
 
@@ -110,7 +110,7 @@ def test_fp32_spreading(nuht, nu):
     g32, info = run(nuht, nu, eps, r, c, w, precision=nuht.NUHT_FP32_SPREAD)
     g64, info64 = run(nuht, nu, eps, r, c, w)
     g1 = direct.dht(nu, r, c, w)
-    g2 = method.nufht_reference(nu, eps, r, c, w)
+    g2 = method.nufht_reference(nu, eps, r, c, w, min_size=info["min_size"])
     print("fp32", nu, rel_l2(g32, g1), rel_max(g32, g1), rel_l2(g32, g2), rel_max(g32, g2),
           "fp64", rel_l2(g64, g1), rel_l2(g64, g2), info["es_width"])
     assert info["es_width"] == info64["es_width"] - 1
@@ -120,14 +120,28 @@ def test_fp32_spreading(nuht, nu):
 
 
 def test_fp32_spreading_full_size_sampled(nuht):
-    # n = m = 1e6 at eps = 1e-6, FP32 spreading, nu = 0 and 10, 200 sampled outputs
+    # n = m = 1e6 at eps = 1e-6, FP32 spreading, nu = 0 and 10, 200 sampled
+    # outputs.  At nu = 10 the paper's (M, z, L) for eps = 1e-6 leave the
+    # method's own truncation at about eps in rel-l2 (FP64 spreading measures
+    # 1.07e-6 on these samples, 1.8e-6 normwise max), so: with the paper's
+    # parameters the FP32 result stays within eps / 5 of the FP64 one (the
+    # spreading's own error, 1.4e-7 measured at nu = 0, adds in quadrature) and
+    # every entry within eps |c|_1 of the direct sum; with the library's
+    # margin option (parameters for eps / 2) rel-l2 and max <= eps.
+    eps = 1e-6
     for nu, seed in ((0, 2), (10, 4)):
         r, w, c = workloads.large_uniform(seed=seed)
-        g, _ = run(nuht, nu, 1e-6, r, c, w, precision=nuht.NUHT_FP32_SPREAD)
         idx = np.random.default_rng(51).choice(w.size, 200, replace=False)
         g1 = direct.dht(nu, r, c, w[idx])
-        print("fp32 full", nu, rel_l2(g[idx], g1), rel_max(g[idx], g1))
-        assert rel_l2(g[idx], g1) <= 1e-6
+        g32, _ = run(nuht, nu, eps, r, c, w, precision=nuht.NUHT_FP32_SPREAD)
+        g64, _ = run(nuht, nu, eps, r, c, w)
+        g32m, _ = run(nuht, nu, eps, r, c, w, precision=nuht.NUHT_FP32_SPREAD, margin=2.0)
+        g32, g64, g32m = g32[idx], g64[idx], g32m[idx]
+        print("fp32 full", nu, rel_l2(g32, g1), rel_max(g32, g1), "fp64", rel_l2(g64, g1),
+              "fp32 margin 2", rel_l2(g32m, g1), rel_max(g32m, g1))
+        assert rel_l2(g32, g64) <= eps / 5
+        assert np.max(np.abs(g32 - g1)) <= eps * np.sum(np.abs(c))
+        assert rel_l2(g32m, g1) <= eps and rel_max(g32m, g1) <= eps
 
 
 @pytest.mark.parametrize("nu", [25, 63, 100])
@@ -143,7 +157,7 @@ def test_high_orders(nuht, nu):
     r, w, c = workloads.uniform(2500, 2000, 1.0, 2500.0, seed=60 + nu)
     g, info = run(nuht, nu, 1e-12, r, c, w)
     assert info["n_asy"] > 0 and info["n_local"] > 0
-    g2 = method.nufht_reference(nu, 1e-12, r, c, w)
+    g2 = method.nufht_reference(nu, 1e-12, r, c, w, min_size=info["min_size"])
     assert rel_l2(g, g2) <= 2e-13, rel_l2(g, g2)
     assert rel_max(g, g2) <= 2e-13, rel_max(g, g2)
     g1 = direct.dht(nu, r, c, w)
@@ -422,8 +436,8 @@ def test_exact_split_matches_oracle(nuht, kind):
     p.close()
     M, z, L = oparams.parameters(0, 1e-12)
     K = direct.staircase(np.sort(r), np.sort(w), z)
-    st = partition.stats(partition.subdivide(K, w.size, r.size, ncand=0))
-    quasi = partition.stats(partition.subdivide(K, w.size, r.size))
+    st = partition.stats(partition.subdivide(K, w.size, r.size, info["min_size"], ncand=0))
+    quasi = partition.stats(partition.subdivide(K, w.size, r.size, info["min_size"]))
     print(kind, "exact: levels", st["levels"], "mixed-free area local", st["L"]["area"], "asy", st["A"]["area"],
           "direct", st["D"]["area"], "| quasi direct", quasi["D"]["area"])
     assert info["n_local"] == st["L"]["count"]
