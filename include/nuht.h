@@ -53,9 +53,11 @@ typedef struct nuht_plan_s *nuht_plan_t;
 /*
  * Options; pass NULL for the defaults.
  *   min_size          direct-block threshold of Alg. 1: an off-diagonal child
- *                     of area <= min_size is applied directly (0 -> 8192; the
- *                     paper, Alg. 2, leaves it to numerical experiments with
- *                     1024 as its example, and 8192 measured fastest here).
+ *                     of area <= min_size is applied directly (0 -> the
+ *                     power of two at or below n m / 256, within [1024,
+ *                     8192]; the paper, Alg. 2, leaves it to numerical
+ *                     experiments with 1024 as its example, and this rule
+ *                     follows what measured fastest here).
  *   M_override        number of asymptotic terms M (0 -> eq. num-asy-terms).
  *   split_candidates  equispaced candidate rows in SplitIndices (0 -> 16);
  *                     -1: every row of a block (the exact optimum of the

@@ -1172,7 +1172,7 @@ static int part_begin(nuht_plan_t pl, PendingPart& pp, Partition& Pt, const Geom
         return NUHT_OK;
     }
     const nuht_opts& o = pl->opts;
-    int64_t min_size = o.min_size > 0 ? o.min_size : kDefaultMinSize;
+    int64_t min_size = o.min_size > 0 ? o.min_size : default_min_size(G.n, G.m);
     // -1: every row of a block is a candidate (the exact split optimum)
     int ncand = o.split_candidates == -1 ? INT32_MAX : (o.split_candidates > 1 ? o.split_candidates : 16);
     int dft_max = o.dft_max == 0 ? 48 : o.dft_max;
@@ -1826,7 +1826,7 @@ static int tune_plan(nuht_plan_t p, const double* c_dev, int reps, nuht_opts* be
     const nuht_opts saved = p->opts;
     nuht_opts cur = saved;
     if (cur.spread_chunk == 0) cur.spread_chunk = kSpreadChunk;
-    if (cur.min_size == 0) cur.min_size = kDefaultMinSize;
+    if (cur.min_size == 0) cur.min_size = default_min_size(p->n, p->m);
     if (cur.dft_max == 0) cur.dft_max = 48;
     if (cur.split_candidates == 0) cur.split_candidates = 16;
     int rc = NUHT_OK;
@@ -2320,7 +2320,7 @@ int nuht_plan_info(nuht_plan_t p, nuht_info* info)
     int64_t bytes = p->geom_bytes + (int64_t)p->b_grad.bytes;
     for (auto& o : p->orders) bytes += o->f.bytes + o->a.bytes;
     info->workspace_bytes = bytes;
-    info->min_size = p->opts.min_size > 0 ? p->opts.min_size : kDefaultMinSize;
+    info->min_size = p->opts.min_size > 0 ? p->opts.min_size : default_min_size(p->n, p->m);
     info->dft_max = p->opts.dft_max == 0 ? 48 : p->opts.dft_max;
     info->spread_chunk = P.spread_chunk;
     info->spread_items = S.n_aitems;

@@ -14,12 +14,21 @@ constexpr int kMaxChannels = 40;       // 2M with M <= 20 (eq. num-asy-terms cap
 constexpr int kMaxFftLog2 = 24;        // largest FFT of an asymptotic block: 2^24 = 4096^2 points (two passes)
 constexpr int kLocalChunk = 4096;      // columns per local-moment work item
 constexpr int kSpreadChunk = 1024;     // default points per spreading work item (a plan option)
-// Default direct-block threshold of Alg. 1.  The paper leaves min_size to
-// numerical experiments (its example: 1024); on this GPU, with the direct
-// entries read from a J_nu table, 8192 measured fastest or within 2% of it
-// on every workload tried (uniform, radial, exponential, Fourier-Bessel,
-// batched).
-constexpr int64_t kDefaultMinSize = 8192;
+// Default direct-block threshold of Alg. 1 for an n x m transform.  The
+// paper leaves min_size to numerical experiments (its example: 1024).  On
+// MI355X, with the direct entries read from a J_nu table, the fastest
+// threshold grows with the matrix: 1024 for n m below about 5e5, 2048 near
+// 1e6, 8192 from about 1e7 on (uniform, radial, exponential, Fourier-Bessel
+// and batched workloads).  The rule takes the power of two at or below
+// n m / 256, within [1024, 8192].
+constexpr int64_t kMinSizeLo = 1024;
+constexpr int64_t kMinSizeHi = 8192;
+inline int64_t default_min_size(int64_t n, int64_t m) {
+    const double a = (double)n * (double)m / 256.0;
+    int64_t s = kMinSizeLo;
+    while (s < kMinSizeHi && (double)(2 * s) <= a) s *= 2;
+    return s;
+}
 constexpr int kMaxEsWidth = 18;        // largest ES kernel width
 constexpr int kEsDeg = 13;             // degree of the per-cell polynomial pieces of the ES kernel
 constexpr int kSpreadAnchors = 6;      // first cells (anchors) one matrix-core spreading item may hold

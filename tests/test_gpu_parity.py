@@ -88,6 +88,16 @@ def test_against_method_exact_reference(nuht):
     assert rel_l2(g, g2) <= 3e-13
 
 
+@pytest.mark.parametrize("n,m,expect", [(512, 128, 1024), (128, 512, 1024), (1000, 1000, 2048),
+                                         (1200, 1000, 4096), (1500, 1500, 8192), (20000, 30000, 8192)])
+def test_default_min_size(nuht, n, m, expect):
+    # The default direct-block threshold: the power of two at or below
+    # n m / 256 within [1024, 8192]; an explicit option is kept as given.
+    r, w, c = workloads.uniform(n, m, 1.0, float(max(n, m)), seed=n + m)
+    assert run(nuht, 0, 1e-12, r, c, w)[1]["min_size"] == expect
+    assert run(nuht, 0, 1e-12, r, c, w, min_size=300)[1]["min_size"] == 300
+
+
 @pytest.mark.parametrize("nu", [1, 2, 3, 5, 10, -1, -4])
 def test_orders(nuht, nu):
     r, w, c = workloads.uniform(3000, 2000, 1.0, 2000.0, seed=40 + abs(nu))
