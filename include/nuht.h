@@ -274,6 +274,18 @@ int nuht_plan_set_order(nuht_plan_t plan, int nu, void *stream);
 int nuht_plan_info(nuht_plan_t plan, nuht_info *info);
 
 /*
+ * nuht_plan_order -- the plan's sorted geometry.  The method works on points
+ * and frequencies in increasing order (Thm. 4.1 and Alg. 1 assume it), so the
+ * plan sorts both once; this copies, on `stream` (device pointers, each may be
+ * NULL to skip it): r_sorted (n doubles, nondecreasing; -0.0 becomes +0.0),
+ * perm_r (n int32: the caller's index of each sorted point, equal values in
+ * the caller's order), and likewise omega_sorted and perm_omega (m each).
+ * NUHT_EINVAL for a null plan.
+ */
+int nuht_plan_order(nuht_plan_t plan, double *r_sorted, int32_t *perm_r, double *omega_sorted,
+                    int32_t *perm_omega, void *stream);
+
+/*
  * nuht_tune -- pick the spreading work-item size, min_size, dft_max and (unless
  * the plan uses the exact split) split_candidates for this plan's geometry and
  * order: coordinate descent over a few candidates of each, every candidate

@@ -61,7 +61,7 @@ class NuhtInfo(ctypes.Structure):
 # every symbol include/nuht.h declares
 EXPORTS = ("nuht_plan", "nuht_plan_half", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_gradient_noalloc",
            "nuht_plan_set_order",
-           "nuht_plan_info", "nuht_tune", "nuht_plan_many", "nuht_execute_many", "nuht_batch_info",
+           "nuht_plan_info", "nuht_plan_order", "nuht_tune", "nuht_plan_many", "nuht_execute_many", "nuht_batch_info",
            "nuht_batch_destroy", "nuht_destroy", "nuht_strerror", "nuht_direct", "nuht_profile", "nuht_profile_read",
            "nuht_fb_plan", "nuht_fb_analysis", "nuht_fb_synthesis", "nuht_fb_helmholtz", "nuht_fb_destroy")
 
@@ -95,6 +95,7 @@ def load_library():
     lib.nuht_batch_destroy.argtypes = [vp]
     lib.nuht_plan_set_order.argtypes = [vp, ctypes.c_int, vp]
     lib.nuht_plan_info.argtypes = [vp, ctypes.POINTER(NuhtInfo)]
+    lib.nuht_plan_order.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.nuht_destroy.argtypes = [vp]
     lib.nuht_strerror.argtypes = [ctypes.c_int]
     lib.nuht_strerror.restype = ctypes.c_char_p
@@ -108,7 +109,7 @@ def load_library():
     lib.nuht_fb_helmholtz.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp, vp]
     lib.nuht_fb_destroy.argtypes = [vp]
     for name in ("nuht_plan", "nuht_plan_half", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_gradient_noalloc",
-                 "nuht_plan_set_order", "nuht_plan_info",
+                 "nuht_plan_set_order", "nuht_plan_info", "nuht_plan_order",
                  "nuht_tune", "nuht_plan_many", "nuht_execute_many", "nuht_batch_info", "nuht_batch_destroy",
                  "nuht_destroy", "nuht_direct", "nuht_profile", "nuht_profile_read", "nuht_fb_plan",
                  "nuht_fb_analysis", "nuht_fb_synthesis", "nuht_fb_helmholtz", "nuht_fb_destroy"):
@@ -240,6 +241,16 @@ class Plan:
         inf = NuhtInfo()
         _check(load_library().nuht_plan_info(self._h, ctypes.byref(inf)))
         return {f: getattr(inf, f) for f, _ in NuhtInfo._fields_}
+
+    def order(self):
+        """The plan's sorted geometry (nuht_plan_order): r sorted, the caller
+        index of each sorted point, omega sorted and its indices."""
+        f64 = dict(dtype=torch.float64, device=self.device)
+        i32 = dict(dtype=torch.int32, device=self.device)
+        rs, pr = torch.empty(self.n, **f64), torch.empty(self.n, **i32)
+        ws, pw = torch.empty(self.m, **f64), torch.empty(self.m, **i32)
+        _check(load_library().nuht_plan_order(self._h, _ptr(rs), _ptr(pr), _ptr(ws), _ptr(pw), _stream()))
+        return rs, pr, ws, pw
 
     def profile(self, enable: bool = True):
         """Start (clearing earlier records) or stop per-stage event timing."""

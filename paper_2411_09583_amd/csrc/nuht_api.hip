@@ -2298,6 +2298,24 @@ int nuht_batch_destroy(nuht_batch_t b)
     return NUHT_OK;
 }
 
+int nuht_plan_order(nuht_plan_t p, double* r_sorted, int32_t* perm_r, double* omega_sorted, int32_t* perm_omega,
+                    void* stream)
+{
+    if (!p) return NUHT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const Geometry& G = p->fwd;   // sorted by plan creation, which synchronised on that work
+    if (r_sorted && G.n > 0) HIP_TRY(hipMemcpyAsync(r_sorted, G.rs, sizeof(double) * (size_t)G.n,
+                                                    hipMemcpyDeviceToDevice, s));
+    if (perm_r && G.n > 0) HIP_TRY(hipMemcpyAsync(perm_r, G.perm_r, sizeof(int32_t) * (size_t)G.n,
+                                                  hipMemcpyDeviceToDevice, s));
+    if (omega_sorted && G.m > 0) HIP_TRY(hipMemcpyAsync(omega_sorted, G.ws, sizeof(double) * (size_t)G.m,
+                                                        hipMemcpyDeviceToDevice, s));
+    if (perm_omega && G.m > 0) HIP_TRY(hipMemcpyAsync(perm_omega, G.perm_w, sizeof(int32_t) * (size_t)G.m,
+                                                      hipMemcpyDeviceToDevice, s));
+    note_use(p, s);
+    return NUHT_OK;
+}
+
 int nuht_plan_info(nuht_plan_t p, nuht_info* info)
 {
     if (!p || !info) return NUHT_EINVAL;

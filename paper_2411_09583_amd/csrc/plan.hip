@@ -370,6 +370,623 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
 }
 
 // ---------------------------------------------------------------------------
+// Sorts with fewer launches for short segments (same stable order as the LSD
+// sort above, whose 25 launches dominate planning there):
+// * both segments up to kSsCap keys: k_sort_small, one workgroup per segment
+//   sorting it in LDS (LSD on 8-bit digits over the bits that vary);
+// * both up to kSsMaxLen keys: a splitter sort in five launches --
+//   1. k_ss_sample: one workgroup per segment sorts a stratified sample of the
+//      keys in LDS (bitonic) and keeps its quantiles, without repeats, as the
+//      splitters u_0 < ... < u_{U-1};
+//   2. k_ss_count: each tile of kSsTile keys counts its keys per bucket (range
+//      bucket 2p: the keys strictly between u_{p-1} and u_p; equality bucket
+//      2p + 1: the keys equal to u_p, which never need sorting) and checks its
+//      inputs;
+//   3. k_ss_scan: per bucket, exclusive offsets over the tiles, the bucket
+//      sizes and the bucket starts;
+//   4. k_ss_scatter: each tile scatters its keys, stably, into the buckets;
+//   5. k_ss_local: one workgroup per bucket sorts it in LDS like k_sort_small;
+//      a bucket beyond the LDS capacity (only when the sample misrepresents
+//      the input) is sorted by the same workgroup through global memory.
+// ---------------------------------------------------------------------------
+constexpr int32_t kSsMaxLen = 1 << 16;   // longest segment the splitter sort takes
+constexpr int kSsBucketMean = 2048;      // target keys per range bucket
+constexpr int kSsMaxSpl = 31;            // splitters per segment at most (kSsMaxLen / kSsBucketMean - 1)
+constexpr int kSsBuckets = 64;           // bucket slots per segment (2 U + 1 <= 63 used)
+constexpr int kSsOversample = 32;        // sample keys per range bucket
+constexpr int kSsSample = 1024;          // sample keys per segment at most
+constexpr int kSsThreads = 512;          // count and scatter workgroups: 8 waves
+constexpr int kSsRounds = 16;            // 64-key rounds per wave
+constexpr int kSsTile = kSsThreads * kSsRounds;
+constexpr int kSsLocalThreads = 256;     // LDS sort workgroups: 4 waves
+constexpr int kSsCap = kSsLocalThreads * kSsRounds;   // longest run sorted in LDS
+static_assert(kSsMaxLen / kSsBucketMean - 1 <= kSsMaxSpl, "splitter table too small");
+static_assert(kSsOversample * (kSsMaxLen / kSsBucketMean) <= kSsSample, "sample buffer too small");
+static_assert(2 * kSsMaxSpl + 1 <= kSsBuckets && kSsBuckets == 64, "bucket table: one lane per bucket");
+
+// Sort key of an input (see k_make_keys); ok is false for a negative, NaN or
+// infinite value, whose key is 0.
+__device__ __forceinline__ uint64_t sort_key(double v, bool& ok)
+{
+    ok = (v >= 0.0) && (v <= 1.7976931348623157e308);
+    return (v == 0.0 || !ok) ? 0ull : (uint64_t)__double_as_longlong(v);
+}
+
+// Bucket of key k among the U sorted splitters su: 2p + (k == u_p), p the
+// number of splitters below k.
+__device__ __forceinline__ int ss_bucket(const uint64_t* su, int U, uint64_t k)
+{
+    int p = 0;
+    #pragma unroll
+    for (int step = 16; step > 0; step >>= 1)
+        if (p + step <= U && su[p + step - 1] < k) p += step;
+    return 2 * p + ((p < U && su[p] == k) ? 1 : 0);
+}
+
+// Lanes of the wave whose bucket b (6 bits) equals the calling lane's, among
+// the lanes with `valid` set.
+__device__ __forceinline__ uint64_t bucket_peers(int b, bool valid)
+{
+    uint64_t peers = __ballot(valid);
+    #pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        uint64_t m = __ballot((b >> i) & 1);
+        peers &= ((b >> i) & 1) ? m : ~m;
+    }
+    return peers;
+}
+
+// Position of sample s of ns in a segment of n keys: one point drawn from each
+// of ns equal strata (a fixed hash of s picks it), so that no period of the
+// input lines up with the sample.
+__device__ __forceinline__ int64_t ss_sample_pos(int s, int ns, int64_t n)
+{
+    uint32_t h = (uint32_t)s * 0x9E3779B9u;
+    h ^= h >> 16; h *= 0x85EBCA6Bu; h ^= h >> 13; h *= 0xC2B2AE35u; h ^= h >> 16;
+    const int64_t lo = ((int64_t)s * n) / ns, hi = ((int64_t)(s + 1) * n) / ns;
+    return lo + (int64_t)(((uint64_t)h * (uint64_t)(hi - lo)) >> 32);
+}
+
+// Stable ranks of the 8-bit digits (key >> shift) of a workgroup's keys, held
+// kSsRounds per lane in (wave, round, lane) order with `rounds` rounds per
+// wave, n_valid of them: rk[q] receives the key's offset among the equal
+// digits before it in its wave, wcnt[v][d] (zeroed by the caller) the count
+// of digit d in wave v's keys.
+__device__ __forceinline__ void ss_rank_digits(const uint64_t (&kr)[kSsRounds], int shift, int rounds, int n_valid,
+                                               int32_t (*wcnt)[256], int (&dg)[kSsRounds], int (&rk)[kSsRounds])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int32_t* cw = wcnt[wave];
+    #pragma unroll
+    for (int q = 0; q < kSsRounds; ++q) {
+        dg[q] = -1;
+        if (q < rounds) {
+            const int i = (wave * rounds + q) * 64 + lane;
+            const bool valid = i < n_valid;
+            const int d = (int)((kr[q] >> shift) & 255);
+            const uint64_t peers = digit_peers(d, valid);
+            const int rank = __popcll(peers & lt_mask);
+            const int32_t before = valid ? cw[d] : 0;
+            wave_sync_lds();
+            if (valid && rank == 0) cw[d] = before + __popcll(peers);
+            wave_sync_lds();
+            rk[q] = before + rank;
+            dg[q] = valid ? d : -1;
+        }
+    }
+}
+
+// Thread d of the 256: the waves' starts of digit d in wcnt (counts in,
+// starts out), after the digit's start among all the keys plus base.
+// Returns the digit's total.
+__device__ __forceinline__ int32_t ss_digit_starts(int32_t (*wcnt)[256], int32_t base, int32_t* wtot)
+{
+    constexpr int kWaves = kSsLocalThreads / 64;
+    const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
+    int32_t c = 0;
+    #pragma unroll
+    for (int v = 0; v < kWaves; ++v) c += wcnt[v][d];
+    const int32_t incl = wave_incl_scan(c);
+    if (lane == 63) wtot[wave] = incl;
+    __syncthreads();
+    int32_t run = base + incl - c;
+    for (int v = 0; v < wave; ++v) run += wtot[v];
+    #pragma unroll
+    for (int v = 0; v < kWaves; ++v) {
+        const int32_t a = wcnt[v][d];
+        wcnt[v][d] = run;
+        run += a;
+    }
+    return c;
+}
+
+// Smallest and largest of the valid keys kr[q] over the block.
+__device__ __forceinline__ void ss_key_range(const uint64_t (&kr)[kSsRounds], int rounds, int n_valid,
+                                             uint64_t* red, uint64_t& kmin, uint64_t& kmax)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t lo = ~0ull, hi = 0ull;
+    #pragma unroll
+    for (int q = 0; q < kSsRounds; ++q) {
+        const int i = (wave * rounds + q) * 64 + lane;
+        if (q < rounds && i < n_valid) { lo = kr[q] < lo ? kr[q] : lo; hi = kr[q] > hi ? kr[q] : hi; }
+    }
+    #pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t a = __shfl_xor(lo, o), b = __shfl_xor(hi, o);
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+    }
+    if (lane == 0) { red[2 * wave] = lo; red[2 * wave + 1] = hi; }
+    __syncthreads();
+    kmin = ~0ull; kmax = 0ull;
+    #pragma unroll
+    for (int v = 0; v < kSsLocalThreads / 64; ++v) {
+        kmin = red[2 * v] < kmin ? red[2 * v] : kmin;
+        kmax = red[2 * v + 1] > kmax ? red[2 * v + 1] : kmax;
+    }
+    __syncthreads();
+}
+
+// LDS of a block sort of up to kSsCap keys.
+struct SsBlockLds {
+    uint64_t key[kSsCap];
+    int32_t val[kSsCap];
+    int32_t wcnt[kSsLocalThreads / 64][256];
+    int32_t wtot[kSsLocalThreads / 64];
+    uint64_t red[2 * (kSsLocalThreads / 64)];
+};
+
+// Rounds per wave for n keys over the block's four waves (wave-major order:
+// key i sits in wave i / (64 rounds), round (i / 64) % rounds, lane i % 64).
+__device__ __forceinline__ int ss_rounds(int n) { return (n + 4 * 64 - 1) / (4 * 64); }
+
+// Stable sort of the block's n <= kSsCap keys (with their values) held in
+// registers as ss_rounds(n) rounds per wave: LSD passes of 8 bits over the
+// bits in which the keys differ, each ranking the keys in registers and
+// exchanging them through LDS.
+__device__ void ss_block_sort(uint64_t (&kr)[kSsRounds], int32_t (&vr)[kSsRounds], int n, SsBlockLds& L)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rounds = ss_rounds(n);
+    int dg[kSsRounds], rk[kSsRounds];
+    uint64_t kmin, kmax;
+    ss_key_range(kr, rounds, n, L.red, kmin, kmax);
+    const uint64_t diff = kmin ^ kmax;
+    const int passes = diff ? (64 - __clzll((long long)diff) + 7) / 8 : 0;
+    for (int p = 0; p < passes; ++p) {
+        for (int i = threadIdx.x; i < kSsLocalThreads / 64 * 256; i += kSsLocalThreads) (&L.wcnt[0][0])[i] = 0;
+        __syncthreads();
+        ss_rank_digits(kr, 8 * p, rounds, n, L.wcnt, dg, rk);
+        __syncthreads();
+        ss_digit_starts(L.wcnt, 0, L.wtot);
+        __syncthreads();
+        #pragma unroll
+        for (int q = 0; q < kSsRounds; ++q) {
+            if (dg[q] >= 0) {
+                const int off = L.wcnt[wave][dg[q]] + rk[q];
+                L.key[off] = kr[q];
+                L.val[off] = vr[q];
+            }
+        }
+        __syncthreads();
+        #pragma unroll
+        for (int q = 0; q < kSsRounds; ++q) {
+            const int i = (wave * rounds + q) * 64 + lane;
+            if (q < rounds && i < n) { kr[q] = L.key[i]; vr[q] = L.val[i]; }
+        }
+    }
+}
+
+// Both segments at most kSsCap keys: one workgroup per segment makes the keys
+// and values, sorts them in LDS into (k0, v0), and sets errs[segment] (1 if
+// the segment holds a negative, NaN or infinite input).
+__global__ __launch_bounds__(kSsLocalThreads) void k_sort_small(const double* __restrict__ r,
+                                                                const double* __restrict__ w, SortSegs S,
+                                                                uint64_t* __restrict__ k0, int32_t* __restrict__ v0,
+                                                                int32_t* __restrict__ errs)
+{
+    __shared__ SsBlockLds L;
+    const int seg = blockIdx.x;
+    const int base = S.off[seg];
+    const int n = S.off[seg + 1] - base;
+    const double* __restrict__ x = seg ? w : r;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rounds = ss_rounds(n);
+    uint64_t kr[kSsRounds];
+    int32_t vr[kSsRounds];
+    bool bad = false;
+    #pragma unroll
+    for (int q = 0; q < kSsRounds; ++q) {
+        const int i = (wave * rounds + q) * 64 + lane;
+        kr[q] = 0ull; vr[q] = 0;
+        if (q < rounds && i < n) {
+            bool ok;
+            kr[q] = sort_key(x[i], ok);
+            bad |= !ok;
+            vr[q] = i;
+        }
+    }
+    const int any_bad = __syncthreads_or(bad ? 1 : 0);
+    if (threadIdx.x == 0) errs[seg] = any_bad ? 1 : 0;
+    if (n == 0) return;
+    ss_block_sort(kr, vr, n, L);
+    #pragma unroll
+    for (int q = 0; q < kSsRounds; ++q) {
+        const int i = (wave * rounds + q) * 64 + lane;
+        if (q < rounds && i < n) { k0[base + i] = kr[q]; v0[base + i] = vr[q]; }
+    }
+}
+
+__global__ __launch_bounds__(kSsSample) void k_ss_sample(const double* __restrict__ r,
+                                                         const double* __restrict__ w, SortSegs S,
+                                                         uint64_t* __restrict__ spl, int32_t* __restrict__ nspl)
+{
+    __shared__ uint64_t sk[kSsSample];
+    __shared__ int32_t wtot[kSsSample / 64];
+    const int seg = blockIdx.x;
+    const int64_t n = S.off[seg + 1] - S.off[seg];
+    const double* __restrict__ x = seg ? w : r;
+    const int B = (int)((n + kSsBucketMean - 1) / kSsBucketMean);   // range buckets wanted
+    if (B <= 1) {
+        if (threadIdx.x == 0) nspl[seg] = 0;
+        return;
+    }
+    const int ns = (int)(n < (int64_t)kSsOversample * B ? n : (int64_t)kSsOversample * B);
+    int np2 = 1;
+    while (np2 < ns) np2 <<= 1;
+    const int t = threadIdx.x;
+    {
+        uint64_t k = ~0ull;
+        if (t < ns) {
+            bool ok;
+            k = sort_key(x[ss_sample_pos(t, ns, n)], ok);
+        }
+        sk[t] = k;
+    }
+    __syncthreads();
+    for (int k = 2; k <= np2; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int l = t ^ j;
+            if (t < np2 && l > t) {
+                const uint64_t a = sk[t], b = sk[l];
+                if ((a > b) == ((t & k) == 0)) { sk[t] = b; sk[l] = a; }
+            }
+            __syncthreads();
+        }
+    // the B - 1 quantiles of the sample, each kept if it differs from the one before
+    const int lane = t & 63, wave = t >> 6;
+    uint64_t c = 0;
+    bool keep = false;
+    if (t < B - 1) {
+        c = sk[((int64_t)(t + 1) * ns) / B];
+        keep = t == 0 || c != sk[((int64_t)t * ns) / B];
+    }
+    const uint64_t kb = __ballot(keep);
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (lane == 0) wtot[wave] = __popcll(kb);
+    __syncthreads();
+    int pos = __popcll(kb & lt_mask);
+    for (int v = 0; v < wave; ++v) pos += wtot[v];
+    if (keep) spl[seg * kSsMaxSpl + pos] = c;
+    if (t == 0) {
+        int tot = 0;
+        for (int v = 0; v < kSsSample / 64; ++v) tot += wtot[v];
+        nspl[seg] = tot;
+    }
+}
+
+// Per tile: the bucket counts (tile-major, kSsBuckets per tile) and
+// errs[tile] (1 if the tile holds a negative, NaN or infinite input).
+__global__ __launch_bounds__(kSsThreads) void k_ss_count(const double* __restrict__ r,
+                                                         const double* __restrict__ w, SortSegs S,
+                                                         const uint64_t* __restrict__ spl,
+                                                         const int32_t* __restrict__ nspl,
+                                                         int32_t* __restrict__ cnt, int32_t* __restrict__ errs)
+{
+    __shared__ uint64_t su[kSsMaxSpl];
+    __shared__ int32_t h[kSsBuckets];
+    const int tile = blockIdx.x;
+    const int seg = tile_segment(S, tile);
+    const int lt = tile - S.tile0[seg];
+    const int base = S.off[seg], end = S.off[seg + 1];
+    const int U = nspl[seg];
+    const double* __restrict__ x = seg ? w : r;
+    if (threadIdx.x < U) su[threadIdx.x] = spl[seg * kSsMaxSpl + threadIdx.x];
+    if (threadIdx.x < kSsBuckets) h[threadIdx.x] = 0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wbase = base + lt * kSsTile + wave * 64 * kSsRounds;
+    double v[kSsRounds];
+    #pragma unroll
+    for (int q = 0; q < kSsRounds; ++q) {
+        const int i = wbase + q * 64 + lane;
+        v[q] = i < end ? x[i - base] : 0.0;
+    }
+    __syncthreads();
+    bool bad = false;
+    #pragma unroll
+    for (int q = 0; q < kSsRounds; ++q) {
+        const int i = wbase + q * 64 + lane;
+        int b = -1;
+        if (i < end) {
+            bool ok;
+            const uint64_t k = sort_key(v[q], ok);
+            bad |= !ok;
+            b = ss_bucket(su, U, k);
+        }
+        // a bucket shared by the whole round (sorted or clustered input) costs one add
+        const int b0 = __shfl(b, 0);
+        const uint64_t valid = __ballot(b >= 0);
+        const uint64_t same = __ballot(b >= 0 && b == b0);
+        if (b0 >= 0 && same == valid) {
+            if (lane == 0) atomicAdd(&h[b0], (int32_t)__popcll(valid));
+        } else if (b >= 0) {
+            atomicAdd(&h[b], 1);
+        }
+    }
+    const int any_bad = __syncthreads_or(bad ? 1 : 0);
+    if (threadIdx.x < kSsBuckets) cnt[(int64_t)tile * kSsBuckets + threadIdx.x] = h[threadIdx.x];
+    if (threadIdx.x == 0) errs[tile] = any_bad ? 1 : 0;
+}
+
+// One wave per segment, one lane per bucket: the bucket's counts over the
+// segment's tiles become exclusive offsets, btot receives the bucket sizes
+// and bstart their exclusive scan over the buckets.
+__global__ __launch_bounds__(kSsBuckets) void k_ss_scan(SortSegs S, int32_t* __restrict__ cnt,
+                                                        int32_t* __restrict__ bstart, int32_t* __restrict__ btot)
+{
+    const int seg = blockIdx.x, b = threadIdx.x;
+    const int t0 = S.tile0[seg], nt = S.tile0[seg + 1] - t0;
+    int32_t run = 0;
+    for (int t = 0; t < nt; ++t) {
+        int32_t* c = cnt + (int64_t)(t0 + t) * kSsBuckets + b;
+        const int32_t v = *c;
+        *c = run;
+        run += v;
+    }
+    btot[seg * kSsBuckets + b] = run;
+    bstart[seg * kSsBuckets + b] = wave_incl_scan(run) - run;
+}
+
+// Stable scatter of a tile into the buckets, through LDS: wave v owns the
+// tile's keys v * 1024 .. v * 1024 + 1023 (in order), ranked 64 at a time
+// among the equal buckets of their round plus the wave's earlier keys of that
+// bucket; one block step turns the waves' counts into LDS starts; the staged
+// tile is written out with consecutive threads on consecutive addresses of
+// each bucket's run.
+__global__ __launch_bounds__(kSsThreads) void k_ss_scatter(const double* __restrict__ r,
+                                                           const double* __restrict__ w, SortSegs S,
+                                                           const uint64_t* __restrict__ spl,
+                                                           const int32_t* __restrict__ nspl,
+                                                           const int32_t* __restrict__ cnt,
+                                                           const int32_t* __restrict__ bstart,
+                                                           uint64_t* __restrict__ kout, int32_t* __restrict__ vout)
+{
+    constexpr int kWaves = kSsThreads / 64;
+    __shared__ uint64_t skey[kSsTile];
+    __shared__ int32_t sval[kSsTile];
+    __shared__ uint8_t sbk[kSsTile];
+    __shared__ uint64_t su[kSsMaxSpl];
+    __shared__ int32_t wcnt[kWaves][kSsBuckets];
+    __shared__ int32_t gbase[kSsBuckets];
+    __shared__ int32_t lstart[kSsBuckets];
+    const int tile = blockIdx.x;
+    const int seg = tile_segment(S, tile);
+    const int lt = tile - S.tile0[seg];
+    const int base = S.off[seg], end = S.off[seg + 1];
+    const int start = base + lt * kSsTile;
+    const int U = nspl[seg];
+    const double* __restrict__ x = seg ? w : r;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int wbase = start + wave * 64 * kSsRounds;
+    uint64_t kr[kSsRounds];
+    #pragma unroll
+    for (int q = 0; q < kSsRounds; ++q) {
+        const int i = wbase + q * 64 + lane;
+        bool ok;
+        kr[q] = i < end ? sort_key(x[i - base], ok) : 0ull;
+    }
+    if (threadIdx.x < U) su[threadIdx.x] = spl[seg * kSsMaxSpl + threadIdx.x];
+    for (int i = threadIdx.x; i < kWaves * kSsBuckets; i += kSsThreads) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+    int bk[kSsRounds], rk[kSsRounds];
+    int32_t* cw = wcnt[wave];
+    #pragma unroll
+    for (int q = 0; q < kSsRounds; ++q) {
+        const int i = wbase + q * 64 + lane;
+        const bool valid = i < end;
+        const int b = valid ? ss_bucket(su, U, kr[q]) : 0;
+        const uint64_t peers = bucket_peers(b, valid);
+        const int rank = __popcll(peers & lt_mask);
+        const int32_t before = valid ? cw[b] : 0;
+        wave_sync_lds();
+        if (valid && rank == 0) cw[b] = before + __popcll(peers);
+        wave_sync_lds();
+        rk[q] = before + rank;
+        bk[q] = valid ? b : -1;
+    }
+    __syncthreads();
+    // wave 0, lane b: the tile's count of bucket b, its LDS start (exclusive
+    // scan over the buckets), the waves' starts and the global base
+    if (wave == 0) {
+        const int b = lane;
+        int32_t c = 0;
+        #pragma unroll
+        for (int v = 0; v < kWaves; ++v) c += wcnt[v][b];
+        const int32_t ls = wave_incl_scan(c) - c;
+        lstart[b] = ls;
+        int32_t run = ls;
+        #pragma unroll
+        for (int v = 0; v < kWaves; ++v) {
+            const int32_t a = wcnt[v][b];
+            wcnt[v][b] = run;
+            run += a;
+        }
+        gbase[b] = base + bstart[seg * kSsBuckets + b] + cnt[(int64_t)tile * kSsBuckets + b];
+    }
+    __syncthreads();
+    #pragma unroll
+    for (int q = 0; q < kSsRounds; ++q) {
+        if (bk[q] >= 0) {
+            const int off = cw[bk[q]] + rk[q];
+            skey[off] = kr[q];
+            sval[off] = wbase + q * 64 + lane - base;
+            sbk[off] = (uint8_t)bk[q];
+        }
+    }
+    __syncthreads();
+    const int n_tile = (end - start) < kSsTile ? (end - start) : kSsTile;
+    for (int q = threadIdx.x; q < n_tile; q += kSsThreads) {
+        const int b = sbk[q];
+        const int dst = gbase[b] + (q - lstart[b]);
+        kout[dst] = skey[q];
+        vout[dst] = sval[q];
+    }
+}
+
+__device__ __forceinline__ uint64_t load_coherent(const uint64_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int32_t load_coherent(const int32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One workgroup per (segment, bucket slot): the bucketed keys (kin, vin) of
+// the bucket, sorted stably, into (kout, vout) at the same offsets.
+__global__ __launch_bounds__(kSsLocalThreads) void k_ss_local(SortSegs S, const int32_t* __restrict__ nspl,
+                                                              const int32_t* __restrict__ bstart,
+                                                              const int32_t* __restrict__ btot,
+                                                              uint64_t* __restrict__ kin, int32_t* __restrict__ vin,
+                                                              uint64_t* __restrict__ kout,
+                                                              int32_t* __restrict__ vout)
+{
+    constexpr int kWaves = kSsLocalThreads / 64;
+    __shared__ SsBlockLds L;
+    __shared__ int32_t gb[256];
+    const int seg = blockIdx.x / kSsBuckets, b = blockIdx.x % kSsBuckets;
+    if (b > 2 * nspl[seg]) return;
+    const int32_t size = btot[seg * kSsBuckets + b];
+    if (size == 0) return;
+    const int64_t start = S.off[seg] + bstart[seg * kSsBuckets + b];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if ((b & 1) || size == 1) {   // equal keys: already in order
+        for (int32_t i = threadIdx.x; i < size; i += kSsLocalThreads) {
+            kout[start + i] = kin[start + i];
+            vout[start + i] = vin[start + i];
+        }
+        return;
+    }
+    uint64_t kr[kSsRounds];
+    int32_t vr[kSsRounds];
+    if (size <= kSsCap) {
+        const int rounds = ss_rounds(size);
+        #pragma unroll
+        for (int q = 0; q < kSsRounds; ++q) {
+            const int i = (wave * rounds + q) * 64 + lane;
+            const bool in = q < rounds && i < size;
+            kr[q] = in ? kin[start + i] : 0ull;
+            vr[q] = in ? vin[start + i] : 0;
+        }
+        ss_block_sort(kr, vr, size, L);
+        #pragma unroll
+        for (int q = 0; q < kSsRounds; ++q) {
+            const int i = (wave * rounds + q) * 64 + lane;
+            if (q < rounds && i < size) { kout[start + i] = kr[q]; vout[start + i] = vr[q]; }
+        }
+        return;
+    }
+    // A bucket beyond the LDS: LSD passes through global memory, chunk by
+    // chunk (kSsCap keys, kSsRounds rounds per wave) in order, between
+    // (kin, vin) and (kout, vout); a chunk's keys are written straight to
+    // their places.  Data written by an earlier pass is read with
+    // cache-coherent loads.
+    int dg[kSsRounds], rk[kSsRounds];
+    uint64_t kmin = ~0ull, kmax = 0ull;
+    for (int32_t c0 = 0; c0 < size; c0 += kSsCap) {
+        const int nv = size - c0 < kSsCap ? size - c0 : kSsCap;
+        #pragma unroll
+        for (int q = 0; q < kSsRounds; ++q) {
+            const int i = (wave * kSsRounds + q) * 64 + lane;
+            kr[q] = i < nv ? kin[start + c0 + i] : 0ull;
+        }
+        uint64_t lo, hi;
+        ss_key_range(kr, kSsRounds, nv, L.red, lo, hi);
+        kmin = lo < kmin ? lo : kmin;
+        kmax = hi > kmax ? hi : kmax;
+    }
+    const uint64_t diff = kmin ^ kmax;
+    const int passes = diff ? (64 - __clzll((long long)diff) + 7) / 8 : 0;
+    uint64_t* ks = kin; int32_t* vs = vin; uint64_t* kd = kout; int32_t* vd = vout;
+    for (int p = 0; p < passes; ++p) {
+        // digit totals over the bucket
+        for (int i = threadIdx.x; i < kWaves * 256; i += kSsLocalThreads) (&L.wcnt[0][0])[i] = 0;
+        __syncthreads();
+        for (int32_t c0 = 0; c0 < size; c0 += kSsCap) {
+            const int nv = size - c0 < kSsCap ? size - c0 : kSsCap;
+            #pragma unroll
+            for (int q = 0; q < kSsRounds; ++q) {
+                const int i = (wave * kSsRounds + q) * 64 + lane;
+                kr[q] = i < nv ? load_coherent(ks + start + c0 + i) : 0ull;
+            }
+            ss_rank_digits(kr, 8 * p, kSsRounds, nv, L.wcnt, dg, rk);   // wcnt accumulates over the chunks
+        }
+        __syncthreads();
+        {
+            int32_t c = 0;
+            #pragma unroll
+            for (int v = 0; v < kWaves; ++v) c += L.wcnt[v][threadIdx.x];
+            const int32_t incl = wave_incl_scan(c);
+            if (lane == 63) L.wtot[wave] = incl;
+            __syncthreads();
+            int32_t ex = incl - c;
+            for (int v = 0; v < wave; ++v) ex += L.wtot[v];
+            gb[threadIdx.x] = ex;   // the digit's next free place in the bucket
+        }
+        __syncthreads();
+        for (int32_t c0 = 0; c0 < size; c0 += kSsCap) {
+            const int nv = size - c0 < kSsCap ? size - c0 : kSsCap;
+            #pragma unroll
+            for (int q = 0; q < kSsRounds; ++q) {
+                const int i = (wave * kSsRounds + q) * 64 + lane;
+                kr[q] = i < nv ? load_coherent(ks + start + c0 + i) : 0ull;
+                vr[q] = i < nv ? load_coherent(vs + start + c0 + i) : 0;
+            }
+            for (int i = threadIdx.x; i < kWaves * 256; i += kSsLocalThreads) (&L.wcnt[0][0])[i] = 0;
+            __syncthreads();
+            ss_rank_digits(kr, 8 * p, kSsRounds, nv, L.wcnt, dg, rk);
+            __syncthreads();
+            const int32_t c = ss_digit_starts(L.wcnt, 0, L.wtot);   // chunk-local starts
+            __syncthreads();
+            #pragma unroll
+            for (int q = 0; q < kSsRounds; ++q) {
+                if (dg[q] >= 0) {
+                    // the digit's next free place + the key's offset among the chunk's keys of that digit
+                    const int32_t dst = gb[dg[q]] + (L.wcnt[wave][dg[q]] + rk[q]) - L.wcnt[0][dg[q]];
+                    kd[start + dst] = kr[q];
+                    vd[start + dst] = vr[q];
+                }
+            }
+            __syncthreads();
+            gb[threadIdx.x] += c;
+            __syncthreads();
+        }
+        uint64_t* tk = ks; ks = kd; kd = tk;
+        int32_t* tv = vs; vs = vd; vd = tv;
+    }
+    if (ks != kout) {   // an even number of passes: the result is still in (kin, vin)
+        for (int32_t i = threadIdx.x; i < size; i += kSsLocalThreads) {
+            kout[start + i] = load_coherent(kin + start + i);
+            vout[start + i] = load_coherent(vin + start + i);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Staircases of the local region (the product decided exactly):
 //   K[j]  = #{k : omega_j r_k <= z}   (rows; K is nonincreasing in j)
 //   Jc[k] = #{j : omega_j r_k <= z}   (columns; Jc is nonincreasing in k)
@@ -966,9 +1583,59 @@ static SortSegs sort_segs(int32_t na, int32_t nb)
     return S;
 }
 
+// Scratch layout of the splitter sort in hist (int32 units): the splitters
+// (2 x kSsMaxSpl uint64), their counts, the bucket starts and sizes (2 x
+// kSsBuckets each), then the tile-major bucket counts.
+constexpr int kSsSplOff = 0, kSsNsplOff = 128, kSsStartOff = 192;
+constexpr int kSsTotOff = kSsStartOff + 2 * kSsBuckets, kSsCntOff = kSsTotOff + 2 * kSsBuckets;
+static_assert(2 * 2 * kSsMaxSpl <= kSsNsplOff, "splitter area too small");
+
+enum class SortPath { small, splitter, lsd };
+
+static SortPath sort_path(int32_t na, int32_t nb)
+{
+    if (na <= kSsCap && nb <= kSsCap) return SortPath::small;
+    if (na <= kSsMaxLen && nb <= kSsMaxLen) return SortPath::splitter;
+    return SortPath::lsd;
+}
+
+static SortSegs ss_segs(int32_t na, int32_t nb)
+{
+    SortSegs S;
+    S.off[0] = 0; S.off[1] = na; S.off[2] = na + nb;
+    const int ta = cdiv(na, kSsTile), tb = cdiv(nb, kSsTile);
+    S.tile0[0] = 0; S.tile0[1] = ta; S.tile0[2] = ta + tb;
+    S.hoff[0] = S.hoff[1] = S.hoff[2] = 0;
+    return S;
+}
+
 hipError_t launch_keys_and_sort(const double* r, int32_t na, const double* w, int32_t nb, uint64_t* k0, int32_t* v0,
                                 uint64_t* k1, int32_t* v1, int32_t* hist, int32_t* errs, hipStream_t s)
 {
+    const SortPath path = sort_path(na, nb);
+    if (path == SortPath::small) {
+        if (na + nb == 0) return hipSuccess;
+        const SortSegs S = ss_segs(na, nb);
+        hipLaunchKernelGGL(k_sort_small, dim3(2), dim3(kSsLocalThreads), 0, s, r, w, S, k0, v0, errs);
+        return hipGetLastError();
+    }
+    if (path == SortPath::splitter) {
+        const SortSegs S = ss_segs(na, nb);
+        const int tiles = S.tile0[2];
+        uint64_t* spl = (uint64_t*)(hist + kSsSplOff);
+        int32_t* nspl = hist + kSsNsplOff;
+        int32_t* bstart = hist + kSsStartOff;
+        int32_t* btot = hist + kSsTotOff;
+        int32_t* cnt = hist + kSsCntOff;
+        hipLaunchKernelGGL(k_ss_sample, dim3(2), dim3(kSsSample), 0, s, r, w, S, spl, nspl);
+        hipLaunchKernelGGL(k_ss_count, dim3(tiles), dim3(kSsThreads), 0, s, r, w, S, spl, nspl, cnt, errs);
+        hipLaunchKernelGGL(k_ss_scan, dim3(2), dim3(kSsBuckets), 0, s, S, cnt, bstart, btot);
+        hipLaunchKernelGGL(k_ss_scatter, dim3(tiles), dim3(kSsThreads), 0, s, r, w, S, spl, nspl, cnt, bstart, k1,
+                           v1);
+        hipLaunchKernelGGL(k_ss_local, dim3(2 * kSsBuckets), dim3(kSsLocalThreads), 0, s, S, nspl, bstart, btot, k1,
+                           v1, k0, v0);
+        return hipGetLastError();
+    }
     const SortSegs S = sort_segs(na, nb);
     const int tiles = S.tile0[2];
     if (tiles == 0) return hipSuccess;
@@ -994,9 +1661,23 @@ hipError_t launch_reduce_errs(const int32_t* errs, int32_t n, int32_t* flag, hip
     return hipGetLastError();
 }
 
-int sort_tiles(int32_t na, int32_t nb) { return cdiv(na, kSortTile) + cdiv(nb, kSortTile); }
+int sort_tiles(int32_t na, int32_t nb)
+{
+    switch (sort_path(na, nb)) {
+        case SortPath::small: return 2;
+        case SortPath::splitter: return cdiv(na, kSsTile) + cdiv(nb, kSsTile);
+        default: return cdiv(na, kSortTile) + cdiv(nb, kSortTile);
+    }
+}
 
-int sort_hist_len(int32_t na, int32_t nb) { return 256 * sort_tiles(na, nb) + 2 * 256; }
+int sort_hist_len(int32_t na, int32_t nb)
+{
+    switch (sort_path(na, nb)) {
+        case SortPath::small: return 1;
+        case SortPath::splitter: return kSsCntOff + kSsBuckets * sort_tiles(na, nb);
+        default: return 256 * sort_tiles(na, nb) + 2 * 256;
+    }
+}
 
 hipError_t launch_planning(const PlanDev& P, const Arena& A, int32_t* K, int32_t* Jc, int32_t* a_cells,
                            int64_t min_size, int32_t ncand, int32_t dft_max, double sigma, Summary* sum,
