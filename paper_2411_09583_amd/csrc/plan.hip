@@ -164,10 +164,12 @@ __device__ __forceinline__ T wave_incl_scan(T v)
     return v;
 }
 
-// Exclusive scan of v[q] over the block; tot[q] receives the block total.
-template <class T, int NV>
+// Exclusive scan of v[q] over the block of NW waves (at most 16); tot[q]
+// receives the block total.
+template <class T, int NV, int NW = 16>
 __device__ void block_scan(T (&v)[NV], T (&tot)[NV], T (*wsum)[16])
 {
+    static_assert(NW >= 1 && NW <= 16, "one wave scans the wave totals");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     T incl[NV];
     #pragma unroll
@@ -180,25 +182,25 @@ __device__ void block_scan(T (&v)[NV], T (&tot)[NV], T (*wsum)[16])
     if (wave == 0) {
         #pragma unroll
         for (int q = 0; q < NV; ++q) {
-            T x = lane < 16 ? wsum[q][lane] : T(0);
+            T x = lane < NW ? wsum[q][lane] : T(0);
             x = wave_incl_scan(x);
-            if (lane < 16) wsum[q][lane] = x;
+            if (lane < NW) wsum[q][lane] = x;
         }
     }
     __syncthreads();
     #pragma unroll
     for (int q = 0; q < NV; ++q) {
         T base = wave > 0 ? wsum[q][wave - 1] : T(0);
-        tot[q] = wsum[q][15];
+        tot[q] = wsum[q][NW - 1];
         v[q] = base + incl[q] - v[q];
     }
     __syncthreads();
 }
 
-// Exclusive scan over the block of VPT consecutive values per thread (NV
-// independent sequences): each thread's own running sums, then a block scan of
-// the thread totals.  tot receives the block totals.
-template <int NV, int VPT>
+// Exclusive scan over the block (NW waves) of VPT consecutive values per
+// thread (NV independent sequences): each thread's own running sums, then a
+// block scan of the thread totals.  tot receives the block totals.
+template <int NV, int VPT, int NW = 16>
 __device__ void block_scan_vpt(int64_t (&v)[VPT][NV], int64_t (&tot)[NV], int64_t (*wsum)[16])
 {
     int64_t t[NV];
@@ -212,7 +214,7 @@ __device__ void block_scan_vpt(int64_t (&v)[VPT][NV], int64_t (&tot)[NV], int64_
             v[k][q] = t[q];
             t[q] += x;
         }
-    block_scan<int64_t, NV>(t, tot, wsum);
+    block_scan<int64_t, NV, NW>(t, tot, wsum);
     #pragma unroll
     for (int k = 0; k < VPT; ++k)
         #pragma unroll
@@ -1340,15 +1342,21 @@ __global__ void k_block_params(PlanDev P, Arena A, int32_t dft_max, double sigma
 }
 
 // ---------------------------------------------------------------------------
-// Offsets and totals (one 1024-thread block): exclusive scans over the blocks
-// of item counts and grid slots, the FFT size classes, membership statistics.
+// Offsets and totals (one workgroup): exclusive scans over the blocks of item
+// counts and grid slots, the FFT size classes, membership statistics.
+// The block and item scans run as one workgroup of kPlanScanThreads (at most
+// 128 VGPRs per wave): a workgroup this small fits on a compute unit as soon
+// as one workgroup of a running transform's kernels retires there, where a
+// 1024-thread one waits for a whole compute unit to drain.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, Summary* __restrict__ sum)
+constexpr int kPlanScanThreads = 256;
+
+__global__ __launch_bounds__(kPlanScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_plan_scan(PlanDev P, Arena A, Summary* __restrict__ sum)
 {
     __shared__ int64_t wsum[2][16];
     __shared__ int32_t cls_cnt[kMaxFftLog2 + 1];
     __shared__ int32_t cls_first[kMaxFftLog2 + 1];
-    __shared__ long long red[9][1024 / 64];
+    __shared__ long long red[9][kPlanScanThreads / 64];
     if (sum->overflow) return;
     const int32_t n_l = sum->n_l, n_a = sum->n_a, n_d = sum->n_d;
     int tid = threadIdx.x;
@@ -1361,9 +1369,9 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, Summary*
     // path), gathered in the same passes
     constexpr int kStats = 9;
     long long st[kStats] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    constexpr int kVpt = 8;                          // blocks per thread per pass (8192 per pass)
+    constexpr int kVpt = 8;                          // blocks per thread per pass (2048 per pass)
     int64_t l_items = 0;
-    for (int32_t c0 = 0; c0 < n_l; c0 += 1024 * kVpt) {
+    for (int32_t c0 = 0; c0 < n_l; c0 += kPlanScanThreads * kVpt) {
         const int32_t i0 = c0 + tid * kVpt;
         int64_t v[kVpt][1];
         #pragma unroll
@@ -1377,14 +1385,14 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, Summary*
             }
         }
         int64_t tot[1];
-        block_scan_vpt<1, kVpt>(v, tot, wsum);
+        block_scan_vpt<1, kVpt, kPlanScanThreads / 64>(v, tot, wsum);
         #pragma unroll
         for (int k = 0; k < kVpt; ++k)
             if (i0 + k < n_l) A.lb[i0 + k].item0 = (int32_t)(l_items + v[k][0]);
         l_items += tot[0];
     }
     int64_t a_items = 0, grid = 0;
-    for (int32_t c0 = 0; c0 < n_a; c0 += 1024 * kVpt) {
+    for (int32_t c0 = 0; c0 < n_a; c0 += kPlanScanThreads * kVpt) {
         const int32_t i0 = c0 + tid * kVpt;
         int64_t v[kVpt][2];
         bool fft[kVpt];
@@ -1408,7 +1416,7 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, Summary*
             }
         }
         int64_t tot[2];
-        block_scan_vpt<2, kVpt>(v, tot, wsum);
+        block_scan_vpt<2, kVpt, kPlanScanThreads / 64>(v, tot, wsum);
         #pragma unroll
         for (int k = 0; k < kVpt; ++k) {
             const int32_t i = i0 + k;
@@ -1437,7 +1445,7 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, Summary*
     }
     __syncthreads();
     // FFT-path blocks grouped by size class (order inside a class is immaterial)
-    for (int32_t i = tid; i < n_a; i += 1024) {
+    for (int32_t i = tid; i < n_a; i += kPlanScanThreads) {
         ABlock B = A.ab[i];
         if (B.fft) {
             int c = 31 - __clz(B.N2);
@@ -1446,7 +1454,7 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, Summary*
             A.ab[i].fft_slot = slot;
         }
     }
-    for (int32_t i = tid; i < n_d; i += 1024) {
+    for (int32_t i = tid; i < n_d; i += kPlanScanThreads) {
         DBlock Db = A.db[i];
         st[4] += (long long)(Db.j1 - Db.j0 + 1) * (Db.k1 - Db.k0 + 1);
     }
@@ -1459,7 +1467,7 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanDev P, Arena A, Summary*
     if (tid == 0) {
         long long t[kStats] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int q = 0; q < kStats; ++q)
-            for (int w2 = 0; w2 < 1024 / 64; ++w2) t[q] += red[q][w2];
+            for (int w2 = 0; w2 < kPlanScanThreads / 64; ++w2) t[q] += red[q][w2];
         sum->l_row = t[0]; sum->l_col = t[1]; sum->a_row = t[2]; sum->a_col = t[3];
         sum->d_ent = t[4]; sum->dft_cells = t[5]; sum->fft_points = t[6];
         sum->dft_row_cells = t[7]; sum->fft_rows = t[8];
@@ -1528,16 +1536,16 @@ __global__ void k_items(PlanDev P, Arena A, Summary* __restrict__ sum, int32_t* 
 // Partial-subgrid offsets of the asymptotic items, and the spreading order:
 // dense items at alist[0 ..) and the others at alist[n_ai - 1], alist[n_ai - 2],
 // ..., each list in item order (one 1024-thread block).
-__global__ __launch_bounds__(1024) void k_item_scan(PlanDev P, Arena A, Summary* __restrict__ sum,
+__global__ __launch_bounds__(kPlanScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_item_scan(PlanDev P, Arena A, Summary* __restrict__ sum,
                                                     const int32_t* __restrict__ a_cells)
 {
     __shared__ int64_t wsum[2][16];
     if (sum->overflow) return;
     const int32_t n_ai = sum->n_aitems;
     const int nch = P.nch;
-    constexpr int kVpt = 8;                          // items per thread per pass (8192 per pass)
+    constexpr int kVpt = 8;                          // items per thread per pass (2048 per pass)
     int64_t run = 0, run_dense = 0;
-    for (int32_t c0 = 0; c0 < n_ai; c0 += 1024 * kVpt) {
+    for (int32_t c0 = 0; c0 < n_ai; c0 += kPlanScanThreads * kVpt) {
         const int32_t i0 = c0 + threadIdx.x * kVpt;
         int64_t v[kVpt][2];
         bool dense[kVpt];
@@ -1549,7 +1557,7 @@ __global__ __launch_bounds__(1024) void k_item_scan(PlanDev P, Arena A, Summary*
             v[k][1] = dense[k] ? 1 : 0;
         }
         int64_t tot[2];
-        block_scan_vpt<2, kVpt>(v, tot, wsum);
+        block_scan_vpt<2, kVpt, kPlanScanThreads / 64>(v, tot, wsum);
         #pragma unroll
         for (int k = 0; k < kVpt; ++k) {
             const int32_t i = i0 + k;
@@ -1688,9 +1696,9 @@ hipError_t launch_planning(const PlanDev& P, const Arena& A, int32_t* K, int32_t
     hipLaunchKernelGGL(k_staircase, dim3(cdiv(n, 256)), dim3(256), 0, s, P.ws, m, P.rs, n, P.z, Jc);
     hipLaunchKernelGGL(k_subdivide, dim3(1), dim3(1024), 0, s, K, Jc, m, n, min_size, ncand, A, sum, errs, n_errs);
     hipLaunchKernelGGL(k_block_params, dim3(256), dim3(128), 0, s, P, A, dft_max, sigma, sum);
-    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, s, P, A, sum);
+    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(kPlanScanThreads), 0, s, P, A, sum);
     hipLaunchKernelGGL(k_items, dim3(512), dim3(128), 0, s, P, A, sum, a_cells);
-    hipLaunchKernelGGL(k_item_scan, dim3(1), dim3(1024), 0, s, P, A, sum, a_cells);
+    hipLaunchKernelGGL(k_item_scan, dim3(1), dim3(kPlanScanThreads), 0, s, P, A, sum, a_cells);
     return hipGetLastError();
 }
 
