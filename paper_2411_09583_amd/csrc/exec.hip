@@ -135,10 +135,11 @@ __global__ void k_half_difference(const double* __restrict__ w, const double* __
 // Local moments t_l = sum_k c_k T_{2l(+1)}(r_k / R) of one chunk of a local
 // block's columns (Sec. 3.1: T^T applied first).  The Chebyshev polynomials
 // come from the recurrence in u = 2y^2 - 1:  T_{2(l+1)+e}(y) = 2u T_{2l+e}(y) - T_{2(l-1)+e}(y).
-// Moments are produced in passes of 32 (the last of 16 or 8 when no more are
-// left).  One 64-lane wave per item: each lane accumulates its points'
-// moments in registers (points strided over the lanes), and the wave reduces
-// them with cross-lane sums.
+// Moments are produced in passes of up to 64 (a multiple of 8: all L + 1 in
+// one pass up to L = 63, so no pass repeats the recurrence through an earlier
+// pass's moments there).  One 64-lane wave per item: each lane accumulates its
+// points' moments in registers (points strided over the lanes), and the wave
+// reduces them with cross-lane sums, in chunks of 64, 32, 16 and 8 moments.
 // ---------------------------------------------------------------------------
 // One reduce-scatter level: v[0 .. 2H) -> v[0 .. H), lanes with bit H set
 // keeping the upper half; partner lane ^ H holds the other copy.
@@ -154,11 +155,44 @@ __device__ __forceinline__ void reduce_scatter_half(double (&v)[NQ], int lane)
     }
 }
 
-// Moments s0 .. s0 + NQ - 1 of the item (those up to L are stored).
+// Sum over the wave of the C moments acc[off .. off + C) (C a power of two,
+// 8 to 64): a reduce-scatter at offsets C/2 .. 1 leaves lane q with moment
+// off + (q mod C) summed over the lanes congruent to q; exchanges at offsets
+// C .. 32 complete the sums.
+template <int C, int NQ>
+__device__ __forceinline__ double reduce_chunk(const double (&acc)[NQ], int off, int lane)
+{
+    double v[C];
+    #pragma unroll
+    for (int i = 0; i < C; ++i) v[i] = acc[off + i];
+    if constexpr (C >= 64) reduce_scatter_half<32>(v, lane);
+    if constexpr (C >= 32) reduce_scatter_half<16>(v, lane);
+    if constexpr (C >= 16) reduce_scatter_half<8>(v, lane);
+    reduce_scatter_half<4>(v, lane);
+    reduce_scatter_half<2>(v, lane);
+    reduce_scatter_half<1>(v, lane);
+    double mine = v[0];
+    #pragma unroll
+    for (int o = C; o < 64; o <<= 1) mine += __shfl_xor(mine, o);
+    return mine;
+}
+
+// Stores the chunk of C moments starting at s0 + off (those up to L).
+template <int C, int NQ>
+__device__ __forceinline__ void store_chunk(const double (&acc)[NQ], int off, int s0, int L, int lane,
+                                            double* __restrict__ dst)
+{
+    const double mine = reduce_chunk<C>(acc, off, lane);
+    if (lane < C && s0 + off + lane <= L) dst[s0 + off + lane] = mine;
+}
+
+// Moments s0 .. s0 + NQ - 1 of the item (those up to L are stored); NQ a
+// multiple of 8 up to 64.
 template <int NQ>
 __device__ __forceinline__ void lmom_pass(const PlanDev& P, const Item& I, const LBlock& B, const double* __restrict__ cs,
                                           double* __restrict__ lpart, int s0, int lane, int bid)
 {
+    static_assert(NQ % 8 == 0 && NQ >= 8 && NQ <= 64, "pass width");
     const int L = P.L;
     const int odd = P.nu & 1;
     double acc[NQ];
@@ -191,21 +225,18 @@ __device__ __forceinline__ void lmom_pass(const PlanDev& P, const Item& I, const
             a0 = a1; a1 = a2; b0 = b1; b1 = b2;
         }
     }
-    // Reduce-scatter over the wave: at offsets NQ/2 .. 1 each lane keeps the
-    // half of its values that its lane bit selects and adds its partner's
-    // copy of that half, so lane q holds moment s0 + (q mod NQ); exchanges at
-    // offsets NQ .. 32 complete the sums.
-    if constexpr (NQ >= 32) reduce_scatter_half<16>(acc, lane);
-    if constexpr (NQ >= 16) reduce_scatter_half<8>(acc, lane);
-    reduce_scatter_half<4>(acc, lane);
-    reduce_scatter_half<2>(acc, lane);
-    reduce_scatter_half<1>(acc, lane);
-    double mine = acc[0];
-    #pragma unroll
-    for (int o = NQ; o < 64; o <<= 1) mine += __shfl_xor(mine, o);
-    if (lane < NQ && s0 + lane <= L) lpart[(int64_t)bid * (L + 1) + s0 + lane] = mine;
+    // the pass's moments in chunks of 64, 32, 16 and 8 (NQ's binary digits)
+    double* __restrict__ dst = lpart + (int64_t)bid * (L + 1);
+    constexpr int c64 = NQ & 64, c32 = NQ & 32, c16 = NQ & 16, c8 = NQ & 8;
+    if constexpr (c64) store_chunk<64>(acc, 0, s0, L, lane, dst);
+    if constexpr (c32) store_chunk<32>(acc, c64, s0, L, lane, dst);
+    if constexpr (c16) store_chunk<16>(acc, c64 + c32, s0, L, lane, dst);
+    if constexpr (c8) store_chunk<8>(acc, c64 + c32 + c16, s0, L, lane, dst);
 }
 
+// MAXQ: the widest pass (32 or 64).  A kernel's registers follow its widest
+// pass, so orders with L < 32 run the 32-wide instance at twice the waves.
+template <int MAXQ>
 __device__ __forceinline__ void lmom_body(const PlanDev& P, int bid)
 {
     const Item I = P.litems[bid];
@@ -214,22 +245,36 @@ __device__ __forceinline__ void lmom_body(const PlanDev& P, int bid)
     const int lane = threadIdx.x;
     const double* __restrict__ cs = P.cs;
     double* __restrict__ lpart = P.lpart;
-    // passes of 32 moments; the last one as narrow as what is left allows
+    // passes of up to MAXQ moments, each the multiple of 8 that covers what is left
     for (int s0 = 0; s0 <= L;) {
         const int rem = L + 1 - s0;
-        if (rem > 16) { lmom_pass<32>(P, I, B, cs, lpart, s0, lane, bid); s0 += 32; }
-        else if (rem > 8) { lmom_pass<16>(P, I, B, cs, lpart, s0, lane, bid); s0 += 16; }
-        else { lmom_pass<8>(P, I, B, cs, lpart, s0, lane, bid); s0 += 8; }
+        const int nq = rem >= MAXQ ? MAXQ : (rem + 7) / 8 * 8;
+        if (nq == 8) lmom_pass<8>(P, I, B, cs, lpart, s0, lane, bid);
+        else if (nq == 16) lmom_pass<16>(P, I, B, cs, lpart, s0, lane, bid);
+        else if (nq == 24) lmom_pass<24>(P, I, B, cs, lpart, s0, lane, bid);
+        else if (nq == 32) lmom_pass<32>(P, I, B, cs, lpart, s0, lane, bid);
+        else if constexpr (MAXQ > 32) {
+            if (nq == 40) lmom_pass<40>(P, I, B, cs, lpart, s0, lane, bid);
+            else if (nq == 48) lmom_pass<48>(P, I, B, cs, lpart, s0, lane, bid);
+            else if (nq == 56) lmom_pass<56>(P, I, B, cs, lpart, s0, lane, bid);
+            else lmom_pass<64>(P, I, B, cs, lpart, s0, lane, bid);
+        }
+        s0 += nq;
     }
 }
 
-__global__ __launch_bounds__(64) void k_lmom(PlanDev P) { lmom_body(P, blockIdx.x); }
+// The instance for an order's local rank L.
+constexpr int lmom_width(int L) { return L + 1 <= 32 ? 32 : 64; }
 
+template <int MAXQ>
+__global__ __launch_bounds__(64) void k_lmom(PlanDev P) { lmom_body<MAXQ>(P, blockIdx.x); }
+
+template <int MAXQ>
 __global__ __launch_bounds__(64) void k_lmom_many(const PlanDev* __restrict__ plans,
                                                   const WorkSeg* __restrict__ segs, int nseg)
 {
     const WorkSeg w = find_seg(segs, nseg);
-    lmom_body(plan_of(plans, w.t), w.g0);
+    lmom_body<MAXQ>(plan_of(plans, w.t), w.g0);
 }
 
 // Sum of a local block's item partials, in item order.
@@ -1855,7 +1900,8 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
                        io.scale_by_points ? 1 : 0);
     mark(marks, 1, s);
     if (S.n_litems > 0) {
-        hipLaunchKernelGGL(k_lmom, dim3(S.n_litems), dim3(64), 0, s, P);
+        if (lmom_width(P.L) == 32) hipLaunchKernelGGL(k_lmom<32>, dim3(S.n_litems), dim3(64), 0, s, P);
+        else hipLaunchKernelGGL(k_lmom<64>, dim3(S.n_litems), dim3(64), 0, s, P);
         hipLaunchKernelGGL(k_lmom_reduce, dim3(cdiv64((int64_t)S.n_l * (P.L + 1), 256)), dim3(256), 0, s, P);
     }
     mark(marks, 2, s);
@@ -1945,9 +1991,10 @@ void build_batch_schedule(const BatchTransform* tr, int count, const int* order,
     add(kGather, 0, 0, 256, [&](const BatchTransform& T, size_t&) -> int64_t {
         return live(*T.P) ? cdiv64(T.P->n, 256) : 0;
     });
-    add(kLmom, 0, 0, 64, [&](const BatchTransform& T, size_t&) -> int64_t {
-        return live(*T.P) ? T.S->n_litems : 0;
-    });
+    for (const int width : {32, 64})
+        add(kLmom, width, 0, 64, [&](const BatchTransform& T, size_t&) -> int64_t {
+            return live(*T.P) && lmom_width(T.P->L) == width ? T.S->n_litems : 0;
+        });
     add(kLmomReduce, 0, 0, 256, [&](const BatchTransform& T, size_t&) -> int64_t {
         return live(*T.P) && T.S->n_litems > 0 ? cdiv64((int64_t)T.S->n_l * (T.P->L + 1), 256) : 0;
     });
@@ -2062,7 +2109,10 @@ hipError_t launch_execute_many(const BatchSchedule& S, const void* table_dev, vo
         switch (L.kind) {
         case kZeroOut: hipLaunchKernelGGL(k_zero_output_many, grid, block, 0, s, plans, sg, L.nseg, gout); break;
         case kGather: hipLaunchKernelGGL(k_gather_many, grid, block, 0, s, plans, sg, L.nseg, cin); break;
-        case kLmom: hipLaunchKernelGGL(k_lmom_many, grid, block, 0, s, plans, sg, L.nseg); break;
+        case kLmom:
+            if (L.variant == 32) hipLaunchKernelGGL(k_lmom_many<32>, grid, block, 0, s, plans, sg, L.nseg);
+            else hipLaunchKernelGGL(k_lmom_many<64>, grid, block, 0, s, plans, sg, L.nseg);
+            break;
         case kLmomReduce: hipLaunchKernelGGL(k_lmom_reduce_many, grid, block, 0, s, plans, sg, L.nseg); break;
         case kSpreadMfma:
             dispatch_channels(L.variant, [&](auto k) {
