@@ -1551,6 +1551,40 @@ __device__ __forceinline__ double besselj_direct(const PlanDev& P, double xh, do
     return besselj_full(P, xh, xl);
 }
 
+// Two entries' table values at once (both arguments on the table): the two
+// panels' loads issue together and the two Horner chains interleave.
+__device__ __forceinline__ bool on_jtab(const PlanDev& P, double xh)
+{
+    const double t = (xh - P.jtab_x0) * (1.0 / kJtabWidth);
+    return t >= 0.0 && t < (double)P.jtab_np;
+}
+
+__device__ __forceinline__ void besselj_table2(const PlanDev& P, double xh1, double xl1, double xh2, double xl2,
+                                               double& j1, double& j2)
+{
+    const int p1 = (int)((xh1 - P.jtab_x0) * (1.0 / kJtabWidth));
+    const int p2 = (int)((xh2 - P.jtab_x0) * (1.0 / kJtabWidth));
+    const double u1 = ((xh1 - __builtin_fma((double)p1, kJtabWidth, P.jtab_x0)) - 1.0) + xl1;
+    const double u2 = ((xh2 - __builtin_fma((double)p2, kJtabWidth, P.jtab_x0)) - 1.0) + xl2;
+    const double2* __restrict__ c1 = (const double2*)(P.jtab + (int64_t)p1 * kJtabCoef);
+    const double2* __restrict__ c2 = (const double2*)(P.jtab + (int64_t)p2 * kJtabCoef);
+    double2 a[kJtabCoef / 2], b[kJtabCoef / 2];
+    #pragma unroll
+    for (int q = 0; q < kJtabCoef / 2; ++q) { a[q] = c1[q]; b[q] = c2[q]; }
+    double v = a[kJtabCoef / 2 - 1].y, w = b[kJtabCoef / 2 - 1].y;
+    #pragma unroll
+    for (int q = kJtabCoef / 2 - 1; q >= 0; --q) {
+        if (q < kJtabCoef / 2 - 1) {
+            v = __builtin_fma(v, u1, a[q].y);
+            w = __builtin_fma(w, u2, b[q].y);
+        }
+        v = __builtin_fma(v, u1, a[q].x);
+        w = __builtin_fma(w, u2, b[q].x);
+    }
+    j1 = v;
+    j2 = w;
+}
+
 // Direct blocks (entry by entry, J_nu to full precision).  One workgroup of
 // kDirectThreads lanes per block: each row of the block is given G lanes (G a
 // power of two up to 64, as many as fit), the lanes of a row sum strided
@@ -1575,9 +1609,22 @@ __device__ __forceinline__ void direct_body(const PlanDev& P, int bid)
         double acc = 0.0;
         if (i < mb) {
             double om = P.ws[D.j0 + i];
-            for (int k = gl; k < nb; k += G) {
-                dd x = two_prod(om, P.rs[D.k0 + k]);
-                acc = __builtin_fma(cs[D.k0 + k], besselj_direct(P, x.hi, x.lo), acc);
+            // two entries per step (the lane's next two, in order): when both
+            // arguments are on the table their evaluations interleave
+            for (int k = gl; k < nb; k += 2 * G) {
+                const bool two = k + G < nb;
+                const int k2 = two ? k + G : k;
+                const dd x1 = two_prod(om, P.rs[D.k0 + k]), x2 = two_prod(om, P.rs[D.k0 + k2]);
+                const double c1 = cs[D.k0 + k], c2 = two ? cs[D.k0 + k2] : 0.0;
+                double j1, j2;
+                if (on_jtab(P, x1.hi) && on_jtab(P, x2.hi)) {
+                    besselj_table2(P, x1.hi, x1.lo, x2.hi, x2.lo, j1, j2);
+                } else {
+                    j1 = besselj_direct(P, x1.hi, x1.lo);
+                    j2 = two ? besselj_direct(P, x2.hi, x2.lo) : 0.0;
+                }
+                acc = __builtin_fma(c1, j1, acc);
+                acc = __builtin_fma(c2, j2, acc);
             }
         }
         for (int o = G >> 1; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
