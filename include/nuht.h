@@ -344,12 +344,17 @@ int nuht_batch_destroy(nuht_batch_t batch);
  * 2 ES spreading, 3 grid assembly, 4 FFTs, 5 direct blocks, 6 asymptotic rows,
  * 7 local rows and output).
  * nuht_profile(plan, 0)
- * stops it.  nuht_profile_read synchronises on the last recorded event and
- * writes the per-stage totals in milliseconds to stage_ms[NUHT_NSTAGES] and
- * the number of profiled calls to *calls (may be NULL).
+ * stops it.  nuht_profile_stages(plan, mask) does the same for the stages
+ * whose bits are set in mask (bit i: stage i; 0 stops), recording events only
+ * at their boundaries, so that timing a few stages disturbs the execution
+ * less; NUHT_EINVAL for bits beyond NUHT_NSTAGES.  nuht_profile_read
+ * synchronises on the last recorded event and writes the per-stage totals in
+ * milliseconds to stage_ms[NUHT_NSTAGES] (0 for stages not timed) and the
+ * number of profiled calls to *calls (may be NULL).
  */
 #define NUHT_NSTAGES 8
 int nuht_profile(nuht_plan_t plan, int enable);
+int nuht_profile_stages(nuht_plan_t plan, uint32_t mask);
 int nuht_profile_read(nuht_plan_t plan, double *stage_ms, int64_t *calls);
 
 /* nuht_destroy -- free the plan and its device memory (NULL is allowed). */

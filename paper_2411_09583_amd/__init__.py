@@ -62,7 +62,8 @@ class NuhtInfo(ctypes.Structure):
 EXPORTS = ("nuht_plan", "nuht_plan_half", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_gradient_noalloc",
            "nuht_plan_set_order",
            "nuht_plan_info", "nuht_plan_order", "nuht_tune", "nuht_plan_many", "nuht_execute_many", "nuht_batch_info",
-           "nuht_batch_destroy", "nuht_destroy", "nuht_strerror", "nuht_direct", "nuht_profile", "nuht_profile_read",
+           "nuht_batch_destroy", "nuht_destroy", "nuht_strerror", "nuht_direct", "nuht_profile",
+           "nuht_profile_stages", "nuht_profile_read",
            "nuht_fb_plan", "nuht_fb_analysis", "nuht_fb_synthesis", "nuht_fb_helmholtz", "nuht_fb_destroy")
 
 STAGES = ("gather", "local_moments", "spread", "grid_assembly", "fft", "direct", "rows_asymptotic", "rows_local")
@@ -101,6 +102,7 @@ def load_library():
     lib.nuht_strerror.restype = ctypes.c_char_p
     lib.nuht_direct.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int64, vp, vp, ctypes.c_int64, vp, vp, vp]
     lib.nuht_profile.argtypes = [vp, ctypes.c_int]
+    lib.nuht_profile_stages.argtypes = [vp, ctypes.c_uint32]
     lib.nuht_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.nuht_fb_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int64, vp, vp, ctypes.c_int64,
                                  ctypes.c_int64, vp, ctypes.c_double, ctypes.c_int32, vp]
@@ -111,7 +113,8 @@ def load_library():
     for name in ("nuht_plan", "nuht_plan_half", "nuht_execute", "nuht_adjoint", "nuht_gradient", "nuht_gradient_noalloc",
                  "nuht_plan_set_order", "nuht_plan_info", "nuht_plan_order",
                  "nuht_tune", "nuht_plan_many", "nuht_execute_many", "nuht_batch_info", "nuht_batch_destroy",
-                 "nuht_destroy", "nuht_direct", "nuht_profile", "nuht_profile_read", "nuht_fb_plan",
+                 "nuht_destroy", "nuht_direct", "nuht_profile", "nuht_profile_stages", "nuht_profile_read",
+                 "nuht_fb_plan",
                  "nuht_fb_analysis", "nuht_fb_synthesis", "nuht_fb_helmholtz", "nuht_fb_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -252,9 +255,14 @@ class Plan:
         _check(load_library().nuht_plan_order(self._h, _ptr(rs), _ptr(pr), _ptr(ws), _ptr(pw), _stream()))
         return rs, pr, ws, pw
 
-    def profile(self, enable: bool = True):
-        """Start (clearing earlier records) or stop per-stage event timing."""
-        _check(load_library().nuht_profile(self._h, 1 if enable else 0))
+    def profile(self, enable: bool = True, stages=None):
+        """Start (clearing earlier records) or stop per-stage event timing;
+        stages: names from STAGES to time only those (all by default)."""
+        if stages is None:
+            _check(load_library().nuht_profile(self._h, 1 if enable else 0))
+        else:
+            mask = sum(1 << STAGES.index(s) for s in stages) if enable else 0
+            _check(load_library().nuht_profile_stages(self._h, mask))
 
     def profile_read(self):
         """Per-stage totals in ms over the profiled calls, and the call count."""

@@ -1848,7 +1848,7 @@ static void dispatch_channels(int nch, F&& f)
 
 static inline void mark(hipEvent_t* marks, int i, hipStream_t s)
 {
-    if (marks) (void)hipEventRecord(marks[i], s);
+    if (marks && marks[i]) (void)hipEventRecord(marks[i], s);
 }
 
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s)

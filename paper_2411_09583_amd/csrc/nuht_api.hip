@@ -989,15 +989,18 @@ struct nuht_plan_s {
     uint64_t clock = 0;
     DevBuf b_grad;               // gradient temporaries (two of n, two of m)
     double* grad_t[4] = {nullptr, nullptr, nullptr, nullptr};
-    // stage timing (diagnostics): kStages + 1 events per profiled call
+    // stage timing (diagnostics): kStages + 1 event slots per profiled call,
+    // the boundaries of the stages in prof_mask filled
     bool prof = false;
+    uint32_t prof_mask = 0;
     std::vector<hipEvent_t> prof_events;
     int64_t prof_calls = 0;
 };
 
 static void prof_clear(nuht_plan_t p)
 {
-    for (hipEvent_t e : p->prof_events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->prof_events)
+        if (e) (void)hipEventDestroy(e);
     p->prof_events.clear();
     p->prof_calls = 0;
 }
@@ -1008,8 +1011,13 @@ static hipEvent_t* prof_marks(nuht_plan_t p)
     if (!p->prof) return nullptr;
     size_t base = p->prof_events.size();
     for (int i = 0; i <= kStages; ++i) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+        hipEvent_t e = nullptr;
+        const bool used = (i < kStages && ((p->prof_mask >> i) & 1)) || (i > 0 && ((p->prof_mask >> (i - 1)) & 1));
+        if (used && hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            p->prof_events.resize(base);
+            return nullptr;
+        }
         p->prof_events.push_back(e);
     }
     p->prof_calls++;
@@ -2348,12 +2356,19 @@ int nuht_plan_info(nuht_plan_t p, nuht_info* info)
     return NUHT_OK;
 }
 
-int nuht_profile(nuht_plan_t p, int enable)
+int nuht_profile_stages(nuht_plan_t p, uint32_t mask)
 {
     if (!p) return NUHT_EINVAL;
+    if (mask >> kStages) return NUHT_EINVAL;
     prof_clear(p);
-    p->prof = enable != 0;
+    p->prof = mask != 0;
+    p->prof_mask = mask;
     return NUHT_OK;
+}
+
+int nuht_profile(nuht_plan_t p, int enable)
+{
+    return nuht_profile_stages(p, enable ? (1u << kStages) - 1 : 0u);
 }
 
 int nuht_profile_read(nuht_plan_t p, double* stage_ms, int64_t* calls)
@@ -2361,10 +2376,15 @@ int nuht_profile_read(nuht_plan_t p, double* stage_ms, int64_t* calls)
     if (!p || !stage_ms) return NUHT_EINVAL;
     for (int i = 0; i < kStages; ++i) stage_ms[i] = 0.0;
     int64_t nc = (int64_t)p->prof_events.size() / (kStages + 1);
-    if (nc > 0) HIP_TRY(hipEventSynchronize(p->prof_events.back()));
+    if (nc > 0) {   // the last call's last recorded event
+        hipEvent_t* e = p->prof_events.data() + (nc - 1) * (kStages + 1);
+        for (int i = kStages; i >= 0; --i)
+            if (e[i]) { HIP_TRY(hipEventSynchronize(e[i])); break; }
+    }
     for (int64_t c = 0; c < nc; ++c) {
         hipEvent_t* e = p->prof_events.data() + c * (kStages + 1);
         for (int i = 0; i < kStages; ++i) {
+            if (!e[i] || !e[i + 1]) continue;
             float ms = 0.0f;
             HIP_TRY(hipEventElapsedTime(&ms, e[i], e[i + 1]));
             stage_ms[i] += ms;

@@ -69,7 +69,7 @@ struct FftClass {
 };
 
 // Execution stages, timed between consecutive events of `marks` (kStages + 1
-// events, or null).
+// events, or null; a null entry records nothing).
 constexpr int kStages = 8;   // gather, local moments, spread, grid assembly, FFT, direct, asymptotic rows, local rows
 // Input and output of one transform.  When the slots are set, the kernels
 // read the input and output pointers from those device locations at run time

@@ -74,6 +74,9 @@ def test_new_entry_points_reject_invalid_arguments_without_gpu(lib):
     assert lib.nuht_batch_info(None, 0, None) == -1
     assert lib.nuht_batch_destroy(None) == 0
     assert lib.nuht_plan_set_order(None, 1, None) == -1
+    assert lib.nuht_plan_order(None, None, None, None, None, None) == -1
+    assert lib.nuht_profile_stages(None, 1) == -1
+    assert lib.nuht_profile(None, 1) == -1
     # batch arguments are validated before anything is created
     many = lib.nuht_plan_many
     one = lambda t, v: (t * 1)(v)
