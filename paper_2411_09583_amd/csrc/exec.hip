@@ -501,7 +501,9 @@ __global__ __launch_bounds__(256) void k_spread_many(const PlanDev* __restrict__
 
 // ---------------------------------------------------------------------------
 // Spreading on the matrix cores (FP64), for items whose points reach the grid
-// from at most kSpreadAnchors first cells (dense items: many points per cell).
+// from at most kSpreadAnchors first cells (dense items: many points per cell)
+// and, in a launch of their own with room for more cell sums, from at most
+// kSpreadAnchorsMed (medium items: tens of points per cell).
 // With the points of an item split by their first cell a (anchor), the
 // item's partial subgrid is
 //   G[a + t][col] = sum over anchors a, over points k with anchor a, of
@@ -528,12 +530,12 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 template <int NCH>
 constexpr int kSpreadTiles = NCH <= 8 ? 1 : 2;
 
-template <int NCH>
+template <int NCH, int ANCH = kSpreadAnchors>
 struct SpreadMfma {
     static constexpr int NCT = kSpreadTiles<NCH>;
     static constexpr int NC = 16 * NCT;            // real columns of the tiles (re, im of 8 NCT channels)
     static constexpr int VS = 2 * NCH + 1;         // LDS stride of a point's 2 NCH columns (odd: conflict-free writes)
-    static constexpr int GC = kSpreadAnchors + 15; // cells an item's anchor tiles reach
+    static constexpr int GC = ANCH + 15;           // cells an item's anchor tiles reach
     // points per step: 64, or 32 with two column tiles, so that the wider
     // point records still let three workgroups share a compute unit's LDS
     static constexpr int WPTS = NCT > 1 ? 32 : 64;
@@ -553,16 +555,18 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Points 0 .. np-1 of the step into the tile of anchor a, two groups of four
-// points per iteration (two independent kernel evaluations).  Lanes past np
-// take B = 0; with MASK, points of other anchors take A = 0.
+// Points g_lo .. g_hi-1 of the step (g_lo a multiple of 8) into the tile of
+// anchor a, two groups of four points per iteration (two independent kernel
+// evaluations).  Lanes past np take B = 0; with MASK, points of other anchors
+// take A = 0.
 template <int NCH, bool MASK>
 __device__ __forceinline__ void spread_mfma_run(v4d (&acc)[kSpreadTiles<NCH>], const double* s_v,
                                                 const double* s_s, const int32_t* s_d,
-                                                const double (&cf)[kEsDeg + 1], int np, int col, int kq, int a)
+                                                const double (&cf)[kEsDeg + 1], int g_lo, int g_hi, int np,
+                                                int col, int kq, int a)
 {
     constexpr int NCT = SpreadMfma<NCH>::NCT, VS = SpreadMfma<NCH>::VS;
-    for (int g = 0; g < np; g += 8) {
+    for (int g = g_lo; g < g_hi; g += 8) {
         const int i0 = g + kq, i1 = g + 4 + kq;
         const bool v0 = i0 < np, v1 = i1 < np;
         const int j0 = v0 ? i0 : g, j1 = v1 ? i1 : g;
@@ -607,15 +611,15 @@ __device__ __forceinline__ void spread_mfma_flush(v4d (&acc)[kSpreadTiles<NCH>],
     wave_sync();   // the next anchor's cells overlap this one's in other lanes
 }
 
-template <int NCH>
-__device__ __forceinline__ void spread_mfma_item(const PlanDev& P, int bid)
+// Item alist[slot] of the plan, with LDS for anchors up to ANCH.
+template <int NCH, int ANCH>
+__device__ __forceinline__ void spread_mfma_item(const PlanDev& P, int slot, double4* spread_lds)
 {
     const double* __restrict__ cs = P.cs;
     const double* __restrict__ es_poly = P.es_poly;
     double2* __restrict__ part = P.part;
-    using SM = SpreadMfma<NCH>;
+    using SM = SpreadMfma<NCH, ANCH>;
     constexpr int NCT = SM::NCT, NC = SM::NC, VS = SM::VS, WPTS = SM::WPTS, GC = SM::GC;
-    extern __shared__ double4 spread_lds[];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     char* base = reinterpret_cast<char*>(spread_lds) + wave * SM::wave_bytes;
@@ -623,7 +627,7 @@ __device__ __forceinline__ void spread_mfma_item(const PlanDev& P, int bid)
     double* s_s = s_v + WPTS * VS;
     int32_t* s_d = reinterpret_cast<int32_t*>(s_s + WPTS);
     double* s_g = reinterpret_cast<double*>(base + SM::wave_bytes - SM::fold_bytes);
-    const Item I = P.aitems[P.alist[bid]];
+    const Item I = P.aitems[P.alist[slot]];
     const ABlock B = P.ab[I.blk];
     const int col = lane & 15, kq = lane >> 4;
     const int w = P.w;
@@ -674,15 +678,19 @@ __device__ __forceinline__ void spread_mfma_item(const PlanDev& P, int bid)
                 if (cur >= 0) spread_mfma_flush<NCH>(acc, s_g, col, kq, cur);
                 cur = a_lo;
             }
-            spread_mfma_run<NCH, false>(acc, s_v, s_s, s_d, cf, np, col, kq, cur);
+            spread_mfma_run<NCH, false>(acc, s_v, s_s, s_d, cf, 0, np, np, col, kq, cur);
         } else {
+            // the points of anchor a are consecutive lanes (points are sorted):
+            // only the groups of eight that hold them are multiplied
             for (int a = a_lo; a <= a_hi; ++a) {
-                if (__ballot(lane < np && dm == a) == 0) continue;
+                const uint64_t mine = __ballot(lane < np && dm == a);
+                if (mine == 0) continue;
                 if (a != cur) {
                     if (cur >= 0) spread_mfma_flush<NCH>(acc, s_g, col, kq, cur);
                     cur = a;
                 }
-                spread_mfma_run<NCH, true>(acc, s_v, s_s, s_d, cf, np, col, kq, a);
+                const int first = __builtin_ctzll(mine), last = 63 - __builtin_clzll(mine);
+                spread_mfma_run<NCH, true>(acc, s_v, s_s, s_d, cf, first & ~7, last + 1, np, col, kq, a);
             }
         }
     }
@@ -701,20 +709,26 @@ __device__ __forceinline__ void spread_mfma_item(const PlanDev& P, int bid)
     }
 }
 
-// Up to 8 channels (one column tile) the kernel fits four waves per SIMD,
-// with two tiles three.
-template <int NCH>
+// Up to 8 channels (one column tile) the dense kernel fits four waves per
+// SIMD, with two tiles three.  ANCH = kSpreadAnchors: the dense items, from
+// slot 0 of the item list; kSpreadAnchorsMed: the medium ones, after them.
+template <int NCH, int ANCH>
 __global__ __launch_bounds__(256) void k_spread_mfma(PlanDev P)
 {
-    spread_mfma_item<NCH>(P, blockIdx.x);
+    __shared__ double4 lds[SpreadMfma<NCH, ANCH>::lds_bytes / sizeof(double4)];
+    const int first = ANCH == kSpreadAnchors ? 0 : P.n_adense;
+    spread_mfma_item<NCH, ANCH>(P, first + blockIdx.x, lds);
 }
 
-template <int NCH>
+template <int NCH, int ANCH>
 __global__ __launch_bounds__(256) void k_spread_mfma_many(const PlanDev* __restrict__ plans,
                                                           const WorkSeg* __restrict__ segs, int nseg)
 {
+    __shared__ double4 lds[SpreadMfma<NCH, ANCH>::lds_bytes / sizeof(double4)];
     const WorkSeg w = find_seg(segs, nseg);
-    spread_mfma_item<NCH>(plan_of(plans, w.t), w.g0);
+    const PlanDev& P = plan_of(plans, w.t);
+    const int first = ANCH == kSpreadAnchors ? 0 : P.n_adense;
+    spread_mfma_item<NCH, ANCH>(P, first + w.g0, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1775,10 +1789,12 @@ static inline int cdiv64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); 
 template <int NCH>
 static void launch_spread(const PlanDev& P, const Summary& S, hipStream_t s)
 {
-    const int32_t n_dense = S.n_adense, n_rest = S.n_aitems - S.n_adense;
+    const int32_t n_dense = S.n_adense, n_med = S.n_amed, n_rest = S.n_aitems - S.n_adense - S.n_amed;
     if constexpr (NCH <= 16) {
         if (n_dense > 0)
-            hipLaunchKernelGGL((k_spread_mfma<NCH>), dim3(n_dense), dim3(256), SpreadMfma<NCH>::lds_bytes, s, P);
+            hipLaunchKernelGGL((k_spread_mfma<NCH, kSpreadAnchors>), dim3(n_dense), dim3(256), 0, s, P);
+        if (n_med > 0)
+            hipLaunchKernelGGL((k_spread_mfma<NCH, kSpreadAnchorsMed>), dim3(n_med), dim3(256), 0, s, P);
     }
     if (n_rest > 0) {
         if (P.fp32)
@@ -2002,7 +2018,7 @@ void small_fft_table(PlanDev& P, const FftClass* cls, int ncls)
 // its channel count (spreading, grid rows) or local-row mode.
 // ---------------------------------------------------------------------------
 enum BatchKind : int32_t {
-    kZeroOut, kGather, kLmom, kLmomReduce, kSpreadMfma, kSpreadVec, kSpreadReduce, kFftSmall,
+    kZeroOut, kGather, kLmom, kLmomReduce, kSpreadMfma, kSpreadMfmaMed, kSpreadVec, kSpreadReduce, kFftSmall,
     kFftPass0, kFftPass1, kFftPass2, kZeroGd, kDirect, kRowsAsy, kRowsLocal
 };
 
@@ -2055,16 +2071,18 @@ void build_batch_schedule(const BatchTransform* tr, int count, const int* order,
     for (const auto& v : variants) {
         const int nch = v.first, fp32 = v.second;
         auto same = [&](const PlanDev& P) { return live(P) && P.nch == nch && P.fp32 == fp32; };
-        if (nch <= 16)
-            add(kSpreadMfma, nch, fp32, 256, [&](const BatchTransform& T, size_t& lds) -> int64_t {
-                if (!same(*T.P) || T.S->n_adense <= 0) return 0;
-                dispatch_channels(nch, [&](auto k) { lds = SpreadMfma<decltype(k)::value>::lds_bytes; });
-                return T.S->n_adense;
+        if (nch <= 16) {   // static LDS: no launch bytes
+            add(kSpreadMfma, nch, fp32, 256, [&](const BatchTransform& T, size_t&) -> int64_t {
+                return same(*T.P) ? T.S->n_adense : 0;
             });
+            add(kSpreadMfmaMed, nch, fp32, 256, [&](const BatchTransform& T, size_t&) -> int64_t {
+                return same(*T.P) ? T.S->n_amed : 0;
+            });
+        }
         add(kSpreadVec, nch, fp32, 256, [&](const BatchTransform& T, size_t& lds) -> int64_t {
             if (!same(*T.P)) return 0;
             lds = fp32 ? spread_lds_bytes<float>(T.P->w) : spread_lds_bytes<double>(T.P->w);
-            return T.S->n_aitems - T.S->n_adense;
+            return T.S->n_aitems - T.S->n_adense - T.S->n_amed;
         });
     }
     for (int fp32 = 0; fp32 <= 1; ++fp32)
@@ -2162,10 +2180,17 @@ hipError_t launch_execute_many(const BatchSchedule& S, const void* table_dev, vo
             break;
         case kLmomReduce: hipLaunchKernelGGL(k_lmom_reduce_many, grid, block, 0, s, plans, sg, L.nseg); break;
         case kSpreadMfma:
+        case kSpreadMfmaMed:
             dispatch_channels(L.variant, [&](auto k) {
                 constexpr int NCH = decltype(k)::value;
-                if constexpr (NCH <= 16)
-                    hipLaunchKernelGGL((k_spread_mfma_many<NCH>), grid, block, L.lds, s, plans, sg, L.nseg);
+                if constexpr (NCH <= 16) {
+                    if (L.kind == kSpreadMfma)
+                        hipLaunchKernelGGL((k_spread_mfma_many<NCH, kSpreadAnchors>), grid, block, 0, s, plans, sg,
+                                           L.nseg);
+                    else
+                        hipLaunchKernelGGL((k_spread_mfma_many<NCH, kSpreadAnchorsMed>), grid, block, 0, s, plans,
+                                           sg, L.nseg);
+                }
             });
             break;
         case kSpreadVec:

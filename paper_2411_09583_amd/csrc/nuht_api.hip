@@ -1251,7 +1251,7 @@ static int part_finish(PendingPart& pp, const HostStage* h, bool* again)
     pp.tmp.bytes = 0;
     Pt.A = pp.A;
     P.n_nodes = S.n_nodes; P.n_l = S.n_l; P.n_a = S.n_a; P.n_d = S.n_d;
-    P.n_litems = S.n_litems; P.n_aitems = S.n_aitems; P.n_adense = S.n_adense;
+    P.n_litems = S.n_litems; P.n_aitems = S.n_aitems; P.n_adense = S.n_adense; P.n_amed = S.n_amed;
 
     // execution buffers
     ExecBuffers& B = Pt.B;
@@ -2350,7 +2350,7 @@ int nuht_plan_info(nuht_plan_t p, nuht_info* info)
     info->dft_max = p->opts.dft_max == 0 ? 48 : p->opts.dft_max;
     info->spread_chunk = P.spread_chunk;
     info->spread_items = S.n_aitems;
-    info->dense_items = S.n_adense;
+    info->dense_items = S.n_adense + S.n_amed;
     info->split_candidates = p->opts.split_candidates == -1 ? -1
                              : (p->opts.split_candidates > 1 ? p->opts.split_candidates : 16);
     return NUHT_OK;

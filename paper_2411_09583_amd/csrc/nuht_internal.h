@@ -31,7 +31,8 @@ inline int64_t default_min_size(int64_t n, int64_t m) {
 }
 constexpr int kMaxEsWidth = 18;        // largest ES kernel width
 constexpr int kEsDeg = 13;             // degree of the per-cell polynomial pieces of the ES kernel
-constexpr int kSpreadAnchors = 6;      // first cells (anchors) one matrix-core spreading item may hold
+constexpr int kSpreadAnchors = 6;      // first cells (anchors) of a dense matrix-core spreading item
+constexpr int kSpreadAnchorsMed = 40;  // first cells of a medium one (its own launch, larger LDS cell sums)
 constexpr int kMaxLevels = 4096;       // subdivision depth limit
 constexpr int kHalfDeg = 20;           // degree of the half-integer local coefficients on a panel
 constexpr double kHalfWidth = 4.0;     // panel width (in omega R) of those coefficients
@@ -85,8 +86,9 @@ struct Item {
     int32_t blk;
     int32_t ka, kb;       // columns ka .. kb-1
     int32_t sub_lo, sub_n;  // spread items: subgrid cells sub_lo .. sub_lo + sub_n - 1
-    int32_t dense;        // spread items: 1 if spread on the matrix cores (its points' first cells
-                          // lie in sub_lo .. sub_lo + kSpreadAnchors - 1), else 0
+    int32_t dense;        // spread items on the matrix cores: 1 (dense) if its points' first cells
+                          // lie in sub_lo .. sub_lo + kSpreadAnchors - 1, 2 (medium) if within
+                          // kSpreadAnchorsMed of sub_lo; else 0 (vector spreading)
     int64_t off;          // spread items: partial-subgrid offset (complex elements)
 };
 
@@ -96,7 +98,7 @@ struct Summary {
     int32_t levels, overflow;
     int32_t n_litems, n_aitems;
     int32_t n_fft, max_nch;
-    int32_t n_adense, pad;  // spread items on the matrix cores (the first n_adense of the item list)
+    int32_t n_adense, n_amed;  // dense and medium spread items (the first n_adense, then n_amed, of the item list)
     int64_t l_row, l_col, a_row, a_col, d_ent;
     int64_t grid_cells;     // sum N1 (all asymptotic blocks)
     int64_t dft_cells;      // sum N1 over direct-sum-path blocks
@@ -157,7 +159,7 @@ struct PlanDev {
                                      // monomial coefficients in u in [-1, 1] of its Chebyshev interpolant
     double jtab_x0;
     int32_t jtab_np, pad2;
-    int32_t n_nodes, n_l, n_a, n_d, n_litems, n_aitems, n_adense, pad1;
+    int32_t n_nodes, n_l, n_a, n_d, n_litems, n_aitems, n_adense, n_amed;
     // execution buffers of the partition
     double* cs;                      // weights gathered into sorted point order (n)
     double* lpart;                   // local-moment partial sums (items x (L + 1))

@@ -1525,8 +1525,10 @@ __global__ void k_items(PlanDev P, Arena A, Summary* __restrict__ sum, int32_t* 
             Item I;
             I.blk = lo; I.ka = ka; I.kb = kb + 1; I.sub_lo = s0; I.sub_n = s1 - s0 + 1; I.off = 0;
             // first cells of the points lie in s0 .. s1 - w + 1 (one cell of
-            // margin each side for rounding): dense if at most kSpreadAnchors
-            I.dense = (P.mfma && I.sub_n - w + 1 <= kSpreadAnchors) ? 1 : 0;
+            // margin each side for rounding): dense if at most kSpreadAnchors,
+            // medium if at most kSpreadAnchorsMed
+            const int32_t anchors = I.sub_n - w + 1;
+            I.dense = !P.mfma ? 0 : anchors <= kSpreadAnchors ? 1 : anchors <= kSpreadAnchorsMed ? 2 : 0;
             A.aitems[ia] = I;
             a_cells[ia] = I.sub_n;
         }
@@ -1534,45 +1536,65 @@ __global__ void k_items(PlanDev P, Arena A, Summary* __restrict__ sum, int32_t* 
 }
 
 // Partial-subgrid offsets of the asymptotic items, and the spreading order:
-// dense items at alist[0 ..) and the others at alist[n_ai - 1], alist[n_ai - 2],
-// ..., each list in item order (one 1024-thread block).
-__global__ __launch_bounds__(kPlanScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_item_scan(PlanDev P, Arena A, Summary* __restrict__ sum,
-                                                    const int32_t* __restrict__ a_cells)
+// dense items at alist[0 ..), medium ones after them, and the others at
+// alist[n_ai - 1], alist[n_ai - 2], ..., each list in item order (one
+// workgroup).
+__global__ __launch_bounds__(kPlanScanThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_item_scan(
+    PlanDev P, Arena A, Summary* __restrict__ sum, const int32_t* __restrict__ a_cells)
 {
-    __shared__ int64_t wsum[2][16];
+    __shared__ int64_t wsum[3][16];
+    __shared__ int32_t n_dense_total;
     if (sum->overflow) return;
     const int32_t n_ai = sum->n_aitems;
     const int nch = P.nch;
     constexpr int kVpt = 8;                          // items per thread per pass (2048 per pass)
-    int64_t run = 0, run_dense = 0;
+    // the dense items' total first: the medium ones follow them in the list
+    {
+        int32_t nd = 0;
+        for (int32_t i = threadIdx.x; i < n_ai; i += kPlanScanThreads) nd += A.aitems[i].dense == 1 ? 1 : 0;
+        for (int o = 32; o >= 1; o >>= 1) nd += __shfl_xor(nd, o);
+        if (threadIdx.x == 0) n_dense_total = 0;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) atomicAdd(&n_dense_total, nd);
+        __syncthreads();
+    }
+    const int64_t nd_total = n_dense_total;
+    int64_t run = 0, run_dense = 0, run_med = 0;
     for (int32_t c0 = 0; c0 < n_ai; c0 += kPlanScanThreads * kVpt) {
         const int32_t i0 = c0 + threadIdx.x * kVpt;
-        int64_t v[kVpt][2];
-        bool dense[kVpt];
+        int64_t v[kVpt][3];
+        int cls[kVpt];
         #pragma unroll
         for (int k = 0; k < kVpt; ++k) {
             const bool act = i0 + k < n_ai;
             v[k][0] = act ? (int64_t)a_cells[i0 + k] : 0;
-            dense[k] = act && A.aitems[i0 + k].dense;
-            v[k][1] = dense[k] ? 1 : 0;
+            cls[k] = act ? A.aitems[i0 + k].dense : 0;
+            v[k][1] = cls[k] == 1 ? 1 : 0;
+            v[k][2] = cls[k] == 2 ? 1 : 0;
         }
-        int64_t tot[2];
-        block_scan_vpt<2, kVpt, kPlanScanThreads / 64>(v, tot, wsum);
+        int64_t tot[3];
+        block_scan_vpt<3, kVpt, kPlanScanThreads / 64>(v, tot, wsum);
         #pragma unroll
         for (int k = 0; k < kVpt; ++k) {
             const int32_t i = i0 + k;
             if (i < n_ai) {
                 A.aitems[i].off = (run + v[k][0]) * nch;
-                const int64_t nd_before = run_dense + v[k][1];
-                A.alist[dense[k] ? nd_before : n_ai - 1 - (i - nd_before)] = i;
+                // dense from the front, then medium, the others from the back
+                const int64_t nd_before = run_dense + v[k][1], nm_before = run_med + v[k][2];
+                const int64_t pos = cls[k] == 1 ? nd_before
+                                  : cls[k] == 2 ? nd_total + nm_before
+                                                : n_ai - 1 - (i - nd_before - nm_before);
+                A.alist[pos] = i;
             }
         }
         run += tot[0];
         run_dense += tot[1];
+        run_med += tot[2];
     }
     if (threadIdx.x == 0) {
         sum->part_cells = run;
         sum->n_adense = (int32_t)run_dense;
+        sum->n_amed = (int32_t)run_med;
     }
 }
 
