@@ -507,8 +507,8 @@ def bench_split(torch, nuht, r, w, c, reps=5):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="outputs of the nu=0 transform computed by the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
