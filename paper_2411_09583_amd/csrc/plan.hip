@@ -4,6 +4,8 @@
 #include "nuht_device.h"
 #include "nuht_launch.h"
 
+#include <type_traits>
+
 namespace nuht {
 
 // ---------------------------------------------------------------------------
@@ -376,9 +378,11 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
 // sort above, whose 25 launches dominate planning there):
 // * both segments up to kSsCap keys: k_sort_small, one workgroup per segment
 //   sorting it in LDS (LSD on 8-bit digits over the bits that vary);
-// * both up to kSsMaxLen keys: a splitter sort in five launches --
+// * both up to 2^18 keys: a splitter sort in five launches (64 bucket slots
+//   per array up to 65536 keys, 1024 above) --
 //   1. k_ss_sample: one workgroup per segment sorts a stratified sample of the
-//      keys in LDS (bitonic) and keeps its quantiles, without repeats, as the
+//      keys in LDS (bitonic for 1024 keys, LSD radix for 16384) and keeps its
+//      quantiles, without repeats, as the
 //      splitters u_0 < ... < u_{U-1};
 //   2. k_ss_count: each tile of kSsTile keys counts its keys per bucket (range
 //      bucket 2p: the keys strictly between u_{p-1} and u_p; equality bucket
@@ -391,20 +395,33 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
 //      a bucket beyond the LDS capacity (only when the sample misrepresents
 //      the input) is sorted by the same workgroup through global memory.
 // ---------------------------------------------------------------------------
-constexpr int32_t kSsMaxLen = 1 << 16;   // longest segment the splitter sort takes
 constexpr int kSsBucketMean = 2048;      // target keys per range bucket
-constexpr int kSsMaxSpl = 31;            // splitters per segment at most (kSsMaxLen / kSsBucketMean - 1)
-constexpr int kSsBuckets = 64;           // bucket slots per segment (2 U + 1 <= 63 used)
 constexpr int kSsOversample = 32;        // sample keys per range bucket
-constexpr int kSsSample = 1024;          // sample keys per segment at most
 constexpr int kSsThreads = 512;          // count and scatter workgroups: 8 waves
 constexpr int kSsRounds = 16;            // 64-key rounds per wave
 constexpr int kSsTile = kSsThreads * kSsRounds;
 constexpr int kSsLocalThreads = 256;     // LDS sort workgroups: 4 waves
 constexpr int kSsCap = kSsLocalThreads * kSsRounds;   // longest run sorted in LDS
-static_assert(kSsMaxLen / kSsBucketMean - 1 <= kSsMaxSpl, "splitter table too small");
-static_assert(kSsOversample * (kSsMaxLen / kSsBucketMean) <= kSsSample, "sample buffer too small");
-static_assert(2 * kSsMaxSpl + 1 <= kSsBuckets && kSsBuckets == 64, "bucket table: one lane per bucket");
+
+// The splitter sort with NB bucket slots per segment (2 U + 1 <= NB - 1
+// used): 64 for segments up to 65536 keys, 1024 up to 2^20.
+template <int NB>
+struct SsCfg {
+    static constexpr int kMaxSpl = NB / 2 - 1;                          // splitters per segment at most
+    static constexpr int32_t kMaxLen = (kMaxSpl + 1) * kSsBucketMean;   // longest segment
+    static constexpr int kSample = kSsOversample * (kMaxSpl + 1);       // sample keys per segment at most
+    static constexpr int kBits = NB == 64 ? 6 : 10;                     // bits of a bucket id
+    using Id = typename std::conditional<(NB <= 256), uint8_t, uint16_t>::type;
+    // scratch layout in hist (int32 units): the splitters (2 x kMaxSpl
+    // uint64), their counts, the bucket starts and sizes (2 x NB each), then
+    // the tile-major bucket counts
+    static constexpr int kNsplOff = (4 * kMaxSpl + 63) / 64 * 64;
+    static constexpr int kStartOff = kNsplOff + 64;
+    static constexpr int kTotOff = kStartOff + 2 * NB;
+    static constexpr int kCntOff = kTotOff + 2 * NB;
+};
+static_assert(SsCfg<64>::kMaxLen == 65536 && SsCfg<64>::kSample == 1024, "small splitter sort");
+static_assert(SsCfg<1024>::kMaxLen == (1 << 20) && SsCfg<1024>::kSample == 16384, "large splitter sort");
 
 // Sort key of an input (see k_make_keys); ok is false for a negative, NaN or
 // infinite value, whose key is 0.
@@ -416,22 +433,24 @@ __device__ __forceinline__ uint64_t sort_key(double v, bool& ok)
 
 // Bucket of key k among the U sorted splitters su: 2p + (k == u_p), p the
 // number of splitters below k.
+template <int NB>
 __device__ __forceinline__ int ss_bucket(const uint64_t* su, int U, uint64_t k)
 {
     int p = 0;
     #pragma unroll
-    for (int step = 16; step > 0; step >>= 1)
+    for (int step = (SsCfg<NB>::kMaxSpl + 1) / 2; step > 0; step >>= 1)
         if (p + step <= U && su[p + step - 1] < k) p += step;
     return 2 * p + ((p < U && su[p] == k) ? 1 : 0);
 }
 
-// Lanes of the wave whose bucket b (6 bits) equals the calling lane's, among
-// the lanes with `valid` set.
+// Lanes of the wave whose bucket b (BITS bits) equals the calling lane's,
+// among the lanes with `valid` set.
+template <int BITS>
 __device__ __forceinline__ uint64_t bucket_peers(int b, bool valid)
 {
     uint64_t peers = __ballot(valid);
     #pragma unroll
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < BITS; ++i) {
         uint64_t m = __ballot((b >> i) & 1);
         peers &= ((b >> i) & 1) ? m : ~m;
     }
@@ -621,44 +640,13 @@ __global__ __launch_bounds__(kSsLocalThreads) void k_sort_small(const double* __
     }
 }
 
-__global__ __launch_bounds__(kSsSample) void k_ss_sample(const double* __restrict__ r,
-                                                         const double* __restrict__ w, SortSegs S,
-                                                         uint64_t* __restrict__ spl, int32_t* __restrict__ nspl)
+// The B - 1 quantiles of the sorted sample sk (ns keys), each kept if it
+// differs from the one before, as the segment's splitters (threads t < B - 1
+// of a 1024-thread block; every thread calls it).
+__device__ __forceinline__ void ss_pick_splitters(const uint64_t* sk, int ns, int B, uint64_t* spl_seg,
+                                                  int32_t* nspl_seg, int32_t* wtot)
 {
-    __shared__ uint64_t sk[kSsSample];
-    __shared__ int32_t wtot[kSsSample / 64];
-    const int seg = blockIdx.x;
-    const int64_t n = S.off[seg + 1] - S.off[seg];
-    const double* __restrict__ x = seg ? w : r;
-    const int B = (int)((n + kSsBucketMean - 1) / kSsBucketMean);   // range buckets wanted
-    if (B <= 1) {
-        if (threadIdx.x == 0) nspl[seg] = 0;
-        return;
-    }
-    const int ns = (int)(n < (int64_t)kSsOversample * B ? n : (int64_t)kSsOversample * B);
-    int np2 = 1;
-    while (np2 < ns) np2 <<= 1;
-    const int t = threadIdx.x;
-    {
-        uint64_t k = ~0ull;
-        if (t < ns) {
-            bool ok;
-            k = sort_key(x[ss_sample_pos(t, ns, n)], ok);
-        }
-        sk[t] = k;
-    }
-    __syncthreads();
-    for (int k = 2; k <= np2; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const int l = t ^ j;
-            if (t < np2 && l > t) {
-                const uint64_t a = sk[t], b = sk[l];
-                if ((a > b) == ((t & k) == 0)) { sk[t] = b; sk[l] = a; }
-            }
-            __syncthreads();
-        }
-    // the B - 1 quantiles of the sample, each kept if it differs from the one before
-    const int lane = t & 63, wave = t >> 6;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     uint64_t c = 0;
     bool keep = false;
     if (t < B - 1) {
@@ -671,32 +659,153 @@ __global__ __launch_bounds__(kSsSample) void k_ss_sample(const double* __restric
     __syncthreads();
     int pos = __popcll(kb & lt_mask);
     for (int v = 0; v < wave; ++v) pos += wtot[v];
-    if (keep) spl[seg * kSsMaxSpl + pos] = c;
+    if (keep) spl_seg[pos] = c;
     if (t == 0) {
         int tot = 0;
-        for (int v = 0; v < kSsSample / 64; ++v) tot += wtot[v];
-        nspl[seg] = tot;
+        for (int v = 0; v < 1024 / 64; ++v) tot += wtot[v];
+        *nspl_seg = tot;
     }
 }
 
-// Per tile: the bucket counts (tile-major, kSsBuckets per tile) and
-// errs[tile] (1 if the tile holds a negative, NaN or infinite input).
+// One workgroup of 1024 threads per segment: a stratified sample of the keys
+// sorted in LDS (bitonic for the 1024-key samples of NB = 64; LSD on 8-bit
+// digits over the bits that vary, 16 waves of up to 16 rounds, for the
+// 16384-key samples of NB = 1024), then its quantiles as splitters.
+template <int NB>
+__global__ __launch_bounds__(1024) void k_ss_sample(const double* __restrict__ r, const double* __restrict__ w,
+                                                    SortSegs S, uint64_t* __restrict__ spl,
+                                                    int32_t* __restrict__ nspl)
+{
+    using C = SsCfg<NB>;
+    __shared__ uint64_t sk[C::kSample];
+    __shared__ int32_t wtot[16];
+    const int seg = blockIdx.x;
+    const int64_t n = S.off[seg + 1] - S.off[seg];
+    const double* __restrict__ x = seg ? w : r;
+    const int B = (int)((n + kSsBucketMean - 1) / kSsBucketMean);   // range buckets wanted
+    if (B <= 1) {
+        if (threadIdx.x == 0) nspl[seg] = 0;
+        return;
+    }
+    const int ns = (int)(n < (int64_t)kSsOversample * B ? n : (int64_t)kSsOversample * B);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if constexpr (NB == 64) {
+        int np2 = 1;
+        while (np2 < ns) np2 <<= 1;
+        {
+            uint64_t k = ~0ull;
+            if (t < ns) {
+                bool ok;
+                k = sort_key(x[ss_sample_pos(t, ns, n)], ok);
+            }
+            sk[t] = k;
+        }
+        __syncthreads();
+        for (int k = 2; k <= np2; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const int l = t ^ j;
+                if (t < np2 && l > t) {
+                    const uint64_t a = sk[t], b = sk[l];
+                    if ((a > b) == ((t & k) == 0)) { sk[t] = b; sk[l] = a; }
+                }
+                __syncthreads();
+            }
+    } else {
+        __shared__ int32_t wcnt[16][256];
+        __shared__ uint64_t red[32];
+        const int rounds = (ns + 1024 - 1) / 1024;
+        uint64_t kr[kSsRounds];
+        #pragma unroll
+        for (int q = 0; q < kSsRounds; ++q) {
+            const int i = (wave * rounds + q) * 64 + lane;
+            kr[q] = 0ull;
+            if (q < rounds && i < ns) {
+                bool ok;
+                kr[q] = sort_key(x[ss_sample_pos(i, ns, n)], ok);
+                sk[i] = kr[q];
+            }
+        }
+        // the bits in which the sample's keys differ
+        uint64_t lo = ~0ull, hi = 0ull;
+        #pragma unroll
+        for (int q = 0; q < kSsRounds; ++q) {
+            const int i = (wave * rounds + q) * 64 + lane;
+            if (q < rounds && i < ns) { lo = kr[q] < lo ? kr[q] : lo; hi = kr[q] > hi ? kr[q] : hi; }
+        }
+        #pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint64_t a = __shfl_xor(lo, o), b = __shfl_xor(hi, o);
+            lo = a < lo ? a : lo;
+            hi = b > hi ? b : hi;
+        }
+        if (lane == 0) { red[2 * wave] = lo; red[2 * wave + 1] = hi; }
+        __syncthreads();
+        uint64_t kmin = ~0ull, kmax = 0ull;
+        for (int v = 0; v < 16; ++v) {
+            kmin = red[2 * v] < kmin ? red[2 * v] : kmin;
+            kmax = red[2 * v + 1] > kmax ? red[2 * v + 1] : kmax;
+        }
+        const uint64_t diff = kmin ^ kmax;
+        const int passes = diff ? (64 - __clzll((long long)diff) + 7) / 8 : 0;
+        int dg[kSsRounds], rk[kSsRounds];
+        for (int p = 0; p < passes; ++p) {
+            for (int i = t; i < 16 * 256; i += 1024) (&wcnt[0][0])[i] = 0;
+            __syncthreads();
+            ss_rank_digits(kr, 8 * p, rounds, ns, wcnt, dg, rk);
+            __syncthreads();
+            // thread d < 256: the digit's start, then the waves' starts
+            int32_t c = 0, incl = 0;
+            if (t < 256) {
+                for (int v = 0; v < 16; ++v) c += wcnt[v][t];
+                incl = wave_incl_scan(c);
+                if (lane == 63) wtot[wave] = incl;
+            }
+            __syncthreads();
+            if (t < 256) {
+                int32_t run = incl - c;
+                for (int v = 0; v < wave; ++v) run += wtot[v];
+                for (int v = 0; v < 16; ++v) {
+                    const int32_t a = wcnt[v][t];
+                    wcnt[v][t] = run;
+                    run += a;
+                }
+            }
+            __syncthreads();
+            #pragma unroll
+            for (int q = 0; q < kSsRounds; ++q)
+                if (dg[q] >= 0) sk[wcnt[wave][dg[q]] + rk[q]] = kr[q];
+            __syncthreads();
+            #pragma unroll
+            for (int q = 0; q < kSsRounds; ++q) {
+                const int i = (wave * rounds + q) * 64 + lane;
+                if (q < rounds && i < ns) kr[q] = sk[i];
+            }
+        }
+        __syncthreads();
+    }
+    ss_pick_splitters(sk, ns, B, spl + seg * C::kMaxSpl, nspl + seg, wtot);
+}
+
+// Per tile: the bucket counts (tile-major, NB per tile) and errs[tile] (1 if
+// the tile holds a negative, NaN or infinite input).
+template <int NB>
 __global__ __launch_bounds__(kSsThreads) void k_ss_count(const double* __restrict__ r,
                                                          const double* __restrict__ w, SortSegs S,
                                                          const uint64_t* __restrict__ spl,
                                                          const int32_t* __restrict__ nspl,
                                                          int32_t* __restrict__ cnt, int32_t* __restrict__ errs)
 {
-    __shared__ uint64_t su[kSsMaxSpl];
-    __shared__ int32_t h[kSsBuckets];
+    using C = SsCfg<NB>;
+    __shared__ uint64_t su[C::kMaxSpl];
+    __shared__ int32_t h[NB];
     const int tile = blockIdx.x;
     const int seg = tile_segment(S, tile);
     const int lt = tile - S.tile0[seg];
     const int base = S.off[seg], end = S.off[seg + 1];
     const int U = nspl[seg];
     const double* __restrict__ x = seg ? w : r;
-    if (threadIdx.x < U) su[threadIdx.x] = spl[seg * kSsMaxSpl + threadIdx.x];
-    if (threadIdx.x < kSsBuckets) h[threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < U; i += kSsThreads) su[i] = spl[seg * C::kMaxSpl + i];
+    for (int i = threadIdx.x; i < NB; i += kSsThreads) h[i] = 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wbase = base + lt * kSsTile + wave * 64 * kSsRounds;
     double v[kSsRounds];
@@ -715,7 +824,7 @@ __global__ __launch_bounds__(kSsThreads) void k_ss_count(const double* __restric
             bool ok;
             const uint64_t k = sort_key(v[q], ok);
             bad |= !ok;
-            b = ss_bucket(su, U, k);
+            b = ss_bucket<NB>(su, U, k);
         }
         // a bucket shared by the whole round (sorted or clustered input) costs one add
         const int b0 = __shfl(b, 0);
@@ -728,27 +837,40 @@ __global__ __launch_bounds__(kSsThreads) void k_ss_count(const double* __restric
         }
     }
     const int any_bad = __syncthreads_or(bad ? 1 : 0);
-    if (threadIdx.x < kSsBuckets) cnt[(int64_t)tile * kSsBuckets + threadIdx.x] = h[threadIdx.x];
+    for (int i = threadIdx.x; i < NB; i += kSsThreads) cnt[(int64_t)tile * NB + i] = h[i];
     if (threadIdx.x == 0) errs[tile] = any_bad ? 1 : 0;
 }
 
-// One wave per segment, one lane per bucket: the bucket's counts over the
-// segment's tiles become exclusive offsets, btot receives the bucket sizes
-// and bstart their exclusive scan over the buckets.
-__global__ __launch_bounds__(kSsBuckets) void k_ss_scan(SortSegs S, int32_t* __restrict__ cnt,
-                                                        int32_t* __restrict__ bstart, int32_t* __restrict__ btot)
+// Per segment, one thread per bucket: the bucket's counts over the segment's
+// tiles become exclusive offsets, btot receives the bucket sizes and bstart
+// their exclusive scan over the buckets (NB = 64: one wave; NB = 1024: one
+// 1024-thread workgroup).
+template <int NB>
+__global__ __launch_bounds__(NB) void k_ss_scan(SortSegs S, int32_t* __restrict__ cnt,
+                                                int32_t* __restrict__ bstart, int32_t* __restrict__ btot)
 {
     const int seg = blockIdx.x, b = threadIdx.x;
     const int t0 = S.tile0[seg], nt = S.tile0[seg + 1] - t0;
     int32_t run = 0;
-    for (int t = 0; t < nt; ++t) {
-        int32_t* c = cnt + (int64_t)(t0 + t) * kSsBuckets + b;
-        const int32_t v = *c;
-        *c = run;
-        run += v;
+    for (int t = 0; t < nt; t += 16) {
+        int32_t v[16];
+        #pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = t + q < nt ? cnt[(int64_t)(t0 + t + q) * NB + b] : 0;
+        #pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (t + q < nt) cnt[(int64_t)(t0 + t + q) * NB + b] = run;
+            run += v[q];
+        }
     }
-    btot[seg * kSsBuckets + b] = run;
-    bstart[seg * kSsBuckets + b] = wave_incl_scan(run) - run;
+    btot[seg * NB + b] = run;
+    if constexpr (NB == 64) {
+        bstart[seg * NB + b] = wave_incl_scan(run) - run;
+    } else {
+        __shared__ int32_t wsum[1][16];
+        int32_t e[1] = {run}, tot[1];
+        block_scan<int32_t, 1, NB / 64>(e, tot, wsum);
+        bstart[seg * NB + b] = e[0];
+    }
 }
 
 // Stable scatter of a tile into the buckets, through LDS: wave v owns the
@@ -757,6 +879,7 @@ __global__ __launch_bounds__(kSsBuckets) void k_ss_scan(SortSegs S, int32_t* __r
 // bucket; one block step turns the waves' counts into LDS starts; the staged
 // tile is written out with consecutive threads on consecutive addresses of
 // each bucket's run.
+template <int NB>
 __global__ __launch_bounds__(kSsThreads) void k_ss_scatter(const double* __restrict__ r,
                                                            const double* __restrict__ w, SortSegs S,
                                                            const uint64_t* __restrict__ spl,
@@ -765,14 +888,17 @@ __global__ __launch_bounds__(kSsThreads) void k_ss_scatter(const double* __restr
                                                            const int32_t* __restrict__ bstart,
                                                            uint64_t* __restrict__ kout, int32_t* __restrict__ vout)
 {
+    using C = SsCfg<NB>;
+    using Id = typename C::Id;
     constexpr int kWaves = kSsThreads / 64;
     __shared__ uint64_t skey[kSsTile];
     __shared__ int32_t sval[kSsTile];
-    __shared__ uint8_t sbk[kSsTile];
-    __shared__ uint64_t su[kSsMaxSpl];
-    __shared__ int32_t wcnt[kWaves][kSsBuckets];
-    __shared__ int32_t gbase[kSsBuckets];
-    __shared__ int32_t lstart[kSsBuckets];
+    __shared__ Id sbk[kSsTile];
+    __shared__ uint64_t su[C::kMaxSpl];
+    __shared__ int32_t wcnt[kWaves][NB];
+    __shared__ int32_t gbase[NB];
+    __shared__ int32_t lstart[NB];
+    __shared__ int32_t wtot[kWaves];
     const int tile = blockIdx.x;
     const int seg = tile_segment(S, tile);
     const int lt = tile - S.tile0[seg];
@@ -790,8 +916,8 @@ __global__ __launch_bounds__(kSsThreads) void k_ss_scatter(const double* __restr
         bool ok;
         kr[q] = i < end ? sort_key(x[i - base], ok) : 0ull;
     }
-    if (threadIdx.x < U) su[threadIdx.x] = spl[seg * kSsMaxSpl + threadIdx.x];
-    for (int i = threadIdx.x; i < kWaves * kSsBuckets; i += kSsThreads) (&wcnt[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < U; i += kSsThreads) su[i] = spl[seg * C::kMaxSpl + i];
+    for (int i = threadIdx.x; i < kWaves * NB; i += kSsThreads) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     int bk[kSsRounds], rk[kSsRounds];
     int32_t* cw = wcnt[wave];
@@ -799,8 +925,8 @@ __global__ __launch_bounds__(kSsThreads) void k_ss_scatter(const double* __restr
     for (int q = 0; q < kSsRounds; ++q) {
         const int i = wbase + q * 64 + lane;
         const bool valid = i < end;
-        const int b = valid ? ss_bucket(su, U, kr[q]) : 0;
-        const uint64_t peers = bucket_peers(b, valid);
+        const int b = valid ? ss_bucket<NB>(su, U, kr[q]) : 0;
+        const uint64_t peers = bucket_peers<C::kBits>(b, valid);
         const int rank = __popcll(peers & lt_mask);
         const int32_t before = valid ? cw[b] : 0;
         wave_sync_lds();
@@ -810,23 +936,56 @@ __global__ __launch_bounds__(kSsThreads) void k_ss_scatter(const double* __restr
         bk[q] = valid ? b : -1;
     }
     __syncthreads();
-    // wave 0, lane b: the tile's count of bucket b, its LDS start (exclusive
-    // scan over the buckets), the waves' starts and the global base
-    if (wave == 0) {
-        const int b = lane;
-        int32_t c = 0;
-        #pragma unroll
-        for (int v = 0; v < kWaves; ++v) c += wcnt[v][b];
-        const int32_t ls = wave_incl_scan(c) - c;
-        lstart[b] = ls;
-        int32_t run = ls;
-        #pragma unroll
-        for (int v = 0; v < kWaves; ++v) {
-            const int32_t a = wcnt[v][b];
-            wcnt[v][b] = run;
-            run += a;
+    // per bucket: the tile's count, its LDS start (exclusive scan over the
+    // buckets), the waves' starts and the global base
+    if constexpr (NB == 64) {
+        if (wave == 0) {
+            const int b = lane;
+            int32_t c = 0;
+            #pragma unroll
+            for (int v = 0; v < kWaves; ++v) c += wcnt[v][b];
+            const int32_t ls = wave_incl_scan(c) - c;
+            lstart[b] = ls;
+            int32_t run = ls;
+            #pragma unroll
+            for (int v = 0; v < kWaves; ++v) {
+                const int32_t a = wcnt[v][b];
+                wcnt[v][b] = run;
+                run += a;
+            }
+            gbase[b] = base + bstart[seg * NB + b] + cnt[(int64_t)tile * NB + b];
         }
-        gbase[b] = base + bstart[seg * kSsBuckets + b] + cnt[(int64_t)tile * kSsBuckets + b];
+    } else {
+        // thread t: buckets BPT t .. BPT t + BPT - 1
+        constexpr int BPT = NB / kSsThreads;
+        const int b0 = BPT * threadIdx.x;
+        int32_t c[BPT], sum = 0;
+        #pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+            c[j] = 0;
+            #pragma unroll
+            for (int v = 0; v < kWaves; ++v) c[j] += wcnt[v][b0 + j];
+            sum += c[j];
+        }
+        const int32_t incl = wave_incl_scan(sum);
+        if (lane == 63) wtot[wave] = incl;
+        __syncthreads();
+        int32_t ex = incl - sum;
+        for (int v = 0; v < wave; ++v) ex += wtot[v];
+        #pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+            const int b = b0 + j;
+            lstart[b] = ex;
+            int32_t run = ex;
+            #pragma unroll
+            for (int v = 0; v < kWaves; ++v) {
+                const int32_t a = wcnt[v][b];
+                wcnt[v][b] = run;
+                run += a;
+            }
+            gbase[b] = base + bstart[seg * NB + b] + cnt[(int64_t)tile * NB + b];
+            ex += c[j];
+        }
     }
     __syncthreads();
     #pragma unroll
@@ -835,7 +994,7 @@ __global__ __launch_bounds__(kSsThreads) void k_ss_scatter(const double* __restr
             const int off = cw[bk[q]] + rk[q];
             skey[off] = kr[q];
             sval[off] = wbase + q * 64 + lane - base;
-            sbk[off] = (uint8_t)bk[q];
+            sbk[off] = (Id)bk[q];
         }
     }
     __syncthreads();
@@ -860,6 +1019,7 @@ __device__ __forceinline__ int32_t load_coherent(const int32_t* p)
 
 // One workgroup per (segment, bucket slot): the bucketed keys (kin, vin) of
 // the bucket, sorted stably, into (kout, vout) at the same offsets.
+template <int NB>
 __global__ __launch_bounds__(kSsLocalThreads) void k_ss_local(SortSegs S, const int32_t* __restrict__ nspl,
                                                               const int32_t* __restrict__ bstart,
                                                               const int32_t* __restrict__ btot,
@@ -870,11 +1030,11 @@ __global__ __launch_bounds__(kSsLocalThreads) void k_ss_local(SortSegs S, const 
     constexpr int kWaves = kSsLocalThreads / 64;
     __shared__ SsBlockLds L;
     __shared__ int32_t gb[256];
-    const int seg = blockIdx.x / kSsBuckets, b = blockIdx.x % kSsBuckets;
+    const int seg = blockIdx.x / NB, b = blockIdx.x % NB;
     if (b > 2 * nspl[seg]) return;
-    const int32_t size = btot[seg * kSsBuckets + b];
+    const int32_t size = btot[seg * NB + b];
     if (size == 0) return;
-    const int64_t start = S.off[seg] + bstart[seg * kSsBuckets + b];
+    const int64_t start = S.off[seg] + bstart[seg * NB + b];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if ((b & 1) || size == 1) {   // equal keys: already in order
         for (int32_t i = threadIdx.x; i < size; i += kSsLocalThreads) {
@@ -1613,19 +1773,21 @@ static SortSegs sort_segs(int32_t na, int32_t nb)
     return S;
 }
 
-// Scratch layout of the splitter sort in hist (int32 units): the splitters
-// (2 x kSsMaxSpl uint64), their counts, the bucket starts and sizes (2 x
-// kSsBuckets each), then the tile-major bucket counts.
-constexpr int kSsSplOff = 0, kSsNsplOff = 128, kSsStartOff = 192;
-constexpr int kSsTotOff = kSsStartOff + 2 * kSsBuckets, kSsCntOff = kSsTotOff + 2 * kSsBuckets;
-static_assert(2 * 2 * kSsMaxSpl <= kSsNsplOff, "splitter area too small");
+// The 1024-slot splitter sort is taken up to 2^18 keys: measured faster than
+// the LSD sort there (200000 keys: plan 0.263 against 0.287 ms); at 1e6 its
+// sample and bucket sorts (ballot ranking, LDS round trips per round) cost
+// 342 us of GPU time against the LSD sort's 276.
+constexpr int32_t kSsLargeMax = 1 << 18;
+static_assert(kSsLargeMax <= SsCfg<1024>::kMaxLen, "splitter sort capacity");
 
-enum class SortPath { small, splitter, lsd };
+enum class SortPath { small, splitter64, splitter1024, lsd };
 
 static SortPath sort_path(int32_t na, int32_t nb)
 {
-    if (na <= kSsCap && nb <= kSsCap) return SortPath::small;
-    if (na <= kSsMaxLen && nb <= kSsMaxLen) return SortPath::splitter;
+    const int32_t mx = na > nb ? na : nb;
+    if (mx <= kSsCap) return SortPath::small;
+    if (mx <= SsCfg<64>::kMaxLen) return SortPath::splitter64;
+    if (mx <= kSsLargeMax) return SortPath::splitter1024;
     return SortPath::lsd;
 }
 
@@ -1639,6 +1801,29 @@ static SortSegs ss_segs(int32_t na, int32_t nb)
     return S;
 }
 
+template <int NB>
+static hipError_t launch_splitter_sort(const double* r, int32_t na, const double* w, int32_t nb, uint64_t* k0,
+                                       int32_t* v0, uint64_t* k1, int32_t* v1, int32_t* hist, int32_t* errs,
+                                       hipStream_t s)
+{
+    using C = SsCfg<NB>;
+    const SortSegs S = ss_segs(na, nb);
+    const int tiles = S.tile0[2];
+    uint64_t* spl = (uint64_t*)hist;
+    int32_t* nspl = hist + C::kNsplOff;
+    int32_t* bstart = hist + C::kStartOff;
+    int32_t* btot = hist + C::kTotOff;
+    int32_t* cnt = hist + C::kCntOff;
+    hipLaunchKernelGGL(k_ss_sample<NB>, dim3(2), dim3(1024), 0, s, r, w, S, spl, nspl);
+    hipLaunchKernelGGL(k_ss_count<NB>, dim3(tiles), dim3(kSsThreads), 0, s, r, w, S, spl, nspl, cnt, errs);
+    hipLaunchKernelGGL(k_ss_scan<NB>, dim3(2), dim3(NB), 0, s, S, cnt, bstart, btot);
+    hipLaunchKernelGGL(k_ss_scatter<NB>, dim3(tiles), dim3(kSsThreads), 0, s, r, w, S, spl, nspl, cnt, bstart, k1,
+                       v1);
+    hipLaunchKernelGGL(k_ss_local<NB>, dim3(2 * NB), dim3(kSsLocalThreads), 0, s, S, nspl, bstart, btot, k1, v1,
+                       k0, v0);
+    return hipGetLastError();
+}
+
 hipError_t launch_keys_and_sort(const double* r, int32_t na, const double* w, int32_t nb, uint64_t* k0, int32_t* v0,
                                 uint64_t* k1, int32_t* v1, int32_t* hist, int32_t* errs, hipStream_t s)
 {
@@ -1649,23 +1834,9 @@ hipError_t launch_keys_and_sort(const double* r, int32_t na, const double* w, in
         hipLaunchKernelGGL(k_sort_small, dim3(2), dim3(kSsLocalThreads), 0, s, r, w, S, k0, v0, errs);
         return hipGetLastError();
     }
-    if (path == SortPath::splitter) {
-        const SortSegs S = ss_segs(na, nb);
-        const int tiles = S.tile0[2];
-        uint64_t* spl = (uint64_t*)(hist + kSsSplOff);
-        int32_t* nspl = hist + kSsNsplOff;
-        int32_t* bstart = hist + kSsStartOff;
-        int32_t* btot = hist + kSsTotOff;
-        int32_t* cnt = hist + kSsCntOff;
-        hipLaunchKernelGGL(k_ss_sample, dim3(2), dim3(kSsSample), 0, s, r, w, S, spl, nspl);
-        hipLaunchKernelGGL(k_ss_count, dim3(tiles), dim3(kSsThreads), 0, s, r, w, S, spl, nspl, cnt, errs);
-        hipLaunchKernelGGL(k_ss_scan, dim3(2), dim3(kSsBuckets), 0, s, S, cnt, bstart, btot);
-        hipLaunchKernelGGL(k_ss_scatter, dim3(tiles), dim3(kSsThreads), 0, s, r, w, S, spl, nspl, cnt, bstart, k1,
-                           v1);
-        hipLaunchKernelGGL(k_ss_local, dim3(2 * kSsBuckets), dim3(kSsLocalThreads), 0, s, S, nspl, bstart, btot, k1,
-                           v1, k0, v0);
-        return hipGetLastError();
-    }
+    if (path == SortPath::splitter64) return launch_splitter_sort<64>(r, na, w, nb, k0, v0, k1, v1, hist, errs, s);
+    if (path == SortPath::splitter1024)
+        return launch_splitter_sort<1024>(r, na, w, nb, k0, v0, k1, v1, hist, errs, s);
     const SortSegs S = sort_segs(na, nb);
     const int tiles = S.tile0[2];
     if (tiles == 0) return hipSuccess;
@@ -1695,7 +1866,8 @@ int sort_tiles(int32_t na, int32_t nb)
 {
     switch (sort_path(na, nb)) {
         case SortPath::small: return 2;
-        case SortPath::splitter: return cdiv(na, kSsTile) + cdiv(nb, kSsTile);
+        case SortPath::splitter64:
+        case SortPath::splitter1024: return cdiv(na, kSsTile) + cdiv(nb, kSsTile);
         default: return cdiv(na, kSortTile) + cdiv(nb, kSortTile);
     }
 }
@@ -1704,7 +1876,8 @@ int sort_hist_len(int32_t na, int32_t nb)
 {
     switch (sort_path(na, nb)) {
         case SortPath::small: return 1;
-        case SortPath::splitter: return kSsCntOff + kSsBuckets * sort_tiles(na, nb);
+        case SortPath::splitter64: return SsCfg<64>::kCntOff + 64 * sort_tiles(na, nb);
+        case SortPath::splitter1024: return SsCfg<1024>::kCntOff + 1024 * sort_tiles(na, nb);
         default: return 256 * sort_tiles(na, nb) + 2 * 256;
     }
 }

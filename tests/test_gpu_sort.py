@@ -3,7 +3,8 @@
 Bar: bit-exact.  The sorted values equal numpy's sort (with -0.0 read as
 +0.0) and the permutations equal numpy's stable argsort, on all three sort
 paths (one workgroup per segment when both hold at most 4096 keys, the
-splitter sort up to 65536, the LSD radix sort above), at ragged sizes around
+splitter sort up to 2^18 -- 64 bucket slots up to 65536 keys, 1024 above --
+and the LSD radix sort beyond), at ragged sizes around
 the tile and bucket sizes, with duplicates, signed zeros, presorted and
 reversed inputs, clustered inputs, values spread over hundreds of binades,
 and inputs built against the sampler so that one bucket overflows the LDS
@@ -16,7 +17,8 @@ import torch
 pytestmark = pytest.mark.gpu
 
 SMALL_MAX = 4096
-SS_MAX = 1 << 16
+SS64_MAX = 1 << 16
+SS_MAX = 1 << 18
 
 
 @pytest.fixture(scope="module")
@@ -52,14 +54,15 @@ def check_each_side(nuht, x, label):
 
 
 @pytest.mark.parametrize("n,m", [(1, 1), (5, 3), (0, 300), (2047, 2048), (SMALL_MAX, SMALL_MAX), (SMALL_MAX + 1, 9),
-                                 (8191, 8193), (30000, 60001), (SS_MAX, SS_MAX), (SS_MAX + 1, 3000),
-                                 (5000, SS_MAX + 7), (1_000_000, 1_000_000)])
+                                 (8191, 8193), (30000, 60001), (SS64_MAX, SS64_MAX), (SS64_MAX + 1, 3000),
+                                 (5000, SS64_MAX + 7), (250_000, 170_001), (SS_MAX, 1000), (1_000_000, 1_000_000),
+                                 (SS_MAX + 1, 3000), (5000, SS_MAX + 7)])
 def test_sort_uniform(nuht, n, m):
     rng = np.random.default_rng(n + 7 * m)
     check_order(nuht, rng.uniform(0.0, 1.0, n), rng.uniform(0.0, 1e5, m), "uniform")
 
 
-@pytest.mark.parametrize("n", [3000, 50_000, 300_000])
+@pytest.mark.parametrize("n", [3000, 50_000, 200_000, 300_000])
 def test_sort_duplicates_and_zeros(nuht, n):
     rng = np.random.default_rng(3 + n)
     r = rng.choice(np.array([0.0, -0.0, 0.25, 0.5, 0.75, 1.0]), n)
@@ -70,7 +73,7 @@ def test_sort_duplicates_and_zeros(nuht, n):
     check_order(nuht, np.zeros(n), np.full(n // 7, 3.0), "all equal")
 
 
-@pytest.mark.parametrize("n", [4000, 60_000, 400_000])
+@pytest.mark.parametrize("n", [4000, 60_000, 200_000, 1_100_000])
 def test_sort_presorted_reversed_clustered(nuht, n):
     k = np.arange(n)
     cheb = 0.5 * (1.0 - np.cos(np.pi * (k + 0.5) / n))          # clustered at both ends
@@ -103,7 +106,8 @@ def test_sort_bucket_overflow(nuht):
     # low bits of the key (3 passes), one of width 1e-12 in 14 (2 passes, so
     # the result is copied back).
     rng = np.random.default_rng(11)
-    for n, width, label in ((60_000, 1e-9, "odd pass count"), (50_000, 1e-12, "even pass count")):
+    for n, width, label in ((60_000, 1e-9, "odd pass count"), (50_000, 1e-12, "even pass count"),
+                            (200_000, 1e-9, "1024 bucket slots")):
         x = 0.5 + width * rng.uniform(0.0, 1.0, n)
         pos = sampler_positions(n)
         assert np.unique(pos).size == pos.size and pos.max() < n
