@@ -526,9 +526,10 @@ __global__ __launch_bounds__(256) void k_spread_many(const PlanDev* __restrict__
 // ---------------------------------------------------------------------------
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// 16-column tiles of the channel columns (re, im of 8 channels each)
+// 16-column tiles of the channel columns (re, im of 8 channels each): one
+// to four, channel counts up to kMfmaMaxChannels
 template <int NCH>
-constexpr int kSpreadTiles = NCH <= 8 ? 1 : 2;
+constexpr int kSpreadTiles = (2 * NCH + 15) / 16;
 
 template <int NCH, int ANCH = kSpreadAnchors>
 struct SpreadMfma {
@@ -536,9 +537,10 @@ struct SpreadMfma {
     static constexpr int NC = 16 * NCT;            // real columns of the tiles (re, im of 8 NCT channels)
     static constexpr int VS = 2 * NCH + 1;         // LDS stride of a point's 2 NCH columns (odd: conflict-free writes)
     static constexpr int GC = ANCH + 15;           // cells an item's anchor tiles reach
-    // points per step: 64, or 32 with two column tiles, so that the wider
-    // point records still let three workgroups share a compute unit's LDS
-    static constexpr int WPTS = NCT > 1 ? 32 : 64;
+    // points per step: 64, 32 with two column tiles, 16 with three or four,
+    // so that the wider point records still fit (three workgroups per compute
+    // unit at two tiles, two at four)
+    static constexpr int WPTS = NCT > 2 ? 16 : NCT > 1 ? 32 : 64;
     // a point: its columns, its s and its anchor
     static constexpr size_t point_bytes = (VS + 1) * sizeof(double) + sizeof(int32_t);
     static constexpr size_t fold_bytes = (size_t)GC * NC * sizeof(double);   // the wave's cell sums
@@ -1790,9 +1792,11 @@ template <int NCH>
 static void launch_spread(const PlanDev& P, const Summary& S, hipStream_t s)
 {
     const int32_t n_dense = S.n_adense, n_med = S.n_amed, n_rest = S.n_aitems - S.n_adense - S.n_amed;
-    if constexpr (NCH <= 16) {
+    if constexpr (NCH <= kMfmaMaxChannels) {
         if (n_dense > 0)
             hipLaunchKernelGGL((k_spread_mfma<NCH, kSpreadAnchors>), dim3(n_dense), dim3(256), 0, s, P);
+    }
+    if constexpr (NCH <= kMfmaMedMaxChannels) {
         if (n_med > 0)
             hipLaunchKernelGGL((k_spread_mfma<NCH, kSpreadAnchorsMed>), dim3(n_med), dim3(256), 0, s, P);
     }
@@ -2071,14 +2075,14 @@ void build_batch_schedule(const BatchTransform* tr, int count, const int* order,
     for (const auto& v : variants) {
         const int nch = v.first, fp32 = v.second;
         auto same = [&](const PlanDev& P) { return live(P) && P.nch == nch && P.fp32 == fp32; };
-        if (nch <= 16) {   // static LDS: no launch bytes
+        if (nch <= kMfmaMaxChannels)   // static LDS: no launch bytes
             add(kSpreadMfma, nch, fp32, 256, [&](const BatchTransform& T, size_t&) -> int64_t {
                 return same(*T.P) ? T.S->n_adense : 0;
             });
+        if (nch <= kMfmaMedMaxChannels)
             add(kSpreadMfmaMed, nch, fp32, 256, [&](const BatchTransform& T, size_t&) -> int64_t {
                 return same(*T.P) ? T.S->n_amed : 0;
             });
-        }
         add(kSpreadVec, nch, fp32, 256, [&](const BatchTransform& T, size_t& lds) -> int64_t {
             if (!same(*T.P)) return 0;
             lds = fp32 ? spread_lds_bytes<float>(T.P->w) : spread_lds_bytes<double>(T.P->w);
@@ -2183,11 +2187,13 @@ hipError_t launch_execute_many(const BatchSchedule& S, const void* table_dev, vo
         case kSpreadMfmaMed:
             dispatch_channels(L.variant, [&](auto k) {
                 constexpr int NCH = decltype(k)::value;
-                if constexpr (NCH <= 16) {
+                if constexpr (NCH <= kMfmaMaxChannels) {
                     if (L.kind == kSpreadMfma)
                         hipLaunchKernelGGL((k_spread_mfma_many<NCH, kSpreadAnchors>), grid, block, 0, s, plans, sg,
                                            L.nseg);
-                    else
+                }
+                if constexpr (NCH <= kMfmaMedMaxChannels) {
+                    if (L.kind == kSpreadMfmaMed)
                         hipLaunchKernelGGL((k_spread_mfma_many<NCH, kSpreadAnchorsMed>), grid, block, 0, s, plans,
                                            sg, L.nseg);
                 }

@@ -1088,7 +1088,7 @@ static int fill_params(PlanDev& P, int nu2, double eps_req, const nuht_opts& o)
     }
     P.w = es_width(eps, o.precision);
     P.fp32 = o.precision == NUHT_FP32_SPREAD ? 1 : 0;
-    P.mfma = (!P.fp32 && P.w <= 16 && P.nch <= 16 && !o.vector_spread) ? 1 : 0;
+    P.mfma = (!P.fp32 && P.w <= 16 && P.nch <= kMfmaMaxChannels && !o.vector_spread) ? 1 : 0;
     P.beta = es_beta(P.w);
     for (int p = 0; p < 2 * M + 2; ++p) P.hank[p] = hankel_coef(nu, p);
     for (int p = 0; p < kMaxChannels; ++p)

@@ -33,6 +33,8 @@ constexpr int kMaxEsWidth = 18;        // largest ES kernel width
 constexpr int kEsDeg = 13;             // degree of the per-cell polynomial pieces of the ES kernel
 constexpr int kSpreadAnchors = 6;      // first cells (anchors) of a dense matrix-core spreading item
 constexpr int kSpreadAnchorsMed = 40;  // first cells of a medium one (its own launch, larger LDS cell sums)
+constexpr int kMfmaMaxChannels = 32;   // channel counts whose dense items go to the matrix cores
+constexpr int kMfmaMedMaxChannels = 16; // ... and whose medium items (their LDS cell sums grow with the channels)
 constexpr int kMaxLevels = 4096;       // subdivision depth limit
 constexpr int kHalfDeg = 20;           // degree of the half-integer local coefficients on a panel
 constexpr double kHalfWidth = 4.0;     // panel width (in omega R) of those coefficients
@@ -131,7 +133,7 @@ struct PlanDev {
     int32_t half_ns, pad0;           // leading panels holding the coefficients divided by x^nu
     int32_t nch, sign;               // channels (2M padded to a kernel instance); (-1)^nu for negative orders, else 1
     int32_t fp32;                    // FP32 spreading (weights, kernel values and channel sums in float)
-    int32_t mfma;                    // dense spreading items go to the matrix cores (FP64, w <= 16, nch <= 16)
+    int32_t mfma;                    // dense spreading items go to the matrix cores (FP64, w <= 16, nch <= 32)
     double z, beta, eps;
     double phi_hi, phi_lo;           // -(2nu+1) pi/4 reduced to [0, 2pi), double-double
     double hank[2 * 20 + 2];         // a_p(nu), p = 0 .. 2M+1 (Hankel coefficients)

@@ -1688,7 +1688,9 @@ __global__ void k_items(PlanDev P, Arena A, Summary* __restrict__ sum, int32_t* 
             // margin each side for rounding): dense if at most kSpreadAnchors,
             // medium if at most kSpreadAnchorsMed
             const int32_t anchors = I.sub_n - w + 1;
-            I.dense = !P.mfma ? 0 : anchors <= kSpreadAnchors ? 1 : anchors <= kSpreadAnchorsMed ? 2 : 0;
+            I.dense = !P.mfma ? 0
+                    : anchors <= kSpreadAnchors ? 1
+                    : (anchors <= kSpreadAnchorsMed && P.nch <= kMfmaMedMaxChannels) ? 2 : 0;
             A.aitems[ia] = I;
             a_cells[ia] = I.sub_n;
         }
