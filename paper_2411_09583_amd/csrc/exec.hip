@@ -1432,7 +1432,37 @@ __device__ __forceinline__ double rcp_refined(double x)
     return y;
 }
 
-template <int NCH>
+// One Horner step of a direct-sum cell sum with the cell's channel-0 value
+// (g0r, g0i) in scalar registers:
+//   (ar, ai) <- (ar, ai) e^{i theta} + (g0r, g0i)
+// in four FMAs, the scalar values as addends and ar, ai updated in place.
+// The compiler would copy the two scalar values into vector registers first
+// and move the results back into ar, ai (six more instructions per cell);
+// the step is written out so that it does not.  Callers pass values that are
+// the same in every lane.
+__device__ __forceinline__ void rotate_add_uniform(double& ar, double& ai, double er, double ei, double g0r, double g0i)
+{
+    double t;
+    asm("v_fma_f64 %2, %0, %4, %6\n\t"     // t  = ar ei + g0i
+        "v_fma_f64 %0, %0, %3, %5\n\t"     // ar = ar er + g0r
+        "v_fma_f64 %0, -%1, %4, %0\n\t"    // ar -= ai ei
+        "v_fma_f64 %1, %1, %3, %2"           // ai = ai er + t
+        : "+v"(ar), "+v"(ai), "=&v"(t)
+        : "v"(er), "v"(ei), "s"(g0r), "s"(g0i));
+}
+
+// a b + c with c the same in every lane, as one FMA with c its scalar addend
+// (the compiler copies such an addend into vector registers first).
+__device__ __forceinline__ double fma_uniform_addend(double a, double b, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
+// UNI: the block index, and so the block's fields and grid, is the same in
+// every lane of the wave.
+template <int NCH, bool UNI>
 __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2* __restrict__ grids)
 {
     const ABlock B = P.ab[ablk];
@@ -1472,15 +1502,26 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
             double2 gv[NCH];
             #pragma unroll
             for (int p = 0; p < NCH; ++p) gv[p] = gp[p];
-            double br = gv[0].x, bi = gv[0].y;
-            #pragma unroll
-            for (int p = 1; p < NCH; ++p) {
-                br = __builtin_fma(gv[p].x, gpow[p], br);
-                bi = __builtin_fma(gv[p].y, gpow[p], bi);
+            if constexpr (UNI) {
+                // the rotation first, channel 0 its addend, then the other
+                // channels straight into ar, ai
+                rotate_add_uniform(ar, ai, er, ei, gv[0].x, gv[0].y);
+                #pragma unroll
+                for (int p = 1; p < NCH; ++p) {
+                    ar = __builtin_fma(gv[p].x, gpow[p], ar);
+                    ai = __builtin_fma(gv[p].y, gpow[p], ai);
+                }
+            } else {
+                double br = gv[0].x, bi = gv[0].y;
+                #pragma unroll
+                for (int p = 1; p < NCH; ++p) {
+                    br = __builtin_fma(gv[p].x, gpow[p], br);
+                    bi = __builtin_fma(gv[p].y, gpow[p], bi);
+                }
+                const double tr = __builtin_fma(ar, er, __builtin_fma(-ai, ei, br));
+                ai = __builtin_fma(ar, ei, __builtin_fma(ai, er, bi));
+                ar = tr;
             }
-            const double tr = __builtin_fma(ar, er, __builtin_fma(-ai, ei, br));
-            ai = __builtin_fma(ar, ei, __builtin_fma(ai, er, bi));
-            ar = tr;
         }
     } else {
         const double2* Aq = grids + B.grid_off;
@@ -1499,25 +1540,28 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
         const double two_over_w = 2.0 / w;
         for (int tap = 0; tap < w; ++tap) {
             int q = q0 + tap;
+            int qi = q & mask;
+            // the tap's channel values first, all loads in flight while the
+            // kernel value is computed
+            double2 gv[NCH];
+            #pragma unroll
+            for (int p = 0; p < NCH; ++p) gv[p] = Aq[(int64_t)p * B.N2 + qi];
             double psi;
-            if constexpr (NCH >= 10) {
+            if constexpr (NCH >= 8) {
                 const double* cf = es_poly + tap * (kEsDeg + 1);
                 psi = cf[kEsDeg];
                 #pragma unroll
-                for (int d = kEsDeg - 1; d >= 0; --d) psi = __builtin_fma(psi, sf, cf[d]);
+                for (int d = kEsDeg - 1; d >= 0; --d) psi = fma_uniform_addend(psi, sf, cf[d]);
             } else {
                 psi = es_kernel((((double)q - v.hi) - vl) * two_over_w, P.beta);
             }
-            int qi = q & mask;
             // Horner's rule in gamma from the highest channel: the loaded values
             // (vector registers here) are the addends
-            double2 top = Aq[(int64_t)(NCH - 1) * B.N2 + qi];
-            double br = top.x, bi = top.y;
+            double br = gv[NCH - 1].x, bi = gv[NCH - 1].y;
             #pragma unroll
             for (int p = NCH - 2; p >= 0; --p) {
-                double2 gv = Aq[(int64_t)p * B.N2 + qi];
-                br = __builtin_fma(br, gam, gv.x);
-                bi = __builtin_fma(bi, gam, gv.y);
+                br = __builtin_fma(br, gam, gv[p].x);
+                bi = __builtin_fma(bi, gam, gv[p].y);
             }
             ar = __builtin_fma(psi, br, ar);
             ai = __builtin_fma(psi, bi, ai);
@@ -1689,8 +1733,8 @@ __device__ __forceinline__ void rows_asy_body(const PlanDev& P, int bid)
             if (nd.ablk >= 0) {
                 int ab = nd.ablk;
                 int abu = __builtin_amdgcn_readfirstlane(ab);
-                if (__all(ab == abu)) acc += asym_eval<NCH>(P, abu, om, grids);
-                else acc += asym_eval<NCH>(P, ab, om, grids);
+                if (__all(ab == abu)) acc += asym_eval<NCH, true>(P, abu, om, grids);
+                else acc += asym_eval<NCH, false>(P, ab, om, grids);
             }
             child = nd.ll;
         }

@@ -575,29 +575,50 @@ static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w
     }
 }
 
-static void eshat_chebyshev(int w, double beta, double kappa_max, double* coef, int nc)
+// ES^ on [0, kappa_max] as a polynomial in s = 2 (kappa / kappa_max)^2 - 1:
+// values at the kEshatTerms Chebyshev points in s (Gauss-Legendre quadrature
+// of the kernel's cosine transform, which converges fast as the kernel is
+// smooth and e^-beta small at the ends), their Chebyshev interpolant, then its
+// monomial coefficients in s, all in long double.
+static void eshat_poly(double beta, double kappa_max, double* coef)
 {
+    constexpr int n = kEshatTerms;
+    const long double pi = 3.141592653589793238462643383279502884L;
     std::vector<double> x, wt;
     gauss_legendre(240, x, wt);
-    std::vector<double> f(nc);
-    for (int j = 0; j < nc; ++j) {
-        double t = std::cos(M_PI * (j + 0.5) / nc);
-        double kappa = 0.5 * (t + 1.0) * kappa_max;
+    long double f[n], c[n];
+    for (int j = 0; j < n; ++j) {
+        const long double t = std::cos(pi * (j + 0.5L) / n);
+        const long double kappa = (long double)kappa_max * std::sqrt(0.5L * (t + 1.0L));
         long double s = 0.0L;
         for (size_t i = 0; i < x.size(); ++i) {
-            double xx = x[i];
-            double es = std::exp(beta * (std::sqrt(std::max(0.0, 1.0 - xx * xx)) - 1.0));
+            const long double xx = x[i];
+            const long double es = std::exp((long double)beta * (std::sqrt(std::max(0.0L, 1.0L - xx * xx)) - 1.0L));
             s += (long double)wt[i] * es * std::cos(kappa * xx);
         }
-        f[j] = (double)s;
+        f[j] = s;
     }
-    for (int k = 0; k < nc; ++k) {
+    for (int k = 0; k < n; ++k) {
         long double s = 0.0L;
-        for (int j = 0; j < nc; ++j) s += (long double)f[j] * std::cos(M_PI * k * (j + 0.5) / nc);
-        coef[k] = (double)(2.0L * s / nc);
+        for (int j = 0; j < n; ++j) s += f[j] * std::cos(pi * k * (j + 0.5L) / n);
+        c[k] = 2.0L * s / n;
     }
-    coef[0] *= 0.5;
-    (void)w;
+    c[0] *= 0.5L;
+    // sum_k c_k T_k(s) in monomials: T_{k+1} = 2 s T_k - T_{k-1}
+    long double Tm[n] = {}, T0[n] = {}, a[n] = {};
+    T0[0] = 1.0L;                 // T_0
+    for (int k = 0; k < n; ++k) {
+        for (int i = 0; i < n; ++i) a[i] += c[k] * T0[i];
+        long double Tn[n] = {};
+        if (k == 0) {
+            Tn[1] = 1.0L;             // T_1 = s
+        } else {
+            for (int i = 0; i + 1 < n; ++i) Tn[i + 1] = 2.0L * T0[i];
+            for (int i = 0; i < n; ++i) Tn[i] -= Tm[i];
+        }
+        for (int i = 0; i < n; ++i) { Tm[i] = T0[i]; T0[i] = Tn[i]; }
+    }
+    for (int i = 0; i < n; ++i) coef[i] = (double)a[i];
 }
 
 // The ES kernel as w polynomial pieces.  A point at grid coordinate u reaches
@@ -1095,18 +1116,20 @@ static int fill_params(PlanDev& P, int nu2, double eps_req, const nuht_opts& o)
         P.chan[p] = p < 2 * M ? (((p >> 1) & 1) ? -P.hank[p] : P.hank[p]) : 0.0;
     phase_offset2(half ? nu2 + 1 : 2 * anu + 1, P.phi_hi, P.phi_lo);
     P.kappa_max = P.w * M_PI / 4.0 * (1.0 + 1e-9);
-    P.n_eshat = 24;   // the series reaches the quadrature's ~1e-15 floor by then (w <= 18)
+    P.eshat_s = 2.0 / (P.kappa_max * P.kappa_max);
     P.spread_chunk = o.spread_chunk > 0 ? o.spread_chunk : kSpreadChunk;
-    // the Chebyshev series depends only on the kernel width (beta follows w)
+    // the polynomial depends only on the kernel width (beta follows w); at
+    // kEshatTerms = 16 terms it is within about 1e-14 of ES^, relative, for
+    // every width up to kMaxEsWidth
     static std::mutex mu;
-    static double cache[32][32];
+    static double cache[32][kEshatTerms];
     static bool have[32] = {};
     std::lock_guard<std::mutex> lock(mu);
     if (!have[P.w]) {
-        eshat_chebyshev(P.w, P.beta, P.kappa_max, cache[P.w], P.n_eshat);
+        eshat_poly(P.beta, P.kappa_max, cache[P.w]);
         have[P.w] = true;
     }
-    for (int i = 0; i < P.n_eshat; ++i) P.eshat[i] = cache[P.w][i];
+    for (int i = 0; i < kEshatTerms; ++i) P.eshat[i] = cache[P.w][i];
     return NUHT_OK;
 }
 

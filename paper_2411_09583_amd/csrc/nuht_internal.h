@@ -30,6 +30,7 @@ inline int64_t default_min_size(int64_t n, int64_t m) {
     return s;
 }
 constexpr int kMaxEsWidth = 18;        // largest ES kernel width
+constexpr int kEshatTerms = 16;        // terms of the polynomial for the ES kernel's Fourier transform
 constexpr int kEsDeg = 13;             // degree of the per-cell polynomial pieces of the ES kernel
 constexpr int kSpreadAnchors = 6;      // first cells (anchors) of a dense matrix-core spreading item
 constexpr int kSpreadAnchorsMed = 40;  // first cells of a medium one (its own launch, larger LDS cell sums)
@@ -138,9 +139,9 @@ struct PlanDev {
     double phi_hi, phi_lo;           // -(2nu+1) pi/4 reduced to [0, 2pi), double-double
     double hank[2 * 20 + 2];         // a_p(nu), p = 0 .. 2M+1 (Hankel coefficients)
     double chan[kMaxChannels];       // channel factors (-1)^(p/2) a_p(nu) for p < 2M (odd p carry a factor i), 0 above
-    double eshat[32];                // Chebyshev coefficients of ES^ on [0, kappa_max]
-    int32_t n_eshat, spread_chunk;   // Chebyshev terms of ES^; points per spreading work item
-    double kappa_max;
+    double eshat[kEshatTerms];       // ES^ on [0, kappa_max]: monomial coefficients in s = 2 (kappa / kappa_max)^2 - 1
+    int32_t spread_chunk, pad3;      // points per spreading work item
+    double kappa_max, eshat_s;       // eshat_s = 2 / kappa_max^2
     const double* rs;                // sorted points (n)
     const double* ws;                // sorted frequencies (m)
     const int32_t* perm_r;           // sorted position -> caller index (points)
