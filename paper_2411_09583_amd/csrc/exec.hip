@@ -1529,15 +1529,14 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
         double vl = v.lo + (sp.lo * B.Khi + sp.hi * B.Klo);
         int q0 = (int)ceil(v.hi - 0.5 * w);
         const int mask = B.N2 - 1;
-        // Tap t sits at offset t + f0 - w/2 from the target, f0 in [0, 1).  At
-        // ten channels and more its kernel value is piece t of the ES kernel at
-        // f0 (the pieces the spreading uses, w x (kEsDeg + 1) monomial
-        // coefficients in 2 f - 1, scalar operands as the table is uniform):
-        // that frees the registers the exponential needs, which would spill
-        // there.  Below ten channels nothing spills and exp is the faster.
+        // Tap t sits at offset t + f0 - w/2 from the target, f0 in [0, 1).  Its
+        // kernel value is piece t of the ES kernel at f0 (the pieces the
+        // spreading uses, w x (kEsDeg + 1) monomial coefficients in 2 f - 1,
+        // the same for every lane: each enters its FMA as the scalar addend).
+        // Against exp and sqrt per tap this is a third of the instructions and
+        // fewer registers.
         const double* __restrict__ es_poly = P.es_poly;
         const double sf = 2.0 * ((((double)q0 - v.hi) - vl) + 0.5 * w) - 1.0;
-        const double two_over_w = 2.0 / w;
         for (int tap = 0; tap < w; ++tap) {
             int q = q0 + tap;
             int qi = q & mask;
@@ -1546,15 +1545,10 @@ __device__ double asym_eval(const PlanDev& P, int ablk, double om, const double2
             double2 gv[NCH];
             #pragma unroll
             for (int p = 0; p < NCH; ++p) gv[p] = Aq[(int64_t)p * B.N2 + qi];
-            double psi;
-            if constexpr (NCH >= 8) {
-                const double* cf = es_poly + tap * (kEsDeg + 1);
-                psi = cf[kEsDeg];
-                #pragma unroll
-                for (int d = kEsDeg - 1; d >= 0; --d) psi = fma_uniform_addend(psi, sf, cf[d]);
-            } else {
-                psi = es_kernel((((double)q - v.hi) - vl) * two_over_w, P.beta);
-            }
+            const double* cf = es_poly + tap * (kEsDeg + 1);
+            double psi = cf[kEsDeg];
+            #pragma unroll
+            for (int d = kEsDeg - 1; d >= 0; --d) psi = fma_uniform_addend(psi, sf, cf[d]);
             // Horner's rule in gamma from the highest channel: the loaded values
             // (vector registers here) are the addends
             double br = gv[NCH - 1].x, bi = gv[NCH - 1].y;

@@ -104,19 +104,6 @@ __device__ __constant__ static const double kInvInt[128] = {
     1.0 / 110, 1.0 / 111, 1.0 / 112, 1.0 / 113, 1.0 / 114, 1.0 / 115, 1.0 / 116, 1.0 / 117, 1.0 / 118, 1.0 / 119,
     1.0 / 120, 1.0 / 121, 1.0 / 122, 1.0 / 123, 1.0 / 124, 1.0 / 125, 1.0 / 126, 1.0 / 127};
 
-// Exponential-of-semicircle kernel exp(beta (sqrt(1 - x^2) - 1)) on |x| < 1.
-__device__ __forceinline__ double es_kernel(double x, double beta)
-{
-    double a = __builtin_fma(-x, x, 1.0);
-    return a > 0.0 ? exp(beta * (sqrt(a) - 1.0)) : 0.0;
-}
-
-__device__ __forceinline__ float es_kernel_f(float x, float beta)
-{
-    float a = __builtin_fmaf(-x, x, 1.0f);
-    return a > 0.0f ? __expf(beta * (sqrtf(a) - 1.0f)) : 0.0f;
-}
-
 // ES^(kappa) = int_{-1}^{1} ES(x) e^{i kappa x} dx for 0 <= kappa <= kappa_max.
 // ES^ is even in kappa, so on that range it is a smooth function of
 // s = 2 (kappa / kappa_max)^2 - 1 in [-1, 1]: the plan holds the monomial
