@@ -1451,15 +1451,6 @@ __device__ __forceinline__ void rotate_add_uniform(double& ar, double& ai, doubl
         : "v"(er), "v"(ei), "s"(g0r), "s"(g0i));
 }
 
-// a b + c with c the same in every lane, as one FMA with c its scalar addend
-// (the compiler copies such an addend into vector registers first).
-__device__ __forceinline__ double fma_uniform_addend(double a, double b, double c)
-{
-    double r;
-    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
-    return r;
-}
-
 // UNI: the block index, and so the block's fields and grid, is the same in
 // every lane of the wave.
 template <int NCH, bool UNI>

@@ -25,6 +25,17 @@ __device__ __forceinline__ dd two_sum(double a, double b)
     return {s, (a - (s - bb)) + (b - bb)};
 }
 
+// a b + c with c the same in every lane (a constant, or a value read through
+// the scalar unit), as one FMA with c its scalar-register addend.  The
+// compiler would keep such an addend in vector registers and copy it before
+// each two-operand FMA, an extra instruction per term of a polynomial.
+__device__ __forceinline__ double fma_uniform_addend(double a, double b, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
 constexpr double kTwoPiHi = 6.283185307179586232;        // 2 pi rounded to double
 constexpr double kTwoPiLo = 2.4492935982947064e-16;       // 2 pi - kTwoPiHi
 constexpr double kInvTwoPi = 0.15915494309189535;        // 1/(2 pi) rounded to double
@@ -47,23 +58,23 @@ __device__ __forceinline__ void sincos_small(double x, double* sp, double* cp)
     r = __builtin_fma(-q, kPio2Lo, r);
     double r2 = r * r;
     double ps = 1.0 / 355687428096000.0;                  // 1/17!
-    ps = __builtin_fma(ps, r2, -1.0 / 1307674368000.0);
-    ps = __builtin_fma(ps, r2, 1.0 / 6227020800.0);
-    ps = __builtin_fma(ps, r2, -1.0 / 39916800.0);
-    ps = __builtin_fma(ps, r2, 1.0 / 362880.0);
-    ps = __builtin_fma(ps, r2, -1.0 / 5040.0);
-    ps = __builtin_fma(ps, r2, 1.0 / 120.0);
-    ps = __builtin_fma(ps, r2, -1.0 / 6.0);
+    ps = fma_uniform_addend(ps, r2, -1.0 / 1307674368000.0);
+    ps = fma_uniform_addend(ps, r2, 1.0 / 6227020800.0);
+    ps = fma_uniform_addend(ps, r2, -1.0 / 39916800.0);
+    ps = fma_uniform_addend(ps, r2, 1.0 / 362880.0);
+    ps = fma_uniform_addend(ps, r2, -1.0 / 5040.0);
+    ps = fma_uniform_addend(ps, r2, 1.0 / 120.0);
+    ps = fma_uniform_addend(ps, r2, -1.0 / 6.0);
     double sn = __builtin_fma(r * r2, ps, r);
     double pc = -1.0 / 6402373705728000.0;                // -1/18!
-    pc = __builtin_fma(pc, r2, 1.0 / 20922789888000.0);
-    pc = __builtin_fma(pc, r2, -1.0 / 87178291200.0);
-    pc = __builtin_fma(pc, r2, 1.0 / 479001600.0);
-    pc = __builtin_fma(pc, r2, -1.0 / 3628800.0);
-    pc = __builtin_fma(pc, r2, 1.0 / 40320.0);
-    pc = __builtin_fma(pc, r2, -1.0 / 720.0);
-    pc = __builtin_fma(pc, r2, 1.0 / 24.0);
-    pc = __builtin_fma(pc, r2, -0.5);
+    pc = fma_uniform_addend(pc, r2, 1.0 / 20922789888000.0);
+    pc = fma_uniform_addend(pc, r2, -1.0 / 87178291200.0);
+    pc = fma_uniform_addend(pc, r2, 1.0 / 479001600.0);
+    pc = fma_uniform_addend(pc, r2, -1.0 / 3628800.0);
+    pc = fma_uniform_addend(pc, r2, 1.0 / 40320.0);
+    pc = fma_uniform_addend(pc, r2, -1.0 / 720.0);
+    pc = fma_uniform_addend(pc, r2, 1.0 / 24.0);
+    pc = __builtin_fma(pc, r2, -0.5);                     // -0.5 is an inline constant
     double cs = __builtin_fma(r2, pc, 1.0);
     int k = (int)q & 3;
     double s0 = (k & 1) ? cs : sn;
