@@ -1205,6 +1205,7 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
             yk1 = yk; yk = ykm1;
             miller_rescale(yk, yk1, S2, dot);
         }
+        i = L;   // where every lane left the loop (N > L): the index is now wave-uniform
         // i = L .. 1 in every lane (the start is above L): L mod 4 single
         // steps, then groups of four whose moments u[i-3 .. i] are read
         // together (u_i = 2 (-1)^i t_i)
@@ -1248,6 +1249,7 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
             yk1 = yk; yk = ykm1;
             miller_rescale(yk, yk1, S2, dot);
         }
+        i = L;   // where every lane left the loop (N > L): the index is now wave-uniform
         auto step = [&](int k, double uk, bool check) {
             S2 = __builtin_fma(2.0 * yk, yk, S2);
             dot = __builtin_fma(uk * yk, yk1, dot);
@@ -1298,19 +1300,20 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
         const int act = s0 - nu;
         const double up = 0x1p332, down = 0x1p-332, down2 = 0x1p-664;
         double syk = yk, syk1 = 0.0;          // leading copy's state at s0
-        double lyk = 0.0, lyk1 = 0.0, lsc = 1.0;
+        double lyk = 0.0, lyk1 = 0.0, lsc = sa;   // lsc: (-1)^a 2^(-332 d)
         int d = 0;
         int i = N;
         for (; i > top; --i) {
-            if (i == s0) { syk = yk; syk1 = yk1; d = 0; lsc = 1.0; }
+            if (i == s0) { syk = yk; syk1 = yk1; d = 0; lsc = sa; }
             S2 = __builtin_fma(2.0 * yk, yk, S2);
             double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
             yk1 = yk; yk = ykm1;
             if (fabs(yk) > up) {
                 yk *= down; yk1 *= down; S2 *= down2; dot *= down2;
-                ++d; lsc = __builtin_amdgcn_ldexp(1.0, -332 * d);
+                ++d; lsc = __builtin_amdgcn_ldexp(sa, -332 * d);
             }
         }
+        i = top;   // where every lane left the loop (N > top): the index is now wave-uniform
         // i = top .. 0 in every lane.  stepB takes the products at index i and
         // (i > 0) moves both copies one index down; rescaleB follows a step
         // whose last products were at index il (stored partners: indices il .. nu).
@@ -1320,7 +1323,7 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
             if (i >= a2 && i <= nu) ring[(i - a2) * stride] = yk;
             if (i >= 1 && i <= hi1) {
                 // 2 (-1)^i t_{a+i} = (-1)^a u_{a+i}
-                dot = __builtin_fma(sa * t[a + i] * yk, lyk * lsc, dot);
+                dot = __builtin_fma(t[a + i] * yk, lyk * lsc, dot);
             }
             if (i <= a && a - i <= L) {
                 int l2 = a - i;
@@ -1340,13 +1343,13 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
             const double ml = group ? fmax(fabs(yk), fabs(yk1)) : fabs(yk);
             if (ml > up) {
                 yk *= down; yk1 *= down; S2 *= down2; dot *= down2;
-                ++d; lsc = __builtin_amdgcn_ldexp(1.0, -332 * d);
+                ++d; lsc = __builtin_amdgcn_ldexp(sa, -332 * d);
                 for (int q = (il > a2 ? il : a2) - a2; q <= nu - a2; ++q) ring[q * stride] *= down;
             }
             const double mg = group ? fmax(fabs(lyk), fabs(lyk1)) : fabs(lyk);
             if (mg > up) {
                 lyk *= down; lyk1 *= down;
-                --d; lsc = __builtin_amdgcn_ldexp(1.0, -332 * d);
+                --d; lsc = __builtin_amdgcn_ldexp(sa, -332 * d);
             }
         };
         if (__all(y >= kMillerGroupY)) {
