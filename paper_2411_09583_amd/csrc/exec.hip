@@ -1299,13 +1299,16 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
         const int s0 = N < hi1 + nu ? N : hi1 + nu;
         const int act = s0 - nu;
         const double up = 0x1p332, down = 0x1p-332, down2 = 0x1p-664;
+        // Here S2 holds half the normalising sum (J_0^2 / 2 + sum_{i>=1} J_i^2),
+        // one FMA per step; the lagging copy starts (i == act) at one or two
+        // steps of a wave, so that test is a wave vote first.
         double syk = yk, syk1 = 0.0;          // leading copy's state at s0
         double lyk = 0.0, lyk1 = 0.0, lsc = sa;   // lsc: (-1)^a 2^(-332 d)
         int d = 0;
         int i = N;
         for (; i > top; --i) {
             if (i == s0) { syk = yk; syk1 = yk1; d = 0; lsc = sa; }
-            S2 = __builtin_fma(2.0 * yk, yk, S2);
+            S2 = __builtin_fma(yk, yk, S2);
             double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
             yk1 = yk; yk = ykm1;
             if (fabs(yk) > up) {
@@ -1318,8 +1321,10 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
         // (i > 0) moves both copies one index down; rescaleB follows a step
         // whose last products were at index il (stored partners: indices il .. nu).
         auto stepB = [&](int i) {
-            if (i == act) { lyk = syk; lyk1 = syk1; }
-            S2 = __builtin_fma(i == 0 ? yk : 2.0 * yk, yk, S2);
+            if (__any(i == act)) {
+                if (i == act) { lyk = syk; lyk1 = syk1; }
+            }
+            S2 = __builtin_fma(i == 0 ? 0.5 * yk : yk, yk, S2);
             if (i >= a2 && i <= nu) ring[(i - a2) * stride] = yk;
             if (i >= 1 && i <= hi1) {
                 // 2 (-1)^i t_{a+i} = (-1)^a u_{a+i}
@@ -1352,9 +1357,39 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
                 --d; lsc = __builtin_amdgcn_ldexp(sa, -332 * d);
             }
         };
-        if (__all(y >= kMillerGroupY)) {
+        // Above nu (i = top .. nu + 1, present when hi1 > nu) a step has no
+        // partner to store or read: only part one's product and the two
+        // recurrences, so these steps skip stepB's index tests, and their
+        // moments t[a + i] (contiguous, wave-uniform) come four at a time.
+        auto stepA = [&](int i, double ti) {
+            if (__any(i == act)) {
+                if (i == act) { lyk = syk; lyk1 = syk1; }
+            }
+            S2 = __builtin_fma(yk, yk, S2);
+            dot = __builtin_fma(ti * yk, lyk * lsc, dot);
+            double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
+            yk1 = yk; yk = ykm1;
+            double lykm1 = __builtin_fma((double)(i + nu) * rec, lyk, -lyk1);
+            lyk1 = lyk; lyk = lykm1;
+        };
+        const bool group = __all(y >= kMillerGroupY);
+        if (group) {
             // one rescale test per four steps (growth below 3.1e26 per group);
             // the copies may rescale at different indices, d counts both
+            Moments4 nx;
+            if (i - 3 > nu) __builtin_memcpy(&nx, t + a + i - 3, sizeof nx);
+            for (; i - 3 > nu; i -= 4) {
+                const Moments4 q = nx;
+                if (i - 7 > nu) __builtin_memcpy(&nx, t + a + i - 7, sizeof nx);
+                stepA(i, q.v[3]); stepA(i - 1, q.v[2]); stepA(i - 2, q.v[1]); stepA(i - 3, q.v[0]);
+                rescaleB(i - 3, true);
+            }
+        }
+        for (; i > nu; --i) {
+            stepA(i, t[a + i]);
+            rescaleB(i, false);
+        }
+        if (group) {
             for (; i >= 4; i -= 4) {
                 stepB(i); stepB(i - 1); stepB(i - 2); stepB(i - 3);
                 rescaleB(i - 3, true);
@@ -1365,7 +1400,7 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
             if (i == 0) break;
             rescaleB(i, false);
         }
-        return dot / S2;
+        return dot / (2.0 * S2);
     }
 }
 
