@@ -1642,15 +1642,19 @@ __device__ __forceinline__ bool on_jtab(const PlanDev& P, double xh)
     return t >= 0.0 && t < (double)P.jtab_np;
 }
 
-__device__ __forceinline__ void besselj_table2(const PlanDev& P, double xh1, double xl1, double xh2, double xl2,
-                                               double& j1, double& j2)
+// The table's panels as (kJtabCoef / 2) double2 records, read from `tab`
+// with a stride of STRIDE double2 per panel (global memory, or the LDS copy
+// whose padded stride spreads consecutive panels over the banks).
+template <int STRIDE, typename Tab>
+__device__ __forceinline__ void besselj_table2(const PlanDev& P, Tab tab, double xh1, double xl1, double xh2,
+                                               double xl2, double& j1, double& j2)
 {
     const int p1 = (int)((xh1 - P.jtab_x0) * (1.0 / kJtabWidth));
     const int p2 = (int)((xh2 - P.jtab_x0) * (1.0 / kJtabWidth));
     const double u1 = ((xh1 - __builtin_fma((double)p1, kJtabWidth, P.jtab_x0)) - 1.0) + xl1;
     const double u2 = ((xh2 - __builtin_fma((double)p2, kJtabWidth, P.jtab_x0)) - 1.0) + xl2;
-    const double2* __restrict__ c1 = (const double2*)(P.jtab + (int64_t)p1 * kJtabCoef);
-    const double2* __restrict__ c2 = (const double2*)(P.jtab + (int64_t)p2 * kJtabCoef);
+    const auto c1 = tab + p1 * STRIDE;
+    const auto c2 = tab + p2 * STRIDE;
     double2 a[kJtabCoef / 2], b[kJtabCoef / 2];
     #pragma unroll
     for (int q = 0; q < kJtabCoef / 2; ++q) { a[q] = c1[q]; b[q] = c2[q]; }
@@ -1675,12 +1679,19 @@ __device__ __forceinline__ void besselj_table2(const PlanDev& P, double xh1, dou
 // row lies in at most one direct block (the last block of its path down the
 // subdivision tree), so the per-row sums are stored, not accumulated.
 constexpr int kDirectThreads = 256;
+// Tables of up to kJtabLdsPanels panels (z up to about 240 with the
+// default range) are copied into LDS by each workgroup and read from there:
+// shorter latency than the cache hierarchy for the eight 16-byte loads per
+// entry.  A panel takes kJtabLdsStride double2 (one more than its
+// coefficients), so that lanes on neighbouring panels read different banks.
+constexpr int kJtabLdsPanels = 64;
+constexpr int kJtabLdsStride = kJtabCoef / 2 + 1;
 
-__device__ __forceinline__ void direct_body(const PlanDev& P, int bid)
+template <bool LDS>
+__device__ __forceinline__ void direct_rows(const PlanDev& P, const DBlock& D, const double2* s_tab)
 {
     const double* __restrict__ cs = P.cs;
     double* __restrict__ gd = P.gd;
-    const DBlock D = P.db[bid];
     const int mb = D.j1 - D.j0 + 1, nb = D.k1 - D.k0 + 1;
     int G = 1;
     while (G < 64 && 2 * G * mb <= kDirectThreads) G <<= 1;
@@ -1701,7 +1712,10 @@ __device__ __forceinline__ void direct_body(const PlanDev& P, int bid)
                 const double c1 = cs[D.k0 + k], c2 = two ? cs[D.k0 + k2] : 0.0;
                 double j1, j2;
                 if (on_jtab(P, x1.hi) && on_jtab(P, x2.hi)) {
-                    besselj_table2(P, x1.hi, x1.lo, x2.hi, x2.lo, j1, j2);
+                    if constexpr (LDS)
+                        besselj_table2<kJtabLdsStride>(P, s_tab, x1.hi, x1.lo, x2.hi, x2.lo, j1, j2);
+                    else
+                        besselj_table2<kJtabCoef / 2>(P, (const double2*)P.jtab, x1.hi, x1.lo, x2.hi, x2.lo, j1, j2);
                 } else {
                     j1 = besselj_direct(P, x1.hi, x1.lo);
                     j2 = two ? besselj_direct(P, x2.hi, x2.lo) : 0.0;
@@ -1712,6 +1726,24 @@ __device__ __forceinline__ void direct_body(const PlanDev& P, int bid)
         }
         for (int o = G >> 1; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
         if (i < mb && gl == 0) gd[D.j0 + i] = acc;
+    }
+}
+
+__device__ __forceinline__ void direct_body(const PlanDev& P, int bid)
+{
+    __shared__ double2 s_tab[kJtabLdsPanels * kJtabLdsStride];
+    const DBlock D = P.db[bid];
+    if (P.jtab_np > 0 && P.jtab_np <= kJtabLdsPanels) {
+        const double2* __restrict__ g = (const double2*)P.jtab;
+        constexpr int per = kJtabCoef / 2;
+        for (int e = threadIdx.x; e < P.jtab_np * per; e += kDirectThreads) {
+            const int pn = e / per;
+            s_tab[pn * kJtabLdsStride + (e - pn * per)] = g[e];
+        }
+        __syncthreads();
+        direct_rows<true>(P, D, s_tab);
+    } else {
+        direct_rows<false>(P, D, nullptr);
     }
 }
 
