@@ -198,12 +198,15 @@ __device__ __forceinline__ void lmom_pass(const PlanDev& P, const Item& I, const
     double acc[NQ];
     #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    // y = r / R through the block's reciprocal (within an ulp of the
+    // quotient; y only enters the Chebyshev recurrence)
+    const double inv_R = 1.0 / B.R;
     // two points per lane per step (the second with weight 0 past the end):
     // both loads issue together and the recurrences are independent chains
     for (int k = I.ka + lane; k < I.kb; k += 128) {
         const bool two = k + 64 < I.kb;
         const int k2 = two ? k + 64 : k;
-        const double ya = P.rs[k] / B.R, yb = P.rs[k2] / B.R;
+        const double ya = P.rs[k] * inv_R, yb = P.rs[k2] * inv_R;
         double ca = cs[k], cb = two ? cs[k2] : 0.0;
         if (P.half) {          // half-integer orders: weights c sqrt(r / R)
             ca *= sqrt(ya);
