@@ -205,7 +205,13 @@ int nuht_plan_half(nuht_plan_t *plan, int nu2, double eps,
  * nuht_execute -- g = A c (forward transform, Alg. 2).
  *   c_dev: n weights in the caller's point order (as passed to nuht_plan).
  *   g_dev: m outputs in the caller's frequency order; overwritten.
- * Asynchronous on `stream`; allocates nothing.
+ * Asynchronous on `stream`; allocates nothing.  The local moments and direct
+ * blocks, which read only the gathered weights, run on a side stream the
+ * library keeps per device and rejoin `stream` before the local rows, so the
+ * call is ordered on `stream` as one sequence of kernels.  While `stream` is
+ * being captured into a graph, or while the local-moment, direct or
+ * local-row stages are timed (nuht_profile_stages), every stage runs on
+ * `stream`.
  */
 int nuht_execute(nuht_plan_t plan, const double *c_dev, double *g_dev, void *stream);
 

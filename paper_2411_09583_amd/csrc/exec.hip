@@ -2057,7 +2057,7 @@ static void launch_fft_large(const PlanDev& P, const FftClass& K, hipStream_t s)
 }
 
 hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers& B, const FftClass* cls, int ncls,
-                          const IoArgs& io, hipStream_t s, hipEvent_t* marks)
+                          const IoArgs& io, hipStream_t s, hipEvent_t* marks, const ExecFork* fork)
 {
     if (P.m == 0) return hipSuccess;
     if (P.n == 0) {   // a fill kernel, not a memset node, so the call can be captured in a graph
@@ -2068,10 +2068,29 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
     hipLaunchKernelGGL(k_gather, dim3(cdiv64(P.n, 256)), dim3(256), 0, s, P, io.c, io.c_slot,
                        io.scale_by_points ? 1 : 0);
     mark(marks, 1, s);
+    // the local moments and direct blocks read only the gathered weights
+    const bool forked = fork && fork->side && (S.n_litems > 0 || P.n_d > 0);
+    const hipStream_t ls = forked ? fork->side : s;
+    if (forked) {
+        hipError_t e = hipEventRecord(fork->ev_fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ls, fork->ev_fork, 0);
+        if (e != hipSuccess) return e;
+    }
     if (S.n_litems > 0) {
-        if (lmom_width(P.L) == 32) hipLaunchKernelGGL(k_lmom<32>, dim3(S.n_litems), dim3(64), 0, s, P);
-        else hipLaunchKernelGGL(k_lmom<64>, dim3(S.n_litems), dim3(64), 0, s, P);
-        hipLaunchKernelGGL(k_lmom_reduce, dim3(cdiv64((int64_t)S.n_l * (P.L + 1), 256)), dim3(256), 0, s, P);
+        if (lmom_width(P.L) == 32) hipLaunchKernelGGL(k_lmom<32>, dim3(S.n_litems), dim3(64), 0, ls, P);
+        else hipLaunchKernelGGL(k_lmom<64>, dim3(S.n_litems), dim3(64), 0, ls, P);
+        hipLaunchKernelGGL(k_lmom_reduce, dim3(cdiv64((int64_t)S.n_l * (P.L + 1), 256)), dim3(256), 0, ls, P);
+    }
+    auto launch_direct = [&](hipStream_t st) {
+        if (P.n_d > 0) {
+            hipLaunchKernelGGL(k_fill_zero, dim3(cdiv64(P.m, 256)), dim3(256), 0, st, P.gd, (int64_t)P.m);
+            hipLaunchKernelGGL(k_direct_blocks, dim3(P.n_d), dim3(kDirectThreads), 0, st, P);
+        }
+    };
+    if (forked) {
+        launch_direct(ls);
+        const hipError_t e = hipEventRecord(fork->ev_join, ls);
+        if (e != hipSuccess) return e;
     }
     mark(marks, 2, s);
     dispatch_channels(P.nch, [&](auto k) { launch_spread<decltype(k)::value>(P, S, s); });
@@ -2089,13 +2108,14 @@ hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers&
     for (int q = 0; q < ncls; ++q)
         if (cls[q].log2n > 12) launch_fft_large(P, cls[q], s);
     mark(marks, 5, s);
-    if (P.n_d > 0) {
-        hipLaunchKernelGGL(k_fill_zero, dim3(cdiv64(P.m, 256)), dim3(256), 0, s, P.gd, (int64_t)P.m);
-        hipLaunchKernelGGL(k_direct_blocks, dim3(P.n_d), dim3(kDirectThreads), 0, s, P);
-    }
+    if (!forked) launch_direct(s);
     mark(marks, 6, s);
     dispatch_channels(P.nch, [&](auto k) { launch_rows_asy<decltype(k)::value>(P, s); });
     mark(marks, 7, s);
+    if (forked) {
+        const hipError_t e = hipStreamWaitEvent(s, fork->ev_join, 0);
+        if (e != hipSuccess) return e;
+    }
     launch_rows_local(P, io, s);
     mark(marks, 8, s);
     return hipGetLastError();

@@ -986,6 +986,7 @@ struct nuht_plan_s {
     hipStream_t ps = nullptr;
     hipEvent_t ev_use = nullptr;
     hipEvent_t ev_plan = nullptr;  // marks the planning stream's queued work when the plan is released
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;   // an execution's fork to the side stream and back
     bool used = false;
     DevBuf b_geom;               // keys, values, sort scratch, summary, flag
     uint64_t* keys = nullptr;    // sorted points then sorted frequencies (bit patterns)
@@ -1420,6 +1421,8 @@ static void free_plan(nuht_plan_t p)
         p->orders.clear();
         if (p->ev_use) (void)hipEventDestroy(p->ev_use);
         if (p->ev_plan) (void)hipEventDestroy(p->ev_plan);
+        if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+        if (p->ev_join) (void)hipEventDestroy(p->ev_join);
         delete p;
         {
             std::lock_guard<std::mutex> lock(retired_mu);
@@ -1434,6 +1437,8 @@ static void free_plan(nuht_plan_t p)
     dev_free(p->b_geom);
     if (p->ev_use) (void)hipEventDestroy(p->ev_use);
     if (p->ev_plan) (void)hipEventDestroy(p->ev_plan);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     delete p;
     reap_retired();
 }
@@ -1447,6 +1452,24 @@ static hipStream_t plan_stream()
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) { (void)hipGetLastError(); return nullptr; }
     std::lock_guard<std::mutex> lock(mu);
     if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        streams[dev] = nullptr;
+    }
+    return streams[dev];
+}
+
+// The library's side stream for executions (per device, default priority):
+// the local moments and direct blocks of an execution run there, beside the
+// spreading chain on the caller's stream.  Made when a plan is made
+// (create), only looked up by executions, which allocate nothing.
+static hipStream_t exec_side_stream(bool create)
+{
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) { (void)hipGetLastError(); return nullptr; }
+    std::lock_guard<std::mutex> lock(mu);
+    if (create && !streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
         streams[dev] = nullptr;
     }
@@ -1512,7 +1535,25 @@ static int run(nuht_plan_t p, const Partition& Pt, const double* in, double* out
     io.c = in;
     io.g = out;
     io.scale_by_points = scale;
-    HIP_TRY(launch_execute(Pt.P, Pt.sum, Pt.B, Pt.cls.data(), (int)Pt.cls.size(), io, s, prof_marks(p)));
+    // The fork needs the plan's events and the side stream; it is left out
+    // while `s` is being captured into a graph (the capture stays one stream)
+    // and while the local moments, direct blocks or local rows are timed
+    // (their intervals are taken on `s`).
+    ExecFork fork;
+    const ExecFork* fk = nullptr;
+    constexpr uint32_t kSerialStages = (1u << 1) | (1u << 5) | (1u << 7);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) {
+        (void)hipGetLastError();
+        cap = hipStreamCaptureStatusActive;
+    }
+    if (p->ev_fork && p->ev_join && cap == hipStreamCaptureStatusNone && !(p->prof && (p->prof_mask & kSerialStages))) {
+        fork.side = exec_side_stream(false);
+        fork.ev_fork = p->ev_fork;
+        fork.ev_join = p->ev_join;
+        if (fork.side) fk = &fork;
+    }
+    HIP_TRY(launch_execute(Pt.P, Pt.sum, Pt.B, Pt.cls.data(), (int)Pt.cls.size(), io, s, prof_marks(p), fk));
     note_use(p, s);
     return NUHT_OK;
 }
@@ -1600,6 +1641,15 @@ static int plan_create(nuht_plan_t* out, int nu2, double eps, int64_t n, const d
         (void)hipGetLastError();
         p->ev_plan = nullptr;
         return fail(NUHT_EHIP);
+    }
+    // the fork events and side stream are optional: without them executions
+    // stay on one stream
+    if (hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess || !exec_side_stream(true)) {
+        (void)hipGetLastError();
+        if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+        if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+        p->ev_fork = p->ev_join = nullptr;
     }
     if (wait_on) {
         if (hipEventRecord(p->ev_use, wait_on) != hipSuccess) return fail(NUHT_EHIP);

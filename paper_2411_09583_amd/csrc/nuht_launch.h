@@ -85,10 +85,21 @@ struct IoArgs {
     bool scale_by_points = false;
 };
 
+// A second stream for the stages that depend only on the gathered weights
+// (local moments, direct blocks): after the gather `s` records ev_fork, `side`
+// waits for it and runs them, records ev_join, and `s` waits for ev_join before
+// the local rows, the first stage to read their results.
+struct ExecFork {
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+};
+
 // One transform with the plan's partition: out = A in (or A^T in on the
-// transposed geometry).
+// transposed geometry).  With `fork` the local moments and direct blocks run
+// on its side stream, beside the spreading, grid assembly and FFT; without,
+// every stage runs on `s` in order.
 hipError_t launch_execute(const PlanDev& P, const Summary& S, const ExecBuffers& B, const FftClass* cls, int ncls,
-                          const IoArgs& io, hipStream_t s, hipEvent_t* marks);
+                          const IoArgs& io, hipStream_t s, hipEvent_t* marks, const ExecFork* fork = nullptr);
 // Fills P.small, the FFT size classes of at most 4096 points, from the
 // partition's classes.
 void small_fft_table(PlanDev& P, const FftClass* cls, int ncls);
