@@ -280,18 +280,29 @@ __global__ __launch_bounds__(64) void k_lmom_many(const PlanDev* __restrict__ pl
     lmom_body<MAXQ>(plan_of(plans, w.t), w.g0);
 }
 
-// Sum of a local block's item partials, in item order.
+// Sum of a local block's item partials, in a fixed order: eight running sums
+// over the items (item i into sum i mod 8), combined pairwise.  A block can
+// hold a few hundred items (the top-level local block spans most columns),
+// and eight independent sums keep eight loads in flight instead of one.
 __device__ __forceinline__ void lmom_reduce_body(const PlanDev& P, int bid)
 {
-    int64_t t = (int64_t)bid * blockDim.x + threadIdx.x;
-    const int Lp = P.L + 1;
-    if (t >= (int64_t)P.n_l * Lp) return;
-    int32_t b = (int32_t)(t / Lp);
-    int32_t l = (int32_t)(t % Lp);
+    const int32_t t = bid * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+    const int32_t Lp = P.L + 1;
+    if (t >= P.n_l * Lp) return;
+    const int32_t b = t / Lp;
+    const int32_t l = t - b * Lp;
     const LBlock B = P.lb[b];
-    const double* __restrict__ lpart = P.lpart;
-    double s = 0.0;
-    for (int32_t it = 0; it < B.nitems; ++it) s += lpart[(int64_t)(B.item0 + it) * Lp + l];
+    const double* __restrict__ col = P.lpart + (int64_t)B.item0 * Lp + l;
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int32_t it = 0;
+    for (; it + 8 <= B.nitems; it += 8) {
+        #pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] += col[(int64_t)(it + q) * Lp];
+    }
+    #pragma unroll
+    for (int q = 0; q < 7; ++q)
+        if (it + q < B.nitems) a[q] += col[(int64_t)(it + q) * Lp];
+    const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     // stored as the row pass uses them: u_0 = t_0, u_l = 2 (-1)^l t_l (integer
     // orders), t_l itself (half-integer orders: the factors are in the table)
     P.lmom[t] = (l == 0 || P.half) ? s : ((l & 1) ? -2.0 * s : 2.0 * s);
@@ -802,11 +813,19 @@ __device__ __forceinline__ void spread_reduce_body(const PlanDev& P, int bid)
             const Item& I = P.aitems[mid];
             if (I.sub_lo + I.sub_n <= l) a = mid + 1; else hi = mid;
         }
+        // b: up to four steps forward from a (where points are spread out a
+        // cell lies in the subgrids of one or two items), then a binary
+        // search over the rest (where a block's points crowd a few cells,
+        // dozens of items cover each)
         int32_t b = a;
-        hi = i1;
-        while (b < hi) {
-            int32_t mid = (b + hi) >> 1;
-            if (P.aitems[mid].sub_lo <= l) b = mid + 1; else hi = mid;
+        for (int k = 0; k < 4 && b < i1 && P.aitems[b].sub_lo <= l; ++k) ++b;
+        if (b < i1 && P.aitems[b].sub_lo <= l) {
+            hi = i1;
+            ++b;
+            while (b < hi) {
+                int32_t mid = (b + hi) >> 1;
+                if (P.aitems[mid].sub_lo <= l) b = mid + 1; else hi = mid;
+            }
         }
         int32_t it = a;
         for (; it + 16 <= b; it += 16) {
