@@ -1221,10 +1221,22 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
     if (MODE == 0) {
         // J_0^2 t_0 + sum_{i=1}^{L} 2 (-1)^i t_i J_i^2
         int i = N;
-        for (; i > L; --i) {
+        // above L: the recurrence alone, with one rescale test per four
+        // steps where the wave's arguments allow it (as in the grouped
+        // steps below)
+        auto lead = [&](int k) {
             S2 = __builtin_fma(2.0 * yk, yk, S2);
-            double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
+            double ykm1 = __builtin_fma((double)k * rec, yk, -yk1);
             yk1 = yk; yk = ykm1;
+        };
+        if (__all(y >= kMillerGroupY)) {
+            for (; i - 3 > L; i -= 4) {
+                lead(i); lead(i - 1); lead(i - 2); lead(i - 3);
+                miller_rescale_group(yk, yk1, S2, dot);
+            }
+        }
+        for (; i > L; --i) {
+            lead(i);
             miller_rescale(yk, yk1, S2, dot);
         }
         i = L;   // where every lane left the loop (N > L): the index is now wave-uniform
@@ -1265,10 +1277,22 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
     } else if (MODE == 1) {
         // 2 t_0 J_0 J_1 + sum_{i=1}^{L} 2 (-1)^i t_i J_i J_{i+1}; yk1 = J_{i+1}
         int i = N;
-        for (; i > L; --i) {
+        // above L: the recurrence alone, with one rescale test per four
+        // steps where the wave's arguments allow it (as in the grouped
+        // steps below)
+        auto lead = [&](int k) {
             S2 = __builtin_fma(2.0 * yk, yk, S2);
-            double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
+            double ykm1 = __builtin_fma((double)k * rec, yk, -yk1);
             yk1 = yk; yk = ykm1;
+        };
+        if (__all(y >= kMillerGroupY)) {
+            for (; i - 3 > L; i -= 4) {
+                lead(i); lead(i - 1); lead(i - 2); lead(i - 3);
+                miller_rescale_group(yk, yk1, S2, dot);
+            }
+        }
+        for (; i > L; --i) {
+            lead(i);
             miller_rescale(yk, yk1, S2, dot);
         }
         i = L;   // where every lane left the loop (N > L): the index is now wave-uniform
@@ -1328,15 +1352,28 @@ __device__ double local_eval(const PlanDev& P, int lblk, double om, const double
         double lyk = 0.0, lyk1 = 0.0, lsc = sa;   // lsc: (-1)^a 2^(-332 d)
         int d = 0;
         int i = N;
-        for (; i > top; --i) {
-            if (i == s0) { syk = yk; syk1 = yk1; d = 0; lsc = sa; }
+        auto lead = [&](int k) {
+            if (k == s0) { syk = yk; syk1 = yk1; d = 0; lsc = sa; }
             S2 = __builtin_fma(yk, yk, S2);
-            double ykm1 = __builtin_fma((double)i * rec, yk, -yk1);
+            double ykm1 = __builtin_fma((double)k * rec, yk, -yk1);
             yk1 = yk; yk = ykm1;
-            if (fabs(yk) > up) {
+        };
+        auto lead_rescale = [&](bool group) {
+            if ((group ? fmax(fabs(yk), fabs(yk1)) : fabs(yk)) > up) {
                 yk *= down; yk1 *= down; S2 *= down2; dot *= down2;
                 ++d; lsc = __builtin_amdgcn_ldexp(sa, -332 * d);
             }
+        };
+        if (__all(y >= kMillerGroupY)) {
+            // one rescale test per four steps, as in the grouped steps below
+            for (; i - 3 > top; i -= 4) {
+                lead(i); lead(i - 1); lead(i - 2); lead(i - 3);
+                lead_rescale(true);
+            }
+        }
+        for (; i > top; --i) {
+            lead(i);
+            lead_rescale(false);
         }
         i = top;   // where every lane left the loop (N > top): the index is now wave-uniform
         // i = top .. 0 in every lane.  stepB takes the products at index i and
