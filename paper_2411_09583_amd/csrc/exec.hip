@@ -612,6 +612,41 @@ __device__ __forceinline__ void spread_mfma_run(v4d (&acc)[kSpreadTiles<NCH>], c
     }
 }
 
+// A full step of one anchor: all WPTS points valid and none masked, the same
+// products in the same order as spread_mfma_run.  The loop is unrolled, so
+// every LDS offset is a constant and no point needs a validity test.
+template <int NCH>
+__device__ __forceinline__ void spread_mfma_run_full(v4d (&acc)[kSpreadTiles<NCH>], const double* s_v,
+                                                     const double* s_s, const double (&cf)[kEsDeg + 1], int col,
+                                                     int kq)
+{
+    constexpr int NCT = SpreadMfma<NCH>::NCT, VS = SpreadMfma<NCH>::VS, WPTS = SpreadMfma<NCH>::WPTS;
+    const double* v = s_v + kq * VS + col;
+    const double* sp = s_s + kq;
+    #pragma unroll
+    for (int g = 0; g < WPTS; g += 8) {
+        double b0[NCT], b1[NCT];
+        #pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+            const bool on = ct * 16 + 16 <= 2 * NCH || ct * 16 + col < 2 * NCH;   // columns past 2 NCH are zero
+            b0[ct] = on ? v[g * VS + ct * 16] : 0.0;
+            b1[ct] = on ? v[(g + 4) * VS + ct * 16] : 0.0;
+        }
+        const double s0 = sp[g], s1 = sp[g + 4];
+        double p0 = cf[kEsDeg], p1 = cf[kEsDeg];
+        #pragma unroll
+        for (int q = kEsDeg - 1; q >= 0; --q) {
+            p0 = __builtin_fma(p0, s0, cf[q]);
+            p1 = __builtin_fma(p1, s1, cf[q]);
+        }
+        #pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+            acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(p0, b0[ct], acc[ct], 0, 0, 0);
+            acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(p1, b1[ct], acc[ct], 0, 0, 0);
+        }
+    }
+}
+
 // Adds the finished tile of anchor a into the wave's cell sums (row t of the
 // tile to cell a + t) and clears it.
 template <int NCH>
@@ -694,7 +729,8 @@ __device__ __forceinline__ void spread_mfma_item(const PlanDev& P, int slot, dou
                 if (cur >= 0) spread_mfma_flush<NCH>(acc, s_g, col, kq, cur);
                 cur = a_lo;
             }
-            spread_mfma_run<NCH, false>(acc, s_v, s_s, s_d, cf, 0, np, np, col, kq, cur);
+            if (np == WPTS) spread_mfma_run_full<NCH>(acc, s_v, s_s, cf, col, kq);
+            else spread_mfma_run<NCH, false>(acc, s_v, s_s, s_d, cf, 0, np, np, col, kq, cur);
         } else {
             // the points of anchor a are consecutive lanes (points are sorted):
             // only the groups of eight that hold them are multiplied
