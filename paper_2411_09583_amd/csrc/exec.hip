@@ -2377,7 +2377,7 @@ void build_batch_schedule(const BatchTransform* tr, int count, const int* order,
 }
 
 hipError_t launch_execute_many(const BatchSchedule& S, const void* table_dev, void* const* c_table,
-                               void* const* g_table, hipStream_t s)
+                               void* const* g_table, hipStream_t s, const ExecFork* fork)
 {
     const char* base = (const char*)table_dev;
     const PlanDev* plans = (const PlanDev*)base;
@@ -2385,18 +2385,43 @@ hipError_t launch_execute_many(const BatchSchedule& S, const void* table_dev, vo
     const FftSeg* fsegs = (const FftSeg*)(base + S.fsegs_off);
     const double* const* cin = (const double* const*)c_table;
     double* const* gout = (double* const*)g_table;
+    // with `fork`: the local moments and direct blocks on its side stream,
+    // forked at the first of them (after the gather) and joined before the
+    // local rows (or at the end)
+    bool forked = false, joined = false;
+    auto join = [&]() -> hipError_t {
+        hipError_t e = hipEventRecord(fork->ev_join, fork->side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, fork->ev_join, 0);
+        joined = true;
+        return e;
+    };
     for (const BatchLaunch& L : S.launches) {
         const dim3 grid(L.blocks), block(L.threads);
+        const bool side_kind = L.kind == kLmom || L.kind == kLmomReduce || L.kind == kZeroGd || L.kind == kDirect;
+        hipStream_t st = s;
+        if (fork && side_kind && !joined) {
+            if (!forked) {
+                hipError_t e = hipEventRecord(fork->ev_fork, s);
+                if (e == hipSuccess) e = hipStreamWaitEvent(fork->side, fork->ev_fork, 0);
+                if (e != hipSuccess) return e;
+                forked = true;
+            }
+            st = fork->side;
+        }
+        if (forked && !joined && L.kind == kRowsLocal) {
+            const hipError_t e = join();
+            if (e != hipSuccess) return e;
+        }
         const WorkSeg* sg = segs + L.seg0;
         const FftSeg* fs = fsegs + L.seg0;
         switch (L.kind) {
         case kZeroOut: hipLaunchKernelGGL(k_zero_output_many, grid, block, 0, s, plans, sg, L.nseg, gout); break;
         case kGather: hipLaunchKernelGGL(k_gather_many, grid, block, 0, s, plans, sg, L.nseg, cin); break;
         case kLmom:
-            if (L.variant == 32) hipLaunchKernelGGL(k_lmom_many<32>, grid, block, 0, s, plans, sg, L.nseg);
-            else hipLaunchKernelGGL(k_lmom_many<64>, grid, block, 0, s, plans, sg, L.nseg);
+            if (L.variant == 32) hipLaunchKernelGGL(k_lmom_many<32>, grid, block, 0, st, plans, sg, L.nseg);
+            else hipLaunchKernelGGL(k_lmom_many<64>, grid, block, 0, st, plans, sg, L.nseg);
             break;
-        case kLmomReduce: hipLaunchKernelGGL(k_lmom_reduce_many, grid, block, 0, s, plans, sg, L.nseg); break;
+        case kLmomReduce: hipLaunchKernelGGL(k_lmom_reduce_many, grid, block, 0, st, plans, sg, L.nseg); break;
         case kSpreadMfma:
         case kSpreadMfmaMed:
             dispatch_channels(L.variant, [&](auto k) {
@@ -2428,8 +2453,8 @@ hipError_t launch_execute_many(const BatchSchedule& S, const void* table_dev, vo
         case kFftPass0:
         case kFftPass1: hipLaunchKernelGGL(k_fft_col_many, grid, block, L.lds, s, plans, fs, L.nseg); break;
         case kFftPass2: hipLaunchKernelGGL(k_fft_row_many, grid, block, L.lds, s, plans, fs, L.nseg); break;
-        case kZeroGd: hipLaunchKernelGGL(k_zero_gd_many, grid, block, 0, s, plans, sg, L.nseg); break;
-        case kDirect: hipLaunchKernelGGL(k_direct_blocks_many, grid, block, 0, s, plans, sg, L.nseg); break;
+        case kZeroGd: hipLaunchKernelGGL(k_zero_gd_many, grid, block, 0, st, plans, sg, L.nseg); break;
+        case kDirect: hipLaunchKernelGGL(k_direct_blocks_many, grid, block, 0, st, plans, sg, L.nseg); break;
         case kRowsAsy:
             dispatch_channels(L.variant, [&](auto k) {
                 hipLaunchKernelGGL((k_rows_asy_many<decltype(k)::value>), grid, block, 0, s, plans, sg, L.nseg);
@@ -2445,6 +2470,10 @@ hipError_t launch_execute_many(const BatchSchedule& S, const void* table_dev, vo
             break;
         default: return hipErrorInvalidValue;
         }
+    }
+    if (forked && !joined) {
+        const hipError_t e = join();
+        if (e != hipSuccess) return e;
     }
     return hipGetLastError();
 }

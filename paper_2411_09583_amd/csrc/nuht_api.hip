@@ -2129,6 +2129,7 @@ struct nuht_batch_s {
     hipStream_t aux[kBatchStreams] = {};
     hipStream_t cap = nullptr;           // capture and replay stream
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;   // the captured graph's branch to aux[0] and back
     DevBuf b_ptrs;                       // device tables of input and output pointers
     void** c_table = nullptr;
     void** g_table = nullptr;
@@ -2155,6 +2156,8 @@ static void free_batch(nuht_batch_t b)
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     delete b;
 }
 
@@ -2194,6 +2197,8 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
     if (!hip_ok(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking))) return fail(NUHT_EHIP);
     if (!hip_ok(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming))) return fail(NUHT_EHIP);
     if (!hip_ok(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming))) return fail(NUHT_EHIP);
+    if (!hip_ok(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming))) return fail(NUHT_EHIP);
+    if (!hip_ok(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming))) return fail(NUHT_EHIP);
     // the inputs are ready once the caller's stream reaches this point
     if (!hip_ok(hipEventRecord(b->ev_in, s))) return fail(NUHT_EHIP);
     for (int k = 0; k < kBatchStreams; ++k)
@@ -2314,15 +2319,22 @@ int nuht_plan_many(nuht_batch_t* out, int count, const int* nu, double eps, cons
 }
 
 // Captures the batch's execution into one graph: the batched launches, stage
-// by stage, on the capture stream alone (each launch covers every transform
-// with work in its stage); inputs and outputs come from the pointer tables.
+// by stage (each launch covers every transform with work in its stage), on
+// the capture stream, with the local moments and direct blocks on a branch
+// of their own (the batch's first planning stream, idle by now, joins the
+// capture through the fork event); inputs and outputs come from the pointer
+// tables.
 static int capture_batch(nuht_batch_t b)
 {
     if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipGetLastError();
         return NUHT_EHIP;
     }
-    hipError_t e = launch_execute_many(b->sched, b->b_table.p, b->c_table, b->g_table, b->cap);
+    ExecFork fork;
+    fork.side = b->aux[0];
+    fork.ev_fork = b->ev_fork;
+    fork.ev_join = b->ev_join;
+    hipError_t e = launch_execute_many(b->sched, b->b_table.p, b->c_table, b->g_table, b->cap, &fork);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {

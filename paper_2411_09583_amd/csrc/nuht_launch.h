@@ -131,7 +131,8 @@ struct BatchSchedule {
 // launch (largest first).
 void build_batch_schedule(const BatchTransform* tr, int count, const int* order, BatchSchedule& out);
 hipError_t launch_execute_many(const BatchSchedule& S, const void* table_dev, void* const* c_table,
-                               void* const* g_table, hipStream_t s);
+                               void* const* g_table, hipStream_t s,
+                               const ExecFork* fork = nullptr);
 // x[i] = v
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
 // -(2 nu + 1) pi / 4 modulo 2 pi as a double-double (the Hankel phase offset).
