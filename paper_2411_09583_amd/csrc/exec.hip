@@ -372,8 +372,10 @@ __device__ __forceinline__ PointEval eval_point(const ABlock& B, double r, doubl
     dd ph = two_prod(B.D, tp.hi);
     double cth, sth;
     cis_dd(ph.hi, __builtin_fma(B.D, tp.lo, ph.lo), cth, sth);
-    double q = B.r0 / r;
-    double w0 = c * sqrt(q);
+    // q = r0 / r in (0, 1] and its square root through the refined hardware
+    // estimates (within an ulp or two; no IEEE division or square root)
+    const double q = B.r0 * rcp_refined(r);
+    const double w0 = c * (q * rsqrt_refined(q));
     // u - w/2 = (tp.hi + tp.lo)/h - w/2
     dd a = two_sum(tp.hi * inv_h, -hw);
     double lo = a.lo + tp.lo * inv_h;
@@ -1544,27 +1546,6 @@ __device__ double local_eval_half(const PlanDev& P, int lblk, double om, const d
 // wave is in the same block (the usual case, frequencies being sorted); the
 // block's fields and its direct-sum grid are then read through the scalar
 // unit and broadcast to all lanes.
-// 1/sqrt(x) and 1/x for positive normal x: the hardware estimate refined by two
-// Newton steps (to within an ulp or two; cheaper than IEEE division and sqrt).
-__device__ __forceinline__ double rsqrt_refined(double x)
-{
-    double y = __builtin_amdgcn_rsq(x);
-    #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const double h = 0.5 * x * y;
-        y = __builtin_fma(y, __builtin_fma(-h, y, 0.5), y);    // y (3/2 - x y^2 / 2)
-    }
-    return y;
-}
-
-__device__ __forceinline__ double rcp_refined(double x)
-{
-    double y = __builtin_amdgcn_rcp(x);
-    #pragma unroll
-    for (int k = 0; k < 2; ++k) y = __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
-    return y;
-}
-
 // One Horner step of a direct-sum cell sum with the cell's channel-0 value
 // (g0r, g0i) in scalar registers:
 //   (ar, ai) <- (ar, ai) e^{i theta} + (g0r, g0i)

@@ -36,6 +36,27 @@ __device__ __forceinline__ double fma_uniform_addend(double a, double b, double 
     return r;
 }
 
+// 1/sqrt(x) and 1/x for positive normal x: the hardware estimate refined by two
+// Newton steps (to within an ulp or two; cheaper than IEEE division and sqrt).
+__device__ __forceinline__ double rsqrt_refined(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    #pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double h = 0.5 * x * y;
+        y = __builtin_fma(y, __builtin_fma(-h, y, 0.5), y);    // y (3/2 - x y^2 / 2)
+    }
+    return y;
+}
+
+__device__ __forceinline__ double rcp_refined(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    #pragma unroll
+    for (int k = 0; k < 2; ++k) y = __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+    return y;
+}
+
 constexpr double kTwoPiHi = 6.283185307179586232;        // 2 pi rounded to double
 constexpr double kTwoPiLo = 2.4492935982947064e-16;       // 2 pi - kTwoPiHi
 constexpr double kInvTwoPi = 0.15915494309189535;        // 1/(2 pi) rounded to double
