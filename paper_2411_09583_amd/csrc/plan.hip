@@ -1298,12 +1298,16 @@ __device__ __forceinline__ NodeSplit split_node(const Rect& R, int32_t kj1, int3
 // loads within the thread, and a pass waits for its slowest thread: one is
 // faster.)
 constexpr int kSubNpt = 1;
+// One workgroup does the whole subdivision.  256 threads rather than 1024:
+// a 1024-thread workgroup needs a compute unit with sixteen free wave slots,
+// which the execution running beside the plan rarely leaves.
+constexpr int kSubThreads = 256;
 // The first entries of each level's queue live in LDS (the queue of the next
 // level is written while the current one is read, so two buffers); entries
 // past them go to the global queues at the same index.
 constexpr int kSubLds = 1920;
 
-__global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ K, const int32_t* __restrict__ Jc,
+__global__ __launch_bounds__(kSubThreads) void k_subdivide(const int32_t* __restrict__ K, const int32_t* __restrict__ Jc,
                                                     int32_t m, int32_t n, int64_t min_size, int32_t ncand, Arena A,
                                                     Summary* __restrict__ sum, const int32_t* __restrict__ errs,
                                                     int32_t n_errs)
@@ -1314,7 +1318,7 @@ __global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ 
     // the summary starts clear (this is the first planning kernel to use it),
     // with the input check's verdict
     int bad = 0;
-    for (int32_t i = tid; i < n_errs; i += 1024) bad |= errs[i];
+    for (int32_t i = tid; i < n_errs; i += kSubThreads) bad |= errs[i];
     bad = __syncthreads_or(bad);
     if (tid == 0) {
         *sum = Summary{};
@@ -1332,7 +1336,7 @@ __global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ 
     while (n_cur > 0) {
         ++level;
         int32_t n_next = 0;
-        for (int32_t c0 = 0; c0 < n_cur; c0 += 1024 * kSubNpt) {
+        for (int32_t c0 = 0; c0 < n_cur; c0 += kSubThreads * kSubNpt) {
             const int32_t i0 = c0 + tid * kSubNpt;
             Rect R[kSubNpt];
             NodeSplit S[kSubNpt];
@@ -1362,7 +1366,7 @@ __global__ __launch_bounds__(1024) void k_subdivide(const int32_t* __restrict__ 
             }
             int32_t v[4] = {cnt[0], cnt[1], cnt[2], cnt[3]};
             int32_t tot[4];
-            block_scan<int32_t, 4>(v, tot, wsum);
+            block_scan<int32_t, 4, kSubThreads / 64>(v, tot, wsum);
             int32_t l_slot = n_l + v[0], a_slot = n_a + v[1], d_slot = n_d + v[2], m_slot = n_next + v[3];
             const int32_t next_base = n_nodes + n_cur;   // first node index of the next level
             #pragma unroll
@@ -1891,7 +1895,7 @@ hipError_t launch_planning(const PlanDev& P, const Arena& A, int32_t* K, int32_t
     const int32_t n = P.n, m = P.m;
     hipLaunchKernelGGL(k_staircase, dim3(cdiv(m, 256)), dim3(256), 0, s, P.rs, n, P.ws, m, P.z, K);
     hipLaunchKernelGGL(k_staircase, dim3(cdiv(n, 256)), dim3(256), 0, s, P.ws, m, P.rs, n, P.z, Jc);
-    hipLaunchKernelGGL(k_subdivide, dim3(1), dim3(1024), 0, s, K, Jc, m, n, min_size, ncand, A, sum, errs, n_errs);
+    hipLaunchKernelGGL(k_subdivide, dim3(1), dim3(kSubThreads), 0, s, K, Jc, m, n, min_size, ncand, A, sum, errs, n_errs);
     hipLaunchKernelGGL(k_block_params, dim3(256), dim3(128), 0, s, P, A, dft_max, sigma, sum);
     hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(kPlanScanThreads), 0, s, P, A, sum);
     hipLaunchKernelGGL(k_items, dim3(512), dim3(128), 0, s, P, A, sum, a_cells);
