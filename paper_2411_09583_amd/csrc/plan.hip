@@ -1167,12 +1167,12 @@ __device__ __forceinline__ bool exact_le(double a, double b, double z)
 // probes per step split the range into 33 parts), then every lane finishes
 // with a binary search inside that bracket (a few steps where the sorted
 // points are spread evenly).
-__global__ __launch_bounds__(256) void k_staircase(const double* __restrict__ sorted, int32_t len,
-                                                   const double* __restrict__ q, int32_t nq, double z,
-                                                   int32_t* __restrict__ out)
+__device__ __forceinline__ void staircase_body(const double* __restrict__ sorted, int32_t len,
+                                               const double* __restrict__ q, int32_t nq, double z,
+                                               int32_t* __restrict__ out, int32_t bid)
 {
     const int lane = threadIdx.x & 63;
-    const int32_t j0 = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) & ~63u);
+    const int32_t j0 = (int32_t)((bid * blockDim.x + threadIdx.x) & ~63u);
     if (j0 >= nq) return;                              // the whole wave
     const int32_t jl = j0 + 63 < nq ? j0 + 63 : nq - 1;
     const int half = lane >> 5, hl = lane & 31;
@@ -1205,6 +1205,18 @@ __global__ __launch_bounds__(256) void k_staircase(const double* __restrict__ so
         if (exact_le(w, sorted[mid], z)) lo = mid + 1; else hi = mid;
     }
     out[j] = lo;
+}
+
+// Both staircases of a geometry in one launch (they are independent): the
+// first nba workgroups count, for each sorted frequency, the sorted points
+// whose product with it is at most z (K); the rest count, for each sorted
+// point, the sorted frequencies (Jc).  One launch fewer on the plan's path.
+__global__ __launch_bounds__(256) void k_staircase(const double* __restrict__ rs, int32_t n,
+                                                   const double* __restrict__ ws, int32_t m, double z,
+                                                   int32_t* __restrict__ K, int32_t* __restrict__ Jc, int32_t nba)
+{
+    if ((int32_t)blockIdx.x < nba) staircase_body(rs, n, ws, m, z, K, blockIdx.x);
+    else staircase_body(ws, m, rs, n, z, Jc, blockIdx.x - nba);
 }
 
 // ---------------------------------------------------------------------------
@@ -1893,8 +1905,8 @@ hipError_t launch_planning(const PlanDev& P, const Arena& A, int32_t* K, int32_t
                            const int32_t* errs, int32_t n_errs, hipStream_t s)
 {
     const int32_t n = P.n, m = P.m;
-    hipLaunchKernelGGL(k_staircase, dim3(cdiv(m, 256)), dim3(256), 0, s, P.rs, n, P.ws, m, P.z, K);
-    hipLaunchKernelGGL(k_staircase, dim3(cdiv(n, 256)), dim3(256), 0, s, P.ws, m, P.rs, n, P.z, Jc);
+    hipLaunchKernelGGL(k_staircase, dim3(cdiv(m, 256) + cdiv(n, 256)), dim3(256), 0, s, P.rs, n, P.ws, m, P.z, K,
+                       Jc, cdiv(m, 256));
     hipLaunchKernelGGL(k_subdivide, dim3(1), dim3(kSubThreads), 0, s, K, Jc, m, n, min_size, ncand, A, sum, errs, n_errs);
     hipLaunchKernelGGL(k_block_params, dim3(256), dim3(128), 0, s, P, A, dft_max, sigma, sum);
     hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(kPlanScanThreads), 0, s, P, A, sum);
