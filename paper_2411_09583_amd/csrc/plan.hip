@@ -1220,7 +1220,7 @@ __global__ __launch_bounds__(256) void k_staircase(const double* __restrict__ rs
 }
 
 // ---------------------------------------------------------------------------
-// Alg. 1 (Subdivide), level by level in one 1024-thread block.  Every mixed
+// Alg. 1 (Subdivide), level by level in one 256-thread block.  Every mixed
 // block of a level becomes a Node; its split follows the quasi-optimal
 // SplitIndices of Sec. 4.1 (candidate rows equispaced over the rows that hold
 // a local entry, minimal mixed area, ties to the smaller row).  Numbering is
